@@ -1,0 +1,223 @@
+/*
+ * rfd.h -- C ABI of the RF-DDES interface-filter library for AMD MI355X (gfx950).
+ *
+ * RF-DDES (Kalantzis, Xi, Saad, "Beyond AMLS: domain decomposition with
+ * rational filtering", arXiv 1711.09487) computes the eigenpairs of a sparse
+ * symmetric pencil A x = lambda M x (M SPD) with lambda in [alpha, beta]:
+ *
+ *   rfd_create_pencil           the pencil (A, M)                       Sec. 1
+ *   rfd_set_partition           interior-first reordering               Sec. 2.3, eq. (2.5)
+ *   rfd_set_interval_and_poles  rational filter poles / weights         Sec. 2.1, eqs. (2.1)-(2.3)
+ *   rfd_set_precision           FP64, or FP32 factors + FP64 refinement
+ *   rfd_filter_interface        Q = orth of 2 Re sum_l w_l S(z_l)^{-1} applied
+ *                               to a block (block Krylov)               Sec. 3.1 eq. (3.5), Alg. 3.1
+ *   rfd_solve_interior          V_j, Sigma_j, Gamma_j and Z             Sec. 4, Sec. 5.1 eqs. (5.2)-(5.5)
+ *   rfd_rayleigh_ritz           Ritz pairs in [alpha, beta]             Alg. 5.1 steps 6-8
+ *
+ * Conventions (all entry points):
+ *  - Every call returns an rfd_status; RFD_OK is 0.  No exception crosses the
+ *    ABI.  On error rfd_last_error() returns a message (thread-local, valid
+ *    until the next call on the same thread).
+ *  - Matrices are column-major, FP64 unless stated.  Index arrays are int32
+ *    except CSR row pointers (int64).
+ *  - "host" pointers are read (or written) before the call returns; "device"
+ *    pointers are HBM addresses on the current HIP device, owned by the
+ *    caller, and are read/written by work enqueued on `stream` (0 = the null
+ *    stream); the call returns after that work has been enqueued and, where a
+ *    host scalar output is produced (mu, k, nfound), after the stream has
+ *    reached that point.
+ *  - A pencil handle is not thread-safe: use one handle per host thread.
+ *  - The library owns its device workspaces; rfd_destroy_pencil frees them.
+ */
+#ifndef RFD_H_
+#define RFD_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rfd_pencil_s* rfd_pencil_t;
+typedef void* rfd_stream_t; /* a hipStream_t */
+
+typedef enum {
+  RFD_OK = 0,
+  RFD_EINVAL = 1,      /* invalid argument or inconsistent input            */
+  RFD_ENOMEM = 2,      /* device or host allocation failed                  */
+  RFD_EBREAKDOWN = 3,  /* a pivot below the breakdown threshold (singular)  */
+  RFD_ENOCONV = 4,     /* iterative refinement did not reach its tolerance  */
+  RFD_EDEVICE = 5,     /* a HIP runtime error                               */
+  RFD_ESTATE = 6       /* call out of order (e.g. filter before partition)  */
+} rfd_status;
+
+enum { RFD_RULE_GAUSS = 0, RFD_RULE_MIDPOINT = 1, RFD_RULE_EXPLICIT = 2 };
+enum { RFD_FP64 = 0, RFD_FP32_REFINE = 1 };
+
+/*
+ * rfd_create_pencil -- the pencil (A, M) of Sec. 1: A symmetric, M symmetric
+ * positive definite, both n x n in CSR with FULL symmetric storage (host
+ * arrays A_ptr[n+1], A_idx[nnz], A_val[nnz], same for M).  Column indices
+ * need not be sorted; duplicates are summed.  The arrays are copied; the
+ * caller keeps ownership.  Errors: RFD_EINVAL if n < 1, an index is out of
+ * range, A or M is not symmetric (|a_ij - a_ji| > 1e-12 max|a|), or some
+ * M_ii <= 0.  Allocates nothing on the device yet.
+ */
+rfd_status rfd_create_pencil(int64_t n, const int64_t* A_ptr, const int32_t* A_idx,
+                             const double* A_val, const int64_t* M_ptr,
+                             const int32_t* M_idx, const double* M_val, rfd_pencil_t* out);
+
+/*
+ * rfd_set_partition -- the interior-first reordering of eq. (2.5).
+ * part[i] in {0..p-1} puts node i in the interior of subdomain part[i];
+ * part[i] = -1 makes it an interface node (host array of length n).  Interior
+ * nodes of each subdomain and the interface keep ascending global order; the
+ * interface block of every interface-sized array in this API uses that order.
+ * Errors: RFD_EINVAL if p < 1, a subdomain is empty, a value is out of range,
+ * or two different subdomains are coupled directly (in |A| + |M|) rather than
+ * through the interface.  Uploads the pencil and index maps to the device
+ * (RFD_ENOMEM / RFD_EDEVICE).  Drops every factor and cache of the pencil.
+ */
+rfd_status rfd_set_partition(rfd_pencil_t pencil, int32_t p, const int32_t* part);
+
+/*
+ * rfd_set_interval_and_poles -- the filter of Sec. 2.1 on the circle with
+ * centre (alpha+beta)/2 and radius (beta-alpha)/2.  rule = RFD_RULE_GAUSS:
+ * n_c Gauss-Legendre nodes on the upper half circle; RFD_RULE_MIDPOINT: the
+ * n_c upper-half nodes of the 2 n_c-point midpoint rule (the paper's choice,
+ * Sec. 6); RFD_RULE_EXPLICIT: zeta[2 n_c] and omega[2 n_c] (host, interleaved
+ * re, im) give the n_c upper-half-plane poles and weights, and the filter is
+ * rho(x) = 2 Re sum_l omega_l / (x - zeta_l), eq. (2.3).  For the built-in
+ * rules zeta/omega may be NULL.  Errors: RFD_EINVAL if alpha >= beta,
+ * n_c < 1 or n_c > 64, or an explicit pole has Im <= 0.  Invalidates the
+ * per-pole factors; keeps the per-pencil caches.
+ */
+rfd_status rfd_set_interval_and_poles(rfd_pencil_t pencil, double alpha, double beta,
+                                      int32_t n_c, int32_t rule, const double* zeta,
+                                      const double* omega);
+
+/*
+ * rfd_set_precision -- RFD_FP64 (default): every factorization and solve in
+ * FP64.  RFD_FP32_REFINE: the shifted interior blocks B_j - zeta M_Bj and the
+ * Schur complements S(zeta) are factored in FP32 on the matrix cores and
+ * every shifted solve is refined in FP64 (FP64 residuals against the FP64
+ * operators) until ||r||_F <= refine_tol ||b||_F, at most max_sweeps
+ * corrections (refine_tol <= 0 or max_sweeps <= 0 select 1e-13 and 8).
+ * Orthonormalisation, the interior levels' residuals and Rayleigh-Ritz stay
+ * FP64.  Errors: RFD_EINVAL for an unknown mode.  Invalidates the factors.
+ */
+rfd_status rfd_set_precision(rfd_pencil_t pencil, int32_t mode, double refine_tol,
+                             int32_t max_sweeps);
+
+/*
+ * rfd_filter_interface -- the interface subspace (Sec. 3.1-3.2).
+ * Factors B_j - zeta_l M_Bj and S(zeta_l), l = 1..n_c, on the first call
+ * after a change of poles/precision/partition, then keeps them.
+ * F = 2 Re sum_l omega_l S(zeta_l)^{-1} (eq. (3.5)); with W_1 = F Y0,
+ * Q_1 = orth(W_1), Q_t = orth(F Q_{t-1}) against [Q_1..Q_{t-1}] (twice),
+ * t = 2..steps, Q = [Q_1 .. Q_steps] (a block form of Alg. 3.1 with full
+ * reorthogonalisation).  orth() drops directions whose residual norm is
+ * <= 1e-13 times the largest column norm of the unprojected block.
+ *   m       block width, 1 <= m <= s
+ *   Y0      device, s x m, leading dimension s (FP64)
+ *   steps   >= 1
+ *   Q       device, s x ldq_cols with leading dimension s, caller-owned;
+ *           ldq_cols >= min(s, steps * m); receives mu orthonormal columns
+ *   mu      host out: number of columns written
+ * Errors: RFD_ESTATE before set_partition / set_interval_and_poles,
+ * RFD_EINVAL for bad sizes, RFD_EBREAKDOWN on a pivot below 1e-300 (FP64) or
+ * 1e-30 (FP32) in magnitude, RFD_ENOCONV if refinement stalls, RFD_ENOMEM.
+ */
+rfd_status rfd_filter_interface(rfd_pencil_t pencil, int32_t m, const double* Y0,
+                                int32_t steps, double* Q, int64_t ldq_cols, int32_t* mu,
+                                rfd_stream_t stream);
+
+/*
+ * rfd_filter_apply -- one application of the interface filter, the left side
+ * of eq. (3.5): W = 2 Re sum_l omega_l S(zeta_l)^{-1} Y (the factor 2 of
+ * eq. (3.5); Alg. 3.1 line 2 omits it, which does not change the range).
+ * Uses (and on first use builds) the same factors as rfd_filter_interface.
+ *   m   number of columns, m >= 1
+ *   Y   device, s x m, leading dimension s (FP64)
+ *   W   device, s x m, leading dimension s (FP64), caller-owned; may not alias Y
+ * Errors as rfd_filter_interface.
+ */
+rfd_status rfd_filter_apply(rfd_pencil_t pencil, int32_t m, const double* Y, double* W,
+                            rfd_stream_t stream);
+
+/*
+ * rfd_solve_interior -- the interior part (Sec. 4 and 5.1) for the Q of the
+ * last rfd_filter_interface call.
+ * V_j: eigenvectors of (B_j, M_Bj) for the nev_b eigenvalues closest to
+ * sigma (a cluster at the cut is kept whole), M_Bj-orthonormal (Alg. 5.1
+ * step 3; cached per pencil and sigma).  Sigma_j^(psi), Gamma_j^(psi) as in
+ * eqs. (5.2)-(5.4) with B_sigma = B_j - sigma M_Bj; every level is made
+ * M_Bj-orthogonal to V_j before the next one is formed (this leaves range(Z)
+ * unchanged because V_j is part of Z).  Z of eq. (5.5) stays on the device.
+ *   k_out   host out: number of columns of Z
+ * Errors: RFD_ESTATE without a Q, RFD_EINVAL for nev_b < 0 or psi < 1,
+ * RFD_EBREAKDOWN if B_sigma is singular to working precision.
+ */
+rfd_status rfd_solve_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b, int32_t psi,
+                              int64_t* k_out, rfd_stream_t stream);
+
+/*
+ * rfd_rayleigh_ritz -- Alg. 5.1 steps 6-8: Z^T A Z G = Z^T M Z G Theta on an
+ * M-orthonormal basis of range(Z) (directions below 1e-12 relative dropped),
+ * Ritz values theta in [alpha, beta] ascending, Ritz vectors x = Z g
+ * permuted back to the original numbering, residuals
+ * ||A x - theta M x||_2 / (||A|| ||x||_2) with ||A|| the largest absolute row
+ * sum of A.
+ *   max_out  capacity of the outputs
+ *   evals    device, max_out           (FP64)
+ *   evecs    device, n x max_out, ld n (FP64), or NULL
+ *   resid    device, max_out, or NULL (then not computed)
+ *   nfound   host out: number of Ritz values in [alpha, beta]; set also when
+ *            it exceeds max_out, in which case RFD_EINVAL is returned and only
+ *            the first max_out are written.
+ */
+rfd_status rfd_rayleigh_ritz(rfd_pencil_t pencil, int32_t max_out, double* evals, double* evecs,
+                             double* resid, int32_t* nfound, rfd_stream_t stream);
+
+/*
+ * rfd_reset_caches -- invalidates every factorization and per-pencil cache
+ * (the B_j(zeta), S(zeta) and B_sigma factors, V_j, Z) while keeping the
+ * pencil, partition, poles and precision; the next calls recompute them.
+ * release = 0 keeps the device buffers for reuse (no allocation on the next
+ * solve of the same shape); release = 1 frees them.
+ */
+rfd_status rfd_reset_caches(rfd_pencil_t pencil, int32_t release);
+
+/* Frees the handle and every device buffer it owns.  NULL is accepted. */
+rfd_status rfd_destroy_pencil(rfd_pencil_t pencil);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* rfd_last_error(void);
+
+/*
+ * rfd_pencil_info -- sizes of a partitioned pencil (host outputs, any may be
+ * NULL): n, p, s, max interior size, and the device bytes currently held.
+ */
+rfd_status rfd_pencil_info(rfd_pencil_t pencil, int64_t* n, int32_t* p, int64_t* s,
+                           int64_t* d_max, int64_t* device_bytes);
+
+/*
+ * rfd_phase_times -- milliseconds spent in each phase of the last calls,
+ * measured with HIP events on the work stream (host array of 16 doubles):
+ * [0] factor B_j(zeta), [1] Schur solves + refinement, [2] Schur assembly,
+ * [3] factor S(zeta), [4] filter solves + refinement, [5] orthonormalisation,
+ * [6] interior basis V_j, [7] factor B_sigma, [8] resolvent levels,
+ * [9] Rayleigh-Ritz projection, [10] small eigensolve, [11] Ritz vectors and
+ * residuals, [12] refinement sweeps (max, Schur solves), [13] refinement
+ * sweeps (max, filter solves), [14], [15] reserved.  Timing is enabled by
+ * rfd_set_timing(pencil, 1); it adds event records but no synchronisation
+ * until this call.
+ */
+rfd_status rfd_set_timing(rfd_pencil_t pencil, int32_t on);
+rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFD_H_ */

@@ -1,0 +1,271 @@
+"""Python binding of the RF-DDES gfx950 library (librfd.so, include/rfd.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors on ``cuda``) and the stream.
+The functions keep the C names; ``Pencil`` is a thin convenience wrapper.
+There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = [
+    "RfdError", "lib", "Pencil", "RFD_FP64", "RFD_FP32_REFINE", "RFD_RULE_GAUSS",
+    "RFD_RULE_MIDPOINT", "RFD_RULE_EXPLICIT", "LIB_PATH",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfd.so")
+RFD_FP64, RFD_FP32_REFINE = 0, 1
+RFD_RULE_GAUSS, RFD_RULE_MIDPOINT, RFD_RULE_EXPLICIT = 0, 1, 2
+STATUS = {0: "RFD_OK", 1: "RFD_EINVAL", 2: "RFD_ENOMEM", 3: "RFD_EBREAKDOWN",
+          4: "RFD_ENOCONV", 5: "RFD_EDEVICE", 6: "RFD_ESTATE"}
+
+EXPORTS = [
+    "rfd_create_pencil", "rfd_set_partition", "rfd_set_interval_and_poles",
+    "rfd_set_precision", "rfd_filter_interface", "rfd_filter_apply", "rfd_solve_interior",
+    "rfd_rayleigh_ritz",
+    "rfd_destroy_pencil", "rfd_last_error", "rfd_pencil_info", "rfd_set_timing",
+    "rfd_phase_times", "rfd_reset_caches",
+]
+
+
+class RfdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+P = C.c_void_p
+I32, I64, F64 = C.c_int32, C.c_int64, C.c_double
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_1711_09487_amd.build.build() (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "rfd_create_pencil": [I64, P, P, P, P, P, P, C.POINTER(P)],
+            "rfd_set_partition": [P, I32, P],
+            "rfd_set_interval_and_poles": [P, F64, F64, I32, I32, P, P],
+            "rfd_set_precision": [P, I32, F64, I32],
+            "rfd_filter_interface": [P, I32, P, I32, P, I64, C.POINTER(I32), P],
+            "rfd_solve_interior": [P, F64, I32, I32, C.POINTER(I64), P],
+            "rfd_filter_apply": [P, I32, P, P, P],
+            "rfd_rayleigh_ritz": [P, I32, P, P, P, C.POINTER(I32), P],
+            "rfd_destroy_pencil": [P],
+            "rfd_pencil_info": [P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I64),
+                                C.POINTER(I64), C.POINTER(I64)],
+            "rfd_set_timing": [P, I32],
+            "rfd_reset_caches": [P, I32],
+            "rfd_phase_times": [P, P],
+            "rfd_test_gemm": [I32, I32, I32, I64, I64, I64, F64, F64, P, P, I64, I64, P, P, I64,
+                              I64, P, P, I64, I64, I32, P],
+            "rfd_test_lu": [I32, I32, I64, I32, P, P, I64, I64, P, P, I64, I64, I64,
+                            C.POINTER(C.c_uint32), P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.rfd_last_error.argtypes = []
+        L.rfd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise RfdError(code, lib().rfd_last_error().decode())
+
+
+def _ptr(t):
+    """Device (or host numpy) address of a contiguous array, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        assert t.flags["C_CONTIGUOUS"] or t.flags["F_CONTIGUOUS"]
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+# ---------------------------------------------------------------------------
+# the C entry points, same names
+# ---------------------------------------------------------------------------
+def rfd_create_pencil(A, M):
+    """A, M: scipy.sparse matrices (full symmetric storage)."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix(A)
+    M = sp.csr_matrix(M)
+    n = A.shape[0]
+    arrs = []
+    for X in (A, M):
+        arrs += [np.ascontiguousarray(X.indptr, dtype=np.int64),
+                 np.ascontiguousarray(X.indices, dtype=np.int32),
+                 np.ascontiguousarray(X.data, dtype=np.float64)]
+    h = P()
+    _check(lib().rfd_create_pencil(n, *[a.ctypes.data for a in arrs], C.byref(h)))
+    return h
+
+
+def rfd_set_partition(h, p, part):
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    _check(lib().rfd_set_partition(h, int(p), part.ctypes.data))
+
+
+def rfd_set_interval_and_poles(h, alpha, beta, n_c, rule=RFD_RULE_GAUSS, zeta=None, omega=None):
+    z = w = None
+    if rule == RFD_RULE_EXPLICIT:
+        z = np.ascontiguousarray(np.column_stack([np.real(zeta), np.imag(zeta)]).ravel())
+        w = np.ascontiguousarray(np.column_stack([np.real(omega), np.imag(omega)]).ravel())
+    _check(lib().rfd_set_interval_and_poles(h, float(alpha), float(beta), int(n_c), int(rule),
+                                            None if z is None else z.ctypes.data,
+                                            None if w is None else w.ctypes.data))
+
+
+def rfd_set_precision(h, mode, refine_tol=0.0, max_sweeps=0):
+    _check(lib().rfd_set_precision(h, int(mode), float(refine_tol), int(max_sweeps)))
+
+
+def rfd_filter_interface(h, m, Y0, steps, Q, stream=None):
+    """Y0: device tensor (s x m, column-major = torch tensor of shape (m, s)
+    contiguous); Q: device tensor with room for ldq_cols columns of length s.
+    Returns mu."""
+    mu = I32()
+    ldq_cols = Q.numel() // Y0.shape[-1]
+    _check(lib().rfd_filter_interface(h, int(m), _ptr(Y0), int(steps), _ptr(Q), int(ldq_cols),
+                                      C.byref(mu), _stream(stream)))
+    return mu.value
+
+
+def rfd_filter_apply(h, m, Y, W, stream=None):
+    """W = 2 Re sum_l omega_l S(zeta_l)^{-1} Y; Y, W device tensors (s x m column-major)."""
+    _check(lib().rfd_filter_apply(h, int(m), _ptr(Y), _ptr(W), _stream(stream)))
+
+
+def rfd_solve_interior(h, sigma, nev_b, psi, stream=None):
+    k = I64()
+    _check(lib().rfd_solve_interior(h, float(sigma), int(nev_b), int(psi), C.byref(k),
+                                    _stream(stream)))
+    return k.value
+
+
+def rfd_rayleigh_ritz(h, max_out, evals, evecs=None, resid=None, stream=None):
+    nf = I32()
+    code = lib().rfd_rayleigh_ritz(h, int(max_out), _ptr(evals), _ptr(evecs), _ptr(resid),
+                                   C.byref(nf), _stream(stream))
+    if code != 0:
+        raise RfdError(code, lib().rfd_last_error().decode() + f" (nfound={nf.value})")
+    return nf.value
+
+
+def rfd_destroy_pencil(h):
+    _check(lib().rfd_destroy_pencil(h))
+
+
+def rfd_last_error():
+    return lib().rfd_last_error().decode()
+
+
+def rfd_pencil_info(h):
+    n, s, d, b = I64(), I64(), I64(), I64()
+    p = I32()
+    _check(lib().rfd_pencil_info(h, C.byref(n), C.byref(p), C.byref(s), C.byref(d), C.byref(b)))
+    return dict(n=n.value, p=p.value, s=s.value, d_max=d.value, device_bytes=b.value)
+
+
+def rfd_reset_caches(h, release=False):
+    _check(lib().rfd_reset_caches(h, int(bool(release))))
+
+
+def rfd_set_timing(h, on):
+    _check(lib().rfd_set_timing(h, int(bool(on))))
+
+
+def rfd_phase_times(h):
+    out = np.zeros(16)
+    _check(lib().rfd_phase_times(h, out.ctypes.data))
+    return out
+
+
+class Pencil:
+    """Owning wrapper of a pencil handle (argument marshalling only)."""
+
+    def __init__(self, A, M):
+        self.h = rfd_create_pencil(A, M)
+        self.n = A.shape[0]
+
+    def close(self):
+        if self.h is not None:
+            rfd_destroy_pencil(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_partition(self, part):
+        part = np.asarray(part, dtype=np.int32)
+        rfd_set_partition(self.h, int(part.max()) + 1, part)
+        self.s = int(np.count_nonzero(part < 0))
+
+    def set_interval_and_poles(self, alpha, beta, n_c, rule=RFD_RULE_GAUSS, zeta=None, omega=None):
+        rfd_set_interval_and_poles(self.h, alpha, beta, n_c, rule, zeta, omega)
+
+    def set_precision(self, mode, refine_tol=0.0, max_sweeps=0):
+        rfd_set_precision(self.h, mode, refine_tol, max_sweeps)
+
+    def filter_interface(self, Y0, steps, stream=None):
+        """Y0: torch float64 tensor on the GPU, shape (m, s) (i.e. s x m
+        column-major).  Returns Q as a (mu, s) tensor (s x mu column-major)."""
+        import torch
+        m, s = Y0.shape
+        cols = min(s, steps * m)
+        Q = torch.empty((cols, s), dtype=torch.float64, device=Y0.device)
+        mu = rfd_filter_interface(self.h, m, Y0, steps, Q, stream)
+        return Q[:mu]
+
+    def filter_apply(self, Y, stream=None):
+        import torch
+        W = torch.empty_like(Y)
+        rfd_filter_apply(self.h, Y.shape[0], Y, W, stream)
+        return W
+
+    def solve_interior(self, sigma, nev_b, psi, stream=None):
+        return rfd_solve_interior(self.h, sigma, nev_b, psi, stream)
+
+    def rayleigh_ritz(self, max_out, vectors=True, residuals=True, device="cuda", stream=None):
+        import torch
+        ev = torch.empty(max_out, dtype=torch.float64, device=device)
+        X = torch.empty((max_out, self.n), dtype=torch.float64, device=device) if vectors else None
+        r = torch.empty(max_out, dtype=torch.float64, device=device) if residuals else None
+        nf = rfd_rayleigh_ritz(self.h, max_out, ev, X, r, stream)
+        return ev[:nf], (X[:nf] if X is not None else None), (r[:nf] if r is not None else None)
+
+    def reset_caches(self, release=False):
+        rfd_reset_caches(self.h, release)
+
+    def set_timing(self, on=True):
+        rfd_set_timing(self.h, on)
+
+    def phase_times(self):
+        return rfd_phase_times(self.h)
+
+    def info(self):
+        return rfd_pencil_info(self.h)

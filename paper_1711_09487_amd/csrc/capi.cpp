@@ -1,0 +1,204 @@
+// The C ABI (include/rfd.h): argument checks, handle lifetime, and the map
+// from C++ exceptions to rfd_status codes.
+#include <cstring>
+#include <memory>
+
+#include "../../include/rfd.h"
+#include "engine.hpp"
+#include "pencil.hpp"
+#include "rfd_capi_util.hpp"
+
+namespace rfd {
+std::string& last_error_slot() {
+  static thread_local std::string msg;
+  return msg;
+}
+}  // namespace rfd
+
+using namespace rfd;
+
+struct rfd_pencil_s {
+  Csr A, M;
+  std::unique_ptr<Partition> part;
+  Poles poles;
+  int mode = RFD_FP64;
+  double tol = 1e-13;
+  int sweeps = 8;
+  bool timing = false;
+  std::unique_ptr<Engine> eng;
+};
+
+static rfd_pencil_s* need(rfd_pencil_t p) {
+  if (!p) throw Error(ST_EINVAL, "null pencil handle");
+  return p;
+}
+
+static Engine& need_engine(rfd_pencil_s* p) {
+  if (!p->part || !p->eng) throw Error(ST_ESTATE, "rfd_set_partition has not been called");
+  return *p->eng;
+}
+
+extern "C" {
+
+rfd_status rfd_create_pencil(int64_t n, const int64_t* A_ptr, const int32_t* A_idx,
+                             const double* A_val, const int64_t* M_ptr, const int32_t* M_idx,
+                             const double* M_val, rfd_pencil_t* out) {
+  return (rfd_status)capi_guard([&] {
+    if (!out) throw Error(ST_EINVAL, "null output handle");
+    *out = nullptr;
+    auto p = std::make_unique<rfd_pencil_s>();
+    p->A = make_csr(n, A_ptr, A_idx, A_val, "A");
+    p->M = make_csr(n, M_ptr, M_idx, M_val, "M");
+    check_symmetric(p->A, "A");
+    check_symmetric(p->M, "M");
+    for (int64_t i = 0; i < n; ++i) {
+      double d = 0;
+      for (int64_t e = p->M.ptr[i]; e < p->M.ptr[i + 1]; ++e)
+        if (p->M.idx[e] == i) d += p->M.val[e];
+      if (!(d > 0)) throw Error(ST_EINVAL, "M has a non-positive diagonal entry");
+    }
+    *out = p.release();
+  });
+}
+
+rfd_status rfd_set_partition(rfd_pencil_t pencil, int32_t p, const int32_t* part) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    P->eng.reset();
+    P->part.reset();
+    auto pt = std::make_unique<Partition>(make_partition(P->A, P->M, p, part));
+    P->eng = std::make_unique<Engine>(P->A, P->M, *pt);
+    P->part = std::move(pt);
+    P->eng->set_precision(P->mode, P->tol, P->sweeps);
+    P->eng->set_timing(P->timing);
+    if (P->poles.set) P->eng->set_poles(P->poles);
+  });
+}
+
+rfd_status rfd_set_interval_and_poles(rfd_pencil_t pencil, double alpha, double beta, int32_t n_c,
+                                      int32_t rule, const double* zeta, const double* omega) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Poles q;
+    make_poles(q, alpha, beta, n_c, rule, zeta, omega);
+    P->poles = q;
+    if (P->eng) P->eng->set_poles(P->poles);
+  });
+}
+
+rfd_status rfd_set_precision(rfd_pencil_t pencil, int32_t mode, double refine_tol,
+                             int32_t max_sweeps) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    if (mode != RFD_FP64 && mode != RFD_FP32_REFINE) throw Error(ST_EINVAL, "unknown precision mode");
+    P->mode = mode;
+    P->tol = refine_tol > 0 ? refine_tol : 1e-13;
+    P->sweeps = max_sweeps > 0 ? max_sweeps : 8;
+    if (P->eng) P->eng->set_precision(P->mode, P->tol, P->sweeps);
+  });
+}
+
+rfd_status rfd_filter_interface(rfd_pencil_t pencil, int32_t m, const double* Y0, int32_t steps,
+                                double* Q, int64_t ldq_cols, int32_t* mu, rfd_stream_t stream) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    if (!P->poles.set) throw Error(ST_ESTATE, "rfd_set_interval_and_poles has not been called");
+    const int64_t s = (int64_t)P->part->iface.size();
+    if (m < 1 || m > s) throw Error(ST_EINVAL, "need 1 <= m <= s");
+    if (steps < 1) throw Error(ST_EINVAL, "need steps >= 1");
+    if (!Y0 || !Q || !mu) throw Error(ST_EINVAL, "null pointer argument");
+    if (ldq_cols < std::min<int64_t>(s, (int64_t)steps * m))
+      throw Error(ST_EINVAL, "Q has too few columns");
+    int mu_i = 0;
+    E.filter_interface((hipStream_t)stream, m, Y0, steps, Q, ldq_cols, &mu_i);
+    *mu = mu_i;
+  });
+}
+
+rfd_status rfd_filter_apply(rfd_pencil_t pencil, int32_t m, const double* Y, double* W,
+                            rfd_stream_t stream) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    if (!P->poles.set) throw Error(ST_ESTATE, "rfd_set_interval_and_poles has not been called");
+    if (m < 1) throw Error(ST_EINVAL, "need m >= 1");
+    if (!Y || !W || Y == W) throw Error(ST_EINVAL, "null or aliased pointer argument");
+    E.filter_apply((hipStream_t)stream, m, Y, W);
+  });
+}
+
+rfd_status rfd_solve_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b, int32_t psi,
+                              int64_t* k_out, rfd_stream_t stream) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    if (nev_b < 0) throw Error(ST_EINVAL, "need nev_b >= 0");
+    if (psi < 1) throw Error(ST_EINVAL, "need psi >= 1");
+    if (!std::isfinite(sigma)) throw Error(ST_EINVAL, "sigma is not finite");
+    int64_t k = 0;
+    E.solve_interior((hipStream_t)stream, sigma, nev_b, psi, &k);
+    if (k_out) *k_out = k;
+  });
+}
+
+rfd_status rfd_rayleigh_ritz(rfd_pencil_t pencil, int32_t max_out, double* evals, double* evecs,
+                             double* resid, int32_t* nfound, rfd_stream_t stream) {
+  int found = 0;
+  rfd_status st = (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    if (max_out < 0) throw Error(ST_EINVAL, "need max_out >= 0");
+    if (!nfound) throw Error(ST_EINVAL, "null nfound");
+    if (max_out > 0 && !evals) throw Error(ST_EINVAL, "null evals");
+    E.rayleigh_ritz((hipStream_t)stream, max_out, evals, evecs, resid, &found);
+    *nfound = found;
+    if (found > max_out)
+      throw Error(ST_EINVAL, "more Ritz values in [alpha, beta] than max_out");
+  });
+  return st;
+}
+
+rfd_status rfd_reset_caches(rfd_pencil_t pencil, int32_t release) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    if (P->eng) P->eng->reset_caches(release != 0);
+  });
+}
+
+rfd_status rfd_destroy_pencil(rfd_pencil_t pencil) {
+  return (rfd_status)capi_guard([&] { delete pencil; });
+}
+
+const char* rfd_last_error(void) { return last_error_slot().c_str(); }
+
+rfd_status rfd_pencil_info(rfd_pencil_t pencil, int64_t* n, int32_t* p, int64_t* s,
+                           int64_t* d_max, int64_t* device_bytes) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    if (n) *n = P->A.n;
+    if (p) *p = P->part ? P->part->p : 0;
+    if (s) *s = P->part ? (int64_t)P->part->iface.size() : 0;
+    if (d_max) *d_max = P->part ? P->part->d_max : 0;
+    if (device_bytes) *device_bytes = P->eng ? P->eng->device_bytes() : 0;
+  });
+}
+
+rfd_status rfd_set_timing(rfd_pencil_t pencil, int32_t on) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    P->timing = on != 0;
+    if (P->eng) P->eng->set_timing(P->timing);
+  });
+}
+
+rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    if (!ms16) throw Error(ST_EINVAL, "null output");
+    for (int i = 0; i < 16; ++i) ms16[i] = 0;
+    if (P->eng) P->eng->phase_times(ms16);
+  });
+}
+
+}  // extern "C"

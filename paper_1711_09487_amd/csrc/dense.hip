@@ -1,0 +1,638 @@
+// Dense batched kernels for gfx950: MFMA GEMM (FP32 / FP64, real / planar
+// complex), LU factorization (blocked, right-looking; the diagonal block is
+// factored and inverted in LDS), pivoted panel factorization, triangular
+// solves through inverted diagonal blocks, elementwise helpers.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "dense.hpp"
+
+namespace rfd {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// GEMM.  Workgroup tile 64 x 64, 4 waves of 32 x 32.  FP32 uses
+// v_mfma_f32_32x32x2f32 (one 32 x 32 block per wave), FP64 uses
+// v_mfma_f64_16x16x4f64 (2 x 2 blocks per wave).  A complex product is four
+// real products into two accumulators (Re += ar br - ai bi, Im += ar bi + ai br).
+// Operand lane layouts: 32x32x2 -- lane l holds A[l%32][l/32], B[l/32][l%32];
+// D register r of lane l is element (8 (r/4) + 4 (l/32) + r%4, l%32).
+// 16x16x4 -- lane l holds A[l%16][l/16], B[l/16][l%16]; D register r is
+// element ((l/16) + 4 r, l%16) (checked on gfx950).
+// ---------------------------------------------------------------------------
+constexpr int GBM = 64, GBN = 64, GKT = 16;
+
+template <typename T, bool CPLX, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T alpha, T beta,
+                                              DMat<T> A, DMat<T> B, DMat<T> C) {
+  constexpr int NP = CPLX ? 2 : 1;
+  __shared__ T As[NP][GKT][GBM + 4];
+  __shared__ T Bs[NP][GKT][GBN + 4];
+  const int64_t m0 = (int64_t)blockIdx.x * GBM, n0 = (int64_t)blockIdx.y * GBN;
+  if (m0 >= M || n0 >= N) return;
+  A = A.item(blockIdx.z);
+  B = B.item(blockIdx.z);
+  C = C.item(blockIdx.z);
+  const bool aim = CPLX && A.im != nullptr;
+  const bool bim = CPLX && B.im != nullptr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+
+  floatx16 fr = {0}, fi = {0};
+  doublex4 dr[2][2], di[2][2];
+  if constexpr (std::is_same<T, double>::value) {
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y) {
+        dr[x][y] = doublex4{0, 0, 0, 0};
+        di[x][y] = doublex4{0, 0, 0, 0};
+      }
+  }
+
+  for (int64_t k0 = 0; k0 < K; k0 += GKT) {
+    for (int e = tid; e < GBM * GKT; e += 256) {
+      int i, k;
+      if (!TA) { i = e % GBM; k = e / GBM; } else { k = e % GKT; i = e / GKT; }
+      const int64_t gi = m0 + i, gk = k0 + k;
+      T vr = 0, vi = 0;
+      if (gi < M && gk < K) {
+        const int64_t off = TA ? (gk + gi * A.ld) : (gi + gk * A.ld);
+        vr = A.re[off];
+        if (aim) vi = A.im[off];
+      }
+      As[0][k][i] = vr;
+      if constexpr (CPLX) As[NP - 1][k][i] = vi;
+    }
+    for (int e = tid; e < GBN * GKT; e += 256) {
+      int j, k;
+      if (!TB) { k = e % GKT; j = e / GKT; } else { j = e % GBN; k = e / GBN; }
+      const int64_t gj = n0 + j, gk = k0 + k;
+      T vr = 0, vi = 0;
+      if (gj < N && gk < K) {
+        const int64_t off = TB ? (gj + gk * B.ld) : (gk + gj * B.ld);
+        vr = B.re[off];
+        if (bim) vi = B.im[off];
+      }
+      Bs[0][k][j] = vr;
+      if constexpr (CPLX) Bs[NP - 1][k][j] = vi;
+    }
+    __syncthreads();
+    if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+      for (int kk = 0; kk < GKT; kk += 2) {
+        const int kr = kk + (lane >> 5), r = lane & 31;
+        const float ar = As[0][kr][wm + r], br = Bs[0][kr][wn + r];
+        fr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, fr, 0, 0, 0);
+        if constexpr (CPLX) {
+          const float ai = As[NP - 1][kr][wm + r], bi = Bs[NP - 1][kr][wn + r];
+          fr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, fr, 0, 0, 0);
+          fi = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, fi, 0, 0, 0);
+          fi = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, fi, 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < GKT; kk += 4) {
+        const int kr = kk + (lane >> 4), r = lane & 15;
+        double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          ar[x] = As[0][kr][wm + 16 * x + r];
+          br[x] = Bs[0][kr][wn + 16 * x + r];
+          if constexpr (CPLX) {
+            ai[x] = As[NP - 1][kr][wm + 16 * x + r];
+            bi[x] = Bs[NP - 1][kr][wn + 16 * x + r];
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            dr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], br[y], dr[x][y], 0, 0, 0);
+            if constexpr (CPLX) {
+              dr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[x], bi[y], dr[x][y], 0, 0, 0);
+              di[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], bi[y], di[x][y], 0, 0, 0);
+              di[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], br[y], di[x][y], 0, 0, 0);
+            }
+          }
+      }
+    }
+    __syncthreads();
+  }
+
+  auto store = [&](int64_t row, int64_t col, T vr, T vi) {
+    if (row >= M || col >= N) return;
+    const int64_t off = row + col * C.ld;
+    T outr = alpha * vr, outi = alpha * vi;
+    if (beta != T(0)) {
+      outr += beta * C.re[off];
+      if constexpr (CPLX) outi += beta * C.im[off];
+    }
+    C.re[off] = outr;
+    if constexpr (CPLX) C.im[off] = outi;
+  };
+  if constexpr (std::is_same<T, float>::value) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int64_t col = n0 + wn + (lane & 31);
+      store(row, col, fr[r], CPLX ? fi[r] : 0.0f);
+    }
+  } else {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wm + 16 * x + (lane >> 4) + 4 * r;
+          const int64_t col = n0 + wn + 16 * y + (lane & 15);
+          store(row, col, dr[x][y][r], CPLX ? di[x][y][r] : 0.0);
+        }
+  }
+}
+
+template <typename T, bool CPLX>
+static void gemm_dispatch(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N,
+                          int64_t K, T alpha, T beta, DMat<T> A, DMat<T> B, DMat<T> C) {
+  if (!ta && !tb) k_gemm<T, CPLX, false, false><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C);
+  else if (ta && !tb) k_gemm<T, CPLX, true, false><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C);
+  else if (!ta && tb) k_gemm<T, CPLX, false, true><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C);
+  else k_gemm<T, CPLX, true, true><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C);
+}
+
+template <typename T>
+void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, DMat<T> A,
+          DMat<T> B, T beta, DMat<T> C, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (batch > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
+  dim3 g((unsigned)((M + GBM - 1) / GBM), (unsigned)((N + GBN - 1) / GBN), (unsigned)batch);
+  if (C.cplx()) gemm_dispatch<T, true>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C);
+  else gemm_dispatch<T, false>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C);
+  RFD_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Scalar complex helpers on (re, im) pairs.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void cmul(T ar, T ai, T br, T bi, T& cr, T& ci) {
+  cr = ar * br - ai * bi;
+  ci = ar * bi + ai * br;
+}
+template <typename T>
+__device__ inline void cinv(T ar, T ai, T& cr, T& ci) {
+  // 1 / (ar + i ai), scaled to avoid overflow of |a|^2
+  const T s = fabs(ar) > fabs(ai) ? fabs(ar) : fabs(ai);
+  const T xr = ar / s, xi = ai / s;
+  const T d = (xr * xr + xi * xi) * s;
+  cr = xr / d;
+  ci = -xi / d;
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal block: factor an NB x NB block without pivoting in LDS, write it
+// back, and write the inverses of its unit-lower and upper triangles.
+// One workgroup per batch item.
+// ---------------------------------------------------------------------------
+template <typename T, bool CPLX>
+__device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], DMat<T> Linv,
+                             DMat<T> Uinv) {
+  constexpr int NP = CPLX ? 2 : 1;
+  const int tid = threadIdx.x;
+  // Linv: column c solved by thread c (forward substitution, unit diagonal)
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = 0; i < NB; ++i) {
+      T sr = (i == c) ? T(1) : T(0), si = 0;
+      if (i > c) {
+        for (int t = c; t < i; ++t) {
+          if constexpr (CPLX) {
+            T pr, pi;
+            cmul(F[0][i][t], F[NP - 1][i][t], X[0][t][c], X[NP - 1][t][c], pr, pi);
+            sr -= pr;
+            si -= pi;
+          } else {
+            sr -= F[0][i][t] * X[0][t][c];
+          }
+        }
+      }
+      X[0][i][c] = sr;
+      if constexpr (CPLX) X[NP - 1][i][c] = si;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += blockDim.x) {
+    const int i = e % NB, c = e / NB;
+    Linv.re[i + c * Linv.ld] = X[0][i][c];
+    if constexpr (CPLX) Linv.im[i + c * Linv.ld] = X[NP - 1][i][c];
+  }
+  __syncthreads();
+  // Uinv: column c by thread c (back substitution)
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = NB - 1; i >= 0; --i) {
+      T sr = 0, si = 0;
+      if (i <= c) {
+        sr = (i == c) ? T(1) : T(0);
+        for (int t = i + 1; t <= c; ++t) {
+          if constexpr (CPLX) {
+            T pr, pi;
+            cmul(F[0][i][t], F[NP - 1][i][t], X[0][t][c], X[NP - 1][t][c], pr, pi);
+            sr -= pr;
+            si -= pi;
+          } else {
+            sr -= F[0][i][t] * X[0][t][c];
+          }
+        }
+        if constexpr (CPLX) {
+          T ir, ii, qr, qi;
+          cinv(F[0][i][i], F[NP - 1][i][i], ir, ii);
+          cmul(sr, si, ir, ii, qr, qi);
+          sr = qr;
+          si = qi;
+        } else {
+          sr = sr / F[0][i][i];
+        }
+      }
+      X[0][i][c] = sr;
+      if constexpr (CPLX) X[NP - 1][i][c] = si;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += blockDim.x) {
+    const int i = e % NB, c = e / NB;
+    Uinv.re[i + c * Uinv.ld] = X[0][i][c];
+    if constexpr (CPLX) Uinv.im[i + c * Uinv.ld] = X[NP - 1][i][c];
+  }
+}
+
+template <typename T, bool CPLX>
+__global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> inv, int iblk,
+                                                 unsigned* flags, T tiny) {
+  constexpr int NP = CPLX ? 2 : 1;
+  __shared__ T F[NP][NB][NB + 1];
+  __shared__ T X[NP][NB][NB + 1];
+  const int tid = threadIdx.x;
+  DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e % NB, j = e / NB;
+    F[0][i][j] = a.re[i + j * a.ld];
+    if constexpr (CPLX) F[NP - 1][i][j] = a.im[i + j * a.ld];
+  }
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    const T pr = F[0][j][j], pim = CPLX ? F[NP - 1][j][j] : T(0);
+    const T mag = CPLX ? sqrt(pr * pr + pim * pim) : fabs(pr);
+    if (tid == 0) {
+      if (!(mag > tiny)) atomicOr(flags, (mag == mag) ? 1u : 2u);
+    }
+    T ir, ii = 0;
+    if constexpr (CPLX) cinv(pr, pim, ir, ii);
+    else ir = T(1) / pr;
+    for (int i = j + 1 + tid; i < NB; i += 256) {
+      if constexpr (CPLX) {
+        T qr, qi;
+        cmul(F[0][i][j], F[NP - 1][i][j], ir, ii, qr, qi);
+        F[0][i][j] = qr;
+        F[NP - 1][i][j] = qi;
+      } else {
+        F[0][i][j] *= ir;
+      }
+    }
+    __syncthreads();
+    const int w = NB - 1 - j;
+    for (int e = tid; e < w * w; e += 256) {
+      const int i = j + 1 + e % w, c = j + 1 + e / w;
+      if constexpr (CPLX) {
+        T pr2, pi2;
+        cmul(F[0][i][j], F[NP - 1][i][j], F[0][j][c], F[NP - 1][j][c], pr2, pi2);
+        F[0][i][c] -= pr2;
+        F[NP - 1][i][c] -= pi2;
+      } else {
+        F[0][i][c] -= F[0][i][j] * F[0][j][c];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e % NB, j = e / NB;
+    a.re[i + j * a.ld] = F[0][i][j];
+    if constexpr (CPLX) a.im[i + j * a.ld] = F[NP - 1][i][j];
+  }
+  DMat<T> iv = inv.item(blockIdx.x);
+  tri_inverses<T, CPLX>(F, X, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB));
+}
+
+// Inverses only (block already factored, e.g. by the pivoted panel).
+template <typename T, bool CPLX>
+__global__ __launch_bounds__(256) void k_tri_inv(DMat<T> A, int64_t k0, DMat<T> inv, int iblk) {
+  constexpr int NP = CPLX ? 2 : 1;
+  __shared__ T F[NP][NB][NB + 1];
+  __shared__ T X[NP][NB][NB + 1];
+  const int tid = threadIdx.x;
+  DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e % NB, j = e / NB;
+    F[0][i][j] = a.re[i + j * a.ld];
+    if constexpr (CPLX) F[NP - 1][i][j] = a.im[i + j * a.ld];
+  }
+  __syncthreads();
+  DMat<T> iv = inv.item(blockIdx.x);
+  tri_inverses<T, CPLX>(F, X, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB));
+}
+
+template <typename T>
+void lu_nopiv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, unsigned* flags,
+              double tiny) {
+  if (n % NB) throw Error(ST_EINVAL, "lu_nopiv: n not a multiple of the block size");
+  const int64_t nblk = n / NB;
+  for (int64_t i = 0; i < nblk; ++i) {
+    const int64_t k0 = i * NB, rest = n - k0 - NB;
+    if (A.cplx())
+      k_lu_diag<T, true><<<batch, 256, 0, s>>>(A, k0, inv, (int)i, flags, (T)tiny);
+    else
+      k_lu_diag<T, false><<<batch, 256, 0, s>>>(A, k0, inv, (int)i, flags, (T)tiny);
+    RFD_CHECK_LAUNCH();
+    if (rest > 0) {
+      DMat<T> Linv = inv.sub(0, 2 * NB * i), Uinv = inv.sub(0, 2 * NB * i + NB);
+      gemm<T>(s, false, false, rest, NB, NB, T(1), A.sub(k0 + NB, k0), Uinv, T(0),
+              A.sub(k0 + NB, k0), batch);
+      gemm<T>(s, false, false, NB, rest, NB, T(1), Linv, A.sub(k0, k0 + NB), T(0),
+              A.sub(k0, k0 + NB), batch);
+      gemm<T>(s, false, false, rest, rest, NB, T(-1), A.sub(k0 + NB, k0), A.sub(k0, k0 + NB),
+              T(1), A.sub(k0 + NB, k0 + NB), batch);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Partial pivoting (real data): panel of width NB, rows k0..n-1, factored by
+// one workgroup per item directly in global memory.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_panel_piv(DMat<T> A, int64_t n, int64_t k0,
+                                                   int32_t* ipiv, unsigned* flags, T tiny) {
+  __shared__ T sval[256];
+  __shared__ int sidx[256];
+  __shared__ T prow[NB];
+  const int tid = threadIdx.x;
+  DMat<T> a = A.item(blockIdx.x);
+  int32_t* piv = ipiv + (int64_t)blockIdx.x * n;
+  for (int j = 0; j < NB; ++j) {
+    const int64_t col = k0 + j;
+    // argmax |a(i, col)|, i >= col (first index on ties)
+    T best = -1;
+    int bi = (int)col;
+    for (int64_t i = col + tid; i < n; i += 256) {
+      const T v = fabs(a.re[i + col * a.ld]);
+      if (v > best) { best = v; bi = (int)i; }
+    }
+    sval[tid] = best;
+    sidx[tid] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) {
+        const T v2 = sval[tid + w];
+        const int i2 = sidx[tid + w];
+        if (v2 > sval[tid] || (v2 == sval[tid] && i2 < sidx[tid])) {
+          sval[tid] = v2;
+          sidx[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = sidx[0];
+    const T pmag = sval[0];
+    __syncthreads();
+    if (tid == 0) {
+      piv[col] = p;
+      if (!(pmag > tiny)) atomicOr(flags, (pmag == pmag) ? 1u : 2u);
+    }
+    // swap rows col and p within the panel columns
+    if (p != col && tid < NB) {
+      const int64_t c = k0 + tid;
+      const T t = a.re[col + c * a.ld];
+      a.re[col + c * a.ld] = a.re[p + c * a.ld];
+      a.re[p + c * a.ld] = t;
+    }
+    __syncthreads();
+    if (tid < NB) prow[tid] = a.re[col + (k0 + tid) * a.ld];
+    __syncthreads();
+    const T inv = T(1) / prow[j];
+    for (int64_t i = col + 1 + tid; i < n; i += 256) {
+      const T l = a.re[i + col * a.ld] * inv;
+      a.re[i + col * a.ld] = l;
+      for (int c = j + 1; c < NB; ++c) a.re[i + (k0 + c) * a.ld] -= l * prow[c];
+    }
+    __syncthreads();
+  }
+}
+
+// Row interchanges ipiv[k0 .. k0+cnt) applied in order to columns [c0, c1).
+template <typename T>
+__global__ void k_laswp(DMat<T> A, int64_t n, const int32_t* ipiv, int64_t k0, int64_t cnt,
+                        int64_t c0, int64_t c1) {
+  const int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  DMat<T> a = A.item(blockIdx.y);
+  const int32_t* piv = ipiv + (int64_t)blockIdx.y * n;
+  for (int64_t i = k0; i < k0 + cnt; ++i) {
+    const int64_t p = piv[i];
+    if (p != i) {
+      const T t = a.re[i + c * a.ld];
+      a.re[i + c * a.ld] = a.re[p + c * a.ld];
+      a.re[p + c * a.ld] = t;
+    }
+  }
+}
+
+template <typename T>
+static void laswp(hipStream_t s, DMat<T> A, int64_t n, const int32_t* ipiv, int64_t k0,
+                  int64_t cnt, int64_t c0, int64_t c1, int batch) {
+  if (c1 <= c0) return;
+  dim3 g(grid1(c1 - c0), batch);
+  k_laswp<T><<<g, 256, 0, s>>>(A, n, ipiv, k0, cnt, c0, c1);
+  RFD_CHECK_LAUNCH();
+}
+
+template <typename T>
+void lu_piv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, int32_t* ipiv,
+            unsigned* flags, double tiny) {
+  if (n % NB) throw Error(ST_EINVAL, "lu_piv: n not a multiple of the block size");
+  if (A.cplx()) throw Error(ST_EINVAL, "lu_piv: real data only");
+  const int64_t nblk = n / NB;
+  for (int64_t i = 0; i < nblk; ++i) {
+    const int64_t k0 = i * NB, rest = n - k0 - NB;
+    k_panel_piv<T><<<batch, 256, 0, s>>>(A, n, k0, ipiv, flags, (T)tiny);
+    RFD_CHECK_LAUNCH();
+    laswp<T>(s, A, n, ipiv, k0, NB, 0, k0, batch);
+    laswp<T>(s, A, n, ipiv, k0, NB, k0 + NB, n, batch);
+    k_tri_inv<T, false><<<batch, 256, 0, s>>>(A, k0, inv, (int)i);
+    RFD_CHECK_LAUNCH();
+    if (rest > 0) {
+      DMat<T> Linv = inv.sub(0, 2 * NB * i);
+      gemm<T>(s, false, false, NB, rest, NB, T(1), Linv, A.sub(k0, k0 + NB), T(0),
+              A.sub(k0, k0 + NB), batch);
+      gemm<T>(s, false, false, rest, rest, NB, T(-1), A.sub(k0 + NB, k0), A.sub(k0, k0 + NB),
+              T(1), A.sub(k0 + NB, k0 + NB), batch);
+    }
+  }
+}
+
+template <typename T>
+void lu_solve(hipStream_t s, DMat<T> LU, DMat<T> inv, const int32_t* ipiv, int64_t n, DMat<T> R,
+              int64_t r, int batch) {
+  if (n % NB) throw Error(ST_EINVAL, "lu_solve: n not a multiple of the block size");
+  const int64_t nblk = n / NB;
+  if (ipiv) laswp<T>(s, R, n, ipiv, 0, n, 0, r, batch);
+  for (int64_t i = 0; i < nblk; ++i) {
+    const int64_t k0 = i * NB, rest = n - k0 - NB;
+    gemm<T>(s, false, false, NB, r, NB, T(1), inv.sub(0, 2 * NB * i), R.sub(k0, 0), T(0),
+            R.sub(k0, 0), batch);
+    if (rest > 0)
+      gemm<T>(s, false, false, rest, r, NB, T(-1), LU.sub(k0 + NB, k0), R.sub(k0, 0), T(1),
+              R.sub(k0 + NB, 0), batch);
+  }
+  for (int64_t i = nblk - 1; i >= 0; --i) {
+    const int64_t k0 = i * NB;
+    gemm<T>(s, false, false, NB, r, NB, T(1), inv.sub(0, 2 * NB * i + NB), R.sub(k0, 0), T(0),
+            R.sub(k0, 0), batch);
+    if (k0 > 0)
+      gemm<T>(s, false, false, k0, r, NB, T(-1), LU.sub(0, k0), R.sub(k0, 0), T(1), R.sub(0, 0),
+              batch);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers.  Grid: x over rows*cols, y over batch.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(DMat<T> X, int64_t rows, int64_t cols, T v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e % rows, j = e / rows;
+  DMat<T> x = X.item(blockIdx.y);
+  x.re[i + j * x.ld] = v;
+  if (x.im) x.im[i + j * x.ld] = 0;
+}
+
+template <typename T>
+void fill(hipStream_t s, DMat<T> X, int64_t rows, int64_t cols, int batch, T value) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 g(grid1(rows * cols), batch);
+  k_fill<T><<<g, 256, 0, s>>>(X, rows, cols, value);
+  RFD_CHECK_LAUNCH();
+}
+
+template <typename T>
+__global__ void k_pad_identity(DMat<T> X, int64_t active, int64_t n) {
+  const int64_t i = active + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  DMat<T> x = X.item(blockIdx.y);
+  x.re[i + i * x.ld] = 1;
+  if (x.im) x.im[i + i * x.ld] = 0;
+}
+
+template <typename T>
+void pad_identity(hipStream_t s, DMat<T> X, int64_t active, int64_t n, int batch) {
+  if (n <= active) return;
+  dim3 g(grid1(n - active), batch);
+  k_pad_identity<T><<<g, 256, 0, s>>>(X, active, n);
+  RFD_CHECK_LAUNCH();
+}
+
+template <typename TD, typename TS>
+__global__ void k_convert(DMat<TS> X, DMat<TD> Y, int64_t rows, int64_t cols, int add) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e % rows, j = e / rows;
+  DMat<TS> x = X.item(blockIdx.y);
+  DMat<TD> y = Y.item(blockIdx.y);
+  const int64_t ox = i + j * x.ld, oy = i + j * y.ld;
+  const TD vr = (TD)x.re[ox];
+  const TD vi = x.im ? (TD)x.im[ox] : TD(0);
+  if (add) {
+    y.re[oy] += vr;
+    if (y.im) y.im[oy] += vi;
+  } else {
+    y.re[oy] = vr;
+    if (y.im) y.im[oy] = vi;
+  }
+}
+
+template <typename TD, typename TS>
+void convert(hipStream_t s, DMat<TS> X, DMat<TD> Y, int64_t rows, int64_t cols, int batch) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 g(grid1(rows * cols), batch);
+  k_convert<TD, TS><<<g, 256, 0, s>>>(X, Y, rows, cols, 0);
+  RFD_CHECK_LAUNCH();
+}
+
+template <typename TD, typename TS>
+void add_to(hipStream_t s, DMat<TS> X, DMat<TD> Y, int64_t rows, int64_t cols, int batch) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 g(grid1(rows * cols), batch);
+  k_convert<TD, TS><<<g, 256, 0, s>>>(X, Y, rows, cols, 1);
+  RFD_CHECK_LAUNCH();
+}
+
+__device__ inline void atomic_max_nonneg(double* p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+template <typename T>
+__global__ void k_absmax(DMat<T> X, int64_t rows, int64_t cols, double* out) {
+  __shared__ double red[256];
+  double m = 0;
+  DMat<T> x = X.item(blockIdx.y);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < rows * cols;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % rows, j = e / rows;
+    double v = fabs((double)x.re[i + j * x.ld]);
+    if (x.im) v = fmax(v, fabs((double)x.im[i + j * x.ld]));
+    if (!(v == v)) v = INFINITY;
+    m = fmax(m, v);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomic_max_nonneg(out, red[0]);
+}
+
+template <typename T>
+void absmax(hipStream_t s, DMat<T> X, int64_t rows, int64_t cols, int batch, double* out) {
+  if (rows <= 0 || cols <= 0) return;
+  const int64_t tot = rows * cols;
+  dim3 g((unsigned)std::min<int64_t>(grid1(tot), 1024), batch);
+  k_absmax<T><<<g, 256, 0, s>>>(X, rows, cols, out);
+  RFD_CHECK_LAUNCH();
+}
+
+// explicit instantiations
+#define RFD_INST(T)                                                                          \
+  template void gemm<T>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, T, DMat<T>,      \
+                        DMat<T>, T, DMat<T>, int);                                           \
+  template void lu_nopiv<T>(hipStream_t, DMat<T>, int64_t, int, DMat<T>, unsigned*, double); \
+  template void lu_piv<T>(hipStream_t, DMat<T>, int64_t, int, DMat<T>, int32_t*, unsigned*,  \
+                          double);                                                           \
+  template void lu_solve<T>(hipStream_t, DMat<T>, DMat<T>, const int32_t*, int64_t, DMat<T>, \
+                            int64_t, int);                                                   \
+  template void fill<T>(hipStream_t, DMat<T>, int64_t, int64_t, int, T);                     \
+  template void pad_identity<T>(hipStream_t, DMat<T>, int64_t, int64_t, int);                \
+  template void absmax<T>(hipStream_t, DMat<T>, int64_t, int64_t, int, double*);
+RFD_INST(float)
+RFD_INST(double)
+template void convert<float, double>(hipStream_t, DMat<double>, DMat<float>, int64_t, int64_t, int);
+template void convert<double, float>(hipStream_t, DMat<float>, DMat<double>, int64_t, int64_t, int);
+template void convert<double, double>(hipStream_t, DMat<double>, DMat<double>, int64_t, int64_t, int);
+template void convert<float, float>(hipStream_t, DMat<float>, DMat<float>, int64_t, int64_t, int);
+template void add_to<double, float>(hipStream_t, DMat<float>, DMat<double>, int64_t, int64_t, int);
+template void add_to<double, double>(hipStream_t, DMat<double>, DMat<double>, int64_t, int64_t, int);
+
+}  // namespace rfd

@@ -1,0 +1,60 @@
+// Dense batched building blocks on the gfx950 matrix cores: GEMM, LU
+// (no pivoting and partial pivoting), triangular solves through inverted
+// diagonal blocks, and elementwise helpers.  All operate on strided batches
+// (DMat) of uniform size; complex data is planar.
+#pragma once
+
+#include "rfd_common.hpp"
+
+namespace rfd {
+
+constexpr int NB = 64;  // LU / triangular-solve block size (= GEMM tile edge)
+
+// C_b = alpha * op(A_b) * op(B_b) + beta * C_b for b < batch.  op = transpose
+// when ta/tb.  Complex when C is complex; a real A or B (im == nullptr) is
+// taken with zero imaginary part.  beta == 0 never reads C.
+template <typename T>
+void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha,
+          DMat<T> A, DMat<T> B, T beta, DMat<T> C, int batch);
+
+// In-place LU without pivoting of n x n items (n multiple of NB).  inv
+// receives, per item, the inverses of the unit-lower and upper diagonal
+// blocks: an NB x (2 n) matrix [Linv_0 Uinv_0 Linv_1 Uinv_1 ...].  A pivot
+// with |u_kk| <= tiny or a non-finite value sets bits in *flags.
+template <typename T>
+void lu_nopiv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, unsigned* flags,
+              double tiny);
+
+// In-place LU with partial pivoting of real n x n items.  ipiv: per item n
+// int32 (0-based row swapped with row i at step i), item stride n.
+template <typename T>
+void lu_piv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, int32_t* ipiv,
+            unsigned* flags, double tiny);
+
+// Solves (LU) X = R in place for n x r items R (n multiple of NB), using the
+// factors and block inverses of lu_nopiv / lu_piv (ipiv may be null).
+template <typename T>
+void lu_solve(hipStream_t s, DMat<T> LU, DMat<T> inv, const int32_t* ipiv, int64_t n,
+              DMat<T> R, int64_t r, int batch);
+
+// Y (n x r, complex planar) <- fill with zero, or with the identity pattern
+// on the padding rows/cols beyond `active` when ident_pad.
+template <typename T>
+void fill(hipStream_t s, DMat<T> X, int64_t rows, int64_t cols, int batch, T value);
+
+template <typename T>
+void pad_identity(hipStream_t s, DMat<T> X, int64_t active, int64_t n, int batch);
+
+// Y = convert(X) elementwise (rows x cols per item), both planes.
+template <typename TD, typename TS>
+void convert(hipStream_t s, DMat<TS> X, DMat<TD> Y, int64_t rows, int64_t cols, int batch);
+
+// Y += convert(X) elementwise.
+template <typename TD, typename TS>
+void add_to(hipStream_t s, DMat<TS> X, DMat<TD> Y, int64_t rows, int64_t cols, int batch);
+
+// max |X| over every item into *out (non-negative double, bitwise atomicMax).
+template <typename T>
+void absmax(hipStream_t s, DMat<T> X, int64_t rows, int64_t cols, int batch, double* out);
+
+}  // namespace rfd

@@ -1,0 +1,450 @@
+// Device-side execution of the RF-DDES path for one pencil (engine.hpp):
+//   factor():            B_j(zeta_l) LU, Schur contributions with FP64 refinement,
+//                        S(zeta_l) assembly and LU                      (Sec. 3.1)
+//   apply_filter():      W = 2 Re sum_l omega_l S(zeta_l)^{-1} Y          (eq. (3.5))
+//   filter_interface():  block Krylov basis with rank-revealing QR       (Alg. 3.1)
+//   solve_interior(), rayleigh_ritz(): interior.hip
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "dense.hpp"
+#include "engine_impl.hpp"
+#include "orth.hpp"
+#include "sparse.hpp"
+
+namespace rfd {
+
+template <typename T>
+static void upload(DevBuf& b, const std::vector<T>& v) {
+  b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
+  if (!v.empty()) RFD_HIP(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+}
+
+static void upload_pair(DevPairGroup& g, const std::vector<const PairCsr*>& blocks) {
+  std::vector<int64_t> roff(1, 0), ptr;
+  std::vector<int32_t> idx;
+  std::vector<double> a, m;
+  for (const PairCsr* B : blocks) {
+    const int64_t base = (int64_t)idx.size();
+    for (int64_t r = 0; r <= B->rows; ++r) ptr.push_back(base + B->ptr[r]);
+    roff.push_back((int64_t)ptr.size());
+    idx.insert(idx.end(), B->idx.begin(), B->idx.end());
+    a.insert(a.end(), B->a.begin(), B->a.end());
+    m.insert(m.end(), B->m.begin(), B->m.end());
+  }
+  upload(g.roff, roff);
+  upload(g.ptr, ptr);
+  upload(g.idx, idx);
+  upload(g.a, a);
+  upload(g.m, m);
+}
+
+DevPairCsr DevPairGroup::view() const {
+  DevPairCsr v;
+  v.roff = roff.as<int64_t>();
+  v.ptr = ptr.as<int64_t>();
+  v.idx = idx.as<int32_t>();
+  v.a = a.as<double>();
+  v.m = m.as<double>();
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+Engine::Engine(const Csr& A, const Csr& M, const Partition& P) : d_(new EngineImpl) {
+  EngineImpl& e = *d_;
+  e.A = &A;
+  e.M = &M;
+  e.P = &P;
+  e.n = A.n;
+  e.p = P.p;
+  e.s = (int64_t)P.iface.size();
+  e.SP = round_up(e.s, NB);
+  e.D = round_up(P.d_max, NB);
+  e.SJ = round_up(std::max<int64_t>(P.sj_max, 1), NB);
+  e.normA = abs_row_sum_max(A);
+  std::vector<const PairCsr*> bl, el, etl;
+  std::vector<int32_t> dj, sj, adj((size_t)e.p * e.SJ, 0);
+  for (int j = 0; j < e.p; ++j) {
+    bl.push_back(&P.Bloc[j]);
+    el.push_back(&P.Eloc[j]);
+    etl.push_back(&P.EtLoc[j]);
+    dj.push_back((int32_t)P.interior[j].size());
+    sj.push_back((int32_t)P.adj[j].size());
+    for (size_t a = 0; a < P.adj[j].size(); ++a) adj[(size_t)j * e.SJ + a] = P.adj[j][a];
+  }
+  upload_pair(e.Bg, bl);
+  upload_pair(e.Eg, el);
+  upload_pair(e.Etg, etl);
+  upload_pair(e.Cg, {&P.Cloc});
+  upload(e.dj, dj);
+  upload(e.sj, sj);
+  upload(e.adj, adj);
+  e.colors_d.resize(P.colors.size());
+  for (size_t c = 0; c < P.colors.size(); ++c) upload(e.colors_d[c], P.colors[c]);
+  // global CSR of A and M and the reordering (interiors, then interface)
+  upload(e.Aptr, A.ptr);
+  upload(e.Aidx, A.idx);
+  upload(e.Aval, A.val);
+  upload(e.Mptr, M.ptr);
+  upload(e.Midx, M.idx);
+  upload(e.Mval, M.val);
+  std::vector<int32_t> order, ioff(1, 0);
+  for (int j = 0; j < e.p; ++j) {
+    order.insert(order.end(), P.interior[j].begin(), P.interior[j].end());
+    ioff.push_back((int32_t)order.size());
+  }
+  order.insert(order.end(), P.iface.begin(), P.iface.end());
+  upload(e.order, order);
+  upload(e.ioff, ioff);
+  e.emax = 0;
+  for (int j = 0; j < e.p; ++j)
+    for (size_t k = 0; k < P.Eloc[j].a.size(); ++k)
+      e.emax = std::max(e.emax, std::fabs(P.Eloc[j].a[k]) + std::fabs(P.Eloc[j].m[k]));
+  e.flags.alloc(sizeof(unsigned) * 4);
+  e.scal.alloc(sizeof(double) * 8);
+  RFD_HIP(hipMemset(e.flags.p, 0, sizeof(unsigned) * 4));
+}
+
+Engine::~Engine() = default;
+
+void Engine::set_poles(const Poles& poles) {
+  EngineImpl& e = *d_;
+  e.poles = poles;
+  std::vector<double> z, w;
+  for (int l = 0; l < poles.n_c; ++l) {
+    z.push_back(poles.zeta[l].real());
+    z.push_back(poles.zeta[l].imag());
+    w.push_back(poles.omega[l].real());
+    w.push_back(poles.omega[l].imag());
+  }
+  upload(e.zeta, z);
+  upload(e.omega, w);
+  e.factored = false;
+}
+
+void Engine::set_precision(int mode, double tol, int sweeps) {
+  EngineImpl& e = *d_;
+  if (mode != e.mode) e.factored = false;
+  e.mode = mode;
+  e.tol = tol;
+  e.sweeps = sweeps;
+}
+
+int64_t Engine::device_bytes() const {
+  return d_->bytes_held();
+}
+
+void Engine::reset_caches(bool release) {
+  EngineImpl& e = *d_;
+  e.factored = false;
+  e.vcache_valid = false;
+  e.bs_valid = false;
+  e.interior_ready = false;
+  if (!release) return;
+  for (DevBuf* b : {&e.K32, &e.K64, &e.Kinv32, &e.Kinv64, &e.X32, &e.X64, &e.R32, &e.R64,
+                    &e.S64, &e.S32, &e.Sinv32, &e.Sinv64, &e.Vb, &e.Bs, &e.Bsinv, &e.Bspiv,
+                    &e.Lev, &e.Zt})
+    b->release();
+}
+
+void Engine::set_timing(bool on) { d_->timer.enabled = on; }
+void Engine::phase_times(double* ms16) { d_->timer.collect(ms16); }
+
+// ---------------------------------------------------------------------------
+void PhaseTimer::begin(hipStream_t s, int phase) {
+  if (!enabled) return;
+  Rec r;
+  r.phase = phase;
+  RFD_HIP(hipEventCreate(&r.a));
+  RFD_HIP(hipEventCreate(&r.b));
+  RFD_HIP(hipEventRecord(r.a, s));
+  open.push_back(r);
+}
+void PhaseTimer::end(hipStream_t s) {
+  if (!enabled || open.empty()) return;
+  Rec r = open.back();
+  open.pop_back();
+  RFD_HIP(hipEventRecord(r.b, s));
+  done.push_back(r);
+}
+void PhaseTimer::collect(double* ms16) {
+  for (auto& r : done) {
+    RFD_HIP(hipEventSynchronize(r.b));
+    float ms = 0;
+    RFD_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    acc[r.phase] += ms;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  done.clear();
+  for (int i = 0; i < 16; ++i) ms16[i] = acc[i];
+  for (int i = 0; i < 16; ++i) acc[i] = 0;
+  ms16[12] = sweeps_schur;
+  ms16[13] = sweeps_filter;
+}
+PhaseTimer::~PhaseTimer() {
+  for (auto& r : done) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto& r : open) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+}
+
+int64_t EngineImpl::bytes_held() const {
+  int64_t t = 0;
+  for (const DevBuf* b : {&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32,
+                          &Sinv32, &Sinv64, &Yc, &Xf, &Rf, &Rf32, &W, &Qint})
+    t += (int64_t)b->bytes;
+  return t + interior_bytes();
+}
+
+double EngineImpl::read_scalar(hipStream_t s, int i) {
+  double v = 0;
+  RFD_HIP(hipMemcpyAsync(&v, scal.as<double>() + i, sizeof(double), hipMemcpyDeviceToHost, s));
+  RFD_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+void EngineImpl::zero_scalar(hipStream_t s, int i) {
+  RFD_HIP(hipMemsetAsync(scal.as<double>() + i, 0, sizeof(double), s));
+}
+
+void EngineImpl::check_flags(hipStream_t s, const char* what) {
+  unsigned f = 0;
+  RFD_HIP(hipMemcpyAsync(&f, flags.as<unsigned>(), sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  RFD_HIP(hipStreamSynchronize(s));
+  if (f) {
+    RFD_HIP(hipMemsetAsync(flags.p, 0, sizeof(unsigned), s));
+    throw Error(ST_EBREAKDOWN, std::string(what) + ": pivot below the breakdown threshold" +
+                                   ((f & 2) ? " (non-finite value)" : ""));
+  }
+}
+
+// Poles processed together for the interior part: as many as fit the budget.
+int EngineImpl::pole_chunk() const {
+  const int64_t items_bytes_per_pole =
+      (int64_t)p * (D * D * (mode == 1 ? 8 : 16) + NB * 2 * D * (mode == 1 ? 8 : 16) +
+                    D * SJ * (mode == 1 ? 16 + 16 + 8 + 8 : 16));
+  const int64_t budget = int64_t(96) << 30;
+  int c = (int)std::max<int64_t>(1, budget / std::max<int64_t>(items_bytes_per_pole, 1));
+  return std::min(c, poles.n_c);
+}
+
+// ---------------------------------------------------------------------------
+// Factorizations for every pole (Sec. 3.1).
+// ---------------------------------------------------------------------------
+void EngineImpl::factor(hipStream_t st) {
+  const int nc = poles.n_c;
+  Shifts z{zeta.as<double>()};
+  const int chunk = pole_chunk();
+  const int items_max = chunk * p;
+  // Schur complements (FP64 planar), all poles
+  const int64_t sbytes = SP * SP * (int64_t)nc * sizeof(double);
+  S64.alloc(2 * sbytes);
+  DMat<double> S{S64.as<double>(), S64.as<double>() + SP * SP * nc, SP, SP * SP};
+  fill<double>(st, S, SP, SP, nc, 0.0);
+  schur_init(st, S, s, SP, nc, 0, Cg.view(), z);
+  const int64_t kk = D * D * (int64_t)items_max, ki = (int64_t)NB * 2 * D * items_max,
+                xs = D * SJ * (int64_t)items_max;
+  const bool fp32 = (mode == 1);
+  if (fp32) {
+    K32.alloc(2 * kk * sizeof(float));
+    Kinv32.alloc(2 * ki * sizeof(float));
+    X32.alloc(2 * xs * sizeof(float));
+  } else {
+    K64.alloc(2 * kk * sizeof(double));
+    Kinv64.alloc(2 * ki * sizeof(double));
+  }
+  X64.alloc(2 * xs * sizeof(double));
+  if (fp32) R64.alloc(2 * xs * sizeof(double));
+  int max_sweeps_used = 0;
+  for (int l0 = 0; l0 < nc; l0 += chunk) {
+    const int np = std::min(chunk, nc - l0);
+    const int items = np * p;
+    DMat<double> X{X64.as<double>(), X64.as<double>() + xs, D, D * SJ};
+    timer.begin(st, 0);
+    if (fp32) {
+      DMat<float> K{K32.as<float>(), K32.as<float>() + kk, D, D * D};
+      DMat<float> Ki{Kinv32.as<float>(), Kinv32.as<float>() + ki, NB, (int64_t)NB * 2 * D};
+      fill<float>(st, K, D, D, items, 0.f);
+      expand_shifted<float>(st, K, D, p, np, l0, dj.as<int32_t>(), Bg.view(), z, false, 0.0);
+      lu_nopiv<float>(st, K, D, items, Ki, flags.as<unsigned>(), 1e-30);
+      timer.end(st);
+      timer.begin(st, 1);
+      DMat<float> X3{X32.as<float>(), X32.as<float>() + xs, D, D * SJ};
+      fill<float>(st, X3, D, SJ, items, 0.f);
+      expand_rhs<float>(st, X3, p, np, l0, dj.as<int32_t>(), Eg.view(), z);
+      lu_solve<float>(st, K, Ki, nullptr, D, X3, SJ, items);
+      convert<double, float>(st, X3, X, D, SJ, items);
+      DMat<double> Rm{R64.as<double>(), R64.as<double>() + xs, D, D * SJ};
+      int sw = 0;
+      for (;; ++sw) {
+        zero_scalar(st, 0);
+        residual_shifted(st, X, Rm, D, SJ, p, np, l0, dj.as<int32_t>(), sj.as<int32_t>(),
+                         Bg.view(), Eg.view(), z, scal.as<double>());
+        const double r = read_scalar(st, 0);
+        if (!(r == r)) throw Error(ST_EBREAKDOWN, "non-finite residual in the interior solves");
+        if (r <= tol * emax) break;
+        if (sw >= sweeps)
+          throw Error(ST_ENOCONV, "interior refinement did not converge (residual " +
+                                      std::to_string(r / emax) + ")");
+        convert<float, double>(st, Rm, X3, D, SJ, items);
+        lu_solve<float>(st, K, Ki, nullptr, D, X3, SJ, items);
+        add_to<double, float>(st, X3, X, D, SJ, items);
+      }
+      max_sweeps_used = std::max(max_sweeps_used, sw);
+      timer.end(st);
+    } else {
+      DMat<double> K{K64.as<double>(), K64.as<double>() + kk, D, D * D};
+      DMat<double> Ki{Kinv64.as<double>(), Kinv64.as<double>() + ki, NB, (int64_t)NB * 2 * D};
+      fill<double>(st, K, D, D, items, 0.0);
+      expand_shifted<double>(st, K, D, p, np, l0, dj.as<int32_t>(), Bg.view(), z, false, 0.0);
+      lu_nopiv<double>(st, K, D, items, Ki, flags.as<unsigned>(), 1e-300);
+      timer.end(st);
+      timer.begin(st, 1);
+      fill<double>(st, X, D, SJ, items, 0.0);
+      expand_rhs<double>(st, X, p, np, l0, dj.as<int32_t>(), Eg.view(), z);
+      lu_solve<double>(st, K, Ki, nullptr, D, X, SJ, items);
+      timer.end(st);
+    }
+    timer.begin(st, 2);
+    DMat<double> Sc = S.item(l0);
+    for (size_t c = 0; c < colors_d.size(); ++c)
+      schur_scatter(st, Sc, X, SJ, p, np, l0, colors_d[c].as<int32_t>(),
+                    (int)P->colors[c].size(), sj.as<int32_t>(), adj.as<int32_t>(), Etg.view(), z);
+    timer.end(st);
+  }
+  check_flags(st, "interior factorization");
+  timer.sweeps_schur = max_sweeps_used;
+  // factor S(zeta_l), all poles in one batch
+  timer.begin(st, 3);
+  if (fp32) {
+    S32.alloc(2 * SP * SP * (int64_t)nc * sizeof(float));
+    Sinv32.alloc(2 * (int64_t)NB * 2 * SP * nc * sizeof(float));
+    DMat<float> S3{S32.as<float>(), S32.as<float>() + SP * SP * nc, SP, SP * SP};
+    DMat<float> Si{Sinv32.as<float>(), Sinv32.as<float>() + (int64_t)NB * 2 * SP * nc, NB,
+                   (int64_t)NB * 2 * SP};
+    convert<float, double>(st, S, S3, SP, SP, nc);
+    lu_nopiv<float>(st, S3, SP, nc, Si, flags.as<unsigned>(), 1e-30);
+    // the interior factors are no longer needed
+    K32.release();
+    Kinv32.release();
+    X32.release();
+    R64.release();
+  } else {
+    Sinv64.alloc(2 * (int64_t)NB * 2 * SP * nc * sizeof(double));
+    DMat<double> Si{Sinv64.as<double>(), Sinv64.as<double>() + (int64_t)NB * 2 * SP * nc, NB,
+                    (int64_t)NB * 2 * SP};
+    lu_nopiv<double>(st, S, SP, nc, Si, flags.as<unsigned>(), 1e-300);
+    K64.release();
+    Kinv64.release();
+  }
+  X64.release();
+  timer.end(st);
+  check_flags(st, "Schur complement factorization");
+  factored = true;
+}
+
+// W = 2 Re sum_l omega_l S(zeta_l)^{-1} Y  (eq. (3.5)); Y real s x m (ld ldy),
+// W real (ld ldw).  FP32 mode refines every pole's solve against S_64.
+void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* Wout,
+                              int64_t ldw) {
+  const int nc = poles.n_c;
+  const int64_t MP = round_up(m, NB);
+  const int64_t ys = SP * MP * (int64_t)nc;
+  Yc.alloc(2 * ys * sizeof(double));
+  DMat<double> Ycm{Yc.as<double>(), Yc.as<double>() + ys, SP, SP * MP};
+  DMat<double> S{S64.as<double>(), S64.as<double>() + SP * SP * nc, SP, SP * SP};
+  timer.begin(st, 4);
+  if (mode == 1) {
+    Xf.alloc(2 * ys * sizeof(double));
+    Rf32.alloc(2 * ys * sizeof(float));
+    DMat<double> X{Xf.as<double>(), Xf.as<double>() + ys, SP, SP * MP};
+    DMat<float> R3{Rf32.as<float>(), Rf32.as<float>() + ys, SP, SP * MP};
+    DMat<float> S3{S32.as<float>(), S32.as<float>() + SP * SP * nc, SP, SP * SP};
+    DMat<float> Si{Sinv32.as<float>(), Sinv32.as<float>() + (int64_t)NB * 2 * SP * nc, NB,
+                   (int64_t)NB * 2 * SP};
+    // |Y| for the stopping test
+    zero_scalar(st, 1);
+    DMat<double> Ym{const_cast<double*>(Y), nullptr, ldy, 0};
+    absmax<double>(st, Ym, s, m, 1, scal.as<double>() + 1);
+    const double ymax = read_scalar(st, 1);
+    broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);   // R = Y - S 0
+    fill<double>(st, X, SP, MP, nc, 0.0);
+    int sw = 0;
+    for (;; ++sw) {
+      convert<float, double>(st, Ycm, R3, SP, MP, nc);
+      lu_solve<float>(st, S3, Si, nullptr, SP, R3, MP, nc);
+      add_to<double, float>(st, R3, X, SP, MP, nc);
+      broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);
+      gemm<double>(st, false, false, SP, MP, SP, -1.0, S, X, 1.0, Ycm, nc);
+      zero_scalar(st, 0);
+      absmax<double>(st, Ycm, SP, MP, nc, scal.as<double>());
+      const double r = read_scalar(st, 0);
+      if (!(r == r)) throw Error(ST_EBREAKDOWN, "non-finite residual in the filter solves");
+      if (r <= tol * ymax) break;
+      if (sw + 1 >= sweeps)
+        throw Error(ST_ENOCONV, "filter refinement did not converge (residual " +
+                                    std::to_string(r / ymax) + ")");
+    }
+    timer.sweeps_filter = std::max(timer.sweeps_filter, sw + 1);
+    filter_accumulate(st, X, omega.as<double>(), nc, Wout, ldw, s, m, false);
+  } else {
+    DMat<double> Si{Sinv64.as<double>(), Sinv64.as<double>() + (int64_t)NB * 2 * SP * nc, NB,
+                    (int64_t)NB * 2 * SP};
+    broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);
+    lu_solve<double>(st, S, Si, nullptr, SP, Ycm, MP, nc);
+    filter_accumulate(st, Ycm, omega.as<double>(), nc, Wout, ldw, s, m, false);
+  }
+  timer.end(st);
+}
+
+void Engine::filter_interface(hipStream_t st, int m, const double* Y0, int steps, double* Q,
+                              int64_t ldq_cols, int* mu) {
+  EngineImpl& e = *d_;
+  if (!e.poles.set) throw Error(ST_ESTATE, "poles not set");
+  if (!e.factored) e.factor(st);
+  const int64_t s = e.s;
+  const int64_t cap = std::min<int64_t>(ldq_cols, std::min<int64_t>(s, (int64_t)steps * m));
+  e.W.alloc(sizeof(double) * s * (int64_t)m);
+  double* W = e.W.as<double>();
+  int total = 0, prev0 = 0, prevw = 0;
+  for (int t = 1; t <= steps; ++t) {
+    if (t == 1) {
+      e.apply_filter(st, Y0, s, m, W, s);
+    } else {
+      if (prevw == 0 || total >= cap) break;
+      e.apply_filter(st, Q + (int64_t)prev0 * s, s, prevw, W, s);
+    }
+    const int width = (t == 1) ? m : prevw;
+    const int room = (int)(cap - total);
+    e.timer.begin(st, 5);
+    int r = orth_block(st, W, s, s, width, Q, s, total, Q + (int64_t)total * s, s, 1e-13,
+                       room, e.ow);
+    e.timer.end(st);
+    r = std::min(r, room);
+    prev0 = total;
+    prevw = r;
+    total += r;
+  }
+  *mu = total;
+  // keep Q for the interior part
+  e.mu = total;
+  e.Qint.alloc(sizeof(double) * std::max<int64_t>(s * total, 1));
+  if (total > 0)
+    RFD_HIP(hipMemcpyAsync(e.Qint.p, Q, sizeof(double) * s * total, hipMemcpyDeviceToDevice, st));
+  e.interior_ready = false;
+}
+
+void Engine::filter_apply(hipStream_t st, int m, const double* Y, double* W) {
+  EngineImpl& e = *d_;
+  if (!e.poles.set) throw Error(ST_ESTATE, "poles not set");
+  if (!e.factored) e.factor(st);
+  e.apply_filter(st, Y, e.s, m, W, e.s);
+}
+
+}  // namespace rfd

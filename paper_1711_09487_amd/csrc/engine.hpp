@@ -1,0 +1,35 @@
+// Device-side execution of the RF-DDES path for one pencil: buffers, the
+// per-pole factorizations, the interface filter, the interior part and the
+// Rayleigh-Ritz step.  Owned by a pencil handle (capi.cpp).
+#pragma once
+
+#include <memory>
+
+#include "pencil.hpp"
+
+namespace rfd {
+
+struct EngineImpl;
+
+class Engine {
+ public:
+  Engine(const Csr& A, const Csr& M, const Partition& P);
+  ~Engine();
+  void set_poles(const Poles& poles);
+  void set_precision(int mode, double tol, int sweeps);
+  void filter_interface(hipStream_t s, int m, const double* Y0, int steps, double* Q,
+                        int64_t ldq_cols, int* mu);
+  void filter_apply(hipStream_t s, int m, const double* Y, double* W);
+  void solve_interior(hipStream_t s, double sigma, int nev_b, int psi, int64_t* k);
+  void rayleigh_ritz(hipStream_t s, int max_out, double* evals, double* evecs, double* resid,
+                     int* nfound);
+  int64_t device_bytes() const;
+  void reset_caches(bool release);
+  void set_timing(bool on);
+  void phase_times(double* ms16);
+
+ private:
+  std::unique_ptr<EngineImpl> d_;
+};
+
+}  // namespace rfd

@@ -1,0 +1,99 @@
+// Internal state of an Engine (see engine.hpp): device copies of the pencil
+// and its reordering maps, factor buffers, the interface basis and the
+// interior / Rayleigh-Ritz workspaces.
+#pragma once
+
+#include <vector>
+
+#include "engine.hpp"
+#include "orth.hpp"
+#include "sparse.hpp"
+
+namespace rfd {
+
+struct DevPairGroup {
+  DevBuf roff, ptr, idx, a, m;
+  DevPairCsr view() const;
+};
+
+struct PhaseTimer {
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  bool enabled = false;
+  std::vector<Rec> open, done;
+  double acc[16] = {0};
+  int sweeps_schur = 0, sweeps_filter = 0;
+  void begin(hipStream_t s, int phase);
+  void end(hipStream_t s);
+  void collect(double* ms16);
+  ~PhaseTimer();
+};
+
+struct EngineImpl {
+  const Csr* A = nullptr;
+  const Csr* M = nullptr;
+  const Partition* P = nullptr;
+  int64_t n = 0, s = 0, SP = 0, D = 0, SJ = 0;
+  int p = 0;
+  double normA = 0, emax = 0;
+  // pencil and maps
+  DevPairGroup Bg, Eg, Etg, Cg;
+  DevBuf dj, sj, adj, order, ioff;
+  std::vector<DevBuf> colors_d;
+  DevBuf Aptr, Aidx, Aval, Mptr, Midx, Mval;      // original numbering
+  DevBuf Arptr, Aridx, Arval, Mrptr, Mridx, Mrval;  // reordered numbering (lazy)
+  // poles and precision
+  Poles poles;
+  DevBuf zeta, omega;
+  int mode = 0;
+  double tol = 1e-13;
+  int sweeps = 8;
+  bool factored = false;
+  // factor buffers
+  DevBuf K32, K64, Kinv32, Kinv64, X32, X64, R32, R64;
+  DevBuf S64, S32, Sinv32, Sinv64;
+  DevBuf Yc, Xf, Rf, Rf32, W;
+  OrthWork ow;
+  // interface basis
+  DevBuf Qint;
+  int mu = 0;
+  // interior part
+  bool interior_ready = false;
+  double sigma = 0;
+  int nev_b = 0, psi = 0;
+  std::vector<int> kappa;                 // per subdomain
+  int kappa_tot = 0;
+  bool vcache_valid = false;
+  double vcache_sigma = 0;
+  int vcache_nevb = -1;
+  DevBuf Vb;                              // per subdomain D x VB (M_B-orthonormal)
+  int64_t VB = 0;                         // padded column capacity per subdomain
+  DevBuf kap_d, delta_d;
+  DevBuf Bs, Bsinv, Bspiv;                // B_sigma LU (FP64, pivoted)
+  bool bs_valid = false;
+  double bs_sigma = 0;
+  DevBuf Lev;                             // levels: per subdomain D x (psi * MUP)
+  int64_t MUP = 0;
+  DevBuf Zt;                              // M-orthonormal basis of range(Z), n x k (reordered)
+  int64_t kz = 0;                         // columns of Zt
+  DevBuf work1, work2, work3, work4, work5, work6;
+  DevBuf ipiv_small, iscal;
+  PhaseTimer timer;
+  DevBuf flags, scal;
+
+  int64_t bytes_held() const;
+  int64_t interior_bytes() const;
+  double read_scalar(hipStream_t s, int i);
+  void zero_scalar(hipStream_t s, int i);
+  void check_flags(hipStream_t s, const char* what);
+  int pole_chunk() const;
+  void factor(hipStream_t st);
+  void apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* W, int64_t ldw);
+  void ensure_reordered();
+  void interior_basis(hipStream_t st, double sigma, int nev_b);
+  void factor_bsigma(hipStream_t st, double sigma);
+};
+
+}  // namespace rfd

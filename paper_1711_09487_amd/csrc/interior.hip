@@ -1,0 +1,669 @@
+// Interior part and Rayleigh-Ritz (Sec. 4, Sec. 5 / Alg. 5.1 steps 3, 6-8).
+//
+//  interior_basis():  V_j = eigenvectors of (B_j, M_Bj) closest to sigma
+//                     (M_Bj diagonal: eigenvectors of M^{-1/2} B M^{-1/2},
+//                     batched over subdomains), M_Bj-orthonormal.
+//  factor_bsigma():   LU with partial pivoting of B_sigma^(j) = B_j - sigma M_Bj.
+//  solve_interior():  resolvent levels of eqs. (5.2)-(5.4), each made
+//                     M_Bj-orthogonal to V_j (deflated recurrence), then an
+//                     M-orthonormal basis of range(Z) (eq. (5.5)) built level by
+//                     level with pivoted Cholesky QR.
+//  rayleigh_ritz():   H = Z^T A Z on that basis, eigenpairs with theta in
+//                     [alpha, beta], Ritz vectors in the original numbering and
+//                     their residuals.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "dense.hpp"
+#include "eig.hpp"
+#include "engine_impl.hpp"
+
+namespace rfd {
+
+__device__ inline double bsum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// diag(M_B^(j)) and 1/sqrt of it, per subdomain row (p x D).
+__global__ void k_mdiag(int64_t D, const int32_t* dj, DevPairCsr B, double* md, double* mis) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= D) return;
+  double m = 1.0;
+  if (r < dj[j]) {
+    const int64_t* ptr = B.ptr + B.roff[j];
+    for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e)
+      if (B.idx[e] == r) m = B.m[e];
+  }
+  md[(int64_t)j * D + r] = m;
+  mis[(int64_t)j * D + r] = 1.0 / sqrt(m);
+}
+
+// C_j = M^{-1/2} B_j M^{-1/2} (dense, zero on entry), padding diagonal = big.
+__global__ void k_expand_scaled(DMat<double> C, int64_t D, const int32_t* dj, DevPairCsr B,
+                                const double* mis, double big) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= D) return;
+  DMat<double> c = C.item(j);
+  if (r >= dj[j]) {
+    c.re[r + r * c.ld] = big;
+    return;
+  }
+  const double* mj = mis + (int64_t)j * D;
+  const int64_t* ptr = B.ptr + B.roff[j];
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+    const int64_t q = B.idx[e];
+    c.re[r + q * c.ld] = B.a[e] * mj[r] * mj[q];
+  }
+}
+
+// X_j[r, c] *= vec[j * D + r] for r < rows, c < cols.
+__global__ void k_scale_rows(DMat<double> X, int64_t rows, int64_t cols, const double* vec,
+                             int64_t D) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t r = e % rows, c = e / rows;
+  DMat<double> x = X.item(blockIdx.y);
+  x.re[r + c * x.ld] *= vec[(int64_t)blockIdx.y * D + r];
+}
+
+// Y_j[r, c] = vec[j * D + r] * X_j[r, c]
+__global__ void k_scaled_copy(DMat<double> X, DMat<double> Y, int64_t rows, int64_t cols,
+                              const double* vec, int64_t D) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t r = e % rows, c = e / rows;
+  DMat<double> x = X.item(blockIdx.y), y = Y.item(blockIdx.y);
+  y.re[r + c * y.ld] = vec[(int64_t)blockIdx.y * D + r] * x.re[r + c * x.ld];
+}
+
+// rhs_j[r, c] = -((Ehat_j - sigma Mhat_E) Q[adj_j, :])[r, c]  (Phi of eq. (5.2), negated
+// so that the first level carries the sign of eq. (5.5)).
+__global__ void k_gather_phi(DMat<double> R, int64_t D, int64_t cols_pad, const int32_t* dj,
+                             DevPairCsr E, double sigma, const double* Q, int64_t ldq, int mu,
+                             const int32_t* adj, int64_t SJ) {
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (e0 >= D * cols_pad) return;
+  const int64_t r = e0 % D, c = e0 / D;
+  DMat<double> x = R.item(j);
+  double v = 0;
+  if (r < dj[j] && c < mu) {
+    const int64_t* ptr = E.ptr + E.roff[j];
+    for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e)
+      v -= (E.a[e] - sigma * E.m[e]) * Q[adj[(int64_t)j * SJ + E.idx[e]] + c * ldq];
+  }
+  x.re[r + c * x.ld] = v;
+}
+
+// Zt[ioff[j] + r, koff[j] + c] = V_j[r, c]
+__global__ void k_scatter_v(double* Z, int64_t ldz, DMat<double> V, const int32_t* ioff,
+                            const int32_t* koff, const int32_t* kap, const int32_t* dj,
+                            int64_t rows) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int64_t kj = kap[j];
+  if (e >= rows * kj) return;
+  const int64_t r = e % rows, c = e / rows;
+  if (r >= dj[j]) return;
+  DMat<double> v = V.item(j);
+  Z[(ioff[j] + r) + (koff[j] + c) * ldz] = v.re[r + c * v.ld];
+}
+
+// level t of Z in the reordered numbering: interior rows from Lev, interface
+// rows Q (t == 0) or 0.
+__global__ void k_build_level(double* L, int64_t ldl, DMat<double> Lev, int t, int64_t MUP,
+                              const int32_t* ioff, int p, int64_t n_int, int64_t n, const double* Q,
+                              int64_t ldq, int mu) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * mu) return;
+  const int64_t i = e % n, c = e / n;
+  double v = 0;
+  if (i < n_int) {
+    int lo = 0, hi = p;  // ioff[lo] <= i < ioff[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (ioff[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    DMat<double> x = Lev.item(lo);
+    v = x.re[(i - ioff[lo]) + (t * MUP + c) * x.ld];
+  } else if (t == 0) {
+    v = Q[(i - n_int) + c * ldq];
+  }
+  L[i + c * ldl] = v;
+}
+
+// Y = op X with op a CSR matrix (n x n) (Y, X dense n x cols).
+__global__ void k_csr_mm(const int64_t* ptr, const int32_t* idx, const double* val, int64_t n,
+                         const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t cols) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * cols) return;
+  const int64_t r = e % n, c = e / n;
+  double acc = 0;
+  for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) acc += val[q] * X[idx[q] + c * ldx];
+  Y[r + c * ldy] = acc;
+}
+
+static void csr_mm(hipStream_t s, const DevBuf& ptr, const DevBuf& idx, const DevBuf& val,
+                   int64_t n, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t cols) {
+  if (cols <= 0) return;
+  k_csr_mm<<<grid1(n * cols), 256, 0, s>>>(ptr.as<int64_t>(), idx.as<int32_t>(), val.as<double>(),
+                                           n, X, ldx, Y, ldy, cols);
+  RFD_CHECK_LAUNCH();
+}
+
+// out[c] = sqrt(x_c^T Y_c) (M-norms with Y = M X), one workgroup per column.
+__global__ void k_col_dots(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
+                           double* out) {
+  __shared__ double red[256];
+  const int64_t c = blockIdx.x;
+  double acc = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += X[i + c * ldx] * Y[i + c * ldy];
+  acc = bsum(acc, red);
+  if (threadIdx.x == 0) out[c] = sqrt(fmax(acc, 0.0));
+}
+
+// X_c *= 1 / nrm[c], or zero the column when nrm[c] <= floor_rel * ref[c].
+__global__ void k_col_normalize(double* X, int64_t ldx, int64_t n, const double* nrm,
+                                const double* ref, double floor_rel) {
+  const int64_t c = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = nrm[c];
+  const bool drop = !(v > 0) || (ref && v <= floor_rel * ref[c]);
+  X[i + c * ldx] = drop ? 0.0 : X[i + c * ldx] / v;
+}
+
+// Y[:, c] = X[:, piv[c]]
+__global__ void k_gather_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t n,
+                              const int* piv, const int* rank) {
+  const int64_t c = blockIdx.y;
+  if (c >= *rank) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Y[i + c * ldy] = X[i + (int64_t)piv[c] * ldx];
+}
+
+__global__ void k_symmetrize(double* H, int64_t ld, int64_t k) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int64_t i = e % k, j = e / k;
+  if (i <= j) return;
+  const double v = 0.5 * (H[i + j * ld] + H[j + i * ld]);
+  H[i + j * ld] = v;
+  H[j + i * ld] = v;
+}
+
+// X[order[i], c] = Xr[i, c]
+__global__ void k_unpermute(const double* Xr, int64_t ldr, const int32_t* order, int64_t n,
+                            double* X, int64_t ldx, int64_t cols) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * cols) return;
+  const int64_t i = e % n, c = e / n;
+  X[order[i] + c * ldx] = Xr[i + c * ldr];
+}
+
+// resid[c] = ||AX_c - theta_c MX_c|| / (normA ||X_c||)
+__global__ void k_resid(const double* AX, const double* MX, const double* X, int64_t ld, int64_t n,
+                        const double* theta, double normA, double* out) {
+  __shared__ double red[256];
+  const int64_t c = blockIdx.x;
+  const double th = theta[c];
+  double r2 = 0, x2 = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double rv = AX[i + c * ld] - th * MX[i + c * ld];
+    r2 += rv * rv;
+    x2 += X[i + c * ld] * X[i + c * ld];
+  }
+  r2 = bsum(r2, red);
+  x2 = bsum(x2, red);
+  if (threadIdx.x == 0) out[c] = sqrt(r2) / (normA * sqrt(x2));
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+static void upload_v(DevBuf& b, const std::vector<T>& v) {
+  b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
+  if (!v.empty()) RFD_HIP(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+}
+
+template <typename T>
+static std::vector<T> download(hipStream_t s, const void* p, size_t n) {
+  std::vector<T> v(n);
+  if (n) {
+    RFD_HIP(hipMemcpyAsync(v.data(), p, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+    RFD_HIP(hipStreamSynchronize(s));
+  }
+  return v;
+}
+
+void EngineImpl::ensure_reordered() {
+  if (Arptr.p) return;
+  std::vector<int32_t> ord;
+  for (int j = 0; j < p; ++j) ord.insert(ord.end(), P->interior[j].begin(), P->interior[j].end());
+  ord.insert(ord.end(), P->iface.begin(), P->iface.end());
+  std::vector<int32_t> pos(n);
+  for (int64_t i = 0; i < n; ++i) pos[ord[i]] = (int32_t)i;
+  for (int w = 0; w < 2; ++w) {
+    const Csr& X = w == 0 ? *A : *M;
+    std::vector<int64_t> ptr(1, 0);
+    std::vector<int32_t> idx;
+    std::vector<double> val;
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t g = ord[i];
+      row.clear();
+      for (int64_t e = X.ptr[g]; e < X.ptr[g + 1]; ++e) row.emplace_back(pos[X.idx[e]], X.val[e]);
+      std::sort(row.begin(), row.end());
+      for (auto& kv : row) {
+        idx.push_back(kv.first);
+        val.push_back(kv.second);
+      }
+      ptr.push_back((int64_t)idx.size());
+    }
+    upload_v(w == 0 ? Arptr : Mrptr, ptr);
+    upload_v(w == 0 ? Aridx : Mridx, idx);
+    upload_v(w == 0 ? Arval : Mrval, val);
+  }
+}
+
+int64_t EngineImpl::interior_bytes() const {
+  int64_t t = 0;
+  for (const DevBuf* b : {&Vb, &Bs, &Bsinv, &Bspiv, &Lev, &Zt, &work1, &work2, &work3, &work4,
+                          &work5, &work6})
+    t += (int64_t)b->bytes;
+  return t;
+}
+
+// Clusters for inverse iteration: consecutive values closer than gap.
+static std::vector<int> clusters(const std::vector<double>& lam, double gap) {
+  std::vector<int> c(lam.size());
+  for (size_t i = 0; i < lam.size(); ++i)
+    c[i] = (i > 0 && lam[i] - lam[i - 1] <= gap) ? c[i - 1] : (int)i;
+  return c;
+}
+
+void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
+  if (vcache_valid && vcache_sigma == sig && vcache_nevb == nevb) return;
+  if (!P->m_diag) throw Error(ST_EINVAL, "the interior basis on the GPU needs a diagonal M");
+  kappa.assign(p, 0);
+  kappa_tot = 0;
+  VB = 0;
+  if (nevb == 0) {
+    vcache_valid = true;
+    vcache_sigma = sig;
+    vcache_nevb = nevb;
+    return;
+  }
+  timer.begin(st, 6);
+  // M-scaled dense blocks
+  work1.alloc(sizeof(double) * 2 * p * D);
+  double* md = work1.as<double>();
+  double* mis = md + p * D;
+  k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, dj.as<int32_t>(), Bg.view(), md, mis);
+  RFD_CHECK_LAUNCH();
+  double mmin = 1e300;
+  for (double v : M->val) mmin = std::min(mmin, v > 0 ? v : 1e300);
+  const double big = 4.0 * normA / std::max(mmin, 1e-300) + 4.0 * std::fabs(sig) + 1.0;
+  work2.alloc(sizeof(double) * D * D * p);
+  DMat<double> C{work2.as<double>(), nullptr, D, D * D};
+  fill<double>(st, C, D, D, p, 0.0);
+  k_expand_scaled<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), mis, big);
+  RFD_CHECK_LAUNCH();
+  TriWork tw;
+  sy_tridiag(st, C, D, p, tw);
+  // indices around sigma
+  std::vector<double> xs(p, sig);
+  work3.alloc(sizeof(double) * p + sizeof(int) * p);
+  RFD_HIP(hipMemcpyAsync(work3.p, xs.data(), sizeof(double) * p, hipMemcpyHostToDevice, st));
+  int* cnt_d = reinterpret_cast<int*>(work3.as<double>() + p);
+  sturm_counts(st, tw, D, p, work3.as<double>(), 1, cnt_d);
+  auto cnt = download<int>(st, cnt_d, p);
+  const int extra = 6;
+  std::vector<int> lo(p), num(p);
+  int maxnum = 0;
+  for (int j = 0; j < p; ++j) {
+    const int d = (int)P->interior[j].size();
+    const int a = std::max(0, cnt[j] - nevb - extra), b = std::min(d, cnt[j] + nevb + extra);
+    lo[j] = a;
+    num[j] = b - a;
+    maxnum = std::max(maxnum, num[j]);
+  }
+  DevBuf lo_d, num_d, lam_d;
+  upload_v(lo_d, lo);
+  upload_v(num_d, num);
+  lam_d.alloc(sizeof(double) * (size_t)p * maxnum);
+  bisect(st, tw, D, p, lo_d.as<int>(), num_d.as<int>(), maxnum, lam_d.as<double>(), maxnum);
+  auto lam = download<double>(st, lam_d.p, (size_t)p * maxnum);
+  // nev_b closest to sigma, whole clusters at the cut (ascending window)
+  std::vector<int> w0(p), w1(p);
+  int kmax = 0;
+  for (int j = 0; j < p; ++j) {
+    std::vector<int> ord(num[j]);
+    std::iota(ord.begin(), ord.end(), 0);
+    const double* lj = lam.data() + (size_t)j * maxnum;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+      return std::fabs(lj[x] - sig) < std::fabs(lj[y] - sig);
+    });
+    int k = std::min(nevb, num[j]);
+    if (k > 0) {
+      const double cut = std::fabs(lj[ord[k - 1]] - sig);
+      while (k < num[j] && std::fabs(lj[ord[k]] - sig) <= cut * (1.0 + 1e-9) + 1e-300) ++k;
+    }
+    int a = num[j], b = 0;
+    for (int q = 0; q < k; ++q) {
+      a = std::min(a, ord[q]);
+      b = std::max(b, ord[q] + 1);
+    }
+    if (k == 0) a = b = 0;
+    w0[j] = a;
+    w1[j] = b;
+    kappa[j] = b - a;
+    kmax = std::max(kmax, kappa[j]);
+  }
+  VB = std::max<int64_t>(kmax, 1);
+  std::vector<double> sel((size_t)p * VB, 0.0);
+  std::vector<int> cl((size_t)p * VB, 0), knum(p);
+  const double tn = big;
+  for (int j = 0; j < p; ++j) {
+    std::vector<double> v(lam.begin() + (size_t)j * maxnum + w0[j],
+                          lam.begin() + (size_t)j * maxnum + w1[j]);
+    auto c = clusters(v, 1e-6 * tn);
+    for (int q = 0; q < kappa[j]; ++q) {
+      sel[(size_t)j * VB + q] = v[q];
+      cl[(size_t)j * VB + q] = c[q];
+    }
+    knum[j] = kappa[j];
+    kappa_tot += kappa[j];
+  }
+  DevBuf sel_d, cl_d, kn_d, scratch;
+  upload_v(sel_d, sel);
+  upload_v(cl_d, cl);
+  upload_v(kn_d, knum);
+  Vb.alloc(sizeof(double) * D * VB * p);
+  DMat<double> Y{Vb.as<double>(), nullptr, D, D * VB};
+  inverse_iteration(st, tw, D, p, sel_d.as<double>(), kn_d.as<int>(), cl_d.as<int>(), VB, Y,
+                    scratch);
+  back_transform(st, C, tw, D, p, Y, kn_d.as<int>(), (int)VB);
+  // V = M^{-1/2} Y
+  k_scale_rows<<<dim3(grid1(D * VB), p), 256, 0, st>>>(Y, D, VB, mis, D);
+  RFD_CHECK_LAUNCH();
+  upload_v(kap_d, kappa);
+  timer.end(st);
+  RFD_HIP(hipStreamSynchronize(st));
+  work2.release();
+  vcache_valid = true;
+  vcache_sigma = sig;
+  vcache_nevb = nevb;
+}
+
+void EngineImpl::factor_bsigma(hipStream_t st, double sig) {
+  if (bs_valid && bs_sigma == sig) return;
+  timer.begin(st, 7);
+  Bs.alloc(sizeof(double) * D * D * p);
+  Bsinv.alloc(sizeof(double) * NB * 2 * D * p);
+  Bspiv.alloc(sizeof(int32_t) * D * p);
+  DMat<double> K{Bs.as<double>(), nullptr, D, D * D};
+  DMat<double> Ki{Bsinv.as<double>(), nullptr, NB, NB * 2 * D};
+  fill<double>(st, K, D, D, p, 0.0);
+  Shifts z{zeta.as<double>()};
+  expand_shifted<double>(st, K, D, p, 1, 0, dj.as<int32_t>(), Bg.view(), z, true, sig);
+  lu_piv<double>(st, K, D, p, Ki, Bspiv.as<int32_t>(), flags.as<unsigned>(), 1e-300);
+  timer.end(st);
+  check_flags(st, "B_sigma factorization");
+  bs_valid = true;
+  bs_sigma = sig;
+}
+
+void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64_t* kout) {
+  EngineImpl& e = *d_;
+  if (e.Qint.p == nullptr) throw Error(ST_ESTATE, "rfd_filter_interface has not been called");
+  if (!e.P->m_diag) throw Error(ST_EINVAL, "the interior part on the GPU needs a diagonal M");
+  e.ensure_reordered();
+  e.interior_basis(st, sig, nevb);
+  e.factor_bsigma(st, sig);
+  const int p = e.p, mu = e.mu;
+  const int64_t D = e.D, n = e.n, s = e.s;
+  const int64_t n_int = n - s;
+  e.sigma = sig;
+  e.nev_b = nevb;
+  e.psi = psi;
+  e.MUP = round_up(std::max(mu, 1), NB);
+  const int64_t MUP = e.MUP;
+  const double* md = e.work1.as<double>();  // diag(M_B) per subdomain row (from interior_basis)
+  if (nevb == 0) {
+    e.work1.alloc(sizeof(double) * 2 * p * D);
+    k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, e.dj.as<int32_t>(), e.Bg.view(),
+                                              e.work1.as<double>(), e.work1.as<double>() + p * D);
+    RFD_CHECK_LAUNCH();
+    md = e.work1.as<double>();
+  }
+  // resolvent levels
+  e.timer.begin(st, 8);
+  e.Lev.alloc(sizeof(double) * D * psi * MUP * p);
+  e.work3.alloc(sizeof(double) * D * MUP * p);            // right-hand side / M_B X
+  e.work4.alloc(sizeof(double) * std::max<int64_t>(e.VB, 1) * MUP * p);  // V^T M X
+  DMat<double> Lv{e.Lev.as<double>(), nullptr, D, D * psi * MUP};
+  DMat<double> Rh{e.work3.as<double>(), nullptr, D, D * MUP};
+  DMat<double> Ki{e.Bsinv.as<double>(), nullptr, NB, NB * 2 * D};
+  DMat<double> Bm{e.Bs.as<double>(), nullptr, D, D * D};
+  DMat<double> Vm{e.Vb.as<double>(), nullptr, D, D * e.VB};
+  DMat<double> Tm{e.work4.as<double>(), nullptr, std::max<int64_t>(e.VB, 1),
+                  std::max<int64_t>(e.VB, 1) * MUP};
+  k_gather_phi<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(
+      Rh, D, MUP, e.dj.as<int32_t>(), e.Eg.view(), sig, e.Qint.as<double>(), s, mu,
+      e.adj.as<int32_t>(), e.SJ);
+  RFD_CHECK_LAUNCH();
+  for (int t = 0; t < psi; ++t) {
+    DMat<double> X = Lv.sub(0, t * MUP);
+    convert<double, double>(st, Rh, X, D, MUP, p);
+    lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p);
+    // make the level M_B-orthogonal to V_j
+    if (e.kappa_tot > 0) {
+      k_scaled_copy<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
+      RFD_CHECK_LAUNCH();
+      gemm<double>(st, true, false, e.VB, MUP, D, 1.0, Vm, Rh, 0.0, Tm, p);
+      gemm<double>(st, false, false, D, MUP, e.VB, -1.0, Vm, Tm, 1.0, X, p);
+    }
+    if (t + 1 < psi) {
+      k_scaled_copy<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
+      RFD_CHECK_LAUNCH();
+    }
+  }
+  e.timer.end(st);
+  // M-orthonormal basis of range(Z): [V | levels orthonormalised level by level]
+  e.timer.begin(st, 9);
+  const int64_t kmax = e.kappa_tot + (int64_t)psi * mu;
+  e.Zt.alloc(sizeof(double) * n * std::max<int64_t>(kmax, 1));
+  double* Z = e.Zt.as<double>();
+  RFD_HIP(hipMemsetAsync(Z, 0, sizeof(double) * n * std::max<int64_t>(kmax, 1), st));
+  std::vector<int32_t> koff(p, 0), ioff(p + 1, 0);
+  for (int j = 0; j < p; ++j) {
+    koff[j] = (j ? koff[j - 1] + e.kappa[j - 1] : 0);
+    ioff[j + 1] = ioff[j] + (int32_t)e.P->interior[j].size();
+  }
+  DevBuf koff_d, kap_d2;
+  upload_v(koff_d, koff);
+  upload_v(kap_d2, e.kappa);
+  if (e.kappa_tot > 0) {
+    k_scatter_v<<<dim3(grid1(D * e.VB), p), 256, 0, st>>>(Z, n, Vm, e.ioff.as<int32_t>(),
+                                                          koff_d.as<int32_t>(),
+                                                          kap_d2.as<int32_t>(), e.dj.as<int32_t>(), D);
+    RFD_CHECK_LAUNCH();
+  }
+  // reordered diagonal of M
+  e.work5.alloc(sizeof(double) * n * (int64_t)mu * 2);
+  double* Lb = e.work5.as<double>();             // current level block (n x mu)
+  double* MLb = Lb + n * (int64_t)mu;            // M * block
+  e.work6.alloc(sizeof(double) * ((int64_t)mu * mu * 3 + std::max<int64_t>(kmax, 1) * mu + 4 * mu + 8));
+  double* G = e.work6.as<double>();
+  double* Linv = G + (int64_t)mu * mu;
+  double* Tp = Linv + (int64_t)mu * mu;          // projections (kmax x mu)
+  double* n0 = Tp + std::max<int64_t>(kmax, 1) * mu;
+  double* n1 = n0 + mu;
+  int* piv = reinterpret_cast<int*>(n1 + mu);
+  int* rank_d = piv + mu;
+  DMat<double> dummy{nullptr, nullptr, 0, 0};
+  (void)dummy;
+  int64_t kz = e.kappa_tot;
+  for (int t = 0; t < psi && mu > 0; ++t) {
+    k_build_level<<<grid1(n * mu), 256, 0, st>>>(Lb, n, Lv, t, MUP, e.ioff.as<int32_t>(), p, n_int,
+                                                 n, e.Qint.as<double>(), s, mu);
+    RFD_CHECK_LAUNCH();
+    // column M-norms before projection
+    csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
+    k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n0);
+    RFD_CHECK_LAUNCH();
+    // project against the previous level blocks (M-inner product), twice
+    const int64_t kprev = kz - e.kappa_tot;
+    if (kprev > 0) {
+      DMat<double> Zp{Z + e.kappa_tot * n, nullptr, n, 0};
+      DMat<double> Tq{Tp, nullptr, kprev, 0};
+      DMat<double> Lm{Lb, nullptr, n, 0};
+      DMat<double> MLm{MLb, nullptr, n, 0};
+      for (int pass = 0; pass < 2; ++pass) {
+        csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
+        gemm<double>(st, true, false, kprev, mu, n, 1.0, Zp, MLm, 0.0, Tq, 1);
+        gemm<double>(st, false, false, n, mu, kprev, -1.0, Zp, Tq, 1.0, Lm, 1);
+      }
+    }
+    csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
+    k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n1);
+    RFD_CHECK_LAUNCH();
+    k_col_normalize<<<dim3(grid1(n), mu), 256, 0, st>>>(Lb, n, n, n1, n0, 1e-10);
+    RFD_CHECK_LAUNCH();
+    // Gram matrix and pivoted Cholesky, then two CholQR passes
+    for (int pass = 0; pass < 2; ++pass) {
+      const int64_t cols = (pass == 0) ? mu : -1;
+      int r = 0;
+      if (pass == 0) {
+        csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, cols);
+        DMat<double> Lm{Lb, nullptr, n, 0}, MLm{MLb, nullptr, n, 0}, Gm{G, nullptr, mu, 0};
+        gemm<double>(st, true, false, mu, mu, n, 1.0, Lm, MLm, 0.0, Gm, 1);
+        pivoted_cholesky(st, G, mu, mu, 1e-14, piv, rank_d, Linv, mu);
+        r = download<int>(st, rank_d, 1)[0];
+        if (r == 0) break;
+        // Q_t = L_t[:, piv[:r]] L^{-T}  -> into Z columns kz..kz+r
+        k_gather_cols<<<dim3(grid1(n), r), 256, 0, st>>>(Lb, n, MLb, n, n, piv, rank_d);
+        RFD_CHECK_LAUNCH();
+        DMat<double> Sel{MLb, nullptr, n, 0}, Li{Linv, nullptr, mu, 0}, Zo{Z + kz * n, nullptr, n, 0};
+        gemm<double>(st, false, true, n, r, r, 1.0, Sel, Li, 0.0, Zo, 1);
+        // second pass on the r new columns
+        csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Z + kz * n, n, MLb, n, r);
+        DMat<double> Zc{Z + kz * n, nullptr, n, 0}, MZc{MLb, nullptr, n, 0}, G2{G, nullptr, r, 0};
+        gemm<double>(st, true, false, r, r, n, 1.0, Zc, MZc, 0.0, G2, 1);
+        pivoted_cholesky(st, G, r, r, 1e-20, piv, rank_d, Linv, r);
+        const int r2 = download<int>(st, rank_d, 1)[0];
+        k_gather_cols<<<dim3(grid1(n), r2), 256, 0, st>>>(Z + kz * n, n, Lb, n, n, piv, rank_d);
+        RFD_CHECK_LAUNCH();
+        DMat<double> Sel2{Lb, nullptr, n, 0}, Li2{Linv, nullptr, r, 0};
+        gemm<double>(st, false, true, n, r2, r2, 1.0, Sel2, Li2, 0.0, Zc, 1);
+        if (r2 < r)
+          RFD_HIP(hipMemsetAsync(Z + (kz + r2) * n, 0, sizeof(double) * n * (r - r2), st));
+        kz += r2;
+        break;
+      }
+    }
+  }
+  e.kz = kz;
+  e.timer.end(st);
+  RFD_HIP(hipStreamSynchronize(st));
+  e.interior_ready = true;
+  *kout = kz;
+}
+
+void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* evecs,
+                           double* resid, int* nfound) {
+  EngineImpl& e = *d_;
+  if (!e.interior_ready) throw Error(ST_ESTATE, "rfd_solve_interior has not been called");
+  const int64_t n = e.n, k = e.kz;
+  *nfound = 0;
+  if (k == 0) return;
+  double* Z = e.Zt.as<double>();
+  // H = Z^T A Z
+  e.timer.begin(st, 9);
+  DevBuf AZ, Hb;
+  AZ.alloc(sizeof(double) * n * k);
+  Hb.alloc(sizeof(double) * k * k);
+  csr_mm(st, e.Arptr, e.Aridx, e.Arval, n, Z, n, AZ.as<double>(), n, k);
+  DMat<double> Zm{Z, nullptr, n, 0}, AZm{AZ.as<double>(), nullptr, n, 0}, Hm{Hb.as<double>(), nullptr, k, 0};
+  gemm<double>(st, true, false, k, k, n, 1.0, Zm, AZm, 0.0, Hm, 1);
+  k_symmetrize<<<grid1(k * k), 256, 0, st>>>(Hb.as<double>(), k, k);
+  RFD_CHECK_LAUNCH();
+  e.timer.end(st);
+  // eigenpairs of H in [alpha, beta]
+  e.timer.begin(st, 10);
+  TriWork tw;
+  sy_tridiag(st, Hm, k, 1, tw);
+  DevBuf xs, cnt;
+  std::vector<double> ab{e.poles.alpha, e.poles.beta};
+  upload_v(xs, ab);
+  cnt.alloc(sizeof(int) * 2);
+  sturm_counts(st, tw, k, 1, xs.as<double>(), 2, cnt.as<int>());
+  auto c = download<int>(st, cnt.p, 2);
+  const int i0 = c[0], nf = c[1] - c[0];
+  *nfound = nf;
+  const int nout = std::min(nf, max_out);
+  if (nout <= 0) {
+    e.timer.end(st);
+    return;
+  }
+  DevBuf lo_d, num_d, lam_d;
+  upload_v(lo_d, std::vector<int>{i0});
+  upload_v(num_d, std::vector<int>{nout});
+  lam_d.alloc(sizeof(double) * nout);
+  bisect(st, tw, k, 1, lo_d.as<int>(), num_d.as<int>(), nout, lam_d.as<double>(), nout);
+  auto lam = download<double>(st, lam_d.p, nout);
+  double tn = 0;
+  for (double v : lam) tn = std::max(tn, std::fabs(v));
+  tn = std::max(tn, e.normA);
+  auto cl = clusters(lam, 1e-6 * tn);
+  DevBuf cl_d, Gv, scratch;
+  upload_v(cl_d, cl);
+  Gv.alloc(sizeof(double) * k * nout);
+  DMat<double> Gm{Gv.as<double>(), nullptr, k, 0};
+  inverse_iteration(st, tw, k, 1, lam_d.as<double>(), num_d.as<int>(), cl_d.as<int>(), nout, Gm,
+                    scratch);
+  back_transform(st, Hm, tw, k, 1, Gm, num_d.as<int>(), nout);
+  e.timer.end(st);
+  // Ritz vectors, original numbering, residuals
+  e.timer.begin(st, 11);
+  RFD_HIP(hipMemcpyAsync(evals, lam_d.p, sizeof(double) * nout, hipMemcpyDeviceToDevice, st));
+  DevBuf Xr, X2, AX, MX;
+  Xr.alloc(sizeof(double) * n * nout);
+  DMat<double> Xm{Xr.as<double>(), nullptr, n, 0};
+  gemm<double>(st, false, false, n, nout, k, 1.0, Zm, Gm, 0.0, Xm, 1);
+  double* Xo = evecs;
+  if (!Xo) {
+    X2.alloc(sizeof(double) * n * nout);
+    Xo = X2.as<double>();
+  }
+  k_unpermute<<<grid1(n * nout), 256, 0, st>>>(Xr.as<double>(), n, e.order.as<int32_t>(), n, Xo, n,
+                                               nout);
+  RFD_CHECK_LAUNCH();
+  if (resid) {
+    AX.alloc(sizeof(double) * n * nout);
+    MX.alloc(sizeof(double) * n * nout);
+    csr_mm(st, e.Aptr, e.Aidx, e.Aval, n, Xo, n, AX.as<double>(), n, nout);
+    csr_mm(st, e.Mptr, e.Midx, e.Mval, n, Xo, n, MX.as<double>(), n, nout);
+    k_resid<<<nout, 256, 0, st>>>(AX.as<double>(), MX.as<double>(), Xo, n, n, lam_d.as<double>(),
+                                  e.normA, resid);
+    RFD_CHECK_LAUNCH();
+  }
+  e.timer.end(st);
+  RFD_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace rfd

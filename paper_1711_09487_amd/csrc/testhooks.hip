@@ -1,0 +1,78 @@
+// Kernel-level entry points for the test-suite: each wraps one batched
+// building block so that it can be checked element by element against a
+// host computation.  Declared in include/rfd_testing.h.
+#include <cstring>
+
+#include "dense.hpp"
+#include "rfd_capi_util.hpp"
+
+using namespace rfd;
+
+template <typename T>
+static DMat<T> dm(void* re, void* im, int64_t ld, int64_t bs) {
+  DMat<T> m;
+  m.re = (T*)re;
+  m.im = (T*)im;
+  m.ld = ld;
+  m.bs = bs;
+  return m;
+}
+
+extern "C" int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K,
+                             double alpha, double beta, void* a_re, void* a_im, int64_t lda,
+                             int64_t sa, void* b_re, void* b_im, int64_t ldb, int64_t sb,
+                             void* c_re, void* c_im, int64_t ldc, int64_t sc, int batch,
+                             void* stream) {
+  return capi_guard([&] {
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == 0)
+      gemm<float>(s, ta, tb, M, N, K, (float)alpha, dm<float>(a_re, a_im, lda, sa),
+                  dm<float>(b_re, b_im, ldb, sb), (float)beta, dm<float>(c_re, c_im, ldc, sc),
+                  batch);
+    else
+      gemm<double>(s, ta, tb, M, N, K, alpha, dm<double>(a_re, a_im, lda, sa),
+                   dm<double>(b_re, b_im, ldb, sb), beta, dm<double>(c_re, c_im, ldc, sc),
+                   batch);
+  });
+}
+
+// Factors A (n x n items, in place) and solves A X = R in place (n x r items).
+// pivot = 1 selects partial pivoting (real only).  *flags_out receives the
+// breakdown flags.
+extern "C" int rfd_test_lu(int dtype, int pivot, int64_t n, int batch, void* a_re, void* a_im,
+                           int64_t lda, int64_t sa, void* r_re, void* r_im, int64_t ldr,
+                           int64_t sr, int64_t r, unsigned* flags_out, void* stream) {
+  return capi_guard([&] {
+    hipStream_t s = (hipStream_t)stream;
+    const size_t es = dtype == 0 ? 4 : 8;
+    const int64_t ibs = NB * 2 * n;
+    const int planes = a_im ? 2 : 1;
+    void* inv = nullptr;
+    unsigned* flags = nullptr;
+    int32_t* ipiv = nullptr;
+    RFD_HIP(hipMalloc(&inv, es * ibs * batch * planes));
+    RFD_HIP(hipMalloc(&flags, sizeof(unsigned)));
+    RFD_HIP(hipMalloc(&ipiv, sizeof(int32_t) * n * batch));
+    RFD_HIP(hipMemsetAsync(flags, 0, sizeof(unsigned), s));
+    char* ib = (char*)inv;
+    void* iim = planes == 2 ? (void*)(ib + es * ibs * batch) : nullptr;
+    if (dtype == 0) {
+      auto A = dm<float>(a_re, a_im, lda, sa);
+      auto I = dm<float>(inv, iim, NB, ibs);
+      if (pivot) lu_piv<float>(s, A, n, batch, I, ipiv, flags, 1e-30);
+      else lu_nopiv<float>(s, A, n, batch, I, flags, 1e-30);
+      if (r > 0) lu_solve<float>(s, A, I, pivot ? ipiv : nullptr, n, dm<float>(r_re, r_im, ldr, sr), r, batch);
+    } else {
+      auto A = dm<double>(a_re, a_im, lda, sa);
+      auto I = dm<double>(inv, iim, NB, ibs);
+      if (pivot) lu_piv<double>(s, A, n, batch, I, ipiv, flags, 1e-300);
+      else lu_nopiv<double>(s, A, n, batch, I, flags, 1e-300);
+      if (r > 0) lu_solve<double>(s, A, I, pivot ? ipiv : nullptr, n, dm<double>(r_re, r_im, ldr, sr), r, batch);
+    }
+    RFD_HIP(hipMemcpyAsync(flags_out, flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    RFD_HIP(hipStreamSynchronize(s));
+    RFD_HIP(hipFree(inv));
+    RFD_HIP(hipFree(flags));
+    RFD_HIP(hipFree(ipiv));
+  });
+}

@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every entry point declared in include/*.h, and argument validation
+rejects bad input with the documented status codes."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            names |= set(re.findall(r"^\s*(?:rfd_status|const char\*|int)\s+(rfd_\w+)\s*\(", txt, re.M))
+    return names
+
+
+def _lib():
+    import paper_1711_09487_amd as R
+    if not os.path.exists(R.LIB_PATH):
+        pytest.skip("library not built")
+    return R
+
+
+def test_library_exports_every_declared_symbol():
+    R = _lib()
+    names = _declared()
+    assert {"rfd_create_pencil", "rfd_set_partition", "rfd_set_interval_and_poles",
+            "rfd_filter_interface", "rfd_solve_interior", "rfd_rayleigh_ritz"} <= names
+    L = R.lib()
+    for nm in sorted(names):
+        assert hasattr(L, nm), nm
+
+
+def test_create_pencil_validation():
+    R = _lib()
+    A = W.laplacian((5, 5))
+    M = sp.identity(25, format="csr")
+    h = R.rfd_create_pencil(A, M)
+    R.rfd_destroy_pencil(h)
+    Ab = A.tolil()
+    Ab[0, 1] = 5.0                       # not symmetric
+    with pytest.raises(R.RfdError) as e:
+        R.rfd_create_pencil(Ab.tocsr(), M)
+    assert e.value.code == 1
+    Mb = sp.diags(np.r_[-1.0, np.ones(24)]).tocsr()
+    with pytest.raises(R.RfdError) as e:
+        R.rfd_create_pencil(A, Mb)
+    assert e.value.code == 1
+
+
+def test_partition_and_interval_validation():
+    R = _lib()
+    A = W.laplacian((7, 7))
+    M = sp.identity(49, format="csr")
+    h = R.rfd_create_pencil(A, M)
+    try:
+        bad = np.zeros(49, dtype=np.int32)
+        bad[25:] = 1                     # subdomains touch directly
+        with pytest.raises(R.RfdError) as e:
+            R.rfd_set_partition(h, 2, bad)
+        assert e.value.code == 1
+        with pytest.raises(R.RfdError):
+            R.rfd_set_partition(h, 2, np.full(49, 5, dtype=np.int32))
+        with pytest.raises(R.RfdError) as e:
+            R.rfd_set_interval_and_poles(h, 1.0, 0.5, 4)
+        assert e.value.code == 1
+        with pytest.raises(R.RfdError):
+            R.rfd_set_interval_and_poles(h, 0.0, 1.0, 0)
+        with pytest.raises(R.RfdError):
+            R.rfd_set_precision(h, 7)
+        with pytest.raises(R.RfdError) as e:
+            R.rfd_solve_interior(h, 0.1, 4, 2, stream=0)
+        assert e.value.code == 6        # before set_partition
+        assert R.rfd_last_error() != ""
+    finally:
+        R.rfd_destroy_pencil(h)
+
+
+def test_destroy_null_is_ok():
+    R = _lib()
+    assert R.lib().rfd_destroy_pencil(None) == 0

@@ -1,0 +1,143 @@
+"""Kernel-level GPU checks of the dense building blocks (batched MFMA GEMM,
+LU without and with pivoting, block triangular solves) against FP64 host
+computations, through the library's test entry points."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _dev(torch, a, dt):
+    """numpy (batch, rows, cols) -> device tensor laid out column-major per item."""
+    t = torch.from_numpy(np.ascontiguousarray(np.swapaxes(a, 1, 2))).to(dt).cuda()
+    return t  # shape (batch, cols, rows): item stride rows*cols, ld = rows
+
+
+def _host(t):
+    return np.swapaxes(t.double().cpu().numpy(), 1, 2)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_batched(dtype, cplx, ta, tb):
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    rs = np.random.default_rng(1)
+    M, N, K, batch = 70, 130, 37, 3
+    dt = torch.float32 if dtype == 0 else torch.float64
+    Ash = (batch, K, M) if ta else (batch, M, K)
+    Bsh = (batch, N, K) if tb else (batch, K, N)
+    Ar, Ai = rs.standard_normal(Ash), rs.standard_normal(Ash)
+    Br, Bi = rs.standard_normal(Bsh), rs.standard_normal(Bsh)
+    Cr, Ci = rs.standard_normal((batch, M, N)), rs.standard_normal((batch, M, N))
+    alpha, beta = -0.75, 0.5
+    A = Ar + 1j * Ai if cplx else Ar
+    B = Br + 1j * Bi if cplx else Br
+    Cref = Cr + 1j * Ci if cplx else Cr.copy()
+    opA = np.swapaxes(A, 1, 2) if ta else A
+    opB = np.swapaxes(B, 1, 2) if tb else B
+    ref = alpha * (opA @ opB) + beta * Cref
+    t = {k: _dev(torch, v, dt) for k, v in dict(ar=Ar, ai=Ai, br=Br, bi=Bi, cr=Cr, ci=Ci).items()}
+    lda, ldb, ldc = Ash[1], Bsh[1], M
+    code = R.lib().rfd_test_gemm(
+        dtype, ta, tb, M, N, K, alpha, beta,
+        t["ar"].data_ptr(), t["ai"].data_ptr() if cplx else None, lda, Ash[1] * Ash[2],
+        t["br"].data_ptr(), t["bi"].data_ptr() if cplx else None, ldb, Bsh[1] * Bsh[2],
+        t["cr"].data_ptr(), t["ci"].data_ptr() if cplx else None, ldc, M * N, batch,
+        torch.cuda.current_stream().cuda_stream)
+    assert code == 0, R.rfd_last_error()
+    torch.cuda.synchronize()
+    got = _host(t["cr"]) + (1j * _host(t["ci"]) if cplx else 0)
+    tol = 2e-5 if dtype == 0 else 1e-13
+    assert np.max(np.abs(got - ref)) < tol * np.max(np.abs(ref)) * np.sqrt(K)
+
+
+def _shifted_blocks(rs, n, batch, cplx):
+    """Shifted 1D/2D-Laplacian-like blocks B - z M, complex symmetric."""
+    out = []
+    for b in range(batch):
+        T = np.diag(4.0 + rs.uniform(0, 0.1, n)) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)
+        k = int(np.sqrt(n))
+        T -= np.diag(np.ones(n - k), k) + np.diag(np.ones(n - k), -k)
+        Md = np.diag(rs.uniform(0.5, 1.5, n))
+        z = (0.3 + 0.05j * (b + 1)) if cplx else 0.0
+        out.append(T - z * Md)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_lu_nopiv_solve(dtype, cplx):
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    rs = np.random.default_rng(2)
+    n, batch, r = 192, 3, 70
+    dt = torch.float32 if dtype == 0 else torch.float64
+    A = _shifted_blocks(rs, n, batch, cplx)
+    Rh = rs.standard_normal((batch, n, r)) + (1j * rs.standard_normal((batch, n, r)) if cplx else 0)
+    X = np.linalg.solve(A, Rh)
+    ar, ai = _dev(torch, A.real, dt), _dev(torch, A.imag, dt)
+    rr, ri = _dev(torch, Rh.real, dt), _dev(torch, np.imag(Rh), dt)
+    flags = C.c_uint32(7)
+    code = R.lib().rfd_test_lu(dtype, 0, n, batch, ar.data_ptr(), ai.data_ptr() if cplx else None,
+                               n, n * n, rr.data_ptr(), ri.data_ptr() if cplx else None, n, n * r,
+                               r, C.byref(flags), torch.cuda.current_stream().cuda_stream)
+    assert code == 0, R.rfd_last_error()
+    assert flags.value == 0
+    got = _host(rr) + (1j * _host(ri) if cplx else 0)
+    tol = 2e-5 if dtype == 0 else 1e-12
+    assert np.max(np.abs(got - X)) < tol * np.max(np.abs(X))
+    # the factors themselves: L U = A
+    F = _host(ar) + (1j * _host(ai) if cplx else 0)
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    assert np.max(np.abs(L @ U - A)) < (5e-6 if dtype == 0 else 1e-13) * np.max(np.abs(A))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_lu_partial_pivoting_solve(dtype):
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    rs = np.random.default_rng(3)
+    n, batch, r = 192, 2, 65
+    dt = torch.float32 if dtype == 0 else torch.float64
+    A = rs.standard_normal((batch, n, n))          # needs pivoting
+    A[:, 0, 0] = 0.0
+    Rh = rs.standard_normal((batch, n, r))
+    X = np.linalg.solve(A, Rh)
+    ar, rr = _dev(torch, A, dt), _dev(torch, Rh, dt)
+    flags = C.c_uint32(7)
+    code = R.lib().rfd_test_lu(dtype, 1, n, batch, ar.data_ptr(), None, n, n * n, rr.data_ptr(),
+                               None, n, n * r, r, C.byref(flags),
+                               torch.cuda.current_stream().cuda_stream)
+    assert code == 0, R.rfd_last_error()
+    assert flags.value == 0
+    got = _host(rr)
+    cond = np.linalg.cond(A[0])
+    tol = (1e-6 if dtype == 0 else 1e-14) * cond
+    assert np.max(np.abs(got - X)) < tol * np.max(np.abs(X))
+
+
+def test_lu_breakdown_flag():
+    """A singular block (a zero leading pivot, no pivoting) raises the flag."""
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    n = 64
+    A = np.eye(n)[None].copy()
+    A[0, 0, 0] = 0.0
+    ar = _dev(torch, A, torch.float64)
+    flags = C.c_uint32(0)
+    code = R.lib().rfd_test_lu(1, 0, n, 1, ar.data_ptr(), None, n, n * n, None, None, n, 0, 0,
+                               C.byref(flags), torch.cuda.current_stream().cuda_stream)
+    assert code == 0
+    assert flags.value != 0
