@@ -216,6 +216,20 @@ rfd_status rfd_pencil_info(rfd_pencil_t pencil, int64_t* n, int32_t* p, int64_t*
 rfd_status rfd_set_timing(rfd_pencil_t pencil, int32_t on);
 rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16);
 
+/*
+ * rfd_kernel_accounting / rfd_kernel_stats -- process-wide timing of every
+ * launch of the batched GEMM kernel (the matrix-core kernel behind the LU
+ * updates, the triangular solves, the refinement residuals and the
+ * Rayleigh-Ritz products).  When on, each launch is bracketed by HIP events
+ * on its own stream and its algorithmic flop count is recorded (2MNK real,
+ * 8MNK complex, times the batch).  rfd_kernel_stats synchronises those
+ * events and returns, for the 16 instantiations key = 8*fp64 + 4*complex +
+ * 2*transA + transB, the number of launches, the summed milliseconds and the
+ * summed flops (host arrays of 16 doubles each), then clears the record.
+ */
+rfd_status rfd_kernel_accounting(int32_t on);
+rfd_status rfd_kernel_stats(double* launches, double* ms, double* flops);
+
 #ifdef __cplusplus
 }
 #endif

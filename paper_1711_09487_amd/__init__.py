@@ -65,6 +65,9 @@ def lib():
                                 C.POINTER(I64), C.POINTER(I64)],
             "rfd_set_timing": [P, I32],
             "rfd_reset_caches": [P, I32],
+            "rfd_test_basis": [P, P, I64, C.POINTER(I64), P],
+            "rfd_kernel_accounting": [I32],
+            "rfd_kernel_stats": [P, P, P],
             "rfd_phase_times": [P, P],
             "rfd_test_gemm": [I32, I32, I32, I64, I64, I64, F64, F64, P, P, I64, I64, P, P, I64,
                               I64, P, P, I64, I64, I32, P],
@@ -190,6 +193,22 @@ def rfd_pencil_info(h):
 
 def rfd_reset_caches(h, release=False):
     _check(lib().rfd_reset_caches(h, int(bool(release))))
+
+
+GEMM_KEYS = {8 * f + 4 * c + 2 * a + b: f"k_gemm<{'double' if f else 'float'}, "
+             f"{'true' if c else 'false'}, {'true' if a else 'false'}, {'true' if b else 'false'}>"
+             for f in (0, 1) for c in (0, 1) for a in (0, 1) for b in (0, 1)}
+
+
+def rfd_kernel_accounting(on):
+    _check(lib().rfd_kernel_accounting(int(bool(on))))
+
+
+def rfd_kernel_stats():
+    """{instantiation name: (launches, ms, flops)} since the last call."""
+    L, T, F = np.zeros(16), np.zeros(16), np.zeros(16)
+    _check(lib().rfd_kernel_stats(L.ctypes.data, T.ctypes.data, F.ctypes.data))
+    return {GEMM_KEYS[k]: (int(L[k]), float(T[k]), float(F[k])) for k in range(16) if L[k] > 0}
 
 
 def rfd_set_timing(h, on):

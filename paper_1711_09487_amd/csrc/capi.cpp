@@ -6,6 +6,7 @@
 #include "../../include/rfd.h"
 #include "engine.hpp"
 #include "pencil.hpp"
+#include "dense.hpp"
 #include "rfd_capi_util.hpp"
 
 namespace rfd {
@@ -198,6 +199,25 @@ rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16) {
     if (!ms16) throw Error(ST_EINVAL, "null output");
     for (int i = 0; i < 16; ++i) ms16[i] = 0;
     if (P->eng) P->eng->phase_times(ms16);
+  });
+}
+
+rfd_status rfd_kernel_accounting(int32_t on) {
+  return (rfd_status)capi_guard([&] { KernelAccount::get().enabled = on != 0; });
+}
+
+rfd_status rfd_kernel_stats(double* launches, double* ms, double* flops) {
+  return (rfd_status)capi_guard([&] {
+    if (!launches || !ms || !flops) throw Error(ST_EINVAL, "null output");
+    KernelAccount::get().collect(launches, ms, flops, 16);
+  });
+}
+
+int rfd_test_basis(void* pencil, double* dst, int64_t cap, int64_t* k_out, void* stream) {
+  return capi_guard([&] {
+    auto* P = need((rfd_pencil_t)pencil);
+    Engine& E = need_engine(P);
+    E.copy_basis((hipStream_t)stream, dst, cap, k_out);
   });
 }
 

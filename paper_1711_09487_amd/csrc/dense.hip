@@ -169,9 +169,55 @@ void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T al
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (batch > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
   dim3 g((unsigned)((M + GBM - 1) / GBM), (unsigned)((N + GBN - 1) / GBN), (unsigned)batch);
+  const int key = (sizeof(T) == 8 ? 8 : 0) + (C.cplx() ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
+  const double flops = (C.cplx() ? 8.0 : 2.0) * (double)M * (double)N * (double)K * batch;
+  KernelAccount::Scope acct(s, key, flops);
   if (C.cplx()) gemm_dispatch<T, true>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C);
   else gemm_dispatch<T, false>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C);
   RFD_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Per-launch accounting of the GEMM instantiations (key = 8 * fp64 + 4 * complex
+// + 2 * ta + tb): HIP events on the launch stream and algorithmic flops.
+// ---------------------------------------------------------------------------
+KernelAccount& KernelAccount::get() {
+  static KernelAccount a;
+  return a;
+}
+
+KernelAccount::Scope::Scope(hipStream_t s, int key, double flops) : s_(s) {
+  KernelAccount& a = get();
+  if (!a.enabled) return;
+  Rec r;
+  r.key = key;
+  r.flops = flops;
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+  (void)hipEventRecord(r.a, s);
+  rec_ = (int)a.recs.size();
+  a.recs.push_back(r);
+}
+
+KernelAccount::Scope::~Scope() {
+  if (rec_ < 0) return;
+  KernelAccount& a = get();
+  (void)hipEventRecord(a.recs[rec_].b, s_);
+}
+
+void KernelAccount::collect(double* launches, double* ms, double* flops, int nkeys) {
+  for (int k = 0; k < nkeys; ++k) launches[k] = ms[k] = flops[k] = 0;
+  for (auto& r : recs) {
+    float t = 0;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess &&
+        r.key < nkeys) {
+      launches[r.key] += 1;
+      ms[r.key] += t;
+      flops[r.key] += r.flops;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  recs.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -199,7 +245,7 @@ __device__ inline void cinv(T ar, T ai, T& cr, T& ci) {
 // ---------------------------------------------------------------------------
 template <typename T, bool CPLX>
 __device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], DMat<T> Linv,
-                             DMat<T> Uinv) {
+                             DMat<T> Uinv, const int* dropped = nullptr) {
   constexpr int NP = CPLX ? 2 : 1;
   const int tid = threadIdx.x;
   // Linv: column c solved by thread c (forward substitution, unit diagonal)
@@ -223,6 +269,12 @@ __device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], DMat<T> Lin
       if constexpr (CPLX) X[NP - 1][i][c] = si;
     }
   }
+  __syncthreads();
+  // a dropped column (semidefinite mode) gets a zero row in Linv, so that the
+  // panel update leaves a zero row of U beside it
+  if (dropped)
+    for (int e = tid; e < NB * NB; e += blockDim.x)
+      if (dropped[e % NB]) X[0][e % NB][e / NB] = 0;
   __syncthreads();
   for (int e = tid; e < NB * NB; e += blockDim.x) {
     const int i = e % NB, c = e / NB;
@@ -271,11 +323,13 @@ __device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], DMat<T> Lin
 
 template <typename T, bool CPLX>
 __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> inv, int iblk,
-                                                 unsigned* flags, T tiny) {
+                                                 unsigned* flags, T tiny, int* drop, T droptol) {
   constexpr int NP = CPLX ? 2 : 1;
   __shared__ T F[NP][NB][NB + 1];
   __shared__ T X[NP][NB][NB + 1];
+  __shared__ int dl[NB];
   const int tid = threadIdx.x;
+  if (tid < NB) dl[tid] = 0;
   DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
   for (int e = tid; e < NB * NB; e += 256) {
     const int i = e % NB, j = e / NB;
@@ -286,6 +340,22 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
   for (int j = 0; j < NB; ++j) {
     const T pr = F[0][j][j], pim = CPLX ? F[NP - 1][j][j] : T(0);
     const T mag = CPLX ? sqrt(pr * pr + pim * pim) : fabs(pr);
+    if (!CPLX && drop && !(pr > droptol)) {
+      // semidefinite mode: the Schur complement pivot vanished, so column j
+      // lies in the span of the earlier ones; it is removed from the factor
+      __syncthreads();
+      for (int i = j + 1 + tid; i < NB; i += 256) {
+        F[0][i][j] = 0;
+        F[0][j][i] = 0;
+      }
+      if (tid == 0) {
+        F[0][j][j] = 1;
+        dl[j] = 1;
+        drop[k0 + j] = 1;
+      }
+      __syncthreads();
+      continue;
+    }
     if (tid == 0) {
       if (!(mag > tiny)) atomicOr(flags, (mag == mag) ? 1u : 2u);
     }
@@ -323,7 +393,8 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
     if constexpr (CPLX) a.im[i + j * a.ld] = F[NP - 1][i][j];
   }
   DMat<T> iv = inv.item(blockIdx.x);
-  tri_inverses<T, CPLX>(F, X, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB));
+  tri_inverses<T, CPLX>(F, X, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB),
+                        drop ? dl : nullptr);
 }
 
 // Inverses only (block already factored, e.g. by the pivoted panel).
@@ -346,15 +417,17 @@ __global__ __launch_bounds__(256) void k_tri_inv(DMat<T> A, int64_t k0, DMat<T> 
 
 template <typename T>
 void lu_nopiv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, unsigned* flags,
-              double tiny) {
+              double tiny, int* drop, double droptol) {
   if (n % NB) throw Error(ST_EINVAL, "lu_nopiv: n not a multiple of the block size");
+  if (drop && (A.cplx() || batch != 1)) throw Error(ST_EINVAL, "lu_nopiv: drop mode is real, unbatched");
   const int64_t nblk = n / NB;
   for (int64_t i = 0; i < nblk; ++i) {
     const int64_t k0 = i * NB, rest = n - k0 - NB;
     if (A.cplx())
-      k_lu_diag<T, true><<<batch, 256, 0, s>>>(A, k0, inv, (int)i, flags, (T)tiny);
+      k_lu_diag<T, true><<<batch, 256, 0, s>>>(A, k0, inv, (int)i, flags, (T)tiny, nullptr, T(0));
     else
-      k_lu_diag<T, false><<<batch, 256, 0, s>>>(A, k0, inv, (int)i, flags, (T)tiny);
+      k_lu_diag<T, false><<<batch, 256, 0, s>>>(A, k0, inv, (int)i, flags, (T)tiny, drop,
+                                                 (T)droptol);
     RFD_CHECK_LAUNCH();
     if (rest > 0) {
       DMat<T> Linv = inv.sub(0, 2 * NB * i), Uinv = inv.sub(0, 2 * NB * i + NB);
@@ -484,11 +557,11 @@ void lu_piv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, int32_t
 
 template <typename T>
 void lu_solve(hipStream_t s, DMat<T> LU, DMat<T> inv, const int32_t* ipiv, int64_t n, DMat<T> R,
-              int64_t r, int batch) {
+              int64_t r, int batch, int parts) {
   if (n % NB) throw Error(ST_EINVAL, "lu_solve: n not a multiple of the block size");
   const int64_t nblk = n / NB;
-  if (ipiv) laswp<T>(s, R, n, ipiv, 0, n, 0, r, batch);
-  for (int64_t i = 0; i < nblk; ++i) {
+  if (ipiv && (parts & 1)) laswp<T>(s, R, n, ipiv, 0, n, 0, r, batch);
+  for (int64_t i = 0; i < nblk && (parts & 1); ++i) {
     const int64_t k0 = i * NB, rest = n - k0 - NB;
     gemm<T>(s, false, false, NB, r, NB, T(1), inv.sub(0, 2 * NB * i), R.sub(k0, 0), T(0),
             R.sub(k0, 0), batch);
@@ -496,7 +569,7 @@ void lu_solve(hipStream_t s, DMat<T> LU, DMat<T> inv, const int32_t* ipiv, int64
       gemm<T>(s, false, false, rest, r, NB, T(-1), LU.sub(k0 + NB, k0), R.sub(k0, 0), T(1),
               R.sub(k0 + NB, 0), batch);
   }
-  for (int64_t i = nblk - 1; i >= 0; --i) {
+  for (int64_t i = nblk - 1; i >= 0 && (parts & 2); --i) {
     const int64_t k0 = i * NB;
     gemm<T>(s, false, false, NB, r, NB, T(1), inv.sub(0, 2 * NB * i + NB), R.sub(k0, 0), T(0),
             R.sub(k0, 0), batch);
@@ -618,11 +691,12 @@ void absmax(hipStream_t s, DMat<T> X, int64_t rows, int64_t cols, int batch, dou
 #define RFD_INST(T)                                                                          \
   template void gemm<T>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, T, DMat<T>,      \
                         DMat<T>, T, DMat<T>, int);                                           \
-  template void lu_nopiv<T>(hipStream_t, DMat<T>, int64_t, int, DMat<T>, unsigned*, double); \
+  template void lu_nopiv<T>(hipStream_t, DMat<T>, int64_t, int, DMat<T>, unsigned*, double,     \
+                            int*, double);                                                   \
   template void lu_piv<T>(hipStream_t, DMat<T>, int64_t, int, DMat<T>, int32_t*, unsigned*,  \
                           double);                                                           \
   template void lu_solve<T>(hipStream_t, DMat<T>, DMat<T>, const int32_t*, int64_t, DMat<T>, \
-                            int64_t, int);                                                   \
+                            int64_t, int, int);                                                   \
   template void fill<T>(hipStream_t, DMat<T>, int64_t, int64_t, int, T);                     \
   template void pad_identity<T>(hipStream_t, DMat<T>, int64_t, int64_t, int);                \
   template void absmax<T>(hipStream_t, DMat<T>, int64_t, int64_t, int, double*);

@@ -25,6 +25,7 @@ class Engine {
                      int* nfound);
   int64_t device_bytes() const;
   void reset_caches(bool release);
+  void copy_basis(hipStream_t s, double* dst, int64_t cap, int64_t* k);
   void set_timing(bool on);
   void phase_times(double* ms16);
 

@@ -79,7 +79,7 @@ struct EngineImpl {
   DevBuf Zt;                              // M-orthonormal basis of range(Z), n x k (reordered)
   int64_t kz = 0;                         // columns of Zt
   DevBuf work1, work2, work3, work4, work5, work6;
-  DevBuf ipiv_small, iscal;
+  DevBuf ipiv_small, iscal, gwork, work6b;
   PhaseTimer timer;
   DevBuf flags, scal;
 
@@ -94,6 +94,10 @@ struct EngineImpl {
   void ensure_reordered();
   void interior_basis(hipStream_t st, double sigma, int nev_b);
   void factor_bsigma(hipStream_t st, double sigma);
+  int gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,
+                double droptol);
+  void project_out(hipStream_t st, double* X, int ncols, double* MX, const double* Zp,
+                   int64_t kprev, int passes);
 };
 
 }  // namespace rfd

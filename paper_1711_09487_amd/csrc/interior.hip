@@ -13,6 +13,8 @@
 //                     their residuals.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "dense.hpp"
@@ -86,6 +88,36 @@ __global__ void k_scaled_copy(DMat<double> X, DMat<double> Y, int64_t rows, int6
   const int64_t r = e % rows, c = e / rows;
   DMat<double> x = X.item(blockIdx.y), y = Y.item(blockIdx.y);
   y.re[r + c * y.ld] = vec[(int64_t)blockIdx.y * D + r] * x.re[r + c * x.ld];
+}
+
+// out[c] = || column c of the level over all subdomains ||_{M_B}, one workgroup per column.
+__global__ void k_level_colnorm(DMat<double> X, int p, const int32_t* dj, const double* md,
+                                int64_t D, double* out) {
+  __shared__ double red[256];
+  const int64_t c = blockIdx.x;
+  double acc = 0;
+  for (int j = 0; j < p; ++j) {
+    DMat<double> x = X.item(j);
+    for (int64_t r = threadIdx.x; r < dj[j]; r += blockDim.x) {
+      const double v = x.re[r + c * x.ld];
+      acc += md[(int64_t)j * D + r] * v * v;
+    }
+  }
+  acc = bsum(acc, red);
+  if (threadIdx.x == 0) out[c] = sqrt(acc);
+}
+
+// Zeroes column c of every subdomain's level when post[c] <= thr * pre[c]:
+// a level that lies inside span(V_j) up to rounding carries no direction.
+__global__ void k_level_drop(DMat<double> X, int64_t D, int64_t cols, const double* pre,
+                             const double* post, double thr) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D * cols) return;
+  const int64_t r = e % D, c = e / D;
+  if (!(post[c] > thr * pre[c])) {
+    DMat<double> x = X.item(blockIdx.y);
+    x.re[r + c * x.ld] = 0.0;
+  }
 }
 
 // rhs_j[r, c] = -((Ehat_j - sigma Mhat_E) Q[adj_j, :])[r, c]  (Phi of eq. (5.2), negated
@@ -394,6 +426,9 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   upload_v(kn_d, knum);
   Vb.alloc(sizeof(double) * D * VB * p);
   DMat<double> Y{Vb.as<double>(), nullptr, D, D * VB};
+  // columns kappa_j .. VB-1 of a subdomain are padding and must stay zero: the
+  // deflation GEMMs run over all VB columns
+  fill<double>(st, Y, D, VB, p, 0.0);
   inverse_iteration(st, tw, D, p, sel_d.as<double>(), kn_d.as<int>(), cl_d.as<int>(), VB, Y,
                     scratch);
   back_transform(st, C, tw, D, p, Y, kn_d.as<int>(), (int)VB);
@@ -425,6 +460,109 @@ void EngineImpl::factor_bsigma(hipStream_t st, double sig) {
   check_flags(st, "B_sigma factorization");
   bs_valid = true;
   bs_sigma = sig;
+}
+
+// Scales column c of U^{-1} by sqrt(u_cc) (the LDL^T diagonal), or zeroes it
+// when c is dropped or padding.
+__global__ void k_scale_uinv(double* Ui, int64_t ld, const double* U, int64_t ldu, const int* drop,
+                             int64_t ncol, int64_t np) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np * np) return;
+  const int64_t i = e % np, c = e / np;
+  const double f = (c < ncol && !drop[c]) ? sqrt(U[c + c * ldu]) : 0.0;
+  Ui[i + c * ld] *= f;
+}
+
+// M-orthonormal basis of the ncol columns of B (n x ncol, ld n): G = B^T M B
+// (unit diagonal for normalised columns), G = L D L^T by the blocked
+// semidefinite LU (pivots <= droptol drop their column), Q = B U^{-1} D^{1/2}
+// over the kept columns, written to Out (ld n).  MB is n x ncol scratch.
+// Returns the number of columns written.
+int EngineImpl::gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,
+                          double droptol) {
+  const int64_t np = round_up(ncol, NB);
+  csr_mm(st, Mrptr, Mridx, Mrval, n, B, n, MB, n, ncol);
+  gwork.alloc(sizeof(double) * (3 * np * np + (int64_t)NB * 2 * np) + sizeof(int) * (2 * np + 2));
+  double* G = gwork.as<double>();
+  double* Ui = G + np * np;
+  double* Tk = Ui + np * np;
+  double* Gi = Tk + np * np;
+  int* drop = reinterpret_cast<int*>(Gi + (int64_t)NB * 2 * np);
+  int* keep = drop + np;
+  DMat<double> Gm{G, nullptr, np, 0}, Uim{Ui, nullptr, np, 0}, Gim{Gi, nullptr, NB, 0};
+  DMat<double> Bm{const_cast<double*>(B), nullptr, n, 0}, MBm{MB, nullptr, n, 0};
+  fill<double>(st, Gm, np, np, 1, 0.0);
+  gemm<double>(st, true, false, ncol, ncol, n, 1.0, Bm, MBm, 0.0, Gm, 1);
+  pad_identity<double>(st, Gm, ncol, np, 1);
+  RFD_HIP(hipMemsetAsync(drop, 0, sizeof(int) * np, st));
+  lu_nopiv<double>(st, Gm, np, 1, Gim, flags.as<unsigned>(), 0.0, drop, droptol);
+  fill<double>(st, Uim, np, np, 1, 0.0);
+  pad_identity<double>(st, Uim, 0, np, 1);
+  lu_solve<double>(st, Gm, Gim, nullptr, np, Uim, np, 1, 2);
+  k_scale_uinv<<<grid1(np * np), 256, 0, st>>>(Ui, np, G, np, drop, ncol, np);
+  RFD_CHECK_LAUNCH();
+  std::vector<int> dh(ncol);
+  RFD_HIP(hipMemcpyAsync(dh.data(), drop, sizeof(int) * ncol, hipMemcpyDeviceToHost, st));
+  RFD_HIP(hipStreamSynchronize(st));
+  std::vector<int> kept;
+  for (int c = 0; c < ncol; ++c)
+    if (!dh[c]) kept.push_back(c);
+  const int r = (int)kept.size();
+  if (r == 0) return 0;
+  kept.push_back(r);  // device copy of the count follows the list
+  RFD_HIP(hipMemcpyAsync(keep, kept.data(), sizeof(int) * (r + 1), hipMemcpyHostToDevice, st));
+  k_gather_cols<<<dim3(grid1(np), r), 256, 0, st>>>(Ui, np, Tk, np, np, keep, keep + r);
+  RFD_CHECK_LAUNCH();
+  DMat<double> Tm{Tk, nullptr, np, 0}, Om{Out, nullptr, n, 0};
+  gemm<double>(st, false, false, n, r, ncol, 1.0, Bm, Tm, 0.0, Om, 1);
+  RFD_HIP(hipStreamSynchronize(st));
+  return r;
+}
+
+// X (n x ncols, reordered numbering) -= V (V^T M X) per subdomain and
+// -= Zp (Zp^T M X) for the kprev previous level columns, `passes` times.
+// MX is n x ncols scratch.
+void EngineImpl::project_out(hipStream_t st, double* X, int ncols, double* MX, const double* Zp,
+                             int64_t kprev, int passes) {
+  if (ncols <= 0) return;
+  DMat<double> Xm{X, nullptr, n, 0}, MXm{MX, nullptr, n, 0};
+  for (int pass = 0; pass < passes; ++pass) {
+    if (kappa_tot > 0) {
+      csr_mm(st, Mrptr, Mridx, Mrval, n, X, n, MX, n, ncols);
+      work4.alloc(sizeof(double) * std::max<int64_t>(VB, 1) * std::max<int64_t>(MUP, ncols) * p);
+      const int64_t ldt = std::max<int64_t>(VB, 1);
+      bool uniform = true;
+      for (int j = 1; j < p; ++j)
+        if (P->interior[j].size() != P->interior[0].size()) uniform = false;
+      if (uniform) {
+        const int64_t d = (int64_t)P->interior[0].size();
+        DMat<double> Vm{Vb.as<double>(), nullptr, D, D * VB};
+        DMat<double> Xb{X, nullptr, n, d}, MXb{MX, nullptr, n, d};
+        DMat<double> Tm{work4.as<double>(), nullptr, ldt, ldt * ncols};
+        gemm<double>(st, true, false, VB, ncols, d, 1.0, Vm, MXb, 0.0, Tm, p);
+        gemm<double>(st, false, false, d, ncols, VB, -1.0, Vm, Tm, 1.0, Xb, p);
+      } else {
+        int64_t off = 0;
+        for (int j = 0; j < p; ++j) {
+          const int64_t d = (int64_t)P->interior[j].size();
+          DMat<double> Vm{Vb.as<double>() + (int64_t)j * D * VB, nullptr, D, 0};
+          DMat<double> Xb{X + off, nullptr, n, 0}, MXb{MX + off, nullptr, n, 0};
+          DMat<double> Tm{work4.as<double>(), nullptr, ldt, 0};
+          gemm<double>(st, true, false, VB, ncols, d, 1.0, Vm, MXb, 0.0, Tm, 1);
+          gemm<double>(st, false, false, d, ncols, VB, -1.0, Vm, Tm, 1.0, Xb, 1);
+          off += d;
+        }
+      }
+    }
+    if (kprev > 0) {
+      csr_mm(st, Mrptr, Mridx, Mrval, n, X, n, MX, n, ncols);
+      work6b.alloc(sizeof(double) * kprev * ncols);
+      DMat<double> Zm{const_cast<double*>(Zp), nullptr, n, 0};
+      DMat<double> Tq{work6b.as<double>(), nullptr, kprev, 0};
+      gemm<double>(st, true, false, kprev, ncols, n, 1.0, Zm, MXm, 0.0, Tq, 1);
+      gemm<double>(st, false, false, n, ncols, kprev, -1.0, Zm, Tq, 1.0, Xm, 1);
+    }
+  }
 }
 
 void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64_t* kout) {
@@ -466,16 +604,32 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
       Rh, D, MUP, e.dj.as<int32_t>(), e.Eg.view(), sig, e.Qint.as<double>(), s, mu,
       e.adj.as<int32_t>(), e.SJ);
   RFD_CHECK_LAUNCH();
+  DevBuf nrm;
+  nrm.alloc(sizeof(double) * 2 * MUP);
+  double* pre = nrm.as<double>();
+  double* post = pre + MUP;
   for (int t = 0; t < psi; ++t) {
     DMat<double> X = Lv.sub(0, t * MUP);
     convert<double, double>(st, Rh, X, D, MUP, p);
     lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p);
-    // make the level M_B-orthogonal to V_j
+    // make the level M_B-orthogonal to V_j (twice)
     if (e.kappa_tot > 0) {
-      k_scaled_copy<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
-      RFD_CHECK_LAUNCH();
-      gemm<double>(st, true, false, e.VB, MUP, D, 1.0, Vm, Rh, 0.0, Tm, p);
-      gemm<double>(st, false, false, D, MUP, e.VB, -1.0, Vm, Tm, 1.0, X, p);
+      if (t > 0) {
+        k_level_colnorm<<<MUP, 256, 0, st>>>(X, p, e.dj.as<int32_t>(), md, D, pre);
+        RFD_CHECK_LAUNCH();
+      }
+      for (int pass = 0; pass < 2; ++pass) {
+        k_scaled_copy<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
+        RFD_CHECK_LAUNCH();
+        gemm<double>(st, true, false, e.VB, MUP, D, 1.0, Vm, Rh, 0.0, Tm, p);
+        gemm<double>(st, false, false, D, MUP, e.VB, -1.0, Vm, Tm, 1.0, X, p);
+      }
+      if (t > 0) {
+        k_level_colnorm<<<MUP, 256, 0, st>>>(X, p, e.dj.as<int32_t>(), md, D, post);
+        RFD_CHECK_LAUNCH();
+        k_level_drop<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, D, MUP, pre, post, 1e-10);
+        RFD_CHECK_LAUNCH();
+      }
     }
     if (t + 1 < psi) {
       k_scaled_copy<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
@@ -503,20 +657,12 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
                                                           kap_d2.as<int32_t>(), e.dj.as<int32_t>(), D);
     RFD_CHECK_LAUNCH();
   }
-  // reordered diagonal of M
   e.work5.alloc(sizeof(double) * n * (int64_t)mu * 2);
   double* Lb = e.work5.as<double>();             // current level block (n x mu)
   double* MLb = Lb + n * (int64_t)mu;            // M * block
-  e.work6.alloc(sizeof(double) * ((int64_t)mu * mu * 3 + std::max<int64_t>(kmax, 1) * mu + 4 * mu + 8));
-  double* G = e.work6.as<double>();
-  double* Linv = G + (int64_t)mu * mu;
-  double* Tp = Linv + (int64_t)mu * mu;          // projections (kmax x mu)
-  double* n0 = Tp + std::max<int64_t>(kmax, 1) * mu;
+  e.work6.alloc(sizeof(double) * (2 * mu + 8));
+  double* n0 = e.work6.as<double>();             // column M-norms before / after projection
   double* n1 = n0 + mu;
-  int* piv = reinterpret_cast<int*>(n1 + mu);
-  int* rank_d = piv + mu;
-  DMat<double> dummy{nullptr, nullptr, 0, 0};
-  (void)dummy;
   int64_t kz = e.kappa_tot;
   for (int t = 0; t < psi && mu > 0; ++t) {
     k_build_level<<<grid1(n * mu), 256, 0, st>>>(Lb, n, Lv, t, MUP, e.ioff.as<int32_t>(), p, n_int,
@@ -526,62 +672,41 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
     csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
     k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n0);
     RFD_CHECK_LAUNCH();
-    // project against the previous level blocks (M-inner product), twice
+    // project against V and the previous level blocks (M-inner product), twice
     const int64_t kprev = kz - e.kappa_tot;
-    if (kprev > 0) {
-      DMat<double> Zp{Z + e.kappa_tot * n, nullptr, n, 0};
-      DMat<double> Tq{Tp, nullptr, kprev, 0};
-      DMat<double> Lm{Lb, nullptr, n, 0};
-      DMat<double> MLm{MLb, nullptr, n, 0};
-      for (int pass = 0; pass < 2; ++pass) {
-        csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
-        gemm<double>(st, true, false, kprev, mu, n, 1.0, Zp, MLm, 0.0, Tq, 1);
-        gemm<double>(st, false, false, n, mu, kprev, -1.0, Zp, Tq, 1.0, Lm, 1);
-      }
-    }
+    e.project_out(st, Lb, mu, MLb, Z + e.kappa_tot * n, kprev, 2);
     csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
     k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n1);
     RFD_CHECK_LAUNCH();
     k_col_normalize<<<dim3(grid1(n), mu), 256, 0, st>>>(Lb, n, n, n1, n0, 1e-10);
     RFD_CHECK_LAUNCH();
-    // Gram matrix and pivoted Cholesky, then two CholQR passes
-    for (int pass = 0; pass < 2; ++pass) {
-      const int64_t cols = (pass == 0) ? mu : -1;
-      int r = 0;
-      if (pass == 0) {
-        csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, cols);
-        DMat<double> Lm{Lb, nullptr, n, 0}, MLm{MLb, nullptr, n, 0}, Gm{G, nullptr, mu, 0};
-        gemm<double>(st, true, false, mu, mu, n, 1.0, Lm, MLm, 0.0, Gm, 1);
-        pivoted_cholesky(st, G, mu, mu, 1e-14, piv, rank_d, Linv, mu);
-        r = download<int>(st, rank_d, 1)[0];
-        if (r == 0) break;
-        // Q_t = L_t[:, piv[:r]] L^{-T}  -> into Z columns kz..kz+r
-        k_gather_cols<<<dim3(grid1(n), r), 256, 0, st>>>(Lb, n, MLb, n, n, piv, rank_d);
-        RFD_CHECK_LAUNCH();
-        DMat<double> Sel{MLb, nullptr, n, 0}, Li{Linv, nullptr, mu, 0}, Zo{Z + kz * n, nullptr, n, 0};
-        gemm<double>(st, false, true, n, r, r, 1.0, Sel, Li, 0.0, Zo, 1);
-        // second pass on the r new columns
-        csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Z + kz * n, n, MLb, n, r);
-        DMat<double> Zc{Z + kz * n, nullptr, n, 0}, MZc{MLb, nullptr, n, 0}, G2{G, nullptr, r, 0};
-        gemm<double>(st, true, false, r, r, n, 1.0, Zc, MZc, 0.0, G2, 1);
-        pivoted_cholesky(st, G, r, r, 1e-20, piv, rank_d, Linv, r);
-        const int r2 = download<int>(st, rank_d, 1)[0];
-        k_gather_cols<<<dim3(grid1(n), r2), 256, 0, st>>>(Z + kz * n, n, Lb, n, n, piv, rank_d);
-        RFD_CHECK_LAUNCH();
-        DMat<double> Sel2{Lb, nullptr, n, 0}, Li2{Linv, nullptr, r, 0};
-        gemm<double>(st, false, true, n, r2, r2, 1.0, Sel2, Li2, 0.0, Zc, 1);
-        if (r2 < r)
-          RFD_HIP(hipMemsetAsync(Z + (kz + r2) * n, 0, sizeof(double) * n * (r - r2), st));
-        kz += r2;
-        break;
-      }
-    }
+    // Cholesky QR through the semidefinite LDL^T: the first pass drops the
+    // columns that depend on earlier ones; a kept column with a small pivot
+    // amplifies rounding, so the result is projected once more before the
+    // second pass restores orthonormality
+    const int r = e.gram_orth(st, Lb, mu, MLb, Z + kz * n, 1e-13);
+    if (r == 0) continue;
+    e.project_out(st, Z + kz * n, r, MLb, Z + e.kappa_tot * n, kprev, 1);
+    const int r2 = e.gram_orth(st, Z + kz * n, r, MLb, Lb, 1e-20);
+    RFD_HIP(hipMemcpyAsync(Z + kz * n, Lb, sizeof(double) * n * r2, hipMemcpyDeviceToDevice, st));
+    if (r2 < r)
+      RFD_HIP(hipMemsetAsync(Z + (kz + r2) * n, 0, sizeof(double) * n * (r - r2), st));
+    kz += r2;
   }
   e.kz = kz;
   e.timer.end(st);
   RFD_HIP(hipStreamSynchronize(st));
   e.interior_ready = true;
   *kout = kz;
+}
+
+void Engine::copy_basis(hipStream_t st, double* dst, int64_t cap, int64_t* k) {
+  EngineImpl& e = *d_;
+  *k = e.interior_ready ? e.kz : 0;
+  const int64_t c = std::min(cap, *k);
+  if (c > 0)
+    RFD_HIP(hipMemcpyAsync(dst, e.Zt.p, sizeof(double) * e.n * c, hipMemcpyDeviceToDevice, st));
+  RFD_HIP(hipStreamSynchronize(st));
 }
 
 void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* evecs,

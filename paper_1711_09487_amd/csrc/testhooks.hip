@@ -76,3 +76,7 @@ extern "C" int rfd_test_lu(int dtype, int pivot, int64_t n, int batch, void* a_r
     RFD_HIP(hipFree(ipiv));
   });
 }
+
+// Copies the current M-orthonormal basis of range(Z) (reordered numbering,
+// n x k, ld n) to dst (device, room for n * cap doubles); returns k in *k_out.
+

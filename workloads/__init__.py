@@ -25,8 +25,9 @@ Recipe (all FP64, natural lexicographic node order, x fastest):
   0 = M diagonal, 1 = starting block Y0, 2 = coefficient field k,
   3 = shapes and intervals (batched / serving mixes), 4 = arrivals.
 * Intervals "enclosing the lowest nev eigenvalues": alpha = 0 (all pencils
-  here are SPD) and beta = (lam_nev + lam_{nev+1}) / 2, so that no
-  eigenvalue sits on the contour.  lam comes from the closed form when
+  here are SPD) and beta = (lam_nev + lam_{nev+1}) / 2 rounded to 10
+  significant digits, so that no eigenvalue sits on the contour and the
+  input is the same on every machine.  lam comes from the closed form when
   M = I with the constant stencil, else from a reference eigensolver
   (dense for small n, ARPACK shift-invert otherwise).
 """
@@ -163,7 +164,10 @@ def interval_lowest(A, M, nev: int, closed_shape=None):
     lam = lowest_eigs(A, M, nev + 1, closed_shape)
     if not lam[nev] - lam[nev - 1] > 1e-10 * abs(lam[nev]):
         raise ValueError("the interval would cut a multiple eigenvalue")
-    return 0.0, 0.5 * (lam[nev - 1] + lam[nev]), lam
+    # rounded to 10 significant digits so that the input does not depend on the
+    # last bits of the reference eigensolver on a given machine
+    beta = float(f"{0.5 * (lam[nev - 1] + lam[nev]):.10g}")
+    return 0.0, beta, lam
 
 
 def random_block(s: int, m: int, gen: np.random.Generator) -> np.ndarray:
