@@ -1,0 +1,57 @@
+/* Kernel-level test entry points of the RF-DDES gfx950 library.
+ *
+ * These expose single building blocks of the filter path so that a test
+ * can check each one element by element against a host computation.  They
+ * are not part of the solver interface (rfd.h) and allocate and free device
+ * workspace on every call.  All pointers named a_*, b_*, c_*, r_*, A, lam, Y,
+ * dst are device pointers; matrices are column-major strided batches (leading
+ * dimension ld*, item stride s*), complex data planar (re, im; im may be NULL
+ * for real data).  Every function returns 0 (RFD_OK) or an rfd_status code,
+ * with the message in rfd_last_error(); stream may be NULL (default stream). */
+#ifndef RFD_TESTING_H
+#define RFD_TESTING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C_b = alpha op(A_b) op(B_b) + beta C_b for b < batch (op = transpose when
+ * ta / tb).  dtype 0 = FP32, 1 = FP64.  Complex when c_im != NULL.  This is
+ * the matrix-core GEMM every dense step of the filter and of the basis
+ * construction runs on (Schur products, eq. (3.3)-(3.5)). */
+int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha,
+                  double beta, void* a_re, void* a_im, int64_t lda, int64_t sa, void* b_re,
+                  void* b_im, int64_t ldb, int64_t sb, void* c_re, void* c_im, int64_t ldc,
+                  int64_t sc, int batch, void* stream);
+
+/* Factors each n x n item of A in place (pivot = 0: LU without pivoting, as
+ * for the shifted blocks B_j - zeta M_Bj and S(zeta) of Section 3; pivot = 1:
+ * partial pivoting, real only, as for B_j - sigma M_Bj of Section 4) and
+ * solves A X = R in place for the n x r items of R (r may be 0).  n must be a
+ * multiple of 64.  *flags_out receives the breakdown bits (1: tiny pivot,
+ * 2: non-finite value). */
+int rfd_test_lu(int dtype, int pivot, int64_t n, int batch, void* a_re, void* a_im, int64_t lda,
+                int64_t sa, void* r_re, void* r_im, int64_t ldr, int64_t sr, int64_t r,
+                unsigned* flags_out, void* stream);
+
+/* Eigenpairs with ascending indices lo .. lo + num - 1 (0-based) of each
+ * symmetric n x n item of A (FP64, ld n, item stride n * n; destroyed), the
+ * dense eigensolver of the Rayleigh-Ritz step (Section 5) and of the
+ * subdomain eigenvectors of Section 4.3: lam receives num values per item,
+ * Y the n x num eigenvectors per item (ld n, item stride n * num). */
+int rfd_test_syevx(int64_t n, int batch, double* A, int lo, int num, double* lam, double* Y,
+                   void* stream);
+
+/* Copies the M-orthonormal basis of the projection subspace (eq. (5.5)) built
+ * by the last rfd_solve_interior call, in the library's internal interior-
+ * first numbering (n x k, ld n), to dst (room for n * cap doubles);
+ * *k_out = k. */
+int rfd_test_basis(void* pencil, double* dst, int64_t cap, int64_t* k_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFD_TESTING_H */

@@ -73,6 +73,7 @@ def lib():
                               I64, P, P, I64, I64, I32, P],
             "rfd_test_lu": [I32, I32, I64, I32, P, P, I64, I64, P, P, I64, I64, I64,
                             C.POINTER(C.c_uint32), P],
+            "rfd_test_syevx": [I64, I32, P, I32, I32, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)

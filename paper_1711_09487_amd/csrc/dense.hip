@@ -1,5 +1,5 @@
-// Dense batched kernels for gfx950: MFMA GEMM (FP32 / FP64, real / planar
-// complex), LU factorization (blocked, right-looking; the diagonal block is
+// Dense batched kernels for gfx950 (the GEMM itself is in gemm.hip): LU
+// factorization (blocked, right-looking; the diagonal block is
 // factored and inverted in LDS), pivoted panel factorization, triangular
 // solves through inverted diagonal blocks, elementwise helpers.
 #include <algorithm>
@@ -9,173 +9,6 @@
 #include "dense.hpp"
 
 namespace rfd {
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
-// ---------------------------------------------------------------------------
-// GEMM.  Workgroup tile 64 x 64, 4 waves of 32 x 32.  FP32 uses
-// v_mfma_f32_32x32x2f32 (one 32 x 32 block per wave), FP64 uses
-// v_mfma_f64_16x16x4f64 (2 x 2 blocks per wave).  A complex product is four
-// real products into two accumulators (Re += ar br - ai bi, Im += ar bi + ai br).
-// Operand lane layouts: 32x32x2 -- lane l holds A[l%32][l/32], B[l/32][l%32];
-// D register r of lane l is element (8 (r/4) + 4 (l/32) + r%4, l%32).
-// 16x16x4 -- lane l holds A[l%16][l/16], B[l/16][l%16]; D register r is
-// element ((l/16) + 4 r, l%16) (checked on gfx950).
-// ---------------------------------------------------------------------------
-constexpr int GBM = 64, GBN = 64, GKT = 16;
-
-template <typename T, bool CPLX, bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T alpha, T beta,
-                                              DMat<T> A, DMat<T> B, DMat<T> C) {
-  constexpr int NP = CPLX ? 2 : 1;
-  __shared__ T As[NP][GKT][GBM + 4];
-  __shared__ T Bs[NP][GKT][GBN + 4];
-  const int64_t m0 = (int64_t)blockIdx.x * GBM, n0 = (int64_t)blockIdx.y * GBN;
-  if (m0 >= M || n0 >= N) return;
-  A = A.item(blockIdx.z);
-  B = B.item(blockIdx.z);
-  C = C.item(blockIdx.z);
-  const bool aim = CPLX && A.im != nullptr;
-  const bool bim = CPLX && B.im != nullptr;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-
-  floatx16 fr = {0}, fi = {0};
-  doublex4 dr[2][2], di[2][2];
-  if constexpr (std::is_same<T, double>::value) {
-    for (int x = 0; x < 2; ++x)
-      for (int y = 0; y < 2; ++y) {
-        dr[x][y] = doublex4{0, 0, 0, 0};
-        di[x][y] = doublex4{0, 0, 0, 0};
-      }
-  }
-
-  for (int64_t k0 = 0; k0 < K; k0 += GKT) {
-    for (int e = tid; e < GBM * GKT; e += 256) {
-      int i, k;
-      if (!TA) { i = e % GBM; k = e / GBM; } else { k = e % GKT; i = e / GKT; }
-      const int64_t gi = m0 + i, gk = k0 + k;
-      T vr = 0, vi = 0;
-      if (gi < M && gk < K) {
-        const int64_t off = TA ? (gk + gi * A.ld) : (gi + gk * A.ld);
-        vr = A.re[off];
-        if (aim) vi = A.im[off];
-      }
-      As[0][k][i] = vr;
-      if constexpr (CPLX) As[NP - 1][k][i] = vi;
-    }
-    for (int e = tid; e < GBN * GKT; e += 256) {
-      int j, k;
-      if (!TB) { k = e % GKT; j = e / GKT; } else { j = e % GBN; k = e / GBN; }
-      const int64_t gj = n0 + j, gk = k0 + k;
-      T vr = 0, vi = 0;
-      if (gj < N && gk < K) {
-        const int64_t off = TB ? (gj + gk * B.ld) : (gk + gj * B.ld);
-        vr = B.re[off];
-        if (bim) vi = B.im[off];
-      }
-      Bs[0][k][j] = vr;
-      if constexpr (CPLX) Bs[NP - 1][k][j] = vi;
-    }
-    __syncthreads();
-    if constexpr (std::is_same<T, float>::value) {
-#pragma unroll
-      for (int kk = 0; kk < GKT; kk += 2) {
-        const int kr = kk + (lane >> 5), r = lane & 31;
-        const float ar = As[0][kr][wm + r], br = Bs[0][kr][wn + r];
-        fr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, fr, 0, 0, 0);
-        if constexpr (CPLX) {
-          const float ai = As[NP - 1][kr][wm + r], bi = Bs[NP - 1][kr][wn + r];
-          fr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, fr, 0, 0, 0);
-          fi = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, fi, 0, 0, 0);
-          fi = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, fi, 0, 0, 0);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < GKT; kk += 4) {
-        const int kr = kk + (lane >> 4), r = lane & 15;
-        double ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          ar[x] = As[0][kr][wm + 16 * x + r];
-          br[x] = Bs[0][kr][wn + 16 * x + r];
-          if constexpr (CPLX) {
-            ai[x] = As[NP - 1][kr][wm + 16 * x + r];
-            bi[x] = Bs[NP - 1][kr][wn + 16 * x + r];
-          }
-        }
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y) {
-            dr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], br[y], dr[x][y], 0, 0, 0);
-            if constexpr (CPLX) {
-              dr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[x], bi[y], dr[x][y], 0, 0, 0);
-              di[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[x], bi[y], di[x][y], 0, 0, 0);
-              di[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[x], br[y], di[x][y], 0, 0, 0);
-            }
-          }
-      }
-    }
-    __syncthreads();
-  }
-
-  auto store = [&](int64_t row, int64_t col, T vr, T vi) {
-    if (row >= M || col >= N) return;
-    const int64_t off = row + col * C.ld;
-    T outr = alpha * vr, outi = alpha * vi;
-    if (beta != T(0)) {
-      outr += beta * C.re[off];
-      if constexpr (CPLX) outi += beta * C.im[off];
-    }
-    C.re[off] = outr;
-    if constexpr (CPLX) C.im[off] = outi;
-  };
-  if constexpr (std::is_same<T, float>::value) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t row = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      const int64_t col = n0 + wn + (lane & 31);
-      store(row, col, fr[r], CPLX ? fi[r] : 0.0f);
-    }
-  } else {
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = m0 + wm + 16 * x + (lane >> 4) + 4 * r;
-          const int64_t col = n0 + wn + 16 * y + (lane & 15);
-          store(row, col, dr[x][y][r], CPLX ? di[x][y][r] : 0.0);
-        }
-  }
-}
-
-template <typename T, bool CPLX>
-static void gemm_dispatch(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N,
-                          int64_t K, T alpha, T beta, DMat<T> A, DMat<T> B, DMat<T> C) {
-  if (!ta && !tb) k_gemm<T, CPLX, false, false><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C);
-  else if (ta && !tb) k_gemm<T, CPLX, true, false><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C);
-  else if (!ta && tb) k_gemm<T, CPLX, false, true><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C);
-  else k_gemm<T, CPLX, true, true><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C);
-}
-
-template <typename T>
-void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, DMat<T> A,
-          DMat<T> B, T beta, DMat<T> C, int batch) {
-  if (M <= 0 || N <= 0 || batch <= 0) return;
-  if (batch > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
-  dim3 g((unsigned)((M + GBM - 1) / GBM), (unsigned)((N + GBN - 1) / GBN), (unsigned)batch);
-  const int key = (sizeof(T) == 8 ? 8 : 0) + (C.cplx() ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
-  const double flops = (C.cplx() ? 8.0 : 2.0) * (double)M * (double)N * (double)K * batch;
-  KernelAccount::Scope acct(s, key, flops);
-  if (C.cplx()) gemm_dispatch<T, true>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C);
-  else gemm_dispatch<T, false>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C);
-  RFD_CHECK_LAUNCH();
-}
 
 // ---------------------------------------------------------------------------
 // Per-launch accounting of the GEMM instantiations (key = 8 * fp64 + 4 * complex
@@ -689,8 +522,6 @@ void absmax(hipStream_t s, DMat<T> X, int64_t rows, int64_t cols, int batch, dou
 
 // explicit instantiations
 #define RFD_INST(T)                                                                          \
-  template void gemm<T>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, T, DMat<T>,      \
-                        DMat<T>, T, DMat<T>, int);                                           \
   template void lu_nopiv<T>(hipStream_t, DMat<T>, int64_t, int, DMat<T>, unsigned*, double,     \
                             int*, double);                                                   \
   template void lu_piv<T>(hipStream_t, DMat<T>, int64_t, int, DMat<T>, int32_t*, unsigned*,  \

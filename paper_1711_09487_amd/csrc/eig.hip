@@ -1,16 +1,10 @@
-// Dense FP64 symmetric eigensolver for selected eigenpairs (see eig.hpp).
-//
-// Tridiagonalization: one Householder reflector per step, two launches per
-// step.  k_tri_a forms p = tau A v over the trailing block, one wavefront per
-// column (A is kept fully symmetric, so column i of A is row i); k_tri_b
-// applies the rank-2 update A -= v w^T + w v^T with w = p - (tau/2)(p^T v) v,
-// each workgroup owning a block of columns and recomputing p^T v itself.  The
-// reflector of step j stays unscaled in column j until step j+1 has read it
-// and is scaled into v (implicit leading 1) by the first workgroup of step
-// j+1 (or by the closing kernel).
+// Dense FP64 symmetric eigensolver for selected eigenpairs (see eig.hpp):
+// blocked Householder tridiagonalization, Sturm-count bisection, inverse
+// iteration, back-transformation.
 #include <algorithm>
 #include <cmath>
 
+#include "dense.hpp"
 #include "eig.hpp"
 
 namespace rfd {
@@ -42,27 +36,108 @@ void TriWork::reserve(int64_t n, int batch) {
   d.alloc(sizeof(double) * need);
   e.alloc(sizeof(double) * need);
   tau.alloc(sizeof(double) * need);
-  scl.alloc(sizeof(double) * need);
   pvec.alloc(sizeof(double) * need);
+  acol.alloc(sizeof(double) * need);
+  vw.alloc(sizeof(double) * need * 2 * TRI_NB);
+  red.alloc(sizeof(double) * (2 * TRI_NB + 2) * batch);
+  sq.alloc(sizeof(double) * ((n + 255) / 256) * batch);
 }
 
-// p[i] = tau * sum_c A[c, i] v[c], i, c in [j+1, n); v[j+1] = 1, v[c] = A[c, j] * scale.
-__global__ __launch_bounds__(256) void k_tri_a(DMat<double> A, int64_t n, int64_t j, double* dv,
-                                               double* ev, double* tauv, double* sclv, double* pv) {
-  __shared__ double red[8];
-  __shared__ double hh[4];
-  const int b = blockIdx.y;
+// Blocked reduction (panels of TRI_NB columns).  Within a panel the trailing
+// matrix is A - V W^T - W V^T with A as it was at the panel's start; V holds
+// the reflectors (unit entry explicit, zero above it) and W the matching
+// update vectors.  For column j (panel position c):
+//   k_tri_col   finishes W[:, c-1], forms the updated column j into acol and
+//               the partial sums of squares below its subdiagonal;
+//   k_tri_symv  makes the reflector from acol (every workgroup), writes it
+//               to V[:, c] and column j of A, and forms p = A v over the
+//               trailing block of the panel-start matrix;
+//   k_tri_dots  forms p^T v, W^T v and V^T v.
+// After the panel, the trailing block takes A -= V W^T + W V^T as two GEMMs.
+// w_c = tau (p - V (W^T v) - W (V^T v)) - (tau/2) (that^T v) v, i.e. the
+// two-sided application of I - tau v v^T to the current trailing matrix.
+
+// One thread per row r >= j.  c = panel position of column j; upd = 0 only
+// finishes W[:, c-1] (end of panel).
+__global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int64_t j, int c,
+                                                 int upd, double* vw, const double* tauv,
+                                                 const double* pv, const double* red, double* acol,
+                                                 double* dv, double* sq) {
+  __shared__ double Vj[TRI_NB], Wj[TRI_NB], xs[TRI_NB], ys[TRI_NB], rs[8];
+  const int b = blockIdx.y, t = threadIdx.x;
   DMat<double> a = A.item(b);
-  const int t = threadIdx.x;
-  // Householder data of column j (every workgroup computes it)
-  double s2 = 0;
-  for (int64_t i = j + 2 + t; i < n; i += blockDim.x) {
-    const double x = a.re[i + j * a.ld];
-    s2 += x * x;
+  double* V = vw + (int64_t)b * n * 2 * TRI_NB;
+  double* W = V + n * TRI_NB;
+  const double* rd = red + (int64_t)b * (2 * TRI_NB + 2);
+  const double* p = pv + (int64_t)b * n;
+  const int64_t r = j + (int64_t)blockIdx.x * 256 + t;
+  const bool act = r < n;
+  if (c == 0) {
+    if (act)
+      for (int q = 0; q < TRI_NB; ++q) {
+        V[r + q * n] = 0.0;
+        W[r + q * n] = 0.0;
+      }
   }
-  s2 = block_sum256(s2, red);
+  if (t < c) {
+    Vj[t] = V[j + (int64_t)t * n];
+    if (t < c - 1) {
+      Wj[t] = W[j + (int64_t)t * n];
+      xs[t] = rd[2 + t];
+      ys[t] = rd[2 + TRI_NB + t];
+    }
+  }
+  __syncthreads();
+  double wr = 0.0;
+  if (c >= 1) {
+    const double tp = tauv[(int64_t)b * n + j - 1];
+    double xy = 0;
+    for (int q = 0; q < c - 1; ++q) xy += xs[q] * ys[q];
+    const double al = -0.5 * tp * tp * (rd[0] - 2.0 * xy);
+    if (t == 0) {
+      double acc = p[j];
+      for (int q = 0; q < c - 1; ++q) acc -= Vj[q] * xs[q] + Wj[q] * ys[q];
+      Wj[c - 1] = tp * acc + al * Vj[c - 1];
+    }
+    if (act) {
+      double acc = p[r];
+      for (int q = 0; q < c - 1; ++q) acc -= V[r + q * n] * xs[q] + W[r + q * n] * ys[q];
+      wr = tp * acc + al * V[r + (int64_t)(c - 1) * n];
+      W[r + (int64_t)(c - 1) * n] = wr;
+    }
+    __syncthreads();
+  }
+  if (!upd) return;
+  double ar = 0.0;
+  if (act) {
+    ar = a.re[r + j * a.ld];
+    for (int q = 0; q < c; ++q) {
+      const double wq = (q == c - 1) ? wr : W[r + q * n];
+      ar -= V[r + q * n] * Wj[q] + wq * Vj[q];
+    }
+    acol[(int64_t)b * n + r] = ar;
+    if (r == j) dv[(int64_t)b * n + j] = ar;
+  }
+  const double s2 = block_sum256((act && r >= j + 2) ? ar * ar : 0.0, rs);
+  if (t == 0) sq[(int64_t)b * ((n + 255) / 256) + blockIdx.x] = s2;
+}
+
+// Reflector of column j and p[q] = sum_r A[r, q] v[r] for q, r in [j+1, n);
+// each wave owns two columns q.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int64_t j, int c,
+                                                  double* vw, double* dv, double* ev, double* tauv,
+                                                  double* pv, const double* acol, const double* sq) {
+  __shared__ double hh[4];
+  const int b = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  DMat<double> a = A.item(b);
+  const double* ac = acol + (int64_t)b * n;
   if (t == 0) {
-    const double alpha = a.re[(j + 1) + j * a.ld];
+    const int nsq = (int)((n - j + 255) / 256);
+    const double* s = sq + (int64_t)b * ((n + 255) / 256);
+    double s2 = 0;
+    for (int i = 0; i < nsq; ++i) s2 += s[i];
+    const double alpha = ac[j + 1];
     double tau = 0, beta = alpha, scale = 0;
     if (s2 > 0) {
       const double nrm = sqrt(alpha * alpha + s2);
@@ -76,71 +151,85 @@ __global__ __launch_bounds__(256) void k_tri_a(DMat<double> A, int64_t n, int64_
   }
   __syncthreads();
   const double tau = hh[0], scale = hh[2];
+  const int64_t j1 = j + 1;
+  auto vval = [&](int64_t r) -> double {
+    return r < j1 ? 0.0 : (r == j1 ? 1.0 : ac[r] * scale);
+  };
   if (blockIdx.x == 0 && t == 0) {
-    dv[b * n + j] = a.re[j + j * a.ld];
-    ev[b * n + j] = hh[1];
-    tauv[b * n + j] = tau;
-    sclv[b * n + j] = scale;
+    ev[(int64_t)b * n + j] = hh[1];
+    tauv[(int64_t)b * n + j] = tau;
   }
-  // the previous step's reflector: scale its column into v (nobody reads it now)
-  if (blockIdx.x == 0 && j >= 1) {
-    const double sp = sclv[b * n + j - 1];
-    for (int64_t i = j + 1 + t; i < n; i += blockDim.x) a.re[i + (j - 1) * a.ld] *= sp;
+  // this workgroup's share of v: V[:, c] and column j of A (rows >= j + 2)
+  const int64_t q0 = j1 + (int64_t)blockIdx.x * 8;
+  double* V = vw + (int64_t)b * n * 2 * TRI_NB;
+  if (t < 8 && q0 + t < n) {
+    const int64_t r = q0 + t;
+    const double v = vval(r);
+    V[r + (int64_t)c * n] = v;
+    if (r >= j + 2) a.re[r + j * a.ld] = v;
   }
-  // one wavefront per column i
-  const int lane = t & 63, wv = t >> 6;
-  const int64_t i = j + 1 + (int64_t)blockIdx.x * 4 + wv;
-  if (i >= n) return;
-  double acc = 0;
-  const double* col = a.re + i * a.ld;
-  const double* vj = a.re + j * a.ld;
-  for (int64_t c = j + 1 + lane; c < n; c += 64) {
-    const double v = (c == j + 1) ? 1.0 : vj[c] * scale;
-    acc += col[c] * v;
-  }
-  acc = wave_sum(acc);
-  if (lane == 0) pv[b * n + i] = tau * acc;
-}
-
-// A[r, c] -= v[r] w[c] + w[r] v[c] for r, c in [j+1, n); columns in blocks of 8.
-__global__ __launch_bounds__(256) void k_tri_b(DMat<double> A, int64_t n, int64_t j,
-                                               const double* tauv, const double* sclv,
-                                               const double* pv) {
-  __shared__ double red[8];
-  const int b = blockIdx.y;
-  DMat<double> a = A.item(b);
-  const int t = threadIdx.x;
-  const double tau = tauv[b * n + j], scale = sclv[b * n + j];
-  if (tau == 0.0) return;
-  const double* vj = a.re + j * a.ld;
-  const double* p = pv + b * n;
-  double dot = 0;
-  for (int64_t c = j + 1 + t; c < n; c += blockDim.x) dot += p[c] * ((c == j + 1) ? 1.0 : vj[c] * scale);
-  dot = block_sum256(dot, red);
-  const double h = 0.5 * tau * dot;
-  const int64_t c0 = j + 1 + (int64_t)blockIdx.x * 8;
-  for (int64_t c = c0; c < c0 + 8 && c < n; ++c) {
-    const double vc = (c == j + 1) ? 1.0 : vj[c] * scale;
-    const double wc = p[c] - h * vc;
-    double* col = a.re + c * a.ld;
-    for (int64_t r = j + 1 + t; r < n; r += blockDim.x) {
-      const double vr = (r == j + 1) ? 1.0 : vj[r] * scale;
-      const double wr = p[r] - h * vr;
-      col[r] -= vr * wc + wr * vc;
+  double acc[2] = {0.0, 0.0};
+  int64_t qs[2];
+  for (int k = 0; k < 2; ++k) qs[k] = q0 + wave * 2 + k;
+  if (VEC) {
+    const int64_t r0 = j1 & ~(int64_t)1;
+    for (int64_t r = r0 + 2 * lane; r < n; r += 128) {
+      const double v0 = vval(r);
+      const double v1 = (r + 1 < n) ? vval(r + 1) : 0.0;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (qs[k] >= n) continue;
+        const double* col = a.re + qs[k] * a.ld;
+        if (r + 1 < n) {
+          const double2 x = *reinterpret_cast<const double2*>(col + r);
+          acc[k] += x.x * v0 + x.y * v1;
+        } else {
+          acc[k] += col[r] * v0;
+        }
+      }
+    }
+  } else {
+    for (int64_t r = j1 + lane; r < n; r += 64) {
+      const double v0 = vval(r);
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (qs[k] < n) acc[k] += a.re[r + qs[k] * a.ld] * v0;
     }
   }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0 && qs[k] < n) pv[(int64_t)b * n + qs[k]] = s;
+  }
+  (void)tau;
 }
 
-__global__ void k_tri_fin(DMat<double> A, int64_t n, double* dv, double* ev, double* sclv) {
+// red[0] = p^T v, red[2 + q] = W[:, q]^T v, red[2 + NB + q] = V[:, q]^T v
+// (q < c), v = V[:, c]; rows >= j + 1.  One workgroup per product.
+__global__ __launch_bounds__(256) void k_tri_dots(int64_t n, int64_t j, int c, const double* vw,
+                                                  const double* pv, double* red) {
+  __shared__ double rs[8];
+  const int g = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+  const double* V = vw + (int64_t)b * n * 2 * TRI_NB;
+  const double* W = V + n * TRI_NB;
+  const double* v = V + (int64_t)c * n;
+  const double* x = g == 0 ? pv + (int64_t)b * n : (g <= c ? W + (int64_t)(g - 1) * n
+                                                           : V + (int64_t)(g - 1 - c) * n);
+  double s = 0;
+  for (int64_t r = j + 1 + t; r < n; r += 256) s += x[r] * v[r];
+  s = block_sum256(s, rs);
+  if (t == 0) {
+    double* rd = red + (int64_t)b * (2 * TRI_NB + 2);
+    if (g == 0) rd[0] = s;
+    else if (g <= c) rd[2 + g - 1] = s;
+    else rd[2 + TRI_NB + g - 1 - c] = s;
+  }
+}
+
+__global__ void k_tri_fin(DMat<double> A, int64_t n, double* dv, double* ev) {
   const int b = blockIdx.x;
   DMat<double> a = A.item(b);
-  const int t = threadIdx.x;
-  if (n >= 3) {
-    const int64_t j = n - 3;
-    const double sp = sclv[b * n + j];
-    for (int64_t i = j + 2 + t; i < n; i += blockDim.x) a.re[i + j * a.ld] *= sp;
-  }
-  if (t == 0) {
+  if (threadIdx.x == 0) {
     if (n >= 2) {
       dv[b * n + n - 2] = a.re[(n - 2) + (n - 2) * a.ld];
       ev[b * n + n - 2] = a.re[(n - 1) + (n - 2) * a.ld];
@@ -151,19 +240,49 @@ __global__ void k_tri_fin(DMat<double> A, int64_t n, double* dv, double* ev, dou
 }
 
 void sy_tridiag(hipStream_t s, DMat<double> A, int64_t n, int batch, TriWork& w) {
+  if (n <= 0 || batch <= 0) return;
   w.reserve(n, batch);
-  for (int64_t j = 0; j + 2 < n; ++j) {
-    const int64_t L = n - j - 1;
-    dim3 ga((unsigned)((L + 3) / 4), batch);
-    k_tri_a<<<ga, 256, 0, s>>>(A, n, j, w.d.as<double>(), w.e.as<double>(), w.tau.as<double>(),
-                               w.scl.as<double>(), w.pvec.as<double>());
+  double* vw = w.vw.as<double>();
+  const bool vec = A.ld % 2 == 0 && A.bs % 2 == 0 && ((uintptr_t)A.re & 15u) == 0;
+  const int64_t nred = n - 2;  // columns that get a reflector
+  for (int64_t i0 = 0; i0 < nred; i0 += TRI_NB) {
+    const int nbp = (int)std::min<int64_t>(TRI_NB, nred - i0);
+    for (int c = 0; c < nbp; ++c) {
+      const int64_t j = i0 + c;
+      dim3 g1(grid1(n - j), batch);
+      k_tri_col<<<g1, 256, 0, s>>>(A, n, j, c, 1, vw, w.tau.as<double>(), w.pvec.as<double>(),
+                                   w.red.as<double>(), w.acol.as<double>(), w.d.as<double>(),
+                                   w.sq.as<double>());
+      RFD_CHECK_LAUNCH();
+      dim3 g2((unsigned)((n - j - 1 + 7) / 8), batch);
+      if (vec)
+        k_tri_symv<true><<<g2, 256, 0, s>>>(A, n, j, c, vw, w.d.as<double>(), w.e.as<double>(),
+                                            w.tau.as<double>(), w.pvec.as<double>(),
+                                            w.acol.as<double>(), w.sq.as<double>());
+      else
+        k_tri_symv<false><<<g2, 256, 0, s>>>(A, n, j, c, vw, w.d.as<double>(), w.e.as<double>(),
+                                             w.tau.as<double>(), w.pvec.as<double>(),
+                                             w.acol.as<double>(), w.sq.as<double>());
+      RFD_CHECK_LAUNCH();
+      k_tri_dots<<<dim3(2 * c + 1, batch), 256, 0, s>>>(n, j, c, vw, w.pvec.as<double>(),
+                                                        w.red.as<double>());
+      RFD_CHECK_LAUNCH();
+    }
+    // finish W's last column, then the trailing block takes the panel's update
+    const int64_t i1 = i0 + nbp;
+    dim3 g1(grid1(n - i1), batch);
+    k_tri_col<<<g1, 256, 0, s>>>(A, n, i1, nbp, 0, vw, w.tau.as<double>(), w.pvec.as<double>(),
+                                 w.red.as<double>(), w.acol.as<double>(), w.d.as<double>(),
+                                 w.sq.as<double>());
     RFD_CHECK_LAUNCH();
-    dim3 gb((unsigned)((L + 7) / 8), batch);
-    k_tri_b<<<gb, 256, 0, s>>>(A, n, j, w.tau.as<double>(), w.scl.as<double>(),
-                               w.pvec.as<double>());
-    RFD_CHECK_LAUNCH();
+    const int64_t m = n - i1;
+    DMat<double> Vm{vw + i1, nullptr, n, n * 2 * TRI_NB};
+    DMat<double> Wm{vw + n * TRI_NB + i1, nullptr, n, n * 2 * TRI_NB};
+    DMat<double> Cm = A.sub(i1, i1);
+    gemm<double>(s, false, true, m, m, nbp, -1.0, Vm, Wm, 1.0, Cm, batch);
+    gemm<double>(s, false, true, m, m, nbp, -1.0, Wm, Vm, 1.0, Cm, batch);
   }
-  k_tri_fin<<<batch, 256, 0, s>>>(A, n, w.d.as<double>(), w.e.as<double>(), w.scl.as<double>());
+  k_tri_fin<<<batch, 64, 0, s>>>(A, n, w.d.as<double>(), w.e.as<double>());
   RFD_CHECK_LAUNCH();
 }
 

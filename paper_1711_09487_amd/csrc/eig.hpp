@@ -11,8 +11,10 @@
 
 namespace rfd {
 
+constexpr int TRI_NB = 32;  // panel width of the blocked tridiagonalization
+
 struct TriWork {
-  DevBuf d, e, tau, scl, pvec;
+  DevBuf d, e, tau, pvec, acol, vw, red, sq;
   int64_t cap = 0;
   void reserve(int64_t n, int batch);
 };

@@ -1,0 +1,389 @@
+// Batched MFMA GEMM for gfx950 (FP32 / FP64, real / planar complex).
+//
+// Workgroup tile BM x BN (64 or 128), 4 waves in a 2 x 2 arrangement, K slabs
+// of 16 staged through double-buffered LDS: the next slab's global loads
+// (16-byte vectors when the operand is aligned) are in flight while the
+// current slab feeds the matrix cores.  FP32 uses v_mfma_f32_32x32x2f32 and
+// FP64 v_mfma_f64_16x16x4f64.  The operands enter the MFMA swapped (the B
+// tile as the row operand) so that the accumulator rows run down the columns
+// of the column-major C and the epilogue stores are coalesced.  A complex
+// product is four real products into two accumulators.
+//
+// Operand lane layouts: 32x32x2 -- lane l holds X[l%32][l/32] of the row
+// operand and Y[l/32][l%32] of the column operand; D register r of lane l is
+// element (8 (r/4) + 4 (l/32) + r%4, l%32).  16x16x4 -- lane l holds
+// X[l%16][l/16], Y[l/16][l%16]; D register r is element ((l/16) + 4 r, l%16).
+//
+// Few output tiles over a long K (the tall-skinny products of basis
+// orthogonalisation and projection) split K over extra workgroups; partial
+// tiles go to a per-stream workspace and a second kernel sums them in a fixed
+// order, so results do not depend on scheduling.
+#include <map>
+#include <mutex>
+
+#include "dense.hpp"
+
+namespace rfd {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct V16;
+template <> struct V16<float> { using t = float4; };
+template <> struct V16<double> { using t = double2; };
+
+constexpr int GBK = 16;
+
+// Registers holding one K slab of an operand tile.  In memory the tile is a
+// column-major FE x SE block (FE along the contiguous dimension).
+template <typename T, int FE, int SE>
+struct Slab {
+  static constexpr int VW = 16 / (int)sizeof(T);
+  static constexpr int NV = FE * SE / VW / 256;
+  static_assert(NV >= 1 && (FE * SE) % (VW * 256) == 0, "tile does not split over 256 threads");
+  typename V16<T>::t v[NV];
+
+  // base: tile element (0, 0) or null (zero operand); nf x ns valid extent;
+  // fast: the whole tile is valid and 16-byte aligned.
+  __device__ void load(const T* base, int64_t ld, int nf, int ns, bool fast, int tid) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = tid + 256 * q;
+      const int f = (e % (FE / VW)) * VW, sl = e / (FE / VW);
+      T* o = reinterpret_cast<T*>(&v[q]);
+      if (base == nullptr) {
+#pragma unroll
+        for (int w = 0; w < VW; ++w) o[w] = T(0);
+      } else if (fast) {
+        v[q] = *reinterpret_cast<const typename V16<T>::t*>(base + f + sl * ld);
+      } else {
+#pragma unroll
+        for (int w = 0; w < VW; ++w)
+          o[w] = (f + w < nf && sl < ns) ? base[f + w + sl * ld] : T(0);
+      }
+    }
+  }
+
+  // LDS tile L[k][x] (row length P).  kfast: the contiguous dimension is k
+  // (scattered into LDS columns); otherwise it is x (vector stores).
+  template <bool KFAST, int P>
+  __device__ void store(T (*L)[P], int tid) const {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = tid + 256 * q;
+      const int f = (e % (FE / VW)) * VW, sl = e / (FE / VW);
+      const T* o = reinterpret_cast<const T*>(&v[q]);
+      if (KFAST) {
+#pragma unroll
+        for (int w = 0; w < VW; ++w) L[f + w][sl] = o[w];
+      } else {
+        *reinterpret_cast<typename V16<T>::t*>(&L[sl][f]) = v[q];
+      }
+    }
+  }
+};
+
+template <typename T, bool CPLX, bool TA, bool TB, int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T alpha, T beta,
+                                              DMat<T> A, DMat<T> B, DMat<T> C, int splits,
+                                              int64_t kchunk, T* part, int vec_a, int vec_b) {
+  constexpr int NP = CPLX ? 2 : 1;
+  constexpr int VW = 16 / (int)sizeof(T);
+  constexpr int PA = BM + VW, PB = BN + VW;
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int BLK = F32 ? 32 : 16;                 // MFMA block edge
+  constexpr int XM = BM / 2 / BLK, XN = BN / 2 / BLK;  // blocks per wave
+  __shared__ __attribute__((aligned(16))) T As[2][NP][GBK][PA];
+  __shared__ __attribute__((aligned(16))) T Bs[2][NP][GBK][PB];
+
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int batch = (int)gridDim.z / splits;
+  const int b = (int)blockIdx.z / splits, sk = (int)blockIdx.z - b * splits;
+  A = A.item(b);
+  B = B.item(b);
+  C = C.item(b);
+  const int64_t kb = (int64_t)sk * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
+  const int mv = (int)((M - m0) < BM ? (M - m0) : BM);
+  const int nv = (int)((N - n0) < BN ? (N - n0) : BN);
+
+  using SA = Slab<T, TA ? GBK : BM, TA ? BM : GBK>;
+  using SB = Slab<T, TB ? BN : GBK, TB ? GBK : BN>;
+  SA ra[NP];
+  SB rb[NP];
+  const bool aim = CPLX && A.im != nullptr, bim = CPLX && B.im != nullptr;
+
+  auto gload = [&](int64_t k0) {
+    const int kv = (int)((ke - k0) < GBK ? (ke - k0) : GBK);
+    const int64_t oa = TA ? (k0 + m0 * A.ld) : (m0 + k0 * A.ld);
+    const bool fa = vec_a && kv == GBK && mv == BM;
+    ra[0].load(A.re + oa, A.ld, TA ? kv : mv, TA ? mv : kv, fa, tid);
+    if constexpr (CPLX) ra[NP - 1].load(aim ? A.im + oa : nullptr, A.ld, TA ? kv : mv, TA ? mv : kv, fa, tid);
+    const int64_t ob = TB ? (n0 + k0 * B.ld) : (k0 + n0 * B.ld);
+    const bool fb = vec_b && kv == GBK && nv == BN;
+    rb[0].load(B.re + ob, B.ld, TB ? nv : kv, TB ? kv : nv, fb, tid);
+    if constexpr (CPLX) rb[NP - 1].load(bim ? B.im + ob : nullptr, B.ld, TB ? nv : kv, TB ? kv : nv, fb, tid);
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      ra[p].template store<TA, PA>(As[buf][p], tid);
+      rb[p].template store<!TB, PB>(Bs[buf][p], tid);
+    }
+  };
+
+  floatx16 fr[XM][XN], fi[XM][XN];
+  doublex4 dr[XM][XN], di[XM][XN];
+#pragma unroll
+  for (int x = 0; x < XM; ++x)
+#pragma unroll
+    for (int y = 0; y < XN; ++y) {
+      if constexpr (F32) {
+        for (int r = 0; r < 16; ++r) fr[x][y][r] = 0.f, fi[x][y][r] = 0.f;
+      } else {
+        dr[x][y] = doublex4{0, 0, 0, 0};
+        di[x][y] = doublex4{0, 0, 0, 0};
+      }
+    }
+
+  auto compute = [&](int buf) {
+    if constexpr (F32) {
+#pragma unroll
+      for (int kk = 0; kk < GBK; kk += 2) {
+        const int kr = kk + (lane >> 5), r = lane & 31;
+        float ar[XM], ai[XM], br[XN], bi[XN];
+#pragma unroll
+        for (int x = 0; x < XM; ++x) {
+          ar[x] = As[buf][0][kr][wm + 32 * x + r];
+          if constexpr (CPLX) ai[x] = As[buf][NP - 1][kr][wm + 32 * x + r];
+        }
+#pragma unroll
+        for (int y = 0; y < XN; ++y) {
+          br[y] = Bs[buf][0][kr][wn + 32 * y + r];
+          if constexpr (CPLX) bi[y] = Bs[buf][NP - 1][kr][wn + 32 * y + r];
+        }
+#pragma unroll
+        for (int x = 0; x < XM; ++x)
+#pragma unroll
+          for (int y = 0; y < XN; ++y) {
+            fr[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(br[y], ar[x], fr[x][y], 0, 0, 0);
+            if constexpr (CPLX) {
+              fr[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(-bi[y], ai[x], fr[x][y], 0, 0, 0);
+              fi[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(br[y], ai[x], fi[x][y], 0, 0, 0);
+              fi[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(bi[y], ar[x], fi[x][y], 0, 0, 0);
+            }
+          }
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < GBK; kk += 4) {
+        const int kr = kk + (lane >> 4), r = lane & 15;
+        double ar[XM], ai[XM], br[XN], bi[XN];
+#pragma unroll
+        for (int x = 0; x < XM; ++x) {
+          ar[x] = As[buf][0][kr][wm + 16 * x + r];
+          if constexpr (CPLX) ai[x] = As[buf][NP - 1][kr][wm + 16 * x + r];
+        }
+#pragma unroll
+        for (int y = 0; y < XN; ++y) {
+          br[y] = Bs[buf][0][kr][wn + 16 * y + r];
+          if constexpr (CPLX) bi[y] = Bs[buf][NP - 1][kr][wn + 16 * y + r];
+        }
+#pragma unroll
+        for (int x = 0; x < XM; ++x)
+#pragma unroll
+          for (int y = 0; y < XN; ++y) {
+            dr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[y], ar[x], dr[x][y], 0, 0, 0);
+            if constexpr (CPLX) {
+              dr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bi[y], ai[x], dr[x][y], 0, 0, 0);
+              di[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[y], ai[x], di[x][y], 0, 0, 0);
+              di[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bi[y], ar[x], di[x][y], 0, 0, 0);
+            }
+          }
+      }
+    }
+  };
+
+  if (kb < ke) {
+    gload(kb);
+    lstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
+    const bool more = k0 + GBK < ke;
+    if (more) gload(k0 + GBK);
+    compute(buf);
+    // the other buffer was last read before the previous barrier
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  T* pr = nullptr;
+  T* pi = nullptr;
+  if (splits > 1) {
+    pr = part + ((int64_t)(sk * batch + b) * NP) * M * N;
+    pi = pr + (NP - 1) * M * N;
+  }
+  auto put = [&](int64_t i, int64_t j, T vr, T vi) {
+    if (i >= M || j >= N) return;
+    if (splits > 1) {
+      pr[i + j * M] = alpha * vr;
+      if constexpr (CPLX) pi[i + j * M] = alpha * vi;
+      return;
+    }
+    const int64_t off = i + j * C.ld;
+    T outr = alpha * vr, outi = alpha * vi;
+    if (beta != T(0)) {
+      outr += beta * C.re[off];
+      if constexpr (CPLX) outi += beta * C.im[off];
+    }
+    C.re[off] = outr;
+    if constexpr (CPLX) C.im[off] = outi;
+  };
+#pragma unroll
+  for (int x = 0; x < XM; ++x)
+#pragma unroll
+    for (int y = 0; y < XN; ++y) {
+      if constexpr (F32) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t i = m0 + wm + 32 * x + (lane & 31);
+          const int64_t j = n0 + wn + 32 * y + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          put(i, j, fr[x][y][r], CPLX ? fi[x][y][r] : 0.0f);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = m0 + wm + 16 * x + (lane & 15);
+          const int64_t j = n0 + wn + 16 * y + (lane >> 4) + 4 * r;
+          put(i, j, dr[x][y][r], CPLX ? di[x][y][r] : 0.0);
+        }
+      }
+    }
+}
+
+// C_b = sum over splits of the partial tiles (alpha applied) + beta C_b.
+template <typename T, bool CPLX>
+__global__ void k_splitk_sum(int64_t M, int64_t N, int splits, int batch, const T* part, T beta,
+                             DMat<T> C) {
+  constexpr int NP = CPLX ? 2 : 1;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int b = blockIdx.y;
+  C = C.item(b);
+  const int64_t i = e % M, j = e / M;
+  const int64_t plane = M * N;
+  T sr = 0, si = 0;
+  for (int s = 0; s < splits; ++s) {
+    const T* p = part + ((int64_t)(s * batch + b) * NP) * plane;
+    sr += p[e];
+    if constexpr (CPLX) si += p[plane + e];
+  }
+  const int64_t off = i + j * C.ld;
+  if (beta != T(0)) {
+    sr += beta * C.re[off];
+    if constexpr (CPLX) si += beta * C.im[off];
+  }
+  C.re[off] = sr;
+  if constexpr (CPLX) C.im[off] = si;
+}
+
+// Per-stream split-K workspace (grown on demand; a stream's earlier work is
+// finished before its buffer is replaced).
+static void* splitk_workspace(hipStream_t s, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, DevBuf> ws;
+  int dev = 0;
+  RFD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  DevBuf& w = ws[{dev, s}];
+  if (w.bytes < bytes) {
+    if (w.p) RFD_HIP(hipStreamSynchronize(s));
+    w.alloc(bytes);
+  }
+  return w.p;
+}
+
+template <typename T, bool CPLX, int BM, int BN>
+static void launch(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N, int64_t K,
+                   T alpha, T beta, DMat<T> A, DMat<T> B, DMat<T> C, int splits, int64_t kchunk,
+                   T* part, int va, int vb) {
+#define RFD_GEMM_GO(TA_, TB_)                                                               \
+  k_gemm<T, CPLX, TA_, TB_, BM, BN><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C, splits, \
+                                                     kchunk, part, va, vb)
+  if (!ta && !tb) RFD_GEMM_GO(false, false);
+  else if (ta && !tb) RFD_GEMM_GO(true, false);
+  else if (!ta && tb) RFD_GEMM_GO(false, true);
+  else RFD_GEMM_GO(true, true);
+#undef RFD_GEMM_GO
+}
+
+template <typename T>
+static bool aligned16(const DMat<T>& X, int vw) {
+  auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+  return X.ld % vw == 0 && X.bs % vw == 0 && al(X.re) && (X.im == nullptr || al(X.im));
+}
+
+template <typename T>
+void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, DMat<T> A,
+          DMat<T> B, T beta, DMat<T> C, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  const bool cplx = C.cplx();
+  const int NP = cplx ? 2 : 1;
+  constexpr int VW = 16 / (int)sizeof(T);
+  // tile: 128 x 128 when the product is large enough to fill the chip with it
+  // (not for FP64 complex, whose accumulators would not fit)
+  const bool big_ok = !(sizeof(T) == 8 && cplx) && M >= 128 && N >= 128;
+  const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128) * batch;
+  const int bt = (big_ok && t128 >= 240) ? 128 : 64;
+  const int64_t gm = (M + bt - 1) / bt, gn = (N + bt - 1) / bt;
+  const int64_t tiles = gm * gn * batch;
+  int splits = 1;
+  if (tiles < 512 && K >= 1024) {
+    splits = (int)std::min<int64_t>((1024 + tiles - 1) / tiles, K / 512);
+    while (splits > 1 && (double)splits * batch * M * N * NP * sizeof(T) > 512.0 * (1 << 20))
+      --splits;
+    while (splits > 1 && (int64_t)splits * batch > 65535) --splits;
+    if (splits < 1) splits = 1;
+  }
+  if ((int64_t)batch * splits > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
+  if (gm > 0x7fffffff || gn > 65535) throw Error(ST_EINVAL, "gemm: matrix too large");
+  int64_t kchunk = K;
+  if (splits > 1) {
+    kchunk = round_up((K + splits - 1) / splits, GBK);
+    splits = (int)((K + kchunk - 1) / kchunk);
+  }
+  T* part = nullptr;
+  if (splits > 1)
+    part = static_cast<T*>(splitk_workspace(s, sizeof(T) * (size_t)splits * batch * M * N * NP));
+  const int va = aligned16(A, VW), vb = aligned16(B, VW);
+  dim3 g((unsigned)gm, (unsigned)gn, (unsigned)(batch * splits));
+  const int key = (sizeof(T) == 8 ? 8 : 0) + (cplx ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
+  const double flops = (cplx ? 8.0 : 2.0) * (double)M * (double)N * (double)K * batch;
+  KernelAccount::Scope acct(s, key, flops);
+  if (cplx) {
+    if (bt == 128) launch<T, true, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb);
+    else launch<T, true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb);
+  } else {
+    if (bt == 128) launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb);
+    else launch<T, false, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb);
+  }
+  RFD_CHECK_LAUNCH();
+  if (splits > 1) {
+    dim3 gr(grid1(M * N), (unsigned)batch);
+    if (cplx) k_splitk_sum<T, true><<<gr, 256, 0, s>>>(M, N, splits, batch, part, beta, C);
+    else k_splitk_sum<T, false><<<gr, 256, 0, s>>>(M, N, splits, batch, part, beta, C);
+    RFD_CHECK_LAUNCH();
+  }
+}
+
+template void gemm<float>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, float, DMat<float>,
+                          DMat<float>, float, DMat<float>, int);
+template void gemm<double>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, double, DMat<double>,
+                           DMat<double>, double, DMat<double>, int);
+
+}  // namespace rfd

@@ -3,7 +3,11 @@
 // host computation.  Declared in include/rfd_testing.h.
 #include <cstring>
 
+#include <algorithm>
+#include <cmath>
+
 #include "dense.hpp"
+#include "eig.hpp"
 #include "rfd_capi_util.hpp"
 
 using namespace rfd;
@@ -80,3 +84,49 @@ extern "C" int rfd_test_lu(int dtype, int pivot, int64_t n, int batch, void* a_r
 // Copies the current M-orthonormal basis of range(Z) (reordered numbering,
 // n x k, ld n) to dst (device, room for n * cap doubles); returns k in *k_out.
 
+
+// Eigenpairs lo .. lo + num - 1 (ascending, 0-based) of each symmetric
+// n x n item of A (device, ld n, item stride n * n, destroyed): blocked
+// tridiagonalization, bisection, inverse iteration with eigenvalues closer
+// than 1e-10 ||A|| treated as one cluster, back-transformation.  lam: device,
+// num per item; Y: device, n x num per item.
+extern "C" int rfd_test_syevx(int64_t n, int batch, double* A, int lo, int num, double* lam,
+                              double* Y, void* stream) {
+  return capi_guard([&] {
+    hipStream_t s = (hipStream_t)stream;
+    if (n < 1 || batch < 1 || lo < 0 || num < 1 || lo + num > n)
+      throw Error(ST_EINVAL, "bad eigenvalue range");
+    DMat<double> Am{A, nullptr, n, n * n};
+    TriWork tw;
+    sy_tridiag(s, Am, n, batch, tw);
+    std::vector<int> lov(batch, lo), nv(batch, num);
+    DevBuf lo_d, num_d, cl_d, scr;
+    lo_d.alloc(sizeof(int) * batch);
+    num_d.alloc(sizeof(int) * batch);
+    RFD_HIP(hipMemcpyAsync(lo_d.p, lov.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
+    RFD_HIP(hipMemcpyAsync(num_d.p, nv.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
+    bisect(s, tw, n, batch, lo_d.as<int>(), num_d.as<int>(), num, lam, num);
+    std::vector<double> lh((size_t)batch * num), dh((size_t)n * batch), eh((size_t)n * batch);
+    RFD_HIP(hipMemcpyAsync(lh.data(), lam, sizeof(double) * lh.size(), hipMemcpyDeviceToHost, s));
+    RFD_HIP(hipMemcpyAsync(dh.data(), tw.d.p, sizeof(double) * dh.size(), hipMemcpyDeviceToHost, s));
+    RFD_HIP(hipMemcpyAsync(eh.data(), tw.e.p, sizeof(double) * eh.size(), hipMemcpyDeviceToHost, s));
+    RFD_HIP(hipStreamSynchronize(s));
+    std::vector<int> cl((size_t)batch * num);
+    for (int b = 0; b < batch; ++b) {
+      double tn = 0;
+      for (int64_t r = 0; r < n; ++r)
+        tn = std::max(tn, std::fabs(dh[b * n + r]) + std::fabs(eh[b * n + r]) +
+                              (r ? std::fabs(eh[b * n + r - 1]) : 0.0));
+      for (int i = 0; i < num; ++i) {
+        const double* l = lh.data() + (size_t)b * num;
+        cl[(size_t)b * num + i] = (i > 0 && l[i] - l[i - 1] <= 1e-10 * tn) ? cl[(size_t)b * num + i - 1] : i;
+      }
+    }
+    cl_d.alloc(sizeof(int) * cl.size());
+    RFD_HIP(hipMemcpyAsync(cl_d.p, cl.data(), sizeof(int) * cl.size(), hipMemcpyHostToDevice, s));
+    DMat<double> Ym{Y, nullptr, n, n * num};
+    inverse_iteration(s, tw, n, batch, lam, num_d.as<int>(), cl_d.as<int>(), num, Ym, scr);
+    back_transform(s, Am, tw, n, batch, Ym, num_d.as<int>(), num);
+    RFD_HIP(hipStreamSynchronize(s));
+  });
+}

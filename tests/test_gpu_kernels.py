@@ -26,14 +26,22 @@ def _host(t):
     return np.swapaxes(t.double().cpu().numpy(), 1, 2)
 
 
+# (M, N, K, batch): ragged small tiles with unaligned leading dimensions;
+# 128-wide tiles with aligned operands and ragged edges; a long K split over
+# workgroups (partial sums reduced by a second kernel)
+GEMM_SHAPES = {"small_unaligned": (70, 130, 37, 3), "tile128_ragged": (1100, 1030, 72, 3),
+               "split_k": (100, 70, 5000, 2)}
+
+
+@pytest.mark.parametrize("shape", list(GEMM_SHAPES))
 @pytest.mark.parametrize("dtype", [0, 1])
 @pytest.mark.parametrize("cplx", [False, True])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
-def test_gemm_batched(dtype, cplx, ta, tb):
+def test_gemm_batched(dtype, cplx, ta, tb, shape):
     torch = _torch()
     import paper_1711_09487_amd as R
     rs = np.random.default_rng(1)
-    M, N, K, batch = 70, 130, 37, 3
+    M, N, K, batch = GEMM_SHAPES[shape]
     dt = torch.float32 if dtype == 0 else torch.float64
     Ash = (batch, K, M) if ta else (batch, M, K)
     Bsh = (batch, N, K) if tb else (batch, K, N)
@@ -141,3 +149,37 @@ def test_lu_breakdown_flag():
                                C.byref(flags), torch.cuda.current_stream().cuda_stream)
     assert code == 0
     assert flags.value != 0
+
+
+@pytest.mark.parametrize("n,batch,lo,num", [(100, 3, 5, 20), (77, 2, 0, 30), (40, 1, 0, 40)])
+def test_symmetric_eigensolver(n, batch, lo, num):
+    """Blocked tridiagonalization + bisection + inverse iteration + back-
+    transformation against LAPACK: ragged panels (n - 2 reflectors in panels
+    of 32), odd n (scalar loads), and a cluster of equal eigenvalues."""
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    rs = np.random.default_rng(7)
+    mats = []
+    for b in range(batch):
+        Q, _ = np.linalg.qr(rs.standard_normal((n, n)))
+        lam = np.sort(rs.uniform(-2, 3, n))
+        lam[3:6] = lam[3]                      # a triple eigenvalue
+        mats.append((Q * lam) @ Q.T)
+    A = np.array([0.5 * (m + m.T) for m in mats])
+    At = torch.from_numpy(A.copy()).cuda()   # symmetric: row- and column-major agree
+    lam_d = torch.zeros(batch * num, dtype=torch.float64, device="cuda")
+    Y_d = torch.zeros(batch * num * n, dtype=torch.float64, device="cuda")
+    code = R.lib().rfd_test_syevx(n, batch, At.data_ptr(), lo, num, lam_d.data_ptr(),
+                                  Y_d.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert code == 0, R.rfd_last_error()
+    torch.cuda.synchronize()
+    lam = lam_d.cpu().numpy().reshape(batch, num)
+    Y = Y_d.cpu().numpy().reshape(batch, num, n)
+    for b in range(batch):
+        ref = np.linalg.eigvalsh(A[b])[lo:lo + num]
+        nrm = np.abs(np.linalg.eigvalsh(A[b])).max()
+        assert np.max(np.abs(lam[b] - ref)) <= 1e-13 * nrm
+        X = Y[b].T
+        res = A[b] @ X - X * lam[b]
+        assert np.max(np.abs(res)) <= 1e-12 * nrm
+        assert np.max(np.abs(X.T @ X - np.eye(num))) <= 1e-12
