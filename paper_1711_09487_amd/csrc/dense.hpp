@@ -36,6 +36,13 @@ template <typename T>
 void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha,
           DMat<T> A, DMat<T> B, T beta, DMat<T> C, int batch);
 
+// As gemm for square N x N results, computing only the output tiles that
+// meet the lower triangle (i >= j); entries above the diagonal are left
+// undefined (the caller mirrors the lower triangle of a symmetric result).
+template <typename T>
+void gemm_lower(hipStream_t s, bool ta, bool tb, int64_t N, int64_t K, T alpha, DMat<T> A,
+                DMat<T> B, T beta, DMat<T> C, int batch);
+
 // In-place LU without pivoting of n x n items (n multiple of NB).  inv
 // receives, per item, the inverses of the unit-lower and upper diagonal
 // blocks: an NB x (2 n) matrix [Linv_0 Uinv_0 Linv_1 Uinv_1 ...].  A pivot

@@ -122,13 +122,16 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
   if (t == 0) sq[(int64_t)b * ((n + 255) / 256) + blockIdx.x] = s2;
 }
 
-// Reflector of column j and p[q] = sum_r A[r, q] v[r] for q, r in [j+1, n);
-// each wave owns two columns q.
+// Reflector of column j and p[q] = sum_r A[r, q] v[r] for q, r in [j+1, n).
+// A workgroup owns 8 columns; its 4 waves split the rows (128 per wave and
+// step, double2 per lane) and combine through LDS, so that each lane keeps 8
+// independent loads in flight.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int64_t j, int c,
                                                   double* vw, double* dv, double* ev, double* tauv,
                                                   double* pv, const double* acol, const double* sq) {
   __shared__ double hh[4];
+  __shared__ double part[4][8];
   const int b = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   DMat<double> a = A.item(b);
   const double* ac = acol + (int64_t)b * n;
@@ -150,14 +153,14 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     hh[2] = scale;
   }
   __syncthreads();
-  const double tau = hh[0], scale = hh[2];
+  const double scale = hh[2];
   const int64_t j1 = j + 1;
   auto vval = [&](int64_t r) -> double {
     return r < j1 ? 0.0 : (r == j1 ? 1.0 : ac[r] * scale);
   };
   if (blockIdx.x == 0 && t == 0) {
     ev[(int64_t)b * n + j] = hh[1];
-    tauv[(int64_t)b * n + j] = tau;
+    tauv[(int64_t)b * n + j] = hh[0];
   }
   // this workgroup's share of v: V[:, c] and column j of A (rows >= j + 2)
   const int64_t q0 = j1 + (int64_t)blockIdx.x * 8;
@@ -168,40 +171,44 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     V[r + (int64_t)c * n] = v;
     if (r >= j + 2) a.re[r + j * a.ld] = v;
   }
-  double acc[2] = {0.0, 0.0};
-  int64_t qs[2];
-  for (int k = 0; k < 2; ++k) qs[k] = q0 + wave * 2 + k;
+  const double* col[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) col[k] = a.re + (q0 + k < n ? q0 + k : q0) * a.ld;
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
   if (VEC) {
     const int64_t r0 = j1 & ~(int64_t)1;
-    for (int64_t r = r0 + 2 * lane; r < n; r += 128) {
+#pragma unroll 2
+    for (int64_t r = r0 + 2 * lane + 128 * wave; r < n; r += 512) {
       const double v0 = vval(r);
-      const double v1 = (r + 1 < n) ? vval(r + 1) : 0.0;
+      if (r + 1 < n) {
+        const double v1 = vval(r + 1);
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        if (qs[k] >= n) continue;
-        const double* col = a.re + qs[k] * a.ld;
-        if (r + 1 < n) {
-          const double2 x = *reinterpret_cast<const double2*>(col + r);
+        for (int k = 0; k < 8; ++k) {
+          const double2 x = *reinterpret_cast<const double2*>(col[k] + r);
           acc[k] += x.x * v0 + x.y * v1;
-        } else {
-          acc[k] += col[r] * v0;
         }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += col[k][r] * v0;
       }
     }
   } else {
-    for (int64_t r = j1 + lane; r < n; r += 64) {
+    for (int64_t r = j1 + lane + 64 * wave; r < n; r += 256) {
       const double v0 = vval(r);
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
-        if (qs[k] < n) acc[k] += a.re[r + qs[k] * a.ld] * v0;
+      for (int k = 0; k < 8; ++k) acc[k] += col[k][r] * v0;
     }
   }
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 8; ++k) {
     const double s = wave_sum(acc[k]);
-    if (lane == 0 && qs[k] < n) pv[(int64_t)b * n + qs[k]] = s;
+    if (lane == 0) part[wave][k] = s;
   }
-  (void)tau;
+  __syncthreads();
+  if (t < 8 && q0 + t < n)
+    pv[(int64_t)b * n + q0 + t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
 }
 
 // red[0] = p^T v, red[2 + q] = W[:, q]^T v, red[2 + NB + q] = V[:, q]^T v
@@ -325,41 +332,62 @@ void sturm_counts(hipStream_t s, const TriWork& w, int64_t n, int batch, const d
   RFD_CHECK_LAUNCH();
 }
 
-__global__ void k_bisect(const double* dv, const double* ev, int64_t n, int batch, const int* lo,
-                         const int* num, int maxnum, double* lam, int64_t ld_lam) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Multisection: one wavefront per eigenvalue; each lane takes the Sturm
+// count at one of 64 interior points of the current bracket, and the bracket
+// shrinks to the two neighbouring points around the wanted index.
+__global__ __launch_bounds__(256) void k_bisect(const double* dv, const double* ev, int64_t n,
+                                                int batch, const int* lo, const int* num,
+                                                int maxnum, double* lam, int64_t ld_lam) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int b = blockIdx.y;
   if (i >= maxnum || i >= num[b]) return;
   const double* d = dv + (int64_t)b * n;
   const double* e = ev + (int64_t)b * n;
-  double gl = d[0], gu = d[0];
-  for (int64_t r = 0; r < n; ++r) {
+  double gl = INFINITY, gu = -INFINITY, em = 1.0;
+  for (int64_t r = lane; r < n; r += 64) {
     const double off = (r > 0 ? fabs(e[r - 1]) : 0.0) + (r + 1 < n ? fabs(e[r]) : 0.0);
     gl = fmin(gl, d[r] - off);
     gu = fmax(gu, d[r] + off);
+    if (r + 1 < n) em = fmax(em, e[r] * e[r]);
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, o, 64));
+    gu = fmax(gu, __shfl_xor(gu, o, 64));
+    em = fmax(em, __shfl_xor(em, o, 64));
+  }
+  const double pivmin = SAFMIN * em / EPS;
   const double tnorm = fmax(fabs(gl), fabs(gu));
   gl -= 2.0 * EPS * tnorm * n + 1e-300;
   gu += 2.0 * EPS * tnorm * n + 1e-300;
-  const double pivmin = pivmin_of(e, n);
-  const int k = lo[b] + i;  // want the k-th smallest (0-based): count(x) <= k < count(y)
+  const int k = lo[b] + i;  // want the k-th smallest (0-based): count(l) <= k < count(u)
   double l = gl, u = gu;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (l + u);
+  for (int it = 0; it < 64; ++it) {
     if (u - l <= 2.0 * EPS * fmax(fabs(l), fabs(u)) + 4.0 * pivmin) break;
-    if (mid <= l || mid >= u) break;
-    if (sturm(d, e, n, mid, pivmin) <= k) l = mid;
-    else u = mid;
+    const double x = l + (u - l) * ((double)(lane + 1) / 65.0);
+    const int cnt = sturm(d, e, n, x, pivmin);
+    const unsigned long long m = __ballot(cnt > k);
+    double nl = l, nu = u;
+    if (m == 0ull) {
+      nl = __shfl(x, 63, 64);
+    } else {
+      const int f = __ffsll((long long)m) - 1;
+      nu = __shfl(x, f, 64);
+      if (f > 0) nl = __shfl(x, f - 1, 64);
+    }
+    if (nl == l && nu == u) break;
+    l = nl;
+    u = nu;
   }
-  lam[(int64_t)b * ld_lam + i] = 0.5 * (l + u);
+  if (lane == 0) lam[(int64_t)b * ld_lam + i] = 0.5 * (l + u);
 }
 
 void bisect(hipStream_t s, const TriWork& w, int64_t n, int batch, const int* lo, const int* num,
             int maxnum, double* lam, int64_t ld_lam) {
   if (maxnum <= 0) return;
-  dim3 g(grid1(maxnum, 64), batch);
-  k_bisect<<<g, 64, 0, s>>>(w.d.as<double>(), w.e.as<double>(), n, batch, lo, num, maxnum, lam,
-                            ld_lam);
+  dim3 g((unsigned)((maxnum + 3) / 4), batch);
+  k_bisect<<<g, 256, 0, s>>>(w.d.as<double>(), w.e.as<double>(), n, batch, lo, num, maxnum, lam,
+                             ld_lam);
   RFD_CHECK_LAUNCH();
 }
 
@@ -376,93 +404,121 @@ __device__ inline double hash_unit(uint64_t a, uint64_t b) {
   return (double)(x >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
 }
 
-__global__ void k_invit(const double* dv, const double* ev, int64_t n, const double* lam,
-                        const int* num, const int* clus, int64_t ld_lam, DMat<double> Y,
-                        double* scratch) {
+// Scratch is interleaved over the threads (element r of slot g at r * S + g)
+// so that a wavefront's accesses at one step are contiguous; the elimination
+// and the substitutions carry their running values in registers.
+__global__ __launch_bounds__(64) void k_invit(const double* dv, const double* ev, int64_t n,
+                                              const double* lam, const int* num, const int* clus,
+                                              int64_t ld_lam, DMat<double> Y, double* scratch,
+                                              int64_t S) {
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
   if (i0 >= num[b] || i0 >= ld_lam) return;
   if (clus[(int64_t)b * ld_lam + i0] != i0) return;  // not a cluster head
   const double* d = dv + (int64_t)b * n;
   const double* e = ev + (int64_t)b * n;
-  double* W = scratch + ((int64_t)b * ld_lam + i0) * 6 * n;
-  double *dl = W, *dd = W + n, *du = W + 2 * n, *du2 = W + 3 * n, *x = W + 4 * n;
-  int* ip = reinterpret_cast<int*>(W + 5 * n);
+  const int64_t g = (int64_t)b * ld_lam + i0;
+  double* dl = scratch + g;
+  double* dd = dl + n * S;
+  double* du = dd + n * S;
+  double* du2 = du + n * S;
+  double* x = du2 + n * S;
+  int* ip = reinterpret_cast<int*>(scratch + 5 * n * S) + g;
   DMat<double> y = Y.item(b);
   double tnorm = 0;
   for (int64_t r = 0; r < n; ++r)
     tnorm = fmax(tnorm, fabs(d[r]) + (r > 0 ? fabs(e[r - 1]) : 0.0) + (r + 1 < n ? fabs(e[r]) : 0.0));
   const double pert = 10.0 * EPS * fmax(tnorm, 1e-300);
+  const double tiny = EPS * fmax(tnorm, 1e-300);
+  auto fix = [&](double v) { return fabs(v) < EPS * tnorm ? (v < 0 ? -tiny : tiny) : v; };
   double prev = -INFINITY;
   for (int i = i0; i < num[b] && clus[(int64_t)b * ld_lam + i] == i0; ++i) {
     double lm = lam[(int64_t)b * ld_lam + i];
     if (lm - prev < pert) lm = prev + pert;
     prev = lm;
-    // LU with partial pivoting of T - lm I (dgttrf)
-    for (int64_t r = 0; r < n; ++r) dd[r] = d[r] - lm;
+    // LU with partial pivoting of T - lm I (as dgttrf); dcur / ucur are the
+    // running diagonal and superdiagonal of the row being eliminated
+    double dcur = d[0] - lm, ucur = n > 1 ? e[0] : 0.0;
+#pragma unroll 4
     for (int64_t r = 0; r + 1 < n; ++r) {
-      dl[r] = e[r];
-      du[r] = e[r];
-    }
-    for (int64_t r = 0; r + 2 < n; ++r) du2[r] = 0.0;
-    for (int64_t r = 0; r + 1 < n; ++r) {
-      if (fabs(dd[r]) >= fabs(dl[r])) {
-        ip[r] = (int)r;
-        const double f = (dd[r] != 0.0) ? dl[r] / dd[r] : 0.0;
-        dl[r] = f;
-        dd[r + 1] -= f * du[r];
+      const double er = e[r];
+      const double dn = d[r + 1] - lm;
+      const double un = (r + 2 < n) ? e[r + 1] : 0.0;
+      if (fabs(dcur) >= fabs(er)) {
+        const double f = (dcur != 0.0) ? er / dcur : 0.0;
+        ip[r * S] = (int)r;
+        dl[r * S] = f;
+        dd[r * S] = fix(dcur);
+        du[r * S] = ucur;
+        du2[r * S] = 0.0;
+        dcur = dn - f * ucur;
+        ucur = un;
       } else {
-        ip[r] = (int)r + 1;
-        const double f = dd[r] / dl[r];
-        dd[r] = dl[r];
-        dl[r] = f;
-        const double tmp = du[r];
-        du[r] = dd[r + 1];
-        dd[r + 1] = tmp - f * dd[r + 1];
-        if (r + 2 < n) {
-          du2[r] = du[r + 1];
-          du[r + 1] = -f * du[r + 1];
-        }
+        const double f = dcur / er;
+        ip[r * S] = (int)r + 1;
+        dl[r * S] = f;
+        dd[r * S] = fix(er);
+        du[r * S] = dn;
+        du2[r * S] = un;
+        dcur = ucur - f * dn;
+        ucur = -f * un;
       }
     }
-    for (int64_t r = 0; r < n; ++r)
-      if (fabs(dd[r]) < EPS * tnorm) dd[r] = (dd[r] < 0 ? -1.0 : 1.0) * EPS * fmax(tnorm, 1e-300);
-    for (int64_t r = 0; r < n; ++r) x[r] = hash_unit((uint64_t)r + 1, (uint64_t)i + 7919ull * b);
+    dd[(n - 1) * S] = fix(dcur);
+    for (int64_t r = 0; r < n; ++r) x[r * S] = hash_unit((uint64_t)r + 1, (uint64_t)i + 7919ull * b);
     for (int it = 0; it < 4; ++it) {
-      // solve L U x = P b in place
+      // L (with the row interchanges): running x[r] in xc
+      double xc = x[0];
+#pragma unroll 4
       for (int64_t r = 0; r + 1 < n; ++r) {
-        if (ip[r] == r) {
-          x[r + 1] -= dl[r] * x[r];
+        const double xn = x[(r + 1) * S];
+        const double f = dl[r * S];
+        if (ip[r * S] == r) {
+          x[r * S] = xc;
+          xc = xn - f * xc;
         } else {
-          const double tmp = x[r];
-          x[r] = x[r + 1];
-          x[r + 1] = tmp - dl[r] * x[r];
+          x[r * S] = xn;
+          xc = xc - f * xn;
         }
       }
-      x[n - 1] /= dd[n - 1];
-      if (n > 1) x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dd[n - 2];
-      for (int64_t r = n - 3; r >= 0; --r) x[r] = (x[r] - du[r] * x[r + 1] - du2[r] * x[r + 2]) / dd[r];
+      x[(n - 1) * S] = xc;
+      // U (two superdiagonals): x1 = x[r + 1], x2 = x[r + 2]
+      double x1 = x[(n - 1) * S] / dd[(n - 1) * S], x2 = 0.0;
+      x[(n - 1) * S] = x1;
+#pragma unroll 4
+      for (int64_t r = n - 2; r >= 0; --r) {
+        const double v = (x[r * S] - du[r * S] * x1 - du2[r * S] * x2) / dd[r * S];
+        x[r * S] = v;
+        x2 = x1;
+        x1 = v;
+      }
       // orthogonalise against the previous members of the cluster (twice)
       for (int pass = 0; pass < 2; ++pass)
         for (int q = i0; q < i; ++q) {
           const double* yq = y.re + (int64_t)q * y.ld;
           double dt = 0;
-          for (int64_t r = 0; r < n; ++r) dt += yq[r] * x[r];
-          for (int64_t r = 0; r < n; ++r) x[r] -= dt * yq[r];
+          for (int64_t r = 0; r < n; ++r) dt += yq[r] * x[r * S];
+          for (int64_t r = 0; r < n; ++r) x[r * S] -= dt * yq[r];
         }
       double nrm = 0;
-      for (int64_t r = 0; r < n; ++r) nrm += x[r] * x[r];
+      for (int64_t r = 0; r < n; ++r) nrm += x[r * S] * x[r * S];
       nrm = sqrt(nrm);
       const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-      for (int64_t r = 0; r < n; ++r) x[r] *= inv;
+      for (int64_t r = 0; r < n; ++r) x[r * S] *= inv;
     }
     // sign convention: largest-magnitude component positive
     int64_t am = 0;
-    for (int64_t r = 1; r < n; ++r)
-      if (fabs(x[r]) > fabs(x[am])) am = r;
-    const double sg = x[am] < 0 ? -1.0 : 1.0;
+    double best = -1.0;
+    for (int64_t r = 0; r < n; ++r) {
+      const double a = fabs(x[r * S]);
+      if (a > best) {
+        best = a;
+        am = r;
+      }
+    }
+    const double sg = x[am * S] < 0 ? -1.0 : 1.0;
     double* yi = y.re + (int64_t)i * y.ld;
-    for (int64_t r = 0; r < n; ++r) yi[r] = sg * x[r];
+    for (int64_t r = 0; r < n; ++r) yi[r] = sg * x[r * S];
   }
 }
 
@@ -470,10 +526,11 @@ void inverse_iteration(hipStream_t s, const TriWork& w, int64_t n, int batch, co
                        const int* num, const int* clus, int64_t ld_lam, DMat<double> Y,
                        DevBuf& scratch) {
   if (ld_lam <= 0) return;
-  scratch.alloc(sizeof(double) * 6 * n * ld_lam * (int64_t)batch);
+  const int64_t S = ld_lam * (int64_t)batch;  // interleaving stride (slots)
+  scratch.alloc(sizeof(double) * 6 * n * S);
   dim3 g(grid1(ld_lam, 64), batch);
   k_invit<<<g, 64, 0, s>>>(w.d.as<double>(), w.e.as<double>(), n, lam, num, clus, ld_lam, Y,
-                           scratch.as<double>());
+                           scratch.as<double>(), S);
   RFD_CHECK_LAUNCH();
 }
 

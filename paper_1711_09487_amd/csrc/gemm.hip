@@ -86,7 +86,8 @@ struct Slab {
 template <typename T, bool CPLX, bool TA, bool TB, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T alpha, T beta,
                                               DMat<T> A, DMat<T> B, DMat<T> C, int splits,
-                                              int64_t kchunk, T* part, int vec_a, int vec_b) {
+                                              int64_t kchunk, T* part, int vec_a, int vec_b,
+                                              int tri) {
   constexpr int NP = CPLX ? 2 : 1;
   constexpr int VW = 16 / (int)sizeof(T);
   constexpr int PA = BM + VW, PB = BN + VW;
@@ -97,6 +98,7 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][GBK][PB];
 
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  if (tri && n0 >= m0 + BM) return;  // strictly upper tile, not wanted
   const int batch = (int)gridDim.z / splits;
   const int b = (int)blockIdx.z / splits, sk = (int)blockIdx.z - b * splits;
   A = A.item(b);
@@ -269,13 +271,14 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
 // C_b = sum over splits of the partial tiles (alpha applied) + beta C_b.
 template <typename T, bool CPLX>
 __global__ void k_splitk_sum(int64_t M, int64_t N, int splits, int batch, const T* part, T beta,
-                             DMat<T> C) {
+                             DMat<T> C, int tri) {
   constexpr int NP = CPLX ? 2 : 1;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M * N) return;
   const int b = blockIdx.y;
   C = C.item(b);
   const int64_t i = e % M, j = e / M;
+  if (tri && j > i) return;
   const int64_t plane = M * N;
   T sr = 0, si = 0;
   for (int s = 0; s < splits; ++s) {
@@ -311,10 +314,10 @@ static void* splitk_workspace(hipStream_t s, size_t bytes) {
 template <typename T, bool CPLX, int BM, int BN>
 static void launch(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N, int64_t K,
                    T alpha, T beta, DMat<T> A, DMat<T> B, DMat<T> C, int splits, int64_t kchunk,
-                   T* part, int va, int vb) {
+                   T* part, int va, int vb, int tri) {
 #define RFD_GEMM_GO(TA_, TB_)                                                               \
   k_gemm<T, CPLX, TA_, TB_, BM, BN><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C, splits, \
-                                                     kchunk, part, va, vb)
+                                                     kchunk, part, va, vb, tri)
   if (!ta && !tb) RFD_GEMM_GO(false, false);
   else if (ta && !tb) RFD_GEMM_GO(true, false);
   else if (!ta && tb) RFD_GEMM_GO(false, true);
@@ -329,15 +332,17 @@ static bool aligned16(const DMat<T>& X, int vw) {
 }
 
 template <typename T>
-void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, DMat<T> A,
-          DMat<T> B, T beta, DMat<T> C, int batch) {
+static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha,
+                      DMat<T> A, DMat<T> B, T beta, DMat<T> C, int batch, int tri) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   const bool cplx = C.cplx();
   const int NP = cplx ? 2 : 1;
   constexpr int VW = 16 / (int)sizeof(T);
   // tile: 128 x 128 when the product is large enough to fill the chip with it
   // (not for FP64 complex, whose accumulators would not fit)
-  const bool big_ok = !(sizeof(T) == 8 && cplx) && M >= 128 && N >= 128;
+  // (and only over a long K: with a few K slabs the single wave per SIMD of
+  // the large tile cannot hide its prologue and epilogue)
+  const bool big_ok = !(sizeof(T) == 8 && cplx) && M >= 128 && N >= 128 && K >= 256;
   const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128) * batch;
   const int bt = (big_ok && t128 >= 240) ? 128 : 64;
   const int64_t gm = (M + bt - 1) / bt, gn = (N + bt - 1) / bt;
@@ -363,27 +368,44 @@ void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T al
   const int va = aligned16(A, VW), vb = aligned16(B, VW);
   dim3 g((unsigned)gm, (unsigned)gn, (unsigned)(batch * splits));
   const int key = (sizeof(T) == 8 ? 8 : 0) + (cplx ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
-  const double flops = (cplx ? 8.0 : 2.0) * (double)M * (double)N * (double)K * batch;
+  // a lower-triangle product counts the N (N + 1) / 2 entries it must produce
+  const double outs = tri ? 0.5 * (double)N * (double)(N + 1) : (double)M * (double)N;
+  const double flops = (cplx ? 8.0 : 2.0) * outs * (double)K * batch;
   KernelAccount::Scope acct(s, key, flops);
   if (cplx) {
-    if (bt == 128) launch<T, true, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb);
-    else launch<T, true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb);
+    if (bt == 128) launch<T, true, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
+    else launch<T, true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
   } else {
-    if (bt == 128) launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb);
-    else launch<T, false, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb);
+    if (bt == 128) launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
+    else launch<T, false, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
   }
   RFD_CHECK_LAUNCH();
   if (splits > 1) {
     dim3 gr(grid1(M * N), (unsigned)batch);
-    if (cplx) k_splitk_sum<T, true><<<gr, 256, 0, s>>>(M, N, splits, batch, part, beta, C);
-    else k_splitk_sum<T, false><<<gr, 256, 0, s>>>(M, N, splits, batch, part, beta, C);
+    if (cplx) k_splitk_sum<T, true><<<gr, 256, 0, s>>>(M, N, splits, batch, part, beta, C, tri);
+    else k_splitk_sum<T, false><<<gr, 256, 0, s>>>(M, N, splits, batch, part, beta, C, tri);
     RFD_CHECK_LAUNCH();
   }
 }
 
-template void gemm<float>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, float, DMat<float>,
-                          DMat<float>, float, DMat<float>, int);
-template void gemm<double>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, double, DMat<double>,
-                           DMat<double>, double, DMat<double>, int);
+template <typename T>
+void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, DMat<T> A,
+          DMat<T> B, T beta, DMat<T> C, int batch) {
+  gemm_impl<T>(s, ta, tb, M, N, K, alpha, A, B, beta, C, batch, 0);
+}
+
+template <typename T>
+void gemm_lower(hipStream_t s, bool ta, bool tb, int64_t N, int64_t K, T alpha, DMat<T> A,
+                DMat<T> B, T beta, DMat<T> C, int batch) {
+  gemm_impl<T>(s, ta, tb, N, N, K, alpha, A, B, beta, C, batch, 1);
+}
+
+#define RFD_GEMM_INST(T)                                                                        \
+  template void gemm<T>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, T, DMat<T>, DMat<T>, \
+                        T, DMat<T>, int);                                                        \
+  template void gemm_lower<T>(hipStream_t, bool, bool, int64_t, int64_t, T, DMat<T>, DMat<T>, T, \
+                              DMat<T>, int);
+RFD_GEMM_INST(float)
+RFD_GEMM_INST(double)
 
 }  // namespace rfd

@@ -228,14 +228,13 @@ __global__ void k_gather_cols(const double* X, int64_t ldx, double* Y, int64_t l
   Y[i + c * ldy] = X[i + (int64_t)piv[c] * ldx];
 }
 
-__global__ void k_symmetrize(double* H, int64_t ld, int64_t k) {
+// H[j, i] = H[i, j] for i > j (the upper triangle mirrors the lower one)
+__global__ void k_mirror_lower(double* H, int64_t ld, int64_t k) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= k * k) return;
   const int64_t i = e % k, j = e / k;
   if (i <= j) return;
-  const double v = 0.5 * (H[i + j * ld] + H[j + i * ld]);
-  H[i + j * ld] = v;
-  H[j + i * ld] = v;
+  H[j + i * ld] = H[i + j * ld];
 }
 
 // X[order[i], c] = Xr[i, c]
@@ -492,7 +491,9 @@ int EngineImpl::gram_orth(hipStream_t st, const double* B, int ncol, double* MB,
   DMat<double> Gm{G, nullptr, np, 0}, Uim{Ui, nullptr, np, 0}, Gim{Gi, nullptr, NB, 0};
   DMat<double> Bm{const_cast<double*>(B), nullptr, n, 0}, MBm{MB, nullptr, n, 0};
   fill<double>(st, Gm, np, np, 1, 0.0);
-  gemm<double>(st, true, false, ncol, ncol, n, 1.0, Bm, MBm, 0.0, Gm, 1);
+  gemm_lower<double>(st, true, false, ncol, n, 1.0, Bm, MBm, 0.0, Gm, 1);
+  k_mirror_lower<<<grid1((int64_t)ncol * ncol), 256, 0, st>>>(G, np, ncol);
+  RFD_CHECK_LAUNCH();
   pad_identity<double>(st, Gm, ncol, np, 1);
   RFD_HIP(hipMemsetAsync(drop, 0, sizeof(int) * np, st));
   lu_nopiv<double>(st, Gm, np, 1, Gim, flags.as<unsigned>(), 0.0, drop, droptol);
@@ -724,8 +725,8 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   Hb.alloc(sizeof(double) * k * k);
   csr_mm(st, e.Arptr, e.Aridx, e.Arval, n, Z, n, AZ.as<double>(), n, k);
   DMat<double> Zm{Z, nullptr, n, 0}, AZm{AZ.as<double>(), nullptr, n, 0}, Hm{Hb.as<double>(), nullptr, k, 0};
-  gemm<double>(st, true, false, k, k, n, 1.0, Zm, AZm, 0.0, Hm, 1);
-  k_symmetrize<<<grid1(k * k), 256, 0, st>>>(Hb.as<double>(), k, k);
+  gemm_lower<double>(st, true, false, k, n, 1.0, Zm, AZm, 0.0, Hm, 1);
+  k_mirror_lower<<<grid1(k * k), 256, 0, st>>>(Hb.as<double>(), k, k);
   RFD_CHECK_LAUNCH();
   e.timer.end(st);
   // eigenpairs of H in [alpha, beta]
