@@ -28,12 +28,12 @@ FP64_PEAK = 78.6         # TFLOP/s, dense FP64 (matrix and vector)
 HBM_PEAK = 8000.0        # GB/s
 
 
-def make_pencil(R, prob, mode):
+def make_pencil(R, prob, mode, refine_tol=0.0):
     P = R.Pencil(prob.A, prob.M)
     P.set_partition(prob.part)
     P.set_interval_and_poles(prob.alpha, prob.beta, prob.n_c,
                              R.RFD_RULE_GAUSS if prob.rule == "gauss" else R.RFD_RULE_MIDPOINT)
-    P.set_precision(R.RFD_FP32_REFINE if mode == "fp32" else R.RFD_FP64)
+    P.set_precision(R.RFD_FP32_REFINE if mode == "fp32" else R.RFD_FP64, refine_tol)
     return P
 
 
@@ -45,8 +45,8 @@ def one_step(P, prob, Y0, torch):
     return ev, r, k
 
 
-def run_mode(R, prob, mode, steps, warmup, ref, torch):
-    P = make_pencil(R, prob, mode)
+def run_mode(R, prob, mode, steps, warmup, ref, torch, refine_tol=0.0):
+    P = make_pencil(R, prob, mode, refine_tol)
     Y0 = torch.from_numpy(np.ascontiguousarray(prob.Y0.T)).cuda()
     for _ in range(warmup):
         one_step(P, prob, Y0, torch)
@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="both", choices=["fp32", "fp64", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--refine-tol", type=float, default=0.0,
+                    help="FP32 refinement stopping tolerance (0: library default)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X "
@@ -160,11 +162,12 @@ def main():
     modes = ["fp32", "fp64"] if a.mode == "both" else [a.mode]
     res = {}
     for mode in modes:
-        res[mode] = run_mode(R, prob, mode, a.steps, a.warmup, ref, torch)
+        res[mode] = run_mode(R, prob, mode, a.steps, a.warmup, ref, torch, a.refine_tol)
         r = res[mode]
         print(f"# {mode}: {1e3 * r['total'] / a.steps:.1f} ms/step, max rel err "
               f"{max(r['errs']):.2e}, good {min(r['good'])}/{prob.nev}, phases(ms) "
-              f"{np.round(r['phases'][:12], 2).tolist()}", file=sys.stderr, flush=True)
+              f"{np.round(r['phases'][:12], 2).tolist()} sweeps {r['phases'][12:14].tolist()}",
+              file=sys.stderr, flush=True)
     head = res["fp32"] if "fp32" in res else res[modes[0]]
     ms = 1e3 * head["total"] / a.steps
     lat = np.array(head["lat"]) * 1e3

@@ -13,6 +13,8 @@
  *                               to a block (block Krylov)               Sec. 3.1 eq. (3.5), Alg. 3.1
  *   rfd_solve_interior          V_j, Sigma_j, Gamma_j and Z             Sec. 4, Sec. 5.1 eqs. (5.2)-(5.5)
  *   rfd_rayleigh_ritz           Ritz pairs in [alpha, beta]             Alg. 5.1 steps 6-8
+ *   rfd_batch_run               many independent solves at once (whole Alg. 5.1 each)
+ *   rfd_server_*                continuous serving of solve requests
  *
  * Conventions (all entry points):
  *  - Every call returns an rfd_status; RFD_OK is 0.  No exception crosses the
@@ -48,7 +50,8 @@ typedef enum {
   RFD_EBREAKDOWN = 3,  /* a pivot below the breakdown threshold (singular)  */
   RFD_ENOCONV = 4,     /* iterative refinement did not reach its tolerance  */
   RFD_EDEVICE = 5,     /* a HIP runtime error                               */
-  RFD_ESTATE = 6       /* call out of order (e.g. filter before partition)  */
+  RFD_ESTATE = 6,      /* call out of order (e.g. filter before partition)  */
+  RFD_EPENDING = 7     /* a served request has not finished yet             */
 } rfd_status;
 
 enum { RFD_RULE_GAUSS = 0, RFD_RULE_MIDPOINT = 1, RFD_RULE_EXPLICIT = 2 };
@@ -229,6 +232,95 @@ rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16);
  */
 rfd_status rfd_kernel_accounting(int32_t on);
 rfd_status rfd_kernel_stats(double* launches, double* ms, double* flops);
+
+/*
+ * ---------------------------------------------------------------------------
+ * Batching and serving.  A job is one complete solve (Alg. 5.1: poles and
+ * weights of Sec. 2.1, the interface filter of Sec. 3 with `steps` block-
+ * Krylov steps, the interior part of Sec. 4 and the Rayleigh-Ritz step) on a
+ * pencil whose partition is set.  Jobs run on a pool of worker threads, each
+ * with its own HIP stream, so the kernels of independent jobs overlap on the
+ * device.  A job is admitted when its estimated device footprint fits the
+ * memory budget next to the jobs already running and the caches that idle
+ * pencils hold (idle pencils' caches are released, least recently used
+ * first, to make room); a job larger than the whole budget runs alone.
+ * Jobs on one pencil run one at a time, in submission order; the pencil's
+ * interval, poles and precision are set from the job, and its per-pencil
+ * state (maps, reordered matrices, and the interior basis and B_sigma
+ * factors while sigma and nev_b repeat) stays on the device between jobs.
+ * While a job on a pencil is queued or running, the caller must not use
+ * that pencil handle directly.
+ * ---------------------------------------------------------------------------
+ */
+typedef struct rfd_job {
+  double alpha, beta;   /* interval, alpha < beta                                  */
+  int32_t n_c;          /* poles in the upper half plane                           */
+  int32_t rule;         /* RFD_RULE_GAUSS or RFD_RULE_MIDPOINT                     */
+  int32_t mode;         /* RFD_FP64 or RFD_FP32_REFINE                             */
+  int32_t max_sweeps;   /* refinement sweeps (<= 0: default)                       */
+  double refine_tol;    /* refinement tolerance (<= 0: default)                    */
+  int32_t m, steps;     /* interface block width and block-Krylov steps            */
+  const double* Y0;     /* device, s x m column-major starting block               */
+  double sigma;         /* interior shift (Sec. 4)                                 */
+  int32_t nev_b, psi;   /* interior eigenvectors per subdomain, resolvent levels   */
+  int32_t max_out;      /* capacity of the outputs                                 */
+  double* evals;        /* device, max_out: Ritz values in [alpha, beta], ascending */
+  double* evecs;        /* device, n x max_out (original numbering) or NULL        */
+  double* resid;        /* device, max_out relative residuals or NULL              */
+} rfd_job;
+
+typedef struct rfd_result {
+  int32_t status;       /* rfd_status of the job                                   */
+  int32_t nfound;       /* Ritz values found in [alpha, beta]                      */
+  int32_t mu;           /* columns of the interface basis                          */
+  int32_t worker;       /* worker (stream) that ran the job                        */
+  int64_t k;            /* dimension of the projection subspace                    */
+  int64_t bytes;        /* device footprint admitted for the job                   */
+  double queued_s;      /* seconds from submission to admission                    */
+  double run_s;         /* seconds from admission to completion                    */
+  char message[160];    /* error message when status != RFD_OK                     */
+} rfd_result;
+
+/*
+ * rfd_batch_run -- runs the nb jobs (jobs[i] on pencils[i]; a pencil may
+ * appear several times) on `workers` worker streams (<= 0: 4) within a
+ * device memory budget of hbm_budget bytes (<= 0: 90% of the free device
+ * memory) and returns when all have finished; results[i] (host) receives
+ * each job's outcome.  Returns RFD_OK when every job succeeded, otherwise
+ * the status of the first failed job (the others still ran).  Errors:
+ * RFD_EINVAL for nb < 1 or null arrays.
+ */
+rfd_status rfd_batch_run(int32_t nb, const rfd_pencil_t* pencils, const rfd_job* jobs,
+                         rfd_result* results, int32_t workers, int64_t hbm_budget);
+
+typedef struct rfd_server_s* rfd_server_t;
+
+/*
+ * rfd_server_create -- a serving loop with `workers` worker streams (<= 0: 4)
+ * and a device memory budget (<= 0: 90% of the free device memory).
+ * rfd_server_submit queues a job (copied; Y0 and the outputs must stay valid
+ * until the job finishes) and returns its id in *request_id; requests are
+ * admitted as workers and memory free up, in submission order except that a
+ * request that fits may pass one that does not.  rfd_server_poll returns
+ * RFD_EPENDING while the request is queued or running (wait = 0), or blocks
+ * until it has finished (wait != 0); on completion *out receives the result
+ * and the id is retired (a second poll returns RFD_EINVAL).
+ * rfd_server_destroy finishes every submitted request, then stops the workers.
+ */
+rfd_status rfd_server_create(int32_t workers, int64_t hbm_budget, rfd_server_t* out);
+rfd_status rfd_server_submit(rfd_server_t server, rfd_pencil_t pencil, const rfd_job* job,
+                             int64_t* request_id);
+rfd_status rfd_server_poll(rfd_server_t server, int64_t request_id, int32_t wait,
+                           rfd_result* out);
+rfd_status rfd_server_destroy(rfd_server_t server);
+
+/*
+ * rfd_server_stats -- host snapshot: queued and running requests, bytes
+ * admitted to running requests, bytes held by idle pencils' caches, and the
+ * number of cache releases made for admission.
+ */
+rfd_status rfd_server_stats(rfd_server_t server, int32_t* queued, int32_t* running,
+                            int64_t* bytes_running, int64_t* bytes_cached, int64_t* evictions);
 
 #ifdef __cplusplus
 }

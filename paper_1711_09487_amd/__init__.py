@@ -13,23 +13,42 @@ import os
 import numpy as np
 
 __all__ = [
-    "RfdError", "lib", "Pencil", "RFD_FP64", "RFD_FP32_REFINE", "RFD_RULE_GAUSS",
-    "RFD_RULE_MIDPOINT", "RFD_RULE_EXPLICIT", "LIB_PATH",
+    "RfdError", "lib", "Pencil", "Job", "Server", "batch_run", "RFD_FP64", "RFD_FP32_REFINE",
+    "RFD_RULE_GAUSS", "RFD_RULE_MIDPOINT", "RFD_RULE_EXPLICIT", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfd.so")
 RFD_FP64, RFD_FP32_REFINE = 0, 1
 RFD_RULE_GAUSS, RFD_RULE_MIDPOINT, RFD_RULE_EXPLICIT = 0, 1, 2
 STATUS = {0: "RFD_OK", 1: "RFD_EINVAL", 2: "RFD_ENOMEM", 3: "RFD_EBREAKDOWN",
-          4: "RFD_ENOCONV", 5: "RFD_EDEVICE", 6: "RFD_ESTATE"}
+          4: "RFD_ENOCONV", 5: "RFD_EDEVICE", 6: "RFD_ESTATE", 7: "RFD_EPENDING"}
+RFD_EPENDING = 7
 
 EXPORTS = [
     "rfd_create_pencil", "rfd_set_partition", "rfd_set_interval_and_poles",
     "rfd_set_precision", "rfd_filter_interface", "rfd_filter_apply", "rfd_solve_interior",
     "rfd_rayleigh_ritz",
     "rfd_destroy_pencil", "rfd_last_error", "rfd_pencil_info", "rfd_set_timing",
-    "rfd_phase_times", "rfd_reset_caches",
+    "rfd_phase_times", "rfd_reset_caches", "rfd_batch_run", "rfd_server_create",
+    "rfd_server_submit", "rfd_server_poll", "rfd_server_destroy", "rfd_server_stats",
 ]
+
+
+class rfd_job(C.Structure):
+    """Mirror of struct rfd_job (include/rfd.h)."""
+    _fields_ = [("alpha", C.c_double), ("beta", C.c_double), ("n_c", C.c_int32),
+                ("rule", C.c_int32), ("mode", C.c_int32), ("max_sweeps", C.c_int32),
+                ("refine_tol", C.c_double), ("m", C.c_int32), ("steps", C.c_int32),
+                ("Y0", C.c_void_p), ("sigma", C.c_double), ("nev_b", C.c_int32),
+                ("psi", C.c_int32), ("max_out", C.c_int32), ("evals", C.c_void_p),
+                ("evecs", C.c_void_p), ("resid", C.c_void_p)]
+
+
+class rfd_result(C.Structure):
+    """Mirror of struct rfd_result (include/rfd.h)."""
+    _fields_ = [("status", C.c_int32), ("nfound", C.c_int32), ("mu", C.c_int32),
+                ("worker", C.c_int32), ("k", C.c_int64), ("bytes", C.c_int64),
+                ("queued_s", C.c_double), ("run_s", C.c_double), ("message", C.c_char * 160)]
 
 
 class RfdError(RuntimeError):
@@ -74,6 +93,13 @@ def lib():
             "rfd_test_lu": [I32, I32, I64, I32, P, P, I64, I64, P, P, I64, I64, I64,
                             C.POINTER(C.c_uint32), P],
             "rfd_test_syevx": [I64, I32, P, I32, I32, P, P, P],
+            "rfd_batch_run": [I32, P, C.POINTER(rfd_job), C.POINTER(rfd_result), I32, I64],
+            "rfd_server_create": [I32, I64, C.POINTER(P)],
+            "rfd_server_submit": [P, P, C.POINTER(rfd_job), C.POINTER(I64)],
+            "rfd_server_poll": [P, I64, I32, C.POINTER(rfd_result)],
+            "rfd_server_destroy": [P],
+            "rfd_server_stats": [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I64),
+                                 C.POINTER(I64), C.POINTER(I64)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -289,3 +315,110 @@ class Pencil:
 
     def info(self):
         return rfd_pencil_info(self.h)
+
+
+# ---------------------------------------------------------------------------
+# batching and serving
+# ---------------------------------------------------------------------------
+class Job:
+    """One complete solve on a pencil (fields of struct rfd_job).  Y0 is a
+    device tensor of shape (m, s) (s x m column-major); the outputs are
+    allocated here on the device (evals, eigenvectors as (max_out, n),
+    residuals) and stay referenced by the Job until it is collected."""
+
+    def __init__(self, pencil, alpha, beta, n_c, Y0, steps, sigma, nev_b, psi, max_out,
+                 mode=RFD_FP64, rule=RFD_RULE_GAUSS, refine_tol=0.0, max_sweeps=0,
+                 vectors=True, residuals=True):
+        import torch
+        self.pencil = pencil
+        self.Y0 = Y0
+        m = Y0.shape[0]
+        dev = Y0.device
+        self.evals = torch.empty(max(max_out, 1), dtype=torch.float64, device=dev)
+        self.evecs = (torch.empty((max(max_out, 1), pencil.n), dtype=torch.float64, device=dev)
+                      if vectors else None)
+        self.resid = torch.empty(max(max_out, 1), dtype=torch.float64, device=dev) if residuals else None
+        self.c = rfd_job(float(alpha), float(beta), int(n_c), int(rule), int(mode),
+                         int(max_sweeps), float(refine_tol), int(m), int(steps), _ptr(Y0),
+                         float(sigma), int(nev_b), int(psi), int(max_out), _ptr(self.evals),
+                         _ptr(self.evecs), _ptr(self.resid))
+        self.result = None
+
+    def outputs(self):
+        """(evals, eigenvectors, residuals) of a finished job, trimmed to nfound."""
+        nf = self.result.nfound if self.result is not None else 0
+        return (self.evals[:nf], None if self.evecs is None else self.evecs[:nf],
+                None if self.resid is None else self.resid[:nf])
+
+
+def _result_dict(r):
+    return dict(status=r.status, nfound=r.nfound, mu=r.mu, worker=r.worker, k=r.k,
+                bytes=r.bytes, queued_s=r.queued_s, run_s=r.run_s, message=r.message.decode())
+
+
+def rfd_batch_run(jobs, workers=0, hbm_budget=0):
+    """Runs the Job objects concurrently (rfd_batch_run); sets job.result and
+    returns the status code (0 when every job succeeded)."""
+    nb = len(jobs)
+    pens = (P * nb)(*[j.pencil.h for j in jobs])
+    cj = (rfd_job * nb)(*[j.c for j in jobs])
+    res = (rfd_result * nb)()
+    code = lib().rfd_batch_run(nb, pens, cj, res, int(workers), int(hbm_budget))
+    for j, r in zip(jobs, res):
+        j.result = r
+    return code
+
+
+def batch_run(jobs, workers=0, hbm_budget=0):
+    """As rfd_batch_run, raising if a job failed; returns the result dicts."""
+    code = rfd_batch_run(jobs, workers, hbm_budget)
+    out = [_result_dict(j.result) for j in jobs]
+    if code != 0:
+        bad = [o for o in out if o["status"] != 0]
+        raise RfdError(code, f"{len(bad)} job(s) failed; first: {bad[0]['message'] if bad else ''}")
+    return out
+
+
+class Server:
+    """Serving loop (rfd_server_*): submit Jobs, poll for results."""
+
+    def __init__(self, workers=0, hbm_budget=0):
+        self.h = P()
+        _check(lib().rfd_server_create(int(workers), int(hbm_budget), C.byref(self.h)))
+        self.jobs = {}
+
+    def submit(self, job):
+        rid = I64()
+        _check(lib().rfd_server_submit(self.h, job.pencil.h, C.byref(job.c), C.byref(rid)))
+        self.jobs[rid.value] = job
+        return rid.value
+
+    def poll(self, rid, wait=False):
+        """The result dict when finished, None while pending."""
+        r = rfd_result()
+        code = lib().rfd_server_poll(self.h, int(rid), int(bool(wait)), C.byref(r))
+        if code == RFD_EPENDING:
+            return None
+        _check(code)
+        job = self.jobs.pop(rid)
+        job.result = r
+        return _result_dict(r)
+
+    def stats(self):
+        q, rn = I32(), I32()
+        br, bc, ev = I64(), I64(), I64()
+        _check(lib().rfd_server_stats(self.h, C.byref(q), C.byref(rn), C.byref(br), C.byref(bc),
+                                      C.byref(ev)))
+        return dict(queued=q.value, running=rn.value, bytes_running=br.value,
+                    bytes_cached=bc.value, evictions=ev.value)
+
+    def close(self):
+        if self.h is not None and self.h.value is not None:
+            _check(lib().rfd_server_destroy(self.h))
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,6 +7,7 @@
 #include "engine.hpp"
 #include "pencil.hpp"
 #include "dense.hpp"
+#include "executor.hpp"
 #include "rfd_capi_util.hpp"
 
 namespace rfd {
@@ -38,6 +39,18 @@ static Engine& need_engine(rfd_pencil_s* p) {
   if (!p->part || !p->eng) throw Error(ST_ESTATE, "rfd_set_partition has not been called");
   return *p->eng;
 }
+
+namespace rfd {
+int64_t pencil_estimate(rfd_pencil_t p, const rfd_job& j) {
+  Engine& E = need_engine(need(p));
+  return E.estimate_bytes(j.mode, j.n_c, j.m, j.steps, j.nev_b, j.psi);
+}
+int64_t pencil_held(rfd_pencil_t p) { return p && p->eng ? p->eng->device_bytes() : 0; }
+void pencil_release(rfd_pencil_t p) {
+  if (p && p->eng) p->eng->reset_caches(true);
+}
+void pencil_check(rfd_pencil_t p) { (void)need_engine(need(p)); }
+}  // namespace rfd
 
 extern "C" {
 
@@ -210,6 +223,76 @@ rfd_status rfd_kernel_stats(double* launches, double* ms, double* flops) {
   return (rfd_status)capi_guard([&] {
     if (!launches || !ms || !flops) throw Error(ST_EINVAL, "null output");
     KernelAccount::get().collect(launches, ms, flops, 16);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Batching and serving (executor.cpp)
+// ---------------------------------------------------------------------------
+struct rfd_server_s {
+  std::unique_ptr<Executor> ex;
+};
+
+rfd_status rfd_batch_run(int32_t nb, const rfd_pencil_t* pencils, const rfd_job* jobs,
+                         rfd_result* results, int32_t workers, int64_t hbm_budget) {
+  rfd_status first = RFD_OK;
+  rfd_status st = (rfd_status)capi_guard([&] {
+    if (nb < 1 || !pencils || !jobs || !results) throw Error(ST_EINVAL, "need nb >= 1 and arrays");
+    for (int32_t i = 0; i < nb; ++i) {
+      if (!pencils[i]) throw Error(ST_EINVAL, "null pencil in the batch");
+      pencil_check(pencils[i]);
+    }
+    Executor ex(workers, hbm_budget);
+    std::vector<int64_t> ids((size_t)nb);
+    for (int32_t i = 0; i < nb; ++i) ids[i] = ex.submit(pencils[i], jobs[i]);
+    for (int32_t i = 0; i < nb; ++i) {
+      ex.poll(ids[i], true, &results[i]);
+      if (results[i].status != RFD_OK && first == RFD_OK) first = (rfd_status)results[i].status;
+    }
+  });
+  if (st != RFD_OK) return st;
+  if (first != RFD_OK) last_error_slot() = "a job of the batch failed (see its result)";
+  return first;
+}
+
+rfd_status rfd_server_create(int32_t workers, int64_t hbm_budget, rfd_server_t* out) {
+  return (rfd_status)capi_guard([&] {
+    if (!out) throw Error(ST_EINVAL, "null output handle");
+    *out = nullptr;
+    auto s = std::make_unique<rfd_server_s>();
+    s->ex = std::make_unique<Executor>(workers, hbm_budget);
+    *out = s.release();
+  });
+}
+
+rfd_status rfd_server_submit(rfd_server_t server, rfd_pencil_t pencil, const rfd_job* job,
+                             int64_t* request_id) {
+  return (rfd_status)capi_guard([&] {
+    if (!server || !job || !request_id) throw Error(ST_EINVAL, "null argument");
+    *request_id = server->ex->submit(pencil, *job);
+  });
+}
+
+rfd_status rfd_server_poll(rfd_server_t server, int64_t request_id, int32_t wait,
+                           rfd_result* out) {
+  int done = 0;
+  rfd_status st = (rfd_status)capi_guard([&] {
+    if (!server) throw Error(ST_EINVAL, "null server");
+    done = server->ex->poll(request_id, wait != 0, out);
+  });
+  if (st != RFD_OK) return st;
+  return done ? RFD_OK : RFD_EPENDING;
+}
+
+rfd_status rfd_server_destroy(rfd_server_t server) {
+  return (rfd_status)capi_guard([&] { delete server; });
+}
+
+rfd_status rfd_server_stats(rfd_server_t server, int32_t* queued, int32_t* running,
+                            int64_t* bytes_running, int64_t* bytes_cached, int64_t* evictions) {
+  return (rfd_status)capi_guard([&] {
+    if (!server) throw Error(ST_EINVAL, "null server");
+    server->ex->stats(queued, running, bytes_running, bytes_cached, evictions);
   });
 }
 

@@ -22,11 +22,14 @@ KernelAccount& KernelAccount::get() {
 KernelAccount::Scope::Scope(hipStream_t s, int key, double flops) : s_(s) {
   KernelAccount& a = get();
   if (!a.enabled) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   Rec r;
   r.key = key;
   r.flops = flops;
   if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
   (void)hipEventRecord(r.a, s);
+  std::lock_guard<std::mutex> g(a.mu);
   rec_ = (int)a.recs.size();
   a.recs.push_back(r);
 }
@@ -34,10 +37,12 @@ KernelAccount::Scope::Scope(hipStream_t s, int key, double flops) : s_(s) {
 KernelAccount::Scope::~Scope() {
   if (rec_ < 0) return;
   KernelAccount& a = get();
-  (void)hipEventRecord(a.recs[rec_].b, s_);
+  std::lock_guard<std::mutex> g(a.mu);
+  if (rec_ < (int)a.recs.size()) (void)hipEventRecord(a.recs[rec_].b, s_);
 }
 
 void KernelAccount::collect(double* launches, double* ms, double* flops, int nkeys) {
+  std::lock_guard<std::mutex> g(mu);
   for (int k = 0; k < nkeys; ++k) launches[k] = ms[k] = flops[k] = 0;
   for (auto& r : recs) {
     float t = 0;

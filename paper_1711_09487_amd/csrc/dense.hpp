@@ -4,6 +4,8 @@
 // (DMat) of uniform size; complex data is planar.
 #pragma once
 
+#include <mutex>
+
 #include "rfd_common.hpp"
 
 namespace rfd {
@@ -18,6 +20,7 @@ struct KernelAccount {
     hipEvent_t a, b;
   };
   bool enabled = false;
+  std::mutex mu;
   std::vector<Rec> recs;
   static KernelAccount& get();
   void collect(double* launches, double* ms, double* flops, int nkeys);

@@ -92,6 +92,7 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
   if (c >= 1) {
     const double tp = tauv[(int64_t)b * n + j - 1];
     double xy = 0;
+#pragma unroll 8
     for (int q = 0; q < c - 1; ++q) xy += xs[q] * ys[q];
     const double al = -0.5 * tp * tp * (rd[0] - 2.0 * xy);
     if (t == 0) {
@@ -101,6 +102,7 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
     }
     if (act) {
       double acc = p[r];
+#pragma unroll 8
       for (int q = 0; q < c - 1; ++q) acc -= V[r + q * n] * xs[q] + W[r + q * n] * ys[q];
       wr = tp * acc + al * V[r + (int64_t)(c - 1) * n];
       W[r + (int64_t)(c - 1) * n] = wr;
@@ -111,6 +113,7 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
   double ar = 0.0;
   if (act) {
     ar = a.re[r + j * a.ld];
+#pragma unroll 8
     for (int q = 0; q < c; ++q) {
       const double wq = (q == c - 1) ? wr : W[r + q * n];
       ar -= V[r + q * n] * Wj[q] + wq * Vj[q];
@@ -139,6 +142,7 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     const int nsq = (int)((n - j + 255) / 256);
     const double* s = sq + (int64_t)b * ((n + 255) / 256);
     double s2 = 0;
+#pragma unroll 8
     for (int i = 0; i < nsq; ++i) s2 += s[i];
     const double alpha = ac[j + 1];
     double tau = 0, beta = alpha, scale = 0;
@@ -223,6 +227,7 @@ __global__ __launch_bounds__(256) void k_tri_dots(int64_t n, int64_t j, int c, c
   const double* x = g == 0 ? pv + (int64_t)b * n : (g <= c ? W + (int64_t)(g - 1) * n
                                                            : V + (int64_t)(g - 1 - c) * n);
   double s = 0;
+#pragma unroll 8
   for (int64_t r = j + 1 + t; r < n; r += 256) s += x[r] * v[r];
   s = block_sum256(s, rs);
   if (t == 0) {
@@ -246,9 +251,7 @@ __global__ void k_tri_fin(DMat<double> A, int64_t n, double* dv, double* ev) {
   }
 }
 
-void sy_tridiag(hipStream_t s, DMat<double> A, int64_t n, int batch, TriWork& w) {
-  if (n <= 0 || batch <= 0) return;
-  w.reserve(n, batch);
+static void tridiag_launches(hipStream_t s, DMat<double> A, int64_t n, int batch, TriWork& w) {
   double* vw = w.vw.as<double>();
   const bool vec = A.ld % 2 == 0 && A.bs % 2 == 0 && ((uintptr_t)A.re & 15u) == 0;
   const int64_t nred = n - 2;  // columns that get a reflector
@@ -291,6 +294,12 @@ void sy_tridiag(hipStream_t s, DMat<double> A, int64_t n, int batch, TriWork& w)
   }
   k_tri_fin<<<batch, 64, 0, s>>>(A, n, w.d.as<double>(), w.e.as<double>());
   RFD_CHECK_LAUNCH();
+}
+
+void sy_tridiag(hipStream_t s, DMat<double> A, int64_t n, int batch, TriWork& w) {
+  if (n <= 0 || batch <= 0) return;
+  w.reserve(n, batch);
+  tridiag_launches(s, A, n, batch, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,9 +414,12 @@ __device__ inline double hash_unit(uint64_t a, uint64_t b) {
 }
 
 // Scratch is interleaved over the threads (element r of slot g at r * S + g)
-// so that a wavefront's accesses at one step are contiguous; the elimination
-// and the substitutions carry their running values in registers.
-__global__ __launch_bounds__(64) void k_invit(const double* dv, const double* ev, int64_t n,
+// so that a wavefront's accesses at one step are contiguous.  The
+// elimination and the substitutions carry their running values in registers,
+// and every loop reads one array and writes another (two vector buffers used
+// in turn), so that loads can run ahead of the dependent arithmetic.
+__global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
+                                              const double* __restrict__ e0, int64_t n,
                                               const double* lam, const int* num, const int* clus,
                                               int64_t ld_lam, DMat<double> Y, double* scratch,
                                               int64_t S) {
@@ -415,17 +427,19 @@ __global__ __launch_bounds__(64) void k_invit(const double* dv, const double* ev
   const int b = blockIdx.y;
   if (i0 >= num[b] || i0 >= ld_lam) return;
   if (clus[(int64_t)b * ld_lam + i0] != i0) return;  // not a cluster head
-  const double* d = dv + (int64_t)b * n;
-  const double* e = ev + (int64_t)b * n;
+  const double* __restrict__ d = d0 + (int64_t)b * n;
+  const double* __restrict__ e = e0 + (int64_t)b * n;
   const int64_t g = (int64_t)b * ld_lam + i0;
-  double* dl = scratch + g;
-  double* dd = dl + n * S;
-  double* du = dd + n * S;
-  double* du2 = du + n * S;
-  double* x = du2 + n * S;
-  int* ip = reinterpret_cast<int*>(scratch + 5 * n * S) + g;
+  double* __restrict__ dl = scratch + g;
+  double* __restrict__ dd = scratch + n * S + g;
+  double* __restrict__ du = scratch + 2 * n * S + g;
+  double* __restrict__ du2 = scratch + 3 * n * S + g;
+  double* xa = scratch + 4 * n * S + g;
+  double* xb = scratch + 5 * n * S + g;
+  int* __restrict__ ip = reinterpret_cast<int*>(scratch + 6 * n * S) + g;
   DMat<double> y = Y.item(b);
   double tnorm = 0;
+#pragma unroll 8
   for (int64_t r = 0; r < n; ++r)
     tnorm = fmax(tnorm, fabs(d[r]) + (r > 0 ? fabs(e[r - 1]) : 0.0) + (r + 1 < n ? fabs(e[r]) : 0.0));
   const double pert = 10.0 * EPS * fmax(tnorm, 1e-300);
@@ -439,7 +453,7 @@ __global__ __launch_bounds__(64) void k_invit(const double* dv, const double* ev
     // LU with partial pivoting of T - lm I (as dgttrf); dcur / ucur are the
     // running diagonal and superdiagonal of the row being eliminated
     double dcur = d[0] - lm, ucur = n > 1 ? e[0] : 0.0;
-#pragma unroll 4
+#pragma unroll 8
     for (int64_t r = 0; r + 1 < n; ++r) {
       const double er = e[r];
       const double dn = d[r + 1] - lm;
@@ -465,60 +479,87 @@ __global__ __launch_bounds__(64) void k_invit(const double* dv, const double* ev
       }
     }
     dd[(n - 1) * S] = fix(dcur);
-    for (int64_t r = 0; r < n; ++r) x[r * S] = hash_unit((uint64_t)r + 1, (uint64_t)i + 7919ull * b);
+#pragma unroll 8
+    for (int64_t r = 0; r < n; ++r) xa[r * S] = hash_unit((uint64_t)r + 1, (uint64_t)i + 7919ull * b);
     for (int it = 0; it < 4; ++it) {
-      // L (with the row interchanges): running x[r] in xc
-      double xc = x[0];
-#pragma unroll 4
-      for (int64_t r = 0; r + 1 < n; ++r) {
-        const double xn = x[(r + 1) * S];
-        const double f = dl[r * S];
-        if (ip[r * S] == r) {
-          x[r * S] = xc;
-          xc = xn - f * xc;
-        } else {
-          x[r * S] = xn;
-          xc = xc - f * xn;
+      {  // L with the row interchanges: xa -> xb, running value in xc
+        const double* __restrict__ src = xa;
+        double* __restrict__ dst = xb;
+        double xc = src[0];
+#pragma unroll 8
+        for (int64_t r = 0; r + 1 < n; ++r) {
+          const double xn = src[(r + 1) * S];
+          const double f = dl[r * S];
+          if (ip[r * S] == r) {
+            dst[r * S] = xc;
+            xc = xn - f * xc;
+          } else {
+            dst[r * S] = xn;
+            xc = xc - f * xn;
+          }
+        }
+        dst[(n - 1) * S] = xc;
+      }
+      {  // U (two superdiagonals): xb -> xa, x1 = x[r + 1], x2 = x[r + 2]
+        const double* __restrict__ src = xb;
+        double* __restrict__ dst = xa;
+        double x1 = src[(n - 1) * S] / dd[(n - 1) * S], x2 = 0.0;
+        dst[(n - 1) * S] = x1;
+#pragma unroll 8
+        for (int64_t r = n - 2; r >= 0; --r) {
+          const double v = (src[r * S] - du[r * S] * x1 - du2[r * S] * x2) / dd[r * S];
+          dst[r * S] = v;
+          x2 = x1;
+          x1 = v;
         }
       }
-      x[(n - 1) * S] = xc;
-      // U (two superdiagonals): x1 = x[r + 1], x2 = x[r + 2]
-      double x1 = x[(n - 1) * S] / dd[(n - 1) * S], x2 = 0.0;
-      x[(n - 1) * S] = x1;
-#pragma unroll 4
-      for (int64_t r = n - 2; r >= 0; --r) {
-        const double v = (x[r * S] - du[r * S] * x1 - du2[r * S] * x2) / dd[r * S];
-        x[r * S] = v;
-        x2 = x1;
-        x1 = v;
-      }
-      // orthogonalise against the previous members of the cluster (twice)
+      // orthogonalise against the previous members of the cluster (twice);
+      // each pass moves the vector to the other buffer
       for (int pass = 0; pass < 2; ++pass)
         for (int q = i0; q < i; ++q) {
-          const double* yq = y.re + (int64_t)q * y.ld;
+          const double* __restrict__ yq = y.re + (int64_t)q * y.ld;
+          const double* __restrict__ src = xa;
+          double* __restrict__ dst = xb;
           double dt = 0;
-          for (int64_t r = 0; r < n; ++r) dt += yq[r] * x[r * S];
-          for (int64_t r = 0; r < n; ++r) x[r * S] -= dt * yq[r];
+#pragma unroll 8
+          for (int64_t r = 0; r < n; ++r) dt += yq[r] * src[r * S];
+#pragma unroll 8
+          for (int64_t r = 0; r < n; ++r) dst[r * S] = src[r * S] - dt * yq[r];
+          double* t = xa;
+          xa = xb;
+          xb = t;
         }
-      double nrm = 0;
-      for (int64_t r = 0; r < n; ++r) nrm += x[r * S] * x[r * S];
-      nrm = sqrt(nrm);
-      const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-      for (int64_t r = 0; r < n; ++r) x[r * S] *= inv;
+      {
+        const double* __restrict__ src = xa;
+        double* __restrict__ dst = xb;
+        double nrm = 0;
+#pragma unroll 8
+        for (int64_t r = 0; r < n; ++r) nrm += src[r * S] * src[r * S];
+        nrm = sqrt(nrm);
+        const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+#pragma unroll 8
+        for (int64_t r = 0; r < n; ++r) dst[r * S] = src[r * S] * inv;
+        double* t = xa;
+        xa = xb;
+        xb = t;
+      }
     }
     // sign convention: largest-magnitude component positive
+    const double* __restrict__ src = xa;
     int64_t am = 0;
     double best = -1.0;
+#pragma unroll 8
     for (int64_t r = 0; r < n; ++r) {
-      const double a = fabs(x[r * S]);
+      const double a = fabs(src[r * S]);
       if (a > best) {
         best = a;
         am = r;
       }
     }
-    const double sg = x[am * S] < 0 ? -1.0 : 1.0;
-    double* yi = y.re + (int64_t)i * y.ld;
-    for (int64_t r = 0; r < n; ++r) yi[r] = sg * x[r * S];
+    const double sg = src[am * S] < 0 ? -1.0 : 1.0;
+    double* __restrict__ yi = y.re + (int64_t)i * y.ld;
+#pragma unroll 8
+    for (int64_t r = 0; r < n; ++r) yi[r] = sg * src[r * S];
   }
 }
 
@@ -527,7 +568,7 @@ void inverse_iteration(hipStream_t s, const TriWork& w, int64_t n, int batch, co
                        DevBuf& scratch) {
   if (ld_lam <= 0) return;
   const int64_t S = ld_lam * (int64_t)batch;  // interleaving stride (slots)
-  scratch.alloc(sizeof(double) * 6 * n * S);
+  scratch.alloc(sizeof(double) * 7 * n * S);
   dim3 g(grid1(ld_lam, 64), batch);
   k_invit<<<g, 64, 0, s>>>(w.d.as<double>(), w.e.as<double>(), n, lam, num, clus, ld_lam, Y,
                            scratch.as<double>(), S);
@@ -535,134 +576,82 @@ void inverse_iteration(hipStream_t s, const TriWork& w, int64_t n, int batch, co
 }
 
 // ---------------------------------------------------------------------------
-// Back-transformation: one workgroup per column of Y.
+// Back-transformation.  Q = H_0 H_1 ... H_{n-3}; the reflectors of one panel
+// of TRI_NB are combined as I - V T V^T (T upper triangular, built column by
+// column from tau and the Gram matrix V^T V), and Y <- Q Y applies the panels
+// last to first as Y -= V (T (V^T Y)), three GEMMs per panel.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_backtr(DMat<double> A, const double* tauv, int64_t n,
-                                                DMat<double> Y, const int* num) {
-  __shared__ double red[8];
-  const int c = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
-  if (c >= num[b]) return;
+// V[r, q] (rows i0 + 1 .. n - 1 of the panel's reflectors, explicit unit
+// entry, zeros above it)
+__global__ void k_wy_v(DMat<double> A, int64_t n, int64_t i0, int nbp, double* V) {
+  const int b = blockIdx.y;
   DMat<double> a = A.item(b);
-  double* y = Y.item(b).re + (int64_t)c * Y.ld;
-  for (int64_t j = n - 3; j >= 0; --j) {
-    const double tau = tauv[(int64_t)b * n + j];
-    if (tau == 0.0) continue;
-    const double* v = a.re + j * a.ld;
-    double dt = 0;
-    for (int64_t r = j + 1 + t; r < n; r += blockDim.x) dt += ((r == j + 1) ? 1.0 : v[r]) * y[r];
-    dt = block_sum256(dt, red);
-    const double f = tau * dt;
-    for (int64_t r = j + 1 + t; r < n; r += blockDim.x) y[r] -= f * ((r == j + 1) ? 1.0 : v[r]);
-    __syncthreads();
-  }
+  const int64_t m = n - i0 - 1;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * TRI_NB) return;
+  const int64_t rr = e % m, q = e / m;
+  const int64_t r = i0 + 1 + rr, j = i0 + q;
+  double v = 0.0;
+  if (q < nbp) v = (r == j + 1) ? 1.0 : (r > j + 1 ? a.re[r + j * a.ld] : 0.0);
+  V[(int64_t)b * m * TRI_NB + rr + q * m] = v;
 }
 
-void back_transform(hipStream_t s, DMat<double> A, const TriWork& w, int64_t n, int batch,
+// T (TRI_NB x TRI_NB, upper) from tau and G = V^T V: T[k][k] = tau_k,
+// T[0:k, k] = -tau_k T[0:k, 0:k] G[0:k, k].  One workgroup per item.
+__global__ void k_wy_t(const double* G, const double* tauv, int64_t n, int64_t i0, int nbp,
+                       double* T) {
+  __shared__ double Ts[TRI_NB][TRI_NB + 1];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const double* g = G + (int64_t)b * TRI_NB * TRI_NB;
+  for (int e = t; e < TRI_NB * TRI_NB; e += blockDim.x) Ts[e % TRI_NB][e / TRI_NB] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < nbp; ++k) {
+    const double tk = tauv[(int64_t)b * n + i0 + k];
+    double v = 0.0;
+    if (t < k) {
+      for (int q = t; q < k; ++q) v += Ts[t][q] * g[q + k * TRI_NB];
+      v *= -tk;
+    }
+    __syncthreads();
+    if (t < k) Ts[t][k] = v;
+    if (t == k) Ts[k][k] = tk;
+    __syncthreads();
+  }
+  double* To = T + (int64_t)b * TRI_NB * TRI_NB;
+  for (int e = t; e < TRI_NB * TRI_NB; e += blockDim.x) To[e] = Ts[e % TRI_NB][e / TRI_NB];
+}
+
+void back_transform(hipStream_t s, DMat<double> A, TriWork& w, int64_t n, int batch,
                     DMat<double> Y, const int* num, int maxcols) {
-  if (maxcols <= 0) return;
-  dim3 g(maxcols, batch);
-  k_backtr<<<g, 256, 0, s>>>(A, w.tau.as<double>(), n, Y, num);
-  RFD_CHECK_LAUNCH();
-}
-
-// ---------------------------------------------------------------------------
-// Pivoted Cholesky (right-looking on the unselected index set, no physical
-// swaps) and the inverse of the pivot-ordered factor.  One workgroup.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_pchol(double* G, int64_t ldg, int64_t m, double tol,
-                                                int* piv, int* rank, double* Lp, double* Linv,
-                                                int64_t ldl, int* sel) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  __shared__ double d0;
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int64_t i = t; i < m; i += nt) sel[i] = -1;
-  double mx = 0;
-  for (int64_t i = t; i < m; i += nt) mx = fmax(mx, G[i + i * ldg]);
-  sv[t] = mx;
-  __syncthreads();
-  for (int w = nt / 2; w > 0; w >>= 1) {
-    if (t < w) sv[t] = fmax(sv[t], sv[t + w]);
-    __syncthreads();
+  (void)num;
+  if (maxcols <= 0 || n < 3) return;
+  const int64_t nred = n - 2;
+  DevBuf &Vb = w.wv, &Gb = w.wg, &Tb = w.wt, &W1 = w.w1, &W2 = w.w2;
+  Vb.alloc(sizeof(double) * (n - 1) * TRI_NB * batch);
+  Gb.alloc(sizeof(double) * TRI_NB * TRI_NB * batch);
+  Tb.alloc(sizeof(double) * TRI_NB * TRI_NB * batch);
+  W1.alloc(sizeof(double) * TRI_NB * maxcols * batch);
+  W2.alloc(sizeof(double) * TRI_NB * maxcols * batch);
+  const int64_t npan = (nred + TRI_NB - 1) / TRI_NB;
+  for (int64_t pi = npan - 1; pi >= 0; --pi) {
+    const int64_t i0 = pi * TRI_NB;
+    const int nbp = (int)std::min<int64_t>(TRI_NB, nred - i0);
+    const int64_t m = n - i0 - 1;
+    k_wy_v<<<dim3(grid1(m * TRI_NB), batch), 256, 0, s>>>(A, n, i0, nbp, Vb.as<double>());
+    RFD_CHECK_LAUNCH();
+    DMat<double> Vm{Vb.as<double>(), nullptr, m, m * TRI_NB};
+    DMat<double> Gm{Gb.as<double>(), nullptr, TRI_NB, TRI_NB * TRI_NB};
+    DMat<double> Tm{Tb.as<double>(), nullptr, TRI_NB, TRI_NB * TRI_NB};
+    DMat<double> W1m{W1.as<double>(), nullptr, TRI_NB, TRI_NB * (int64_t)maxcols};
+    DMat<double> W2m{W2.as<double>(), nullptr, TRI_NB, TRI_NB * (int64_t)maxcols};
+    DMat<double> Ys = Y.sub(i0 + 1, 0);
+    gemm<double>(s, true, false, TRI_NB, TRI_NB, m, 1.0, Vm, Vm, 0.0, Gm, batch);
+    k_wy_t<<<batch, 64, 0, s>>>(Gb.as<double>(), w.tau.as<double>(), n, i0, nbp, Tb.as<double>());
+    RFD_CHECK_LAUNCH();
+    gemm<double>(s, true, false, TRI_NB, maxcols, m, 1.0, Vm, Ys, 0.0, W1m, batch);
+    gemm<double>(s, false, false, TRI_NB, maxcols, TRI_NB, 1.0, Tm, W1m, 0.0, W2m, batch);
+    gemm<double>(s, false, false, m, maxcols, TRI_NB, -1.0, Vm, W2m, 1.0, Ys, batch);
   }
-  if (t == 0) d0 = sv[0];
-  __syncthreads();
-  const double thr = tol * d0;
-  int r = 0;
-  for (int64_t k = 0; k < m; ++k) {
-    double best = -1;
-    int bi = -1;
-    for (int64_t i = t; i < m; i += nt)
-      if (sel[i] < 0 && G[i + i * ldg] > best) { best = G[i + i * ldg]; bi = (int)i; }
-    sv[t] = best;
-    si[t] = bi;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (t < w && (sv[t + w] > sv[t] || (sv[t + w] == sv[t] && si[t + w] >= 0 &&
-                                          (si[t] < 0 || si[t + w] < si[t])))) {
-        sv[t] = sv[t + w];
-        si[t] = si[t + w];
-      }
-      __syncthreads();
-    }
-    const int pk = si[0];
-    const double dk = sv[0];
-    __syncthreads();
-    if (pk < 0 || !(dk > thr)) break;
-    const double lkk = sqrt(dk);
-    // column k of L (original indexing) into Lp[:, k]
-    for (int64_t i = t; i < m; i += nt) {
-      double v = 0;
-      if (i == pk) v = lkk;
-      else if (sel[i] < 0) v = G[i + (int64_t)pk * ldg] / lkk;
-      Lp[i + k * ldl] = v;
-    }
-    __syncthreads();
-    if (t == 0) {
-      sel[pk] = (int)k;
-      piv[k] = pk;
-    }
-    __syncthreads();
-    // trailing update over unselected rows/cols
-    for (int64_t e = t; e < m * m; e += nt) {
-      const int64_t i = e % m, c = e / m;
-      if (sel[i] < 0 && sel[c] < 0) G[i + c * ldg] -= Lp[i + k * ldl] * Lp[c + k * ldl];
-    }
-    __syncthreads();
-    ++r;
-  }
-  if (t == 0) *rank = r;
-  __syncthreads();
-  // pivot-ordered L (r x r) back into G's leading block: L[a, b] = Lp[piv[a], b]
-  for (int64_t e = t; e < (int64_t)r * r; e += nt) {
-    const int64_t a = e % r, bcol = e / r;
-    G[a + bcol * ldg] = (a >= bcol) ? Lp[piv[a] + bcol * ldl] : 0.0;
-  }
-  __syncthreads();
-  // Linv: column c by one thread, forward substitution
-  for (int64_t c = t; c < r; c += nt) {
-    for (int64_t i = 0; i < r; ++i) {
-      double v = 0;
-      if (i == c) v = 1.0 / G[c + c * ldg];
-      else if (i > c) {
-        double sacc = 0;
-        for (int64_t q = c; q < i; ++q) sacc += G[i + q * ldg] * Linv[q + c * ldl];
-        v = -sacc / G[i + i * ldg];
-      }
-      Linv[i + c * ldl] = v;
-    }
-  }
-}
-
-void pivoted_cholesky(hipStream_t s, double* G, int64_t ldg, int64_t m, double tol, int* piv,
-                      int* rank, double* Linv, int64_t ldl) {
-  // scratch: Lp (m x m) and sel (m) right after Linv's m x m block
-  static thread_local DevBuf scratch;
-  scratch.alloc(sizeof(double) * (m * m + m));
-  double* Lp = scratch.as<double>();
-  int* sel = reinterpret_cast<int*>(Lp + m * m);
-  k_pchol<<<1, 1024, 0, s>>>(G, ldg, m, tol, piv, rank, Lp, Linv, ldl, sel);
-  RFD_CHECK_LAUNCH();
 }
 
 }  // namespace rfd

@@ -1,8 +1,6 @@
 // Dense FP64 symmetric eigensolver for selected eigenpairs (batched):
 // Householder tridiagonalization, Sturm-count bisection, inverse iteration
-// with reorthogonalisation inside clusters, back-transformation.  Plus a
-// pivoted Cholesky factorization with triangular inverse (rank-revealing
-// Gram reduction).
+// with reorthogonalisation inside clusters, back-transformation.
 #pragma once
 
 #include <vector>
@@ -13,8 +11,11 @@ namespace rfd {
 
 constexpr int TRI_NB = 32;  // panel width of the blocked tridiagonalization
 
+// Work space of the eigensolver (kept by the caller so that repeated solves
+// of one shape reuse it).
 struct TriWork {
   DevBuf d, e, tau, pvec, acol, vw, red, sq;
+  DevBuf wv, wg, wt, w1, w2;  // back-transformation panels
   int64_t cap = 0;
   void reserve(int64_t n, int batch);
 };
@@ -42,15 +43,9 @@ void inverse_iteration(hipStream_t s, const TriWork& w, int64_t n, int batch, co
                        DevBuf& scratch);
 
 // Y <- Q Y with Q the product of the Householder reflectors left in A by
-// sy_tridiag (cols columns per item; only the first num[b] are used).
-void back_transform(hipStream_t s, DMat<double> A, const TriWork& w, int64_t n, int batch,
+// sy_tridiag (cols columns per item; columns beyond num[b] must be zero or
+// are transformed along).
+void back_transform(hipStream_t s, DMat<double> A, TriWork& w, int64_t n, int batch,
                     DMat<double> Y, const int* num, int maxcols);
-
-// Pivoted Cholesky of the m x m SPD item G (in place, lower triangle):
-// P^T G P = L L^T for the first r pivots, stopping when the largest remaining
-// diagonal is <= tol * (largest initial diagonal).  piv[i] = original index of
-// the i-th pivot, *rank = r.  Linv (m x m, ld m) receives L^{-1} (r x r).
-void pivoted_cholesky(hipStream_t s, double* G, int64_t ldg, int64_t m, double tol, int* piv,
-                      int* rank, double* Linv, int64_t ldl);
 
 }  // namespace rfd

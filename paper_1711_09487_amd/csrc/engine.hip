@@ -131,6 +131,28 @@ void Engine::set_precision(int mode, double tol, int sweeps) {
   e.sweeps = sweeps;
 }
 
+int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, int psi) const {
+  const EngineImpl& e = *d_;
+  const bool f32 = mode == 1;
+  const int64_t es = f32 ? 4 : 8, D = e.D, SP = e.SP, SJ = e.SJ, p = e.p, n = e.n;
+  const int64_t per_pole = p * (D * D * 2 * es + (int64_t)NB * 2 * D * 2 * es +
+                                D * SJ * (f32 ? 16 + 16 + 8 + 8 : 16));
+  const int64_t chunk = std::min<int64_t>(n_c, std::max<int64_t>(1, (int64_t(96) << 30) / per_pole));
+  const int64_t MP = round_up(std::max(m, 1), NB);
+  const int64_t mu = std::min<int64_t>(e.s, (int64_t)steps * m);
+  const int64_t MUP = round_up(std::max<int64_t>(mu, 1), NB);
+  const int64_t VB = nev_b + 16;
+  const int64_t k = p * VB + (int64_t)psi * mu;
+  int64_t b = chunk * per_pole;                                   // shifted blocks, Schur solves
+  b += SP * SP * n_c * 16 + (f32 ? SP * SP * n_c * 8 : 0);        // S (FP64, FP32 copy)
+  b += (int64_t)NB * 2 * SP * n_c * 2 * es;                       // S block inverses
+  b += SP * MP * n_c * (f32 ? 16 + 16 + 8 : 16);                  // filter right-hand sides
+  b += e.s * (mu + m) * 8 * 3;                                    // interface basis, orth work
+  b += p * (D * VB + 3 * D * D + D * (int64_t)psi * MUP) * 8;     // V_j, B_sigma, levels
+  b += n * (k * 3 + 4 * mu) * 8 + k * k * 8 * 2;                  // Z, A Z, H, level work
+  return b + b / 10 + (int64_t(64) << 20);
+}
+
 int64_t Engine::device_bytes() const {
   return d_->bytes_held();
 }
@@ -142,10 +164,11 @@ void Engine::reset_caches(bool release) {
   e.bs_valid = false;
   e.interior_ready = false;
   if (!release) return;
-  for (DevBuf* b : {&e.K32, &e.K64, &e.Kinv32, &e.Kinv64, &e.X32, &e.X64, &e.R32, &e.R64,
-                    &e.S64, &e.S32, &e.Sinv32, &e.Sinv64, &e.Vb, &e.Bs, &e.Bsinv, &e.Bspiv,
-                    &e.Lev, &e.Zt})
-    b->release();
+  for (DevBuf* b : e.solve_buffers()) b->release();
+  e.tw_v.cap = e.tw_h.cap = 0;
+  e.ow.v_elems = 0;
+  e.ow.m_cap = e.ow.mu_cap = 0;
+  e.kz = 0;
 }
 
 void Engine::set_timing(bool on) { d_->timer.enabled = on; }
@@ -194,12 +217,24 @@ PhaseTimer::~PhaseTimer() {
   }
 }
 
+std::vector<DevBuf*> EngineImpl::solve_buffers() {
+  std::vector<DevBuf*> v{&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32,
+                         &Sinv32, &Sinv64, &Yc, &Xf, &Rf, &Rf32, &W, &Qint, &Vb, &Bs, &Bsinv,
+                         &Bspiv, &Lev, &Zt, &work1, &work2, &work3, &work4, &work5, &work6,
+                         &ipiv_small, &iscal, &gwork, &work6b, &rr_az, &rr_h, &ow.V, &ow.T,
+                         &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank};
+  for (TriWork* t : {&tw_v, &tw_h})
+    for (DevBuf* b : {&t->d, &t->e, &t->tau, &t->pvec, &t->acol, &t->vw, &t->red, &t->sq,
+                      &t->wv, &t->wg, &t->wt, &t->w1, &t->w2})
+      v.push_back(b);
+  for (DevBuf& b : tmp) v.push_back(&b);
+  return v;
+}
+
 int64_t EngineImpl::bytes_held() const {
   int64_t t = 0;
-  for (const DevBuf* b : {&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32,
-                          &Sinv32, &Sinv64, &Yc, &Xf, &Rf, &Rf32, &W, &Qint})
-    t += (int64_t)b->bytes;
-  return t + interior_bytes();
+  for (DevBuf* b : const_cast<EngineImpl*>(this)->solve_buffers()) t += (int64_t)b->bytes;
+  return t;
 }
 
 double EngineImpl::read_scalar(hipStream_t s, int i) {

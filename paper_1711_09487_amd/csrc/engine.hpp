@@ -24,6 +24,8 @@ class Engine {
   void rayleigh_ritz(hipStream_t s, int max_out, double* evals, double* evecs, double* resid,
                      int* nfound);
   int64_t device_bytes() const;
+  // Upper estimate of the device memory one solve with these parameters holds.
+  int64_t estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, int psi) const;
   void reset_caches(bool release);
   void copy_basis(hipStream_t s, double* dst, int64_t cap, int64_t* k);
   void set_timing(bool on);

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "engine.hpp"
+#include "eig.hpp"
 #include "orth.hpp"
 #include "sparse.hpp"
 
@@ -80,7 +81,12 @@ struct EngineImpl {
   int64_t kz = 0;                         // columns of Zt
   DevBuf work1, work2, work3, work4, work5, work6;
   DevBuf ipiv_small, iscal, gwork, work6b;
+  DevBuf rr_az, rr_h;   // Rayleigh-Ritz: A Z and the projected matrix
+  DevBuf tmp[24];       // small per-call buffers, kept to avoid device-wide frees
+  TriWork tw_v, tw_h;   // eigensolver work: subdomain blocks, projected matrix
   PhaseTimer timer;
+  // every buffer that a solve grows (released by reset_caches(true))
+  std::vector<DevBuf*> solve_buffers();
   DevBuf flags, scal;
 
   int64_t bytes_held() const;
@@ -91,7 +97,7 @@ struct EngineImpl {
   int pole_chunk() const;
   void factor(hipStream_t st);
   void apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* W, int64_t ldw);
-  void ensure_reordered();
+  void ensure_reordered(hipStream_t st);
   void interior_basis(hipStream_t st, double sigma, int nev_b);
   void factor_bsigma(hipStream_t st, double sigma);
   int gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,

@@ -264,10 +264,14 @@ __global__ void k_resid(const double* AX, const double* MX, const double* X, int
 }
 
 // ---------------------------------------------------------------------------
+// Stream-ordered upload (the host vector may be released on return).
 template <typename T>
-static void upload_v(DevBuf& b, const std::vector<T>& v) {
+static void upload_v(hipStream_t st, DevBuf& b, const std::vector<T>& v) {
   b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
-  if (!v.empty()) RFD_HIP(hipMemcpy(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  if (!v.empty()) {
+    RFD_HIP(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    RFD_HIP(hipStreamSynchronize(st));
+  }
 }
 
 template <typename T>
@@ -280,7 +284,7 @@ static std::vector<T> download(hipStream_t s, const void* p, size_t n) {
   return v;
 }
 
-void EngineImpl::ensure_reordered() {
+void EngineImpl::ensure_reordered(hipStream_t st) {
   if (Arptr.p) return;
   std::vector<int32_t> ord;
   for (int j = 0; j < p; ++j) ord.insert(ord.end(), P->interior[j].begin(), P->interior[j].end());
@@ -304,9 +308,9 @@ void EngineImpl::ensure_reordered() {
       }
       ptr.push_back((int64_t)idx.size());
     }
-    upload_v(w == 0 ? Arptr : Mrptr, ptr);
-    upload_v(w == 0 ? Aridx : Mridx, idx);
-    upload_v(w == 0 ? Arval : Mrval, val);
+    upload_v(st, w == 0 ? Arptr : Mrptr, ptr);
+    upload_v(st, w == 0 ? Aridx : Mridx, idx);
+    upload_v(st, w == 0 ? Arval : Mrval, val);
   }
 }
 
@@ -353,7 +357,7 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   fill<double>(st, C, D, D, p, 0.0);
   k_expand_scaled<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), mis, big);
   RFD_CHECK_LAUNCH();
-  TriWork tw;
+  TriWork& tw = tw_v;
   sy_tridiag(st, C, D, p, tw);
   // indices around sigma
   std::vector<double> xs(p, sig);
@@ -372,9 +376,9 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
     num[j] = b - a;
     maxnum = std::max(maxnum, num[j]);
   }
-  DevBuf lo_d, num_d, lam_d;
-  upload_v(lo_d, lo);
-  upload_v(num_d, num);
+  DevBuf &lo_d = tmp[0], &num_d = tmp[1], &lam_d = tmp[2];
+  upload_v(st, lo_d, lo);
+  upload_v(st, num_d, num);
   lam_d.alloc(sizeof(double) * (size_t)p * maxnum);
   bisect(st, tw, D, p, lo_d.as<int>(), num_d.as<int>(), maxnum, lam_d.as<double>(), maxnum);
   auto lam = download<double>(st, lam_d.p, (size_t)p * maxnum);
@@ -419,10 +423,10 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
     knum[j] = kappa[j];
     kappa_tot += kappa[j];
   }
-  DevBuf sel_d, cl_d, kn_d, scratch;
-  upload_v(sel_d, sel);
-  upload_v(cl_d, cl);
-  upload_v(kn_d, knum);
+  DevBuf &sel_d = tmp[3], &cl_d = tmp[4], &kn_d = tmp[5], &scratch = tmp[6];
+  upload_v(st, sel_d, sel);
+  upload_v(st, cl_d, cl);
+  upload_v(st, kn_d, knum);
   Vb.alloc(sizeof(double) * D * VB * p);
   DMat<double> Y{Vb.as<double>(), nullptr, D, D * VB};
   // columns kappa_j .. VB-1 of a subdomain are padding and must stay zero: the
@@ -434,7 +438,7 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   // V = M^{-1/2} Y
   k_scale_rows<<<dim3(grid1(D * VB), p), 256, 0, st>>>(Y, D, VB, mis, D);
   RFD_CHECK_LAUNCH();
-  upload_v(kap_d, kappa);
+  upload_v(st, kap_d, kappa);
   timer.end(st);
   RFD_HIP(hipStreamSynchronize(st));
   work2.release();
@@ -570,7 +574,7 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   EngineImpl& e = *d_;
   if (e.Qint.p == nullptr) throw Error(ST_ESTATE, "rfd_filter_interface has not been called");
   if (!e.P->m_diag) throw Error(ST_EINVAL, "the interior part on the GPU needs a diagonal M");
-  e.ensure_reordered();
+  e.ensure_reordered(st);
   e.interior_basis(st, sig, nevb);
   e.factor_bsigma(st, sig);
   const int p = e.p, mu = e.mu;
@@ -605,7 +609,7 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
       Rh, D, MUP, e.dj.as<int32_t>(), e.Eg.view(), sig, e.Qint.as<double>(), s, mu,
       e.adj.as<int32_t>(), e.SJ);
   RFD_CHECK_LAUNCH();
-  DevBuf nrm;
+  DevBuf& nrm = e.tmp[7];
   nrm.alloc(sizeof(double) * 2 * MUP);
   double* pre = nrm.as<double>();
   double* post = pre + MUP;
@@ -649,9 +653,9 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
     koff[j] = (j ? koff[j - 1] + e.kappa[j - 1] : 0);
     ioff[j + 1] = ioff[j] + (int32_t)e.P->interior[j].size();
   }
-  DevBuf koff_d, kap_d2;
-  upload_v(koff_d, koff);
-  upload_v(kap_d2, e.kappa);
+  DevBuf &koff_d = e.tmp[8], &kap_d2 = e.tmp[9];
+  upload_v(st, koff_d, koff);
+  upload_v(st, kap_d2, e.kappa);
   if (e.kappa_tot > 0) {
     k_scatter_v<<<dim3(grid1(D * e.VB), p), 256, 0, st>>>(Z, n, Vm, e.ioff.as<int32_t>(),
                                                           koff_d.as<int32_t>(),
@@ -720,7 +724,8 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   double* Z = e.Zt.as<double>();
   // H = Z^T A Z
   e.timer.begin(st, 9);
-  DevBuf AZ, Hb;
+  DevBuf& AZ = e.rr_az;
+  DevBuf& Hb = e.rr_h;
   AZ.alloc(sizeof(double) * n * k);
   Hb.alloc(sizeof(double) * k * k);
   csr_mm(st, e.Arptr, e.Aridx, e.Arval, n, Z, n, AZ.as<double>(), n, k);
@@ -731,11 +736,11 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   e.timer.end(st);
   // eigenpairs of H in [alpha, beta]
   e.timer.begin(st, 10);
-  TriWork tw;
+  TriWork& tw = e.tw_h;
   sy_tridiag(st, Hm, k, 1, tw);
-  DevBuf xs, cnt;
+  DevBuf &xs = e.tmp[10], &cnt = e.tmp[11];
   std::vector<double> ab{e.poles.alpha, e.poles.beta};
-  upload_v(xs, ab);
+  upload_v(st, xs, ab);
   cnt.alloc(sizeof(int) * 2);
   sturm_counts(st, tw, k, 1, xs.as<double>(), 2, cnt.as<int>());
   auto c = download<int>(st, cnt.p, 2);
@@ -746,9 +751,9 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
     e.timer.end(st);
     return;
   }
-  DevBuf lo_d, num_d, lam_d;
-  upload_v(lo_d, std::vector<int>{i0});
-  upload_v(num_d, std::vector<int>{nout});
+  DevBuf &lo_d = e.tmp[12], &num_d = e.tmp[13], &lam_d = e.tmp[14];
+  upload_v(st, lo_d, std::vector<int>{i0});
+  upload_v(st, num_d, std::vector<int>{nout});
   lam_d.alloc(sizeof(double) * nout);
   bisect(st, tw, k, 1, lo_d.as<int>(), num_d.as<int>(), nout, lam_d.as<double>(), nout);
   auto lam = download<double>(st, lam_d.p, nout);
@@ -756,8 +761,8 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   for (double v : lam) tn = std::max(tn, std::fabs(v));
   tn = std::max(tn, e.normA);
   auto cl = clusters(lam, 1e-6 * tn);
-  DevBuf cl_d, Gv, scratch;
-  upload_v(cl_d, cl);
+  DevBuf &cl_d = e.tmp[15], &Gv = e.tmp[16], &scratch = e.tmp[17];
+  upload_v(st, cl_d, cl);
   Gv.alloc(sizeof(double) * k * nout);
   DMat<double> Gm{Gv.as<double>(), nullptr, k, 0};
   inverse_iteration(st, tw, k, 1, lam_d.as<double>(), num_d.as<int>(), cl_d.as<int>(), nout, Gm,
@@ -767,7 +772,7 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   // Ritz vectors, original numbering, residuals
   e.timer.begin(st, 11);
   RFD_HIP(hipMemcpyAsync(evals, lam_d.p, sizeof(double) * nout, hipMemcpyDeviceToDevice, st));
-  DevBuf Xr, X2, AX, MX;
+  DevBuf &Xr = e.tmp[18], &X2 = e.tmp[19], &AX = e.tmp[20], &MX = e.tmp[21];
   Xr.alloc(sizeof(double) * n * nout);
   DMat<double> Xm{Xr.as<double>(), nullptr, n, 0};
   gemm<double>(st, false, false, n, nout, k, 1.0, Zm, Gm, 0.0, Xm, 1);

@@ -42,7 +42,7 @@ struct Error : std::runtime_error {
 };
 
 enum { ST_OK = 0, ST_EINVAL = 1, ST_ENOMEM = 2, ST_EBREAKDOWN = 3, ST_ENOCONV = 4,
-       ST_EDEVICE = 5, ST_ESTATE = 6 };
+       ST_EDEVICE = 5, ST_ESTATE = 6, ST_EPENDING = 7 };
 
 #define RFD_HIP(call)                                                                  \
   do {                                                                                 \

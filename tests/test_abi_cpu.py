@@ -87,3 +87,44 @@ def test_partition_and_interval_validation():
 def test_destroy_null_is_ok():
     R = _lib()
     assert R.lib().rfd_destroy_pencil(None) == 0
+
+
+def test_job_and_result_layout_match_the_header(tmp_path):
+    """The ctypes mirrors of rfd_job / rfd_result have the C layout (offset of
+    every field and the size), checked with the host C compiler."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    import paper_1711_09487_amd as R
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    lines = []
+    for st in (R.rfd_job, R.rfd_result):
+        name = st.__name__
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "rfd.h"\nint main(void){'
+                   + "".join(lines) + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True,
+                                                        text=True, check=True).stdout.split("\n") if l)
+    for st in (R.rfd_job, R.rfd_result):
+        name = st.__name__
+        assert int(out[f"{name} size"]) == C.sizeof(st)
+        for f, _ in st._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(st, f).offset, (name, f)
+
+
+def test_batch_and_server_argument_validation():
+    R = _lib()
+    L = R.lib()
+    import ctypes as C
+    assert L.rfd_batch_run(0, None, None, None, 0, 0) == 1
+    res = R.rfd_result()
+    assert L.rfd_server_poll(None, 1, 0, C.byref(res)) == 1
+    assert L.rfd_server_submit(None, None, None, None) == 1
+    assert L.rfd_server_destroy(None) == 0
