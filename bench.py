@@ -1,19 +1,35 @@
 """Benchmark of the RF-DDES path on one MI355X.
 
-A step is one complete solve of the 2D 255x255 pencil with diagonal random M
-(n = 65025, 64 subdomains of 31x31, interface s = 3521, the lowest 200
-eigenvalues, 8 Gauss-Legendre poles, block of 300, 2 block-Krylov steps,
-nev_b = 20, psi = 4): every factorization is recomputed (caches invalidated),
-then filter_interface, solve_interior and rayleigh_ritz with eigenvectors and
-residuals.  The pencil and the starting block are resident on the device
-before the timed region.  Every step's Ritz values are checked against the
-CPU oracle's stored values (tests/golden/oracle_c2.json); only eigenpairs
-within 1e-10 relative error are counted.
+Headline (one JSON line on stdout): a step is one complete solve of the 2D
+255x255 pencil with diagonal random M (n = 65025, 64 subdomains of 31x31,
+interface s = 3521, the lowest 200 eigenvalues, 8 Gauss-Legendre poles,
+block of 300, 2 block-Krylov steps, nev_b = 20, psi = 4): every
+factorization is recomputed (caches invalidated), then filter_interface,
+solve_interior and rayleigh_ritz with eigenvectors and residuals.  The
+pencil and the starting block are resident on the device before the timed
+region.  Every step's Ritz values are checked against the CPU oracle's
+stored values (tests/golden/oracle_c2.json); only eigenpairs within 1e-10
+relative error are counted.  Both precision modes run: FP32 factors with
+FP64 refinement to the 1e-10 target (the value) and plain FP64 (beside it).
+
+Beside the headline:
+  batched  -- pencils of the batched workload (variable coefficient, random
+              M, uneven sizes) run as one rfd_batch_run on several worker
+              streams, against the same jobs on one worker;
+  serving  -- a seeded Poisson stream of spectrum-slicing requests on the
+              31x31, 255x255 and two batched-workload pencils, replayed at
+              0.5x and 0.8x the measured saturated rate: p50 / p99 latency
+              and throughput;
+  roofline -- the FP32 complex GEMM (LU updates and triangular solves of the
+              shifted blocks and of S), timed per launch with HIP events on
+              its own stream over the timed steps;
+  cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp32|fp64|both]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -26,18 +42,22 @@ sys.path.insert(0, ROOT)
 FP32_MFMA_PEAK = 157.3   # TFLOP/s, dense FP32 matrix
 FP64_PEAK = 78.6         # TFLOP/s, dense FP64 (matrix and vector)
 HBM_PEAK = 8000.0        # GB/s
+TARGET_TOL = 1e-10       # refinement tolerance matching the accuracy target
+
+
+def rule_of(R, prob):
+    return R.RFD_RULE_GAUSS if prob.rule == "gauss" else R.RFD_RULE_MIDPOINT
 
 
 def make_pencil(R, prob, mode, refine_tol=0.0):
     P = R.Pencil(prob.A, prob.M)
     P.set_partition(prob.part)
-    P.set_interval_and_poles(prob.alpha, prob.beta, prob.n_c,
-                             R.RFD_RULE_GAUSS if prob.rule == "gauss" else R.RFD_RULE_MIDPOINT)
+    P.set_interval_and_poles(prob.alpha, prob.beta, prob.n_c, rule_of(R, prob))
     P.set_precision(R.RFD_FP32_REFINE if mode == "fp32" else R.RFD_FP64, refine_tol)
     return P
 
 
-def one_step(P, prob, Y0, torch):
+def one_step(P, prob, Y0):
     P.reset_caches(False)
     P.filter_interface(Y0, prob.steps)
     k = P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
@@ -45,45 +65,215 @@ def one_step(P, prob, Y0, torch):
     return ev, r, k
 
 
-def run_mode(R, prob, mode, steps, warmup, ref, torch, refine_tol=0.0):
+def count_good(th, ref, tol=1e-10):
+    """Reference eigenvalues matched by a Ritz value within tol (relative),
+    pairing the two ascending lists in order (a Ritz value serves one
+    eigenvalue); and the largest relative error when the counts agree."""
+    th, ref = np.sort(th), np.sort(ref)
+    i = j = good = 0
+    while i < ref.size and j < th.size:
+        if abs(th[j] - ref[i]) <= tol * abs(ref[i]):
+            good += 1
+            i += 1
+            j += 1
+        elif th[j] < ref[i]:
+            j += 1
+        else:
+            i += 1
+    err = float(np.max(np.abs(th - ref) / np.abs(ref))) if th.size == ref.size and th.size else float("inf")
+    return good, err
+
+
+def run_mode(R, prob, mode, steps, warmup, ref, torch, refine_tol, account):
     P = make_pencil(R, prob, mode, refine_tol)
     Y0 = torch.from_numpy(np.ascontiguousarray(prob.Y0.T)).cuda()
     for _ in range(warmup):
-        one_step(P, prob, Y0, torch)
+        one_step(P, prob, Y0)
     torch.cuda.synchronize()
     P.set_timing(True)
     P.phase_times()                        # clear
+    if account:
+        R.rfd_kernel_accounting(True)
+        R.rfd_kernel_stats()               # clear
     lat, good, errs, res = [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
-        ev, r, k = one_step(P, prob, Y0, torch)
+        ev, r, k = one_step(P, prob, Y0)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
-        th = ev.cpu().numpy()
-        if th.size == ref.size:
-            rel = np.abs(th - ref) / np.abs(ref)
-            good.append(int(np.count_nonzero(rel <= 1e-10)))
-            errs.append(float(rel.max()))
-        else:
-            good.append(0)
-            errs.append(float("inf"))
+        g, e = count_good(ev.cpu().numpy(), ref)
+        good.append(g)
+        errs.append(e)
         res.append(float(r.max().item()) if r.numel() else 0.0)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    kstats = None
+    if account:
+        kstats = R.rfd_kernel_stats()
+        R.rfd_kernel_accounting(False)
     ph = P.phase_times() / steps
     P.close()
-    return dict(total=total, lat=lat, good=good, errs=errs, resid=res, phases=ph, k=k)
+    return dict(total=total, lat=lat, good=good, errs=errs, resid=res, phases=ph, k=k,
+                kstats=kstats)
 
 
+# ---------------------------------------------------------------------------
+# batched leg
+# ---------------------------------------------------------------------------
+# interior sizing of the batched pencils (few poles: more block steps and a
+# richer interior basis reach the 1e-10 target against exact eigenvalues)
+BATCH_NEV_B, BATCH_PSI, BATCH_STEPS = 40, 6, 3
+
+
+def batch_leg(R, W, torch, count, workers):
+    specs = W.batch_specs(count)
+    probs = [W.batch_problem(b, sp, nev_b=BATCH_NEV_B, psi=BATCH_PSI, steps=BATCH_STEPS)
+             for b, sp in enumerate(specs)]
+    pens = []
+    for prob in probs:
+        P = R.Pencil(prob.A, prob.M)
+        P.set_partition(prob.part)
+        pens.append(P)
+    y0 = [torch.from_numpy(np.ascontiguousarray(pr.Y0.T)).cuda() for pr in probs]
+
+    def jobs():
+        return [R.Job(P, pr.alpha, pr.beta, pr.n_c, y, pr.steps, pr.sigma, pr.nev_b, pr.psi,
+                      pr.nev + 30, mode=R.RFD_FP32_REFINE, rule=rule_of(R, pr),
+                      refine_tol=TARGET_TOL)
+                for P, pr, y in zip(pens, probs, y0)]
+
+    R.batch_run(jobs(), workers=workers)          # first use: maps, reordered matrices
+    out = {}
+    for w in (workers, 1):
+        js = jobs()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R.batch_run(js, workers=w)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        good = found = 0
+        for j, pr in zip(js, probs):
+            ev = j.outputs()[0].cpu().numpy()
+            found += ev.size
+            g, _ = count_good(ev, pr.exact[:pr.nev])
+            good += g
+        out[w] = dict(wall=wall, good=good, found=found)
+    for P in pens:
+        P.close()
+    b, s1 = out[workers], out[1]
+    return {"pencils": count, "workers": workers, "eigenpairs": b["good"],
+            "eigenpairs_found": b["found"], "value": b["good"] / b["wall"],
+            "unit": "eigenpairs/s", "wall_s": b["wall"], "one_worker_value": s1["good"] / s1["wall"],
+            "one_worker_wall_s": s1["wall"], "speedup_vs_one_worker": s1["wall"] / b["wall"],
+            "mode": "fp32+refine", "counted": "Ritz values within 1e-10 of a reference eigensolver",
+            "nev_b": BATCH_NEV_B, "psi": BATCH_PSI, "block_steps": BATCH_STEPS,
+            "sizes": {"N": [s["N"] for s in specs], "P": [s["P"] for s in specs],
+                      "nev": [s["nev"] for s in specs], "n_c": [s["n_c"] for s in specs]}}
+
+
+# ---------------------------------------------------------------------------
+# serving leg
+# ---------------------------------------------------------------------------
+def serve_leg(R, W, torch, prob2, gold2, nreq, workers):
+    import scipy.linalg as sl
+    c1 = W.config(1)
+    pencils = {"C1": c1, "C2": prob2}
+    spectra = {"C1": sl.eigh(c1.A.toarray(), c1.M.toarray(), eigvals_only=True),
+               "C2": np.array(gold2["reference_eigs"])}
+    for b, spec in enumerate(W.batch_specs(256)):
+        if spec["N"] >= 100 and spec["P"] == 2 and "B" not in pencils:
+            pb = W.batch_problem(b, spec)
+            pencils["B"] = pb
+            spectra["B"] = W.lowest_eigs(pb.A, pb.M, 120)
+            break
+    weights = {"C1": 0.6, "C2": 0.3, "B": 0.1}
+    reqs, gaps = W.serving_requests(nreq, spectra, weights)
+    replicas = {nm: [] for nm in pencils}
+    for nm, pr in pencils.items():
+        for _ in range(2):
+            P = R.Pencil(pr.A, pr.M)
+            P.set_partition(pr.part)
+            replicas[nm].append(P)
+
+    def build(i, rq):
+        pr = pencils[rq["pencil"]]
+        P = replicas[rq["pencil"]][i % 2]
+        k = rq["k"]
+        m = min(pr.s, int(math.ceil(1.5 * k)))
+        y = np.random.default_rng([5, 1, i]).standard_normal((m, pr.s))
+        Y0 = torch.from_numpy(y).cuda()
+        a, b = rq["alpha"], rq["beta"]
+        # interior basis sized with the slice: 1.5 k over the subdomains
+        nev_b = max(20, int(math.ceil(1.5 * k / pr.p)) + 10)
+        return R.Job(P, a, b, 8, Y0, 2, 0.5 * (a + b), nev_b, 6, k + 40,
+                     mode=R.RFD_FP32_REFINE, refine_tol=TARGET_TOL, vectors=True)
+
+    def check(rq, job):
+        lam = spectra[rq["pencil"]][rq["i0"] - 1: rq["i0"] - 1 + rq["k"]]
+        ev = job.outputs()[0].cpu().numpy()
+        g, _ = count_good(ev, lam)
+        return g
+
+    def replay(qps):
+        srv = R.Server(workers=workers)
+        jobs = [build(i, rq) for i, rq in enumerate(reqs)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        arrive = np.cumsum(gaps) / qps if qps else np.zeros(len(reqs))
+        ids, lat, pending = {}, {}, set()
+        i = 0
+        while i < len(jobs) or pending:
+            now = time.perf_counter() - t0
+            while i < len(jobs) and arrive[i] <= now:
+                ids[i] = srv.submit(jobs[i])
+                pending.add(i)
+                i += 1
+            for q in list(pending):
+                r = srv.poll(ids[q])
+                if r is not None:
+                    if r["status"] != 0:
+                        raise RuntimeError(r["message"])
+                    lat[q] = r["queued_s"] + r["run_s"]
+                    pending.discard(q)
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        good = sum(check(rq, j) for rq, j in zip(reqs, jobs))
+        want = sum(rq["k"] for rq in reqs)
+        L = np.array([lat[q] for q in range(len(jobs))]) * 1e3
+        return dict(wall_s=wall, eigenpairs=good, eigenpairs_wanted=want,
+                    throughput=good / wall, p50_ms=float(np.percentile(L, 50)),
+                    p99_ms=float(np.percentile(L, 99)), evictions=st["evictions"])
+
+    replay(None)                                   # first use of every pencil
+    sat = replay(None)                             # all requests at once
+    rate = nreq / sat["wall_s"]
+    out = {"requests": nreq, "workers": workers, "replicas_per_pencil": 2,
+           "interior": "nev_b = max(20, ceil(1.5 k / p) + 10), psi = 6, 2 block steps, m = min(s, 1.5 k)",
+           "mix": weights, "pencils": {nm: pr.name for nm, pr in pencils.items()},
+           "mode": "fp32+refine", "unit_latency": "ms", "unit_throughput": "eigenpairs/s",
+           "saturated": dict(sat, requests_per_s=rate)}
+    for frac in (0.5, 0.8):
+        out[f"qps_{frac}x"] = dict(replay(frac * rate), qps=frac * rate)
+    for ps in replicas.values():
+        for P in ps:
+            P.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle on a bounded sample
+# ---------------------------------------------------------------------------
 def cpu_baseline(prob, gold):
     """The oracle (unchanged) on a bounded sample of the same workload: pole 1
-    of n_c with 8 of the 64 subdomains (Schur contributions, interior basis,
+    of n_c with 16 of the 64 subdomains (Schur contributions, interior basis,
     resolvent levels), one S(zeta) LU and solve, and a Rayleigh-Ritz on a
     quarter of the columns; the full-job time is extrapolated linearly in
-    poles, subdomains and block steps and quadratically in Rayleigh-Ritz
-    columns."""
+    poles, subdomains and block steps and cubically in Rayleigh-Ritz columns
+    (its dense eigensolve dominates)."""
     import oracle as O
     import scipy.linalg as sl
     t = {}
@@ -91,7 +281,7 @@ def cpu_baseline(prob, gold):
     dd = O.DD(prob.A, prob.M, prob.part)
     t["setup"] = time.perf_counter() - t0
     z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
-    sub = 8
+    sub = 16
     full_p = dd.p
     for attr in ("interior", "adj", "B", "MB", "E", "ME"):
         setattr(dd, attr, getattr(dd, attr)[:sub])
@@ -114,7 +304,6 @@ def cpu_baseline(prob, gold):
     t0 = time.perf_counter()
     O.interior_levels(dd, prob.sigma, prob.psi, Q, V)
     t["levels_sub"] = time.perf_counter() - t0
-    # Rayleigh-Ritz on k/4 columns of a basis with the workload's shape
     kq = gold["k"] // 4
     dd2 = O.DD(prob.A, prob.M, prob.part)
     Zs = rng.standard_normal((dd2.n, kq))
@@ -125,9 +314,9 @@ def cpu_baseline(prob, gold):
     scale_sub = full_p / sub
     est = (t["setup"] + prob.n_c * (scale_sub * t["schur_sub"] + t["slu"])
            + prob.steps * prob.n_c * t["fsolve"] + scale_sub * (t["vbasis_sub"] + t["levels_sub"])
-           + 16.0 * t["rr_quarter"])
-    import multiprocessing
-    cores = int(os.environ.get("OMP_NUM_THREADS", multiprocessing.cpu_count()))
+           + 64.0 * t["rr_quarter"])
+    threads = os.environ.get("OMP_NUM_THREADS")
+    cores = int(threads) if threads else os.cpu_count()
     return dict(value=prob.nev / est, unit="eigenpairs/s", cores=cores, kind="oracle",
                 sample=(f"oracle phases on pole 1 of {prob.n_c}, {sub} of {full_p} subdomains, one "
                         f"S LU + solve, Rayleigh-Ritz on {kq} of {gold['k']} columns; "
@@ -142,8 +331,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="both", choices=["fp32", "fp64", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--refine-tol", type=float, default=0.0,
-                    help="FP32 refinement stopping tolerance (0: library default)")
+    ap.add_argument("--refine-tol", type=float, default=TARGET_TOL,
+                    help="FP32 refinement tolerance (relative max-norm residual)")
+    ap.add_argument("--batch-pencils", type=int, default=32,
+                    help="pencils of the batched workload (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests per serving replay (0: skip)")
+    ap.add_argument("--workers", type=int, default=4)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X "
@@ -162,7 +356,8 @@ def main():
     modes = ["fp32", "fp64"] if a.mode == "both" else [a.mode]
     res = {}
     for mode in modes:
-        res[mode] = run_mode(R, prob, mode, a.steps, a.warmup, ref, torch, a.refine_tol)
+        res[mode] = run_mode(R, prob, mode, a.steps, a.warmup, ref, torch, a.refine_tol,
+                             account=True)
         r = res[mode]
         print(f"# {mode}: {1e3 * r['total'] / a.steps:.1f} ms/step, max rel err "
               f"{max(r['errs']):.2e}, good {min(r['good'])}/{prob.nev}, phases(ms) "
@@ -172,34 +367,48 @@ def main():
     ms = 1e3 * head["total"] / a.steps
     lat = np.array(head["lat"]) * 1e3
     value = min(head["good"]) / (head["total"] / a.steps)
-    # roofline of the dominant phase: batched LU of the shifted interior blocks
-    d = int(np.max(np.bincount(prob.part[prob.part >= 0])))
-    lu_flops = prob.p * prob.n_c * (8.0 / 3.0) * d ** 3
-    lu_ms = head["phases"][0]
-    achieved = lu_flops / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else 0.0
-    peak = FP32_MFMA_PEAK if "fp32" in res else FP64_PEAK
+    # roofline: the complex GEMM of the head mode (FP32 MFMA in fp32 mode)
+    f32 = "fp32" in res and head is res["fp32"]
+    kname = R.GEMM_KEYS[(0 if f32 else 8) + 4]
+    launches, kms, kfl = head["kstats"].get(kname, (0, 0.0, 0.0))
+    achieved = kfl / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+    peak = FP32_MFMA_PEAK if f32 else FP64_PEAK
     out = {
         "metric": "eigenpairs/sec at 1e-10 rel err, FP32+refine batched vs FP64; p50/p99",
         "value": value, "unit": "eigenpairs/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64" if "fp32" in res else "f64",
+        "vs_baseline": None, "dtype": "f32+f64" if f32 else "f64",
         "data": "synthetic",
         "config": {"workload": prob.name, "n": prob.n, "p": prob.p, "s": prob.s,
                    "nev": prob.nev, "n_c": prob.n_c, "m": prob.m, "block_steps": prob.steps,
-                   "nev_b": prob.nev_b, "psi": prob.psi, "rr_columns": head["k"]},
+                   "nev_b": prob.nev_b, "psi": prob.psi, "rr_columns": head["k"],
+                   "refine_tol": a.refine_tol},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "accuracy": {"max_rel_err_vs_oracle": max(head["errs"]),
                      "max_resid": max(head["resid"])},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "batched complex LU of B_j - zeta M_Bj (phase)"},
+                     "kernel": f"{kname} (LU updates and triangular solves)",
+                     "launches_per_step": launches / a.steps,
+                     "avg_launch_us": 1e3 * kms / max(launches, 1),
+                     "flops_per_launch": kfl / max(launches, 1)},
     }
     if "fp64" in res and "fp32" in res:
         f64 = res["fp64"]
         out["fp64"] = {"value": min(f64["good"]) / (f64["total"] / a.steps),
                        "ms_per_step": 1e3 * f64["total"] / a.steps,
                        "max_rel_err_vs_oracle": max(f64["errs"])}
+        out["fp32_over_fp64"] = out["value"] / out["fp64"]["value"]
     out["phases_ms"] = {m: np.round(res[m]["phases"][:12], 3).tolist() for m in res}
+    out["kernels"] = {m: {k: dict(launches=v[0], ms=v[1], tflops=v[2] / max(v[1], 1e-9) / 1e9)
+                          for k, v in res[m]["kstats"].items()} for m in res}
+    if a.batch_pencils > 0:
+        out["batched"] = batch_leg(R, W, torch, a.batch_pencils, a.workers)
+        print(f"# batched: {json.dumps({k: v for k, v in out['batched'].items() if k != 'sizes'})}",
+              file=sys.stderr, flush=True)
+    if a.serve_requests > 0:
+        out["serving"] = serve_leg(R, W, torch, prob, gold, a.serve_requests, a.workers)
+        print(f"# serving: {json.dumps(out['serving'])}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, gold)
     print(json.dumps(out))

@@ -677,18 +677,18 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
     csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
     k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n0);
     RFD_CHECK_LAUNCH();
-    // project against V and the previous level blocks (M-inner product), twice
+    // project against V and the previous level blocks (M-inner product)
     const int64_t kprev = kz - e.kappa_tot;
-    e.project_out(st, Lb, mu, MLb, Z + e.kappa_tot * n, kprev, 2);
+    e.project_out(st, Lb, mu, MLb, Z + e.kappa_tot * n, kprev, 1);
     csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
     k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n1);
     RFD_CHECK_LAUNCH();
     k_col_normalize<<<dim3(grid1(n), mu), 256, 0, st>>>(Lb, n, n, n1, n0, 1e-10);
     RFD_CHECK_LAUNCH();
-    // Cholesky QR through the semidefinite LDL^T: the first pass drops the
-    // columns that depend on earlier ones; a kept column with a small pivot
-    // amplifies rounding, so the result is projected once more before the
-    // second pass restores orthonormality
+    // block Gram-Schmidt twice with Cholesky QR through the semidefinite
+    // LDL^T: the first pass drops the columns that depend on earlier ones; a
+    // kept column with a small pivot amplifies rounding, so the result is
+    // projected once more before the second pass restores orthonormality
     const int r = e.gram_orth(st, Lb, mu, MLb, Z + kz * n, 1e-13);
     if (r == 0) continue;
     e.project_out(st, Z + kz * n, r, MLb, Z + e.kappa_tot * n, kprev, 1);

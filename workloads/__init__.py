@@ -287,3 +287,41 @@ def tiny(N=11, dim=2, P=2, nev=6, n_c=4, m=None, steps=2, nev_b=8, psi=3,
     return grid_problem(f"tiny {shape} P={P} {mass_kind}", cfg_id, shape, P, nev, n_c,
                         s if m is None else m, steps, nev_b, psi, mass_kind=mass_kind,
                         kfield=kfield, rule=rule, sigma=sigma)
+
+
+def serving_requests(count: int, spectra: dict, weights: dict, cfg_id: int = 5,
+                     kmin: int = 20, kmax: int = 300, i0max: int = 500):
+    """A seeded stream of spectrum-slicing requests (stream 3 for shapes,
+    stream 4 for arrivals).
+
+    spectra: pencil name -> ascending known eigenvalues of that pencil (the
+    lowest ones; a slice never reaches beyond them); weights: pencil name ->
+    probability.  Each request picks a pencil, a count k ~ U{kmin..kmax} and a
+    first index i0 ~ U{1..min(i0max, len - k - 1)} (1-based, clipped to what
+    the known spectrum allows), and the interval alpha = (lam_{i0-1} +
+    lam_{i0}) / 2 (0 for i0 = 1), beta = (lam_{i0+k-1} + lam_{i0+k}) / 2, both
+    rounded to 10 significant digits; slices that would cut a multiple
+    eigenvalue are moved by one.  Returns a list of dicts (pencil, alpha,
+    beta, k, i0) and unit-rate exponential inter-arrival gaps (scale them by
+    1 / QPS)."""
+    g = rng(cfg_id, STREAM_SHAPE)
+    names = sorted(weights)
+    prob = np.array([weights[nm] for nm in names], dtype=float)
+    prob /= prob.sum()
+    out = []
+    for _ in range(count):
+        nm = names[int(g.choice(len(names), p=prob))]
+        lam = np.asarray(spectra[nm])
+        L = lam.size
+        k = int(g.integers(kmin, min(kmax, L - 2) + 1))
+        i0 = int(g.integers(1, max(1, min(i0max, L - k - 1)) + 1))
+        gap = 1e-10 * max(1.0, abs(lam[-1]))
+        while i0 > 1 and lam[i0 - 1] - lam[i0 - 2] <= gap:
+            i0 -= 1
+        while i0 + k < L and lam[i0 + k] - lam[i0 + k - 1] <= gap:
+            k -= 1
+        alpha = 0.0 if i0 == 1 else float(f"{0.5 * (lam[i0 - 2] + lam[i0 - 1]):.10g}")
+        beta = float(f"{0.5 * (lam[i0 + k - 2] + lam[i0 + k - 1]):.10g}")
+        out.append(dict(pencil=nm, alpha=alpha, beta=beta, k=k, i0=i0))
+    gaps = rng(cfg_id, STREAM_ARRIVAL).exponential(1.0, count)
+    return out, gaps
