@@ -18,8 +18,17 @@
 // orthogonalisation and projection) split K over extra workgroups; partial
 // tiles go to a per-stream workspace and a second kernel sums them in a fixed
 // order, so results do not depend on scheduling.
+//
+// Plain FP64 real products with many output tiles (the projected matrix of
+// the Rayleigh-Ritz step, basis updates Z T, Ritz vectors) go to rocBLAS,
+// whose tuned FP64 kernels run these shapes faster; everything complex,
+// FP32, or tall-skinny runs here.
+#include <rocblas/rocblas.h>
+
 #include <map>
 #include <mutex>
+#include <string>
+#include <type_traits>
 
 #include "dense.hpp"
 
@@ -311,6 +320,54 @@ static void* splitk_workspace(hipStream_t s, size_t bytes) {
   return w.p;
 }
 
+// One rocBLAS handle per (device, stream), created on first use.
+static rocblas_handle blas_handle(hipStream_t s) {
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, rocblas_handle> hs;
+  int dev = 0;
+  RFD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  rocblas_handle& h = hs[{dev, s}];
+  if (!h) {
+    if (rocblas_create_handle(&h) != rocblas_status_success) {
+      h = nullptr;
+      throw Error(ST_EDEVICE, "rocblas_create_handle failed");
+    }
+    rocblas_set_pointer_mode(h, rocblas_pointer_mode_host);
+  }
+  if (rocblas_set_stream(h, s) != rocblas_status_success)
+    throw Error(ST_EDEVICE, "rocblas_set_stream failed");
+  return h;
+}
+
+static void blas_check(rocblas_status st, const char* what) {
+  if (st != rocblas_status_success)
+    throw Error(ST_EDEVICE, std::string(what) + ": " + rocblas_status_to_string(st));
+}
+
+// C = alpha op(A) op(B) + beta C in FP64 through rocBLAS.  A lower-triangle
+// request computes the full square (rocBLAS's triangular-output product is
+// slower than its full product on these shapes).
+static void blas_dgemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K,
+                       double alpha, DMat<double> A, DMat<double> B, double beta, DMat<double> C,
+                       int batch) {
+  rocblas_handle h = blas_handle(s);
+  const rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
+  const rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
+  if (batch == 1) {
+    blas_check(rocblas_dgemm(h, oa, ob, (rocblas_int)M, (rocblas_int)N, (rocblas_int)K, &alpha,
+                             A.re, (rocblas_int)A.ld, B.re, (rocblas_int)B.ld, &beta, C.re,
+                             (rocblas_int)C.ld),
+               "rocblas_dgemm");
+  } else {
+    blas_check(rocblas_dgemm_strided_batched(h, oa, ob, (rocblas_int)M, (rocblas_int)N,
+                                             (rocblas_int)K, &alpha, A.re, (rocblas_int)A.ld, A.bs,
+                                             B.re, (rocblas_int)B.ld, B.bs, &beta, C.re,
+                                             (rocblas_int)C.ld, C.bs, (rocblas_int)batch),
+               "rocblas_dgemm_strided_batched");
+  }
+}
+
 template <typename T, bool CPLX, int BM, int BN>
 static void launch(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N, int64_t K,
                    T alpha, T beta, DMat<T> A, DMat<T> B, DMat<T> C, int splits, int64_t kchunk,
@@ -342,7 +399,7 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   // (not for FP64 complex, whose accumulators would not fit)
   // (and only over a long K: with a few K slabs the single wave per SIMD of
   // the large tile cannot hide its prologue and epilogue)
-  const bool big_ok = !(sizeof(T) == 8 && cplx) && M >= 128 && N >= 128 && K >= 256;
+  const bool big_ok = sizeof(T) == 4 && M >= 128 && N >= 128 && K >= 256;
   const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128) * batch;
   const int bt = (big_ok && t128 >= 240) ? 128 : 64;
   const int64_t gm = (M + bt - 1) / bt, gn = (N + bt - 1) / bt;
@@ -354,6 +411,16 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
       --splits;
     while (splits > 1 && (int64_t)splits * batch > 65535) --splits;
     if (splits < 1) splits = 1;
+  }
+  if constexpr (std::is_same<T, double>::value) {
+    const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64) * batch;
+    if (!cplx && splits == 1 && t64 >= 512 && K >= 32 && M <= 0x7fffffff && N <= 0x7fffffff &&
+        K <= 0x7fffffff) {
+      KernelAccount::Scope acct(s, 8 + (ta ? 2 : 0) + (tb ? 1 : 0),
+                                2.0 * (double)M * (double)N * (double)K * batch);
+      blas_dgemm(s, ta, tb, M, N, K, alpha, A, B, beta, C, batch);
+      return;
+    }
   }
   if ((int64_t)batch * splits > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
   if (gm > 0x7fffffff || gn > 65535) throw Error(ST_EINVAL, "gemm: matrix too large");
@@ -372,11 +439,15 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   const double outs = tri ? 0.5 * (double)N * (double)(N + 1) : (double)M * (double)N;
   const double flops = (cplx ? 8.0 : 2.0) * outs * (double)K * batch;
   KernelAccount::Scope acct(s, key, flops);
-  if (cplx) {
-    if (bt == 128) launch<T, true, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
-    else launch<T, true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
-  } else {
-    if (bt == 128) launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
+  // 128-wide tiles exist for FP32 only (FP64 products of that size go to rocBLAS)
+  if constexpr (sizeof(T) == 4) {
+    if (bt == 128) {
+      if (cplx) launch<T, true, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
+      else launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
+    }
+  }
+  if (bt == 64 || sizeof(T) == 8) {
+    if (cplx) launch<T, true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
     else launch<T, false, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
   }
   RFD_CHECK_LAUNCH();
