@@ -41,6 +41,7 @@ void TriWork::reserve(int64_t n, int batch) {
   vw.alloc(sizeof(double) * need * 2 * TRI_NB);
   red.alloc(sizeof(double) * (2 * TRI_NB + 2) * batch);
   sq.alloc(sizeof(double) * ((n + 255) / 256) * batch);
+  ptvp.alloc(sizeof(double) * ((n + 7) / 8) * batch);
 }
 
 // Blocked reduction (panels of TRI_NB columns).  Within a panel the trailing
@@ -51,8 +52,9 @@ void TriWork::reserve(int64_t n, int batch) {
 //               the partial sums of squares below its subdiagonal;
 //   k_tri_symv  makes the reflector from acol (every workgroup), writes it
 //               to V[:, c] and column j of A, and forms p = A v over the
-//               trailing block of the panel-start matrix;
-//   k_tri_dots  forms p^T v, W^T v and V^T v.
+//               trailing block of the panel-start matrix with per-workgroup
+//               partial sums of p^T v; 2c extra workgroups of the same
+//               launch form W^T v and V^T v.
 // After the panel, the trailing block takes A -= V W^T + W V^T as two GEMMs.
 // w_c = tau (p - V (W^T v) - W (V^T v)) - (tau/2) (that^T v) v, i.e. the
 // two-sided application of I - tau v v^T to the current trailing matrix.
@@ -62,7 +64,7 @@ void TriWork::reserve(int64_t n, int batch) {
 __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int64_t j, int c,
                                                  int upd, double* vw, const double* tauv,
                                                  const double* pv, const double* red, double* acol,
-                                                 double* dv, double* sq) {
+                                                 double* dv, double* sq, const double* ptvp) {
   __shared__ double Vj[TRI_NB], Wj[TRI_NB], xs[TRI_NB], ys[TRI_NB], rs[8];
   const int b = blockIdx.y, t = threadIdx.x;
   DMat<double> a = A.item(b);
@@ -90,11 +92,17 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
   __syncthreads();
   double wr = 0.0;
   if (c >= 1) {
+    // p^T v of the previous column: partial sums of its mat-vec workgroups
+    const int np = (int)((n - j + 7) / 8);
+    const double* pp = ptvp + (int64_t)b * ((n + 7) / 8);
+    double ps = 0.0;
+    for (int i = t; i < np; i += 256) ps += pp[i];
+    const double ptv = block_sum256(ps, rs);
     const double tp = tauv[(int64_t)b * n + j - 1];
     double xy = 0;
 #pragma unroll 8
     for (int q = 0; q < c - 1; ++q) xy += xs[q] * ys[q];
-    const double al = -0.5 * tp * tp * (rd[0] - 2.0 * xy);
+    const double al = -0.5 * tp * tp * (ptv - 2.0 * xy);
     if (t == 0) {
       double acc = p[j];
       for (int q = 0; q < c - 1; ++q) acc -= Vj[q] * xs[q] + Wj[q] * ys[q];
@@ -132,9 +140,11 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int64_t j, int c,
                                                   double* vw, double* dv, double* ev, double* tauv,
-                                                  double* pv, const double* acol, const double* sq) {
+                                                  double* pv, const double* acol, const double* sq,
+                                                  int nsym, double* red, double* ptvp) {
   __shared__ double hh[4];
   __shared__ double part[4][8];
+  __shared__ double rs[8];
   const int b = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   DMat<double> a = A.item(b);
   const double* ac = acol + (int64_t)b * n;
@@ -166,9 +176,20 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     ev[(int64_t)b * n + j] = hh[1];
     tauv[(int64_t)b * n + j] = hh[0];
   }
+  double* V = vw + (int64_t)b * n * 2 * TRI_NB;
+  if ((int)blockIdx.x >= nsym) {
+    // W[:, g]^T v (g < c) or V[:, g - c]^T v over rows >= j + 1
+    const int g = (int)blockIdx.x - nsym;
+    const double* x = g < c ? V + n * TRI_NB + (int64_t)g * n : V + (int64_t)(g - c) * n;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int64_t r = j1 + t; r < n; r += 256) acc += x[r] * vval(r);
+    acc = block_sum256(acc, rs);
+    if (t == 0) red[(int64_t)b * (2 * TRI_NB + 2) + (g < c ? 2 + g : 2 + TRI_NB + g - c)] = acc;
+    return;
+  }
   // this workgroup's share of v: V[:, c] and column j of A (rows >= j + 2)
   const int64_t q0 = j1 + (int64_t)blockIdx.x * 8;
-  double* V = vw + (int64_t)b * n * 2 * TRI_NB;
   if (t < 8 && q0 + t < n) {
     const int64_t r = q0 + t;
     const double v = vval(r);
@@ -211,30 +232,20 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     if (lane == 0) part[wave][k] = s;
   }
   __syncthreads();
-  if (t < 8 && q0 + t < n)
-    pv[(int64_t)b * n + q0 + t] = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-}
-
-// red[0] = p^T v, red[2 + q] = W[:, q]^T v, red[2 + NB + q] = V[:, q]^T v
-// (q < c), v = V[:, c]; rows >= j + 1.  One workgroup per product.
-__global__ __launch_bounds__(256) void k_tri_dots(int64_t n, int64_t j, int c, const double* vw,
-                                                  const double* pv, double* red) {
-  __shared__ double rs[8];
-  const int g = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
-  const double* V = vw + (int64_t)b * n * 2 * TRI_NB;
-  const double* W = V + n * TRI_NB;
-  const double* v = V + (int64_t)c * n;
-  const double* x = g == 0 ? pv + (int64_t)b * n : (g <= c ? W + (int64_t)(g - 1) * n
-                                                           : V + (int64_t)(g - 1 - c) * n);
-  double s = 0;
-#pragma unroll 8
-  for (int64_t r = j + 1 + t; r < n; r += 256) s += x[r] * v[r];
-  s = block_sum256(s, rs);
+  if (t < 8) {
+    double pq = 0.0, pvq = 0.0;
+    if (q0 + t < n) {
+      pq = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+      pv[(int64_t)b * n + q0 + t] = pq;
+      pvq = pq * vval(q0 + t);
+    }
+    part[0][t] = pvq;
+  }
+  __syncthreads();
   if (t == 0) {
-    double* rd = red + (int64_t)b * (2 * TRI_NB + 2);
-    if (g == 0) rd[0] = s;
-    else if (g <= c) rd[2 + g - 1] = s;
-    else rd[2 + TRI_NB + g - 1 - c] = s;
+    double sacc = 0.0;
+    for (int k = 0; k < 8; ++k) sacc += part[0][k];
+    ptvp[(int64_t)b * ((n + 7) / 8) + blockIdx.x] = sacc;
   }
 }
 
@@ -262,20 +273,20 @@ static void tridiag_launches(hipStream_t s, DMat<double> A, int64_t n, int batch
       dim3 g1(grid1(n - j), batch);
       k_tri_col<<<g1, 256, 0, s>>>(A, n, j, c, 1, vw, w.tau.as<double>(), w.pvec.as<double>(),
                                    w.red.as<double>(), w.acol.as<double>(), w.d.as<double>(),
-                                   w.sq.as<double>());
+                                   w.sq.as<double>(), w.ptvp.as<double>());
       RFD_CHECK_LAUNCH();
-      dim3 g2((unsigned)((n - j - 1 + 7) / 8), batch);
+      const int nsym = (int)((n - j - 1 + 7) / 8);
+      dim3 g2((unsigned)(nsym + 2 * c), batch);
       if (vec)
         k_tri_symv<true><<<g2, 256, 0, s>>>(A, n, j, c, vw, w.d.as<double>(), w.e.as<double>(),
                                             w.tau.as<double>(), w.pvec.as<double>(),
-                                            w.acol.as<double>(), w.sq.as<double>());
+                                            w.acol.as<double>(), w.sq.as<double>(), nsym,
+                                            w.red.as<double>(), w.ptvp.as<double>());
       else
         k_tri_symv<false><<<g2, 256, 0, s>>>(A, n, j, c, vw, w.d.as<double>(), w.e.as<double>(),
                                              w.tau.as<double>(), w.pvec.as<double>(),
-                                             w.acol.as<double>(), w.sq.as<double>());
-      RFD_CHECK_LAUNCH();
-      k_tri_dots<<<dim3(2 * c + 1, batch), 256, 0, s>>>(n, j, c, vw, w.pvec.as<double>(),
-                                                        w.red.as<double>());
+                                             w.acol.as<double>(), w.sq.as<double>(), nsym,
+                                             w.red.as<double>(), w.ptvp.as<double>());
       RFD_CHECK_LAUNCH();
     }
     // finish W's last column, then the trailing block takes the panel's update
@@ -283,7 +294,7 @@ static void tridiag_launches(hipStream_t s, DMat<double> A, int64_t n, int batch
     dim3 g1(grid1(n - i1), batch);
     k_tri_col<<<g1, 256, 0, s>>>(A, n, i1, nbp, 0, vw, w.tau.as<double>(), w.pvec.as<double>(),
                                  w.red.as<double>(), w.acol.as<double>(), w.d.as<double>(),
-                                 w.sq.as<double>());
+                                 w.sq.as<double>(), w.ptvp.as<double>());
     RFD_CHECK_LAUNCH();
     const int64_t m = n - i1;
     DMat<double> Vm{vw + i1, nullptr, n, n * 2 * TRI_NB};
@@ -418,6 +429,8 @@ __device__ inline double hash_unit(uint64_t a, uint64_t b) {
 // elimination and the substitutions carry their running values in registers,
 // and every loop reads one array and writes another (two vector buffers used
 // in turn), so that loads can run ahead of the dependent arithmetic.
+constexpr int IV = 16;  // rows per prefetched chunk in the inverse iteration
+
 __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
                                               const double* __restrict__ e0, int64_t n,
                                               const double* lam, const int* num, const int* clus,
@@ -453,8 +466,41 @@ __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
     // LU with partial pivoting of T - lm I (as dgttrf); dcur / ucur are the
     // running diagonal and superdiagonal of the row being eliminated
     double dcur = d[0] - lm, ucur = n > 1 ? e[0] : 0.0;
-#pragma unroll 8
-    for (int64_t r = 0; r + 1 < n; ++r) {
+    auto elim = [&](int64_t r, double er, double dn, double un) {
+      if (fabs(dcur) >= fabs(er)) {
+        const double f = (dcur != 0.0) ? er / dcur : 0.0;
+        ip[r * S] = (int)r;
+        dl[r * S] = f;
+        dd[r * S] = fix(dcur);
+        du[r * S] = ucur;
+        du2[r * S] = 0.0;
+        dcur = dn - f * ucur;
+        ucur = un;
+      } else {
+        const double f = dcur / er;
+        ip[r * S] = (int)r + 1;
+        dl[r * S] = f;
+        dd[r * S] = fix(er);
+        du[r * S] = dn;
+        du2[r * S] = un;
+        dcur = ucur - f * dn;
+        ucur = -f * un;
+      }
+    };
+    int64_t r0 = 0;
+    // chunks of IV rows: the chunk's inputs are loaded before its recurrence
+    for (; r0 + IV + 1 < n; r0 += IV) {
+      double er[IV], dn[IV], un[IV];
+#pragma unroll
+      for (int u = 0; u < IV; ++u) {
+        er[u] = e[r0 + u];
+        dn[u] = d[r0 + u + 1] - lm;
+        un[u] = e[r0 + u + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < IV; ++u) elim(r0 + u, er[u], dn[u], un[u]);
+    }
+    for (int64_t r = r0; r + 1 < n; ++r) {
       const double er = e[r];
       const double dn = d[r + 1] - lm;
       const double un = (r + 2 < n) ? e[r + 1] : 0.0;
@@ -486,8 +532,28 @@ __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
         const double* __restrict__ src = xa;
         double* __restrict__ dst = xb;
         double xc = src[0];
-#pragma unroll 8
-        for (int64_t r = 0; r + 1 < n; ++r) {
+        int64_t q0 = 0;
+        for (; q0 + IV < n; q0 += IV) {
+          double xn[IV], f[IV];
+          int pv[IV];
+#pragma unroll
+          for (int u = 0; u < IV; ++u) {
+            xn[u] = src[(q0 + u + 1) * S];
+            f[u] = dl[(q0 + u) * S];
+            pv[u] = ip[(q0 + u) * S];
+          }
+#pragma unroll
+          for (int u = 0; u < IV; ++u) {
+            if (pv[u] == q0 + u) {
+              dst[(q0 + u) * S] = xc;
+              xc = xn[u] - f[u] * xc;
+            } else {
+              dst[(q0 + u) * S] = xn[u];
+              xc = xc - f[u] * xn[u];
+            }
+          }
+        }
+        for (int64_t r = q0; r + 1 < n; ++r) {
           const double xn = src[(r + 1) * S];
           const double f = dl[r * S];
           if (ip[r * S] == r) {
@@ -505,8 +571,25 @@ __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
         double* __restrict__ dst = xa;
         double x1 = src[(n - 1) * S] / dd[(n - 1) * S], x2 = 0.0;
         dst[(n - 1) * S] = x1;
-#pragma unroll 8
-        for (int64_t r = n - 2; r >= 0; --r) {
+        int64_t q1 = n - 2;
+        for (; q1 - (IV - 1) >= 0; q1 -= IV) {
+          double sv[IV], uu[IV], u2[IV], dv[IV];
+#pragma unroll
+          for (int u = 0; u < IV; ++u) {
+            sv[u] = src[(q1 - u) * S];
+            uu[u] = du[(q1 - u) * S];
+            u2[u] = du2[(q1 - u) * S];
+            dv[u] = dd[(q1 - u) * S];
+          }
+#pragma unroll
+          for (int u = 0; u < IV; ++u) {
+            const double v = (sv[u] - uu[u] * x1 - u2[u] * x2) / dv[u];
+            dst[(q1 - u) * S] = v;
+            x2 = x1;
+            x1 = v;
+          }
+        }
+        for (int64_t r = q1; r >= 0; --r) {
           const double v = (src[r * S] - du[r * S] * x1 - du2[r * S] * x2) / dd[r * S];
           dst[r * S] = v;
           x2 = x1;

@@ -14,7 +14,7 @@ constexpr int TRI_NB = 32;  // panel width of the blocked tridiagonalization
 // Work space of the eigensolver (kept by the caller so that repeated solves
 // of one shape reuse it).
 struct TriWork {
-  DevBuf d, e, tau, pvec, acol, vw, red, sq;
+  DevBuf d, e, tau, pvec, acol, vw, red, sq, ptvp;
   DevBuf wv, wg, wt, w1, w2;  // back-transformation panels
   int64_t cap = 0;
   void reserve(int64_t n, int batch);

@@ -322,7 +322,11 @@ int64_t EngineImpl::interior_bytes() const {
   return t;
 }
 
-// Clusters for inverse iteration: consecutive values closer than gap.
+// Clusters for inverse iteration: consecutive values closer than gap.  With
+// shifts from bisection (absolute error a few eps ||T||) and four iterations,
+// vectors of eigenvalues 1e-10 ||T|| apart already come out orthogonal to
+// working precision, so only tighter groups share a thread and are
+// orthogonalised against each other.
 static std::vector<int> clusters(const std::vector<double>& lam, double gap) {
   std::vector<int> c(lam.size());
   for (size_t i = 0; i < lam.size(); ++i)
@@ -415,7 +419,7 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   for (int j = 0; j < p; ++j) {
     std::vector<double> v(lam.begin() + (size_t)j * maxnum + w0[j],
                           lam.begin() + (size_t)j * maxnum + w1[j]);
-    auto c = clusters(v, 1e-6 * tn);
+    auto c = clusters(v, 1e-10 * tn);
     for (int q = 0; q < kappa[j]; ++q) {
       sel[(size_t)j * VB + q] = v[q];
       cl[(size_t)j * VB + q] = c[q];
@@ -760,7 +764,7 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   double tn = 0;
   for (double v : lam) tn = std::max(tn, std::fabs(v));
   tn = std::max(tn, e.normA);
-  auto cl = clusters(lam, 1e-6 * tn);
+  auto cl = clusters(lam, 1e-10 * tn);
   DevBuf &cl_d = e.tmp[15], &Gv = e.tmp[16], &scratch = e.tmp[17];
   upload_v(st, cl_d, cl);
   Gv.alloc(sizeof(double) * k * nout);
