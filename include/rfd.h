@@ -220,18 +220,27 @@ rfd_status rfd_set_timing(rfd_pencil_t pencil, int32_t on);
 rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16);
 
 /*
- * rfd_kernel_accounting / rfd_kernel_stats -- process-wide timing of every
- * launch of the batched GEMM kernel (the matrix-core kernel behind the LU
+ * rfd_kernel_accounting / rfd_kernel_stats -- process-wide, sampled timing of
+ * selected kernels: the batched GEMM (the matrix-core kernel behind the LU
  * updates, the triangular solves, the refinement residuals and the
- * Rayleigh-Ritz products).  When on, each launch is bracketed by HIP events
- * on its own stream and its algorithmic flop count is recorded (2MNK real,
- * 8MNK complex, times the batch).  rfd_kernel_stats synchronises those
- * events and returns, for the 16 instantiations key = 8*fp64 + 4*complex +
- * 2*transA + transB, the number of launches, the summed milliseconds and the
- * summed flops (host arrays of 16 doubles each), then clears the record.
+ * Rayleigh-Ritz products, Secs. 3-5) and the symmetric mat-vec of the dense
+ * eigensolver's tridiagonalization.  With every = k >= 1, every k-th launch
+ * of each kernel gets a pair of HIP events on its own stream, stamped at the
+ * kernel's start and end by the launch itself (around the call for products
+ * handed to rocBLAS), and its algorithmic flop and byte counts are recorded
+ * (GEMM: 2MNK real or 8MNK complex flops; bytes of A and B read once and of
+ * C written, plus read when beta != 0; mat-vec: the trailing block and its
+ * vectors).  every = 0 turns it off.  rfd_kernel_stats synchronises the
+ * events and returns, for 32 keys (host arrays of 32 doubles each), the
+ * number of launches, the number sampled, and the summed milliseconds, flops
+ * and bytes of the sampled launches, then clears the record.  Keys 0..15:
+ * the hand-written GEMM with key = 8*fp64 + 4*complex + 2*transA + transB;
+ * key 16: the tridiagonalization mat-vec; key 17: FP64 products handed to
+ * rocBLAS; the other keys are unused.
  */
-rfd_status rfd_kernel_accounting(int32_t on);
-rfd_status rfd_kernel_stats(double* launches, double* ms, double* flops);
+rfd_status rfd_kernel_accounting(int32_t every);
+rfd_status rfd_kernel_stats(double* launches, double* sampled, double* ms, double* flops,
+                            double* bytes);
 
 /*
  * ---------------------------------------------------------------------------

@@ -86,7 +86,7 @@ def lib():
             "rfd_reset_caches": [P, I32],
             "rfd_test_basis": [P, P, I64, C.POINTER(I64), P],
             "rfd_kernel_accounting": [I32],
-            "rfd_kernel_stats": [P, P, P],
+            "rfd_kernel_stats": [P, P, P, P, P],
             "rfd_phase_times": [P, P],
             "rfd_test_gemm": [I32, I32, I32, I64, I64, I64, F64, F64, P, P, I64, I64, P, P, I64,
                               I64, P, P, I64, I64, I32, P],
@@ -225,17 +225,24 @@ def rfd_reset_caches(h, release=False):
 GEMM_KEYS = {8 * f + 4 * c + 2 * a + b: f"k_gemm<{'double' if f else 'float'}, "
              f"{'true' if c else 'false'}, {'true' if a else 'false'}, {'true' if b else 'false'}>"
              for f in (0, 1) for c in (0, 1) for a in (0, 1) for b in (0, 1)}
+KERNEL_KEYS = dict(GEMM_KEYS)
+KERNEL_KEYS[16] = "k_tri_symv"
+KERNEL_KEYS[17] = "rocblas_dgemm"
 
 
-def rfd_kernel_accounting(on):
-    _check(lib().rfd_kernel_accounting(int(bool(on))))
+def rfd_kernel_accounting(every):
+    """Sample every `every`-th launch of the accounted kernels (0: off)."""
+    _check(lib().rfd_kernel_accounting(int(every)))
 
 
 def rfd_kernel_stats():
-    """{instantiation name: (launches, ms, flops)} since the last call."""
-    L, T, F = np.zeros(16), np.zeros(16), np.zeros(16)
-    _check(lib().rfd_kernel_stats(L.ctypes.data, T.ctypes.data, F.ctypes.data))
-    return {GEMM_KEYS[k]: (int(L[k]), float(T[k]), float(F[k])) for k in range(16) if L[k] > 0}
+    """{kernel name: (launches, sampled, ms, flops, bytes)} since the last
+    call; ms, flops and bytes are summed over the sampled launches."""
+    L, S, T, F, B = (np.zeros(32) for _ in range(5))
+    _check(lib().rfd_kernel_stats(L.ctypes.data, S.ctypes.data, T.ctypes.data, F.ctypes.data,
+                                  B.ctypes.data))
+    return {KERNEL_KEYS[k]: (int(L[k]), int(S[k]), float(T[k]), float(F[k]), float(B[k]))
+            for k in range(32) if L[k] > 0 and k in KERNEL_KEYS}
 
 
 def rfd_set_timing(h, on):

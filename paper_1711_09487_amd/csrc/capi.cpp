@@ -215,14 +215,20 @@ rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16) {
   });
 }
 
-rfd_status rfd_kernel_accounting(int32_t on) {
-  return (rfd_status)capi_guard([&] { KernelAccount::get().enabled = on != 0; });
+rfd_status rfd_kernel_accounting(int32_t every) {
+  return (rfd_status)capi_guard([&] {
+    if (every < 0) throw Error(ST_EINVAL, "need every >= 0");
+    KernelAccount& k = KernelAccount::get();
+    std::lock_guard<std::mutex> g(k.mu);
+    k.every = every;
+  });
 }
 
-rfd_status rfd_kernel_stats(double* launches, double* ms, double* flops) {
+rfd_status rfd_kernel_stats(double* launches, double* sampled, double* ms, double* flops,
+                            double* bytes) {
   return (rfd_status)capi_guard([&] {
-    if (!launches || !ms || !flops) throw Error(ST_EINVAL, "null output");
-    KernelAccount::get().collect(launches, ms, flops, 16);
+    if (!launches || !sampled || !ms || !flops || !bytes) throw Error(ST_EINVAL, "null output");
+    KernelAccount::get().collect(launches, sampled, ms, flops, bytes, KA_KEYS);
   });
 }
 

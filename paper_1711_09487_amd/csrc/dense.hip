@@ -19,43 +19,56 @@ KernelAccount& KernelAccount::get() {
   return a;
 }
 
-KernelAccount::Scope::Scope(hipStream_t s, int key, double flops) : s_(s) {
-  KernelAccount& a = get();
-  if (!a.enabled) return;
+KernelAccount::Scope::Scope(hipStream_t s, int key, double flops, double bytes) : s_(s) {
+  KernelAccount& k = get();
+  if (k.every <= 0 || key < 0 || key >= KA_KEYS) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  std::lock_guard<std::mutex> g(k.mu);
+  if (k.count[key]++ % k.every != 0) return;
   Rec r;
   r.key = key;
   r.flops = flops;
-  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
-  (void)hipEventRecord(r.a, s);
-  std::lock_guard<std::mutex> g(a.mu);
-  rec_ = (int)a.recs.size();
-  a.recs.push_back(r);
+  r.bytes = bytes;
+  if (hipEventCreate(&r.a) != hipSuccess) return;
+  if (hipEventCreate(&r.b) != hipSuccess) {
+    (void)hipEventDestroy(r.a);
+    return;
+  }
+  a_ = r.a;
+  b_ = r.b;
+  k.recs.push_back(r);
 }
 
-KernelAccount::Scope::~Scope() {
-  if (rec_ < 0) return;
-  KernelAccount& a = get();
-  std::lock_guard<std::mutex> g(a.mu);
-  if (rec_ < (int)a.recs.size()) (void)hipEventRecord(a.recs[rec_].b, s_);
+void KernelAccount::Scope::mark_start() {
+  if (a_) (void)hipEventRecord(a_, s_);
 }
 
-void KernelAccount::collect(double* launches, double* ms, double* flops, int nkeys) {
+void KernelAccount::Scope::mark_stop() {
+  if (b_) (void)hipEventRecord(b_, s_);
+}
+
+void KernelAccount::collect(double* launches, double* sampled, double* ms, double* flops,
+                            double* bytes, int nkeys) {
   std::lock_guard<std::mutex> g(mu);
-  for (int k = 0; k < nkeys; ++k) launches[k] = ms[k] = flops[k] = 0;
+  for (int k = 0; k < nkeys; ++k) {
+    launches[k] = (k < KA_KEYS) ? (double)count[k] : 0.0;
+    sampled[k] = ms[k] = flops[k] = bytes[k] = 0;
+  }
   for (auto& r : recs) {
     float t = 0;
     if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess &&
         r.key < nkeys) {
-      launches[r.key] += 1;
+      sampled[r.key] += 1;
       ms[r.key] += t;
       flops[r.key] += r.flops;
+      bytes[r.key] += r.bytes;
     }
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
   recs.clear();
+  for (auto& c : count) c = 0;
 }
 
 // ---------------------------------------------------------------------------

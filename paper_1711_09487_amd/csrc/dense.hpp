@@ -12,23 +12,39 @@ namespace rfd {
 
 constexpr int NB = 64;  // LU / triangular-solve block size (= GEMM tile edge)
 
-// Optional per-launch timing of the GEMM kernel instantiations.
+// Optional per-launch timing of selected kernels, sampled: every `every`-th
+// launch of a key gets a pair of HIP events on its launch stream, stamped by
+// the launch itself (hipExtLaunchKernelGGL) where the kernel is launched
+// here, around the call otherwise, together with the launch's algorithmic
+// flops and bytes.  Keys 0..15: the GEMM instantiations (8 fp64 + 4 complex
+// + 2 transA + transB) of the hand-written kernel; KA_TRI_SYMV: the
+// symmetric mat-vec of the tridiagonalization; KA_ROCBLAS: FP64 products
+// handed to rocBLAS.
+constexpr int KA_KEYS = 32;
+constexpr int KA_TRI_SYMV = 16;
+constexpr int KA_ROCBLAS = 17;
 struct KernelAccount {
   struct Rec {
     int key;
-    double flops;
+    double flops, bytes;
     hipEvent_t a, b;
   };
-  bool enabled = false;
+  int every = 0;  // 0: off
   std::mutex mu;
   std::vector<Rec> recs;
+  int64_t count[KA_KEYS] = {};
   static KernelAccount& get();
-  void collect(double* launches, double* ms, double* flops, int nkeys);
+  void collect(double* launches, double* sampled, double* ms, double* flops, double* bytes,
+               int nkeys);
+  // Decides whether this launch is sampled and holds its events.
   struct Scope {
-    Scope(hipStream_t s, int key, double flops);
-    ~Scope();
+    Scope(hipStream_t s, int key, double flops, double bytes = 0.0);
+    hipEvent_t start() const { return a_; }
+    hipEvent_t stop() const { return b_; }
+    void mark_start();  // for launches that cannot stamp the events themselves
+    void mark_stop();
     hipStream_t s_;
-    int rec_ = -1;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
   };
 };
 

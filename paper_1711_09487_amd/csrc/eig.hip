@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "dense.hpp"
 #include "eig.hpp"
 
@@ -277,16 +279,15 @@ static void tridiag_launches(hipStream_t s, DMat<double> A, int64_t n, int batch
       RFD_CHECK_LAUNCH();
       const int nsym = (int)((n - j - 1 + 7) / 8);
       dim3 g2((unsigned)(nsym + 2 * c), batch);
-      if (vec)
-        k_tri_symv<true><<<g2, 256, 0, s>>>(A, n, j, c, vw, w.d.as<double>(), w.e.as<double>(),
-                                            w.tau.as<double>(), w.pvec.as<double>(),
-                                            w.acol.as<double>(), w.sq.as<double>(), nsym,
-                                            w.red.as<double>(), w.ptvp.as<double>());
-      else
-        k_tri_symv<false><<<g2, 256, 0, s>>>(A, n, j, c, vw, w.d.as<double>(), w.e.as<double>(),
-                                             w.tau.as<double>(), w.pvec.as<double>(),
-                                             w.acol.as<double>(), w.sq.as<double>(), nsym,
-                                             w.red.as<double>(), w.ptvp.as<double>());
+      // algorithmic bytes: the trailing block, the column and p, V / W columns
+      const double nt = (double)(n - j - 1);
+      KernelAccount::Scope acct(s, KA_TRI_SYMV, 2.0 * nt * nt * batch,
+                                8.0 * (nt * nt + 4.0 * nt + 4.0 * c * nt) * batch);
+      hipExtLaunchKernelGGL(vec ? k_tri_symv<true> : k_tri_symv<false>, g2, dim3(256), 0, s,
+                            acct.start(), acct.stop(), 0, A, n, j, c, vw, w.d.as<double>(),
+                            w.e.as<double>(), w.tau.as<double>(), w.pvec.as<double>(),
+                            (const double*)w.acol.as<double>(), (const double*)w.sq.as<double>(),
+                            nsym, w.red.as<double>(), w.ptvp.as<double>());
       RFD_CHECK_LAUNCH();
     }
     // finish W's last column, then the trailing block takes the panel's update

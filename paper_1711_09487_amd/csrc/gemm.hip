@@ -23,6 +23,7 @@
 // the Rayleigh-Ritz step, basis updates Z T, Ritz vectors) go to rocBLAS,
 // whose tuned FP64 kernels run these shapes faster; everything complex,
 // FP32, or tall-skinny runs here.
+#include <hip/hip_ext.h>
 #include <rocblas/rocblas.h>
 
 #include <map>
@@ -371,10 +372,10 @@ static void blas_dgemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, in
 template <typename T, bool CPLX, int BM, int BN>
 static void launch(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N, int64_t K,
                    T alpha, T beta, DMat<T> A, DMat<T> B, DMat<T> C, int splits, int64_t kchunk,
-                   T* part, int va, int vb, int tri) {
-#define RFD_GEMM_GO(TA_, TB_)                                                               \
-  k_gemm<T, CPLX, TA_, TB_, BM, BN><<<g, 256, 0, s>>>(M, N, K, alpha, beta, A, B, C, splits, \
-                                                     kchunk, part, va, vb, tri)
+                   T* part, int va, int vb, int tri, hipEvent_t ea, hipEvent_t eb) {
+#define RFD_GEMM_GO(TA_, TB_)                                                                  \
+  hipExtLaunchKernelGGL(k_gemm<T, CPLX, TA_, TB_, BM, BN>, g, dim3(256), 0, s, ea, eb, 0, M, N, \
+                        K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri)
   if (!ta && !tb) RFD_GEMM_GO(false, false);
   else if (ta && !tb) RFD_GEMM_GO(true, false);
   else if (!ta && tb) RFD_GEMM_GO(false, true);
@@ -416,9 +417,12 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
     const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64) * batch;
     if (!cplx && splits == 1 && t64 >= 512 && K >= 32 && M <= 0x7fffffff && N <= 0x7fffffff &&
         K <= 0x7fffffff) {
-      KernelAccount::Scope acct(s, 8 + (ta ? 2 : 0) + (tb ? 1 : 0),
-                                2.0 * (double)M * (double)N * (double)K * batch);
+      KernelAccount::Scope acct(s, KA_ROCBLAS, 2.0 * (double)M * (double)N * (double)K * batch,
+                                8.0 * ((double)M * K + (double)K * N +
+                                       (beta != 0.0 ? 2.0 : 1.0) * (double)M * N) * batch);
+      acct.mark_start();
       blas_dgemm(s, ta, tb, M, N, K, alpha, A, B, beta, C, batch);
+      acct.mark_stop();
       return;
     }
   }
@@ -438,23 +442,31 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   // a lower-triangle product counts the N (N + 1) / 2 entries it must produce
   const double outs = tri ? 0.5 * (double)N * (double)(N + 1) : (double)M * (double)N;
   const double flops = (cplx ? 8.0 : 2.0) * outs * (double)K * batch;
-  KernelAccount::Scope acct(s, key, flops);
+  // algorithmic bytes: A and B read once, C written (and read when beta != 0)
+  const double planes = cplx ? 2.0 : 1.0;
+  const double bytes = planes * sizeof(T) *
+                       ((double)M * K + (double)K * N + (beta != T(0) ? 2.0 : 1.0) * outs) * batch;
+  KernelAccount::Scope acct(s, key, flops, bytes);
   // 128-wide tiles exist for FP32 only (FP64 products of that size go to rocBLAS)
   if constexpr (sizeof(T) == 4) {
     if (bt == 128) {
-      if (cplx) launch<T, true, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
-      else launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
+      if (cplx) launch<T, true, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri, acct.start(), splits > 1 ? nullptr : acct.stop());
+      else launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri, acct.start(), splits > 1 ? nullptr : acct.stop());
     }
   }
   if (bt == 64 || sizeof(T) == 8) {
-    if (cplx) launch<T, true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
-    else launch<T, false, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri);
+    if (cplx) launch<T, true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri, acct.start(), splits > 1 ? nullptr : acct.stop());
+    else launch<T, false, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri, acct.start(), splits > 1 ? nullptr : acct.stop());
   }
   RFD_CHECK_LAUNCH();
   if (splits > 1) {
     dim3 gr(grid1(M * N), (unsigned)batch);
-    if (cplx) k_splitk_sum<T, true><<<gr, 256, 0, s>>>(M, N, splits, batch, part, beta, C, tri);
-    else k_splitk_sum<T, false><<<gr, 256, 0, s>>>(M, N, splits, batch, part, beta, C, tri);
+    if (cplx)
+      hipExtLaunchKernelGGL(k_splitk_sum<T, true>, gr, dim3(256), 0, s, nullptr, acct.stop(), 0, M,
+                            N, splits, batch, (const T*)part, beta, C, tri);
+    else
+      hipExtLaunchKernelGGL(k_splitk_sum<T, false>, gr, dim3(256), 0, s, nullptr, acct.stop(), 0,
+                            M, N, splits, batch, (const T*)part, beta, C, tri);
     RFD_CHECK_LAUNCH();
   }
 }
