@@ -95,91 +95,104 @@ __device__ inline void cinv(T ar, T ai, T& cr, T& ci) {
 // One workgroup per batch item.
 // ---------------------------------------------------------------------------
 template <typename T, bool CPLX>
-__device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], DMat<T> Linv,
-                             DMat<T> Uinv, const int* dropped = nullptr) {
-  constexpr int NP = CPLX ? 2 : 1;
-  const int tid = threadIdx.x;
-  // Linv: column c solved by thread c (forward substitution, unit diagonal)
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) {
-      T sr = (i == c) ? T(1) : T(0), si = 0;
-      if (i > c) {
-        for (int t = c; t < i; ++t) {
-          if constexpr (CPLX) {
-            T pr, pi;
-            cmul(F[0][i][t], F[NP - 1][i][t], X[0][t][c], X[NP - 1][t][c], pr, pi);
-            sr -= pr;
-            si -= pi;
-          } else {
-            sr -= F[0][i][t] * X[0][t][c];
-          }
-        }
-      }
-      X[0][i][c] = sr;
-      if constexpr (CPLX) X[NP - 1][i][c] = si;
-    }
-  }
-  __syncthreads();
-  // a dropped column (semidefinite mode) gets a zero row in Linv, so that the
-  // panel update leaves a zero row of U beside it
-  if (dropped)
-    for (int e = tid; e < NB * NB; e += blockDim.x)
-      if (dropped[e % NB]) X[0][e % NB][e / NB] = 0;
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int i = e % NB, c = e / NB;
-    Linv.re[i + c * Linv.ld] = X[0][i][c];
-    if constexpr (CPLX) Linv.im[i + c * Linv.ld] = X[NP - 1][i][c];
-  }
-  __syncthreads();
-  // Uinv: column c by thread c (back substitution)
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = NB - 1; i >= 0; --i) {
-      T sr = 0, si = 0;
-      if (i <= c) {
-        sr = (i == c) ? T(1) : T(0);
-        for (int t = i + 1; t <= c; ++t) {
-          if constexpr (CPLX) {
-            T pr, pi;
-            cmul(F[0][i][t], F[NP - 1][i][t], X[0][t][c], X[NP - 1][t][c], pr, pi);
-            sr -= pr;
-            si -= pi;
-          } else {
-            sr -= F[0][i][t] * X[0][t][c];
-          }
-        }
-        if constexpr (CPLX) {
-          T ir, ii, qr, qi;
-          cinv(F[0][i][i], F[NP - 1][i][i], ir, ii);
-          cmul(sr, si, ir, ii, qr, qi);
-          sr = qr;
-          si = qi;
-        } else {
-          sr = sr / F[0][i][i];
-        }
-      }
-      X[0][i][c] = sr;
-      if constexpr (CPLX) X[NP - 1][i][c] = si;
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int i = e % NB, c = e / NB;
-    Uinv.re[i + c * Uinv.ld] = X[0][i][c];
-    if constexpr (CPLX) Uinv.im[i + c * Uinv.ld] = X[NP - 1][i][c];
+__device__ inline void fma_sub(T& sr, T& si, T ar, T ai, T br, T bi) {
+  if constexpr (CPLX) {
+    sr -= ar * br - ai * bi;
+    si -= ar * bi + ai * br;
+  } else {
+    sr -= ar * br;
   }
 }
 
+// Inverses of the unit-lower and the upper triangle of the factored block F,
+// one row at a time: the 64 columns of a row are formed in parallel, each as
+// four partial sums (256 threads), so a row costs at most 16 products per
+// thread and two barriers.  A dropped column (semidefinite mode) gets a zero
+// row in Linv, so that the panel update leaves a zero row of U beside it.
+template <typename T, bool CPLX>
+__device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], T (*P)[4][NB],
+                             DMat<T> Linv, DMat<T> Uinv, const int* dropped = nullptr) {
+  constexpr int NP = CPLX ? 2 : 1;
+  const int tid = threadIdx.x, c = tid & (NB - 1), g = tid >> 6;
+  // Linv: X[i][c] = -sum_{t=c}^{i-1} L[i][t] X[t][c] (c < i), X[i][i] = 1
+  for (int e = tid; e < NB * NB; e += 256) {
+    X[0][e % NB][e / NB] = (e % NB == e / NB) ? T(1) : T(0);
+    if constexpr (CPLX) X[NP - 1][e % NB][e / NB] = 0;
+  }
+  __syncthreads();
+  for (int i = 1; i < NB; ++i) {
+    T sr = 0, si = 0;
+    if (c < i)
+      for (int t = c + g; t < i; t += 4)
+        fma_sub<T, CPLX>(sr, si, F[0][i][t], F[NP - 1][i][t], X[0][t][c], X[NP - 1][t][c]);
+    P[0][g][c] = sr;
+    if constexpr (CPLX) P[NP - 1][g][c] = si;
+    __syncthreads();
+    if (g == 0 && c < i) {
+      X[0][i][c] = P[0][0][c] + P[0][1][c] + P[0][2][c] + P[0][3][c];
+      if constexpr (CPLX) X[NP - 1][i][c] = P[NP - 1][0][c] + P[NP - 1][1][c] + P[NP - 1][2][c] + P[NP - 1][3][c];
+    }
+    __syncthreads();
+  }
+  if (dropped)
+    for (int e = tid; e < NB * NB; e += 256)
+      if (dropped[e % NB]) X[0][e % NB][e / NB] = 0;
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e % NB, cc = e / NB;
+    Linv.re[i + cc * Linv.ld] = X[0][i][cc];
+    if constexpr (CPLX) Linv.im[i + cc * Linv.ld] = X[NP - 1][i][cc];
+  }
+  __syncthreads();
+  // Uinv: X[i][c] = (delta_ic - sum_{t=i+1}^{c} U[i][t] X[t][c]) / U[i][i] (c >= i)
+  for (int e = tid; e < NB * NB; e += 256) {
+    X[0][e % NB][e / NB] = 0;
+    if constexpr (CPLX) X[NP - 1][e % NB][e / NB] = 0;
+  }
+  __syncthreads();
+  for (int i = NB - 1; i >= 0; --i) {
+    T sr = 0, si = 0;
+    if (c >= i)
+      for (int t = i + 1 + g; t <= c; t += 4)
+        fma_sub<T, CPLX>(sr, si, F[0][i][t], F[NP - 1][i][t], X[0][t][c], X[NP - 1][t][c]);
+    P[0][g][c] = sr;
+    if constexpr (CPLX) P[NP - 1][g][c] = si;
+    __syncthreads();
+    if (g == 0 && c >= i) {
+      T vr = (c == i ? T(1) : T(0)) + P[0][0][c] + P[0][1][c] + P[0][2][c] + P[0][3][c];
+      if constexpr (CPLX) {
+        T vi = P[NP - 1][0][c] + P[NP - 1][1][c] + P[NP - 1][2][c] + P[NP - 1][3][c];
+        T ir, ii, qr, qi;
+        cinv(F[0][i][i], F[NP - 1][i][i], ir, ii);
+        cmul(vr, vi, ir, ii, qr, qi);
+        X[0][i][c] = qr;
+        X[NP - 1][i][c] = qi;
+      } else {
+        X[0][i][c] = vr / F[0][i][i];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e % NB, cc = e / NB;
+    Uinv.re[i + cc * Uinv.ld] = X[0][i][cc];
+    if constexpr (CPLX) Uinv.im[i + cc * Uinv.ld] = X[NP - 1][i][cc];
+  }
+}
+
+// Factor one NB x NB diagonal block without pivoting in LDS.  Thread t owns
+// the 4 x 4 sub-block rows 4 (t / 16) .. +3, columns 4 (t % 16) .. +3 of the
+// rank-1 updates.
 template <typename T, bool CPLX>
 __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> inv, int iblk,
                                                  unsigned* flags, T tiny, int* drop, T droptol) {
   constexpr int NP = CPLX ? 2 : 1;
   __shared__ T F[NP][NB][NB + 1];
   __shared__ T X[NP][NB][NB + 1];
+  __shared__ T P[NP][4][NB];
   __shared__ int dl[NB];
   const int tid = threadIdx.x;
+  const int r0 = 4 * (tid >> 4), c0 = 4 * (tid & 15);
   if (tid < NB) dl[tid] = 0;
   DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
   for (int e = tid; e < NB * NB; e += 256) {
@@ -190,7 +203,6 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
   __syncthreads();
   for (int j = 0; j < NB; ++j) {
     const T pr = F[0][j][j], pim = CPLX ? F[NP - 1][j][j] : T(0);
-    const T mag = CPLX ? sqrt(pr * pr + pim * pim) : fabs(pr);
     if (!CPLX && drop && !(pr > droptol)) {
       // semidefinite mode: the Schur complement pivot vanished, so column j
       // lies in the span of the earlier ones; it is removed from the factor
@@ -208,33 +220,50 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
       continue;
     }
     if (tid == 0) {
+      const T mag = CPLX ? sqrt(pr * pr + pim * pim) : fabs(pr);
       if (!(mag > tiny)) atomicOr(flags, (mag == mag) ? 1u : 2u);
     }
-    T ir, ii = 0;
-    if constexpr (CPLX) cinv(pr, pim, ir, ii);
-    else ir = T(1) / pr;
-    for (int i = j + 1 + tid; i < NB; i += 256) {
+    // column j below the diagonal scaled by 1 / pivot (by the 64 lowest threads)
+    if (tid > j && tid < NB) {
+      T ir, ii = 0;
       if constexpr (CPLX) {
+        cinv(pr, pim, ir, ii);
         T qr, qi;
-        cmul(F[0][i][j], F[NP - 1][i][j], ir, ii, qr, qi);
-        F[0][i][j] = qr;
-        F[NP - 1][i][j] = qi;
+        cmul(F[0][tid][j], F[NP - 1][tid][j], ir, ii, qr, qi);
+        F[0][tid][j] = qr;
+        F[NP - 1][tid][j] = qi;
       } else {
-        F[0][i][j] *= ir;
+        ir = T(1) / pr;
+        F[0][tid][j] *= ir;
       }
     }
     __syncthreads();
-    const int w = NB - 1 - j;
-    for (int e = tid; e < w * w; e += 256) {
-      const int i = j + 1 + e % w, c = j + 1 + e / w;
-      if constexpr (CPLX) {
-        T pr2, pi2;
-        cmul(F[0][i][j], F[NP - 1][i][j], F[0][j][c], F[NP - 1][j][c], pr2, pi2);
-        F[0][i][c] -= pr2;
-        F[NP - 1][i][c] -= pi2;
-      } else {
-        F[0][i][c] -= F[0][i][j] * F[0][j][c];
+    // rank-1 update of the trailing block over the owned 4 x 4 entries
+    if (r0 + 3 > j && c0 + 3 > j) {
+      T lr[4], li[4], ur[4], ui[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        lr[q] = F[0][r0 + q][j];
+        ur[q] = F[0][j][c0 + q];
+        if constexpr (CPLX) {
+          li[q] = F[NP - 1][r0 + q][j];
+          ui[q] = F[NP - 1][j][c0 + q];
+        } else {
+          li[q] = ui[q] = 0;
+        }
       }
+#pragma unroll
+      for (int qi = 0; qi < 4; ++qi)
+#pragma unroll
+        for (int qc = 0; qc < 4; ++qc) {
+          const int i = r0 + qi, cc = c0 + qc;
+          if (i > j && cc > j) {
+            T sr = F[0][i][cc], si = CPLX ? F[NP - 1][i][cc] : T(0);
+            fma_sub<T, CPLX>(sr, si, lr[qi], li[qi], ur[qc], ui[qc]);
+            F[0][i][cc] = sr;
+            if constexpr (CPLX) F[NP - 1][i][cc] = si;
+          }
+        }
     }
     __syncthreads();
   }
@@ -244,7 +273,7 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
     if constexpr (CPLX) a.im[i + j * a.ld] = F[NP - 1][i][j];
   }
   DMat<T> iv = inv.item(blockIdx.x);
-  tri_inverses<T, CPLX>(F, X, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB),
+  tri_inverses<T, CPLX>(F, X, P, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB),
                         drop ? dl : nullptr);
 }
 
@@ -254,6 +283,7 @@ __global__ __launch_bounds__(256) void k_tri_inv(DMat<T> A, int64_t k0, DMat<T> 
   constexpr int NP = CPLX ? 2 : 1;
   __shared__ T F[NP][NB][NB + 1];
   __shared__ T X[NP][NB][NB + 1];
+  __shared__ T P[NP][4][NB];
   const int tid = threadIdx.x;
   DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
   for (int e = tid; e < NB * NB; e += 256) {
@@ -263,7 +293,78 @@ __global__ __launch_bounds__(256) void k_tri_inv(DMat<T> A, int64_t k0, DMat<T> 
   }
   __syncthreads();
   DMat<T> iv = inv.item(blockIdx.x);
-  tri_inverses<T, CPLX>(F, X, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB));
+  tri_inverses<T, CPLX>(F, X, P, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB));
+}
+
+// ---------------------------------------------------------------------------
+// Recursive block forms.  Splitting in halves (multiples of NB) puts most of
+// the flops into products with K = n/2, n/4, ... instead of K = NB, so the
+// matrix cores run the large-K GEMM tiles.  Leaves multiply by the inverted
+// NB x NB diagonal blocks written by k_lu_diag (inv = [Linv_0 Uinv_0 Linv_1
+// ...]); a leaf product overwrites its own operand, which is safe because it
+// has a single tile row (M = NB) or column (N = NB).
+// ---------------------------------------------------------------------------
+// B <- L^{-1} B, L = unit-lower factor rows/cols n0 .. n0+nb-1; row i of B is row n0+i
+template <typename T>
+static void trsm_ll(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n0, int64_t nb, DMat<T> B,
+                    int64_t cols, int batch) {
+  if (nb == NB) {
+    gemm<T>(s, false, false, NB, cols, NB, T(1), inv.sub(0, 2 * n0), B, T(0), B, batch);
+    return;
+  }
+  const int64_t h = (nb / NB / 2) * NB;
+  trsm_ll<T>(s, LU, inv, n0, h, B, cols, batch);
+  gemm<T>(s, false, false, nb - h, cols, h, T(-1), LU.sub(n0 + h, n0), B, T(1), B.sub(h, 0), batch);
+  trsm_ll<T>(s, LU, inv, n0 + h, nb - h, B.sub(h, 0), cols, batch);
+}
+
+// B <- U^{-1} B, U = upper factor rows/cols n0 .. n0+nb-1; row i of B is row n0+i
+template <typename T>
+static void trsm_ul(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n0, int64_t nb, DMat<T> B,
+                    int64_t cols, int batch) {
+  if (nb == NB) {
+    gemm<T>(s, false, false, NB, cols, NB, T(1), inv.sub(0, 2 * n0 + NB), B, T(0), B, batch);
+    return;
+  }
+  const int64_t h = (nb / NB / 2) * NB;
+  trsm_ul<T>(s, LU, inv, n0 + h, nb - h, B.sub(h, 0), cols, batch);
+  gemm<T>(s, false, false, h, cols, nb - h, T(-1), LU.sub(n0, n0 + h), B.sub(h, 0), T(1), B, batch);
+  trsm_ul<T>(s, LU, inv, n0, h, B, cols, batch);
+}
+
+// B <- B U^{-1}, U = upper factor rows/cols n0 .. n0+nb-1; column j of B is column n0+j
+template <typename T>
+static void trsm_ur(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n0, int64_t nb, DMat<T> B,
+                    int64_t rows, int batch) {
+  if (nb == NB) {
+    gemm<T>(s, false, false, rows, NB, NB, T(1), B, inv.sub(0, 2 * n0 + NB), T(0), B, batch);
+    return;
+  }
+  const int64_t h = (nb / NB / 2) * NB;
+  trsm_ur<T>(s, LU, inv, n0, h, B, rows, batch);
+  gemm<T>(s, false, false, rows, nb - h, h, T(-1), B, LU.sub(n0, n0 + h), T(1), B.sub(0, h), batch);
+  trsm_ur<T>(s, LU, inv, n0 + h, nb - h, B.sub(0, h), rows, batch);
+}
+
+// LU without pivoting of rows/cols n0 .. n0+nb-1 (all earlier updates applied)
+template <typename T>
+static void lu_rec(hipStream_t s, DMat<T> A, DMat<T> inv, int64_t n0, int64_t nb, int batch,
+                   unsigned* flags, double tiny) {
+  if (nb == NB) {
+    if (A.cplx())
+      k_lu_diag<T, true><<<batch, 256, 0, s>>>(A, n0, inv, (int)(n0 / NB), flags, (T)tiny, nullptr, T(0));
+    else
+      k_lu_diag<T, false><<<batch, 256, 0, s>>>(A, n0, inv, (int)(n0 / NB), flags, (T)tiny, nullptr, T(0));
+    RFD_CHECK_LAUNCH();
+    return;
+  }
+  const int64_t h = (nb / NB / 2) * NB, r = nb - h;
+  lu_rec<T>(s, A, inv, n0, h, batch, flags, tiny);
+  trsm_ll<T>(s, A, inv, n0, h, A.sub(n0, n0 + h), r, batch);   // U12 = L11^{-1} A12
+  trsm_ur<T>(s, A, inv, n0, h, A.sub(n0 + h, n0), r, batch);   // L21 = A21 U11^{-1}
+  gemm<T>(s, false, false, r, r, h, T(-1), A.sub(n0 + h, n0), A.sub(n0, n0 + h), T(1),
+          A.sub(n0 + h, n0 + h), batch);
+  lu_rec<T>(s, A, inv, n0 + h, r, batch, flags, tiny);
 }
 
 template <typename T>
@@ -271,6 +372,11 @@ void lu_nopiv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, unsig
               double tiny, int* drop, double droptol) {
   if (n % NB) throw Error(ST_EINVAL, "lu_nopiv: n not a multiple of the block size");
   if (drop && (A.cplx() || batch != 1)) throw Error(ST_EINVAL, "lu_nopiv: drop mode is real, unbatched");
+  if (!drop) {
+    lu_rec<T>(s, A, inv, 0, n, batch, flags, tiny);
+    return;
+  }
+  // semidefinite drop mode: right-looking, one NB block at a time
   const int64_t nblk = n / NB;
   for (int64_t i = 0; i < nblk; ++i) {
     const int64_t k0 = i * NB, rest = n - k0 - NB;
@@ -410,24 +516,10 @@ template <typename T>
 void lu_solve(hipStream_t s, DMat<T> LU, DMat<T> inv, const int32_t* ipiv, int64_t n, DMat<T> R,
               int64_t r, int batch, int parts) {
   if (n % NB) throw Error(ST_EINVAL, "lu_solve: n not a multiple of the block size");
-  const int64_t nblk = n / NB;
+  if (n == 0 || r <= 0) return;
   if (ipiv && (parts & 1)) laswp<T>(s, R, n, ipiv, 0, n, 0, r, batch);
-  for (int64_t i = 0; i < nblk && (parts & 1); ++i) {
-    const int64_t k0 = i * NB, rest = n - k0 - NB;
-    gemm<T>(s, false, false, NB, r, NB, T(1), inv.sub(0, 2 * NB * i), R.sub(k0, 0), T(0),
-            R.sub(k0, 0), batch);
-    if (rest > 0)
-      gemm<T>(s, false, false, rest, r, NB, T(-1), LU.sub(k0 + NB, k0), R.sub(k0, 0), T(1),
-              R.sub(k0 + NB, 0), batch);
-  }
-  for (int64_t i = nblk - 1; i >= 0 && (parts & 2); --i) {
-    const int64_t k0 = i * NB;
-    gemm<T>(s, false, false, NB, r, NB, T(1), inv.sub(0, 2 * NB * i + NB), R.sub(k0, 0), T(0),
-            R.sub(k0, 0), batch);
-    if (k0 > 0)
-      gemm<T>(s, false, false, k0, r, NB, T(-1), LU.sub(0, k0), R.sub(k0, 0), T(1), R.sub(0, 0),
-              batch);
-  }
+  if (parts & 1) trsm_ll<T>(s, LU, inv, 0, n, R, r, batch);
+  if (parts & 2) trsm_ul<T>(s, LU, inv, 0, n, R, r, batch);
 }
 
 // ---------------------------------------------------------------------------

@@ -365,20 +365,25 @@ void EngineImpl::factor(hipStream_t st) {
                    (int64_t)NB * 2 * SP};
     convert<float, double>(st, S, S3, SP, SP, nc);
     lu_nopiv<float>(st, S3, SP, nc, Si, flags.as<unsigned>(), 1e-30);
-    // the interior factors are no longer needed
-    K32.release();
-    Kinv32.release();
-    X32.release();
-    R64.release();
+    // the interior factors are no longer needed; large ones are released
+    // (a release synchronises the device, small ones stay for the next solve)
+    if (K32.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
+      K32.release();
+      Kinv32.release();
+      X32.release();
+      R64.release();
+    }
   } else {
     Sinv64.alloc(2 * (int64_t)NB * 2 * SP * nc * sizeof(double));
     DMat<double> Si{Sinv64.as<double>(), Sinv64.as<double>() + (int64_t)NB * 2 * SP * nc, NB,
                     (int64_t)NB * 2 * SP};
     lu_nopiv<double>(st, S, SP, nc, Si, flags.as<unsigned>(), 1e-300);
-    K64.release();
-    Kinv64.release();
+    if (K64.bytes > (size_t(16) << 30)) {
+      K64.release();
+      Kinv64.release();
+    }
   }
-  X64.release();
+  if (X64.bytes > (size_t(8) << 30)) X64.release();
   timer.end(st);
   check_flags(st, "Schur complement factorization");
   factored = true;

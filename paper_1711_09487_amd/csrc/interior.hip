@@ -445,7 +445,6 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   upload_v(st, kap_d, kappa);
   timer.end(st);
   RFD_HIP(hipStreamSynchronize(st));
-  work2.release();
   vcache_valid = true;
   vcache_sigma = sig;
   vcache_nevb = nevb;
