@@ -220,6 +220,18 @@ rfd_status rfd_set_timing(rfd_pencil_t pencil, int32_t on);
 rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16);
 
 /*
+ * rfd_set_pole_window -- the filter (eq. (3.5)) sums over the poles; by
+ * default the factors of B_j - zeta_l M_Bj's Schur complements S(zeta_l) for
+ * all poles are kept on the device together when they fit in the free device
+ * memory, and are otherwise computed and applied a window of poles at a time
+ * (each window's factors replace the previous ones, so every application of
+ * the filter factors again).  max_poles >= 1 caps the window at that many
+ * poles; 0 restores the default.  Results do not depend on the window beyond
+ * the order of the final sum.  Errors: RFD_EINVAL for max_poles < 0.
+ */
+rfd_status rfd_set_pole_window(rfd_pencil_t pencil, int32_t max_poles);
+
+/*
  * rfd_kernel_accounting / rfd_kernel_stats -- process-wide, sampled timing of
  * selected kernels: the batched GEMM (the matrix-core kernel behind the LU
  * updates, the triangular solves, the refinement residuals and the

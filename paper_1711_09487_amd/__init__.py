@@ -29,7 +29,7 @@ EXPORTS = [
     "rfd_set_precision", "rfd_filter_interface", "rfd_filter_apply", "rfd_solve_interior",
     "rfd_rayleigh_ritz",
     "rfd_destroy_pencil", "rfd_last_error", "rfd_pencil_info", "rfd_set_timing",
-    "rfd_phase_times", "rfd_reset_caches", "rfd_batch_run", "rfd_server_create",
+    "rfd_phase_times", "rfd_reset_caches", "rfd_set_pole_window", "rfd_batch_run", "rfd_server_create",
     "rfd_server_submit", "rfd_server_poll", "rfd_server_destroy", "rfd_server_stats",
 ]
 
@@ -83,6 +83,7 @@ def lib():
             "rfd_pencil_info": [P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I64),
                                 C.POINTER(I64), C.POINTER(I64)],
             "rfd_set_timing": [P, I32],
+            "rfd_set_pole_window": [P, I32],
             "rfd_reset_caches": [P, I32],
             "rfd_test_basis": [P, P, I64, C.POINTER(I64), P],
             "rfd_kernel_accounting": [I32],
@@ -245,6 +246,10 @@ def rfd_kernel_stats():
             for k in range(32) if L[k] > 0 and k in KERNEL_KEYS}
 
 
+def rfd_set_pole_window(h, max_poles):
+    _check(lib().rfd_set_pole_window(h, int(max_poles)))
+
+
 def rfd_set_timing(h, on):
     _check(lib().rfd_set_timing(h, int(bool(on))))
 
@@ -316,6 +321,9 @@ class Pencil:
 
     def set_timing(self, on=True):
         rfd_set_timing(self.h, on)
+
+    def set_pole_window(self, max_poles):
+        rfd_set_pole_window(self.h, max_poles)
 
     def phase_times(self):
         return rfd_phase_times(self.h)

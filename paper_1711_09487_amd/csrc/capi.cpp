@@ -27,6 +27,7 @@ struct rfd_pencil_s {
   double tol = 1e-13;
   int sweeps = 8;
   bool timing = false;
+  int window = 0;
   std::unique_ptr<Engine> eng;
 };
 
@@ -85,6 +86,7 @@ rfd_status rfd_set_partition(rfd_pencil_t pencil, int32_t p, const int32_t* part
     P->part = std::move(pt);
     P->eng->set_precision(P->mode, P->tol, P->sweeps);
     P->eng->set_timing(P->timing);
+    P->eng->set_pole_window(P->window);
     if (P->poles.set) P->eng->set_poles(P->poles);
   });
 }
@@ -203,6 +205,15 @@ rfd_status rfd_set_timing(rfd_pencil_t pencil, int32_t on) {
     auto* P = need(pencil);
     P->timing = on != 0;
     if (P->eng) P->eng->set_timing(P->timing);
+  });
+}
+
+rfd_status rfd_set_pole_window(rfd_pencil_t pencil, int32_t max_poles) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    if (max_poles < 0) throw Error(ST_EINVAL, "need max_poles >= 0");
+    P->window = max_poles;
+    if (P->eng) P->eng->set_pole_window(max_poles);
   });
 }
 

@@ -172,6 +172,11 @@ void Engine::reset_caches(bool release) {
 }
 
 void Engine::set_timing(bool on) { d_->timer.enabled = on; }
+
+void Engine::set_pole_window(int w) {
+  if (d_->max_window != w) d_->factored = false;
+  d_->max_window = w;
+}
 void Engine::phase_times(double* ms16) { d_->timer.collect(ms16); }
 
 // ---------------------------------------------------------------------------
@@ -272,17 +277,17 @@ int EngineImpl::pole_chunk() const {
 // ---------------------------------------------------------------------------
 // Factorizations for every pole (Sec. 3.1).
 // ---------------------------------------------------------------------------
-void EngineImpl::factor(hipStream_t st) {
-  const int nc = poles.n_c;
+void EngineImpl::factor(hipStream_t st, int w0, int wn) {
+  const int nc = wn;  // poles in the window; pole index = w0 + item
   Shifts z{zeta.as<double>()};
-  const int chunk = pole_chunk();
+  const int chunk = std::min(pole_chunk(), wn);
   const int items_max = chunk * p;
   // Schur complements (FP64 planar), all poles
   const int64_t sbytes = SP * SP * (int64_t)nc * sizeof(double);
   S64.alloc(2 * sbytes);
   DMat<double> S{S64.as<double>(), S64.as<double>() + SP * SP * nc, SP, SP * SP};
   fill<double>(st, S, SP, SP, nc, 0.0);
-  schur_init(st, S, s, SP, nc, 0, Cg.view(), z);
+  schur_init(st, S, s, SP, nc, w0, Cg.view(), z);
   const int64_t kk = D * D * (int64_t)items_max, ki = (int64_t)NB * 2 * D * items_max,
                 xs = D * SJ * (int64_t)items_max;
   const bool fp32 = (mode == 1);
@@ -297,8 +302,8 @@ void EngineImpl::factor(hipStream_t st) {
   X64.alloc(2 * xs * sizeof(double));
   if (fp32) R64.alloc(2 * xs * sizeof(double));
   int max_sweeps_used = 0;
-  for (int l0 = 0; l0 < nc; l0 += chunk) {
-    const int np = std::min(chunk, nc - l0);
+  for (int l0 = w0; l0 < w0 + nc; l0 += chunk) {
+    const int np = std::min(chunk, w0 + nc - l0);
     const int items = np * p;
     DMat<double> X{X64.as<double>(), X64.as<double>() + xs, D, D * SJ};
     timer.begin(st, 0);
@@ -347,7 +352,7 @@ void EngineImpl::factor(hipStream_t st) {
       timer.end(st);
     }
     timer.begin(st, 2);
-    DMat<double> Sc = S.item(l0);
+    DMat<double> Sc = S.item(l0 - w0);
     for (size_t c = 0; c < colors_d.size(); ++c)
       schur_scatter(st, Sc, X, SJ, p, np, l0, colors_d[c].as<int32_t>(),
                     (int)P->colors[c].size(), sj.as<int32_t>(), adj.as<int32_t>(), Etg.view(), z);
@@ -386,14 +391,59 @@ void EngineImpl::factor(hipStream_t st) {
   if (X64.bytes > (size_t(8) << 30)) X64.release();
   timer.end(st);
   check_flags(st, "Schur complement factorization");
-  factored = true;
+  win0 = w0;
+  winn = wn;
+  factored = (w0 == 0 && wn == poles.n_c);
+}
+
+// Poles whose factors fit together in the device memory: all of them when
+// they fit, else the largest window that does (at least one pole).
+int EngineImpl::pole_window() const {
+  const int nc = poles.n_c;
+  const int64_t esS = (mode == 1) ? 8 + 4 : 8;  // FP64 S plus the FP32 copy
+  const int64_t per_pole = 2 * SP * SP * esS + 2 * (int64_t)NB * 2 * SP * (mode == 1 ? 4 : 8) +
+                           3 * 2 * SP * round_up(std::max<int64_t>(s, 1), NB) * 8;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return nc;
+  }
+  // what this pencil already holds counts as available
+  const double avail = 0.8 * ((double)fr + (double)bytes_held());
+  const int64_t chunk_bytes =
+      (int64_t)p * (D * D * (mode == 1 ? 8 : 16) + (int64_t)NB * 2 * D * (mode == 1 ? 8 : 16) +
+                    D * SJ * (mode == 1 ? 48 : 16));
+  int w = (max_window > 0) ? std::min(max_window, nc) : nc;
+  while (w > 1 && (double)w * per_pole + (double)chunk_bytes > avail) --w;
+  return w;
+}
+
+void EngineImpl::run_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* W,
+                            int64_t ldw) {
+  const int nc = poles.n_c;
+  if (factored) {
+    apply_filter(st, Y, ldy, m, W, ldw, false);
+    return;
+  }
+  const int w = pole_window();
+  if (w >= nc) {
+    factor(st, 0, nc);
+    apply_filter(st, Y, ldy, m, W, ldw, false);
+    return;
+  }
+  for (int l = 0; l < nc; l += w) {
+    factor(st, l, std::min(w, nc - l));
+    apply_filter(st, Y, ldy, m, W, ldw, l > 0);
+  }
+  factored = false;  // only the last window's factors are held
 }
 
 // W = 2 Re sum_l omega_l S(zeta_l)^{-1} Y  (eq. (3.5)); Y real s x m (ld ldy),
 // W real (ld ldw).  FP32 mode refines every pole's solve against S_64.
 void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* Wout,
-                              int64_t ldw) {
-  const int nc = poles.n_c;
+                              int64_t ldw, bool add) {
+  const int nc = winn;
+  const double* om = omega.as<double>() + 2 * (int64_t)win0;
   const int64_t MP = round_up(m, NB);
   const int64_t ys = SP * MP * (int64_t)nc;
   Yc.alloc(2 * ys * sizeof(double));
@@ -432,13 +482,13 @@ void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int 
                                     std::to_string(r / ymax) + ")");
     }
     timer.sweeps_filter = std::max(timer.sweeps_filter, sw + 1);
-    filter_accumulate(st, X, omega.as<double>(), nc, Wout, ldw, s, m, false);
+    filter_accumulate(st, X, om, nc, Wout, ldw, s, m, add);
   } else {
     DMat<double> Si{Sinv64.as<double>(), Sinv64.as<double>() + (int64_t)NB * 2 * SP * nc, NB,
                     (int64_t)NB * 2 * SP};
     broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);
     lu_solve<double>(st, S, Si, nullptr, SP, Ycm, MP, nc);
-    filter_accumulate(st, Ycm, omega.as<double>(), nc, Wout, ldw, s, m, false);
+    filter_accumulate(st, Ycm, om, nc, Wout, ldw, s, m, add);
   }
   timer.end(st);
 }
@@ -447,7 +497,6 @@ void Engine::filter_interface(hipStream_t st, int m, const double* Y0, int steps
                               int64_t ldq_cols, int* mu) {
   EngineImpl& e = *d_;
   if (!e.poles.set) throw Error(ST_ESTATE, "poles not set");
-  if (!e.factored) e.factor(st);
   const int64_t s = e.s;
   const int64_t cap = std::min<int64_t>(ldq_cols, std::min<int64_t>(s, (int64_t)steps * m));
   e.W.alloc(sizeof(double) * s * (int64_t)m);
@@ -455,10 +504,10 @@ void Engine::filter_interface(hipStream_t st, int m, const double* Y0, int steps
   int total = 0, prev0 = 0, prevw = 0;
   for (int t = 1; t <= steps; ++t) {
     if (t == 1) {
-      e.apply_filter(st, Y0, s, m, W, s);
+      e.run_filter(st, Y0, s, m, W, s);
     } else {
       if (prevw == 0 || total >= cap) break;
-      e.apply_filter(st, Q + (int64_t)prev0 * s, s, prevw, W, s);
+      e.run_filter(st, Q + (int64_t)prev0 * s, s, prevw, W, s);
     }
     const int width = (t == 1) ? m : prevw;
     const int room = (int)(cap - total);
@@ -483,8 +532,7 @@ void Engine::filter_interface(hipStream_t st, int m, const double* Y0, int steps
 void Engine::filter_apply(hipStream_t st, int m, const double* Y, double* W) {
   EngineImpl& e = *d_;
   if (!e.poles.set) throw Error(ST_ESTATE, "poles not set");
-  if (!e.factored) e.factor(st);
-  e.apply_filter(st, Y, e.s, m, W, e.s);
+  e.run_filter(st, Y, e.s, m, W, e.s);
 }
 
 }  // namespace rfd

@@ -29,6 +29,7 @@ class Engine {
   void reset_caches(bool release);
   void copy_basis(hipStream_t s, double* dst, int64_t cap, int64_t* k);
   void set_timing(bool on);
+  void set_pole_window(int w);
   void phase_times(double* ms16);
 
  private:

@@ -95,8 +95,17 @@ struct EngineImpl {
   void zero_scalar(hipStream_t s, int i);
   void check_flags(hipStream_t s, const char* what);
   int pole_chunk() const;
-  void factor(hipStream_t st);
-  void apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* W, int64_t ldw);
+  // Factors poles [w0, w0 + wn) (the "window": S buffers hold wn poles)
+  void factor(hipStream_t st, int w0, int wn);
+  // W (=, or += when add) 2 Re sum over the window of omega_l S_l^{-1} Y
+  void apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* W, int64_t ldw,
+                    bool add);
+  // The filter over every pole: factored once when all poles fit the device
+  // memory, else window by window (factors dropped after their window)
+  void run_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* W, int64_t ldw);
+  int pole_window() const;  // poles whose factors fit together (n_c when all do)
+  int win0 = 0, winn = 0;
+  int max_window = 0;  // caller's cap on the pole window (0: by free memory)
   void ensure_reordered(hipStream_t st);
   void interior_basis(hipStream_t st, double sigma, int nev_b);
   void factor_bsigma(hipStream_t st, double sigma);

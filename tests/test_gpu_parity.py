@@ -106,6 +106,31 @@ def test_filter_apply_elementwise(name, mode):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("window", [1, 3])
+def test_pole_windows_match_the_oracle(window, mode):
+    """Poles factored and applied a window at a time (the path taken when the
+    factors of all poles do not fit the device memory) give the filter of
+    eq. (3.5) and the same Ritz values."""
+    torch = _torch()
+    prob, ro = _prob("mid_7tiles")              # 8 poles: windows of 1 and of 3, 3, 2
+    dd = O.DD(prob.A, prob.M, prob.part)
+    z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
+    ref = O.filter_apply(O.factor_poles(dd, z), w, prob.Y0)
+    P = _pencil(prob, mode)
+    P.set_pole_window(window)
+    Wg = P.filter_apply(_dev_block(torch, prob.Y0)).cpu().numpy().T
+    err = np.max(np.abs(Wg - ref)) / np.max(np.abs(ref))
+    assert err < (1e-12 if mode == 0 else 1e-11), err
+    P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
+    P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+    ev, _, _ = P.rayleigh_ritz(max(prob.nev + 20, 64), vectors=False)
+    th = ev.cpu().numpy()
+    P.close()
+    assert th.size == ro.theta.size
+    assert np.max(np.abs(th - ro.theta) / np.abs(ro.theta)) <= EIG_TOL
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("name", list(CASES))
 def test_end_to_end_parity(name, mode):
     prob, ro = _prob(name)

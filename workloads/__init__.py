@@ -213,7 +213,9 @@ class Problem:
 
 
 def grid_problem(name, cfg_id, shape, P, nev, n_c, m, steps, nev_b, psi,
-                 mass_kind="identity", kfield=False, rule="gauss", sigma="center"):
+                 mass_kind="identity", kfield=False, rule="gauss", sigma="center", known=None):
+    """known = (alpha, beta, lam) skips the reference eigensolve (values stored
+    by a previous run of it, e.g. for the 63^3 pencil)."""
     shape = tuple(shape)
     n = int(np.prod(shape))
     kc = np.exp(rng(cfg_id, STREAM_K).standard_normal(n)) if kfield else None
@@ -221,7 +223,10 @@ def grid_problem(name, cfg_id, shape, P, nev, n_c, m, steps, nev_b, psi,
     M = mass(n, mass_kind, rng(cfg_id, STREAM_M), A)
     part = grid_partition(shape, P)
     closed = shape if (mass_kind == "identity" and not kfield) else None
-    alpha, beta, lam = interval_lowest(A, M, nev, closed)
+    if known is not None:
+        alpha, beta, lam = float(known[0]), float(known[1]), np.asarray(known[2])
+    else:
+        alpha, beta, lam = interval_lowest(A, M, nev, closed)
     s = int(np.count_nonzero(part < 0))
     m = min(m, s)
     Y0 = random_block(s, m, rng(cfg_id, STREAM_Y0))
@@ -232,7 +237,7 @@ def grid_problem(name, cfg_id, shape, P, nev, n_c, m, steps, nev_b, psi,
                    meta=dict(cfg_id=cfg_id, P=P, mass=mass_kind, kfield=kfield))
 
 
-def config(i: int) -> Problem:
+def config(i: int, known=None) -> Problem:
     """The measured workloads.
 
     1: 2D 31x31, M = I, 2x2 partition (4 interiors of 15x15, s = 61), lowest 20,
@@ -240,7 +245,9 @@ def config(i: int) -> Problem:
     2: 2D 255x255, M = diag U[0.5,1.5], 8x8 partition (31x31 interiors,
        s = 3521), lowest 200, 8 poles, m = 300.
     3: 3D 63^3, M = diag U[0.5,1.5], 4x4x4 partition (15^3 interiors,
-       s = 34047), lowest 500, 8 poles, m = 700.
+       s = 34047), lowest 500, 8 poles, m = 700.  Its interval needs the 501
+       lowest eigenvalues of a 250047 x 250047 pencil; pass known = (alpha,
+       beta, lam) from a stored run to skip that eigensolve.
     """
     if i == 1:
         return grid_problem("C1 2D 31x31 M=I p=4", 1, (31, 31), 2, 20, 4, 30, 2, 20, 4)
@@ -249,7 +256,7 @@ def config(i: int) -> Problem:
                             mass_kind="random")
     if i == 3:
         return grid_problem("C3 3D 63^3 Mdiag p=64", 3, (63, 63, 63), 4, 500, 8, 700, 1, 20, 4,
-                            mass_kind="random")
+                            mass_kind="random", known=known)
     raise ValueError(i)
 
 
