@@ -269,7 +269,7 @@ int EngineImpl::pole_chunk() const {
   const int64_t items_bytes_per_pole =
       (int64_t)p * (D * D * (mode == 1 ? 8 : 16) + NB * 2 * D * (mode == 1 ? 8 : 16) +
                     D * SJ * (mode == 1 ? 16 + 16 + 8 + 8 : 16));
-  const int64_t budget = int64_t(96) << 30;
+  const int64_t budget = int64_t(48) << 30;
   int c = (int)std::max<int64_t>(1, budget / std::max<int64_t>(items_bytes_per_pole, 1));
   return std::min(c, poles.n_c);
 }
@@ -397,12 +397,20 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
 }
 
 // Poles whose factors fit together in the device memory: all of them when
-// they fit, else the largest window that does (at least one pole).
-int EngineImpl::pole_window() const {
+// they fit, else the largest window that does (at least one pole).  Counts
+// the FP64 Schur complements (and the FP32 copies), their block inverses, the
+// filter's right-hand sides for a block of m columns, and the interior
+// factors of the poles processed together.
+int EngineImpl::pole_window(int m) const {
   const int nc = poles.n_c;
-  const int64_t esS = (mode == 1) ? 8 + 4 : 8;  // FP64 S plus the FP32 copy
-  const int64_t per_pole = 2 * SP * SP * esS + 2 * (int64_t)NB * 2 * SP * (mode == 1 ? 4 : 8) +
-                           3 * 2 * SP * round_up(std::max<int64_t>(s, 1), NB) * 8;
+  const bool f32 = mode == 1;
+  const int64_t MP = round_up(std::max(m, 1), NB);
+  const int64_t per_pole = 2 * SP * SP * (f32 ? 8 + 4 : 8) +
+                           2 * (int64_t)NB * 2 * SP * (f32 ? 4 : 8) +
+                           2 * SP * MP * (f32 ? 8 + 8 + 4 : 8);
+  const int64_t per_chunk_pole =
+      (int64_t)p * (D * D * (f32 ? 8 : 16) + (int64_t)NB * 2 * D * (f32 ? 8 : 16) +
+                    D * SJ * (f32 ? 48 : 16));
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
     (void)hipGetLastError();
@@ -410,11 +418,11 @@ int EngineImpl::pole_window() const {
   }
   // what this pencil already holds counts as available
   const double avail = 0.8 * ((double)fr + (double)bytes_held());
-  const int64_t chunk_bytes =
-      (int64_t)p * (D * D * (mode == 1 ? 8 : 16) + (int64_t)NB * 2 * D * (mode == 1 ? 8 : 16) +
-                    D * SJ * (mode == 1 ? 48 : 16));
   int w = (max_window > 0) ? std::min(max_window, nc) : nc;
-  while (w > 1 && (double)w * per_pole + (double)chunk_bytes > avail) --w;
+  auto need = [&](int wn) {
+    return (double)wn * per_pole + (double)std::min(pole_chunk(), wn) * per_chunk_pole;
+  };
+  while (w > 1 && need(w) > avail) --w;
   return w;
 }
 
@@ -425,7 +433,7 @@ void EngineImpl::run_filter(hipStream_t st, const double* Y, int64_t ldy, int m,
     apply_filter(st, Y, ldy, m, W, ldw, false);
     return;
   }
-  const int w = pole_window();
+  const int w = pole_window(m);
   if (w >= nc) {
     factor(st, 0, nc);
     apply_filter(st, Y, ldy, m, W, ldw, false);
@@ -435,7 +443,13 @@ void EngineImpl::run_filter(hipStream_t st, const double* Y, int64_t ldy, int m,
     factor(st, l, std::min(w, nc - l));
     apply_filter(st, Y, ldy, m, W, ldw, l > 0);
   }
-  factored = false;  // only the last window's factors are held
+  // only the last window's factors would remain: they are released, making
+  // room for the interior part (the next application factors again)
+  RFD_HIP(hipStreamSynchronize(st));
+  for (DevBuf* b : {&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32, &Sinv32,
+                    &Sinv64, &Yc, &Xf, &Rf, &Rf32})
+    b->release();
+  factored = false;
 }
 
 // W = 2 Re sum_l omega_l S(zeta_l)^{-1} Y  (eq. (3.5)); Y real s x m (ld ldy),
@@ -471,7 +485,16 @@ void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int 
       lu_solve<float>(st, S3, Si, nullptr, SP, R3, MP, nc);
       add_to<double, float>(st, R3, X, SP, MP, nc);
       broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);
-      gemm<double>(st, false, false, SP, MP, SP, -1.0, S, X, 1.0, Ycm, nc);
+      // R = Y - S_64 X as four real products on the planes (large real FP64
+      // products run on rocBLAS)
+      {
+        auto re = [](DMat<double> a) { a.im = nullptr; return a; };
+        auto im = [](DMat<double> a) { a.re = a.im; a.im = nullptr; return a; };
+        gemm<double>(st, false, false, SP, MP, SP, -1.0, re(S), re(X), 1.0, re(Ycm), nc);
+        gemm<double>(st, false, false, SP, MP, SP, 1.0, im(S), im(X), 1.0, re(Ycm), nc);
+        gemm<double>(st, false, false, SP, MP, SP, -1.0, re(S), im(X), 1.0, im(Ycm), nc);
+        gemm<double>(st, false, false, SP, MP, SP, -1.0, im(S), re(X), 1.0, im(Ycm), nc);
+      }
       zero_scalar(st, 0);
       absmax<double>(st, Ycm, SP, MP, nc, scal.as<double>());
       const double r = read_scalar(st, 0);

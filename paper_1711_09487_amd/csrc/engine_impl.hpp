@@ -103,7 +103,7 @@ struct EngineImpl {
   // The filter over every pole: factored once when all poles fit the device
   // memory, else window by window (factors dropped after their window)
   void run_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* W, int64_t ldw);
-  int pole_window() const;  // poles whose factors fit together (n_c when all do)
+  int pole_window(int m) const;  // poles whose factors fit together (n_c when all do)
   int win0 = 0, winn = 0;
   int max_window = 0;  // caller's cap on the pole window (0: by free memory)
   void ensure_reordered(hipStream_t st);

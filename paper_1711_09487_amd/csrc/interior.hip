@@ -177,23 +177,39 @@ __global__ void k_build_level(double* L, int64_t ldl, DMat<double> Lev, int t, i
   L[i + c * ldl] = v;
 }
 
-// Y = op X with op a CSR matrix (n x n) (Y, X dense n x cols).
+// Y = op X with op a CSR matrix (n x n) (Y, X dense n x cols).  One thread
+// per row and group of four columns: the row's entries are read once for the
+// four columns; the y grid dimension runs over column groups.
 __global__ void k_csr_mm(const int64_t* ptr, const int32_t* idx, const double* val, int64_t n,
                          const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t cols) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * cols) return;
-  const int64_t r = e % n, c = e / n;
-  double acc = 0;
-  for (int64_t q = ptr[r]; q < ptr[r + 1]; ++q) acc += val[q] * X[idx[q] + c * ldx];
-  Y[r + c * ldy] = acc;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t c0 = (int64_t)blockIdx.y * 4;
+  const int nc = (int)((cols - c0) < 4 ? (cols - c0) : 4);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t q1 = ptr[r + 1];
+  for (int64_t q = ptr[r]; q < q1; ++q) {
+    const double v = val[q];
+    const double* x = X + idx[q] + c0 * ldx;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < nc) acc[u] += v * x[u * ldx];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (u < nc) Y[r + (c0 + u) * ldy] = acc[u];
 }
 
 static void csr_mm(hipStream_t s, const DevBuf& ptr, const DevBuf& idx, const DevBuf& val,
                    int64_t n, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t cols) {
-  if (cols <= 0) return;
-  k_csr_mm<<<grid1(n * cols), 256, 0, s>>>(ptr.as<int64_t>(), idx.as<int32_t>(), val.as<double>(),
-                                           n, X, ldx, Y, ldy, cols);
-  RFD_CHECK_LAUNCH();
+  if (cols <= 0 || n <= 0) return;
+  for (int64_t c = 0; c < cols; c += 4 * 65535) {
+    const int64_t cc = std::min<int64_t>(cols - c, 4 * 65535);
+    dim3 g(grid1(n), (unsigned)((cc + 3) / 4));
+    k_csr_mm<<<g, 256, 0, s>>>(ptr.as<int64_t>(), idx.as<int32_t>(), val.as<double>(), n,
+                               X + c * ldx, ldx, Y + c * ldy, ldy, cc);
+    RFD_CHECK_LAUNCH();
+  }
 }
 
 // out[c] = sqrt(x_c^T Y_c) (M-norms with Y = M X), one workgroup per column.
