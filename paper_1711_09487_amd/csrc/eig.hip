@@ -83,6 +83,16 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
         W[r + q * n] = 0.0;
       }
   }
+  // this row of V and W (all loads issued together), and the inputs of the
+  // previous column's W
+  double vr[TRI_NB], wrow[TRI_NB];
+#pragma unroll
+  for (int q = 0; q < TRI_NB; ++q) {
+    vr[q] = (act && q < c) ? V[r + q * n] : 0.0;
+    wrow[q] = (act && q < c - 1) ? W[r + q * n] : 0.0;
+  }
+  const double pr = (act && c >= 1) ? p[r] : 0.0;
+  const double ajr = (act && upd) ? a.re[r + j * a.ld] : 0.0;
   if (t < c) {
     Vj[t] = V[j + (int64_t)t * n];
     if (t < c - 1) {
@@ -92,7 +102,6 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
     }
   }
   __syncthreads();
-  double wr = 0.0;
   if (c >= 1) {
     // p^T v of the previous column: partial sums of its mat-vec workgroups
     const int np = (int)((n - j + 7) / 8);
@@ -111,23 +120,29 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
       Wj[c - 1] = tp * acc + al * Vj[c - 1];
     }
     if (act) {
-      double acc = p[r];
-#pragma unroll 8
-      for (int q = 0; q < c - 1; ++q) acc -= V[r + q * n] * xs[q] + W[r + q * n] * ys[q];
-      wr = tp * acc + al * V[r + (int64_t)(c - 1) * n];
-      W[r + (int64_t)(c - 1) * n] = wr;
+      double acc = pr;
+#pragma unroll
+      for (int q = 0; q < TRI_NB; ++q)
+        if (q < c - 1) acc -= vr[q] * xs[q] + wrow[q] * ys[q];
+      double wc = 0.0;
+#pragma unroll
+      for (int q = 0; q < TRI_NB; ++q)
+        if (q == c - 1) wc = vr[q];
+      wc = tp * acc + al * wc;
+#pragma unroll
+      for (int q = 0; q < TRI_NB; ++q)
+        if (q == c - 1) wrow[q] = wc;
+      W[r + (int64_t)(c - 1) * n] = wc;
     }
     __syncthreads();
   }
   if (!upd) return;
   double ar = 0.0;
   if (act) {
-    ar = a.re[r + j * a.ld];
-#pragma unroll 8
-    for (int q = 0; q < c; ++q) {
-      const double wq = (q == c - 1) ? wr : W[r + q * n];
-      ar -= V[r + q * n] * Wj[q] + wq * Vj[q];
-    }
+    ar = ajr;
+#pragma unroll
+    for (int q = 0; q < TRI_NB; ++q)
+      if (q < c) ar -= vr[q] * Wj[q] + wrow[q] * Vj[q];
     acol[(int64_t)b * n + r] = ar;
     if (r == j) dv[(int64_t)b * n + j] = ar;
   }

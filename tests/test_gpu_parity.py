@@ -6,8 +6,8 @@ nev_b, psi, steps) through both sides:
   * the interface subspace (same number of columns, principal angles);
   * the Ritz values in [alpha, beta] (relative error <= 1e-10), their
     residuals, and the Ritz vectors (principal angles per cluster).
-Sizes span one to several 64-wide tiles with ragged tails, uneven subdomains
-and both precision modes.  The full-size workload with 64 subdomains
+Sizes span one to several 64-wide tiles with ragged tails, uneven subdomains,
+a 3D pencil (eight 5^3 interiors, plane separators) and both precision modes.  The full-size workload with 64 subdomains
 (n = 65025) is compared with the oracle's stored results
 (tests/golden/oracle_c2.json, written by make_oracle_golden.py).
 """
@@ -43,6 +43,8 @@ CASES = {
     "midpoint_rule": lambda: W.tiny(N=17, P=2, nev=8, n_c=4, m=20, steps=2, nev_b=10, psi=4,
                                     mass_kind="random", rule="midpoint", cfg_id=44),
     "config1": lambda: W.config(1),
+    "tiny3d_p8": lambda: W.tiny(N=11, dim=3, P=2, nev=8, n_c=6, m=40, steps=2, nev_b=10, psi=4,
+                                mass_kind="random", cfg_id=45),
 }
 _cache = {}
 
