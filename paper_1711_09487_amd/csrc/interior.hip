@@ -378,13 +378,16 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   k_expand_scaled<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), mis, big);
   RFD_CHECK_LAUNCH();
   TriWork& tw = tw_v;
-  sy_tridiag(st, C, D, p, tw);
+  // the eigensolver runs on the leading DE = max d_j rows and columns: beyond
+  // them every block is the decoupled identity padding
+  const int64_t DE = std::max<int64_t>(P->d_max, 1);
+  sy_tridiag(st, C, DE, p, tw);
   // indices around sigma
   std::vector<double> xs(p, sig);
   work3.alloc(sizeof(double) * p + sizeof(int) * p);
   RFD_HIP(hipMemcpyAsync(work3.p, xs.data(), sizeof(double) * p, hipMemcpyHostToDevice, st));
   int* cnt_d = reinterpret_cast<int*>(work3.as<double>() + p);
-  sturm_counts(st, tw, D, p, work3.as<double>(), 1, cnt_d);
+  sturm_counts(st, tw, DE, p, work3.as<double>(), 1, cnt_d);
   auto cnt = download<int>(st, cnt_d, p);
   const int extra = 6;
   std::vector<int> lo(p), num(p);
@@ -400,7 +403,7 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   upload_v(st, lo_d, lo);
   upload_v(st, num_d, num);
   lam_d.alloc(sizeof(double) * (size_t)p * maxnum);
-  bisect(st, tw, D, p, lo_d.as<int>(), num_d.as<int>(), maxnum, lam_d.as<double>(), maxnum);
+  bisect(st, tw, DE, p, lo_d.as<int>(), num_d.as<int>(), maxnum, lam_d.as<double>(), maxnum);
   auto lam = download<double>(st, lam_d.p, (size_t)p * maxnum);
   // nev_b closest to sigma, whole clusters at the cut (ascending window)
   std::vector<int> w0(p), w1(p);
@@ -452,9 +455,9 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   // columns kappa_j .. VB-1 of a subdomain are padding and must stay zero: the
   // deflation GEMMs run over all VB columns
   fill<double>(st, Y, D, VB, p, 0.0);
-  inverse_iteration(st, tw, D, p, sel_d.as<double>(), kn_d.as<int>(), cl_d.as<int>(), VB, Y,
+  inverse_iteration(st, tw, DE, p, sel_d.as<double>(), kn_d.as<int>(), cl_d.as<int>(), VB, Y,
                     scratch);
-  back_transform(st, C, tw, D, p, Y, kn_d.as<int>(), (int)VB);
+  back_transform(st, C, tw, DE, p, Y, kn_d.as<int>(), (int)VB);
   // V = M^{-1/2} Y
   k_scale_rows<<<dim3(grid1(D * VB), p), 256, 0, st>>>(Y, D, VB, mis, D);
   RFD_CHECK_LAUNCH();
