@@ -32,67 +32,94 @@ __device__ inline double block_sum256(double v, double* red) {
 }
 
 void TriWork::reserve(int64_t n, int batch) {
+  // each buffer grows on its own (DevBuf::alloc keeps a larger one): the
+  // tile buffers grow with n^2, the others with n
   const int64_t need = n * (int64_t)batch;
-  if (need <= cap) return;
-  cap = need;
+  cap = std::max(cap, need);
   d.alloc(sizeof(double) * need);
   e.alloc(sizeof(double) * need);
   tau.alloc(sizeof(double) * need);
-  pvec.alloc(sizeof(double) * need);
   acol.alloc(sizeof(double) * need);
-  vw.alloc(sizeof(double) * need * 2 * TRI_NB);
+  vw.alloc(sizeof(double) * need * 3 * TRI_NB);
   red.alloc(sizeof(double) * (2 * TRI_NB + 2) * batch);
-  sq.alloc(sizeof(double) * ((n + 255) / 256) * batch);
-  ptvp.alloc(sizeof(double) * ((n + 7) / 8) * batch);
+  sq.alloc(sizeof(double) * ((n + 63) / 64) * batch);
+  const int64_t nb = tri_blocks(n);
+  pt.alloc(sizeof(double) * (nb + 1) * need);
+  ptvp.alloc(sizeof(double) * (nb * (nb + 1) / 2) * batch);
 }
 
 // Blocked reduction (panels of TRI_NB columns).  Within a panel the trailing
 // matrix is A - V W^T - W V^T with A as it was at the panel's start; V holds
 // the reflectors (unit entry explicit, zero above it) and W the matching
-// update vectors.  For column j (panel position c):
+// update vectors.  Only the lower triangle of A is read or updated.  For
+// column j (panel position c):
 //   k_tri_col   finishes W[:, c-1], forms the updated column j into acol and
 //               the partial sums of squares below its subdiagonal;
-//   k_tri_symv  makes the reflector from acol (every workgroup), writes it
-//               to V[:, c] and column j of A, and forms p = A v over the
-//               trailing block of the panel-start matrix with per-workgroup
-//               partial sums of p^T v; 2c extra workgroups of the same
-//               launch form W^T v and V^T v.
-// After the panel, the trailing block takes A -= V W^T + W V^T as two GEMMs.
+//   k_tri_symv  makes the reflector v from acol (every workgroup), writes it
+//               to V[:, c] and column j of A, and forms the pieces of
+//               p = A v over the trailing block of the panel-start matrix,
+//               64 x 64 lower tiles at a time (the next k_tri_col sums them);
+//               2c extra workgroups of the same launch form W^T v and V^T v.
+// After the panel, the lower triangle of the trailing block takes
+// A -= [V W] [W V]^T as one product.
 // w_c = tau (p - V (W^T v) - W (V^T v)) - (tau/2) (that^T v) v, i.e. the
 // two-sided application of I - tau v v^T to the current trailing matrix.
+// Both kernels issue all their global loads before their first barrier, so
+// that each costs one round trip to memory.
+//
+// Work arrays per matrix: vw holds V, W and a second copy of V (n x TRI_NB
+// each), so that [V W] and [W V] are both contiguous; pt holds the tile
+// pieces of p, one row of n per slot; sq the partial sums of squares, one
+// per 64 rows.
+constexpr int COL_R = 64;  // rows per workgroup of k_tri_col (4 lanes per row)
 
-// One thread per row r >= j.  c = panel position of column j; upd = 0 only
-// finishes W[:, c-1] (end of panel).
+// Four lanes per row r >= j: lane k of a row takes the V / W columns and the
+// slots of p congruent to k mod 4.  c = panel position of column j; upd = 0
+// only finishes W[:, c-1] (end of panel).  nslot / ntp: slots of p and
+// partial sums of p^T v left by the previous column's k_tri_symv.
 __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int64_t j, int c,
                                                  int upd, double* vw, const double* tauv,
-                                                 const double* pv, const double* red, double* acol,
-                                                 double* dv, double* sq, const double* ptvp) {
-  __shared__ double Vj[TRI_NB], Wj[TRI_NB], xs[TRI_NB], ys[TRI_NB], rs[8];
-  const int b = blockIdx.y, t = threadIdx.x;
+                                                 const double* pt, int64_t pts, int nslot,
+                                                 const double* red, double* acol, double* dv,
+                                                 double* sq, int64_t sqs, const double* ptvp,
+                                                 int64_t ptvs, int ntp) {
+  constexpr int NQ = TRI_NB / 4;
+  __shared__ double Vj[TRI_NB], Wj[TRI_NB], xs[TRI_NB], ys[TRI_NB], rs[8], pjs[1];
+  const int b = blockIdx.y, t = threadIdx.x, k = t & 3, lane = t & 63, wave = t >> 6;
   DMat<double> a = A.item(b);
-  double* V = vw + (int64_t)b * n * 2 * TRI_NB;
+  double* V = vw + (int64_t)b * n * 3 * TRI_NB;
   double* W = V + n * TRI_NB;
   const double* rd = red + (int64_t)b * (2 * TRI_NB + 2);
-  const double* p = pv + (int64_t)b * n;
-  const int64_t r = j + (int64_t)blockIdx.x * 256 + t;
+  const double* p = pt + (int64_t)b * pts;
+  const int64_t r = j + (int64_t)blockIdx.x * COL_R + (t >> 2);
   const bool act = r < n;
-  if (c == 0) {
-    if (act)
-      for (int q = 0; q < TRI_NB; ++q) {
-        V[r + q * n] = 0.0;
-        W[r + q * n] = 0.0;
-      }
-  }
-  // this row of V and W (all loads issued together), and the inputs of the
-  // previous column's W
-  double vr[TRI_NB], wrow[TRI_NB];
+  // every global load first: this row of V and W, its slots of p, column j,
+  // the partial sums of p^T v, p at row j, and the inputs of W[:, c-1]
+  double vr[NQ], wr[NQ];
 #pragma unroll
-  for (int q = 0; q < TRI_NB; ++q) {
-    vr[q] = (act && q < c) ? V[r + q * n] : 0.0;
-    wrow[q] = (act && q < c - 1) ? W[r + q * n] : 0.0;
+  for (int i = 0; i < NQ; ++i) {
+    const int q = 4 * i + k;
+    vr[i] = (act && q < c) ? V[r + q * n] : 0.0;
+    wr[i] = (act && q < c - 1) ? W[r + q * n] : 0.0;
   }
-  const double pr = (act && c >= 1) ? p[r] : 0.0;
-  const double ajr = (act && upd) ? a.re[r + j * a.ld] : 0.0;
+  double pr = 0.0, ps = 0.0, pjp = 0.0, tp = 0.0;
+  if (c >= 1) {
+    if (act) {
+      for (int s0 = k; s0 < nslot; s0 += 16) {
+        const double p0 = p[r + (int64_t)s0 * n];
+        const double p1 = s0 + 4 < nslot ? p[r + (int64_t)(s0 + 4) * n] : 0.0;
+        const double p2 = s0 + 8 < nslot ? p[r + (int64_t)(s0 + 8) * n] : 0.0;
+        const double p3 = s0 + 12 < nslot ? p[r + (int64_t)(s0 + 12) * n] : 0.0;
+        pr += (p0 + p1) + (p2 + p3);
+      }
+    }
+    const double* pp = ptvp + (int64_t)b * ptvs;
+    for (int i = t; i < ntp; i += 256) ps += pp[i];
+    if (wave == 1)
+      for (int s = lane; s < nslot; s += 64) pjp += p[j + (int64_t)s * n];
+    tp = tauv[(int64_t)b * n + j - 1];
+  }
+  const double ajr = (act && upd && k == 0) ? a.re[r + j * a.ld] : 0.0;
   if (t < c) {
     Vj[t] = V[j + (int64_t)t * n];
     if (t < c - 1) {
@@ -101,168 +128,225 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
       ys[t] = rd[2 + TRI_NB + t];
     }
   }
+  if (c == 0 && act) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int q = 4 * i + k;
+      V[r + q * n] = 0.0;
+      W[r + q * n] = 0.0;
+      V[r + (2 * TRI_NB + q) * n] = 0.0;
+    }
+  }
+  pr += __shfl_xor(pr, 1, 64);
+  pr += __shfl_xor(pr, 2, 64);
+  if (wave == 1) {
+    pjp = wave_sum(pjp);
+    if (lane == 0) pjs[0] = pjp;
+  }
   __syncthreads();
   if (c >= 1) {
-    // p^T v of the previous column: partial sums of its mat-vec workgroups
-    const int np = (int)((n - j + 7) / 8);
-    const double* pp = ptvp + (int64_t)b * ((n + 7) / 8);
-    double ps = 0.0;
-    for (int i = t; i < np; i += 256) ps += pp[i];
     const double ptv = block_sum256(ps, rs);
-    const double tp = tauv[(int64_t)b * n + j - 1];
     double xy = 0;
 #pragma unroll 8
     for (int q = 0; q < c - 1; ++q) xy += xs[q] * ys[q];
     const double al = -0.5 * tp * tp * (ptv - 2.0 * xy);
     if (t == 0) {
-      double acc = p[j];
+      double acc = pjs[0];
       for (int q = 0; q < c - 1; ++q) acc -= Vj[q] * xs[q] + Wj[q] * ys[q];
       Wj[c - 1] = tp * acc + al * Vj[c - 1];
     }
-    if (act) {
-      double acc = pr;
+    // W[r, c-1]
+    double part = 0.0, vl = 0.0;
 #pragma unroll
-      for (int q = 0; q < TRI_NB; ++q)
-        if (q < c - 1) acc -= vr[q] * xs[q] + wrow[q] * ys[q];
-      double wc = 0.0;
-#pragma unroll
-      for (int q = 0; q < TRI_NB; ++q)
-        if (q == c - 1) wc = vr[q];
-      wc = tp * acc + al * wc;
-#pragma unroll
-      for (int q = 0; q < TRI_NB; ++q)
-        if (q == c - 1) wrow[q] = wc;
-      W[r + (int64_t)(c - 1) * n] = wc;
+    for (int i = 0; i < NQ; ++i) {
+      const int q = 4 * i + k;
+      if (q < c - 1) part += vr[i] * xs[q] + wr[i] * ys[q];
+      if (q == c - 1) vl = vr[i];
     }
+    part += __shfl_xor(part, 1, 64);
+    part += __shfl_xor(part, 2, 64);
+    vl = __shfl(vl, (lane & ~3) | ((c - 1) & 3), 64);
+    const double wc = tp * (pr - part) + al * vl;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+      if (4 * i + k == c - 1) wr[i] = wc;
+    if (act && k == 0) W[r + (int64_t)(c - 1) * n] = wc;
     __syncthreads();
   }
   if (!upd) return;
-  double ar = 0.0;
-  if (act) {
-    ar = ajr;
+  double part = 0.0;
 #pragma unroll
-    for (int q = 0; q < TRI_NB; ++q)
-      if (q < c) ar -= vr[q] * Wj[q] + wrow[q] * Vj[q];
+  for (int i = 0; i < NQ; ++i) {
+    const int q = 4 * i + k;
+    if (q < c) part += vr[i] * Wj[q] + wr[i] * Vj[q];
+  }
+  part += __shfl_xor(part, 1, 64);
+  part += __shfl_xor(part, 2, 64);
+  const double ar = __shfl(ajr, lane & ~3, 64) - part;
+  if (act && k == 0) {
     acol[(int64_t)b * n + r] = ar;
     if (r == j) dv[(int64_t)b * n + j] = ar;
   }
-  const double s2 = block_sum256((act && r >= j + 2) ? ar * ar : 0.0, rs);
-  if (t == 0) sq[(int64_t)b * ((n + 255) / 256) + blockIdx.x] = s2;
+  const double s2 = block_sum256((act && k == 0 && r >= j + 2) ? ar * ar : 0.0, rs);
+  if (t == 0) sq[(int64_t)b * sqs + blockIdx.x] = s2;
 }
 
-// Reflector of column j and p[q] = sum_r A[r, q] v[r] for q, r in [j+1, n).
-// A workgroup owns 8 columns; its 4 waves split the rows (128 per wave and
-// step, double2 per lane) and combine through LDS, so that each lane keeps 8
-// independent loads in flight.
+// Reflector of column j and the tile pieces of p = T v for the trailing
+// block T = A[j1:n, j1:n] (j1 = j + 1) from its lower triangle.  Tiles of
+// 64 x 64 are anchored at jb (j1, or j1 rounded down to even when the
+// columns allow 16-byte loads; rows and columns below j1 are masked).
+// Workgroup g < ntile owns lower tile (I, J), I >= J, numbered row by row:
+// it writes T_IJ v_J (rows of block I) to slot J and T_IJ^T v_I (rows of
+// block J) to slot I + 1; a diagonal tile gives its strict lower part to
+// slot I and its lower part with the diagonal to slot I + 1.  Every row of
+// block R thus gets one value in each slot 0 .. nbt, and p = their sum.  The
+// workgroup's share of p^T v goes to ptvp[g].  Within a tile, each wave owns
+// 16 columns and each half-wave one column per step, two rows per lane.
+// The reflector is v = e_j1 + scale u with u the entries of column j below
+// row j1, so the loads of u and of the tile do not wait for scale.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int64_t j, int c,
-                                                  double* vw, double* dv, double* ev, double* tauv,
-                                                  double* pv, const double* acol, const double* sq,
-                                                  int nsym, double* red, double* ptvp) {
+                                                  double* vw, double* ev, double* tauv,
+                                                  const double* acol, const double* sq, int nsq,
+                                                  int64_t sqs, int64_t jb, int ntile, double* red,
+                                                  double* pt, int64_t pts, double* ptvp,
+                                                  int64_t ptvs) {
   __shared__ double hh[4];
-  __shared__ double part[4][8];
+  __shared__ double rsl[8][TRI_TB];
+  __shared__ double cdl[TRI_TB];
   __shared__ double rs[8];
   const int b = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = (int)blockIdx.x;
   DMat<double> a = A.item(b);
   const double* ac = acol + (int64_t)b * n;
-  if (t == 0) {
-    const int nsq = (int)((n - j + 255) / 256);
-    const double* s = sq + (int64_t)b * ((n + 255) / 256);
-    double s2 = 0;
-#pragma unroll 8
-    for (int i = 0; i < nsq; ++i) s2 += s[i];
-    const double alpha = ac[j + 1];
-    double tau = 0, beta = alpha, scale = 0;
-    if (s2 > 0) {
-      const double nrm = sqrt(alpha * alpha + s2);
-      beta = alpha >= 0 ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+  const int64_t j1 = j + 1;
+  auto uval = [&](int64_t r) -> double { return (r > j1 && r < n) ? ac[r] : 0.0; };
+  // tile coordinates (row-major lower tiles: g = I (I + 1) / 2 + J)
+  int I = 0, J = 0;
+  const bool tile = g < ntile;
+  if (tile) {
+    I = (int)((sqrt(8.0 * (double)g + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= g) ++I;
+    while (I * (I + 1) / 2 > g) --I;
+    J = g - I * (I + 1) / 2;
+  }
+  const int64_t rb = jb + (int64_t)TRI_TB * I, cb = jb + (int64_t)TRI_TB * J;
+  const int h = lane >> 5;
+  const int64_t r0 = rb + 2 * (lane & 31);
+  // all global loads first
+  double2 x[8];
+  double uq[8];
+  double u0 = 0.0, u1 = 0.0, ur = 0.0, uc = 0.0;
+  double dot = 0.0, y1 = 0.0;
+  if (tile) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t q = cb + 16 * wave + 2 * i + h;
+      const bool qok = q >= j1 && q < n;
+      const double* colp = a.re + (qok ? q : j1) * a.ld;
+      double2 v2 = make_double2(0.0, 0.0);
+      if (VEC && qok && r0 + 1 < n) {
+        v2 = *reinterpret_cast<const double2*>(colp + r0);
+      } else {
+        if (qok && r0 < n) v2.x = colp[r0];
+        if (qok && r0 + 1 < n) v2.y = colp[r0 + 1];
+      }
+      x[i] = v2;
+      uq[i] = uval(q);
     }
-    hh[0] = tau;
-    hh[1] = beta;
-    hh[2] = scale;
+    u0 = uval(r0);
+    u1 = uval(r0 + 1);
+    if (t < TRI_TB) {
+      ur = uval(rb + t);
+      uc = uval(cb + t);
+    }
+  } else {
+    // W[:, e]^T u (e < c) or V[:, e - c]^T u, and the entries at row j1
+    const int e = g - ntile;
+    const double* V = vw + (int64_t)b * n * 3 * TRI_NB;
+    const double* y = e < c ? V + n * TRI_NB + (int64_t)e * n : V + (int64_t)(e - c) * n;
+#pragma unroll 4
+    for (int64_t r = j1 + 1 + t; r < n; r += 256) dot += y[r] * ac[r];
+    if (t == 0) y1 = y[j1];
+  }
+  double s2 = 0.0;
+  if (wave == 0)
+    for (int i = lane; i < nsq; i += 64) s2 += sq[(int64_t)b * sqs + i];
+  const double alpha = ac[j1];
+  if (wave == 0) {
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+      double tau = 0, beta = alpha, scale = 0;
+      if (s2 > 0) {
+        const double nrm = sqrt(alpha * alpha + s2);
+        beta = alpha >= 0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      hh[0] = tau;
+      hh[1] = beta;
+      hh[2] = scale;
+    }
   }
   __syncthreads();
   const double scale = hh[2];
-  const int64_t j1 = j + 1;
-  auto vval = [&](int64_t r) -> double {
-    return r < j1 ? 0.0 : (r == j1 ? 1.0 : ac[r] * scale);
-  };
-  if (blockIdx.x == 0 && t == 0) {
+  if (g == 0 && t == 0) {
     ev[(int64_t)b * n + j] = hh[1];
     tauv[(int64_t)b * n + j] = hh[0];
   }
-  double* V = vw + (int64_t)b * n * 2 * TRI_NB;
-  if ((int)blockIdx.x >= nsym) {
-    // W[:, g]^T v (g < c) or V[:, g - c]^T v over rows >= j + 1
-    const int g = (int)blockIdx.x - nsym;
-    const double* x = g < c ? V + n * TRI_NB + (int64_t)g * n : V + (int64_t)(g - c) * n;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int64_t r = j1 + t; r < n; r += 256) acc += x[r] * vval(r);
-    acc = block_sum256(acc, rs);
-    if (t == 0) red[(int64_t)b * (2 * TRI_NB + 2) + (g < c ? 2 + g : 2 + TRI_NB + g - c)] = acc;
+  if (!tile) {
+    const int e = g - ntile;
+    dot = block_sum256(dot, rs);
+    if (t == 0)
+      red[(int64_t)b * (2 * TRI_NB + 2) + (e < c ? 2 + e : 2 + TRI_NB + e - c)] = scale * dot + y1;
     return;
   }
-  // this workgroup's share of v: V[:, c] and column j of A (rows >= j + 2)
-  const int64_t q0 = j1 + (int64_t)blockIdx.x * 8;
-  if (t < 8 && q0 + t < n) {
-    const int64_t r = q0 + t;
-    const double v = vval(r);
-    V[r + (int64_t)c * n] = v;
-    if (r >= j + 2) a.re[r + j * a.ld] = v;
+  auto vof = [&](int64_t r, double u) -> double { return r == j1 ? 1.0 : scale * u; };
+  const double vi0 = vof(r0, u0), vi1 = vof(r0 + 1, u1);
+  double rs0 = 0.0, rs1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t q = cb + 16 * wave + 2 * i + h;
+    const double vq = vof(q, uq[i]);
+    // the strict lower part feeds the row sums, the lower part with the
+    // diagonal the column sums; rows below j1 are masked
+    const double x0 = (r0 >= j1) ? x[i].x : 0.0, x1 = (r0 + 1 >= j1) ? x[i].y : 0.0;
+    rs0 += (r0 > q ? x0 : 0.0) * vq;
+    rs1 += (r0 + 1 > q ? x1 : 0.0) * vq;
+    double cd = (r0 >= q ? x0 : 0.0) * vi0 + (r0 + 1 >= q ? x1 : 0.0) * vi1;
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) cd += __shfl_xor(cd, o, 64);
+    if ((lane & 31) == 0) cdl[16 * wave + 2 * i + h] = cd;
   }
-  const double* col[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) col[k] = a.re + (q0 + k < n ? q0 + k : q0) * a.ld;
-  double acc[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
-  if (VEC) {
-    const int64_t r0 = j1 & ~(int64_t)1;
-#pragma unroll 2
-    for (int64_t r = r0 + 2 * lane + 128 * wave; r < n; r += 512) {
-      const double v0 = vval(r);
-      if (r + 1 < n) {
-        const double v1 = vval(r + 1);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const double2 x = *reinterpret_cast<const double2*>(col[k] + r);
-          acc[k] += x.x * v0 + x.y * v1;
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) acc[k] += col[k][r] * v0;
-      }
+  rsl[2 * wave + h][2 * (lane & 31)] = rs0;
+  rsl[2 * wave + h][2 * (lane & 31) + 1] = rs1;
+  if (I == J && t < TRI_TB) {
+    // the reflector: V[:, c] (both copies) and column j of A (rows >= j + 2)
+    const int64_t r = rb + t;
+    if (r >= j1 && r < n) {
+      const double v = vof(r, ur);
+      double* V = vw + (int64_t)b * n * 3 * TRI_NB;
+      V[r + (int64_t)c * n] = v;
+      V[r + (int64_t)(2 * TRI_NB + c) * n] = v;
+      if (r >= j + 2) a.re[r + j * a.ld] = v;
     }
-  } else {
-    for (int64_t r = j1 + lane + 64 * wave; r < n; r += 256) {
-      const double v0 = vval(r);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) acc[k] += col[k][r] * v0;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const double s = wave_sum(acc[k]);
-    if (lane == 0) part[wave][k] = s;
   }
   __syncthreads();
-  if (t < 8) {
-    double pq = 0.0, pvq = 0.0;
-    if (q0 + t < n) {
-      pq = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-      pv[(int64_t)b * n + q0 + t] = pq;
-      pvq = pq * vval(q0 + t);
-    }
-    part[0][t] = pvq;
+  double share = 0.0;
+  if (t < TRI_TB) {
+    double rsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) rsum += rsl[k][t];
+    const double cd = cdl[t];
+    double* pb = pt + (int64_t)b * pts;
+    const int64_t r = rb + t, q = cb + t;
+    if (r < n) pb[(int64_t)J * n + r] = rsum;
+    if (q < n) pb[(int64_t)(I + 1) * n + q] = cd;
+    share = vof(r, ur) * rsum + vof(q, uc) * cd;
   }
-  __syncthreads();
-  if (t == 0) {
-    double sacc = 0.0;
-    for (int k = 0; k < 8; ++k) sacc += part[0][k];
-    ptvp[(int64_t)b * ((n + 7) / 8) + blockIdx.x] = sacc;
+  if (wave == 0) {
+    share = wave_sum(share);
+    if (t == 0) ptvp[(int64_t)b * ptvs + g] = share;
   }
 }
 
@@ -282,42 +366,56 @@ __global__ void k_tri_fin(DMat<double> A, int64_t n, double* dv, double* ev) {
 static void tridiag_launches(hipStream_t s, DMat<double> A, int64_t n, int batch, TriWork& w) {
   double* vw = w.vw.as<double>();
   const bool vec = A.ld % 2 == 0 && A.bs % 2 == 0 && ((uintptr_t)A.re & 15u) == 0;
+  const int64_t nbmax = tri_blocks(n);
+  const int64_t pts = (nbmax + 1) * n;                 // pt per matrix
+  const int64_t ptvs = nbmax * (nbmax + 1) / 2;        // ptvp per matrix
+  const int64_t sqs = (n + COL_R - 1) / COL_R;         // sq per matrix
+  // tile anchor and counts of the mat-vec over the trailing block from row j1
+  auto anchor = [&](int64_t j1) { return vec ? (j1 & ~(int64_t)1) : j1; };
+  auto nblk = [&](int64_t j1) { return (int)((n - anchor(j1) + TRI_TB - 1) / TRI_TB); };
+  auto col = [&](int64_t j, int c, int upd) {
+    // the previous column's mat-vec covered rows from j
+    const int nb = c >= 1 ? nblk(j) : 0;
+    dim3 g1((unsigned)((n - j + COL_R - 1) / COL_R), batch);
+    k_tri_col<<<g1, 256, 0, s>>>(A, n, j, c, upd, vw, w.tau.as<double>(), w.pt.as<double>(), pts,
+                                 nb + 1, w.red.as<double>(), w.acol.as<double>(),
+                                 w.d.as<double>(), w.sq.as<double>(), sqs, w.ptvp.as<double>(),
+                                 ptvs, nb * (nb + 1) / 2);
+    RFD_CHECK_LAUNCH();
+  };
   const int64_t nred = n - 2;  // columns that get a reflector
   for (int64_t i0 = 0; i0 < nred; i0 += TRI_NB) {
     const int nbp = (int)std::min<int64_t>(TRI_NB, nred - i0);
     for (int c = 0; c < nbp; ++c) {
       const int64_t j = i0 + c;
-      dim3 g1(grid1(n - j), batch);
-      k_tri_col<<<g1, 256, 0, s>>>(A, n, j, c, 1, vw, w.tau.as<double>(), w.pvec.as<double>(),
-                                   w.red.as<double>(), w.acol.as<double>(), w.d.as<double>(),
-                                   w.sq.as<double>(), w.ptvp.as<double>());
-      RFD_CHECK_LAUNCH();
-      const int nsym = (int)((n - j - 1 + 7) / 8);
-      dim3 g2((unsigned)(nsym + 2 * c), batch);
-      // algorithmic bytes: the trailing block, the column and p, V / W columns
+      col(j, c, 1);
+      const int nb = nblk(j + 1);
+      const int ntile = nb * (nb + 1) / 2;
+      dim3 g2((unsigned)(ntile + 2 * c), batch);
+      // algorithmic bytes: the lower triangle of the trailing block, the
+      // column, p, V / W columns
       const double nt = (double)(n - j - 1);
       KernelAccount::Scope acct(s, KA_TRI_SYMV, 2.0 * nt * nt * batch,
-                                8.0 * (nt * nt + 4.0 * nt + 4.0 * c * nt) * batch);
+                                8.0 * (0.5 * nt * (nt + 1.0) + 4.0 * nt + 4.0 * c * nt) * batch);
       hipExtLaunchKernelGGL(vec ? k_tri_symv<true> : k_tri_symv<false>, g2, dim3(256), 0, s,
-                            acct.start(), acct.stop(), 0, A, n, j, c, vw, w.d.as<double>(),
-                            w.e.as<double>(), w.tau.as<double>(), w.pvec.as<double>(),
-                            (const double*)w.acol.as<double>(), (const double*)w.sq.as<double>(),
-                            nsym, w.red.as<double>(), w.ptvp.as<double>());
+                            acct.start(), acct.stop(), 0, A, n, j, c, vw, w.e.as<double>(),
+                            w.tau.as<double>(), (const double*)w.acol.as<double>(),
+                            (const double*)w.sq.as<double>(),
+                            (int)((n - j + COL_R - 1) / COL_R), sqs, anchor(j + 1), ntile,
+                            w.red.as<double>(), w.pt.as<double>(), pts, w.ptvp.as<double>(),
+                            ptvs);
       RFD_CHECK_LAUNCH();
     }
-    // finish W's last column, then the trailing block takes the panel's update
+    // finish W's last column, then the lower triangle of the trailing block
+    // takes the panel's update A -= [V W] [W V]^T (columns beyond the panel
+    // are zero)
     const int64_t i1 = i0 + nbp;
-    dim3 g1(grid1(n - i1), batch);
-    k_tri_col<<<g1, 256, 0, s>>>(A, n, i1, nbp, 0, vw, w.tau.as<double>(), w.pvec.as<double>(),
-                                 w.red.as<double>(), w.acol.as<double>(), w.d.as<double>(),
-                                 w.sq.as<double>(), w.ptvp.as<double>());
-    RFD_CHECK_LAUNCH();
+    col(i1, nbp, 0);
     const int64_t m = n - i1;
-    DMat<double> Vm{vw + i1, nullptr, n, n * 2 * TRI_NB};
-    DMat<double> Wm{vw + n * TRI_NB + i1, nullptr, n, n * 2 * TRI_NB};
+    DMat<double> VW{vw + i1, nullptr, n, n * 3 * TRI_NB};
+    DMat<double> WV{vw + n * TRI_NB + i1, nullptr, n, n * 3 * TRI_NB};
     DMat<double> Cm = A.sub(i1, i1);
-    gemm<double>(s, false, true, m, m, nbp, -1.0, Vm, Wm, 1.0, Cm, batch);
-    gemm<double>(s, false, true, m, m, nbp, -1.0, Wm, Vm, 1.0, Cm, batch);
+    gemm_lower<double>(s, false, true, m, 2 * TRI_NB, -1.0, VW, WV, 1.0, Cm, batch);
   }
   k_tri_fin<<<batch, 64, 0, s>>>(A, n, w.d.as<double>(), w.e.as<double>());
   RFD_CHECK_LAUNCH();

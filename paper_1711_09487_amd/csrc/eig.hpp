@@ -10,11 +10,15 @@
 namespace rfd {
 
 constexpr int TRI_NB = 32;  // panel width of the blocked tridiagonalization
+constexpr int TRI_TB = 64;  // tile of its symmetric mat-vec
+
+// Tile blocks (plus one) of the mat-vec over an n x n matrix.
+inline int64_t tri_blocks(int64_t n) { return (n + TRI_TB - 1) / TRI_TB + 1; }
 
 // Work space of the eigensolver (kept by the caller so that repeated solves
 // of one shape reuse it).
 struct TriWork {
-  DevBuf d, e, tau, pvec, acol, vw, red, sq, ptvp;
+  DevBuf d, e, tau, pt, acol, vw, red, sq, ptvp;
   DevBuf wv, wg, wt, w1, w2;  // back-transformation panels
   int64_t cap = 0;
   void reserve(int64_t n, int batch);

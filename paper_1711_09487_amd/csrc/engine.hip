@@ -229,7 +229,7 @@ std::vector<DevBuf*> EngineImpl::solve_buffers() {
                          &ipiv_small, &iscal, &gwork, &work6b, &rr_az, &rr_h, &ow.V, &ow.T,
                          &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank};
   for (TriWork* t : {&tw_v, &tw_h})
-    for (DevBuf* b : {&t->d, &t->e, &t->tau, &t->pvec, &t->acol, &t->vw, &t->red, &t->sq, &t->ptvp,
+    for (DevBuf* b : {&t->d, &t->e, &t->tau, &t->pt, &t->acol, &t->vw, &t->red, &t->sq, &t->ptvp,
                       &t->wv, &t->wg, &t->wt, &t->w1, &t->w2})
       v.push_back(b);
   for (DevBuf& b : tmp) v.push_back(&b);

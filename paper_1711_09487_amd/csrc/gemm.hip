@@ -419,7 +419,10 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
     // (an output that overwrites an operand stays on the hand-written kernel,
     // where a single tile row or column makes that safe)
     const bool aliased = C.re == A.re || C.re == B.re;
-    if (!cplx && !aliased && splits == 1 && t64 >= 512 && K >= 32 && M <= 0x7fffffff &&
+    // (a lower-triangle update of short K stays here too: rocBLAS would
+    // produce the full square, twice the bytes)
+    const bool short_tri = tri && K < 256;
+    if (!cplx && !aliased && !short_tri && splits == 1 && t64 >= 512 && K >= 32 && M <= 0x7fffffff &&
         N <= 0x7fffffff && K <= 0x7fffffff) {
       KernelAccount::Scope acct(s, KA_ROCBLAS, 2.0 * (double)M * (double)N * (double)K * batch,
                                 8.0 * ((double)M * K + (double)K * N +

@@ -151,11 +151,13 @@ def test_lu_breakdown_flag():
     assert flags.value != 0
 
 
-@pytest.mark.parametrize("n,batch,lo,num", [(100, 3, 5, 20), (77, 2, 0, 30), (40, 1, 0, 40)])
+@pytest.mark.parametrize("n,batch,lo,num", [(100, 3, 5, 20), (77, 2, 0, 30), (40, 1, 0, 40),
+                                             (300, 2, 10, 40), (517, 1, 100, 30)])
 def test_symmetric_eigensolver(n, batch, lo, num):
     """Blocked tridiagonalization + bisection + inverse iteration + back-
     transformation against LAPACK: ragged panels (n - 2 reflectors in panels
-    of 32), odd n (scalar loads), and a cluster of equal eigenvalues."""
+    of 32), several 64 x 64 tiles of the mat-vec with odd and even anchors,
+    odd n (scalar loads), and a cluster of equal eigenvalues."""
     torch = _torch()
     import paper_1711_09487_amd as R
     rs = np.random.default_rng(7)
