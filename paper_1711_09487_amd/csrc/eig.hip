@@ -104,17 +104,26 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
   }
   double pr = 0.0, ps = 0.0, pjp = 0.0, tp = 0.0;
   if (c >= 1) {
+    // (blocks of independent loads: up to 64 slots and 2048 partial sums
+    // in one round)
     if (act) {
-      for (int s0 = k; s0 < nslot; s0 += 16) {
-        const double p0 = p[r + (int64_t)s0 * n];
-        const double p1 = s0 + 4 < nslot ? p[r + (int64_t)(s0 + 4) * n] : 0.0;
-        const double p2 = s0 + 8 < nslot ? p[r + (int64_t)(s0 + 8) * n] : 0.0;
-        const double p3 = s0 + 12 < nslot ? p[r + (int64_t)(s0 + 12) * n] : 0.0;
-        pr += (p0 + p1) + (p2 + p3);
+      for (int s0 = k; s0 < nslot; s0 += 64) {
+        double pv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          pv[i] = s0 + 4 * i < nslot ? p[r + (int64_t)(s0 + 4 * i) * n] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) pr += pv[i];
       }
     }
     const double* pp = ptvp + (int64_t)b * ptvs;
-    for (int i = t; i < ntp; i += 256) ps += pp[i];
+    for (int i0 = t; i0 < ntp; i0 += 2048) {
+      double pv[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) pv[i] = i0 + 256 * i < ntp ? pp[i0 + 256 * i] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ps += pv[i];
+    }
     if (wave == 1)
       for (int s = lane; s < nslot; s += 64) pjp += p[j + (int64_t)s * n];
     tp = tauv[(int64_t)b * n + j - 1];
@@ -265,8 +274,17 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     const int e = g - ntile;
     const double* V = vw + (int64_t)b * n * 3 * TRI_NB;
     const double* y = e < c ? V + n * TRI_NB + (int64_t)e * n : V + (int64_t)(e - c) * n;
-#pragma unroll 4
-    for (int64_t r = j1 + 1 + t; r < n; r += 256) dot += y[r] * ac[r];
+    for (int64_t r0 = j1 + 1 + t; r0 < n; r0 += 8 * 256) {
+      double yv[8], av[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t r = r0 + 256 * i;
+        yv[i] = r < n ? y[r] : 0.0;
+        av[i] = r < n ? ac[r] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dot += yv[i] * av[i];
+    }
     if (t == 0) y1 = y[j1];
   }
   double s2 = 0.0;
@@ -780,42 +798,94 @@ void inverse_iteration(hipStream_t s, const TriWork& w, int64_t n, int batch, co
 // ---------------------------------------------------------------------------
 // V[r, q] (rows i0 + 1 .. n - 1 of the panel's reflectors, explicit unit
 // entry, zeros above it)
+// Reflectors are applied in blocks of WY_NB (compact WY: I - V T V^T).
+constexpr int WY_NB = 128;
+
+// V (m x WY_NB, m = n - i0 - 1) of the block of reflectors i0 .. i0 + nbp - 1,
+// with the unit entries explicit and zero columns beyond nbp.
 __global__ void k_wy_v(DMat<double> A, int64_t n, int64_t i0, int nbp, double* V) {
   const int b = blockIdx.y;
   DMat<double> a = A.item(b);
   const int64_t m = n - i0 - 1;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m * TRI_NB) return;
+  if (e >= m * WY_NB) return;
   const int64_t rr = e % m, q = e / m;
   const int64_t r = i0 + 1 + rr, j = i0 + q;
   double v = 0.0;
   if (q < nbp) v = (r == j + 1) ? 1.0 : (r > j + 1 ? a.re[r + j * a.ld] : 0.0);
-  V[(int64_t)b * m * TRI_NB + rr + q * m] = v;
+  V[(int64_t)b * m * WY_NB + rr + q * m] = v;
 }
 
-// T (TRI_NB x TRI_NB, upper) from tau and G = V^T V: T[k][k] = tau_k,
-// T[0:k, k] = -tau_k T[0:k, 0:k] G[0:k, k].  One workgroup per item.
-__global__ void k_wy_t(const double* G, const double* tauv, int64_t n, int64_t i0, int nbp,
-                       double* T) {
-  __shared__ double Ts[TRI_NB][TRI_NB + 1];
+// T (WY_NB x WY_NB, upper) of the block from tau and G = V^T V.  The
+// recurrence T[k][k] = tau_k, T[0:k, k] = -tau_k T[0:k, 0:k] G[0:k, k] runs
+// on the four diagonal 32 x 32 blocks at once (a group of 64 threads each,
+// in shared memory); then block column b takes
+// T[0:32b, blk b] = -T[0:32b, 0:32b] G[0:32b, blk b] T_bb, which is the same
+// recurrence applied a block at a time.  One workgroup of 256 per item; T is
+// written to global memory and read back by the same workgroup.
+constexpr int WY_SB = 32;
+__global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tauv, int64_t n,
+                                              int64_t i0, int nbp, double* T) {
+  constexpr int NS = WY_NB / WY_SB;
+  __shared__ double Ts[NS][WY_SB][WY_SB + 1];
+  // the diagonal blocks of G, later X (both fit in the larger of the two)
+  constexpr int SH = NS * WY_SB * (WY_SB + 1) > (WY_NB - WY_SB) * (WY_SB + 1)
+                         ? NS * WY_SB * (WY_SB + 1)
+                         : (WY_NB - WY_SB) * (WY_SB + 1);
+  __shared__ double sh[SH];
+  auto Gd = [&](int a, int r, int c) -> double& { return sh[(a * WY_SB + r) * (WY_SB + 1) + c]; };
+  auto X = [&](int r, int c) -> double& { return sh[r * (WY_SB + 1) + c]; };
   const int b = blockIdx.x, t = threadIdx.x;
-  const double* g = G + (int64_t)b * TRI_NB * TRI_NB;
-  for (int e = t; e < TRI_NB * TRI_NB; e += blockDim.x) Ts[e % TRI_NB][e / TRI_NB] = 0.0;
+  const int grp = t / 64, lt = t % 64;
+  const double* g = G + (int64_t)b * WY_NB * WY_NB;
+  double* To = T + (int64_t)b * WY_NB * WY_NB;
+  for (int e = t; e < NS * WY_SB * (WY_SB + 1); e += 256) (&Ts[0][0][0])[e] = 0.0;
+  for (int e = t; e < NS * WY_SB * WY_SB; e += 256) {
+    const int a = e / (WY_SB * WY_SB), r = e % WY_SB, c = (e / WY_SB) % WY_SB;
+    Gd(a, r, c) = g[(a * WY_SB + r) + (int64_t)(a * WY_SB + c) * WY_NB];
+  }
+  for (int e = t; e < WY_NB * WY_NB; e += 256) To[e] = 0.0;
   __syncthreads();
-  for (int k = 0; k < nbp; ++k) {
-    const double tk = tauv[(int64_t)b * n + i0 + k];
+  // diagonal blocks: group grp owns block grp (reflectors k0 + k)
+  const int k0 = grp * WY_SB;
+  for (int k = 0; k < WY_SB; ++k) {
+    const int kk = k0 + k;
+    const double tk = kk < nbp ? tauv[(int64_t)b * n + i0 + kk] : 0.0;
     double v = 0.0;
-    if (t < k) {
-      for (int q = t; q < k; ++q) v += Ts[t][q] * g[q + k * TRI_NB];
+    if (lt < k) {
+      for (int q = lt; q < k; ++q) v += Ts[grp][lt][q] * Gd(grp, q, k);
       v *= -tk;
     }
     __syncthreads();
-    if (t < k) Ts[t][k] = v;
-    if (t == k) Ts[k][k] = tk;
+    if (lt < k) Ts[grp][lt][k] = v;
+    if (lt == k) Ts[grp][k][k] = tk;
     __syncthreads();
   }
-  double* To = T + (int64_t)b * TRI_NB * TRI_NB;
-  for (int e = t; e < TRI_NB * TRI_NB; e += blockDim.x) To[e] = Ts[e % TRI_NB][e / TRI_NB];
+  for (int e = t; e < NS * WY_SB * WY_SB; e += 256) {
+    const int a = e / (WY_SB * WY_SB), r = e % WY_SB, c = (e / WY_SB) % WY_SB;
+    To[(a * WY_SB + r) + (int64_t)(a * WY_SB + c) * WY_NB] = Ts[a][r][c];
+  }
+  __syncthreads();
+  // off-diagonal block columns
+  for (int bc = 1; bc < NS; ++bc) {
+    const int c0 = bc * WY_SB, rows = c0;
+    // X = G[0:c0, blk] T_bb
+    for (int e = t; e < rows * WY_SB; e += 256) {
+      const int r = e % rows, c = e / rows;
+      double acc = 0.0;
+      for (int q = 0; q <= c; ++q) acc += g[r + (int64_t)(c0 + q) * WY_NB] * Ts[bc][q][c];
+      X(r, c) = acc;
+    }
+    __syncthreads();
+    // T[0:c0, blk] = -T[0:c0, 0:c0] X (upper triangular: column q >= r)
+    for (int e = t; e < rows * WY_SB; e += 256) {
+      const int r = e % rows, c = e / rows;
+      double acc = 0.0;
+      for (int q = r; q < rows; ++q) acc += To[r + (int64_t)q * WY_NB] * X(q, c);
+      To[r + (int64_t)(c0 + c) * WY_NB] = -acc;
+    }
+    __syncthreads();
+  }
 }
 
 void back_transform(hipStream_t s, DMat<double> A, TriWork& w, int64_t n, int batch,
@@ -824,30 +894,30 @@ void back_transform(hipStream_t s, DMat<double> A, TriWork& w, int64_t n, int ba
   if (maxcols <= 0 || n < 3) return;
   const int64_t nred = n - 2;
   DevBuf &Vb = w.wv, &Gb = w.wg, &Tb = w.wt, &W1 = w.w1, &W2 = w.w2;
-  Vb.alloc(sizeof(double) * (n - 1) * TRI_NB * batch);
-  Gb.alloc(sizeof(double) * TRI_NB * TRI_NB * batch);
-  Tb.alloc(sizeof(double) * TRI_NB * TRI_NB * batch);
-  W1.alloc(sizeof(double) * TRI_NB * maxcols * batch);
-  W2.alloc(sizeof(double) * TRI_NB * maxcols * batch);
-  const int64_t npan = (nred + TRI_NB - 1) / TRI_NB;
-  for (int64_t pi = npan - 1; pi >= 0; --pi) {
-    const int64_t i0 = pi * TRI_NB;
-    const int nbp = (int)std::min<int64_t>(TRI_NB, nred - i0);
+  Vb.alloc(sizeof(double) * (n - 1) * WY_NB * batch);
+  Gb.alloc(sizeof(double) * WY_NB * WY_NB * batch);
+  Tb.alloc(sizeof(double) * WY_NB * WY_NB * batch);
+  W1.alloc(sizeof(double) * WY_NB * maxcols * batch);
+  W2.alloc(sizeof(double) * WY_NB * maxcols * batch);
+  const int64_t nblk = (nred + WY_NB - 1) / WY_NB;
+  for (int64_t pi = nblk - 1; pi >= 0; --pi) {
+    const int64_t i0 = pi * WY_NB;
+    const int nbp = (int)std::min<int64_t>(WY_NB, nred - i0);
     const int64_t m = n - i0 - 1;
-    k_wy_v<<<dim3(grid1(m * TRI_NB), batch), 256, 0, s>>>(A, n, i0, nbp, Vb.as<double>());
+    k_wy_v<<<dim3(grid1(m * WY_NB), batch), 256, 0, s>>>(A, n, i0, nbp, Vb.as<double>());
     RFD_CHECK_LAUNCH();
-    DMat<double> Vm{Vb.as<double>(), nullptr, m, m * TRI_NB};
-    DMat<double> Gm{Gb.as<double>(), nullptr, TRI_NB, TRI_NB * TRI_NB};
-    DMat<double> Tm{Tb.as<double>(), nullptr, TRI_NB, TRI_NB * TRI_NB};
-    DMat<double> W1m{W1.as<double>(), nullptr, TRI_NB, TRI_NB * (int64_t)maxcols};
-    DMat<double> W2m{W2.as<double>(), nullptr, TRI_NB, TRI_NB * (int64_t)maxcols};
+    DMat<double> Vm{Vb.as<double>(), nullptr, m, m * WY_NB};
+    DMat<double> Gm{Gb.as<double>(), nullptr, WY_NB, WY_NB * WY_NB};
+    DMat<double> Tm{Tb.as<double>(), nullptr, WY_NB, WY_NB * WY_NB};
+    DMat<double> W1m{W1.as<double>(), nullptr, WY_NB, WY_NB * (int64_t)maxcols};
+    DMat<double> W2m{W2.as<double>(), nullptr, WY_NB, WY_NB * (int64_t)maxcols};
     DMat<double> Ys = Y.sub(i0 + 1, 0);
-    gemm<double>(s, true, false, TRI_NB, TRI_NB, m, 1.0, Vm, Vm, 0.0, Gm, batch);
-    k_wy_t<<<batch, 64, 0, s>>>(Gb.as<double>(), w.tau.as<double>(), n, i0, nbp, Tb.as<double>());
+    gemm<double>(s, true, false, WY_NB, WY_NB, m, 1.0, Vm, Vm, 0.0, Gm, batch);
+    k_wy_t<<<batch, 256, 0, s>>>(Gb.as<double>(), w.tau.as<double>(), n, i0, nbp, Tb.as<double>());
     RFD_CHECK_LAUNCH();
-    gemm<double>(s, true, false, TRI_NB, maxcols, m, 1.0, Vm, Ys, 0.0, W1m, batch);
-    gemm<double>(s, false, false, TRI_NB, maxcols, TRI_NB, 1.0, Tm, W1m, 0.0, W2m, batch);
-    gemm<double>(s, false, false, m, maxcols, TRI_NB, -1.0, Vm, W2m, 1.0, Ys, batch);
+    gemm<double>(s, true, false, WY_NB, maxcols, m, 1.0, Vm, Ys, 0.0, W1m, batch);
+    gemm<double>(s, false, false, WY_NB, maxcols, WY_NB, 1.0, Tm, W1m, 0.0, W2m, batch);
+    gemm<double>(s, false, false, m, maxcols, WY_NB, -1.0, Vm, W2m, 1.0, Ys, batch);
   }
 }
 

@@ -744,7 +744,11 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   *nfound = 0;
   if (k == 0) return;
   double* Z = e.Zt.as<double>();
-  // H = Z^T A Z
+  // H = Z^T A Z, lower triangle (all the eigensolver reads).  Z = [Zv Zl]:
+  // the kv deflation columns of subdomain j live on its interior rows only,
+  // and interiors couple through the interface alone, so H_vv is block
+  // diagonal (one kappa_j block per subdomain) and H_lv = (A Zl)^T Zv needs
+  // each subdomain's interior rows only; H_ll = Zl^T (A Zl) is dense.
   e.timer.begin(st, 9);
   DevBuf& AZ = e.rr_az;
   DevBuf& Hb = e.rr_h;
@@ -752,9 +756,42 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   Hb.alloc(sizeof(double) * k * k);
   csr_mm(st, e.Arptr, e.Aridx, e.Arval, n, Z, n, AZ.as<double>(), n, k);
   DMat<double> Zm{Z, nullptr, n, 0}, AZm{AZ.as<double>(), nullptr, n, 0}, Hm{Hb.as<double>(), nullptr, k, 0};
-  gemm_lower<double>(st, true, false, k, n, 1.0, Zm, AZm, 0.0, Hm, 1);
-  k_mirror_lower<<<grid1(k * k), 256, 0, st>>>(Hb.as<double>(), k, k);
-  RFD_CHECK_LAUNCH();
+  const int64_t kv = std::min<int64_t>(e.kappa_tot, k), kl = k - kv;
+  bool uniform = kv > 0;
+  for (int j = 1; j < e.p && uniform; ++j)
+    uniform = e.P->interior[j].size() == e.P->interior[0].size() && e.kappa[j] == e.kappa[0];
+  if (uniform) {
+    // one batched product per block over the subdomains (item j: rows j d,
+    // deflation columns j kj)
+    fill<double>(st, Hm, kv, kv, 1, 0.0);
+    const int64_t d = (int64_t)e.P->interior[0].size(), kj = e.kappa[0];
+    DMat<double> Zb{Z, nullptr, n, d + kj * n}, AZb{AZ.as<double>(), nullptr, n, d + kj * n};
+    DMat<double> Hvv{Hb.as<double>(), nullptr, k, kj + kj * k};
+    gemm<double>(st, true, false, kj, kj, d, 1.0, Zb, AZb, 0.0, Hvv, e.p);
+    if (kl > 0) {
+      DMat<double> AZl{AZ.as<double>() + kv * n, nullptr, n, d};
+      DMat<double> Hlv{Hb.as<double>() + kv, nullptr, k, kj * k};
+      gemm<double>(st, true, false, kl, kj, d, 1.0, AZl, Zb, 0.0, Hlv, e.p);
+    }
+  } else if (kv > 0) {
+    fill<double>(st, Hm, kv, kv, 1, 0.0);
+    int64_t off = 0, kof = 0;
+    for (int j = 0; j < e.p; ++j) {
+      const int64_t d = (int64_t)e.P->interior[j].size(), kj = e.kappa[j];
+      if (kj > 0) {
+        DMat<double> Zj = Zm.sub(off, kof), AZj = AZm.sub(off, kof);
+        gemm<double>(st, true, false, kj, kj, d, 1.0, Zj, AZj, 0.0, Hm.sub(kof, kof), 1);
+        if (kl > 0)
+          gemm<double>(st, true, false, kl, kj, d, 1.0, AZm.sub(off, kv), Zj, 0.0,
+                       Hm.sub(kv, kof), 1);
+      }
+      off += d;
+      kof += kj;
+    }
+  }
+  if (kl > 0)
+    gemm<double>(st, true, false, kl, kl, n, 1.0, Zm.sub(0, kv), AZm.sub(0, kv), 0.0,
+                 Hm.sub(kv, kv), 1);
   e.timer.end(st);
   // eigenpairs of H in [alpha, beta]
   e.timer.begin(st, 10);
