@@ -60,6 +60,8 @@ def make_pencil(R, prob, mode, refine_tol=0.0):
 
 def one_step(P, prob, Y0):
     P.reset_caches(False)
+    # V_j and the B_sigma factors do not depend on Q: they run beside the filter
+    P.prepare_interior(prob.sigma, prob.nev_b)
     P.filter_interface(Y0, prob.steps)
     k = P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
     ev, X, r = P.rayleigh_ritz(prob.nev + 50)

@@ -11,6 +11,7 @@
  *   rfd_set_precision           FP64, or FP32 factors + FP64 refinement
  *   rfd_filter_interface        Q = orth of 2 Re sum_l w_l S(z_l)^{-1} applied
  *                               to a block (block Krylov)               Sec. 3.1 eq. (3.5), Alg. 3.1
+ *   rfd_prepare_interior        V_j and B_sigma factors, concurrently   Sec. 4, Alg. 5.1 step 3
  *   rfd_solve_interior          V_j, Sigma_j, Gamma_j and Z             Sec. 4, Sec. 5.1 eqs. (5.2)-(5.5)
  *   rfd_rayleigh_ritz           Ritz pairs in [alpha, beta]             Alg. 5.1 steps 6-8
  *   rfd_batch_run               many independent solves at once (whole Alg. 5.1 each)
@@ -147,6 +148,20 @@ rfd_status rfd_filter_interface(rfd_pencil_t pencil, int32_t m, const double* Y0
  */
 rfd_status rfd_filter_apply(rfd_pencil_t pencil, int32_t m, const double* Y, double* W,
                             rfd_stream_t stream);
+
+/*
+ * rfd_prepare_interior -- starts the parts of the interior step that do not
+ * depend on Q (Sec. 4: the deflation basis V_j for (sigma, nev_b), Alg. 5.1
+ * step 3, and the factors of B_j - sigma M_Bj) on a thread and stream of the
+ * library's own, and returns at once, so that they run on the device while
+ * rfd_filter_interface / rfd_filter_apply work on the caller's stream.
+ * rfd_solve_interior with the same sigma and nev_b then reuses them.  Every
+ * other call on the pencil first waits for the preparation to finish.
+ * Errors: RFD_EINVAL for nev_b < 0 or a non-finite sigma (at this call);
+ * errors of the preparation itself (RFD_EBREAKDOWN for a singular B_sigma,
+ * RFD_ENOMEM) are returned by the next call on the pencil that waits for it.
+ */
+rfd_status rfd_prepare_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b);
 
 /*
  * rfd_solve_interior -- the interior part (Sec. 4 and 5.1) for the Q of the

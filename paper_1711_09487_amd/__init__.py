@@ -26,7 +26,8 @@ RFD_EPENDING = 7
 
 EXPORTS = [
     "rfd_create_pencil", "rfd_set_partition", "rfd_set_interval_and_poles",
-    "rfd_set_precision", "rfd_filter_interface", "rfd_filter_apply", "rfd_solve_interior",
+    "rfd_set_precision", "rfd_filter_interface", "rfd_filter_apply", "rfd_prepare_interior",
+    "rfd_solve_interior",
     "rfd_rayleigh_ritz",
     "rfd_destroy_pencil", "rfd_last_error", "rfd_pencil_info", "rfd_set_timing",
     "rfd_phase_times", "rfd_reset_caches", "rfd_set_pole_window", "rfd_batch_run", "rfd_server_create",
@@ -76,6 +77,7 @@ def lib():
             "rfd_set_interval_and_poles": [P, F64, F64, I32, I32, P, P],
             "rfd_set_precision": [P, I32, F64, I32],
             "rfd_filter_interface": [P, I32, P, I32, P, I64, C.POINTER(I32), P],
+            "rfd_prepare_interior": [P, C.c_double, I32],
             "rfd_solve_interior": [P, F64, I32, I32, C.POINTER(I64), P],
             "rfd_filter_apply": [P, I32, P, P, P],
             "rfd_rayleigh_ritz": [P, I32, P, P, P, C.POINTER(I32), P],
@@ -186,6 +188,10 @@ def rfd_filter_interface(h, m, Y0, steps, Q, stream=None):
 def rfd_filter_apply(h, m, Y, W, stream=None):
     """W = 2 Re sum_l omega_l S(zeta_l)^{-1} Y; Y, W device tensors (s x m column-major)."""
     _check(lib().rfd_filter_apply(h, int(m), _ptr(Y), _ptr(W), _stream(stream)))
+
+
+def rfd_prepare_interior(h, sigma, nev_b):
+    _check(lib().rfd_prepare_interior(h, float(sigma), int(nev_b)))
 
 
 def rfd_solve_interior(h, sigma, nev_b, psi, stream=None):
@@ -304,6 +310,9 @@ class Pencil:
         W = torch.empty_like(Y)
         rfd_filter_apply(self.h, Y.shape[0], Y, W, stream)
         return W
+
+    def prepare_interior(self, sigma, nev_b):
+        rfd_prepare_interior(self.h, sigma, nev_b)
 
     def solve_interior(self, sigma, nev_b, psi, stream=None):
         return rfd_solve_interior(self.h, sigma, nev_b, psi, stream)

@@ -144,6 +144,16 @@ rfd_status rfd_filter_apply(rfd_pencil_t pencil, int32_t m, const double* Y, dou
   });
 }
 
+rfd_status rfd_prepare_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    if (nev_b < 0) throw Error(ST_EINVAL, "need nev_b >= 0");
+    if (!std::isfinite(sigma)) throw Error(ST_EINVAL, "sigma is not finite");
+    E.prepare_interior(sigma, nev_b);
+  });
+}
+
 rfd_status rfd_solve_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b, int32_t psi,
                               int64_t* k_out, rfd_stream_t stream) {
   return (rfd_status)capi_guard([&] {

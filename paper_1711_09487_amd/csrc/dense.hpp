@@ -58,6 +58,10 @@ void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T al
 // As gemm for square N x N results, computing only the output tiles that
 // meet the lower triangle (i >= j); entries above the diagonal are left
 // undefined (the caller mirrors the lower triangle of a symmetric result).
+// Drops the split-K workspace and the rocBLAS handle kept for stream s (call
+// before destroying a stream that ran products).
+void release_stream_resources(hipStream_t s);
+
 template <typename T>
 void gemm_lower(hipStream_t s, bool ta, bool tb, int64_t N, int64_t K, T alpha, DMat<T> A,
                 DMat<T> B, T beta, DMat<T> C, int batch);

@@ -53,6 +53,7 @@ DevPairCsr DevPairGroup::view() const {
 // ---------------------------------------------------------------------------
 Engine::Engine(const Csr& A, const Csr& M, const Partition& P) : d_(new EngineImpl) {
   EngineImpl& e = *d_;
+  RFD_HIP(hipGetDevice(&e.device));
   e.A = &A;
   e.M = &M;
   e.P = &P;
@@ -106,9 +107,20 @@ Engine::Engine(const Csr& A, const Csr& M, const Partition& P) : d_(new EngineIm
   RFD_HIP(hipMemset(e.flags.p, 0, sizeof(unsigned) * 4));
 }
 
-Engine::~Engine() = default;
+Engine::~Engine() {
+  EngineImpl& e = *d_;
+  try {
+    e.join_prepare();
+  } catch (...) {
+  }
+  if (e.prep_stream) {
+    release_stream_resources(e.prep_stream);
+    (void)hipStreamDestroy(e.prep_stream);
+  }
+}
 
 void Engine::set_poles(const Poles& poles) {
+  d_->join_prepare();
   EngineImpl& e = *d_;
   e.poles = poles;
   std::vector<double> z, w;
@@ -124,6 +136,7 @@ void Engine::set_poles(const Poles& poles) {
 }
 
 void Engine::set_precision(int mode, double tol, int sweeps) {
+  d_->join_prepare();
   EngineImpl& e = *d_;
   if (mode != e.mode) e.factored = false;
   e.mode = mode;
@@ -154,10 +167,12 @@ int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, i
 }
 
 int64_t Engine::device_bytes() const {
+  d_->join_prepare();
   return d_->bytes_held();
 }
 
 void Engine::reset_caches(bool release) {
+  d_->join_prepare();
   EngineImpl& e = *d_;
   e.factored = false;
   e.vcache_valid = false;
@@ -171,32 +186,51 @@ void Engine::reset_caches(bool release) {
   e.kz = 0;
 }
 
-void Engine::set_timing(bool on) { d_->timer.enabled = on; }
+void Engine::set_timing(bool on) {
+  d_->join_prepare();
+  d_->timer.enabled = on;
+}
 
 void Engine::set_pole_window(int w) {
+  d_->join_prepare();
   if (d_->max_window != w) d_->factored = false;
   d_->max_window = w;
 }
-void Engine::phase_times(double* ms16) { d_->timer.collect(ms16); }
+void Engine::phase_times(double* ms16) {
+  d_->join_prepare();
+  d_->timer.collect(ms16);
+}
 
 // ---------------------------------------------------------------------------
 void PhaseTimer::begin(hipStream_t s, int phase) {
   if (!enabled) return;
   Rec r;
   r.phase = phase;
+  r.s = s;
   RFD_HIP(hipEventCreate(&r.a));
   RFD_HIP(hipEventCreate(&r.b));
   RFD_HIP(hipEventRecord(r.a, s));
+  std::lock_guard<std::mutex> g(mu);
   open.push_back(r);
 }
+// closes the innermost open phase of stream s
 void PhaseTimer::end(hipStream_t s) {
-  if (!enabled || open.empty()) return;
-  Rec r = open.back();
-  open.pop_back();
+  if (!enabled) return;
+  Rec r;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = open.rbegin();
+    while (it != open.rend() && it->s != s) ++it;
+    if (it == open.rend()) return;
+    r = *it;
+    open.erase(std::next(it).base());
+  }
   RFD_HIP(hipEventRecord(r.b, s));
+  std::lock_guard<std::mutex> g(mu);
   done.push_back(r);
 }
 void PhaseTimer::collect(double* ms16) {
+  std::lock_guard<std::mutex> g(mu);
   for (auto& r : done) {
     RFD_HIP(hipEventSynchronize(r.b));
     float ms = 0;
@@ -236,10 +270,60 @@ std::vector<DevBuf*> EngineImpl::solve_buffers() {
   return v;
 }
 
+// Buffers an interior preparation writes (see prepare_interior).
+std::vector<DevBuf*> EngineImpl::prep_buffers() {
+  std::vector<DevBuf*> v{&Vb, &work1, &work2, &work3, &kap_d, &Bs, &Bsinv, &Bspiv, &prep_flags};
+  for (DevBuf* b : {&tw_v.d, &tw_v.e, &tw_v.tau, &tw_v.pt, &tw_v.acol, &tw_v.vw, &tw_v.red,
+                    &tw_v.sq, &tw_v.ptvp, &tw_v.wv, &tw_v.wg, &tw_v.wt, &tw_v.w1, &tw_v.w2})
+    v.push_back(b);
+  for (int i = 0; i <= 6; ++i) v.push_back(&tmp[i]);
+  return v;
+}
+
 int64_t EngineImpl::bytes_held() const {
+  EngineImpl* e = const_cast<EngineImpl*>(this);
+  // while a preparation runs, its buffers change size under it: they are
+  // left out (the estimate of what this pencil holds only gets smaller)
+  std::vector<DevBuf*> skip;
+  if (prep_running.load()) skip = e->prep_buffers();
   int64_t t = 0;
-  for (DevBuf* b : const_cast<EngineImpl*>(this)->solve_buffers()) t += (int64_t)b->bytes;
+  for (DevBuf* b : e->solve_buffers())
+    if (std::find(skip.begin(), skip.end(), b) == skip.end()) t += (int64_t)b->bytes;
   return t;
+}
+
+void EngineImpl::join_prepare() {
+  if (prep.joinable()) prep.join();
+  prep_running.store(false);
+  if (prep_err) {
+    std::exception_ptr e = prep_err;
+    prep_err = nullptr;
+    std::rethrow_exception(e);
+  }
+}
+
+void Engine::prepare_interior(double sig, int nevb) {
+  EngineImpl& e = *d_;
+  e.join_prepare();
+  if (e.vcache_valid && e.vcache_sigma == sig && e.vcache_nevb == nevb && e.bs_valid &&
+      e.bs_sigma == sig)
+    return;
+  if (!e.prep_stream) RFD_HIP(hipStreamCreateWithFlags(&e.prep_stream, hipStreamNonBlocking));
+  if (!e.prep_flags.p) {
+    e.prep_flags.alloc(sizeof(unsigned));
+    RFD_HIP(hipMemsetAsync(e.prep_flags.p, 0, sizeof(unsigned), e.prep_stream));
+  }
+  e.prep_running.store(true);
+  e.prep = std::thread([&e, sig, nevb]() {
+    try {
+      RFD_HIP(hipSetDevice(e.device));
+      e.interior_basis(e.prep_stream, sig, nevb);
+      e.factor_bsigma(e.prep_stream, sig, &e.prep_flags);
+      RFD_HIP(hipStreamSynchronize(e.prep_stream));
+    } catch (...) {
+      e.prep_err = std::current_exception();
+    }
+  });
 }
 
 double EngineImpl::read_scalar(hipStream_t s, int i) {
@@ -253,12 +337,13 @@ void EngineImpl::zero_scalar(hipStream_t s, int i) {
   RFD_HIP(hipMemsetAsync(scal.as<double>() + i, 0, sizeof(double), s));
 }
 
-void EngineImpl::check_flags(hipStream_t s, const char* what) {
+void EngineImpl::check_flags(hipStream_t s, const char* what, DevBuf* fb) {
+  DevBuf& fw = fb ? *fb : flags;
   unsigned f = 0;
-  RFD_HIP(hipMemcpyAsync(&f, flags.as<unsigned>(), sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  RFD_HIP(hipMemcpyAsync(&f, fw.as<unsigned>(), sizeof(unsigned), hipMemcpyDeviceToHost, s));
   RFD_HIP(hipStreamSynchronize(s));
   if (f) {
-    RFD_HIP(hipMemsetAsync(flags.p, 0, sizeof(unsigned), s));
+    RFD_HIP(hipMemsetAsync(fw.p, 0, sizeof(unsigned), s));
     throw Error(ST_EBREAKDOWN, std::string(what) + ": pivot below the breakdown threshold" +
                                    ((f & 2) ? " (non-finite value)" : ""));
   }

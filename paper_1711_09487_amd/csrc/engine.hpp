@@ -20,6 +20,10 @@ class Engine {
   void filter_interface(hipStream_t s, int m, const double* Y0, int steps, double* Q,
                         int64_t ldq_cols, int* mu);
   void filter_apply(hipStream_t s, int m, const double* Y, double* W);
+  // Starts the sigma-dependent interior caches (V_j, the B_sigma factors) on
+  // an internal thread and stream; every call below except filter_interface
+  // and filter_apply first waits for it (and reports its error).
+  void prepare_interior(double sigma, int nev_b);
   void solve_interior(hipStream_t s, double sigma, int nev_b, int psi, int64_t* k);
   void rayleigh_ritz(hipStream_t s, int max_out, double* evals, double* evecs, double* resid,
                      int* nfound);

@@ -3,6 +3,10 @@
 // interior / Rayleigh-Ritz workspaces.
 #pragma once
 
+#include <atomic>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "engine.hpp"
@@ -20,8 +24,10 @@ struct DevPairGroup {
 struct PhaseTimer {
   struct Rec {
     int phase;
+    hipStream_t s;
     hipEvent_t a, b;
   };
+  std::mutex mu;  // phases may run on two host threads (interior preparation)
   bool enabled = false;
   std::vector<Rec> open, done;
   double acc[16] = {0};
@@ -88,12 +94,22 @@ struct EngineImpl {
   // every buffer that a solve grows (released by reset_caches(true))
   std::vector<DevBuf*> solve_buffers();
   DevBuf flags, scal;
+  // interior preparation (V_j and the B_sigma factors) running on a thread
+  // and stream of its own, concurrently with the filter
+  int device = 0;
+  std::thread prep;
+  std::atomic<bool> prep_running{false};
+  std::exception_ptr prep_err;
+  hipStream_t prep_stream = nullptr;
+  DevBuf prep_flags;
+  std::vector<DevBuf*> prep_buffers();
+  void join_prepare();
 
   int64_t bytes_held() const;
   int64_t interior_bytes() const;
   double read_scalar(hipStream_t s, int i);
   void zero_scalar(hipStream_t s, int i);
-  void check_flags(hipStream_t s, const char* what);
+  void check_flags(hipStream_t s, const char* what, DevBuf* f = nullptr);
   int pole_chunk() const;
   // Factors poles [w0, w0 + wn) (the "window": S buffers hold wn poles)
   void factor(hipStream_t st, int w0, int wn);
@@ -108,7 +124,7 @@ struct EngineImpl {
   int max_window = 0;  // caller's cap on the pole window (0: by free memory)
   void ensure_reordered(hipStream_t st);
   void interior_basis(hipStream_t st, double sigma, int nev_b);
-  void factor_bsigma(hipStream_t st, double sigma);
+  void factor_bsigma(hipStream_t st, double sigma, DevBuf* fl = nullptr);
   int gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,
                 double droptol);
   void project_out(hipStream_t st, double* X, int ncols, double* MX, const double* Zp,

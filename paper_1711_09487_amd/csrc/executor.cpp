@@ -193,6 +193,8 @@ void Executor::run(Req& r, hipStream_t st, DevBuf& Q, int w) {
       s = (rfd_status)code;
       break;
     }
+    // the Q-independent interior caches run beside the filter
+    if ((s = rfd_prepare_interior(P, j.sigma, j.nev_b))) break;
     int32_t mu = 0;
     if ((s = rfd_filter_interface(P, j.m, j.Y0, j.steps, Q.as<double>(), cols, &mu, st))) break;
     out.mu = mu;

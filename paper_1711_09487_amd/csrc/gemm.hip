@@ -307,9 +307,14 @@ __global__ void k_splitk_sum(int64_t M, int64_t N, int splits, int batch, const 
 
 // Per-stream split-K workspace (grown on demand; a stream's earlier work is
 // finished before its buffer is replaced).
+static std::mutex ws_mu;
+static std::map<std::pair<int, hipStream_t>, DevBuf> ws_map;
+static std::mutex h_mu;
+static std::map<std::pair<int, hipStream_t>, rocblas_handle> h_map;
+
 static void* splitk_workspace(hipStream_t s, size_t bytes) {
-  static std::mutex mu;
-  static std::map<std::pair<int, hipStream_t>, DevBuf> ws;
+  std::mutex& mu = ws_mu;
+  auto& ws = ws_map;
   int dev = 0;
   RFD_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> g(mu);
@@ -323,8 +328,8 @@ static void* splitk_workspace(hipStream_t s, size_t bytes) {
 
 // One rocBLAS handle per (device, stream), created on first use.
 static rocblas_handle blas_handle(hipStream_t s) {
-  static std::mutex mu;
-  static std::map<std::pair<int, hipStream_t>, rocblas_handle> hs;
+  std::mutex& mu = h_mu;
+  auto& hs = h_map;
   int dev = 0;
   RFD_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> g(mu);
@@ -339,6 +344,22 @@ static rocblas_handle blas_handle(hipStream_t s) {
   if (rocblas_set_stream(h, s) != rocblas_status_success)
     throw Error(ST_EDEVICE, "rocblas_set_stream failed");
   return h;
+}
+
+void release_stream_resources(hipStream_t s) {
+  int dev = 0;
+  RFD_HIP(hipGetDevice(&dev));
+  RFD_HIP(hipStreamSynchronize(s));
+  {
+    std::lock_guard<std::mutex> g(ws_mu);
+    ws_map.erase({dev, s});
+  }
+  std::lock_guard<std::mutex> g(h_mu);
+  auto it = h_map.find({dev, s});
+  if (it != h_map.end()) {
+    if (it->second) (void)rocblas_destroy_handle(it->second);
+    h_map.erase(it);
+  }
 }
 
 static void blas_check(rocblas_status st, const char* what) {

@@ -469,7 +469,8 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   vcache_nevb = nevb;
 }
 
-void EngineImpl::factor_bsigma(hipStream_t st, double sig) {
+void EngineImpl::factor_bsigma(hipStream_t st, double sig, DevBuf* fl) {
+  DevBuf& fw = fl ? *fl : flags;
   if (bs_valid && bs_sigma == sig) return;
   timer.begin(st, 7);
   Bs.alloc(sizeof(double) * D * D * p);
@@ -480,9 +481,9 @@ void EngineImpl::factor_bsigma(hipStream_t st, double sig) {
   fill<double>(st, K, D, D, p, 0.0);
   Shifts z{zeta.as<double>()};
   expand_shifted<double>(st, K, D, p, 1, 0, dj.as<int32_t>(), Bg.view(), z, true, sig);
-  lu_piv<double>(st, K, D, p, Ki, Bspiv.as<int32_t>(), flags.as<unsigned>(), 1e-300);
+  lu_piv<double>(st, K, D, p, Ki, Bspiv.as<int32_t>(), fw.as<unsigned>(), 1e-300);
   timer.end(st);
-  check_flags(st, "B_sigma factorization");
+  check_flags(st, "B_sigma factorization", &fw);
   bs_valid = true;
   bs_sigma = sig;
 }
@@ -594,6 +595,7 @@ void EngineImpl::project_out(hipStream_t st, double* X, int ncols, double* MX, c
 
 void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64_t* kout) {
   EngineImpl& e = *d_;
+  e.join_prepare();
   if (e.Qint.p == nullptr) throw Error(ST_ESTATE, "rfd_filter_interface has not been called");
   if (!e.P->m_diag) throw Error(ST_EINVAL, "the interior part on the GPU needs a diagonal M");
   e.ensure_reordered(st);
@@ -729,6 +731,7 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
 
 void Engine::copy_basis(hipStream_t st, double* dst, int64_t cap, int64_t* k) {
   EngineImpl& e = *d_;
+  e.join_prepare();
   *k = e.interior_ready ? e.kz : 0;
   const int64_t c = std::min(cap, *k);
   if (c > 0)
@@ -739,6 +742,7 @@ void Engine::copy_basis(hipStream_t st, double* dst, int64_t cap, int64_t* k) {
 void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* evecs,
                            double* resid, int* nfound) {
   EngineImpl& e = *d_;
+  e.join_prepare();
   if (!e.interior_ready) throw Error(ST_ESTATE, "rfd_solve_interior has not been called");
   const int64_t n = e.n, k = e.kz;
   *nfound = 0;

@@ -185,6 +185,40 @@ def test_config2_full_size_against_stored_oracle():
         assert np.max(g["resid"]) <= 10 * max(gold["resid"]) + 1e-12
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_prepared_interior_matches_the_sequential_path(mode):
+    """rfd_prepare_interior runs V_j and the B_sigma factors on the
+    library's own thread and stream beside the filter; the Ritz values and
+    residuals equal those of the plain call sequence, and the oracle's."""
+    torch = _torch()
+    prob, ref = _prob("tiny_uneven_p9_random")
+    outs = []
+    for prepared in (False, True):
+        P = _pencil(prob, mode)
+        if prepared:
+            P.prepare_interior(prob.sigma, prob.nev_b)
+        P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
+        P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+        ev, _, res = P.rayleigh_ritz(prob.nev + 20)
+        outs.append((ev.cpu().numpy(), res.cpu().numpy()))
+        # a second preparation with another sigma, then the old one again
+        P.prepare_interior(prob.sigma + 0.1, prob.nev_b)
+        P.prepare_interior(prob.sigma, prob.nev_b)
+        P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+        ev2, _, _ = P.rayleigh_ritz(prob.nev + 20)
+        assert np.array_equal(ev2.cpu().numpy(), outs[-1][0])
+        # calls that must wait for a running preparation
+        P.prepare_interior(prob.sigma + 0.05, prob.nev_b)
+        P.reset_caches(True)
+        P.prepare_interior(prob.sigma, prob.nev_b)
+        P.close()
+    (a, ra), (b, rb) = outs
+    assert a.size == b.size == ref.theta.size
+    assert np.max(np.abs(a - b) / np.abs(b)) <= 1e-14
+    assert np.max(np.abs(ra - rb)) <= 1e-14
+    assert np.max(np.abs(b - ref.theta) / np.abs(ref.theta)) <= EIG_TOL
+
+
 # ---------------------------------------------------------------- edge cases
 def test_empty_interval_finds_nothing():
     torch = _torch()
