@@ -251,16 +251,19 @@ rfd_status rfd_set_pole_window(rfd_pencil_t pencil, int32_t max_poles);
  * selected kernels: the batched GEMM (the matrix-core kernel behind the LU
  * updates, the triangular solves, the refinement residuals and the
  * Rayleigh-Ritz products, Secs. 3-5) and the symmetric mat-vec of the dense
- * eigensolver's tridiagonalization.  With every = k >= 1, every k-th launch
- * of each kernel gets a pair of HIP events on its own stream, stamped at the
+ * eigensolver's tridiagonalization.  With every = k >= 1, one launch in k of
+ * each kernel (picked by a fixed hash of the launch count, so that a periodic
+ * launch sequence is not sampled at a few phases only; the same launches in
+ * every run) gets a pair of HIP events on its own stream, stamped at the
  * kernel's start and end by the launch itself (around the call for products
  * handed to rocBLAS), and its algorithmic flop and byte counts are recorded
  * (GEMM: 2MNK real or 8MNK complex flops; bytes of A and B read once and of
- * C written, plus read when beta != 0; mat-vec: the trailing block and its
- * vectors).  every = 0 turns it off.  rfd_kernel_stats synchronises the
- * events and returns, for 32 keys (host arrays of 32 doubles each), the
- * number of launches, the number sampled, and the summed milliseconds, flops
- * and bytes of the sampled launches, then clears the record.  Keys 0..15:
+ * C written, plus read when beta != 0; mat-vec: the lower triangle of the
+ * trailing block and its vectors).  every = 0 turns it off.
+ * rfd_kernel_stats synchronises the events and returns, for 32 keys (host
+ * arrays of 32 doubles each), the number of launches, the number sampled,
+ * and the summed milliseconds, flops and bytes of the sampled launches, then
+ * clears the record.  Keys 0..15:
  * the hand-written GEMM with key = 8*fp64 + 4*complex + 2*transA + transB;
  * key 16: the tridiagonalization mat-vec; key 17: FP64 products handed to
  * rocBLAS; the other keys are unused.

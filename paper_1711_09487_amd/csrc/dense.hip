@@ -25,7 +25,13 @@ KernelAccount::Scope::Scope(hipStream_t s, int key, double flops, double bytes) 
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> g(k.mu);
-  if (k.count[key]++ % k.every != 0) return;
+  // a pseudo-random one launch in `every` (a fixed hash of the launch count):
+  // a plain stride would sample a periodic launch sequence at a few phases
+  uint64_t h = (uint64_t)k.count[key]++ * 0x9E3779B97F4A7C15ull + (uint64_t)key;
+  h ^= h >> 31;
+  h *= 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 29;
+  if (h % (uint64_t)k.every != 0) return;
   Rec r;
   r.key = key;
   r.flops = flops;
