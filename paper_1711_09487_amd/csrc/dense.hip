@@ -110,95 +110,169 @@ __device__ inline void fma_sub(T& sr, T& si, T ar, T ai, T br, T bi) {
   }
 }
 
-// Inverses of the unit-lower and the upper triangle of the factored block F,
-// one row at a time: the 64 columns of a row are formed in parallel, each as
-// four partial sums (256 threads), so a row costs at most 16 products per
-// thread and two barriers.  A dropped column (semidefinite mode) gets a zero
-// row in Linv, so that the panel update leaves a zero row of U beside it.
 template <typename T, bool CPLX>
-__device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], T (*P)[4][NB],
-                             DMat<T> Linv, DMat<T> Uinv, const int* dropped = nullptr) {
-  constexpr int NP = CPLX ? 2 : 1;
-  const int tid = threadIdx.x, c = tid & (NB - 1), g = tid >> 6;
-  // Linv: X[i][c] = -sum_{t=c}^{i-1} L[i][t] X[t][c] (c < i), X[i][i] = 1
-  for (int e = tid; e < NB * NB; e += 256) {
-    X[0][e % NB][e / NB] = (e % NB == e / NB) ? T(1) : T(0);
-    if constexpr (CPLX) X[NP - 1][e % NB][e / NB] = 0;
-  }
-  __syncthreads();
-  for (int i = 1; i < NB; ++i) {
-    T sr = 0, si = 0;
-    if (c < i)
-      for (int t = c + g; t < i; t += 4)
-        fma_sub<T, CPLX>(sr, si, F[0][i][t], F[NP - 1][i][t], X[0][t][c], X[NP - 1][t][c]);
-    P[0][g][c] = sr;
-    if constexpr (CPLX) P[NP - 1][g][c] = si;
-    __syncthreads();
-    if (g == 0 && c < i) {
-      X[0][i][c] = P[0][0][c] + P[0][1][c] + P[0][2][c] + P[0][3][c];
-      if constexpr (CPLX) X[NP - 1][i][c] = P[NP - 1][0][c] + P[NP - 1][1][c] + P[NP - 1][2][c] + P[NP - 1][3][c];
-    }
-    __syncthreads();
-  }
-  if (dropped)
-    for (int e = tid; e < NB * NB; e += 256)
-      if (dropped[e % NB]) X[0][e % NB][e / NB] = 0;
-  __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, cc = e / NB;
-    Linv.re[i + cc * Linv.ld] = X[0][i][cc];
-    if constexpr (CPLX) Linv.im[i + cc * Linv.ld] = X[NP - 1][i][cc];
-  }
-  __syncthreads();
-  // Uinv: X[i][c] = (delta_ic - sum_{t=i+1}^{c} U[i][t] X[t][c]) / U[i][i] (c >= i)
-  for (int e = tid; e < NB * NB; e += 256) {
-    X[0][e % NB][e / NB] = 0;
-    if constexpr (CPLX) X[NP - 1][e % NB][e / NB] = 0;
-  }
-  __syncthreads();
-  for (int i = NB - 1; i >= 0; --i) {
-    T sr = 0, si = 0;
-    if (c >= i)
-      for (int t = i + 1 + g; t <= c; t += 4)
-        fma_sub<T, CPLX>(sr, si, F[0][i][t], F[NP - 1][i][t], X[0][t][c], X[NP - 1][t][c]);
-    P[0][g][c] = sr;
-    if constexpr (CPLX) P[NP - 1][g][c] = si;
-    __syncthreads();
-    if (g == 0 && c >= i) {
-      T vr = (c == i ? T(1) : T(0)) + P[0][0][c] + P[0][1][c] + P[0][2][c] + P[0][3][c];
-      if constexpr (CPLX) {
-        T vi = P[NP - 1][0][c] + P[NP - 1][1][c] + P[NP - 1][2][c] + P[NP - 1][3][c];
-        T ir, ii, qr, qi;
-        cinv(F[0][i][i], F[NP - 1][i][i], ir, ii);
-        cmul(vr, vi, ir, ii, qr, qi);
-        X[0][i][c] = qr;
-        X[NP - 1][i][c] = qi;
-      } else {
-        X[0][i][c] = vr / F[0][i][i];
-      }
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, cc = e / NB;
-    Uinv.re[i + cc * Uinv.ld] = X[0][i][cc];
-    if constexpr (CPLX) Uinv.im[i + cc * Uinv.ld] = X[NP - 1][i][cc];
+__device__ inline void fma_add(T& sr, T& si, T ar, T ai, T br, T bi) {
+  if constexpr (CPLX) {
+    sr += ar * br - ai * bi;
+    si += ar * bi + ai * br;
+  } else {
+    sr += ar * br;
   }
 }
 
-// Factor one NB x NB diagonal block without pivoting in LDS.  Thread t owns
-// the 4 x 4 sub-block rows 4 (t / 16) .. +3, columns 4 (t % 16) .. +3 of the
-// rank-1 updates.
+// Inverses of the unit-lower and the upper triangle of the factored block F
+// (NB = 64), blocked: the four 16 x 16 diagonal blocks are inverted at once
+// (a wave each, a lane per column), then pairs are merged into 32 x 32 and
+// those into 64 x 64 with
+//   [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1} C^{-1}]
+// (and the upper-triangular mirror), two small products per merge.  A
+// dropped column (semidefinite mode) gets a zero row in Linv, so that the
+// panel update leaves a zero row of U beside it.  Tb: 32 x 33 per plane.
+template <typename T, bool CPLX>
+__device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], T (*Tb)[32][33],
+                             DMat<T> Linv, DMat<T> Uinv, const int* dropped = nullptr) {
+  constexpr int NP = CPLX ? 2 : 1;
+  static_assert(NB == 64, "blocked inversion assumes 64 x 64 blocks");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int half = 0; half < 2; ++half) {
+    const bool lower = half == 0;
+    // element (i, j) of the triangle being inverted, from F (unit diagonal
+    // for L)
+    auto tr = [&](int i, int j, T& vr, T& vi) {
+      vr = F[0][i][j];
+      vi = CPLX ? F[NP - 1][i][j] : T(0);
+    };
+    for (int e = tid; e < NB * NB; e += 256) {
+      X[0][e % NB][e / NB] = 0;
+      if constexpr (CPLX) X[NP - 1][e % NB][e / NB] = 0;
+    }
+    __syncthreads();
+    // 16 x 16 diagonal blocks: wave g, lane c = column
+    if (lane < 16) {
+      const int b = 16 * wave, c = lane;
+      T xr[16], xi[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xr[i] = xi[i] = 0;
+      if (lower) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if (i == c) xr[i] = 1;
+          if (i > c) {
+            T sr = 0, si = 0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+              if (t >= c && t < i) {
+                T lr, li;
+                tr(b + i, b + t, lr, li);
+                fma_sub<T, CPLX>(sr, si, lr, li, xr[t], xi[t]);
+              }
+            xr[i] = sr;
+            xi[i] = si;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+          if (i <= c) {
+            T sr = (i == c) ? T(1) : T(0), si = 0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+              if (t > i && t <= c) {
+                T ur, ui;
+                tr(b + i, b + t, ur, ui);
+                fma_sub<T, CPLX>(sr, si, ur, ui, xr[t], xi[t]);
+              }
+            T dr, di;
+            tr(b + i, b + i, dr, di);
+            if constexpr (CPLX) {
+              T ir, ii;
+              cinv(dr, di, ir, ii);
+              cmul(sr, si, ir, ii, xr[i], xi[i]);
+            } else {
+              xr[i] = sr / dr;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        X[0][b + i][b + c] = xr[i];
+        if constexpr (CPLX) X[NP - 1][b + i][b + c] = xi[i];
+      }
+    }
+    __syncthreads();
+    // merges: width w = 16 (two pairs), then w = 32 (one pair)
+    for (int w = 16; w <= 32; w *= 2) {
+      const int npair = NB / (2 * w);
+      const int per = w * w;  // entries of one off-diagonal block
+      // lower: T = B X_A (B = L[b+w.., b..], X_A = X[b.., b..]);
+      // upper: T = U_AB X_C (U_AB = U[b.., b+w..], X_C = X[b+w.., b+w..])
+      for (int e = tid; e < npair * per; e += 256) {
+        const int pr = e / per, q = e % per, i = q % w, j = q / w, b = 2 * w * pr;
+        T sr = 0, si = 0;
+        for (int t = 0; t < w; ++t) {
+          T ar, ai;
+          if (lower) {
+            tr(b + w + i, b + t, ar, ai);
+            fma_add<T, CPLX>(sr, si, ar, ai, X[0][b + t][b + j], CPLX ? X[NP - 1][b + t][b + j] : T(0));
+          } else {
+            tr(b + i, b + w + t, ar, ai);
+            fma_add<T, CPLX>(sr, si, ar, ai, X[0][b + w + t][b + w + j],
+                             CPLX ? X[NP - 1][b + w + t][b + w + j] : T(0));
+          }
+        }
+        Tb[0][pr * w + i][j] = sr;
+        if constexpr (CPLX) Tb[NP - 1][pr * w + i][j] = si;
+      }
+      __syncthreads();
+      // lower: X[b+w+i, b+j] = -(X_C T)[i, j]; upper: X[b+i, b+w+j] = -(X_A T)[i, j]
+      for (int e = tid; e < npair * per; e += 256) {
+        const int pr = e / per, q = e % per, i = q % w, j = q / w, b = 2 * w * pr;
+        T sr = 0, si = 0;
+        for (int t = 0; t < w; ++t) {
+          const int xi0 = lower ? b + w + i : b + i, xj0 = lower ? b + w + t : b + t;
+          fma_sub<T, CPLX>(sr, si, X[0][xi0][xj0], CPLX ? X[NP - 1][xi0][xj0] : T(0),
+                           Tb[0][pr * w + t][j], CPLX ? Tb[NP - 1][pr * w + t][j] : T(0));
+        }
+        const int oi = lower ? b + w + i : b + i, oj = lower ? b + j : b + w + j;
+        X[0][oi][oj] = sr;
+        if constexpr (CPLX) X[NP - 1][oi][oj] = si;
+      }
+      __syncthreads();
+    }
+    if (lower && dropped) {
+      for (int e = tid; e < NB * NB; e += 256)
+        if (dropped[e % NB]) {
+          X[0][e % NB][e / NB] = 0;
+          if constexpr (CPLX) X[NP - 1][e % NB][e / NB] = 0;
+        }
+      __syncthreads();
+    }
+    DMat<T> out = lower ? Linv : Uinv;
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int i = e % NB, cc = e / NB;
+      out.re[i + cc * out.ld] = X[0][i][cc];
+      if constexpr (CPLX) out.im[i + cc * out.ld] = X[NP - 1][i][cc];
+    }
+    __syncthreads();
+  }
+}
+
+// Factor one NB x NB diagonal block without pivoting in LDS, in four panels
+// of 16 columns: wave 0 factors the panel (a lane per row, the pivot row
+// passed by shuffles, no barrier per column), then 16 threads solve the
+// block row of U right of the panel and all threads update the trailing
+// block.
 template <typename T, bool CPLX>
 __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> inv, int iblk,
                                                  unsigned* flags, T tiny, int* drop, T droptol) {
   constexpr int NP = CPLX ? 2 : 1;
+  constexpr int PW = 16;
   __shared__ T F[NP][NB][NB + 1];
   __shared__ T X[NP][NB][NB + 1];
-  __shared__ T P[NP][4][NB];
+  __shared__ T Tb[NP][32][33];
   __shared__ int dl[NB];
-  const int tid = threadIdx.x;
-  const int r0 = 4 * (tid >> 4), c0 = 4 * (tid & 15);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid < NB) dl[tid] = 0;
   DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
   for (int e = tid; e < NB * NB; e += 256) {
@@ -207,69 +281,101 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
     if constexpr (CPLX) F[NP - 1][i][j] = a.im[i + j * a.ld];
   }
   __syncthreads();
-  for (int j = 0; j < NB; ++j) {
-    const T pr = F[0][j][j], pim = CPLX ? F[NP - 1][j][j] : T(0);
-    if (!CPLX && drop && !(pr > droptol)) {
-      // semidefinite mode: the Schur complement pivot vanished, so column j
-      // lies in the span of the earlier ones; it is removed from the factor
-      __syncthreads();
-      for (int i = j + 1 + tid; i < NB; i += 256) {
-        F[0][i][j] = 0;
-        F[0][j][i] = 0;
+  for (int c0 = 0; c0 < NB; c0 += PW) {
+    if (wave == 0) {
+      const int r = lane;
+      T ar[PW], ai[PW];
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        ar[q] = F[0][r][c0 + q];
+        ai[q] = CPLX ? F[NP - 1][r][c0 + q] : T(0);
       }
-      if (tid == 0) {
-        F[0][j][j] = 1;
-        dl[j] = 1;
-        drop[k0 + j] = 1;
+#pragma unroll
+      for (int kk = 0; kk < PW; ++kk) {
+        const int j = c0 + kk;
+        const T pr = __shfl(ar[kk], j, 64);
+        const T pim = CPLX ? __shfl(ai[kk], j, 64) : T(0);
+        if (!CPLX && drop && !(pr > droptol)) {
+          // semidefinite mode: the pivot of the Schur complement vanished,
+          // so column j lies in the span of the earlier ones; it is removed
+          // from the factor (unit column of L, unit row of U)
+          if (r > j) ar[kk] = 0;
+          if (r == j) {
+            ar[kk] = 1;
+#pragma unroll
+            for (int q = 0; q < PW; ++q)
+              if (q > kk) ar[q] = 0;
+            dl[j] = 1;
+            drop[k0 + j] = 1;
+          }
+          continue;
+        }
+        if (r == 0) {
+          const T mag = CPLX ? sqrt(pr * pr + pim * pim) : fabs(pr);
+          if (!(mag > tiny)) atomicOr(flags, (mag == mag) ? 1u : 2u);
+        }
+        T ir, ii = 0;
+        if constexpr (CPLX) cinv(pr, pim, ir, ii);
+        else ir = T(1) / pr;
+        T lr = 0, li = 0;
+        if (r > j) {
+          if constexpr (CPLX) cmul(ar[kk], ai[kk], ir, ii, lr, li);
+          else lr = ar[kk] * ir;
+          ar[kk] = lr;
+          ai[kk] = li;
+        }
+#pragma unroll
+        for (int q = 0; q < PW; ++q)
+          if (q > kk) {
+            const T ur = __shfl(ar[q], j, 64);
+            const T ui = CPLX ? __shfl(ai[q], j, 64) : T(0);
+            if (r > j) fma_sub<T, CPLX>(ar[q], ai[q], lr, li, ur, ui);
+          }
       }
-      __syncthreads();
-      continue;
-    }
-    if (tid == 0) {
-      const T mag = CPLX ? sqrt(pr * pr + pim * pim) : fabs(pr);
-      if (!(mag > tiny)) atomicOr(flags, (mag == mag) ? 1u : 2u);
-    }
-    // column j below the diagonal scaled by 1 / pivot (by the 64 lowest threads)
-    if (tid > j && tid < NB) {
-      T ir, ii = 0;
-      if constexpr (CPLX) {
-        cinv(pr, pim, ir, ii);
-        T qr, qi;
-        cmul(F[0][tid][j], F[NP - 1][tid][j], ir, ii, qr, qi);
-        F[0][tid][j] = qr;
-        F[NP - 1][tid][j] = qi;
-      } else {
-        ir = T(1) / pr;
-        F[0][tid][j] *= ir;
+      if (r >= c0) {
+#pragma unroll
+        for (int q = 0; q < PW; ++q) {
+          F[0][r][c0 + q] = ar[q];
+          if constexpr (CPLX) F[NP - 1][r][c0 + q] = ai[q];
+        }
       }
     }
     __syncthreads();
-    // rank-1 update of the trailing block over the owned 4 x 4 entries
-    if (r0 + 3 > j && c0 + 3 > j) {
-      T lr[4], li[4], ur[4], ui[4];
+    const int c1 = c0 + PW, m2 = NB - c1;
+    if (m2 <= 0) break;
+    // U12 = L11^{-1} A12: a thread per column right of the panel
+    if (tid < m2) {
+      const int cc = c1 + tid;
+      T xr[PW], xi[PW];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        lr[q] = F[0][r0 + q][j];
-        ur[q] = F[0][j][c0 + q];
-        if constexpr (CPLX) {
-          li[q] = F[NP - 1][r0 + q][j];
-          ui[q] = F[NP - 1][j][c0 + q];
-        } else {
-          li[q] = ui[q] = 0;
-        }
+      for (int i = 0; i < PW; ++i) {
+        T sr = F[0][c0 + i][cc], si = CPLX ? F[NP - 1][c0 + i][cc] : T(0);
+#pragma unroll
+        for (int t = 0; t < PW; ++t)
+          if (t < i)
+            fma_sub<T, CPLX>(sr, si, F[0][c0 + i][c0 + t], CPLX ? F[NP - 1][c0 + i][c0 + t] : T(0),
+                             xr[t], xi[t]);
+        if (dl[c0 + i]) sr = si = 0;
+        xr[i] = sr;
+        xi[i] = si;
       }
 #pragma unroll
-      for (int qi = 0; qi < 4; ++qi)
+      for (int i = 0; i < PW; ++i) {
+        F[0][c0 + i][cc] = xr[i];
+        if constexpr (CPLX) F[NP - 1][c0 + i][cc] = xi[i];
+      }
+    }
+    __syncthreads();
+    // A22 -= L21 U12
+    for (int e = tid; e < m2 * m2; e += 256) {
+      const int i = c1 + e % m2, cc = c1 + e / m2;
+      T sr = F[0][i][cc], si = CPLX ? F[NP - 1][i][cc] : T(0);
 #pragma unroll
-        for (int qc = 0; qc < 4; ++qc) {
-          const int i = r0 + qi, cc = c0 + qc;
-          if (i > j && cc > j) {
-            T sr = F[0][i][cc], si = CPLX ? F[NP - 1][i][cc] : T(0);
-            fma_sub<T, CPLX>(sr, si, lr[qi], li[qi], ur[qc], ui[qc]);
-            F[0][i][cc] = sr;
-            if constexpr (CPLX) F[NP - 1][i][cc] = si;
-          }
-        }
+      for (int t = 0; t < PW; ++t)
+        fma_sub<T, CPLX>(sr, si, F[0][i][c0 + t], CPLX ? F[NP - 1][i][c0 + t] : T(0),
+                         F[0][c0 + t][cc], CPLX ? F[NP - 1][c0 + t][cc] : T(0));
+      F[0][i][cc] = sr;
+      if constexpr (CPLX) F[NP - 1][i][cc] = si;
     }
     __syncthreads();
   }
@@ -279,7 +385,7 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
     if constexpr (CPLX) a.im[i + j * a.ld] = F[NP - 1][i][j];
   }
   DMat<T> iv = inv.item(blockIdx.x);
-  tri_inverses<T, CPLX>(F, X, P, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB),
+  tri_inverses<T, CPLX>(F, X, Tb, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB),
                         drop ? dl : nullptr);
 }
 
@@ -289,7 +395,7 @@ __global__ __launch_bounds__(256) void k_tri_inv(DMat<T> A, int64_t k0, DMat<T> 
   constexpr int NP = CPLX ? 2 : 1;
   __shared__ T F[NP][NB][NB + 1];
   __shared__ T X[NP][NB][NB + 1];
-  __shared__ T P[NP][4][NB];
+  __shared__ T Tb[NP][32][33];
   const int tid = threadIdx.x;
   DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
   for (int e = tid; e < NB * NB; e += 256) {
@@ -299,7 +405,7 @@ __global__ __launch_bounds__(256) void k_tri_inv(DMat<T> A, int64_t k0, DMat<T> 
   }
   __syncthreads();
   DMat<T> iv = inv.item(blockIdx.x);
-  tri_inverses<T, CPLX>(F, X, P, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB));
+  tri_inverses<T, CPLX>(F, X, Tb, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB));
 }
 
 // ---------------------------------------------------------------------------
