@@ -818,16 +818,17 @@ __global__ void k_wy_v(DMat<double> A, int64_t n, int64_t i0, int nbp, double* V
 
 // T (WY_NB x WY_NB, upper) of the block from tau and G = V^T V.  The
 // recurrence T[k][k] = tau_k, T[0:k, k] = -tau_k T[0:k, 0:k] G[0:k, k] runs
-// on the four diagonal 32 x 32 blocks at once (a group of 64 threads each,
-// in shared memory); then block column b takes
-// T[0:32b, blk b] = -T[0:32b, 0:32b] G[0:32b, blk b] T_bb, which is the same
-// recurrence applied a block at a time.  One workgroup of 256 per item; T is
-// written to global memory and read back by the same workgroup.
+// on the four diagonal 32 x 32 blocks at once (a group of 64 threads each);
+// then block column b takes T[0:32b, blk b] = -T[0:32b, 0:32b] G[0:32b, blk b]
+// T_bb, which is the same recurrence applied a block at a time.  One
+// workgroup of 256 per item; the upper triangle of T stays in shared memory
+// (packed by columns) until it is written out whole.
 constexpr int WY_SB = 32;
 __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tauv, int64_t n,
                                               int64_t i0, int nbp, double* T) {
   constexpr int NS = WY_NB / WY_SB;
   __shared__ double Ts[NS][WY_SB][WY_SB + 1];
+  __shared__ double Tp[WY_NB * (WY_NB + 1) / 2];
   // the diagonal blocks of G, later X (both fit in the larger of the two)
   constexpr int SH = NS * WY_SB * (WY_SB + 1) > (WY_NB - WY_SB) * (WY_SB + 1)
                          ? NS * WY_SB * (WY_SB + 1)
@@ -835,16 +836,17 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
   __shared__ double sh[SH];
   auto Gd = [&](int a, int r, int c) -> double& { return sh[(a * WY_SB + r) * (WY_SB + 1) + c]; };
   auto X = [&](int r, int c) -> double& { return sh[r * (WY_SB + 1) + c]; };
+  auto Tu = [&](int r, int c) -> double& { return Tp[c * (c + 1) / 2 + r]; };  // r <= c
   const int b = blockIdx.x, t = threadIdx.x;
   const int grp = t / 64, lt = t % 64;
   const double* g = G + (int64_t)b * WY_NB * WY_NB;
   double* To = T + (int64_t)b * WY_NB * WY_NB;
   for (int e = t; e < NS * WY_SB * (WY_SB + 1); e += 256) (&Ts[0][0][0])[e] = 0.0;
+  for (int e = t; e < WY_NB * (WY_NB + 1) / 2; e += 256) Tp[e] = 0.0;
   for (int e = t; e < NS * WY_SB * WY_SB; e += 256) {
     const int a = e / (WY_SB * WY_SB), r = e % WY_SB, c = (e / WY_SB) % WY_SB;
     Gd(a, r, c) = g[(a * WY_SB + r) + (int64_t)(a * WY_SB + c) * WY_NB];
   }
-  for (int e = t; e < WY_NB * WY_NB; e += 256) To[e] = 0.0;
   __syncthreads();
   // diagonal blocks: group grp owns block grp (reflectors k0 + k)
   const int k0 = grp * WY_SB;
@@ -863,7 +865,7 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
   }
   for (int e = t; e < NS * WY_SB * WY_SB; e += 256) {
     const int a = e / (WY_SB * WY_SB), r = e % WY_SB, c = (e / WY_SB) % WY_SB;
-    To[(a * WY_SB + r) + (int64_t)(a * WY_SB + c) * WY_NB] = Ts[a][r][c];
+    if (r <= c) Tu(a * WY_SB + r, a * WY_SB + c) = Ts[a][r][c];
   }
   __syncthreads();
   // off-diagonal block columns
@@ -881,10 +883,14 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
     for (int e = t; e < rows * WY_SB; e += 256) {
       const int r = e % rows, c = e / rows;
       double acc = 0.0;
-      for (int q = r; q < rows; ++q) acc += To[r + (int64_t)q * WY_NB] * X(q, c);
-      To[r + (int64_t)(c0 + c) * WY_NB] = -acc;
+      for (int q = r; q < rows; ++q) acc += Tu(r, q) * X(q, c);
+      Tu(r, c0 + c) = -acc;
     }
     __syncthreads();
+  }
+  for (int e = t; e < WY_NB * WY_NB; e += 256) {
+    const int r = e % WY_NB, c = e / WY_NB;
+    To[e] = r <= c ? Tu(r, c) : 0.0;
   }
 }
 
