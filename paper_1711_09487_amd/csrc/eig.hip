@@ -448,13 +448,24 @@ void sy_tridiag(hipStream_t s, DMat<double> A, int64_t n, int batch, TriWork& w)
 // ---------------------------------------------------------------------------
 // Sturm counts and bisection.
 // ---------------------------------------------------------------------------
+// 1 / q from the hardware reciprocal estimate and two Newton steps (each
+// r <- r + r (1 - q r) doubles the correct bits), about 1 ulp: the Sturm
+// recurrence stays backward stable and its dependent chain is shorter than a
+// correctly rounded division's.
+__device__ inline double rcp_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
 __device__ inline int sturm(const double* d, const double* e, int64_t n, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0) ++cnt;
   for (int64_t i = 1; i < n; ++i) {
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    q = d[i] - x - e[i - 1] * e[i - 1] * rcp_nr(q);
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0) ++cnt;
   }
@@ -659,7 +670,10 @@ __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
     dd[(n - 1) * S] = fix(dcur);
 #pragma unroll 8
     for (int64_t r = 0; r < n; ++r) xa[r * S] = hash_unit((uint64_t)r + 1, (uint64_t)i + 7919ull * b);
-    for (int it = 0; it < 4; ++it) {
+    // three solves from a random start; the vector is normalised once at
+    // the end (one solve grows it by at most ~1 / (eps ||T||), far from
+    // overflow after three)
+    for (int it = 0; it < 3; ++it) {
       {  // L with the row interchanges: xa -> xb, running value in xc
         const double* __restrict__ src = xa;
         double* __restrict__ dst = xb;
@@ -744,22 +758,10 @@ __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
           xa = xb;
           xb = t;
         }
-      {
-        const double* __restrict__ src = xa;
-        double* __restrict__ dst = xb;
-        double nrm = 0;
-#pragma unroll 8
-        for (int64_t r = 0; r < n; ++r) nrm += src[r * S] * src[r * S];
-        nrm = sqrt(nrm);
-        const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-#pragma unroll 8
-        for (int64_t r = 0; r < n; ++r) dst[r * S] = src[r * S] * inv;
-        double* t = xa;
-        xa = xb;
-        xb = t;
-      }
     }
-    // sign convention: largest-magnitude component positive
+    // unit norm, sign convention: largest-magnitude component positive (the
+    // norm is accumulated on a scaled copy so that a large vector cannot
+    // overflow the sum of squares)
     const double* __restrict__ src = xa;
     int64_t am = 0;
     double best = -1.0;
@@ -771,10 +773,18 @@ __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
         am = r;
       }
     }
-    const double sg = src[am * S] < 0 ? -1.0 : 1.0;
+    const double sc = best > 0 ? 1.0 / best : 0.0;
+    double nrm = 0;
+#pragma unroll 8
+    for (int64_t r = 0; r < n; ++r) {
+      const double v = src[r * S] * sc;
+      nrm += v * v;
+    }
+    nrm = sqrt(nrm);
+    const double f = (src[am * S] < 0 ? -1.0 : 1.0) * (nrm > 0 ? sc / nrm : 0.0);
     double* __restrict__ yi = y.re + (int64_t)i * y.ld;
 #pragma unroll 8
-    for (int64_t r = 0; r < n; ++r) yi[r] = sg * src[r * S];
+    for (int64_t r = 0; r < n; ++r) yi[r] = f * src[r * S];
   }
 }
 
