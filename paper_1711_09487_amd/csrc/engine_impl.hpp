@@ -51,6 +51,7 @@ struct EngineImpl {
   std::vector<DevBuf> colors_d;
   DevBuf Aptr, Aidx, Aval, Mptr, Midx, Mval;      // original numbering
   DevBuf Arptr, Aridx, Arval, Mrptr, Mridx, Mrval;  // reordered numbering (lazy)
+  DevBuf Mrdiag;                                   // diag(M), reordered (diagonal M)
   // poles and precision
   Poles poles;
   DevBuf zeta, omega;
@@ -123,6 +124,9 @@ struct EngineImpl {
   int win0 = 0, winn = 0;
   int max_window = 0;  // caller's cap on the pole window (0: by free memory)
   void ensure_reordered(hipStream_t st);
+  // Y = M X in the reordered numbering (a row scaling when M is diagonal)
+  void apply_m(hipStream_t st, const double* X, int64_t ldx, double* Y, int64_t ldy,
+               int64_t cols);
   void interior_basis(hipStream_t st, double sigma, int nev_b);
   void factor_bsigma(hipStream_t st, double sigma, DevBuf* fl = nullptr);
   int gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,

@@ -327,6 +327,37 @@ void EngineImpl::ensure_reordered(hipStream_t st) {
     upload_v(st, w == 0 ? Arptr : Mrptr, ptr);
     upload_v(st, w == 0 ? Aridx : Mridx, idx);
     upload_v(st, w == 0 ? Arval : Mrval, val);
+    if (w == 1 && P->m_diag) {
+      std::vector<double> dg(n, 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e)
+          if (idx[e] == i) dg[i] += val[e];
+      upload_v(st, Mrdiag, dg);
+    }
+  }
+}
+
+// Y[:, c] = dg .* X[:, c]
+__global__ void k_diag_scale(const double* dg, int64_t n, const double* X, int64_t ldx, double* Y,
+                             int64_t ldy) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t c = blockIdx.y;
+  Y[r + c * ldy] = dg[r] * X[r + c * ldx];
+}
+
+void EngineImpl::apply_m(hipStream_t st, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                         int64_t cols) {
+  if (cols <= 0 || n <= 0) return;
+  if (!P->m_diag || !Mrdiag.p) {
+    csr_mm(st, Mrptr, Mridx, Mrval, n, X, ldx, Y, ldy, cols);
+    return;
+  }
+  for (int64_t c = 0; c < cols; c += 65535) {
+    const int64_t cc = std::min<int64_t>(cols - c, 65535);
+    k_diag_scale<<<dim3(grid1(n), (unsigned)cc), 256, 0, st>>>(Mrdiag.as<double>(), n, X + c * ldx,
+                                                              ldx, Y + c * ldy, ldy);
+    RFD_CHECK_LAUNCH();
   }
 }
 
@@ -507,7 +538,7 @@ __global__ void k_scale_uinv(double* Ui, int64_t ld, const double* U, int64_t ld
 int EngineImpl::gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,
                           double droptol) {
   const int64_t np = round_up(ncol, NB);
-  csr_mm(st, Mrptr, Mridx, Mrval, n, B, n, MB, n, ncol);
+  apply_m(st, B, n, MB, n, ncol);
   gwork.alloc(sizeof(double) * (3 * np * np + (int64_t)NB * 2 * np) + sizeof(int) * (2 * np + 2));
   double* G = gwork.as<double>();
   double* Ui = G + np * np;
@@ -556,7 +587,7 @@ void EngineImpl::project_out(hipStream_t st, double* X, int ncols, double* MX, c
   DMat<double> Xm{X, nullptr, n, 0}, MXm{MX, nullptr, n, 0};
   for (int pass = 0; pass < passes; ++pass) {
     if (kappa_tot > 0) {
-      csr_mm(st, Mrptr, Mridx, Mrval, n, X, n, MX, n, ncols);
+      apply_m(st, X, n, MX, n, ncols);
       work4.alloc(sizeof(double) * std::max<int64_t>(VB, 1) * std::max<int64_t>(MUP, ncols) * p);
       const int64_t ldt = std::max<int64_t>(VB, 1);
       bool uniform = true;
@@ -583,7 +614,7 @@ void EngineImpl::project_out(hipStream_t st, double* X, int ncols, double* MX, c
       }
     }
     if (kprev > 0) {
-      csr_mm(st, Mrptr, Mridx, Mrval, n, X, n, MX, n, ncols);
+      apply_m(st, X, n, MX, n, ncols);
       work6b.alloc(sizeof(double) * kprev * ncols);
       DMat<double> Zm{const_cast<double*>(Zp), nullptr, n, 0};
       DMat<double> Tq{work6b.as<double>(), nullptr, kprev, 0};
@@ -698,13 +729,13 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
                                                  n, e.Qint.as<double>(), s, mu);
     RFD_CHECK_LAUNCH();
     // column M-norms before projection
-    csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
+    e.apply_m(st, Lb, n, MLb, n, mu);
     k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n0);
     RFD_CHECK_LAUNCH();
     // project against V and the previous level blocks (M-inner product)
     const int64_t kprev = kz - e.kappa_tot;
     e.project_out(st, Lb, mu, MLb, Z + e.kappa_tot * n, kprev, 1);
-    csr_mm(st, e.Mrptr, e.Mridx, e.Mrval, n, Lb, n, MLb, n, mu);
+    e.apply_m(st, Lb, n, MLb, n, mu);
     k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n1);
     RFD_CHECK_LAUNCH();
     k_col_normalize<<<dim3(grid1(n), mu), 256, 0, st>>>(Lb, n, n, n1, n0, 1e-10);
