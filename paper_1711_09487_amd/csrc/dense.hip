@@ -417,31 +417,54 @@ __global__ __launch_bounds__(256) void k_tri_inv(DMat<T> A, int64_t k0, DMat<T> 
 // has a single tile row (M = NB) or column (N = NB).
 // ---------------------------------------------------------------------------
 // B <- L^{-1} B, L = unit-lower factor rows/cols n0 .. n0+nb-1; row i of B is row n0+i
+// Optional wide leaves for the solves: inverses of the LW x LW diagonal
+// blocks (merge_inverses) and a workspace for the leaf product, which cannot
+// overwrite its operand once it spans several tile rows.
+template <typename T>
+struct WideLeaves {
+  DMat<T> inv2;
+  int LW = 0;
+  DMat<T> work;
+};
+
 template <typename T>
 static void trsm_ll(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n0, int64_t nb, DMat<T> B,
-                    int64_t cols, int batch) {
+                    int64_t cols, int batch, const WideLeaves<T>& wl = WideLeaves<T>{}) {
+  if (wl.LW && nb == wl.LW) {
+    gemm<T>(s, false, false, nb, cols, nb, T(1), wl.inv2.sub(0, 2 * n0), B, T(0), wl.work, batch);
+    convert<T, T>(s, wl.work, B, nb, cols, batch);
+    return;
+  }
   if (nb == NB) {
     gemm<T>(s, false, false, NB, cols, NB, T(1), inv.sub(0, 2 * n0), B, T(0), B, batch);
     return;
   }
-  const int64_t h = (nb / NB / 2) * NB;
-  trsm_ll<T>(s, LU, inv, n0, h, B, cols, batch);
+  const int64_t unit = wl.LW ? wl.LW : NB;
+  const int64_t h = (nb / unit / 2) * unit;
+  trsm_ll<T>(s, LU, inv, n0, h, B, cols, batch, wl);
   gemm<T>(s, false, false, nb - h, cols, h, T(-1), LU.sub(n0 + h, n0), B, T(1), B.sub(h, 0), batch);
-  trsm_ll<T>(s, LU, inv, n0 + h, nb - h, B.sub(h, 0), cols, batch);
+  trsm_ll<T>(s, LU, inv, n0 + h, nb - h, B.sub(h, 0), cols, batch, wl);
 }
 
 // B <- U^{-1} B, U = upper factor rows/cols n0 .. n0+nb-1; row i of B is row n0+i
 template <typename T>
 static void trsm_ul(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n0, int64_t nb, DMat<T> B,
-                    int64_t cols, int batch) {
+                    int64_t cols, int batch, const WideLeaves<T>& wl = WideLeaves<T>{}) {
+  if (wl.LW && nb == wl.LW) {
+    gemm<T>(s, false, false, nb, cols, nb, T(1), wl.inv2.sub(0, 2 * n0 + nb), B, T(0), wl.work,
+            batch);
+    convert<T, T>(s, wl.work, B, nb, cols, batch);
+    return;
+  }
   if (nb == NB) {
     gemm<T>(s, false, false, NB, cols, NB, T(1), inv.sub(0, 2 * n0 + NB), B, T(0), B, batch);
     return;
   }
-  const int64_t h = (nb / NB / 2) * NB;
-  trsm_ul<T>(s, LU, inv, n0 + h, nb - h, B.sub(h, 0), cols, batch);
+  const int64_t unit = wl.LW ? wl.LW : NB;
+  const int64_t h = (nb / unit / 2) * unit;
+  trsm_ul<T>(s, LU, inv, n0 + h, nb - h, B.sub(h, 0), cols, batch, wl);
   gemm<T>(s, false, false, h, cols, nb - h, T(-1), LU.sub(n0, n0 + h), B.sub(h, 0), T(1), B, batch);
-  trsm_ul<T>(s, LU, inv, n0, h, B, cols, batch);
+  trsm_ul<T>(s, LU, inv, n0, h, B, cols, batch, wl);
 }
 
 // B <- B U^{-1}, U = upper factor rows/cols n0 .. n0+nb-1; column j of B is column n0+j
@@ -626,12 +649,56 @@ void lu_piv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, int32_t
 
 template <typename T>
 void lu_solve(hipStream_t s, DMat<T> LU, DMat<T> inv, const int32_t* ipiv, int64_t n, DMat<T> R,
-              int64_t r, int batch, int parts) {
+              int64_t r, int batch, int parts, DMat<T> inv2, int LW, DMat<T> work) {
   if (n % NB) throw Error(ST_EINVAL, "lu_solve: n not a multiple of the block size");
   if (n == 0 || r <= 0) return;
+  WideLeaves<T> wl;
+  if (LW > 0) {
+    if (LW % NB || n % LW || !inv2.re || !work.re)
+      throw Error(ST_EINVAL, "lu_solve: wide leaves need LW | n, NB | LW and their buffers");
+    wl.inv2 = inv2;
+    wl.LW = LW;
+    wl.work = work;
+  }
   if (ipiv && (parts & 1)) laswp<T>(s, R, n, ipiv, 0, n, 0, r, batch);
-  if (parts & 1) trsm_ll<T>(s, LU, inv, 0, n, R, r, batch);
-  if (parts & 2) trsm_ul<T>(s, LU, inv, 0, n, R, r, batch);
+  if (parts & 1) trsm_ll<T>(s, LU, inv, 0, n, R, r, batch, wl);
+  if (parts & 2) trsm_ul<T>(s, LU, inv, 0, n, R, r, batch, wl);
+}
+
+template <typename T>
+void merge_inverses(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n, int batch, DMat<T> inv2,
+                    int LW, DMat<T> work) {
+  if (LW % NB || n % LW || (LW / NB & (LW / NB - 1)))
+    throw Error(ST_EINVAL, "merge_inverses: LW must be NB times a power of two dividing n");
+  const int64_t nblk = n / LW;
+  fill<T>(s, inv2, LW, 2 * n, batch, T(0));
+  // items are the batch; the diagonal blocks of one item are a strided batch
+  for (int it = 0; it < batch; ++it) {
+    DMat<T> lu = LU.item(it), iv = inv.item(it), i2 = inv2.item(it), wk = work;
+    lu.bs = LW + LW * lu.ld;           // next diagonal block
+    iv.bs = 2 * LW * iv.ld;            // its NB-block inverses
+    i2.bs = 2 * LW * i2.ld;            // its wide inverses
+    for (int q = 0; q < LW / NB; ++q) {
+      convert<T, T>(s, iv.sub(0, 2 * q * NB), i2.sub(q * NB, q * NB), NB, NB, (int)nblk);
+      convert<T, T>(s, iv.sub(0, 2 * q * NB + NB), i2.sub(q * NB, LW + q * NB), NB, NB, (int)nblk);
+    }
+    // [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1} C^{-1}] and
+    // [A B; 0 C]^{-1} = [A^{-1} -A^{-1} B C^{-1}; 0 C^{-1}], widths NB, 2 NB, ...
+    for (int w = NB; 2 * w <= LW; w *= 2)
+      for (int o = 0; o < LW; o += 2 * w) {
+        DMat<T> tw = wk;
+        tw.ld = w;
+        tw.bs = (int64_t)w * w;
+        gemm<T>(s, false, false, w, w, w, T(1), lu.sub(o + w, o), i2.sub(o, o), T(0), tw,
+                (int)nblk);
+        gemm<T>(s, false, false, w, w, w, T(-1), i2.sub(o + w, o + w), tw, T(0), i2.sub(o + w, o),
+                (int)nblk);
+        gemm<T>(s, false, false, w, w, w, T(1), lu.sub(o, o + w), i2.sub(o + w, LW + o + w), T(0),
+                tw, (int)nblk);
+        gemm<T>(s, false, false, w, w, w, T(-1), i2.sub(o, LW + o), tw, T(0), i2.sub(o, LW + o + w),
+                (int)nblk);
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -749,7 +816,9 @@ void absmax(hipStream_t s, DMat<T> X, int64_t rows, int64_t cols, int batch, dou
   template void lu_piv<T>(hipStream_t, DMat<T>, int64_t, int, DMat<T>, int32_t*, unsigned*,  \
                           double);                                                           \
   template void lu_solve<T>(hipStream_t, DMat<T>, DMat<T>, const int32_t*, int64_t, DMat<T>, \
-                            int64_t, int, int);                                                   \
+                            int64_t, int, int, DMat<T>, int, DMat<T>);                            \
+  template void merge_inverses<T>(hipStream_t, DMat<T>, DMat<T>, int64_t, int, DMat<T>, int,   \
+                                  DMat<T>);                                                   \
   template void fill<T>(hipStream_t, DMat<T>, int64_t, int64_t, int, T);                     \
   template void pad_identity<T>(hipStream_t, DMat<T>, int64_t, int64_t, int);                \
   template void absmax<T>(hipStream_t, DMat<T>, int64_t, int64_t, int, double*);

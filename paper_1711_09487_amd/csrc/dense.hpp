@@ -88,7 +88,18 @@ void lu_piv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, int32_t
 // parts: 1 = forward (L) only, 2 = backward (U) only, 3 = both.
 template <typename T>
 void lu_solve(hipStream_t s, DMat<T> LU, DMat<T> inv, const int32_t* ipiv, int64_t n,
-              DMat<T> R, int64_t r, int batch, int parts = 3);
+              DMat<T> R, int64_t r, int batch, int parts = 3, DMat<T> inv2 = DMat<T>{},
+              int LW = 0, DMat<T> work = DMat<T>{});
+
+// Wide leaves for lu_solve: inverses of the LW x LW diagonal blocks of the
+// factors of lu_nopiv (LW = NB times a power of two, dividing n), merged from
+// the NB-block inverses in inv: inv2 is LW x 2n per item, [Linv_0 Uinv_0
+// Linv_1 ...] as inv.  work: (LW / 2)^2 (n / LW) elements per plane, reused
+// for every item.  lu_solve with inv2, LW and a work of LW x r per item then
+// stops its recursion at LW (fewer, larger products).
+template <typename T>
+void merge_inverses(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n, int batch, DMat<T> inv2,
+                    int LW, DMat<T> work);
 
 // Y (n x r, complex planar) <- fill with zero, or with the identity pattern
 // on the padding rows/cols beyond `active` when ident_pad.

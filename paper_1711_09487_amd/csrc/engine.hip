@@ -258,7 +258,7 @@ PhaseTimer::~PhaseTimer() {
 
 std::vector<DevBuf*> EngineImpl::solve_buffers() {
   std::vector<DevBuf*> v{&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32,
-                         &Sinv32, &Sinv64, &Yc, &Xf, &Rf, &Rf32, &W, &Qint, &Vb, &Bs, &Bsinv,
+                         &Sinv32, &Sinv64, &Swide, &Swork, &Yc, &Xf, &Rf, &Rf32, &W, &Qint, &Vb, &Bs, &Bsinv,
                          &Bspiv, &Lev, &Zt, &work1, &work2, &work3, &work4, &work5, &work6,
                          &ipiv_small, &iscal, &gwork, &work6b, &rr_az, &rr_h, &ow.V, &ow.T,
                          &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank};
@@ -362,6 +362,23 @@ int EngineImpl::pole_chunk() const {
 // ---------------------------------------------------------------------------
 // Factorizations for every pole (Sec. 3.1).
 // ---------------------------------------------------------------------------
+// The filter solves with S stop their recursion at SLW-wide diagonal blocks
+// (SLW = 256 or 128 when it divides SP): their inverses are merged once per
+// factorization, so that each solve needs a few large products instead of
+// SP / 64 small sequential ones.
+template <typename T>
+void EngineImpl::wide_inverses(hipStream_t st, DMat<T> LU, DMat<T> inv, int nc) {
+  SLW = (SP % 256 == 0 && SP > 256) ? 256 : ((SP % 128 == 0 && SP > 128) ? 128 : 0);
+  if (!SLW) return;
+  const int64_t per = (int64_t)SLW * 2 * SP;  // elements per plane per pole
+  Swide.alloc(2 * per * nc * sizeof(T));
+  DMat<T> w2{Swide.as<T>(), Swide.as<T>() + per * nc, SLW, per};
+  const int64_t mw = (int64_t)(SLW / 2) * (SLW / 2) * (SP / SLW);
+  Swork.alloc(std::max<int64_t>(Swork.bytes, 2 * mw * sizeof(T)));
+  DMat<T> wk{Swork.as<T>(), Swork.as<T>() + mw, SLW / 2, 0};
+  merge_inverses<T>(st, LU, inv, SP, nc, w2, SLW, wk);
+}
+
 void EngineImpl::factor(hipStream_t st, int w0, int wn) {
   const int nc = wn;  // poles in the window; pole index = w0 + item
   Shifts z{zeta.as<double>()};
@@ -455,6 +472,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
                    (int64_t)NB * 2 * SP};
     convert<float, double>(st, S, S3, SP, SP, nc);
     lu_nopiv<float>(st, S3, SP, nc, Si, flags.as<unsigned>(), 1e-30);
+    wide_inverses<float>(st, S3, Si, nc);
     // the interior factors are no longer needed; large ones are released
     // (a release synchronises the device, small ones stay for the next solve)
     if (K32.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
@@ -468,6 +486,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
     DMat<double> Si{Sinv64.as<double>(), Sinv64.as<double>() + (int64_t)NB * 2 * SP * nc, NB,
                     (int64_t)NB * 2 * SP};
     lu_nopiv<double>(st, S, SP, nc, Si, flags.as<unsigned>(), 1e-300);
+    wide_inverses<double>(st, S, Si, nc);
     if (K64.bytes > (size_t(16) << 30)) {
       K64.release();
       Kinv64.release();
@@ -532,7 +551,7 @@ void EngineImpl::run_filter(hipStream_t st, const double* Y, int64_t ldy, int m,
   // room for the interior part (the next application factors again)
   RFD_HIP(hipStreamSynchronize(st));
   for (DevBuf* b : {&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32, &Sinv32,
-                    &Sinv64, &Yc, &Xf, &Rf, &Rf32})
+                    &Sinv64, &Swide, &Swork, &Yc, &Xf, &Rf, &Rf32})
     b->release();
   factored = false;
 }
@@ -567,7 +586,8 @@ void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int 
     int sw = 0;
     for (;; ++sw) {
       convert<float, double>(st, Ycm, R3, SP, MP, nc);
-      lu_solve<float>(st, S3, Si, nullptr, SP, R3, MP, nc);
+      lu_solve<float>(st, S3, Si, nullptr, SP, R3, MP, nc, 3, wide<float>(nc), SLW,
+                      solve_work<float>(MP, nc));
       add_to<double, float>(st, R3, X, SP, MP, nc);
       broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);
       // R = Y - S_64 X as four real products on the planes (large real FP64
@@ -595,7 +615,8 @@ void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int 
     DMat<double> Si{Sinv64.as<double>(), Sinv64.as<double>() + (int64_t)NB * 2 * SP * nc, NB,
                     (int64_t)NB * 2 * SP};
     broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);
-    lu_solve<double>(st, S, Si, nullptr, SP, Ycm, MP, nc);
+    lu_solve<double>(st, S, Si, nullptr, SP, Ycm, MP, nc, 3, wide<double>(nc), SLW,
+                     solve_work<double>(MP, nc));
     filter_accumulate(st, Ycm, om, nc, Wout, ldw, s, m, add);
   }
   timer.end(st);

@@ -62,6 +62,8 @@ struct EngineImpl {
   // factor buffers
   DevBuf K32, K64, Kinv32, Kinv64, X32, X64, R32, R64;
   DevBuf S64, S32, Sinv32, Sinv64;
+  DevBuf Swide, Swork;  // inverses of the SLW-wide diagonal blocks of S's factors, workspace
+  int SLW = 0;
   DevBuf Yc, Xf, Rf, Rf32, W;
   OrthWork ow;
   // interface basis
@@ -114,6 +116,22 @@ struct EngineImpl {
   int pole_chunk() const;
   // Factors poles [w0, w0 + wn) (the "window": S buffers hold wn poles)
   void factor(hipStream_t st, int w0, int wn);
+  template <typename T>
+  void wide_inverses(hipStream_t st, DMat<T> LU, DMat<T> inv, int nc);
+  // views of the wide inverses of S and of a leaf workspace for r columns
+  template <typename T>
+  DMat<T> wide(int nc) {
+    const int64_t per = (int64_t)SLW * 2 * SP;
+    if (!SLW) return DMat<T>{};
+    return DMat<T>{Swide.as<T>(), Swide.as<T>() + per * nc, SLW, per};
+  }
+  template <typename T>
+  DMat<T> solve_work(int64_t r, int nc) {
+    if (!SLW) return DMat<T>{};
+    const int64_t per = (int64_t)SLW * r;
+    Swork.alloc(std::max<int64_t>(Swork.bytes, 2 * per * nc * sizeof(T)));
+    return DMat<T>{Swork.as<T>(), Swork.as<T>() + per * nc, SLW, per};
+  }
   // W (=, or += when add) 2 Re sum over the window of omega_l S_l^{-1} Y
   void apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* W, int64_t ldw,
                     bool add);

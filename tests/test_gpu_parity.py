@@ -7,7 +7,8 @@ nev_b, psi, steps) through both sides:
   * the Ritz values in [alpha, beta] (relative error <= 1e-10), their
     residuals, and the Ritz vectors (principal angles per cluster).
 Sizes span one to several 64-wide tiles with ragged tails, uneven subdomains,
-a 3D pencil (eight 5^3 interiors, plane separators) and both precision modes.  The full-size workload with 64 subdomains
+a 3D pencil (eight 5^3 interiors, plane separators), an interface wide enough
+for the solves' wide diagonal blocks, and both precision modes.  The full-size workload with 64 subdomains
 (n = 65025) is compared with the oracle's stored results
 (tests/golden/oracle_c2.json, written by make_oracle_golden.py).
 """
@@ -45,6 +46,9 @@ CASES = {
     "config1": lambda: W.config(1),
     "tiny3d_p8": lambda: W.tiny(N=11, dim=3, P=2, nev=8, n_c=6, m=40, steps=2, nev_b=10, psi=4,
                                 mass_kind="random", cfg_id=45),
+    # s = 324 padded to 384: the filter solves stop at 128-wide diagonal blocks
+    "p9_wide_leaves": lambda: W.tiny(N=82, P=3, nev=12, n_c=6, m=40, steps=2, nev_b=10, psi=4,
+                                     mass_kind="random", cfg_id=46),
 }
 _cache = {}
 
