@@ -113,10 +113,11 @@ Engine::~Engine() {
     e.join_prepare();
   } catch (...) {
   }
-  if (e.prep_stream) {
-    release_stream_resources(e.prep_stream);
-    (void)hipStreamDestroy(e.prep_stream);
-  }
+  for (hipStream_t ps : {e.prep_stream, e.prep_stream2})
+    if (ps) {
+      release_stream_resources(ps);
+      (void)hipStreamDestroy(ps);
+    }
 }
 
 void Engine::set_poles(const Poles& poles) {
@@ -309,6 +310,7 @@ void Engine::prepare_interior(double sig, int nevb) {
       e.bs_sigma == sig)
     return;
   if (!e.prep_stream) RFD_HIP(hipStreamCreateWithFlags(&e.prep_stream, hipStreamNonBlocking));
+  if (!e.prep_stream2) RFD_HIP(hipStreamCreateWithFlags(&e.prep_stream2, hipStreamNonBlocking));
   if (!e.prep_flags.p) {
     e.prep_flags.alloc(sizeof(unsigned));
     RFD_HIP(hipMemsetAsync(e.prep_flags.p, 0, sizeof(unsigned), e.prep_stream));
@@ -317,10 +319,17 @@ void Engine::prepare_interior(double sig, int nevb) {
   e.prep = std::thread([&e, sig, nevb]() {
     try {
       RFD_HIP(hipSetDevice(e.device));
+      // B_sigma's factorization (no host round trip until its flag check) is
+      // enqueued on a second stream first, so that it runs beside the
+      // subdomain eigensolver, whose steps wait on the host
+      e.factor_bsigma(e.prep_stream2, sig, &e.prep_flags, false);
       e.interior_basis(e.prep_stream, sig, nevb);
-      e.factor_bsigma(e.prep_stream, sig, &e.prep_flags);
+      e.check_flags(e.prep_stream2, "B_sigma factorization", &e.prep_flags);
       RFD_HIP(hipStreamSynchronize(e.prep_stream));
     } catch (...) {
+      // nothing half-made is kept
+      e.vcache_valid = false;
+      e.bs_valid = false;
       e.prep_err = std::current_exception();
     }
   });

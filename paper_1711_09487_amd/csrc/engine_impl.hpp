@@ -103,7 +103,7 @@ struct EngineImpl {
   std::thread prep;
   std::atomic<bool> prep_running{false};
   std::exception_ptr prep_err;
-  hipStream_t prep_stream = nullptr;
+  hipStream_t prep_stream = nullptr, prep_stream2 = nullptr;
   DevBuf prep_flags;
   std::vector<DevBuf*> prep_buffers();
   void join_prepare();
@@ -146,7 +146,7 @@ struct EngineImpl {
   void apply_m(hipStream_t st, const double* X, int64_t ldx, double* Y, int64_t ldy,
                int64_t cols);
   void interior_basis(hipStream_t st, double sigma, int nev_b);
-  void factor_bsigma(hipStream_t st, double sigma, DevBuf* fl = nullptr);
+  void factor_bsigma(hipStream_t st, double sigma, DevBuf* fl = nullptr, bool check = true);
   int gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,
                 double droptol);
   void project_out(hipStream_t st, double* X, int ncols, double* MX, const double* Zp,

@@ -500,7 +500,7 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   vcache_nevb = nevb;
 }
 
-void EngineImpl::factor_bsigma(hipStream_t st, double sig, DevBuf* fl) {
+void EngineImpl::factor_bsigma(hipStream_t st, double sig, DevBuf* fl, bool check) {
   DevBuf& fw = fl ? *fl : flags;
   if (bs_valid && bs_sigma == sig) return;
   timer.begin(st, 7);
@@ -514,7 +514,9 @@ void EngineImpl::factor_bsigma(hipStream_t st, double sig, DevBuf* fl) {
   expand_shifted<double>(st, K, D, p, 1, 0, dj.as<int32_t>(), Bg.view(), z, true, sig);
   lu_piv<double>(st, K, D, p, Ki, Bspiv.as<int32_t>(), fw.as<unsigned>(), 1e-300);
   timer.end(st);
-  check_flags(st, "B_sigma factorization", &fw);
+  // (the caller checks the flags itself when check is false, after it has
+  // enqueued its other work)
+  if (check) check_flags(st, "B_sigma factorization", &fw);
   bs_valid = true;
   bs_sigma = sig;
 }
