@@ -110,6 +110,41 @@ __device__ inline void fma_sub(T& sr, T& si, T ar, T ai, T br, T bi) {
   }
 }
 
+// The NB x NB block at a into F: every thread's 16 loads are issued before
+// any is stored, one round trip to memory instead of sixteen.
+template <typename T, bool CPLX>
+__device__ inline void load_block(T (*F)[NB][NB + 1], const DMat<T>& a, int tid) {
+  constexpr int NP = CPLX ? 2 : 1;
+  constexpr int PER = NB * NB / 256;
+  T vr[PER], vi[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e % NB, j = e / NB;
+    vr[q] = a.re[i + j * a.ld];
+    vi[q] = CPLX ? a.im[i + j * a.ld] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e % NB, j = e / NB;
+    F[0][i][j] = vr[q];
+    if constexpr (CPLX) F[NP - 1][i][j] = vi[q];
+  }
+}
+
+// value of v in lane `lane` (uniform over the wave): a scalar read, not a
+// trip through the shared-memory crossbar
+template <typename T>
+__device__ inline T lane_read(T v, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+  } else {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+}
+
 template <typename T, bool CPLX>
 __device__ inline void fma_add(T& sr, T& si, T ar, T ai, T br, T bi) {
   if constexpr (CPLX) {
@@ -275,11 +310,7 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid < NB) dl[tid] = 0;
   DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, j = e / NB;
-    F[0][i][j] = a.re[i + j * a.ld];
-    if constexpr (CPLX) F[NP - 1][i][j] = a.im[i + j * a.ld];
-  }
+  load_block<T, CPLX>(F, a, tid);
   __syncthreads();
   for (int c0 = 0; c0 < NB; c0 += PW) {
     if (wave == 0) {
@@ -293,8 +324,8 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
 #pragma unroll
       for (int kk = 0; kk < PW; ++kk) {
         const int j = c0 + kk;
-        const T pr = __shfl(ar[kk], j, 64);
-        const T pim = CPLX ? __shfl(ai[kk], j, 64) : T(0);
+        const T pr = lane_read(ar[kk], j);
+        const T pim = CPLX ? lane_read(ai[kk], j) : T(0);
         if (!CPLX && drop && !(pr > droptol)) {
           // semidefinite mode: the pivot of the Schur complement vanished,
           // so column j lies in the span of the earlier ones; it is removed
@@ -327,8 +358,8 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
 #pragma unroll
         for (int q = 0; q < PW; ++q)
           if (q > kk) {
-            const T ur = __shfl(ar[q], j, 64);
-            const T ui = CPLX ? __shfl(ai[q], j, 64) : T(0);
+            const T ur = lane_read(ar[q], j);
+            const T ui = CPLX ? lane_read(ai[q], j) : T(0);
             if (r > j) fma_sub<T, CPLX>(ar[q], ai[q], lr, li, ur, ui);
           }
       }
@@ -398,11 +429,7 @@ __global__ __launch_bounds__(256) void k_tri_inv(DMat<T> A, int64_t k0, DMat<T> 
   __shared__ T Tb[NP][32][33];
   const int tid = threadIdx.x;
   DMat<T> a = A.item(blockIdx.x).sub(k0, k0);
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, j = e / NB;
-    F[0][i][j] = a.re[i + j * a.ld];
-    if constexpr (CPLX) F[NP - 1][i][j] = a.im[i + j * a.ld];
-  }
+  load_block<T, CPLX>(F, a, tid);
   __syncthreads();
   DMat<T> iv = inv.item(blockIdx.x);
   tri_inverses<T, CPLX>(F, X, Tb, iv.sub(0, 2 * NB * iblk), iv.sub(0, 2 * NB * iblk + NB));
