@@ -156,140 +156,138 @@ __device__ inline void fma_add(T& sr, T& si, T ar, T ai, T br, T bi) {
 }
 
 // Inverses of the unit-lower and the upper triangle of the factored block F
-// (NB = 64), blocked: the four 16 x 16 diagonal blocks are inverted at once
-// (a wave each, a lane per column), then pairs are merged into 32 x 32 and
-// those into 64 x 64 with
-//   [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1} C^{-1}]
-// (and the upper-triangular mirror), two small products per merge.  A
-// dropped column (semidefinite mode) gets a zero row in Linv, so that the
+// (NB = 64), both at once, blocked.  X holds the two results in one array as F
+// holds the factors: the strictly lower part is L^{-1} (unit diagonal
+// implied), the upper part with the diagonal is U^{-1}.
+//  * The four 16 x 16 diagonal blocks: wave g inverts block g, lanes 0-15 a
+//    column of the lower inverse each, lanes 16-31 a column of the upper one
+//    with rows and columns taken in reverse order, which turns the backward
+//    substitution into the same forward recurrence (one instruction stream).
+//  * Pairs of diagonal blocks are merged into 32 x 32, those into 64 x 64:
+//      [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1}  C^{-1}]
+//      [A E; 0 C]^{-1} = [A^{-1} -A^{-1} E C^{-1}; 0 C^{-1}]
+//    two products per merge, whose sums run over the nonzero band of the
+//    triangular factor only.  E C^{-1} is parked in the lower off-diagonal
+//    block of the pair until the upper result has been formed from it.
+// A dropped column (semidefinite mode) gets a zero row in Linv, so that the
 // panel update leaves a zero row of U beside it.  Tb: 32 x 33 per plane.
 template <typename T, bool CPLX>
-__device__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], T (*Tb)[32][33],
+__device__ __forceinline__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB + 1], T (*Tb)[32][33],
                              DMat<T> Linv, DMat<T> Uinv, const int* dropped = nullptr) {
   constexpr int NP = CPLX ? 2 : 1;
   static_assert(NB == 64, "blocked inversion assumes 64 x 64 blocks");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int half = 0; half < 2; ++half) {
-    const bool lower = half == 0;
-    // element (i, j) of the triangle being inverted, from F (unit diagonal
-    // for L)
-    auto tr = [&](int i, int j, T& vr, T& vi) {
-      vr = F[0][i][j];
-      vi = CPLX ? F[NP - 1][i][j] : T(0);
-    };
-    for (int e = tid; e < NB * NB; e += 256) {
-      X[0][e % NB][e / NB] = 0;
-      if constexpr (CPLX) X[NP - 1][e % NB][e / NB] = 0;
+  auto ld = [&](T (*Y)[NB][NB + 1], int i, int j, T& vr, T& vi) {
+    vr = Y[0][i][j];
+    vi = CPLX ? Y[NP - 1][i][j] : T(0);
+  };
+  auto st = [&](T (*Y)[NB][NB + 1], int i, int j, T vr, T vi) {
+    Y[0][i][j] = vr;
+    if constexpr (CPLX) Y[NP - 1][i][j] = vi;
+  };
+  if (lane < 32) {
+    const int up = lane >> 4, c = lane & 15, b = 16 * wave;
+    T xr[16], xi[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      xr[i] = (i == c) ? T(1) : T(0);
+      xi[i] = 0;
     }
-    __syncthreads();
-    // 16 x 16 diagonal blocks: wave g, lane c = column
-    if (lane < 16) {
-      const int b = 16 * wave, c = lane;
-      T xr[16], xi[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) xr[i] = xi[i] = 0;
-      if (lower) {
+    for (int i = 0; i < 16; ++i) {
+      // one row of loads in flight at a time (the whole triangle would not
+      // fit in registers)
+      __builtin_amdgcn_sched_barrier(0);
+      const int ri = up ? 15 - i : i;
+      T sr = xr[i], si = xi[i];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          if (i == c) xr[i] = 1;
-          if (i > c) {
-            T sr = 0, si = 0;
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-              if (t >= c && t < i) {
-                T lr, li;
-                tr(b + i, b + t, lr, li);
-                fma_sub<T, CPLX>(sr, si, lr, li, xr[t], xi[t]);
-              }
-            xr[i] = sr;
-            xi[i] = si;
-          }
-        }
+      for (int t = 0; t < i; ++t) {
+        T er, ei;
+        ld(F, b + ri, b + (up ? 15 - t : t), er, ei);
+        fma_sub<T, CPLX>(sr, si, er, ei, xr[t], xi[t]);
+      }
+      // unit diagonal for L, the pivot for U
+      T dr = T(1), di = T(0);
+      if (up) ld(F, b + ri, b + ri, dr, di);
+      if constexpr (CPLX) {
+        T ir, ii;
+        cinv(dr, di, ir, ii);
+        cmul(sr, si, ir, ii, xr[i], xi[i]);
       } else {
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-          if (i <= c) {
-            T sr = (i == c) ? T(1) : T(0), si = 0;
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-              if (t > i && t <= c) {
-                T ur, ui;
-                tr(b + i, b + t, ur, ui);
-                fma_sub<T, CPLX>(sr, si, ur, ui, xr[t], xi[t]);
-              }
-            T dr, di;
-            tr(b + i, b + i, dr, di);
-            if constexpr (CPLX) {
-              T ir, ii;
-              cinv(dr, di, ir, ii);
-              cmul(sr, si, ir, ii, xr[i], xi[i]);
-            } else {
-              xr[i] = sr / dr;
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        X[0][b + i][b + c] = xr[i];
-        if constexpr (CPLX) X[NP - 1][b + i][b + c] = xi[i];
+        xr[i] = sr / dr;
       }
     }
-    __syncthreads();
-    // merges: width w = 16 (two pairs), then w = 32 (one pair)
-    for (int w = 16; w <= 32; w *= 2) {
-      const int npair = NB / (2 * w);
-      const int per = w * w;  // entries of one off-diagonal block
-      // lower: T = B X_A (B = L[b+w.., b..], X_A = X[b.., b..]);
-      // upper: T = U_AB X_C (U_AB = U[b.., b+w..], X_C = X[b+w.., b+w..])
-      for (int e = tid; e < npair * per; e += 256) {
-        const int pr = e / per, q = e % per, i = q % w, j = q / w, b = 2 * w * pr;
-        T sr = 0, si = 0;
-        for (int t = 0; t < w; ++t) {
-          T ar, ai;
-          if (lower) {
-            tr(b + w + i, b + t, ar, ai);
-            fma_add<T, CPLX>(sr, si, ar, ai, X[0][b + t][b + j], CPLX ? X[NP - 1][b + t][b + j] : T(0));
-          } else {
-            tr(b + i, b + w + t, ar, ai);
-            fma_add<T, CPLX>(sr, si, ar, ai, X[0][b + w + t][b + w + j],
-                             CPLX ? X[NP - 1][b + w + t][b + w + j] : T(0));
-          }
+    // lower: rows below the diagonal of column c; upper: rows 15-i <= 15-c
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (up) {
+        if (i >= c) st(X, b + 15 - i, b + 15 - c, xr[i], xi[i]);
+      } else {
+        if (i > c) st(X, b + i, b + c, xr[i], xi[i]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int w = 16; w <= 32; w *= 2) {
+    const int per = w * w, half = (NB / (2 * w)) * per;
+    // T_L = B A^{-1} into Tb (row pr w + i), T_U = E C^{-1} parked at X21
+    for (int e = tid; e < 2 * half; e += 256) {
+      const bool up = e >= half;
+      const int q0 = up ? e - half : e;
+      const int pr = q0 / per, q = q0 % per, i = q % w, j = q / w, b = 2 * w * pr;
+      T sr = 0, si = 0, ar, ai, br, bi;
+      if (!up) {
+        ld(F, b + w + i, b + j, sr, si);
+        for (int t = j + 1; t < w; ++t) {
+          ld(F, b + w + i, b + t, ar, ai);
+          ld(X, b + t, b + j, br, bi);
+          fma_add<T, CPLX>(sr, si, ar, ai, br, bi);
         }
         Tb[0][pr * w + i][j] = sr;
         if constexpr (CPLX) Tb[NP - 1][pr * w + i][j] = si;
-      }
-      __syncthreads();
-      // lower: X[b+w+i, b+j] = -(X_C T)[i, j]; upper: X[b+i, b+w+j] = -(X_A T)[i, j]
-      for (int e = tid; e < npair * per; e += 256) {
-        const int pr = e / per, q = e % per, i = q % w, j = q / w, b = 2 * w * pr;
-        T sr = 0, si = 0;
-        for (int t = 0; t < w; ++t) {
-          const int xi0 = lower ? b + w + i : b + i, xj0 = lower ? b + w + t : b + t;
-          fma_sub<T, CPLX>(sr, si, X[0][xi0][xj0], CPLX ? X[NP - 1][xi0][xj0] : T(0),
-                           Tb[0][pr * w + t][j], CPLX ? Tb[NP - 1][pr * w + t][j] : T(0));
+      } else {
+        for (int t = 0; t <= j; ++t) {
+          ld(F, b + i, b + w + t, ar, ai);
+          ld(X, b + w + t, b + w + j, br, bi);
+          fma_add<T, CPLX>(sr, si, ar, ai, br, bi);
         }
-        const int oi = lower ? b + w + i : b + i, oj = lower ? b + j : b + w + j;
-        X[0][oi][oj] = sr;
-        if constexpr (CPLX) X[NP - 1][oi][oj] = si;
+        st(X, b + w + i, b + j, sr, si);
       }
-      __syncthreads();
-    }
-    if (lower && dropped) {
-      for (int e = tid; e < NB * NB; e += 256)
-        if (dropped[e % NB]) {
-          X[0][e % NB][e / NB] = 0;
-          if constexpr (CPLX) X[NP - 1][e % NB][e / NB] = 0;
-        }
-      __syncthreads();
-    }
-    DMat<T> out = lower ? Linv : Uinv;
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int i = e % NB, cc = e / NB;
-      out.re[i + cc * out.ld] = X[0][i][cc];
-      if constexpr (CPLX) out.im[i + cc * out.ld] = X[NP - 1][i][cc];
     }
     __syncthreads();
+    // X12 = -A^{-1} T_U (upper triangle of A^{-1}: t >= i)
+    for (int e = tid; e < half; e += 256) {
+      const int pr = e / per, q = e % per, i = q % w, j = q / w, b = 2 * w * pr;
+      T sr = 0, si = 0, ar, ai, br, bi;
+      for (int t = i; t < w; ++t) {
+        ld(X, b + i, b + t, ar, ai);
+        ld(X, b + w + t, b + j, br, bi);
+        fma_sub<T, CPLX>(sr, si, ar, ai, br, bi);
+      }
+      st(X, b + i, b + w + j, sr, si);
+    }
+    __syncthreads();
+    // X21 = -C^{-1} T_L (unit lower C^{-1}: t < i, plus the diagonal)
+    for (int e = tid; e < half; e += 256) {
+      const int pr = e / per, q = e % per, i = q % w, j = q / w, b = 2 * w * pr;
+      T sr = -Tb[0][pr * w + i][j], si = CPLX ? -Tb[NP - 1][pr * w + i][j] : T(0), ar, ai;
+      for (int t = 0; t < i; ++t) {
+        ld(X, b + w + i, b + w + t, ar, ai);
+        fma_sub<T, CPLX>(sr, si, ar, ai, Tb[0][pr * w + t][j], CPLX ? Tb[NP - 1][pr * w + t][j] : T(0));
+      }
+      st(X, b + w + i, b + j, sr, si);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int i = e % NB, cc = e / NB;
+    T xr, xi;
+    ld(X, i, cc, xr, xi);
+    const bool lo = i > cc, zr = dropped && dropped[i];
+    Linv.re[i + cc * Linv.ld] = zr ? T(0) : lo ? xr : (i == cc ? T(1) : T(0));
+    if constexpr (CPLX) Linv.im[i + cc * Linv.ld] = (zr || !lo) ? T(0) : xi;
+    Uinv.re[i + cc * Uinv.ld] = lo ? T(0) : xr;
+    if constexpr (CPLX) Uinv.im[i + cc * Uinv.ld] = lo ? T(0) : xi;
   }
 }
 
@@ -380,6 +378,7 @@ __global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> 
       T xr[PW], xi[PW];
 #pragma unroll
       for (int i = 0; i < PW; ++i) {
+        __builtin_amdgcn_sched_barrier(0);
         T sr = F[0][c0 + i][cc], si = CPLX ? F[NP - 1][c0 + i][cc] : T(0);
 #pragma unroll
         for (int t = 0; t < PW; ++t)

@@ -44,6 +44,23 @@ template <> struct V16<double> { using t = double2; };
 
 constexpr int GBK = 16;
 
+// Logical block index of this workgroup.  The dispatcher deals the
+// workgroups of a grid to the 8 XCDs in turn (linear id L, x fastest, runs on
+// XCD L % 8), and each XCD has its own L2.  Numbering the blocks so that XCD c
+// works the c-th contiguous eighth of the (x, y, z) order keeps the tiles that
+// share an operand panel (same item, same K chunk, neighbouring rows and
+// columns) on one L2 instead of fetching every panel into all eight.
+constexpr unsigned NXCD = 8;
+__device__ inline uint3 xcd_block() {
+  const unsigned gx = gridDim.x, gy = gridDim.y;
+  const unsigned total = gx * gy * gridDim.z;
+  const unsigned L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned q = total / NXCD, r = total % NXCD, c = L % NXCD, j = L / NXCD;
+  // XCD c holds q + 1 blocks when c < r, else q
+  const unsigned l = (c < r ? c * (q + 1) : r * (q + 1) + (c - r) * q) + j;
+  return make_uint3(l % gx, (l / gx) % gy, l / (gx * gy));
+}
+
 // Registers holding one K slab of an operand tile.  In memory the tile is a
 // column-major FE x SE block (FE along the contiguous dimension).
 template <typename T, int FE, int SE>
@@ -107,10 +124,11 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
   __shared__ __attribute__((aligned(16))) T As[2][NP][GBK][PA];
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][GBK][PB];
 
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const uint3 blk = xcd_block();
+  const int64_t m0 = (int64_t)blk.x * BM, n0 = (int64_t)blk.y * BN;
   if (tri && n0 >= m0 + BM) return;  // strictly upper tile, not wanted
   const int batch = (int)gridDim.z / splits;
-  const int b = (int)blockIdx.z / splits, sk = (int)blockIdx.z - b * splits;
+  const int b = (int)blk.z / splits, sk = (int)blk.z - b * splits;
   A = A.item(b);
   B = B.item(b);
   C = C.item(b);
@@ -426,7 +444,8 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128) * batch;
   const int bt = (big_ok && t128 >= 240) ? 128 : 64;
   const int64_t gm = (M + bt - 1) / bt, gn = (N + bt - 1) / bt;
-  const int64_t tiles = gm * gn * batch;
+  // tiles that do work (a lower-triangle product skips the strictly upper ones)
+  const int64_t tiles = (tri ? gm * (gm + 1) / 2 : gm * gn) * batch;
   int splits = 1;
   if (tiles < 512 && K >= 1024) {
     splits = (int)std::min<int64_t>((1024 + tiles - 1) / tiles, K / 512);
@@ -455,6 +474,7 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
     }
   }
   if ((int64_t)batch * splits > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
+  if (gm * gn * batch * splits >= ((int64_t)1 << 32)) throw Error(ST_EINVAL, "gemm: grid too large");
   if (gm > 0x7fffffff || gn > 65535) throw Error(ST_EINVAL, "gemm: matrix too large");
   int64_t kchunk = K;
   if (splits > 1) {
