@@ -561,7 +561,11 @@ void lu_nopiv(hipStream_t s, DMat<T> A, int64_t n, int batch, DMat<T> inv, unsig
 
 // ---------------------------------------------------------------------------
 // Partial pivoting (real data): panel of width NB, rows k0..n-1, factored by
-// one workgroup per item directly in global memory.
+// one workgroup per item directly in global memory.  Each thread owns rows
+// tid, tid + 256, ...; per column it loads the rest of its row's panel at
+// once, applies the rank-1 update in registers and stores it, so a column
+// costs one memory round trip per owned row instead of one per entry.  The
+// pivot search of the next column rides along with the update.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_panel_piv(DMat<T> A, int64_t n, int64_t k0,
@@ -571,16 +575,19 @@ __global__ __launch_bounds__(256) void k_panel_piv(DMat<T> A, int64_t n, int64_t
   __shared__ T prow[NB];
   const int tid = threadIdx.x;
   DMat<T> a = A.item(blockIdx.x);
+  T* a0 = a.re + k0 * a.ld;  // column k0 of the panel
+  const int64_t ld = a.ld;
   int32_t* piv = ipiv + (int64_t)blockIdx.x * n;
+  // argmax |a(i, k0)|, i >= k0, per thread (rows in increasing order keep the
+  // first index on ties)
+  T best = -1;
+  int bi = (int)k0;
+  for (int64_t i = k0 + tid; i < n; i += 256) {
+    const T v = fabs(a0[i]);
+    if (v > best) { best = v; bi = (int)i; }
+  }
   for (int j = 0; j < NB; ++j) {
     const int64_t col = k0 + j;
-    // argmax |a(i, col)|, i >= col (first index on ties)
-    T best = -1;
-    int bi = (int)col;
-    for (int64_t i = col + tid; i < n; i += 256) {
-      const T v = fabs(a.re[i + col * a.ld]);
-      if (v > best) { best = v; bi = (int)i; }
-    }
     sval[tid] = best;
     sidx[tid] = bi;
     __syncthreads();
@@ -604,19 +611,43 @@ __global__ __launch_bounds__(256) void k_panel_piv(DMat<T> A, int64_t n, int64_t
     }
     // swap rows col and p within the panel columns
     if (p != col && tid < NB) {
-      const int64_t c = k0 + tid;
-      const T t = a.re[col + c * a.ld];
-      a.re[col + c * a.ld] = a.re[p + c * a.ld];
-      a.re[p + c * a.ld] = t;
+      const T t = a0[col + tid * ld];
+      a0[col + tid * ld] = a0[p + tid * ld];
+      a0[p + tid * ld] = t;
     }
     __syncthreads();
-    if (tid < NB) prow[tid] = a.re[col + (k0 + tid) * a.ld];
+    if (tid < NB) prow[tid] = a0[col + tid * ld];
     __syncthreads();
     const T inv = T(1) / prow[j];
+    best = -1;
+    bi = (int)(col + 1);
     for (int64_t i = col + 1 + tid; i < n; i += 256) {
-      const T l = a.re[i + col * a.ld] * inv;
-      a.re[i + col * a.ld] = l;
-      for (int c = j + 1; c < NB; ++c) a.re[i + (k0 + c) * a.ld] -= l * prow[c];
+      T v[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c >= j) v[c] = a0[i + c * ld];
+      // v[j] by a select over the unrolled indices (a runtime index would
+      // move v to scratch memory)
+      T vj = 0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c == j) vj = v[c];
+      const T l = vj * inv;
+      a0[i + j * ld] = l;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c > j) {
+          v[c] -= l * prow[c];
+          a0[i + c * ld] = v[c];
+        }
+      if (j + 1 < NB) {
+        T vn = 0;
+#pragma unroll
+        for (int c = 1; c < NB; ++c)
+          if (c == j + 1) vn = v[c];
+        const T m = fabs(vn);
+        if (m > best) { best = m; bi = (int)i; }
+      }
     }
     __syncthreads();
   }

@@ -26,6 +26,7 @@
 #include <hip/hip_ext.h>
 #include <rocblas/rocblas.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -422,6 +423,36 @@ static void launch(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N
 #undef RFD_GEMM_GO
 }
 
+// Workgroups of one k_gemm variant that the device holds at once (per-CU
+// occupancy from registers and LDS, times the CU count), per device.
+template <typename T, bool CPLX, int BM, int BN>
+static int64_t resident_blocks() {
+  static std::atomic<int64_t> cached[16];
+  int dev = 0;
+  RFD_HIP(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 16) {
+    const int64_t c = cached[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int per_cu = 0, cus = 0;
+  RFD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(k_gemm<T, CPLX, false, false, BM, BN>), 256, 0));
+  RFD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t r = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
+  if (dev >= 0 && dev < 16) cached[dev].store(r, std::memory_order_relaxed);
+  return r;
+}
+
+template <typename T>
+static int64_t resident_for(bool cplx, int bt) {
+  if constexpr (sizeof(T) == 4) {
+    if (bt == 128) return resident_blocks<T, false, 128, 128>();
+    return cplx ? resident_blocks<T, true, 64, 64>() : resident_blocks<T, false, 64, 64>();
+  } else {
+    return cplx ? resident_blocks<T, true, 64, 64>() : resident_blocks<T, false, 64, 64>();
+  }
+}
+
 template <typename T>
 static bool aligned16(const DMat<T>& X, int vw) {
   auto al = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
@@ -446,9 +477,25 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   const int64_t gm = (M + bt - 1) / bt, gn = (N + bt - 1) / bt;
   // tiles that do work (a lower-triangle product skips the strictly upper ones)
   const int64_t tiles = (tri ? gm * (gm + 1) / 2 : gm * gn) * batch;
+  // split K when the tiles fill less than half the device, into as many
+  // chunks as give one full round of resident workgroups: a second, partial
+  // round would take as long as the first
+  const int64_t slots = resident_for<T>(cplx, bt);
   int splits = 1;
-  if (tiles < 512 && K >= 1024) {
-    splits = (int)std::min<int64_t>((1024 + tiles - 1) / tiles, K / 512);
+  if (tiles < slots && K >= 1024) {
+    // fewer tiles than one round of resident workgroups: split K into the
+    // chunk count that minimises rounds x (chunk length + a per-workgroup
+    // overhead worth 256 of K)
+    const int64_t smax = std::min<int64_t>(K / 256, 64);
+    double best = (double)K + 256.0;
+    for (int64_t sp = 2; sp <= smax; ++sp) {
+      const double rounds = (double)((tiles * sp + slots - 1) / slots);
+      const double c = rounds * ((double)K / (double)sp + 256.0);
+      if (c < best) {
+        best = c;
+        splits = (int)sp;
+      }
+    }
     while (splits > 1 && (double)splits * batch * M * N * NP * sizeof(T) > 512.0 * (1 << 20))
       --splits;
     while (splits > 1 && (int64_t)splits * batch > 65535) --splits;
@@ -462,8 +509,40 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
     // (a lower-triangle update of short K stays here too: rocBLAS would
     // produce the full square, twice the bytes)
     const bool short_tri = tri && K < 256;
-    if (!cplx && !aliased && !short_tri && splits == 1 && t64 >= 512 && K >= 32 && M <= 0x7fffffff &&
-        N <= 0x7fffffff && K <= 0x7fffffff) {
+    const bool fits_int = M <= 0x7fffffff && N <= 0x7fffffff && K <= 0x7fffffff;
+    // a long-K product with few output tiles: the K chunks as one strided
+    // batch on rocBLAS into the split-K workspace, then the fixed-order sum
+    // (a lower-triangle product stays on the hand-written kernel, which
+    // computes half the tiles)
+    const int nsp = (int)std::min<int64_t>(16, K / 2048);
+    const int64_t kc = round_up((K + std::max(nsp, 1) - 1) / std::max(nsp, 1), GBK);
+    const int64_t nfull = kc > 0 ? K / kc : 0, krem = K - nfull * kc;
+    const int nparts = (int)nfull + (krem > 0 ? 1 : 0);
+    if (!cplx && !aliased && !tri && batch == 1 && t64 < 512 && nsp >= 2 && fits_int &&
+        (double)nparts * M * N * sizeof(double) <= 512.0 * (1 << 20)) {
+      KernelAccount::Scope acct(s, KA_ROCBLAS, 2.0 * (double)M * (double)N * (double)K,
+                                8.0 * ((double)M * K + (double)K * N +
+                                       (beta != 0.0 ? 2.0 : 1.0) * (double)M * N));
+      double* part =
+          static_cast<double*>(splitk_workspace(s, sizeof(double) * (size_t)nparts * M * N));
+      acct.mark_start();
+      DMat<double> Ac = A, Bc = B, Pc{part, nullptr, M, M * N};
+      Ac.bs = ta ? kc : kc * A.ld;
+      Bc.bs = tb ? kc * B.ld : kc;
+      blas_dgemm(s, ta, tb, M, N, kc, alpha, Ac, Bc, 0.0, Pc, (int)nfull);
+      if (krem > 0) {
+        DMat<double> Ar = A, Br = B, Pr{part + nfull * M * N, nullptr, M, 0};
+        Ar.re += ta ? nfull * kc : nfull * kc * A.ld;
+        Br.re += tb ? nfull * kc * B.ld : nfull * kc;
+        blas_dgemm(s, ta, tb, M, N, krem, alpha, Ar, Br, 0.0, Pr, 1);
+      }
+      k_splitk_sum<double, false><<<dim3(grid1(M * N), 1), 256, 0, s>>>(M, N, nparts, 1, part, beta,
+                                                                       C, 0);
+      RFD_CHECK_LAUNCH();
+      acct.mark_stop();
+      return;
+    }
+    if (!cplx && !aliased && !short_tri && splits == 1 && t64 >= 512 && K >= 32 && fits_int) {
       KernelAccount::Scope acct(s, KA_ROCBLAS, 2.0 * (double)M * (double)N * (double)K * batch,
                                 8.0 * ((double)M * K + (double)K * N +
                                        (beta != 0.0 ? 2.0 : 1.0) * (double)M * N) * batch);
