@@ -809,7 +809,6 @@ void inverse_iteration(hipStream_t s, const TriWork& w, int64_t n, int batch, co
 // V[r, q] (rows i0 + 1 .. n - 1 of the panel's reflectors, explicit unit
 // entry, zeros above it)
 // Reflectors are applied in blocks of WY_NB (compact WY: I - V T V^T).
-constexpr int WY_NB = 128;
 
 // V (m x WY_NB, m = n - i0 - 1) of the block of reflectors i0 .. i0 + nbp - 1,
 // with the unit entries explicit and zero columns beyond nbp.
@@ -832,14 +831,19 @@ __global__ void k_wy_v(DMat<double> A, int64_t n, int64_t i0, int nbp, double* V
 // then block column b takes T[0:32b, blk b] = -T[0:32b, 0:32b] G[0:32b, blk b]
 // T_bb, which is the same recurrence applied a block at a time.  One
 // workgroup of 256 per item; the upper triangle of T stays in shared memory
-// (packed by columns) until it is written out whole.
+// (packed by columns) until it is written out whole.  Every operand read in
+// a dependent chain (the block's tau, the diagonal blocks of G, the block
+// column of G of each merge) is staged in shared memory first, with all its
+// global loads in flight together.
 constexpr int WY_SB = 32;
 __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tauv, int64_t n,
                                               int64_t i0, int nbp, double* T) {
   constexpr int NS = WY_NB / WY_SB;
   __shared__ double Ts[NS][WY_SB][WY_SB + 1];
   __shared__ double Tp[WY_NB * (WY_NB + 1) / 2];
-  // the diagonal blocks of G, later X (both fit in the larger of the two)
+  __shared__ double tl[WY_NB];
+  // the diagonal blocks of G, later a block column of G, then X (each fits
+  // in the larger of the two shapes)
   constexpr int SH = NS * WY_SB * (WY_SB + 1) > (WY_NB - WY_SB) * (WY_SB + 1)
                          ? NS * WY_SB * (WY_SB + 1)
                          : (WY_NB - WY_SB) * (WY_SB + 1);
@@ -853,16 +857,28 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
   double* To = T + (int64_t)b * WY_NB * WY_NB;
   for (int e = t; e < NS * WY_SB * (WY_SB + 1); e += 256) (&Ts[0][0][0])[e] = 0.0;
   for (int e = t; e < WY_NB * (WY_NB + 1) / 2; e += 256) Tp[e] = 0.0;
-  for (int e = t; e < NS * WY_SB * WY_SB; e += 256) {
-    const int a = e / (WY_SB * WY_SB), r = e % WY_SB, c = (e / WY_SB) % WY_SB;
-    Gd(a, r, c) = g[(a * WY_SB + r) + (int64_t)(a * WY_SB + c) * WY_NB];
+  if (t < WY_NB) tl[t] = t < nbp ? tauv[(int64_t)b * n + i0 + t] : 0.0;
+  {
+    constexpr int NE = NS * WY_SB * WY_SB / 256;
+    double gv[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = t + 256 * i;
+      const int a = e / (WY_SB * WY_SB), r = e % WY_SB, c = (e / WY_SB) % WY_SB;
+      gv[i] = g[(a * WY_SB + r) + (int64_t)(a * WY_SB + c) * WY_NB];
+    }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = t + 256 * i;
+      const int a = e / (WY_SB * WY_SB), r = e % WY_SB, c = (e / WY_SB) % WY_SB;
+      Gd(a, r, c) = gv[i];
+    }
   }
   __syncthreads();
   // diagonal blocks: group grp owns block grp (reflectors k0 + k)
   const int k0 = grp * WY_SB;
   for (int k = 0; k < WY_SB; ++k) {
-    const int kk = k0 + k;
-    const double tk = kk < nbp ? tauv[(int64_t)b * n + i0 + kk] : 0.0;
+    const double tk = tl[k0 + k];
     double v = 0.0;
     if (lt < k) {
       for (int q = lt; q < k; ++q) v += Ts[grp][lt][q] * Gd(grp, q, k);
@@ -879,14 +895,42 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
   }
   __syncthreads();
   // off-diagonal block columns
+  constexpr int NX = (WY_NB - WY_SB) * WY_SB / 256;  // entries of X per thread, at most
   for (int bc = 1; bc < NS; ++bc) {
     const int c0 = bc * WY_SB, rows = c0;
-    // X = G[0:c0, blk] T_bb
-    for (int e = t; e < rows * WY_SB; e += 256) {
-      const int r = e % rows, c = e / rows;
+    // G[0:c0, blk] into shared memory (sh is free: the diagonal blocks of G
+    // and the previous X are no longer read)
+    {
+      double gv[NX];
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        const int e = t + 256 * i;
+        gv[i] = e < rows * WY_SB ? g[e % rows + (int64_t)(c0 + e / rows) * WY_NB] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < NX; ++i) {
+        const int e = t + 256 * i;
+        if (e < rows * WY_SB) X(e % rows, e / rows) = gv[i];
+      }
+    }
+    __syncthreads();
+    // X = G[0:c0, blk] T_bb, formed in registers, then written over G's block
+    double xv[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int e = t + 256 * i;
       double acc = 0.0;
-      for (int q = 0; q <= c; ++q) acc += g[r + (int64_t)(c0 + q) * WY_NB] * Ts[bc][q][c];
-      X(r, c) = acc;
+      if (e < rows * WY_SB) {
+        const int r = e % rows, c = e / rows;
+        for (int q = 0; q <= c; ++q) acc += X(r, q) * Ts[bc][q][c];
+      }
+      xv[i] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int e = t + 256 * i;
+      if (e < rows * WY_SB) X(e % rows, e / rows) = xv[i];
     }
     __syncthreads();
     // T[0:c0, blk] = -T[0:c0, 0:c0] X (upper triangular: column q >= r)
@@ -902,6 +946,14 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
     const int r = e % WY_NB, c = e / WY_NB;
     To[e] = r <= c ? Tu(r, c) : 0.0;
   }
+}
+
+void wy_triangle(hipStream_t s, const double* G, const double* tau, int64_t ld_tau, int64_t i0,
+                 int nbp, double* T, int batch) {
+  if (batch <= 0) return;
+  if (nbp < 0 || nbp > WY_NB) throw Error(ST_EINVAL, "wy_triangle: block of more than WY_NB reflectors");
+  k_wy_t<<<batch, 256, 0, s>>>(G, tau, ld_tau, i0, nbp, T);
+  RFD_CHECK_LAUNCH();
 }
 
 void back_transform(hipStream_t s, DMat<double> A, TriWork& w, int64_t n, int batch,
@@ -929,8 +981,7 @@ void back_transform(hipStream_t s, DMat<double> A, TriWork& w, int64_t n, int ba
     DMat<double> W2m{W2.as<double>(), nullptr, WY_NB, WY_NB * (int64_t)maxcols};
     DMat<double> Ys = Y.sub(i0 + 1, 0);
     gemm<double>(s, true, false, WY_NB, WY_NB, m, 1.0, Vm, Vm, 0.0, Gm, batch);
-    k_wy_t<<<batch, 256, 0, s>>>(Gb.as<double>(), w.tau.as<double>(), n, i0, nbp, Tb.as<double>());
-    RFD_CHECK_LAUNCH();
+    wy_triangle(s, Gb.as<double>(), w.tau.as<double>(), n, i0, nbp, Tb.as<double>(), batch);
     gemm<double>(s, true, false, WY_NB, maxcols, m, 1.0, Vm, Ys, 0.0, W1m, batch);
     gemm<double>(s, false, false, WY_NB, maxcols, WY_NB, 1.0, Tm, W1m, 0.0, W2m, batch);
     gemm<double>(s, false, false, m, maxcols, WY_NB, -1.0, Vm, W2m, 1.0, Ys, batch);

@@ -46,6 +46,16 @@ void inverse_iteration(hipStream_t s, const TriWork& w, int64_t n, int batch, co
                        const int* num, const int* clus, int64_t ld_lam, DMat<double> Y,
                        DevBuf& scratch);
 
+// Reflectors per compact-WY block (I - V T V^T).
+constexpr int WY_NB = 128;
+
+// T (WY_NB x WY_NB, upper triangular, per item) of the compact-WY form
+// H_i0 .. H_{i0+nbp-1} = I - V T V^T, from G = V^T V (WY_NB x WY_NB per item,
+// finite; its rows and columns beyond nbp are not used) and the scalars
+// tau[b * ld_tau + i0 + k], k < nbp.  Rows and columns of T beyond nbp are 0.
+void wy_triangle(hipStream_t s, const double* G, const double* tau, int64_t ld_tau, int64_t i0,
+                 int nbp, double* T, int batch);
+
 // Y <- Q Y with Q the product of the Householder reflectors left in A by
 // sy_tridiag (cols columns per item; columns beyond num[b] must be zero or
 // are transformed along).

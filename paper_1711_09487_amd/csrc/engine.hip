@@ -262,7 +262,8 @@ std::vector<DevBuf*> EngineImpl::solve_buffers() {
                          &Sinv32, &Sinv64, &Swide, &Swork, &Yc, &Xf, &Rf, &Rf32, &W, &Qint, &Vb, &Bs, &Bsinv,
                          &Bspiv, &Lev, &Zt, &work1, &work2, &work3, &work4, &work5, &work6,
                          &ipiv_small, &iscal, &gwork, &work6b, &rr_az, &rr_h, &ow.V, &ow.T,
-                         &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank};
+                         &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank, &ow.wg, &ow.wt,
+                         &ow.w1, &ow.w2};
   for (TriWork* t : {&tw_v, &tw_h})
     for (DevBuf* b : {&t->d, &t->e, &t->tau, &t->pt, &t->acol, &t->vw, &t->red, &t->sq, &t->ptvp,
                       &t->wv, &t->wg, &t->wt, &t->w1, &t->w2})

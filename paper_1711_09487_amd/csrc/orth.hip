@@ -8,11 +8,12 @@
 // the consumed mask of the current step), so all agree without a grid
 // barrier; each workgroup writes only its own column and its own entries of
 // the next step's state (double-buffered by step parity).  The explicit
-// factor Q = H_0 .. H_{r-1} [I_r; 0] is formed column by column in one more
-// launch: column c needs only H_0 .. H_c.
+// factor Q = H_0 .. H_{r-1} [I_r; 0] is formed in compact-WY blocks of
+// reflectors (I - V T V^T), last block first, with matrix products.
 #include <algorithm>
 
 #include "dense.hpp"
+#include "eig.hpp"
 #include "orth.hpp"
 
 namespace rfd {
@@ -28,6 +29,32 @@ __device__ inline double block_sum(double v, double* red) {
   const double r = red[0];
   __syncthreads();
   return r;
+}
+
+// Sums over a workgroup of exactly 256 threads (four wavefronts): shuffles
+// within each wavefront, then the four partial sums in a fixed order.
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline void block_sum256x2(double& a, double& b, double* red) {
+  a = wave_sum64(a);
+  b = wave_sum64(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = a;
+    red[4 + w] = b;
+  }
+  __syncthreads();
+  a = (red[0] + red[1]) + (red[2] + red[3]);
+  b = (red[4] + red[5]) + (red[6] + red[7]);
+  __syncthreads();
+}
+__device__ inline double block_sum256(double a, double* red) {
+  double b = 0.0;
+  block_sum256x2(a, b, red);
+  return a;
 }
 
 // Column norms (one workgroup per column); optionally tol = factor * max.
@@ -75,25 +102,34 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
   double* cnn = cn + (int64_t)nxt * m;
   const int* usc = used + (int64_t)cur * m;
   int* usn = used + (int64_t)nxt * m;
-  // pivot: the unconsumed column of largest norm (lowest index on ties)
+  // pivot: the unconsumed column of largest norm (lowest index on ties),
+  // per thread, then across each wavefront by shuffles, then the four
+  // wavefronts in order
   double best = -1.0;
   int bi = m;
   for (int q = t; q < m; q += blockDim.x)
     if (!usc[q] && cnc[q] > best) { best = cnc[q]; bi = q; }
-  sv[t] = best;
-  ired[t] = bi;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      if (sv[t + w] > sv[t] || (sv[t + w] == sv[t] && ired[t + w] < ired[t])) {
-        sv[t] = sv[t + w];
-        ired[t] = ired[t + w];
-      }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
     }
-    __syncthreads();
   }
-  const int P = ired[0];
-  const double cmax = sv[0];
+  if ((t & 63) == 0) {
+    sv[t >> 6] = best;
+    ired[t >> 6] = bi;
+  }
+  __syncthreads();
+  double cmax = sv[0];
+  int P = ired[0];
+  for (int w = 1; w < 4; ++w)
+    if (sv[w] > cmax || (sv[w] == cmax && ired[w] < P)) {
+      cmax = sv[w];
+      P = ired[w];
+    }
   __syncthreads();
   const bool stop = (P >= m) || !(cmax > *tol_abs) || (j >= rows);
   if (stop || usc[c]) {
@@ -104,17 +140,26 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
     }
     return;
   }
-  // Householder vector of column P below row j (beta = -sign(x0) ||x||)
+  // Householder vector of column P below row j (beta = -sign(x0) ||x||),
+  // v = [1; x[1:] / (x0 - beta)].  The other columns take, in the same pass,
+  // e = x[1:]^T a[j+1:], so that v^T a = a[j] + e / (x0 - beta).
   const double* ap = A + (int64_t)P * lda;
-  double s2 = 0;
-  for (int64_t i = j + t; i < rows; i += blockDim.x) s2 += ap[i] * ap[i];
-  s2 = block_sum(s2, red);
+  double* ac = A + (int64_t)c * lda;
+  const bool piv_col = c == P;
   const double x0 = ap[j];
+  const double acj = piv_col ? 0.0 : ac[j];
+  double s2 = 0, e = 0;
+  for (int64_t i = j + t; i < rows; i += blockDim.x) {
+    const double x = ap[i];
+    s2 += x * x;
+    if (!piv_col && i > j) e += x * ac[i];
+  }
+  block_sum256x2(s2, e, red);
   const double nrm = sqrt(s2);
   const double beta = x0 >= 0 ? -nrm : nrm;
   const double tj = (beta - x0) / beta;
   const double scal = 1.0 / (x0 - beta);
-  if (c == P) {
+  if (piv_col) {
     double* v = V + (int64_t)j * ldv;
     for (int64_t i = t; i < rows; i += blockDim.x)
       v[i] = (i < j) ? 0.0 : (i == j ? 1.0 : ap[i] * scal);
@@ -126,10 +171,7 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
     }
     return;
   }
-  double* ac = A + (int64_t)c * lda;
-  double d = 0;
-  for (int64_t i = j + t; i < rows; i += blockDim.x) d += (i == j ? 1.0 : ap[i] * scal) * ac[i];
-  d = block_sum(d, red);
+  const double d = acj + scal * e;
   const double f = tj * d;
   double s3 = 0;
   for (int64_t i = j + t; i < rows; i += blockDim.x) {
@@ -137,7 +179,7 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
     ac[i] = nv;
     if (i > j) s3 += nv * nv;
   }
-  s3 = block_sum(s3, red);
+  s3 = block_sum256(s3, red);
   if (t == 0) {
     cnn[c] = sqrt(s3);
     usn[c] = 0;
@@ -149,23 +191,31 @@ __global__ void k_hqr_finish_rank(int* rank, int steps) {
 }
 
 // Column c of Q = H_0 H_1 .. H_c e_c, c < rank.
-__global__ __launch_bounds__(256) void k_hqr_formq(const double* V, int64_t ldv, const double* tau,
-                                                   const int* rank, int64_t rows, double* Q,
-                                                   int64_t ldq) {
-  __shared__ double red[256];
-  const int c = blockIdx.x, t = threadIdx.x;
-  if (c >= *rank) return;
-  double* q = Q + (int64_t)c * ldq;
-  for (int64_t i = t; i < rows; i += blockDim.x) q[i] = (i == c) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int jj = c; jj >= 0; --jj) {
-    const double* v = V + (int64_t)jj * ldv;
-    double d = 0;
-    for (int64_t i = jj + t; i < rows; i += blockDim.x) d += v[i] * q[i];
-    d = block_sum(d, red);
-    const double f = tau[jj] * d;
-    for (int64_t i = jj + t; i < rows; i += blockDim.x) q[i] -= f * v[i];
-    __syncthreads();
+// Q = H_0 .. H_{r-1} [I_r; 0] (rows x r, ld ldq) from the reflectors in V
+// (column j zero above row j, 1 at row j) and tau: blocks of WY_NB
+// reflectors, last block first, Q <- Q - V_k T_k (V_k^T Q), where the rows
+// above the block's first reflector are untouched.
+static void form_q(hipStream_t s, OrthWork& w, int64_t rows, int r, double* Q, int64_t ldq) {
+  DMat<double> Qm{Q, nullptr, ldq, 0};
+  fill<double>(s, Qm, rows, r, 1, 0.0);
+  pad_identity<double>(s, Qm, 0, r, 1);
+  w.wg.alloc(sizeof(double) * WY_NB * WY_NB);
+  w.wt.alloc(sizeof(double) * WY_NB * WY_NB);
+  w.w1.alloc(sizeof(double) * WY_NB * (int64_t)r);
+  w.w2.alloc(sizeof(double) * WY_NB * (int64_t)r);
+  DMat<double> Gm{w.wg.as<double>(), nullptr, WY_NB, 0}, Tm{w.wt.as<double>(), nullptr, WY_NB, 0};
+  DMat<double> W1m{w.w1.as<double>(), nullptr, WY_NB, 0}, W2m{w.w2.as<double>(), nullptr, WY_NB, 0};
+  for (int64_t k0 = ((int64_t)(r - 1) / WY_NB) * WY_NB; k0 >= 0; k0 -= WY_NB) {
+    const int nbp = (int)std::min<int64_t>(WY_NB, r - k0);
+    const int64_t m = rows - k0;
+    DMat<double> Vk{w.V.as<double>() + k0 + k0 * rows, nullptr, rows, 0};
+    DMat<double> Qk = Qm.sub(k0, 0);
+    fill<double>(s, Gm, WY_NB, WY_NB, 1, 0.0);
+    gemm<double>(s, true, false, nbp, nbp, m, 1.0, Vk, Vk, 0.0, Gm, 1);
+    wy_triangle(s, w.wg.as<double>(), w.tau.as<double>(), 0, k0, nbp, w.wt.as<double>(), 1);
+    gemm<double>(s, true, false, nbp, r, m, 1.0, Vk, Qk, 0.0, W1m, 1);
+    gemm<double>(s, false, false, nbp, r, nbp, 1.0, Tm, W1m, 0.0, W2m, 1);
+    gemm<double>(s, false, false, m, r, nbp, -1.0, Vk, W2m, 1.0, Qk, 1);
   }
 }
 
@@ -219,11 +269,11 @@ int orth_block(hipStream_t s, double* W, int64_t ldw, int64_t rows, int m, const
   }
   k_hqr_finish_rank<<<1, 1, 0, s>>>(w.rank.as<int>(), steps);
   RFD_CHECK_LAUNCH();
-  k_hqr_formq<<<steps, 256, 0, s>>>(w.V.as<double>(), rows, w.tau.as<double>(), w.rank.as<int>(),
-                                    rows, Qout, ldq);
-  RFD_CHECK_LAUNCH();
   int r = 0;
   RFD_HIP(hipMemcpyAsync(&r, w.rank.as<int>(), sizeof(int), hipMemcpyDeviceToHost, s));
+  RFD_HIP(hipStreamSynchronize(s));
+  if (r < 0 || r > steps) throw Error(ST_EDEVICE, "orth_block: rank out of range");
+  if (r > 0) form_q(s, w, rows, r, Qout, ldq);
   RFD_HIP(hipStreamSynchronize(s));
   return r;
 }

@@ -7,6 +7,7 @@ namespace rfd {
 
 struct OrthWork {
   DevBuf V, T, cn, used, piv, tau, scal, rank;
+  DevBuf wg, wt, w1, w2;  // compact-WY formation of Q
   int64_t v_elems = 0;
   int m_cap = 0, mu_cap = 0;
   void reserve(int64_t rows, int m, int mu_max);
