@@ -729,15 +729,28 @@ void merge_inverses(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n, int batch
     throw Error(ST_EINVAL, "merge_inverses: LW must be NB times a power of two dividing n");
   const int64_t nblk = n / LW;
   fill<T>(s, inv2, LW, 2 * n, batch, T(0));
-  // items are the batch; the diagonal blocks of one item are a strided batch
-  for (int it = 0; it < batch; ++it) {
-    DMat<T> lu = LU.item(it), iv = inv.item(it), i2 = inv2.item(it), wk = work;
-    lu.bs = LW + LW * lu.ld;           // next diagonal block
-    iv.bs = 2 * LW * iv.ld;            // its NB-block inverses
-    i2.bs = 2 * LW * i2.ld;            // its wide inverses
+  // one launch covers the diagonal blocks of one item (a strided batch), or
+  // one block position of every item (the item stride), whichever is more
+  const bool across_items = batch > nblk;
+  const int outer = across_items ? (int)nblk : batch;
+  const int cnt = across_items ? batch : (int)nblk;
+  for (int it = 0; it < outer; ++it) {
+    DMat<T> lu, iv, i2, wk = work;
+    if (across_items) {
+      lu = LU.sub((int64_t)it * LW, (int64_t)it * LW);
+      iv = inv.sub(0, 2 * (int64_t)it * LW);
+      i2 = inv2.sub(0, 2 * (int64_t)it * LW);
+    } else {
+      lu = LU.item(it);
+      iv = inv.item(it);
+      i2 = inv2.item(it);
+      lu.bs = LW + LW * lu.ld;           // next diagonal block
+      iv.bs = 2 * LW * iv.ld;            // its NB-block inverses
+      i2.bs = 2 * LW * i2.ld;            // its wide inverses
+    }
     for (int q = 0; q < LW / NB; ++q) {
-      convert<T, T>(s, iv.sub(0, 2 * q * NB), i2.sub(q * NB, q * NB), NB, NB, (int)nblk);
-      convert<T, T>(s, iv.sub(0, 2 * q * NB + NB), i2.sub(q * NB, LW + q * NB), NB, NB, (int)nblk);
+      convert<T, T>(s, iv.sub(0, 2 * q * NB), i2.sub(q * NB, q * NB), NB, NB, cnt);
+      convert<T, T>(s, iv.sub(0, 2 * q * NB + NB), i2.sub(q * NB, LW + q * NB), NB, NB, cnt);
     }
     // [A 0; B C]^{-1} = [A^{-1} 0; -C^{-1} B A^{-1} C^{-1}] and
     // [A B; 0 C]^{-1} = [A^{-1} -A^{-1} B C^{-1}; 0 C^{-1}], widths NB, 2 NB, ...
@@ -746,14 +759,13 @@ void merge_inverses(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n, int batch
         DMat<T> tw = wk;
         tw.ld = w;
         tw.bs = (int64_t)w * w;
-        gemm<T>(s, false, false, w, w, w, T(1), lu.sub(o + w, o), i2.sub(o, o), T(0), tw,
-                (int)nblk);
+        gemm<T>(s, false, false, w, w, w, T(1), lu.sub(o + w, o), i2.sub(o, o), T(0), tw, cnt);
         gemm<T>(s, false, false, w, w, w, T(-1), i2.sub(o + w, o + w), tw, T(0), i2.sub(o + w, o),
-                (int)nblk);
+                cnt);
         gemm<T>(s, false, false, w, w, w, T(1), lu.sub(o, o + w), i2.sub(o + w, LW + o + w), T(0),
-                tw, (int)nblk);
+                tw, cnt);
         gemm<T>(s, false, false, w, w, w, T(-1), i2.sub(o, LW + o), tw, T(0), i2.sub(o, LW + o + w),
-                (int)nblk);
+                cnt);
       }
   }
 }

@@ -94,9 +94,11 @@ void lu_solve(hipStream_t s, DMat<T> LU, DMat<T> inv, const int32_t* ipiv, int64
 // Wide leaves for lu_solve: inverses of the LW x LW diagonal blocks of the
 // factors of lu_nopiv (LW = NB times a power of two, dividing n), merged from
 // the NB-block inverses in inv: inv2 is LW x 2n per item, [Linv_0 Uinv_0
-// Linv_1 ...] as inv.  work: (LW / 2)^2 (n / LW) elements per plane, reused
-// for every item.  lu_solve with inv2, LW and a work of LW x r per item then
-// stops its recursion at LW (fewer, larger products).
+// Linv_1 ...] as inv.  work: (LW / 2)^2 max(n / LW, batch) elements per
+// plane.  lu_solve with inv2, LW and a work of LW x r per item then stops its
+// recursion at LW (fewer, larger products).  Works for the factors of lu_piv
+// as well: the rows a later panel interchanges lie below every leaf it
+// touches.
 template <typename T>
 void merge_inverses(hipStream_t s, DMat<T> LU, DMat<T> inv, int64_t n, int batch, DMat<T> inv2,
                     int LW, DMat<T> work);

@@ -163,6 +163,7 @@ int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, i
   b += SP * MP * n_c * (f32 ? 16 + 16 + 8 : 16);                  // filter right-hand sides
   b += e.s * (mu + m) * 8 * 3;                                    // interface basis, orth work
   b += p * (D * VB + 3 * D * D + D * (int64_t)psi * MUP) * 8;     // V_j, B_sigma, levels
+  b += p * (2 * 256 * D + 256 * MUP) * 8;                          // B_sigma wide leaves, their work
   b += n * (k * 3 + 4 * mu) * 8 + k * k * 8 * 2;                  // Z, A Z, H, level work
   return b + b / 10 + (int64_t(64) << 20);
 }
@@ -260,7 +261,7 @@ PhaseTimer::~PhaseTimer() {
 std::vector<DevBuf*> EngineImpl::solve_buffers() {
   std::vector<DevBuf*> v{&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32,
                          &Sinv32, &Sinv64, &Swide, &Swork, &Yc, &Xf, &Rf, &Rf32, &W, &Qint, &Vb, &Bs, &Bsinv,
-                         &Bspiv, &Lev, &Zt, &work1, &work2, &work3, &work4, &work5, &work6,
+                         &Bspiv, &Bswide, &Bswork, &Lev, &Zt, &work1, &work2, &work3, &work4, &work5, &work6,
                          &ipiv_small, &iscal, &gwork, &work6b, &rr_az, &rr_h, &ow.V, &ow.T,
                          &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank, &ow.wg, &ow.wt,
                          &ow.w1, &ow.w2};
@@ -274,7 +275,8 @@ std::vector<DevBuf*> EngineImpl::solve_buffers() {
 
 // Buffers an interior preparation writes (see prepare_interior).
 std::vector<DevBuf*> EngineImpl::prep_buffers() {
-  std::vector<DevBuf*> v{&Vb, &work1, &work2, &work3, &kap_d, &Bs, &Bsinv, &Bspiv, &prep_flags};
+  std::vector<DevBuf*> v{&Vb, &work1, &work2, &work3, &kap_d, &Bs, &Bsinv, &Bspiv, &Bswide,
+                         &Bswork, &prep_flags};
   for (DevBuf* b : {&tw_v.d, &tw_v.e, &tw_v.tau, &tw_v.pt, &tw_v.acol, &tw_v.vw, &tw_v.red,
                     &tw_v.sq, &tw_v.ptvp, &tw_v.wv, &tw_v.wg, &tw_v.wt, &tw_v.w1, &tw_v.w2})
     v.push_back(b);
@@ -383,7 +385,7 @@ void EngineImpl::wide_inverses(hipStream_t st, DMat<T> LU, DMat<T> inv, int nc) 
   const int64_t per = (int64_t)SLW * 2 * SP;  // elements per plane per pole
   Swide.alloc(2 * per * nc * sizeof(T));
   DMat<T> w2{Swide.as<T>(), Swide.as<T>() + per * nc, SLW, per};
-  const int64_t mw = (int64_t)(SLW / 2) * (SLW / 2) * (SP / SLW);
+  const int64_t mw = (int64_t)(SLW / 2) * (SLW / 2) * std::max<int64_t>(SP / SLW, nc);
   Swork.alloc(std::max<int64_t>(Swork.bytes, 2 * mw * sizeof(T)));
   DMat<T> wk{Swork.as<T>(), Swork.as<T>() + mw, SLW / 2, 0};
   merge_inverses<T>(st, LU, inv, SP, nc, w2, SLW, wk);

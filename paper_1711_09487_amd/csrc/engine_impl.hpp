@@ -82,6 +82,8 @@ struct EngineImpl {
   int64_t VB = 0;                         // padded column capacity per subdomain
   DevBuf kap_d, delta_d;
   DevBuf Bs, Bsinv, Bspiv;                // B_sigma LU (FP64, pivoted)
+  DevBuf Bswide, Bswork;                  // its BLW-wide diagonal inverses, leaf workspace
+  int BLW = 0;
   bool bs_valid = false;
   double bs_sigma = 0;
   DevBuf Lev;                             // levels: per subdomain D x (psi * MUP)

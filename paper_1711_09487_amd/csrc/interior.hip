@@ -363,8 +363,8 @@ void EngineImpl::apply_m(hipStream_t st, const double* X, int64_t ldx, double* Y
 
 int64_t EngineImpl::interior_bytes() const {
   int64_t t = 0;
-  for (const DevBuf* b : {&Vb, &Bs, &Bsinv, &Bspiv, &Lev, &Zt, &work1, &work2, &work3, &work4,
-                          &work5, &work6})
+  for (const DevBuf* b : {&Vb, &Bs, &Bsinv, &Bspiv, &Bswide, &Bswork, &Lev, &Zt, &work1, &work2,
+                          &work3, &work4, &work5, &work6})
     t += (int64_t)b->bytes;
   return t;
 }
@@ -513,6 +513,17 @@ void EngineImpl::factor_bsigma(hipStream_t st, double sig, DevBuf* fl, bool chec
   Shifts z{zeta.as<double>()};
   expand_shifted<double>(st, K, D, p, 1, 0, dj.as<int32_t>(), Bg.view(), z, true, sig);
   lu_piv<double>(st, K, D, p, Ki, Bspiv.as<int32_t>(), fw.as<unsigned>(), 1e-300);
+  // the level solves stop their recursion at BLW-wide diagonal blocks (256 or
+  // 128 when it divides D): their inverses are merged here once
+  BLW = (D % 256 == 0 && D > 256) ? 256 : ((D % 128 == 0 && D > 128) ? 128 : 0);
+  if (BLW) {
+    const int64_t per = (int64_t)BLW * 2 * D;
+    Bswide.alloc(sizeof(double) * per * p);
+    const int64_t mw = (int64_t)(BLW / 2) * (BLW / 2) * std::max<int64_t>(D / BLW, p);
+    Bswork.alloc(std::max<int64_t>(Bswork.bytes, sizeof(double) * mw));
+    merge_inverses<double>(st, K, Ki, D, p, DMat<double>{Bswide.as<double>(), nullptr, BLW, per},
+                           BLW, DMat<double>{Bswork.as<double>(), nullptr, BLW / 2, 0});
+  }
   timer.end(st);
   // (the caller checks the flags itself when check is false, after it has
   // enqueued its other work)
@@ -673,7 +684,15 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   for (int t = 0; t < psi; ++t) {
     DMat<double> X = Lv.sub(0, t * MUP);
     convert<double, double>(st, Rh, X, D, MUP, p);
-    lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p);
+    if (e.BLW) {
+      const int64_t per = (int64_t)e.BLW * 2 * D;
+      e.Bswork.alloc(std::max<int64_t>(e.Bswork.bytes, sizeof(double) * e.BLW * MUP * p));
+      lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p, 3,
+                       DMat<double>{e.Bswide.as<double>(), nullptr, e.BLW, per}, e.BLW,
+                       DMat<double>{e.Bswork.as<double>(), nullptr, e.BLW, e.BLW * MUP});
+    } else {
+      lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p);
+    }
     // make the level M_B-orthogonal to V_j (twice)
     if (e.kappa_tot > 0) {
       if (t > 0) {
