@@ -67,38 +67,71 @@ void expand_rhs(hipStream_t s, DMat<T> R, int p, int npoles, int pole0, const in
 }
 
 // ---------------------------------------------------------------------------
-// One thread per (row r, column c) of an item: R = E_z[r, c] - (K_z X)[r, c].
+// FP64 residual of the Schur-contribution solves, R = E_z - K_z X per item
+// (local CSR of B_j and E_j with their mass values, shift of the item's pole),
+// and max |R| into rmax.  A thread owns one row r and RS_C consecutive
+// columns: it reads the row's
+// CSR entries and forms the shifted values once, then gathers the columns'
+// entries of X together.
+constexpr int RS_C = 8;
 __global__ void k_residual_shifted(DMat<double> X, DMat<double> R, int64_t D, int64_t SJ, int p,
                                    int pole0, const int32_t* dj, const int32_t* sj, DevPairCsr B,
                                    DevPairCsr E, Shifts z, double* rmax) {
-  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y, j = b % p, l = pole0 + b / p;
+  const int64_t ncg = (SJ + RS_C - 1) / RS_C;
   double mx = 0;
-  if (e0 < D * SJ) {
-    const int64_t r = e0 % D, c = e0 / D;
+  if (t0 < D * ncg) {
+    const int64_t r = t0 % D, c0 = (t0 / D) * RS_C;
     DMat<double> x = X.item(b), rr = R.item(b);
-    double vr = 0, vi = 0;
-    if (r < dj[j] && c < sj[j]) {
+    const int64_t dr = dj[j], sc = sj[j];
+    double vr[RS_C], vi[RS_C];
+#pragma unroll
+    for (int q = 0; q < RS_C; ++q) vr[q] = vi[q] = 0.0;
+    if (r < dr) {
       const double zr = z.z[2 * l], zi = z.z[2 * l + 1];
       const int64_t* pe = E.ptr + E.roff[j];
-      for (int64_t e = pe[r]; e < pe[r + 1]; ++e)
-        if (E.idx[e] == c) {
-          vr += E.a[e] - zr * E.m[e];
-          vi += -zi * E.m[e];
-        }
+      for (int64_t e = pe[r]; e < pe[r + 1]; ++e) {
+        const int64_t c = E.idx[e] - c0;
+        const double er = E.a[e] - zr * E.m[e], ei = -zi * E.m[e];
+#pragma unroll
+        for (int q = 0; q < RS_C; ++q)
+          if (q == c) {
+            vr[q] += er;
+            vi[q] += ei;
+          }
+      }
       const int64_t* pb = B.ptr + B.roff[j];
       for (int64_t e = pb[r]; e < pb[r + 1]; ++e) {
-        const int64_t q = B.idx[e] + c * x.ld;
         const double kr = B.a[e] - zr * B.m[e], ki = -zi * B.m[e];
-        const double xr = x.re[q], xi = x.im[q];
-        vr -= kr * xr - ki * xi;
-        vi -= kr * xi + ki * xr;
+        const int64_t base = B.idx[e] + c0 * x.ld;
+        double xr[RS_C], xi[RS_C];
+#pragma unroll
+        for (int q = 0; q < RS_C; ++q) {
+          const bool ok = c0 + q < sc;
+          xr[q] = ok ? x.re[base + q * x.ld] : 0.0;
+          xi[q] = ok ? x.im[base + q * x.ld] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < RS_C; ++q) {
+          vr[q] -= kr * xr[q] - ki * xi[q];
+          vi[q] -= kr * xi[q] + ki * xr[q];
+        }
       }
-      mx = fmax(fabs(vr), fabs(vi));
-      if (!(mx == mx)) mx = INFINITY;
     }
-    rr.re[r + c * rr.ld] = vr;
-    rr.im[r + c * rr.ld] = vi;
+#pragma unroll
+    for (int q = 0; q < RS_C; ++q) {
+      const int64_t c = c0 + q;
+      if (c >= SJ) break;
+      const bool ok = r < dr && c < sc;
+      const double wr = ok ? vr[q] : 0.0, wi = ok ? vi[q] : 0.0;
+      rr.re[r + c * rr.ld] = wr;
+      rr.im[r + c * rr.ld] = wi;
+      if (ok) {
+        const double m = fmax(fabs(wr), fabs(wi));
+        mx = (m == m) ? fmax(mx, m) : INFINITY;
+      }
+    }
   }
   __shared__ double red[256];
   red[threadIdx.x] = mx;
@@ -113,7 +146,7 @@ __global__ void k_residual_shifted(DMat<double> X, DMat<double> R, int64_t D, in
 void residual_shifted(hipStream_t s, DMat<double> X, DMat<double> R, int64_t D, int64_t SJ, int p,
                       int npoles, int pole0, const int32_t* dj, const int32_t* sj, DevPairCsr B,
                       DevPairCsr E, Shifts z, double* rmax) {
-  dim3 g(grid1(D * SJ), p * npoles);
+  dim3 g(grid1(D * ((SJ + RS_C - 1) / RS_C)), p * npoles);
   k_residual_shifted<<<g, 256, 0, s>>>(X, R, D, SJ, p, pole0, dj, sj, B, E, z, rmax);
   RFD_CHECK_LAUNCH();
 }
