@@ -154,23 +154,32 @@ __global__ void k_scatter_v(double* Z, int64_t ldz, DMat<double> V, const int32_
 }
 
 // level t of Z in the reordered numbering: interior rows from Lev, interface
-// rows Q (t == 0) or 0.
+// rows Q (t == 0) or 0.  The subdomain of a row is found by bisection over
+// the interior offsets, held in shared memory when there are at most
+// BL_MAXP + 1 of them.
+constexpr int BL_MAXP = 4095;
 __global__ void k_build_level(double* L, int64_t ldl, DMat<double> Lev, int t, int64_t MUP,
                               const int32_t* ioff, int p, int64_t n_int, int64_t n, const double* Q,
                               int64_t ldq, int mu) {
+  __shared__ int32_t so[BL_MAXP + 1];
+  const bool in_lds = p <= BL_MAXP;
+  if (in_lds)
+    for (int k = threadIdx.x; k <= p; k += blockDim.x) so[k] = ioff[k];
+  __syncthreads();
+  const int32_t* off = in_lds ? so : ioff;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * mu) return;
   const int64_t i = e % n, c = e / n;
   double v = 0;
   if (i < n_int) {
-    int lo = 0, hi = p;  // ioff[lo] <= i < ioff[hi]
+    int lo = 0, hi = p;  // off[lo] <= i < off[hi]
     while (hi - lo > 1) {
       const int mid = (lo + hi) / 2;
-      if (ioff[mid] <= i) lo = mid;
+      if (off[mid] <= i) lo = mid;
       else hi = mid;
     }
     DMat<double> x = Lev.item(lo);
-    v = x.re[(i - ioff[lo]) + (t * MUP + c) * x.ld];
+    v = x.re[(i - off[lo]) + (t * MUP + c) * x.ld];
   } else if (t == 0) {
     v = Q[(i - n_int) + c * ldq];
   }
@@ -179,7 +188,9 @@ __global__ void k_build_level(double* L, int64_t ldl, DMat<double> Lev, int t, i
 
 // Y = op X with op a CSR matrix (n x n) (Y, X dense n x cols).  One thread
 // per row and group of four columns: the row's entries are read once for the
-// four columns; the y grid dimension runs over column groups.
+// four columns, eight at a time with all their loads in flight before the
+// gathers of X that depend on them; the y grid dimension runs over column
+// groups.
 __global__ void k_csr_mm(const int64_t* ptr, const int32_t* idx, const double* val, int64_t n,
                          const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t cols) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -187,13 +198,27 @@ __global__ void k_csr_mm(const int64_t* ptr, const int32_t* idx, const double* v
   const int64_t c0 = (int64_t)blockIdx.y * 4;
   const int nc = (int)((cols - c0) < 4 ? (cols - c0) : 4);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int64_t q1 = ptr[r + 1];
-  for (int64_t q = ptr[r]; q < q1; ++q) {
-    const double v = val[q];
-    const double* x = X + idx[q] + c0 * ldx;
+  const int64_t q0 = ptr[r], q1 = ptr[r + 1];
+  const double* xc = X + c0 * ldx;
+  for (int64_t qb = q0; qb < q1; qb += 8) {
+    int32_t ix[8];
+    double v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (u < nc) acc[u] += v * x[u * ldx];
+    for (int k = 0; k < 8; ++k) {
+      const bool ok = qb + k < q1;
+      ix[k] = ok ? idx[qb + k] : 0;
+      v[k] = ok ? val[qb + k] : 0.0;
+    }
+    double xv[8][4];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        xv[k][u] = (qb + k < q1 && u < nc) ? xc[ix[k] + u * ldx] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += v[k] * xv[k][u];
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
