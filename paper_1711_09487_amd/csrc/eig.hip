@@ -472,26 +472,64 @@ __device__ inline int sturm(const double* d, const double* e, int64_t n, double 
   return cnt;
 }
 
-__device__ inline double pivmin_of(const double* e, int64_t n) {
-  double m = 1.0;
-  for (int64_t i = 0; i + 1 < n; ++i) m = fmax(m, e[i] * e[i]);
-  return SAFMIN * m / EPS;
+// The same count from d and the squares e2[i] = e[i]^2 (bitwise the same
+// products as above), read from shared memory by the kernels below.
+__device__ inline int sturm_sq(const double* d, const double* e2, int64_t n, double x,
+                               double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0) ++cnt;
+  for (int64_t i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] * rcp_nr(q);
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
 }
 
-__global__ void k_sturm(const double* dv, const double* ev, int64_t n, int batch, const double* x,
-                        int nx, int* cnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= batch * nx) return;
-  const int b = i / nx;
+// Tridiagonals up to this order are staged in shared memory (d and e^2,
+// 16 bytes a row) by the Sturm-count kernels: the recurrence then waits on
+// no global load.
+constexpr int64_t STURM_LDS_N = 4096;
+
+// Copies d and e^2 of one item into shared memory (all threads of the
+// workgroup; ends with a barrier).
+__device__ inline void stage_tridiag(const double* d, const double* e, int64_t n, double* sd,
+                                     double* se2) {
+  for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    sd[r] = d[r];
+    se2[r] = r + 1 < n ? e[r] * e[r] : 0.0;
+  }
+  __syncthreads();
+}
+
+// One wavefront per item: pivmin from the largest e^2 (a max, so the order
+// of the reduction does not matter), then a count per shift, lanes over x.
+__global__ __launch_bounds__(64) void k_sturm(const double* dv, const double* ev, int64_t n,
+                                              int batch, const double* x, int nx, int* cnt) {
+  extern __shared__ double st_sh[];
+  const int b = blockIdx.x, lane = threadIdx.x;
   const double* d = dv + (int64_t)b * n;
   const double* e = ev + (int64_t)b * n;
-  cnt[i] = sturm(d, e, n, x[i], pivmin_of(e, n));
+  const bool staged = n <= STURM_LDS_N;
+  if (staged) stage_tridiag(d, e, n, st_sh, st_sh + n);
+  double m = 1.0;
+  for (int64_t r = lane; r + 1 < n; r += 64) m = fmax(m, e[r] * e[r]);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  const double pivmin = SAFMIN * m / EPS;
+  for (int t = lane; t < nx; t += 64) {
+    const double xv = x[(int64_t)b * nx + t];
+    cnt[(int64_t)b * nx + t] =
+        staged ? sturm_sq(st_sh, st_sh + n, n, xv, pivmin) : sturm(d, e, n, xv, pivmin);
+  }
 }
 
 void sturm_counts(hipStream_t s, const TriWork& w, int64_t n, int batch, const double* x, int nx,
                   int* cnt) {
-  k_sturm<<<grid1((int64_t)batch * nx), 256, 0, s>>>(w.d.as<double>(), w.e.as<double>(), n, batch,
-                                                     x, nx, cnt);
+  if (batch <= 0 || nx <= 0 || n <= 0) return;
+  const size_t sh = n <= STURM_LDS_N ? sizeof(double) * 2 * n : 0;
+  k_sturm<<<batch, 64, sh, s>>>(w.d.as<double>(), w.e.as<double>(), n, batch, x, nx, cnt);
   RFD_CHECK_LAUNCH();
 }
 
@@ -501,12 +539,17 @@ void sturm_counts(hipStream_t s, const TriWork& w, int64_t n, int batch, const d
 __global__ __launch_bounds__(256) void k_bisect(const double* dv, const double* ev, int64_t n,
                                                 int batch, const int* lo, const int* num,
                                                 int maxnum, double* lam, int64_t ld_lam) {
+  extern __shared__ double bi_sh[];
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int b = blockIdx.y;
-  if (i >= maxnum || i >= num[b]) return;
   const double* d = dv + (int64_t)b * n;
   const double* e = ev + (int64_t)b * n;
+  // the workgroup's four eigenvalues belong to one item: its d and e^2 go to
+  // shared memory once
+  const bool staged = n <= STURM_LDS_N;
+  if (staged) stage_tridiag(d, e, n, bi_sh, bi_sh + n);
+  if (i >= maxnum || i >= num[b]) return;
   double gl = INFINITY, gu = -INFINITY, em = 1.0;
   for (int64_t r = lane; r < n; r += 64) {
     const double off = (r > 0 ? fabs(e[r - 1]) : 0.0) + (r + 1 < n ? fabs(e[r]) : 0.0);
@@ -528,7 +571,7 @@ __global__ __launch_bounds__(256) void k_bisect(const double* dv, const double* 
   for (int it = 0; it < 64; ++it) {
     if (u - l <= 2.0 * EPS * fmax(fabs(l), fabs(u)) + 4.0 * pivmin) break;
     const double x = l + (u - l) * ((double)(lane + 1) / 65.0);
-    const int cnt = sturm(d, e, n, x, pivmin);
+    const int cnt = staged ? sturm_sq(bi_sh, bi_sh + n, n, x, pivmin) : sturm(d, e, n, x, pivmin);
     const unsigned long long m = __ballot(cnt > k);
     double nl = l, nu = u;
     if (m == 0ull) {
@@ -549,8 +592,9 @@ void bisect(hipStream_t s, const TriWork& w, int64_t n, int batch, const int* lo
             int maxnum, double* lam, int64_t ld_lam) {
   if (maxnum <= 0) return;
   dim3 g((unsigned)((maxnum + 3) / 4), batch);
-  k_bisect<<<g, 256, 0, s>>>(w.d.as<double>(), w.e.as<double>(), n, batch, lo, num, maxnum, lam,
-                             ld_lam);
+  const size_t sh = n <= STURM_LDS_N ? sizeof(double) * 2 * n : 0;
+  k_bisect<<<g, 256, sh, s>>>(w.d.as<double>(), w.e.as<double>(), n, batch, lo, num, maxnum, lam,
+                              ld_lam);
   RFD_CHECK_LAUNCH();
 }
 
