@@ -238,6 +238,7 @@ __device__ __forceinline__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB +
       T sr = 0, si = 0, ar, ai, br, bi;
       if (!up) {
         ld(F, b + w + i, b + j, sr, si);
+#pragma unroll 4
         for (int t = j + 1; t < w; ++t) {
           ld(F, b + w + i, b + t, ar, ai);
           ld(X, b + t, b + j, br, bi);
@@ -246,6 +247,7 @@ __device__ __forceinline__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB +
         Tb[0][pr * w + i][j] = sr;
         if constexpr (CPLX) Tb[NP - 1][pr * w + i][j] = si;
       } else {
+#pragma unroll 4
         for (int t = 0; t <= j; ++t) {
           ld(F, b + i, b + w + t, ar, ai);
           ld(X, b + w + t, b + w + j, br, bi);
@@ -259,6 +261,7 @@ __device__ __forceinline__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB +
     for (int e = tid; e < half; e += 256) {
       const int pr = e / per, q = e % per, i = q % w, j = q / w, b = 2 * w * pr;
       T sr = 0, si = 0, ar, ai, br, bi;
+#pragma unroll 4
       for (int t = i; t < w; ++t) {
         ld(X, b + i, b + t, ar, ai);
         ld(X, b + w + t, b + j, br, bi);
@@ -271,6 +274,7 @@ __device__ __forceinline__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB +
     for (int e = tid; e < half; e += 256) {
       const int pr = e / per, q = e % per, i = q % w, j = q / w, b = 2 * w * pr;
       T sr = -Tb[0][pr * w + i][j], si = CPLX ? -Tb[NP - 1][pr * w + i][j] : T(0), ar, ai;
+#pragma unroll 4
       for (int t = 0; t < i; ++t) {
         ld(X, b + w + i, b + w + t, ar, ai);
         fma_sub<T, CPLX>(sr, si, ar, ai, Tb[0][pr * w + t][j], CPLX ? Tb[NP - 1][pr * w + t][j] : T(0));

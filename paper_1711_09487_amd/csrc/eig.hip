@@ -616,7 +616,7 @@ __device__ inline double hash_unit(uint64_t a, uint64_t b) {
 // elimination and the substitutions carry their running values in registers,
 // and every loop reads one array and writes another (two vector buffers used
 // in turn), so that loads can run ahead of the dependent arithmetic.
-constexpr int IV = 16;  // rows per prefetched chunk in the inverse iteration
+constexpr int IV = 32;  // rows per prefetched chunk in the inverse iteration
 
 __global__ __launch_bounds__(64) void k_invit(const double* __restrict__ d0,
                                               const double* __restrict__ e0, int64_t n,
@@ -925,6 +925,7 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
     const double tk = tl[k0 + k];
     double v = 0.0;
     if (lt < k) {
+#pragma unroll 8
       for (int q = lt; q < k; ++q) v += Ts[grp][lt][q] * Gd(grp, q, k);
       v *= -tk;
     }
@@ -966,6 +967,7 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
       double acc = 0.0;
       if (e < rows * WY_SB) {
         const int r = e % rows, c = e / rows;
+#pragma unroll 8
         for (int q = 0; q <= c; ++q) acc += X(r, q) * Ts[bc][q][c];
       }
       xv[i] = acc;
@@ -981,6 +983,7 @@ __global__ __launch_bounds__(256) void k_wy_t(const double* G, const double* tau
     for (int e = t; e < rows * WY_SB; e += 256) {
       const int r = e % rows, c = e / rows;
       double acc = 0.0;
+#pragma unroll 8
       for (int q = r; q < rows; ++q) acc += Tu(r, q) * X(q, c);
       Tu(r, c0 + c) = -acc;
     }
