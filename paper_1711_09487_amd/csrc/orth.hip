@@ -159,10 +159,25 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
   const double beta = x0 >= 0 ? -nrm : nrm;
   const double tj = (beta - x0) / beta;
   const double scal = 1.0 / (x0 - beta);
+  // (loops below load eight of the thread's rows before storing any: the
+  // compiler cannot tell the columns apart, so a load after a store would
+  // wait for it)
+  constexpr int U8 = 8;
   if (piv_col) {
     double* v = V + (int64_t)j * ldv;
-    for (int64_t i = t; i < rows; i += blockDim.x)
-      v[i] = (i < j) ? 0.0 : (i == j ? 1.0 : ap[i] * scal);
+    for (int64_t i0 = t; i0 < rows; i0 += 256 * U8) {
+      double xv[U8];
+#pragma unroll
+      for (int u = 0; u < U8; ++u) {
+        const int64_t i = i0 + 256 * u;
+        xv[u] = (i < rows && i > j) ? ap[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U8; ++u) {
+        const int64_t i = i0 + 256 * u;
+        if (i < rows) v[i] = (i < j) ? 0.0 : (i == j ? 1.0 : xv[u] * scal);
+      }
+    }
     if (t == 0) {
       piv[j] = P;
       tau[j] = tj;
@@ -174,10 +189,24 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
   const double d = acj + scal * e;
   const double f = tj * d;
   double s3 = 0;
-  for (int64_t i = j + t; i < rows; i += blockDim.x) {
-    const double nv = ac[i] - f * (i == j ? 1.0 : ap[i] * scal);
-    ac[i] = nv;
-    if (i > j) s3 += nv * nv;
+  for (int64_t i0 = j + t; i0 < rows; i0 += 256 * U8) {
+    double av[U8], pv[U8];
+#pragma unroll
+    for (int u = 0; u < U8; ++u) {
+      const int64_t i = i0 + 256 * u;
+      const bool ok = i < rows;
+      av[u] = ok ? ac[i] : 0.0;
+      pv[u] = ok ? ap[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U8; ++u) {
+      const int64_t i = i0 + 256 * u;
+      if (i < rows) {
+        const double nv = av[u] - f * (i == j ? 1.0 : pv[u] * scal);
+        ac[i] = nv;
+        if (i > j) s3 += nv * nv;
+      }
+    }
   }
   s3 = block_sum256(s3, red);
   if (t == 0) {
