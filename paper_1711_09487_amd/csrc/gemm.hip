@@ -482,11 +482,11 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   // round would take as long as the first
   const int64_t slots = resident_for<T>(cplx, bt);
   int splits = 1;
-  if (tiles < slots && K >= 1024) {
+  if (tiles < slots && K >= 256) {
     // fewer tiles than one round of resident workgroups: split K into the
     // chunk count that minimises rounds x (chunk length + a per-workgroup
     // overhead worth 256 of K)
-    const int64_t smax = std::min<int64_t>(K / 256, 64);
+    const int64_t smax = std::min<int64_t>(K / 64, 64);
     double best = (double)K + 256.0;
     for (int64_t sp = 2; sp <= smax; ++sp) {
       const double rounds = (double)((tiles * sp + slots - 1) / slots);
