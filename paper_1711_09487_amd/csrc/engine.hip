@@ -15,6 +15,29 @@
 
 namespace rfd {
 
+// Z = X_re + X_im (rows x cols per item).
+__global__ void k_plane_sum(DMat<double> X, DMat<double> Z, int64_t rows, int64_t cols) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e % rows, j = e / rows;
+  const DMat<double> x = X.item(blockIdx.y), z = Z.item(blockIdx.y);
+  z.re[i + j * z.ld] = x.re[i + j * x.ld] + x.im[i + j * x.ld];
+}
+
+// The rest of R -= S X in Gauss's form, with P1 = S_re X_re, P2 = S_im X_im
+// and R_im already holding Y_im - (S_re + S_im)(X_re + X_im):
+// R_re += P2 - P1, R_im += P1 + P2.
+__global__ void k_gauss_combine(DMat<double> Rm, DMat<double> P1, DMat<double> P2, int64_t rows,
+                                int64_t cols) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e % rows, j = e / rows;
+  const DMat<double> r = Rm.item(blockIdx.y), a = P1.item(blockIdx.y), c = P2.item(blockIdx.y);
+  const double p1 = a.re[i + j * a.ld], p2 = c.re[i + j * c.ld];
+  r.re[i + j * r.ld] += p2 - p1;
+  r.im[i + j * r.ld] += p1 + p2;
+}
+
 template <typename T>
 static void upload(DevBuf& b, const std::vector<T>& v) {
   b.alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
@@ -159,6 +182,8 @@ int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, i
   const int64_t k = p * VB + (int64_t)psi * mu;
   int64_t b = chunk * per_pole;                                   // shifted blocks, Schur solves
   b += SP * SP * n_c * 16 + (f32 ? SP * SP * n_c * 8 : 0);        // S (FP64, FP32 copy)
+  if (f32 && SP * SP * n_c * 8 <= EngineImpl::GAUSS_MAX_BYTES)
+    b += SP * SP * n_c * 8 + SP * round_up(std::max(m, 1), NB) * n_c * 24;  // S_re + S_im, P1 P2 X sum
   b += (int64_t)NB * 2 * SP * n_c * 2 * es;                       // S block inverses
   b += SP * MP * n_c * (f32 ? 16 + 16 + 8 : 16);                  // filter right-hand sides
   b += e.s * (mu + m) * 8 * 3;                                    // interface basis, orth work
@@ -260,6 +285,7 @@ PhaseTimer::~PhaseTimer() {
 
 std::vector<DevBuf*> EngineImpl::solve_buffers() {
   std::vector<DevBuf*> v{&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32,
+                         &Ssum, &Xsum, &Pg,
                          &Sinv32, &Sinv64, &Swide, &Swork, &Yc, &Xf, &Rf, &Rf32, &W, &Qint, &Vb, &Bs, &Bsinv,
                          &Bspiv, &Bswide, &Bswork, &Lev, &Zt, &work1, &work2, &work3, &work4, &work5, &work6,
                          &ipiv_small, &iscal, &gwork, &work6b, &rr_az, &rr_h, &ow.V, &ow.T,
@@ -483,6 +509,17 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
     DMat<float> Si{Sinv32.as<float>(), Sinv32.as<float>() + (int64_t)NB * 2 * SP * nc, NB,
                    (int64_t)NB * 2 * SP};
     convert<float, double>(st, S, S3, SP, SP, nc);
+    // the refinement residual takes three real products instead of four
+    // when S_re + S_im fits in GAUSS_MAX_BYTES
+    gauss3 = sbytes <= GAUSS_MAX_BYTES;
+    if (gauss3) {
+      Ssum.alloc(sbytes);
+      DMat<double> Sz{Ssum.as<double>(), nullptr, SP, SP * SP};
+      k_plane_sum<<<dim3(grid1(SP * SP), nc), 256, 0, st>>>(S, Sz, SP, SP);
+      RFD_CHECK_LAUNCH();
+    } else {
+      Ssum.release();
+    }
     lu_nopiv<float>(st, S3, SP, nc, Si, flags.as<unsigned>(), 1e-30);
     wide_inverses<float>(st, S3, Si, nc);
     // the interior factors are no longer needed; large ones are released
@@ -536,7 +573,11 @@ int EngineImpl::pole_window(int m) const {
   const double avail = 0.8 * ((double)fr + (double)bytes_held());
   int w = (max_window > 0) ? std::min(max_window, nc) : nc;
   auto need = [&](int wn) {
-    return (double)wn * per_pole + (double)std::min(pole_chunk(), wn) * per_chunk_pole;
+    double b = (double)wn * per_pole + (double)std::min(pole_chunk(), wn) * per_chunk_pole;
+    // S_re + S_im and the three-product work of the FP32 refinement
+    if (f32 && SP * SP * (int64_t)wn * 8 <= GAUSS_MAX_BYTES)
+      b += (double)wn * (SP * SP * 8 + SP * MP * 24);
+    return b;
   };
   while (w > 1 && need(w) > avail) --w;
   return w;
@@ -562,7 +603,8 @@ void EngineImpl::run_filter(hipStream_t st, const double* Y, int64_t ldy, int m,
   // only the last window's factors would remain: they are released, making
   // room for the interior part (the next application factors again)
   RFD_HIP(hipStreamSynchronize(st));
-  for (DevBuf* b : {&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32, &Sinv32,
+  for (DevBuf* b : {&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32, &Ssum,
+                    &Xsum, &Pg, &Sinv32,
                     &Sinv64, &Swide, &Swork, &Yc, &Xf, &Rf, &Rf32})
     b->release();
   factored = false;
@@ -602,15 +644,32 @@ void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int 
                       solve_work<float>(MP, nc));
       add_to<double, float>(st, R3, X, SP, MP, nc);
       broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);
-      // R = Y - S_64 X as four real products on the planes (large real FP64
-      // products run on rocBLAS)
+      // R = Y - S_64 X as real products on the planes (large real FP64
+      // products run on rocBLAS): three in Gauss's form when S_re + S_im is
+      // kept, else four
       {
         auto re = [](DMat<double> a) { a.im = nullptr; return a; };
         auto im = [](DMat<double> a) { a.re = a.im; a.im = nullptr; return a; };
-        gemm<double>(st, false, false, SP, MP, SP, -1.0, re(S), re(X), 1.0, re(Ycm), nc);
-        gemm<double>(st, false, false, SP, MP, SP, 1.0, im(S), im(X), 1.0, re(Ycm), nc);
-        gemm<double>(st, false, false, SP, MP, SP, -1.0, re(S), im(X), 1.0, im(Ycm), nc);
-        gemm<double>(st, false, false, SP, MP, SP, -1.0, im(S), re(X), 1.0, im(Ycm), nc);
+        if (gauss3) {
+          Xsum.alloc(ys * sizeof(double));
+          Pg.alloc(2 * ys * sizeof(double));
+          DMat<double> Sz{Ssum.as<double>(), nullptr, SP, SP * SP};
+          DMat<double> Xz{Xsum.as<double>(), nullptr, SP, SP * MP};
+          DMat<double> P1{Pg.as<double>(), nullptr, SP, SP * MP};
+          DMat<double> P2{Pg.as<double>() + ys, nullptr, SP, SP * MP};
+          k_plane_sum<<<dim3(grid1(SP * MP), nc), 256, 0, st>>>(X, Xz, SP, MP);
+          RFD_CHECK_LAUNCH();
+          gemm<double>(st, false, false, SP, MP, SP, 1.0, re(S), re(X), 0.0, P1, nc);
+          gemm<double>(st, false, false, SP, MP, SP, 1.0, im(S), im(X), 0.0, P2, nc);
+          gemm<double>(st, false, false, SP, MP, SP, -1.0, Sz, Xz, 1.0, im(Ycm), nc);
+          k_gauss_combine<<<dim3(grid1(SP * MP), nc), 256, 0, st>>>(Ycm, P1, P2, SP, MP);
+          RFD_CHECK_LAUNCH();
+        } else {
+          gemm<double>(st, false, false, SP, MP, SP, -1.0, re(S), re(X), 1.0, re(Ycm), nc);
+          gemm<double>(st, false, false, SP, MP, SP, 1.0, im(S), im(X), 1.0, re(Ycm), nc);
+          gemm<double>(st, false, false, SP, MP, SP, -1.0, re(S), im(X), 1.0, im(Ycm), nc);
+          gemm<double>(st, false, false, SP, MP, SP, -1.0, im(S), re(X), 1.0, im(Ycm), nc);
+        }
       }
       zero_scalar(st, 0);
       absmax<double>(st, Ycm, SP, MP, nc, scal.as<double>());

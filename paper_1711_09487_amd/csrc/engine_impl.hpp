@@ -65,6 +65,11 @@ struct EngineImpl {
   DevBuf Swide, Swork;  // inverses of the SLW-wide diagonal blocks of S's factors, workspace
   int SLW = 0;
   DevBuf Yc, Xf, Rf, Rf32, W;
+  // FP32 mode: S_re + S_im per pole, for the refinement residual in Gauss's
+  // three-product form (kept when it takes at most GAUSS_MAX_BYTES)
+  DevBuf Ssum, Xsum, Pg;
+  bool gauss3 = false;
+  static constexpr int64_t GAUSS_MAX_BYTES = int64_t(4) << 30;
   OrthWork ow;
   // interface basis
   DevBuf Qint;
