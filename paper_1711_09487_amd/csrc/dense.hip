@@ -300,8 +300,11 @@ __device__ __forceinline__ void tri_inverses(T (*F)[NB][NB + 1], T (*X)[NB][NB +
 // passed by shuffles, no barrier per column), then 16 threads solve the
 // block row of U right of the panel and all threads update the trailing
 // block.
+// (complex FP32: two workgroups per CU fit in shared memory; the bound keeps
+// the registers within two waves per SIMD as well, for the 512-item batches)
 template <typename T, bool CPLX>
-__global__ __launch_bounds__(256) void k_lu_diag(DMat<T> A, int64_t k0, DMat<T> inv, int iblk,
+__global__ __launch_bounds__(256, (CPLX && sizeof(T) == 4) ? 2 : 1) void k_lu_diag(
+    DMat<T> A, int64_t k0, DMat<T> inv, int iblk,
                                                  unsigned* flags, T tiny, int* drop, T droptol) {
   constexpr int NP = CPLX ? 2 : 1;
   constexpr int PW = 16;
