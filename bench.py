@@ -397,9 +397,9 @@ def main():
                          "the HBM byte counters of a profiler)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X "
-              "(see the design notes for how the path would shard); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the whole path on a single "
+              "MI355X (the path would shard by pole, with one all-reduce of the filtered "
+              "block per step); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1711_09487_amd as R
