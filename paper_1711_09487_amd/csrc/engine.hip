@@ -136,11 +136,14 @@ Engine::~Engine() {
     e.join_prepare();
   } catch (...) {
   }
-  for (hipStream_t ps : {e.prep_stream, e.prep_stream2})
+  if (e.h_stream) (void)hipStreamSynchronize(e.h_stream);
+  for (hipStream_t ps : {e.prep_stream, e.prep_stream2, e.h_stream})
     if (ps) {
       release_stream_resources(ps);
       (void)hipStreamDestroy(ps);
     }
+  for (hipEvent_t ev : {e.h_lvl, e.h_done})
+    if (ev) (void)hipEventDestroy(ev);
 }
 
 void Engine::set_poles(const Poles& poles) {

@@ -98,6 +98,15 @@ struct EngineImpl {
   DevBuf work1, work2, work3, work4, work5, work6;
   DevBuf ipiv_small, iscal, gwork, work6b;
   DevBuf rr_az, rr_h;   // Rayleigh-Ritz: A Z and the projected matrix
+  // H = Z^T A Z assembled on a helper stream while Z is built: each finished
+  // block of columns adds its rows (lower triangle, ld h_ld); h_ready marks
+  // an H for the current basis of h_k columns (the eigensolver overwrites it)
+  hipStream_t h_stream = nullptr;
+  hipEvent_t h_lvl = nullptr, h_done = nullptr;
+  bool h_ready = false;
+  int64_t h_ld = 0, h_k = 0;
+  void h_begin();
+  void h_add_block(hipStream_t st, int64_t c0, int64_t r);
   DevBuf tmp[24];       // small per-call buffers, kept to avoid device-wide frees
   TriWork tw_v, tw_h;   // eigensolver work: subdomain blocks, projected matrix
   PhaseTimer timer;

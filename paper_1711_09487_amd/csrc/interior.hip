@@ -662,6 +662,82 @@ void EngineImpl::project_out(hipStream_t st, double* X, int ncols, double* MX, c
   }
 }
 
+// The helper stream and its events (created on first use, on the caller's
+// device); earlier work on it is finished before its buffers are reused.
+void EngineImpl::h_begin() {
+  if (!h_stream) {
+    RFD_HIP(hipStreamCreateWithFlags(&h_stream, hipStreamNonBlocking));
+    RFD_HIP(hipEventCreateWithFlags(&h_lvl, hipEventDisableTiming));
+    RFD_HIP(hipEventCreateWithFlags(&h_done, hipEventDisableTiming));
+  }
+  RFD_HIP(hipStreamSynchronize(h_stream));
+  h_ready = false;
+}
+
+// Columns [c0, c0 + r) of Z are final on st: on the helper stream, A Z for
+// them and H's rows c0 .. c0 + r - 1 up to the block's diagonal.  The
+// deflation columns (c0 = 0, r = kappa_tot) give the block-diagonal H_vv (one
+// kappa_j block per subdomain, their interior rows only); a level block gives
+// its rows against the deflation columns ((A Z_blk)^T Z_v, the subdomain's
+// rows only, as interiors couple through the interface alone) and against the
+// level columns so far (Z_blk^T A Z).
+void EngineImpl::h_add_block(hipStream_t st, int64_t c0, int64_t r) {
+  if (r <= 0) return;
+  RFD_HIP(hipEventRecord(h_lvl, st));
+  RFD_HIP(hipStreamWaitEvent(h_stream, h_lvl, 0));
+  hipStream_t s2 = h_stream;
+  double* Z = Zt.as<double>();
+  double* AZ = rr_az.as<double>();
+  double* H = rr_h.as<double>();
+  const int64_t ld = h_ld, kv = kappa_tot;
+  csr_mm(s2, Arptr, Aridx, Arval, n, Z + c0 * n, n, AZ + c0 * n, n, r);
+  DMat<double> Zm{Z, nullptr, n, 0}, AZm{AZ, nullptr, n, 0}, Hm{H, nullptr, ld, 0};
+  bool uniform = true;
+  for (int j = 1; j < p && uniform; ++j)
+    uniform = P->interior[j].size() == P->interior[0].size() && kappa[j] == kappa[0];
+  if (c0 < kv) {
+    fill<double>(s2, Hm, kv, kv, 1, 0.0);
+    if (uniform) {
+      const int64_t d = (int64_t)P->interior[0].size(), kj = kappa[0];
+      DMat<double> Zb{Z, nullptr, n, d + kj * n}, AZb{AZ, nullptr, n, d + kj * n};
+      DMat<double> Hvv{H, nullptr, ld, kj + kj * ld};
+      gemm<double>(s2, true, false, kj, kj, d, 1.0, Zb, AZb, 0.0, Hvv, p);
+    } else {
+      int64_t off = 0, kof = 0;
+      for (int j = 0; j < p; ++j) {
+        const int64_t d = (int64_t)P->interior[j].size(), kj = kappa[j];
+        if (kj > 0)
+          gemm<double>(s2, true, false, kj, kj, d, 1.0, Zm.sub(off, kof), AZm.sub(off, kof), 0.0,
+                       Hm.sub(kof, kof), 1);
+        off += d;
+        kof += kj;
+      }
+    }
+    return;
+  }
+  if (kv > 0) {
+    if (uniform) {
+      const int64_t d = (int64_t)P->interior[0].size(), kj = kappa[0];
+      DMat<double> Zb{Z, nullptr, n, d + kj * n};
+      DMat<double> AZl{AZ + c0 * n, nullptr, n, d};
+      DMat<double> Hlv{H + c0, nullptr, ld, kj * ld};
+      gemm<double>(s2, true, false, r, kj, d, 1.0, AZl, Zb, 0.0, Hlv, p);
+    } else {
+      int64_t off = 0, kof = 0;
+      for (int j = 0; j < p; ++j) {
+        const int64_t d = (int64_t)P->interior[j].size(), kj = kappa[j];
+        if (kj > 0)
+          gemm<double>(s2, true, false, r, kj, d, 1.0, AZm.sub(off, c0), Zm.sub(off, kof), 0.0,
+                       Hm.sub(c0, kof), 1);
+        off += d;
+        kof += kj;
+      }
+    }
+  }
+  gemm<double>(s2, true, false, r, c0 + r - kv, n, 1.0, Zm.sub(0, c0), AZm.sub(0, kv), 0.0,
+               Hm.sub(c0, kv), 1);
+}
+
 void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64_t* kout) {
   EngineImpl& e = *d_;
   e.join_prepare();
@@ -746,9 +822,13 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   // M-orthonormal basis of range(Z): [V | levels orthonormalised level by level]
   e.timer.begin(st, 9);
   const int64_t kmax = e.kappa_tot + (int64_t)psi * mu;
+  e.h_begin();
   e.Zt.alloc(sizeof(double) * n * std::max<int64_t>(kmax, 1));
   double* Z = e.Zt.as<double>();
   RFD_HIP(hipMemsetAsync(Z, 0, sizeof(double) * n * std::max<int64_t>(kmax, 1), st));
+  e.h_ld = std::max<int64_t>(kmax, 1);
+  e.rr_az.alloc(sizeof(double) * n * e.h_ld);
+  e.rr_h.alloc(sizeof(double) * e.h_ld * e.h_ld);
   std::vector<int32_t> koff(p, 0), ioff(p + 1, 0);
   for (int j = 0; j < p; ++j) {
     koff[j] = (j ? koff[j - 1] + e.kappa[j - 1] : 0);
@@ -762,6 +842,7 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
                                                           koff_d.as<int32_t>(),
                                                           kap_d2.as<int32_t>(), e.dj.as<int32_t>(), D);
     RFD_CHECK_LAUNCH();
+    e.h_add_block(st, 0, e.kappa_tot);
   }
   e.work5.alloc(sizeof(double) * n * (int64_t)mu * 2);
   double* Lb = e.work5.as<double>();             // current level block (n x mu)
@@ -797,9 +878,13 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
     RFD_HIP(hipMemcpyAsync(Z + kz * n, Lb, sizeof(double) * n * r2, hipMemcpyDeviceToDevice, st));
     if (r2 < r)
       RFD_HIP(hipMemsetAsync(Z + (kz + r2) * n, 0, sizeof(double) * n * (r - r2), st));
+    e.h_add_block(st, kz, r2);
     kz += r2;
   }
   e.kz = kz;
+  RFD_HIP(hipEventRecord(e.h_done, e.h_stream));
+  e.h_ready = true;
+  e.h_k = kz;
   e.timer.end(st);
   RFD_HIP(hipStreamSynchronize(st));
   e.interior_ready = true;
@@ -816,64 +901,11 @@ void Engine::copy_basis(hipStream_t st, double* dst, int64_t cap, int64_t* k) {
   RFD_HIP(hipStreamSynchronize(st));
 }
 
-void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* evecs,
-                           double* resid, int* nfound) {
-  EngineImpl& e = *d_;
-  e.join_prepare();
-  if (!e.interior_ready) throw Error(ST_ESTATE, "rfd_solve_interior has not been called");
-  const int64_t n = e.n, k = e.kz;
-  *nfound = 0;
-  if (k == 0) return;
-  double* Z = e.Zt.as<double>();
-  // H = Z^T A Z, lower triangle (all the eigensolver reads).  Z = [Zv Zl]:
-  // the kv deflation columns of subdomain j live on its interior rows only,
-  // and interiors couple through the interface alone, so H_vv is block
-  // diagonal (one kappa_j block per subdomain) and H_lv = (A Zl)^T Zv needs
-  // each subdomain's interior rows only; H_ll = Zl^T (A Zl) is dense.
-  e.timer.begin(st, 9);
-  DevBuf& AZ = e.rr_az;
-  DevBuf& Hb = e.rr_h;
-  AZ.alloc(sizeof(double) * n * k);
-  Hb.alloc(sizeof(double) * k * k);
-  csr_mm(st, e.Arptr, e.Aridx, e.Arval, n, Z, n, AZ.as<double>(), n, k);
-  DMat<double> Zm{Z, nullptr, n, 0}, AZm{AZ.as<double>(), nullptr, n, 0}, Hm{Hb.as<double>(), nullptr, k, 0};
-  const int64_t kv = std::min<int64_t>(e.kappa_tot, k), kl = k - kv;
-  bool uniform = kv > 0;
-  for (int j = 1; j < e.p && uniform; ++j)
-    uniform = e.P->interior[j].size() == e.P->interior[0].size() && e.kappa[j] == e.kappa[0];
-  if (uniform) {
-    // one batched product per block over the subdomains (item j: rows j d,
-    // deflation columns j kj)
-    fill<double>(st, Hm, kv, kv, 1, 0.0);
-    const int64_t d = (int64_t)e.P->interior[0].size(), kj = e.kappa[0];
-    DMat<double> Zb{Z, nullptr, n, d + kj * n}, AZb{AZ.as<double>(), nullptr, n, d + kj * n};
-    DMat<double> Hvv{Hb.as<double>(), nullptr, k, kj + kj * k};
-    gemm<double>(st, true, false, kj, kj, d, 1.0, Zb, AZb, 0.0, Hvv, e.p);
-    if (kl > 0) {
-      DMat<double> AZl{AZ.as<double>() + kv * n, nullptr, n, d};
-      DMat<double> Hlv{Hb.as<double>() + kv, nullptr, k, kj * k};
-      gemm<double>(st, true, false, kl, kj, d, 1.0, AZl, Zb, 0.0, Hlv, e.p);
-    }
-  } else if (kv > 0) {
-    fill<double>(st, Hm, kv, kv, 1, 0.0);
-    int64_t off = 0, kof = 0;
-    for (int j = 0; j < e.p; ++j) {
-      const int64_t d = (int64_t)e.P->interior[j].size(), kj = e.kappa[j];
-      if (kj > 0) {
-        DMat<double> Zj = Zm.sub(off, kof), AZj = AZm.sub(off, kof);
-        gemm<double>(st, true, false, kj, kj, d, 1.0, Zj, AZj, 0.0, Hm.sub(kof, kof), 1);
-        if (kl > 0)
-          gemm<double>(st, true, false, kl, kj, d, 1.0, AZm.sub(off, kv), Zj, 0.0,
-                       Hm.sub(kv, kof), 1);
-      }
-      off += d;
-      kof += kj;
-    }
-  }
-  if (kl > 0)
-    gemm<double>(st, true, false, kl, kl, n, 1.0, Zm.sub(0, kv), AZm.sub(0, kv), 0.0,
-                 Hm.sub(kv, kv), 1);
-  e.timer.end(st);
+// Eigenpairs of H (lower triangle, k x k, overwritten) in [alpha, beta], the
+// Ritz vectors Z G in the original numbering, their residuals.
+static void rr_eigen(EngineImpl& e, hipStream_t st, DMat<double> Hm, DMat<double> Zm, int64_t k,
+                     int max_out, double* evals, double* evecs, double* resid, int* nfound) {
+  const int64_t n = e.n;
   // eigenpairs of H in [alpha, beta]
   e.timer.begin(st, 10);
   TriWork& tw = e.tw_h;
@@ -935,6 +967,78 @@ void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* e
   }
   e.timer.end(st);
   RFD_HIP(hipStreamSynchronize(st));
+}
+
+void Engine::rayleigh_ritz(hipStream_t st, int max_out, double* evals, double* evecs,
+                           double* resid, int* nfound) {
+  EngineImpl& e = *d_;
+  e.join_prepare();
+  if (!e.interior_ready) throw Error(ST_ESTATE, "rfd_solve_interior has not been called");
+  const int64_t n = e.n, k = e.kz;
+  *nfound = 0;
+  if (k == 0) return;
+  double* Z = e.Zt.as<double>();
+  // H = Z^T A Z, lower triangle (all the eigensolver reads).  Z = [Zv Zl]:
+  // the kv deflation columns of subdomain j live on its interior rows only,
+  // and interiors couple through the interface alone, so H_vv is block
+  // diagonal (one kappa_j block per subdomain) and H_lv = (A Zl)^T Zv needs
+  // each subdomain's interior rows only; H_ll = Zl^T (A Zl) is dense.
+  DMat<double> Zm{Z, nullptr, n, 0};
+  if (e.h_ready && e.h_k == k) {
+    // assembled beside the construction of Z; used once (the eigensolver
+    // overwrites it, a later call forms it again below)
+    RFD_HIP(hipStreamWaitEvent(st, e.h_done, 0));
+    e.h_ready = false;
+    rr_eigen(e, st, DMat<double>{e.rr_h.as<double>(), nullptr, e.h_ld, 0}, Zm, k, max_out, evals,
+             evecs, resid, nfound);
+    return;
+  }
+  e.h_ready = false;
+  e.timer.begin(st, 9);
+  DevBuf& AZ = e.rr_az;
+  DevBuf& Hb = e.rr_h;
+  AZ.alloc(sizeof(double) * n * k);
+  Hb.alloc(sizeof(double) * k * k);
+  csr_mm(st, e.Arptr, e.Aridx, e.Arval, n, Z, n, AZ.as<double>(), n, k);
+  DMat<double> AZm{AZ.as<double>(), nullptr, n, 0}, Hm{Hb.as<double>(), nullptr, k, 0};
+  const int64_t kv = std::min<int64_t>(e.kappa_tot, k), kl = k - kv;
+  bool uniform = kv > 0;
+  for (int j = 1; j < e.p && uniform; ++j)
+    uniform = e.P->interior[j].size() == e.P->interior[0].size() && e.kappa[j] == e.kappa[0];
+  if (uniform) {
+    // one batched product per block over the subdomains (item j: rows j d,
+    // deflation columns j kj)
+    fill<double>(st, Hm, kv, kv, 1, 0.0);
+    const int64_t d = (int64_t)e.P->interior[0].size(), kj = e.kappa[0];
+    DMat<double> Zb{Z, nullptr, n, d + kj * n}, AZb{AZ.as<double>(), nullptr, n, d + kj * n};
+    DMat<double> Hvv{Hb.as<double>(), nullptr, k, kj + kj * k};
+    gemm<double>(st, true, false, kj, kj, d, 1.0, Zb, AZb, 0.0, Hvv, e.p);
+    if (kl > 0) {
+      DMat<double> AZl{AZ.as<double>() + kv * n, nullptr, n, d};
+      DMat<double> Hlv{Hb.as<double>() + kv, nullptr, k, kj * k};
+      gemm<double>(st, true, false, kl, kj, d, 1.0, AZl, Zb, 0.0, Hlv, e.p);
+    }
+  } else if (kv > 0) {
+    fill<double>(st, Hm, kv, kv, 1, 0.0);
+    int64_t off = 0, kof = 0;
+    for (int j = 0; j < e.p; ++j) {
+      const int64_t d = (int64_t)e.P->interior[j].size(), kj = e.kappa[j];
+      if (kj > 0) {
+        DMat<double> Zj = Zm.sub(off, kof), AZj = AZm.sub(off, kof);
+        gemm<double>(st, true, false, kj, kj, d, 1.0, Zj, AZj, 0.0, Hm.sub(kof, kof), 1);
+        if (kl > 0)
+          gemm<double>(st, true, false, kl, kj, d, 1.0, AZm.sub(off, kv), Zj, 0.0,
+                       Hm.sub(kv, kof), 1);
+      }
+      off += d;
+      kof += kj;
+    }
+  }
+  if (kl > 0)
+    gemm<double>(st, true, false, kl, kl, n, 1.0, Zm.sub(0, kv), AZm.sub(0, kv), 0.0,
+                 Hm.sub(kv, kv), 1);
+  e.timer.end(st);
+  rr_eigen(e, st, Hm, Zm, k, max_out, evals, evecs, resid, nfound);
 }
 
 }  // namespace rfd
