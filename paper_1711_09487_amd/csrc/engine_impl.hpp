@@ -103,9 +103,9 @@ struct EngineImpl {
   // an H for the current basis of h_k columns (the eigensolver overwrites it)
   hipStream_t h_stream = nullptr;
   hipEvent_t h_lvl = nullptr, h_done = nullptr;
-  bool h_ready = false;
+  bool h_ready = false, h_use = false;
   int64_t h_ld = 0, h_k = 0;
-  void h_begin();
+  void h_begin(bool use);
   void h_add_block(hipStream_t st, int64_t c0, int64_t r);
   DevBuf tmp[24];       // small per-call buffers, kept to avoid device-wide frees
   TriWork tw_v, tw_h;   // eigensolver work: subdomain blocks, projected matrix

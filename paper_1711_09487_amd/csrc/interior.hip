@@ -664,14 +664,19 @@ void EngineImpl::project_out(hipStream_t st, double* X, int ncols, double* MX, c
 
 // The helper stream and its events (created on first use, on the caller's
 // device); earlier work on it is finished before its buffers are reused.
-void EngineImpl::h_begin() {
+// Small bases (A Z under 2^24 entries) form H in the Rayleigh-Ritz call
+// instead: their blocks are too small to gain from the overlap, and a stream
+// per engine would crowd the hardware queues that concurrent engines share.
+void EngineImpl::h_begin(bool use) {
+  h_ready = false;
+  h_use = use;
+  if (h_stream) RFD_HIP(hipStreamSynchronize(h_stream));
+  if (!use) return;
   if (!h_stream) {
     RFD_HIP(hipStreamCreateWithFlags(&h_stream, hipStreamNonBlocking));
     RFD_HIP(hipEventCreateWithFlags(&h_lvl, hipEventDisableTiming));
     RFD_HIP(hipEventCreateWithFlags(&h_done, hipEventDisableTiming));
   }
-  RFD_HIP(hipStreamSynchronize(h_stream));
-  h_ready = false;
 }
 
 // Columns [c0, c0 + r) of Z are final on st: on the helper stream, A Z for
@@ -682,7 +687,7 @@ void EngineImpl::h_begin() {
 // rows only, as interiors couple through the interface alone) and against the
 // level columns so far (Z_blk^T A Z).
 void EngineImpl::h_add_block(hipStream_t st, int64_t c0, int64_t r) {
-  if (r <= 0) return;
+  if (r <= 0 || !h_use) return;
   RFD_HIP(hipEventRecord(h_lvl, st));
   RFD_HIP(hipStreamWaitEvent(h_stream, h_lvl, 0));
   hipStream_t s2 = h_stream;
@@ -822,13 +827,15 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   // M-orthonormal basis of range(Z): [V | levels orthonormalised level by level]
   e.timer.begin(st, 9);
   const int64_t kmax = e.kappa_tot + (int64_t)psi * mu;
-  e.h_begin();
+  e.h_begin(n * std::max<int64_t>(kmax, 1) >= (int64_t(1) << 24));
   e.Zt.alloc(sizeof(double) * n * std::max<int64_t>(kmax, 1));
   double* Z = e.Zt.as<double>();
   RFD_HIP(hipMemsetAsync(Z, 0, sizeof(double) * n * std::max<int64_t>(kmax, 1), st));
-  e.h_ld = std::max<int64_t>(kmax, 1);
-  e.rr_az.alloc(sizeof(double) * n * e.h_ld);
-  e.rr_h.alloc(sizeof(double) * e.h_ld * e.h_ld);
+  if (e.h_use) {
+    e.h_ld = std::max<int64_t>(kmax, 1);
+    e.rr_az.alloc(sizeof(double) * n * e.h_ld);
+    e.rr_h.alloc(sizeof(double) * e.h_ld * e.h_ld);
+  }
   std::vector<int32_t> koff(p, 0), ioff(p + 1, 0);
   for (int j = 0; j < p; ++j) {
     koff[j] = (j ? koff[j - 1] + e.kappa[j - 1] : 0);
@@ -882,9 +889,11 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
     kz += r2;
   }
   e.kz = kz;
-  RFD_HIP(hipEventRecord(e.h_done, e.h_stream));
-  e.h_ready = true;
-  e.h_k = kz;
+  if (e.h_use) {
+    RFD_HIP(hipEventRecord(e.h_done, e.h_stream));
+    e.h_ready = true;
+    e.h_k = kz;
+  }
   e.timer.end(st);
   RFD_HIP(hipStreamSynchronize(st));
   e.interior_ready = true;
