@@ -93,9 +93,9 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
                                                   int j, const double* tol_abs, double* cn,
                                                   int* used, int* piv, double* tau, double* V,
                                                   int64_t ldv, int* rank) {
-  __shared__ double red[256];
-  __shared__ int ired[256];
-  __shared__ double sv[256];
+  __shared__ double red[8];  // two sums of four wavefront partials
+  __shared__ int ired[4];    // pivot candidates of the four wavefronts
+  __shared__ double sv[4];
   const int c = blockIdx.x, t = threadIdx.x;
   const int cur = j & 1, nxt = cur ^ 1;
   const double* cnc = cn + (int64_t)cur * m;
