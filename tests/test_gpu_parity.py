@@ -306,3 +306,33 @@ def test_mode_switch_refactors():
     W1 = P.filter_apply(_dev_block(torch, prob.Y0)).cpu().numpy()
     P.close()
     assert np.max(np.abs(W0 - W1)) < 1e-11 * np.max(np.abs(W0))
+
+
+def test_block_assembled_rayleigh_ritz_matrix_on_uneven_subdomains():
+    """For a large basis (A Z of at least 2^24 entries) H = Z^T A Z is
+    assembled block by block on a helper stream while Z is built; a second
+    Rayleigh-Ritz call forms H directly from Z.  On a partition with uneven
+    subdomains (27 and 28 grid lines, so the per-subdomain deflation blocks
+    differ in size) both give the same Ritz values and residuals."""
+    torch = _torch()
+    prob = W.tiny(N=200, P=7, nev=20, n_c=4, m=60, steps=2, nev_b=10, psi=4, cfg_id=48)
+    sizes = np.bincount(prob.part[prob.part >= 0])
+    assert sizes.min() < sizes.max()                      # uneven interiors
+    P = _pencil(prob, 0)
+    P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
+    k = P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+    assert prob.A.shape[0] * k >= 1 << 24                 # the block-assembled path
+    ev1, _, r1 = P.rayleigh_ritz(prob.nev + 10)
+    ev2, _, r2 = P.rayleigh_ritz(prob.nev + 10)
+    torch.cuda.synchronize()
+    a, b = ev1.cpu().numpy(), ev2.cpu().numpy()
+    ra, rb = r1.cpu().numpy(), r2.cpu().numpy()
+    P.close()
+    assert a.size == b.size == prob.nev
+    assert np.max(np.abs(a - b) / np.abs(b)) <= 1e-12
+    assert np.max(np.abs(ra - rb)) <= 1e-10 * max(1.0, np.max(rb))
+    # Ritz values of a compression of (A, I) bound the exact eigenvalues of the
+    # same rank from above (Courant-Fischer; closed form for M = I)
+    lam = np.asarray(prob.exact)[:prob.nev]
+    assert np.all((a >= prob.alpha) & (a <= prob.beta))
+    assert np.all(a >= lam * (1.0 - 1e-12))
