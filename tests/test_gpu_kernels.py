@@ -153,6 +153,34 @@ def test_lu_breakdown_flag():
     assert flags.value != 0
 
 
+def test_symmetric_eigensolver_beyond_the_staged_tridiagonal():
+    """n above 4096: the Sturm counts and the bisection read the tridiagonal
+    from global memory (smaller ones stage it in shared memory).  A is built
+    from known eigenvalues, A = Q diag(lam) Q^T, so no dense reference solve
+    is needed; the tolerances allow for the rounding of that construction."""
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    n, num = 4100, 16
+    rs = np.random.default_rng(11)
+    Q, _ = np.linalg.qr(rs.standard_normal((n, n)))
+    lam = np.sort(rs.uniform(-2, 3, n))
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    At = torch.from_numpy(A.reshape(1, n, n).copy()).cuda()
+    lam_d = torch.zeros(num, dtype=torch.float64, device="cuda")
+    Y_d = torch.zeros(num * n, dtype=torch.float64, device="cuda")
+    code = R.lib().rfd_test_syevx(n, 1, At.data_ptr(), 0, num, lam_d.data_ptr(), Y_d.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+    assert code == 0, R.rfd_last_error()
+    torch.cuda.synchronize()
+    got = lam_d.cpu().numpy()
+    X = Y_d.cpu().numpy().reshape(num, n).T
+    nrm = np.abs(lam).max()
+    assert np.max(np.abs(got - lam[:num])) <= 1e-11 * nrm
+    assert np.max(np.abs(A @ X - X * got)) <= 1e-11 * nrm
+    assert np.max(np.abs(X.T @ X - np.eye(num))) <= 1e-11
+
+
 @pytest.mark.parametrize("n,batch,lo,num", [(100, 3, 5, 20), (77, 2, 0, 30), (40, 1, 0, 40),
                                              (300, 2, 10, 40), (517, 1, 100, 30)])
 def test_symmetric_eigensolver(n, batch, lo, num):
