@@ -172,6 +172,11 @@ rfd_status rfd_prepare_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b
  * eqs. (5.2)-(5.4) with B_sigma = B_j - sigma M_Bj; every level is made
  * M_Bj-orthogonal to V_j before the next one is formed (this leaves range(Z)
  * unchanged because V_j is part of Z).  Z of eq. (5.5) stays on the device.
+ * For a large basis (A Z of 2^24 entries or more) the projected matrix
+ * Z^T A Z of rfd_rayleigh_ritz is assembled block by block on a library
+ * stream while Z is built, and may still be in progress when this call
+ * returns; rfd_rayleigh_ritz waits for it on its own stream, and any later
+ * call that reuses the pencil's buffers waits for it first.
  *   k_out   host out: number of columns of Z
  * Errors: RFD_ESTATE without a Q, RFD_EINVAL for nev_b < 0 or psi < 1,
  * RFD_EBREAKDOWN if B_sigma is singular to working precision.
