@@ -208,6 +208,9 @@ void Engine::reset_caches(bool release) {
   e.vcache_valid = false;
   e.bs_valid = false;
   e.interior_ready = false;
+  // the projected matrix may still be assembling on the helper stream
+  if (e.h_stream) RFD_HIP(hipStreamSynchronize(e.h_stream));
+  e.h_ready = false;
   if (!release) return;
   for (DevBuf* b : e.solve_buffers()) b->release();
   e.tw_v.cap = e.tw_h.cap = 0;
