@@ -336,3 +336,27 @@ def test_block_assembled_rayleigh_ritz_matrix_on_uneven_subdomains():
     lam = np.asarray(prob.exact)[:prob.nev]
     assert np.all((a >= prob.alpha) & (a <= prob.beta))
     assert np.all(a >= lam * (1.0 - 1e-12))
+
+
+def test_release_while_the_projected_matrix_is_assembling():
+    """Freeing the pencil's buffers right after rfd_solve_interior of a large
+    basis (while H may still be assembling on the helper stream) is safe; the
+    next solve recomputes everything and gives the same Ritz values."""
+    torch = _torch()
+    prob = W.tiny(N=200, P=7, nev=20, n_c=4, m=60, steps=2, nev_b=10, psi=4, cfg_id=48)
+    P = _pencil(prob, 0)
+    out = []
+    for release in (True, False):
+        P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
+        P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+        if release:
+            P.reset_caches(True)
+            P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
+            P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+        ev, _, _ = P.rayleigh_ritz(prob.nev + 10)
+        torch.cuda.synchronize()
+        out.append(ev.cpu().numpy())
+        P.reset_caches(False)
+    P.close()
+    assert out[0].size == out[1].size == prob.nev
+    assert np.max(np.abs(out[0] - out[1]) / np.abs(out[1])) <= 1e-12
