@@ -161,6 +161,7 @@ struct EngineImpl {
   // Y = M X in the reordered numbering (a row scaling when M is diagonal)
   void apply_m(hipStream_t st, const double* X, int64_t ldx, double* Y, int64_t ldy,
                int64_t cols);
+  void col_mnorms(hipStream_t st, const double* X, int64_t cols, double* MX, double* out);
   void interior_basis(hipStream_t st, double sigma, int nev_b);
   void factor_bsigma(hipStream_t st, double sigma, DevBuf* fl = nullptr, bool check = true);
   int gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,

@@ -80,14 +80,31 @@ __global__ void k_scale_rows(DMat<double> X, int64_t rows, int64_t cols, const d
   x.re[r + c * x.ld] *= vec[(int64_t)blockIdx.y * D + r];
 }
 
-// Y_j[r, c] = vec[j * D + r] * X_j[r, c]
+// The elementwise kernels over tall column blocks below give each thread one
+// row and CG consecutive columns (grid: row blocks x column groups [x items]),
+// so that per-row data is read once and no index is split by division.
+constexpr int CG = 4;
+
+static unsigned col_groups(int64_t cols) {
+  const int64_t g = (cols + CG - 1) / CG;
+  if (g > 65535) throw Error(ST_EINVAL, "too many columns for one launch");
+  return (unsigned)std::max<int64_t>(g, 1);
+}
+
+// Y_j[r, c] = vec[j * D + r] * X_j[r, c]  (items over the z grid dimension)
 __global__ void k_scaled_copy(DMat<double> X, DMat<double> Y, int64_t rows, int64_t cols,
                               const double* vec, int64_t D) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= rows * cols) return;
-  const int64_t r = e % rows, c = e / rows;
-  DMat<double> x = X.item(blockIdx.y), y = Y.item(blockIdx.y);
-  y.re[r + c * y.ld] = vec[(int64_t)blockIdx.y * D + r] * x.re[r + c * x.ld];
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t c0 = (int64_t)blockIdx.y * CG;
+  DMat<double> x = X.item(blockIdx.z), y = Y.item(blockIdx.z);
+  const double f = vec[(int64_t)blockIdx.z * D + r];
+  double v[CG];
+#pragma unroll
+  for (int u = 0; u < CG; ++u) v[u] = c0 + u < cols ? x.re[r + (c0 + u) * x.ld] : 0.0;
+#pragma unroll
+  for (int u = 0; u < CG; ++u)
+    if (c0 + u < cols) y.re[r + (c0 + u) * y.ld] = f * v[u];
 }
 
 // out[c] = || column c of the level over all subdomains ||_{M_B}, one workgroup per column.
@@ -98,9 +115,19 @@ __global__ void k_level_colnorm(DMat<double> X, int p, const int32_t* dj, const 
   double acc = 0;
   for (int j = 0; j < p; ++j) {
     DMat<double> x = X.item(j);
-    for (int64_t r = threadIdx.x; r < dj[j]; r += blockDim.x) {
-      const double v = x.re[r + c * x.ld];
-      acc += md[(int64_t)j * D + r] * v * v;
+    const int64_t dr = dj[j];
+    const double* xc = x.re + c * x.ld;
+    const double* mj = md + (int64_t)j * D;
+    for (int64_t r0 = threadIdx.x; r0 < dr; r0 += 4 * 256) {
+      double v[4], m[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t r = r0 + 256 * u;
+        v[u] = r < dr ? xc[r] : 0.0;
+        m[u] = r < dr ? mj[r] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += m[u] * v[u] * v[u];
     }
   }
   acc = bsum(acc, red);
@@ -111,12 +138,14 @@ __global__ void k_level_colnorm(DMat<double> X, int p, const int32_t* dj, const 
 // a level that lies inside span(V_j) up to rounding carries no direction.
 __global__ void k_level_drop(DMat<double> X, int64_t D, int64_t cols, const double* pre,
                              const double* post, double thr) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= D * cols) return;
-  const int64_t r = e % D, c = e / D;
-  if (!(post[c] > thr * pre[c])) {
-    DMat<double> x = X.item(blockIdx.y);
-    x.re[r + c * x.ld] = 0.0;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  const int64_t c0 = (int64_t)blockIdx.y * CG;
+  DMat<double> x = X.item(blockIdx.z);
+#pragma unroll
+  for (int u = 0; u < CG; ++u) {
+    const int64_t c = c0 + u;
+    if (c < cols && !(post[c] > thr * pre[c])) x.re[r + c * x.ld] = 0.0;
   }
 }
 
@@ -167,10 +196,12 @@ __global__ void k_build_level(double* L, int64_t ldl, DMat<double> Lev, int t, i
     for (int k = threadIdx.x; k <= p; k += blockDim.x) so[k] = ioff[k];
   __syncthreads();
   const int32_t* off = in_lds ? so : ioff;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * mu) return;
-  const int64_t i = e % n, c = e / n;
-  double v = 0;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c0 = (int64_t)blockIdx.y * CG;
+  // the source of row i: its subdomain's level rows, Q's row, or nothing
+  const double* src = nullptr;
+  int64_t lds = 0;
   if (i < n_int) {
     int lo = 0, hi = p;  // off[lo] <= i < off[hi]
     while (hi - lo > 1) {
@@ -179,11 +210,18 @@ __global__ void k_build_level(double* L, int64_t ldl, DMat<double> Lev, int t, i
       else hi = mid;
     }
     DMat<double> x = Lev.item(lo);
-    v = x.re[(i - off[lo]) + (t * MUP + c) * x.ld];
+    src = x.re + (i - off[lo]) + (t * MUP + c0) * x.ld;
+    lds = x.ld;
   } else if (t == 0) {
-    v = Q[(i - n_int) + c * ldq];
+    src = Q + (i - n_int) + c0 * ldq;
+    lds = ldq;
   }
-  L[i + c * ldl] = v;
+  double v[CG];
+#pragma unroll
+  for (int u = 0; u < CG; ++u) v[u] = (src && c0 + u < mu) ? src[u * lds] : 0.0;
+#pragma unroll
+  for (int u = 0; u < CG; ++u)
+    if (c0 + u < mu) L[i + (c0 + u) * ldl] = v[u];
 }
 
 // Y = op X with op a CSR matrix (n x n) (Y, X dense n x cols).  One thread
@@ -237,13 +275,49 @@ static void csr_mm(hipStream_t s, const DevBuf& ptr, const DevBuf& idx, const De
   }
 }
 
-// out[c] = sqrt(x_c^T Y_c) (M-norms with Y = M X), one workgroup per column.
+// out[c] = sqrt(x_c^T Y_c) (M-norms with Y = M X), one workgroup of 256 per
+// column, eight loads of each operand in flight per thread.
 __global__ void k_col_dots(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
                            double* out) {
   __shared__ double red[256];
   const int64_t c = blockIdx.x;
+  const double* x = X + c * ldx;
+  const double* y = Y + c * ldy;
   double acc = 0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += X[i + c * ldx] * Y[i + c * ldy];
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * 256) {
+    double xv[8], yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + 256 * u;
+      xv[u] = i < n ? x[i] : 0.0;
+      yv[u] = i < n ? y[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += xv[u] * yv[u];
+  }
+  acc = bsum(acc, red);
+  if (threadIdx.x == 0) out[c] = sqrt(fmax(acc, 0.0));
+}
+
+// The same M-norms for a diagonal M = diag(dg), from X alone:
+// out[c] = sqrt(sum_i x_i (dg_i x_i)).
+__global__ void k_col_mnorm(const double* dg, const double* X, int64_t ldx, int64_t n,
+                            double* out) {
+  __shared__ double red[256];
+  const int64_t c = blockIdx.x;
+  const double* x = X + c * ldx;
+  double acc = 0;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * 256) {
+    double xv[8], dv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + 256 * u;
+      xv[u] = i < n ? x[i] : 0.0;
+      dv[u] = i < n ? dg[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += xv[u] * (dv[u] * xv[u]);
+  }
   acc = bsum(acc, red);
   if (threadIdx.x == 0) out[c] = sqrt(fmax(acc, 0.0));
 }
@@ -362,13 +436,19 @@ void EngineImpl::ensure_reordered(hipStream_t st) {
   }
 }
 
-// Y[:, c] = dg .* X[:, c]
+// Y[:, c] = dg .* X[:, c] for c < cols
 __global__ void k_diag_scale(const double* dg, int64_t n, const double* X, int64_t ldx, double* Y,
-                             int64_t ldy) {
+                             int64_t ldy, int64_t cols) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const int64_t c = blockIdx.y;
-  Y[r + c * ldy] = dg[r] * X[r + c * ldx];
+  const int64_t c0 = (int64_t)blockIdx.y * CG;
+  const double f = dg[r];
+  double v[CG];
+#pragma unroll
+  for (int u = 0; u < CG; ++u) v[u] = c0 + u < cols ? X[r + (c0 + u) * ldx] : 0.0;
+#pragma unroll
+  for (int u = 0; u < CG; ++u)
+    if (c0 + u < cols) Y[r + (c0 + u) * ldy] = f * v[u];
 }
 
 void EngineImpl::apply_m(hipStream_t st, const double* X, int64_t ldx, double* Y, int64_t ldy,
@@ -378,12 +458,26 @@ void EngineImpl::apply_m(hipStream_t st, const double* X, int64_t ldx, double* Y
     csr_mm(st, Mrptr, Mridx, Mrval, n, X, ldx, Y, ldy, cols);
     return;
   }
-  for (int64_t c = 0; c < cols; c += 65535) {
-    const int64_t cc = std::min<int64_t>(cols - c, 65535);
-    k_diag_scale<<<dim3(grid1(n), (unsigned)cc), 256, 0, st>>>(Mrdiag.as<double>(), n, X + c * ldx,
-                                                              ldx, Y + c * ldy, ldy);
+  for (int64_t c = 0; c < cols; c += (int64_t)CG * 65535) {
+    const int64_t cc = std::min<int64_t>(cols - c, (int64_t)CG * 65535);
+    k_diag_scale<<<dim3(grid1(n), col_groups(cc)), 256, 0, st>>>(
+        Mrdiag.as<double>(), n, X + c * ldx, ldx, Y + c * ldy, ldy, cc);
     RFD_CHECK_LAUNCH();
   }
+}
+
+// out[c] = ||X[:, c]||_M for c < cols (MX: n x cols scratch, used only when M
+// is not diagonal).
+void EngineImpl::col_mnorms(hipStream_t st, const double* X, int64_t cols, double* MX,
+                            double* out) {
+  if (cols <= 0 || n <= 0) return;
+  if (P->m_diag && Mrdiag.p) {
+    k_col_mnorm<<<(unsigned)cols, 256, 0, st>>>(Mrdiag.as<double>(), X, n, n, out);
+  } else {
+    apply_m(st, X, n, MX, n, cols);
+    k_col_dots<<<(unsigned)cols, 256, 0, st>>>(X, n, MX, n, n, out);
+  }
+  RFD_CHECK_LAUNCH();
 }
 
 int64_t EngineImpl::interior_bytes() const {
@@ -806,7 +900,7 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
         RFD_CHECK_LAUNCH();
       }
       for (int pass = 0; pass < 2; ++pass) {
-        k_scaled_copy<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
+        k_scaled_copy<<<dim3(grid1(D), col_groups(MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
         RFD_CHECK_LAUNCH();
         gemm<double>(st, true, false, e.VB, MUP, D, 1.0, Vm, Rh, 0.0, Tm, p);
         gemm<double>(st, false, false, D, MUP, e.VB, -1.0, Vm, Tm, 1.0, X, p);
@@ -814,12 +908,13 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
       if (t > 0) {
         k_level_colnorm<<<MUP, 256, 0, st>>>(X, p, e.dj.as<int32_t>(), md, D, post);
         RFD_CHECK_LAUNCH();
-        k_level_drop<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, D, MUP, pre, post, 1e-10);
+        k_level_drop<<<dim3(grid1(D), col_groups(MUP), p), 256, 0, st>>>(X, D, MUP, pre, post,
+                                                                          1e-10);
         RFD_CHECK_LAUNCH();
       }
     }
     if (t + 1 < psi) {
-      k_scaled_copy<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
+      k_scaled_copy<<<dim3(grid1(D), col_groups(MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
       RFD_CHECK_LAUNCH();
     }
   }
@@ -859,19 +954,15 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   double* n1 = n0 + mu;
   int64_t kz = e.kappa_tot;
   for (int t = 0; t < psi && mu > 0; ++t) {
-    k_build_level<<<grid1(n * mu), 256, 0, st>>>(Lb, n, Lv, t, MUP, e.ioff.as<int32_t>(), p, n_int,
-                                                 n, e.Qint.as<double>(), s, mu);
+    k_build_level<<<dim3(grid1(n), col_groups(mu)), 256, 0, st>>>(
+        Lb, n, Lv, t, MUP, e.ioff.as<int32_t>(), p, n_int, n, e.Qint.as<double>(), s, mu);
     RFD_CHECK_LAUNCH();
     // column M-norms before projection
-    e.apply_m(st, Lb, n, MLb, n, mu);
-    k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n0);
-    RFD_CHECK_LAUNCH();
+    e.col_mnorms(st, Lb, mu, MLb, n0);
     // project against V and the previous level blocks (M-inner product)
     const int64_t kprev = kz - e.kappa_tot;
     e.project_out(st, Lb, mu, MLb, Z + e.kappa_tot * n, kprev, 1);
-    e.apply_m(st, Lb, n, MLb, n, mu);
-    k_col_dots<<<mu, 256, 0, st>>>(Lb, n, MLb, n, n, n1);
-    RFD_CHECK_LAUNCH();
+    e.col_mnorms(st, Lb, mu, MLb, n1);
     k_col_normalize<<<dim3(grid1(n), mu), 256, 0, st>>>(Lb, n, n, n1, n0, 1e-10);
     RFD_CHECK_LAUNCH();
     // block Gram-Schmidt twice with Cholesky QR through the semidefinite
