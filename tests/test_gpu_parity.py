@@ -308,6 +308,33 @@ def test_mode_switch_refactors():
     assert np.max(np.abs(W0 - W1)) < 1e-11 * np.max(np.abs(W0))
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_filter_with_coupled_mass_matches_the_oracle(mode):
+    """A non-diagonal M couples the interface to the interiors (M_E != 0), so
+    the off-diagonal blocks of A - zeta M carry zeta and the Schur complement
+    takes their plain transpose (Sec. 3.1).  The filtered block (eq. (3.5))
+    matches the oracle element by element on nine uneven subdomains with a
+    two-tile interface.  The interior part needs a diagonal M on the GPU and
+    says so instead of computing."""
+    import paper_1711_09487_amd as R
+    torch = _torch()
+    prob = W.tiny(N=27, P=3, nev=6, n_c=4, m=16, steps=1, nev_b=6, psi=2,
+                  mass_kind="coupled", cfg_id=49)
+    dd = O.DD(prob.A, prob.M, prob.part)
+    z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
+    ref = O.filter_apply(O.factor_poles(dd, z), w, prob.Y0)
+    P = _pencil(prob, mode)
+    try:
+        Wg = P.filter_apply(_dev_block(torch, prob.Y0)).cpu().numpy().T
+        err = np.max(np.abs(Wg - ref)) / np.max(np.abs(ref))
+        assert err < (1e-12 if mode == 0 else 1e-11), err
+        P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
+        with pytest.raises(R.RfdError, match="diagonal M"):
+            P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+    finally:
+        P.close()
+
+
 def test_block_assembled_rayleigh_ritz_matrix_on_uneven_subdomains():
     """For a large basis (A Z of at least 2^24 entries) H = Z^T A Z is
     assembled block by block on a helper stream while Z is built; a second
