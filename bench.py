@@ -20,9 +20,11 @@ Beside the headline:
               31x31, 255x255 and two batched-workload pencils, replayed at
               0.5x and 0.8x the measured saturated rate: p50 / p99 latency
               and throughput;
-  roofline -- the FP32 complex GEMM (LU updates and triangular solves of the
-              shifted blocks and of S), timed per launch with HIP events on
-              its own stream over the timed steps;
+  roofline -- the hand-written kernel with the most summed time, the
+              trailing-block mat-vec of the Householder tridiagonalization
+              (HBM-bound), and as roofline_mfma the FP32 complex GEMM (LU
+              updates and triangular solves of the shifted blocks and of S),
+              each timed per launch with HIP events over the timed steps;
   cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp32|fp64|both]
@@ -163,6 +165,9 @@ def roofline_entry(kname, st, f32, steps):
         achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
         e = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
              "kernel": f"{kname} (LU updates and triangular solves)"}
+        if "float, true" in kname:
+            e["flops_counted"] = ("8 per complex multiply-add; the kernel runs three real "
+                                  "products (Gauss), 6 flops on the matrix cores")
     e["frac"] = e["achieved"] / e["peak"]
     e["traffic"] = measured_traffic(kname)
     e["launches_per_step"] = launches / steps
