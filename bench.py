@@ -100,7 +100,7 @@ def run_mode(R, prob, mode, steps, warmup, ref, torch, refine_tol, account):
     if account:
         R.rfd_kernel_accounting(ACCOUNT_EVERY)
         R.rfd_kernel_stats()               # clear
-    lat, good, errs, res = [], [], [], []
+    lat, outs, good, errs, res = [], [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -108,12 +108,14 @@ def run_mode(R, prob, mode, steps, warmup, ref, torch, refine_tol, account):
         ev, r, k = one_step(P, prob, Y0)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - ts)
+        outs.append((ev, r))               # checked after the timed region
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    for ev, r in outs:
         g, e = count_good(ev.cpu().numpy(), ref)
         good.append(g)
         errs.append(e)
         res.append(float(r.max().item()) if r.numel() else 0.0)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
     kstats = None
     if account:
         kstats = R.rfd_kernel_stats()
