@@ -96,6 +96,55 @@ def _run_gpu(prob, mode):
     return out
 
 
+def _project_out(Q, X):
+    return X - Q @ (Q.T @ X)
+
+
+def _check_krylov_blocks(prob, Qg, Qo, mode, tol=1e-10):
+    """Every block step of the interface basis (Alg. 3.1, run on a block):
+    with F the oracle's filter (eq. (3.5)),
+      * F Y0 lies in span(Q_gpu) and in span(Q_oracle);
+      * for t < steps, F Q_t^oracle and F Q_t^gpu lie in span(Q_gpu), where
+        Q_t^gpu is found by running the GPU with t steps (its first t blocks
+        are those of the full run: the same deterministic code path).
+    Residuals are measured relative to the largest entry of the block."""
+    torch = _torch()
+    dd = O.DD(prob.A, prob.M, prob.part)
+    z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
+    fac = O.factor_poles(dd, z)
+    F = lambda X: O.filter_apply(fac, w, X)
+    W1 = F(prob.Y0)
+    for Qx in (Qg, Qo):
+        assert np.max(np.abs(_project_out(Qx, W1))) < tol * np.max(np.abs(W1))
+    # the oracle's blocks (same drop rule as its filter_interface)
+    blocks_o, K = [], None
+    Qt = O.orth(W1)
+    for t in range(1, prob.steps):
+        blocks_o.append(Qt)
+        K = Qt if K is None else np.hstack([K, Qt])
+        if Qt.shape[1] == 0 or K.shape[1] >= dd.s:
+            break
+        Qt = O.orth(F(Qt), K)
+    for t, B in enumerate(blocks_o, 1):
+        FB = F(B)
+        if FB.size and np.max(np.abs(FB)) > 0:
+            r = np.max(np.abs(_project_out(Qg, FB))) / np.max(np.abs(FB))
+            assert r < tol, ("oracle block", t, r)
+    # the GPU's blocks: widths from runs with fewer steps
+    prev = 0
+    for t in range(1, prob.steps):
+        P = _pencil(prob, mode)
+        wt = P.filter_interface(_dev_block(torch, prob.Y0), t).shape[0]
+        P.close()
+        B = Qg[:, prev:wt]
+        prev = wt
+        if B.shape[1] == 0:
+            break
+        FB = F(B)
+        r = np.max(np.abs(_project_out(Qg, FB))) / np.max(np.abs(FB))
+        assert r < tol, ("gpu block", t, r)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("name", list(CASES))
 def test_filter_apply_elementwise(name, mode):
@@ -141,17 +190,15 @@ def test_pole_windows_match_the_oracle(window, mode):
 def test_end_to_end_parity(name, mode):
     prob, ro = _prob(name)
     g = _run_gpu(prob, mode)
-    # interface subspace: same dimension, orthonormal, and both bases contain
-    # the filtered block F Y0 (directions with tiny pivots are ill-determined,
-    # so the bases are compared through what they must span)
+    # interface subspace: same dimension, orthonormal, and every Krylov block
+    # is followed: both bases contain the filtered block F Y0, the oracle's
+    # F Q_t (t < steps) lies in the GPU's span, and the oracle's filter
+    # applied to each of the GPU's own blocks Q_t (t < steps) lies in it too
+    # (span{Q_1..Q_t+1} contains F Q_t up to the dropped directions, whose
+    # pivots are below 1e-13 of the block's scale)
     assert g["Q"].shape[1] == ro.mu
     assert np.max(np.abs(g["Q"].T @ g["Q"] - np.eye(ro.mu))) < 1e-12
-    dd = O.DD(prob.A, prob.M, prob.part)
-    z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
-    W1 = O.filter_apply(O.factor_poles(dd, z), w, prob.Y0)
-    for Qx in (g["Q"], ro.Q):
-        res = W1 - Qx @ (Qx.T @ W1)
-        assert np.max(np.abs(res)) < 1e-10 * np.max(np.abs(W1))
+    _check_krylov_blocks(prob, g["Q"], ro.Q, mode)
     # Ritz values in [alpha, beta]
     assert g["theta"].size == ro.theta.size == prob.nev
     rel = np.abs(g["theta"] - ro.theta) / np.abs(ro.theta)
@@ -257,15 +304,20 @@ def test_saturated_krylov_steps():
     assert np.max(np.abs(g["theta"] - ro.theta) / ro.theta) <= EIG_TOL
 
 
-def test_no_deflation_runs():
-    """nev_b = 0 (no V_j): the path still runs; the Ritz values lie in the
-    interval and are accurate to the method's (coarse) level here."""
+def test_no_deflation_matches_the_oracle():
+    """nev_b = 0 (no V_j, so the resolvent levels are not deflated and Z is
+    ill-conditioned): the Ritz values equal the oracle's (same count, relative
+    error <= 1e-10) in both modes.  The (2,2) mode of this 11 x 11 grid
+    vanishes on the cross-shaped separator, so one of the six eigenvalues is
+    missed by both sides."""
     prob = W.tiny(N=11, P=2, nev=6, n_c=8, m=21, steps=1, nev_b=0, psi=6)
-    g = _run_gpu(prob, 0)
-    ex = W.closed_form_eigs((11, 11))[:6]
-    assert 1 <= g["theta"].size <= 6
-    assert np.all((g["theta"] >= prob.alpha) & (g["theta"] <= prob.beta))
-    assert np.min(np.abs(g["theta"][:, None] - ex[None, :]), axis=1).max() < 1e-2
+    ro = O.run(prob)
+    for mode in (0, 1):
+        g = _run_gpu(prob, mode)
+        assert g["theta"].size == ro.theta.size, (mode, g["theta"], ro.theta)
+        rel = np.abs(g["theta"] - ro.theta) / np.abs(ro.theta)
+        assert np.max(rel) <= EIG_TOL, (mode, rel)
+        assert np.all(g["resid"] <= 10 * ro.resid + 1e-12)
 
 
 def test_max_out_too_small_reports_count():

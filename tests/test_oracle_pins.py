@@ -389,3 +389,58 @@ def test_deflated_levels_keep_the_span():
     sv = np.linalg.svd(b1.T @ b2, compute_uv=False)
     assert np.min(sv) > 1 - 1e-8
     assert c2 > 100 * c1          # the deflated basis is far better conditioned
+
+
+# ---------------------------------------------------------------- residual and ||A||
+def _norm_a_pin_errors(norm_a):
+    """Deviations of a candidate ||A|| routine from closed-form largest
+    absolute row sums: 8 for the 2D five-point stencil (4 + 4 x |-1|), 12
+    for the 3D seven-point stencil, 7 for a hand-written 3 x 3 matrix."""
+    hand = sp.csr_matrix(np.array([[2.0, -1.0, 0.0], [-1.0, 3.0, -2.0], [0.0, -2.0, 5.0]]))
+    cases = [(W.laplacian((9, 9)), 8.0), (W.laplacian((6, 6, 6)), 12.0), (hand, 7.0)]
+    return [abs(norm_a(A) - v) / v for A, v in cases]
+
+
+def test_norm_a_closed_form_row_sums():
+    assert max(_norm_a_pin_errors(O.norm_a)) < 1e-15
+    # an upper bound of ||A||_2, which equals 8 sin^2(pi N / (2 (N + 1))) in 2D
+    A = W.laplacian((9, 9))
+    assert O.norm_a(A) >= 8.0 * np.sin(np.pi * 9 / 20.0) ** 2
+    # a planted mistake (twice the norm, or the largest entry instead of the row sum) fails
+    assert max(_norm_a_pin_errors(lambda A: 2.0 * O.norm_a(A))) > 0.5
+    assert max(_norm_a_pin_errors(lambda A: float(abs(A).max()))) > 0.1
+
+
+def _residual_pin_errors(residuals):
+    """Exact eigenpairs (lam_i, x_i) of a random-diagonal-M pencil from a
+    dense generalized eigensolver, perturbed to theta_i = lam_i (1 + delta_i):
+    then A x_i - theta_i M x_i = -lam_i delta_i M x_i, whose 2-norm is known.
+    With ||A|| = 8 (closed form of the 2D stencil) the relative residual is
+    |lam_i delta_i| ||M x_i||_2 / (8 ||x_i||_2).  The columns carry arbitrary
+    scales (the residual is scale-free).  Returns the largest deviation
+    relative to the expected values (absolute where they vanish)."""
+    prob = W.tiny(N=7, P=2, nev=4, mass_kind="random", cfg_id=61)
+    mdiag = prob.M.diagonal()
+    lam, X = sl.eigh(prob.A.toarray(), prob.M.toarray())
+    pick = np.array([0, 3, 10, 25, 48])
+    delta = np.array([0.0, 1e-3, -2e-2, 0.5, -1e-6])
+    scale = np.array([1.0, 3.0, 0.25, -7.0, 1e3])
+    Xs = X[:, pick] * scale[None, :]
+    theta = lam[pick] * (1.0 + delta)
+    mx = np.sqrt(np.sum((mdiag[:, None] * Xs) ** 2, axis=0))
+    expect = np.abs(lam[pick] * delta) * mx / (8.0 * np.sqrt(np.sum(Xs ** 2, axis=0)))
+    got = residuals(prob.A, prob.M, theta, Xs)
+    err = np.abs(got - expect) / np.maximum(expect, 1e-300)
+    err[delta == 0] = got[delta == 0]          # exact pair: rounding level only
+    return err
+
+
+def test_residuals_known_values():
+    err = _residual_pin_errors(O.residuals)
+    assert np.max(err[[1, 2, 3, 4]]) < 1e-8 and err[0] < 1e-14, err
+    assert O.residuals(W.laplacian((3, 3)), sp.identity(9), np.zeros(0), np.zeros((9, 0))).size == 0
+    # planted mistakes fail: M dropped from theta M x, ||A|| doubled, zeros returned
+    drop_m = lambda A, M, th, X: O.residuals(A, sp.identity(A.shape[0], format="csr"), th, X)
+    assert np.max(_residual_pin_errors(drop_m)[1:]) > 1e-2
+    assert np.max(_residual_pin_errors(lambda A, M, th, X: 0.5 * O.residuals(A, M, th, X))[1:]) > 0.4
+    assert np.max(_residual_pin_errors(lambda A, M, th, X: np.zeros(th.size))[1:]) > 0.9
