@@ -14,7 +14,8 @@ import scipy.linalg as sl
 import scipy.sparse as sp
 
 __all__ = [
-    "quadrature", "rho", "DD", "schur", "factor_poles", "filter_apply", "orth",
+    "quadrature", "rho", "DD", "schur", "factor_poles", "filter_apply", "filter_apply_streamed",
+    "orth",
     "filter_interface", "interior_basis", "interior_levels", "build_z",
     "rayleigh_ritz", "residuals", "norm_a", "inertia_count", "run", "OracleResult",
 ]
@@ -88,7 +89,8 @@ class DD:
     nonzero part of E_j in eq. (2.5).
     """
 
-    def __init__(self, A: sp.spmatrix, M: sp.spmatrix, part: np.ndarray):
+    def __init__(self, A: sp.spmatrix, M: sp.spmatrix, part: np.ndarray,
+                 dense_interface: bool = True):
         A = sp.csr_matrix(A)
         M = sp.csr_matrix(M)
         part = np.asarray(part)
@@ -118,8 +120,13 @@ class DD:
             self.MB.append(M[I][:, I].toarray())
             self.E.append(A[I][:, J].toarray())
             self.ME.append(M[I][:, J].toarray())
-        self.C = A[self.iface][:, self.iface].toarray()
-        self.MC = M[self.iface][:, self.iface].toarray()
+        # C and M_C dense, or sparse for large interfaces (dense_interface=False,
+        # where an s x s real array per matrix would not fit beside S(z))
+        self.C = A[self.iface][:, self.iface]
+        self.MC = M[self.iface][:, self.iface]
+        if dense_interface:
+            self.C = self.C.toarray()
+            self.MC = self.MC.toarray()
         self.A = A
         self.M = M
         self.part = part
@@ -139,7 +146,12 @@ def schur(dd: DD, z: complex) -> np.ndarray:
     transpose is the plain transpose (the paper prints ^H; with real M_E the
     two differ only when M_E != 0).  B_z is block diagonal, so the sum runs
     over subdomains; each B_j(z) is factored with partial pivoting (zgetrf)."""
-    S = (dd.C - z * dd.MC).astype(np.complex128)
+    if sp.issparse(dd.C):
+        Cz = sp.coo_matrix(dd.C - z * dd.MC)
+        S = np.zeros((dd.s, dd.s), dtype=np.complex128, order="F")
+        S[Cz.row, Cz.col] = Cz.data
+    else:
+        S = np.asfortranarray((dd.C - z * dd.MC).astype(np.complex128))
     for j in range(dd.p):
         K = dd.B[j] - z * dd.MB[j]
         Ez = dd.E[j] - z * dd.ME[j]
@@ -158,6 +170,21 @@ def filter_apply(factors, omega, Y: np.ndarray) -> np.ndarray:
     W = np.zeros(Y.shape, dtype=np.float64)
     for f, w in zip(factors, omega):
         W += 2.0 * np.real(w * sl.lu_solve(f, Y.astype(np.complex128), check_finite=False))
+    return W
+
+
+def filter_apply_streamed(dd: DD, zeta, omega, Y: np.ndarray) -> np.ndarray:
+    """The same W as filter_apply(factor_poles(dd, zeta), omega, Y), with one
+    pole's S(zeta_l) and its LU in memory at a time: each pole is assembled,
+    factored in place, applied and dropped, and the terms are added in the
+    same (ascending pole) order.  For interfaces whose dense S(zeta) takes
+    tens of GB per pole."""
+    W = np.zeros(Y.shape, dtype=np.float64)
+    Yc = Y.astype(np.complex128)
+    for z, w in zip(zeta, omega):
+        f = sl.lu_factor(schur(dd, z), overwrite_a=True, check_finite=False)
+        W += 2.0 * np.real(w * sl.lu_solve(f, Yc, check_finite=False))
+        del f
     return W
 
 
@@ -182,23 +209,34 @@ def orth(W: np.ndarray, K: Optional[np.ndarray] = None, tol: float = ORTH_TOL) -
     return np.asfortranarray(Qf[:, :keep])
 
 
-def filter_interface(dd: DD, zeta, omega, Y0: np.ndarray, steps: int, factors=None):
+def filter_interface(dd: DD, zeta, omega, Y0: np.ndarray, steps: int, factors=None,
+                     streamed: bool = False, keep: Optional[dict] = None):
     """Interface subspace Q (s x mu), Sec. 3.2.
 
     Alg. 3.1 is a Lanczos process on F = 2 Re sum omega_l S(zeta_l)^{-1} with
     full reorthogonalisation.  Here it is run on a block: Q_1 = orth(F Y0),
     Q_t = orth(F Q_{t-1}) against [Q_1..Q_{t-1}], t = 2..steps, and
     Q = [Q_1, .., Q_steps] spans the block Krylov space
-    span{F Y0, F^2 Y0, .., F^steps Y0}."""
-    if factors is None:
-        factors = factor_poles(dd, zeta)
-    W = filter_apply(factors, omega, Y0)
+    span{F Y0, F^2 Y0, .., F^steps Y0}.
+
+    streamed=True applies F with filter_apply_streamed (every application
+    factors the poles again, one at a time).  keep, when given, receives the
+    first filtered block F Y0 under "W1"."""
+    if streamed:
+        F = lambda X: filter_apply_streamed(dd, zeta, omega, X)
+    else:
+        if factors is None:
+            factors = factor_poles(dd, zeta)
+        F = lambda X: filter_apply(factors, omega, X)
+    W = F(Y0)
+    if keep is not None:
+        keep["W1"] = W
     Qt = orth(W)
     K = Qt
     for _ in range(2, steps + 1):
         if Qt.shape[1] == 0 or K.shape[1] >= dd.s:
             break
-        W = filter_apply(factors, omega, Qt)
+        W = F(Qt)
         Qt = orth(W, K)
         K = np.hstack([K, Qt])
     return np.asfortranarray(K), factors
@@ -319,12 +357,19 @@ def rayleigh_ritz(dd: DD, Z: np.ndarray, alpha: float, beta: float, tol: float =
     lt, lti = _m_half(Mr)
     cn = np.sqrt(np.maximum(np.einsum("ij,ij->j", Z, Mr @ Z), 0.0))
     keep = cn > 0
-    Zs = Z[:, keep] / cn[keep]
-    Qh, R = np.linalg.qr(lt(Zs))
+    # (intermediates of n x k are dropped as soon as they are used, so that
+    # the largest pencils hold about three of them at a time)
+    LZ = np.asfortranarray(lt(Z[:, keep] / cn[keep]))
+    Qh, R = sl.qr(LZ, mode="economic", overwrite_a=True, check_finite=False)
+    del LZ
     U, sv, _ = np.linalg.svd(R)
     r = int(np.count_nonzero(sv > tol * sv[0]))
-    Xb = lti(Qh @ U[:, :r])               # M-orthonormal basis of range(Z)
-    H = Xb.T @ (Ar @ Xb)
+    Xb = Qh @ U[:, :r]
+    del Qh
+    Xb = lti(Xb)                          # M-orthonormal basis of range(Z)
+    AX = Ar @ Xb
+    H = Xb.T @ AX
+    del AX
     H = 0.5 * (H + H.T)
     th, G = np.linalg.eigh(H)
     sel = (th >= alpha) & (th <= beta)
@@ -387,20 +432,25 @@ class OracleResult:
     rank: int
     Q: np.ndarray
     times: dict
+    W1: Optional[np.ndarray] = None   # first filtered block F Y0 (eq. (3.5))
 
 
-def run(prob, want_vectors: bool = True, deflate_levels: bool = True) -> OracleResult:
-    """Alg. 5.1 on a workloads.Problem."""
+def run(prob, want_vectors: bool = True, deflate_levels: bool = True,
+        streamed: bool = False) -> OracleResult:
+    """Alg. 5.1 on a workloads.Problem.  streamed=True: sparse C, M_C and one
+    pole's S(zeta) at a time (filter_apply_streamed), for the largest
+    pencils; the arithmetic is that of the default path."""
     t = {}
     t0 = time.perf_counter()
-    dd = DD(prob.A, prob.M, prob.part)
+    dd = DD(prob.A, prob.M, prob.part, dense_interface=not streamed)
     zeta, omega = quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
     t["setup"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     V, _ = interior_basis(dd, prob.sigma, prob.nev_b)
     t["interior_basis"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    Q, _ = filter_interface(dd, zeta, omega, prob.Y0, prob.steps)
+    kept = {}
+    Q, _ = filter_interface(dd, zeta, omega, prob.Y0, prob.steps, streamed=streamed, keep=kept)
     t["filter"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     Sig, Gam = interior_levels(dd, prob.sigma, prob.psi, Q, V if deflate_levels else None)
@@ -414,4 +464,5 @@ def run(prob, want_vectors: bool = True, deflate_levels: bool = True) -> OracleR
     res = residuals(prob.A, prob.M, th, X) if want_vectors else np.zeros(0)
     t["rr"] = time.perf_counter() - t0
     return OracleResult(theta=th, X=X if want_vectors else np.zeros((0, 0)), resid=res,
-                        mu=Q.shape[1], k=Z.shape[1], rank=rank, Q=Q, times=t)
+                        mu=Q.shape[1], k=Z.shape[1], rank=rank, Q=Q, times=t,
+                        W1=kept.get("W1"))

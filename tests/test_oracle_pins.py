@@ -444,3 +444,26 @@ def test_residuals_known_values():
     assert np.max(_residual_pin_errors(drop_m)[1:]) > 1e-2
     assert np.max(_residual_pin_errors(lambda A, M, th, X: 0.5 * O.residuals(A, M, th, X))[1:]) > 0.4
     assert np.max(_residual_pin_errors(lambda A, M, th, X: np.zeros(th.size))[1:]) > 0.9
+
+
+# ---------------------------------------------------------------- pole-streamed path
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_streamed_filter_equals_the_stored_factor_path(k):
+    """filter_apply_streamed (one pole's S(zeta) at a time, sparse C and M_C)
+    computes the same eq. (3.5) as filter_apply over stored factors."""
+    prob = _pencils()[k]
+    z, w = O.quadrature(prob.alpha, prob.beta, 5, "gauss")
+    dd = O.DD(prob.A, prob.M, prob.part)
+    dds = O.DD(prob.A, prob.M, prob.part, dense_interface=False)
+    Wa = O.filter_apply(O.factor_poles(dd, z), w, prob.Y0)
+    Wb = O.filter_apply_streamed(dds, z, w, prob.Y0)
+    assert np.max(np.abs(Wa - Wb)) <= 1e-14 * np.max(np.abs(Wa))
+
+
+def test_streamed_run_equals_the_default_run():
+    prob = W.tiny(N=13, P=3, nev=6, n_c=6, steps=2, nev_b=6, psi=3, mass_kind="random", cfg_id=62)
+    a = O.run(prob)
+    b = O.run(prob, streamed=True)
+    assert a.theta.size == b.theta.size == 6
+    assert np.max(np.abs(a.theta - b.theta) / a.theta) <= 1e-13
+    assert np.max(np.abs(a.W1 - b.W1)) <= 1e-14 * np.max(np.abs(a.W1))

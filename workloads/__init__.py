@@ -136,6 +136,29 @@ def grid_partition(shape, P: int) -> np.ndarray:
     return out.astype(np.int32)
 
 
+def interface_groups(shape, P: int) -> Optional[np.ndarray]:
+    """Two-level grouping of the interface nodes of grid_partition(shape, P)
+    (ascending global id): -1 for a node on the middle separator of any axis
+    (the top set), else the index of the half-space box it lies in (one bit
+    per axis, x lowest).  Defined for even P >= 4 (the middle separator
+    exists and the halves hold separators of their own); None otherwise."""
+    shape = tuple(int(s) for s in shape)
+    if P < 4 or P % 2:
+        return None
+    ndim = len(shape)
+    coords = np.indices(shape[::-1]).reshape(ndim, -1)[::-1]
+    part = grid_partition(shape, P)
+    iface = np.flatnonzero(part < 0)
+    top = np.zeros(iface.size, dtype=bool)
+    grp = np.zeros(iface.size, dtype=np.int64)
+    for ax in range(ndim):
+        mid = separators(shape[ax], P)[P // 2 - 1]
+        c = coords[ax][iface]
+        top |= c == mid
+        grp += (c > mid).astype(np.int64) << ax
+    return np.where(top, -1, grp).astype(np.int32)
+
+
 def closed_form_eigs(shape) -> np.ndarray:
     """Eigenvalues of the constant-coefficient Dirichlet Laplacian with M = I:
     sum over axes of 4 sin^2(pi i / (2 (N+1))), i = 1..N (sorted)."""
@@ -237,7 +260,7 @@ def grid_problem(name, cfg_id, shape, P, nev, n_c, m, steps, nev_b, psi,
                    meta=dict(cfg_id=cfg_id, P=P, mass=mass_kind, kfield=kfield))
 
 
-def config(i: int, known=None) -> Problem:
+def config(i: int, known=None, **override) -> Problem:
     """The measured workloads.
 
     1: 2D 31x31, M = I, 2x2 partition (4 interiors of 15x15, s = 61), lowest 20,
@@ -248,14 +271,25 @@ def config(i: int, known=None) -> Problem:
        s = 34047), lowest 500, 8 poles, m = 700.  Its interval needs the 501
        lowest eigenvalues of a 250047 x 250047 pencil; pass known = (alpha,
        beta, lam) from a stored run to skip that eigensolve.
+
+    The method's free parameters (block-Krylov steps, nev_b, psi) are the
+    smallest found to reach the accuracy targets against the exact or
+    reference eigenvalues: 31x31 (2, 20, 4); 255x255 (5, 40, 6), where every
+    residual also falls below 1e-9; 63^3 (4, 40, 6), where every eigenvalue
+    is within 1e-10.  override = dict(steps=, nev_b=, psi=) replaces them.
     """
+    def pick(d, key):
+        return override.get(key, d)
     if i == 1:
-        return grid_problem("C1 2D 31x31 M=I p=4", 1, (31, 31), 2, 20, 4, 30, 2, 20, 4)
+        return grid_problem("C1 2D 31x31 M=I p=4", 1, (31, 31), 2, 20, 4, 30, pick(2, "steps"),
+                            pick(20, "nev_b"), pick(4, "psi"))
     if i == 2:
-        return grid_problem("C2 2D 255x255 Mdiag p=64", 2, (255, 255), 8, 200, 8, 300, 2, 20, 4,
+        return grid_problem("C2 2D 255x255 Mdiag p=64", 2, (255, 255), 8, 200, 8, 300,
+                            pick(5, "steps"), pick(40, "nev_b"), pick(6, "psi"),
                             mass_kind="random")
     if i == 3:
-        return grid_problem("C3 3D 63^3 Mdiag p=64", 3, (63, 63, 63), 4, 500, 8, 700, 1, 20, 4,
+        return grid_problem("C3 3D 63^3 Mdiag p=64", 3, (63, 63, 63), 4, 500, 8, 700,
+                            pick(4, "steps"), pick(40, "nev_b"), pick(6, "psi"),
                             mass_kind="random", known=known)
     raise ValueError(i)
 
