@@ -9,6 +9,7 @@
  *   rfd_set_partition           interior-first reordering               Sec. 2.3, eq. (2.5)
  *   rfd_set_interval_and_poles  rational filter poles / weights         Sec. 2.1, eqs. (2.1)-(2.3)
  *   rfd_set_precision           FP64, or FP32 factors + FP64 refinement
+ *   rfd_set_interface_groups    two-level (nested-dissection) S(zeta)   Sec. 2.3 applied to S, Sec. 7
  *   rfd_filter_interface        Q = orth of 2 Re sum_l w_l S(z_l)^{-1} applied
  *                               to a block (block Krylov)               Sec. 3.1 eq. (3.5), Alg. 3.1
  *   rfd_prepare_interior        V_j and B_sigma factors, concurrently   Sec. 4, Alg. 5.1 step 3
@@ -250,6 +251,30 @@ rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16);
  * the order of the final sum.  Errors: RFD_EINVAL for max_poles < 0.
  */
 rfd_status rfd_set_pole_window(rfd_pencil_t pencil, int32_t max_poles);
+
+/*
+ * rfd_set_interface_groups -- factor S(zeta) in two levels (a nested
+ * dissection of the interface: the paper's interior-first reordering of
+ * Sec. 2.3, eq. (2.5), applied once more to S itself, as in the recursive
+ * form of RF-DDES proposed in Sec. 7).  group[a] (host array over the s
+ * interface nodes, in the interface order of rfd_set_partition) is in
+ * {0..ngroups-1} for a node of group g and -1 for a node of the top set T.
+ * S(zeta) must not couple two different groups: no C or M_C entry may join
+ * them and no subdomain may be adjacent to nodes of two groups.  Then, with
+ * the groups ordered first, S = [S_GG S_GT; S_GT^T S_TT] with S_GG block
+ * diagonal (S is complex symmetric), and the filter solves use its block LU:
+ * the group blocks S_gg, X_g = S_gg^{-1} S_gT, the top complement
+ * S_TT - sum_g S_gT^T X_g and its LU, all without pivoting (every shifted
+ * block has a field of values off the real axis, Sec. 3.1), in the current
+ * precision mode (FP32 mode refines against the FP64 blocks).  The result
+ * equals the dense S(zeta)^{-1} up to rounding; the work and memory fall from
+ * s^2 per pole to sum_g (|g|^2 + |g| |T_g|) + |T|^2, T_g being the top
+ * nodes coupled to g.  ngroups = 0 returns to the dense S.  Invalidates the
+ * per-pole factors; rfd_set_partition drops the grouping.
+ * Errors: RFD_ESTATE before rfd_set_partition; RFD_EINVAL for a value out of
+ * range, an empty group, an empty top set, or a coupling between groups.
+ */
+rfd_status rfd_set_interface_groups(rfd_pencil_t pencil, int32_t ngroups, const int32_t* group);
 
 /*
  * rfd_kernel_accounting / rfd_kernel_stats -- process-wide, sampled timing of

@@ -30,7 +30,8 @@ EXPORTS = [
     "rfd_solve_interior",
     "rfd_rayleigh_ritz",
     "rfd_destroy_pencil", "rfd_last_error", "rfd_pencil_info", "rfd_set_timing",
-    "rfd_phase_times", "rfd_reset_caches", "rfd_set_pole_window", "rfd_batch_run", "rfd_server_create",
+    "rfd_phase_times", "rfd_reset_caches", "rfd_set_pole_window", "rfd_set_interface_groups",
+    "rfd_batch_run", "rfd_server_create",
     "rfd_server_submit", "rfd_server_poll", "rfd_server_destroy", "rfd_server_stats",
 ]
 
@@ -86,6 +87,7 @@ def lib():
                                 C.POINTER(I64), C.POINTER(I64)],
             "rfd_set_timing": [P, I32],
             "rfd_set_pole_window": [P, I32],
+            "rfd_set_interface_groups": [P, I32, P],
             "rfd_reset_caches": [P, I32],
             "rfd_test_basis": [P, P, I64, C.POINTER(I64), P],
             "rfd_kernel_accounting": [I32],
@@ -256,6 +258,16 @@ def rfd_set_pole_window(h, max_poles):
     _check(lib().rfd_set_pole_window(h, int(max_poles)))
 
 
+def rfd_set_interface_groups(h, group):
+    """group: int32 per interface node (interface order), -1 for the top set,
+    or None for the dense S."""
+    if group is None:
+        _check(lib().rfd_set_interface_groups(h, 0, None))
+        return
+    g = np.ascontiguousarray(group, dtype=np.int32)
+    _check(lib().rfd_set_interface_groups(h, int(g.max()) + 1, g.ctypes.data))
+
+
 def rfd_set_timing(h, on):
     _check(lib().rfd_set_timing(h, int(bool(on))))
 
@@ -333,6 +345,9 @@ class Pencil:
 
     def set_pole_window(self, max_poles):
         rfd_set_pole_window(self.h, max_poles)
+
+    def set_interface_groups(self, group):
+        rfd_set_interface_groups(self.h, group)
 
     def phase_times(self):
         return rfd_phase_times(self.h)

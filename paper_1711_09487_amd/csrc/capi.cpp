@@ -227,6 +227,16 @@ rfd_status rfd_set_pole_window(rfd_pencil_t pencil, int32_t max_poles) {
   });
 }
 
+rfd_status rfd_set_interface_groups(rfd_pencil_t pencil, int32_t ngroups, const int32_t* group) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    if (ngroups < 0) throw Error(ST_EINVAL, "need ngroups >= 0");
+    if (ngroups > 0 && !group) throw Error(ST_EINVAL, "null group array");
+    E.set_interface_groups(ngroups, group);
+  });
+}
+
 rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16) {
   return (rfd_status)capi_guard([&] {
     auto* P = need(pencil);

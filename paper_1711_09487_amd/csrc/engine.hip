@@ -184,11 +184,15 @@ int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, i
   const int64_t VB = nev_b + 16;
   const int64_t k = p * VB + (int64_t)psi * mu;
   int64_t b = chunk * per_pole;                                   // shifted blocks, Schur solves
-  b += SP * SP * n_c * 16 + (f32 ? SP * SP * n_c * 8 : 0);        // S (FP64, FP32 copy)
-  if (f32 && SP * SP * n_c * 8 <= EngineImpl::GAUSS_MAX_BYTES)
-    b += SP * SP * n_c * 8 + SP * round_up(std::max(m, 1), NB) * n_c * 24;  // S_re + S_im, P1 P2 X sum
-  b += (int64_t)NB * 2 * SP * n_c * 2 * es;                       // S block inverses
-  b += SP * MP * n_c * (f32 ? 16 + 16 + 8 : 16);                  // filter right-hand sides
+  if (e.tree.L > 0) {
+    b += n_c * e.tree_pole_bytes(MP, mode);                        // two-level S, right-hand sides
+  } else {
+    b += SP * SP * n_c * 16 + (f32 ? SP * SP * n_c * 8 : 0);      // S (FP64, FP32 copy)
+    if (f32 && SP * SP * n_c * 8 <= EngineImpl::GAUSS_MAX_BYTES)
+      b += SP * SP * n_c * 8 + SP * round_up(std::max(m, 1), NB) * n_c * 24;  // S_re + S_im, P1 P2 X sum
+    b += (int64_t)NB * 2 * SP * n_c * 2 * es;                     // S block inverses
+    b += SP * MP * n_c * (f32 ? 16 + 16 + 8 : 16);                // filter right-hand sides
+  }
   b += e.s * (mu + m) * 8 * 3;                                    // interface basis, orth work
   b += p * (D * VB + 3 * D * D + D * (int64_t)psi * MUP) * 8;     // V_j, B_sigma, levels
   b += p * (2 * 256 * D + 256 * MUP) * 8;                          // B_sigma wide leaves, their work
@@ -296,7 +300,9 @@ std::vector<DevBuf*> EngineImpl::solve_buffers() {
                          &Bspiv, &Bswide, &Bswork, &Lev, &Zt, &work1, &work2, &work3, &work4, &work5, &work6,
                          &ipiv_small, &iscal, &gwork, &work6b, &rr_az, &rr_h, &ow.V, &ow.T,
                          &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank, &ow.wg, &ow.wt,
-                         &ow.w1, &ow.w2};
+                         &ow.w1, &ow.w2, &Tgg64, &TgT64, &Ttt64, &Txc64, &Tgg32, &TgT32,
+                         &Txc32, &Ttt32, &Tinvg, &Tinvt, &Twide, &Twork, &Tgt, &TRG, &TRT, &TXG,
+                         &TXT, &TRG32, &TRT32, &TU, &TXTg};
   for (TriWork* t : {&tw_v, &tw_h})
     for (DevBuf* b : {&t->d, &t->e, &t->tau, &t->pt, &t->acol, &t->vw, &t->red, &t->sq, &t->ptvp,
                       &t->wv, &t->wg, &t->wt, &t->w1, &t->w2})
@@ -430,10 +436,29 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
   const int items_max = chunk * p;
   // Schur complements (FP64 planar), all poles
   const int64_t sbytes = SP * SP * (int64_t)nc * sizeof(double);
-  S64.alloc(2 * sbytes);
-  DMat<double> S{S64.as<double>(), S64.as<double>() + SP * SP * nc, SP, SP * SP};
-  fill<double>(st, S, SP, SP, nc, 0.0);
-  schur_init(st, S, s, SP, nc, w0, Cg.view(), z);
+  const bool two_level = tree.L > 0;
+  DMat<double> S, Tg, TgT, Tt;
+  const int64_t TG_ = tree.NGP, TGT_ = tree.TGP, TP_ = tree.TP;
+  const int tL = tree.L;
+  if (!two_level) {
+    S64.alloc(2 * sbytes);
+    S = DMat<double>{S64.as<double>(), S64.as<double>() + SP * SP * nc, SP, SP * SP};
+    fill<double>(st, S, SP, SP, nc, 0.0);
+    schur_init(st, S, s, SP, nc, w0, Cg.view(), z);
+  } else {
+    // the two-level blocks of S (group blocks, their top couplings, the top block)
+    const int64_t ni = (int64_t)nc * tL;
+    Tgg64.alloc(2 * TG_ * TG_ * ni * sizeof(double));
+    TgT64.alloc(2 * TG_ * TGT_ * ni * sizeof(double));
+    Ttt64.alloc(2 * TP_ * TP_ * nc * sizeof(double));
+    Tg = DMat<double>{Tgg64.as<double>(), Tgg64.as<double>() + TG_ * TG_ * ni, TG_, TG_ * TG_};
+    TgT = DMat<double>{TgT64.as<double>(), TgT64.as<double>() + TG_ * TGT_ * ni, TG_, TG_ * TGT_};
+    Tt = DMat<double>{Ttt64.as<double>(), Ttt64.as<double>() + TP_ * TP_ * nc, TP_, TP_ * TP_};
+    fill<double>(st, Tg, TG_, TG_, (int)ni, 0.0);
+    fill<double>(st, TgT, TG_, TGT_, (int)ni, 0.0);
+    fill<double>(st, Tt, TP_, TP_, nc, 0.0);
+    tree_init(st, Tg, TgT, Tt, nc, w0, Cg.view(), tree, z);
+  }
   const int64_t kk = D * D * (int64_t)items_max, ki = (int64_t)NB * 2 * D * items_max,
                 xs = D * SJ * (int64_t)items_max;
   const bool fp32 = (mode == 1);
@@ -498,17 +523,36 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
       timer.end(st);
     }
     timer.begin(st, 2);
-    DMat<double> Sc = S.item(l0 - w0);
-    for (size_t c = 0; c < colors_d.size(); ++c)
-      schur_scatter(st, Sc, X, SJ, p, np, l0, colors_d[c].as<int32_t>(),
-                    (int)P->colors[c].size(), sj.as<int32_t>(), adj.as<int32_t>(), Etg.view(), z);
+    if (!two_level) {
+      DMat<double> Sc = S.item(l0 - w0);
+      for (size_t c = 0; c < colors_d.size(); ++c)
+        schur_scatter(st, Sc, X, SJ, p, np, l0, colors_d[c].as<int32_t>(),
+                      (int)P->colors[c].size(), sj.as<int32_t>(), adj.as<int32_t>(), Etg.view(),
+                      z);
+    } else {
+      const int64_t i0 = (int64_t)(l0 - w0) * tL;
+      for (size_t c = 0; c < colors_d.size(); ++c)
+        tree_scatter(st, Tg.item(i0), TgT.item(i0), Tt.item(l0 - w0), X, SJ, p, np, l0,
+                     colors_d[c].as<int32_t>(), (int)P->colors[c].size(), sj.as<int32_t>(),
+                     Etg.view(), tree, z);
+    }
     timer.end(st);
   }
   check_flags(st, "interior factorization");
   timer.sweeps_schur = max_sweeps_used;
   // factor S(zeta_l), all poles in one batch
   timer.begin(st, 3);
-  if (fp32) {
+  if (two_level) {
+    tree_factor(st, nc);
+    if (K32.bytes + K64.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
+      K32.release();
+      Kinv32.release();
+      X32.release();
+      R64.release();
+      K64.release();
+      Kinv64.release();
+    }
+  } else if (fp32) {
     S32.alloc(2 * SP * SP * (int64_t)nc * sizeof(float));
     Sinv32.alloc(2 * (int64_t)NB * 2 * SP * nc * sizeof(float));
     DMat<float> S3{S32.as<float>(), S32.as<float>() + SP * SP * nc, SP, SP * SP};
@@ -564,9 +608,10 @@ int EngineImpl::pole_window(int m) const {
   const int nc = poles.n_c;
   const bool f32 = mode == 1;
   const int64_t MP = round_up(std::max(m, 1), NB);
-  const int64_t per_pole = 2 * SP * SP * (f32 ? 8 + 4 : 8) +
-                           2 * (int64_t)NB * 2 * SP * (f32 ? 4 : 8) +
-                           2 * SP * MP * (f32 ? 8 + 8 + 4 : 8);
+  const int64_t per_pole = tree.L > 0 ? tree_pole_bytes(MP, mode)
+                                       : 2 * SP * SP * (f32 ? 8 + 4 : 8) +
+                                             2 * (int64_t)NB * 2 * SP * (f32 ? 4 : 8) +
+                                             2 * SP * MP * (f32 ? 8 + 8 + 4 : 8);
   const int64_t per_chunk_pole =
       (int64_t)p * (D * D * (f32 ? 8 : 16) + (int64_t)NB * 2 * D * (f32 ? 8 : 16) +
                     D * SJ * (f32 ? 48 : 16));
@@ -581,7 +626,7 @@ int EngineImpl::pole_window(int m) const {
   auto need = [&](int wn) {
     double b = (double)wn * per_pole + (double)std::min(pole_chunk(), wn) * per_chunk_pole;
     // S_re + S_im and the three-product work of the FP32 refinement
-    if (f32 && SP * SP * (int64_t)wn * 8 <= GAUSS_MAX_BYTES)
+    if (tree.L == 0 && f32 && SP * SP * (int64_t)wn * 8 <= GAUSS_MAX_BYTES)
       b += (double)wn * (SP * SP * 8 + SP * MP * 24);
     return b;
   };
@@ -610,8 +655,9 @@ void EngineImpl::run_filter(hipStream_t st, const double* Y, int64_t ldy, int m,
   // room for the interior part (the next application factors again)
   RFD_HIP(hipStreamSynchronize(st));
   for (DevBuf* b : {&K32, &K64, &Kinv32, &Kinv64, &X32, &X64, &R32, &R64, &S64, &S32, &Ssum,
-                    &Xsum, &Pg, &Sinv32,
-                    &Sinv64, &Swide, &Swork, &Yc, &Xf, &Rf, &Rf32})
+                    &Xsum, &Pg, &Sinv32, &Sinv64, &Swide, &Swork, &Yc, &Xf, &Rf, &Rf32, &Tgg64,
+                    &TgT64, &Ttt64, &Txc64, &Tgg32, &TgT32, &Txc32, &Ttt32, &Tinvg, &Tinvt, &Twide,
+                    &Twork, &Tgt, &TRG, &TRT, &TXG, &TXT, &TRG32, &TRT32, &TU, &TXTg})
     b->release();
   factored = false;
 }
@@ -620,6 +666,10 @@ void EngineImpl::run_filter(hipStream_t st, const double* Y, int64_t ldy, int m,
 // W real (ld ldw).  FP32 mode refines every pole's solve against S_64.
 void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* Wout,
                               int64_t ldw, bool add) {
+  if (tree.L > 0) {
+    tree_apply(st, Y, ldy, m, Wout, ldw, add);
+    return;
+  }
   const int nc = winn;
   const double* om = omega.as<double>() + 2 * (int64_t)win0;
   const int64_t MP = round_up(m, NB);

@@ -34,6 +34,9 @@ class Engine {
   void copy_basis(hipStream_t s, double* dst, int64_t cap, int64_t* k);
   void set_timing(bool on);
   void set_pole_window(int w);
+  // Two-level factorization of S(zeta) over L interface groups (group[a] per
+  // interface position, -1 = top set); L = 0 returns to the dense S.
+  void set_interface_groups(int L, const int32_t* group);
   void phase_times(double* ms16);
 
  private:

@@ -11,6 +11,7 @@
 
 #include "engine.hpp"
 #include "eig.hpp"
+#include "nested.hpp"
 #include "orth.hpp"
 #include "sparse.hpp"
 
@@ -71,6 +72,24 @@ struct EngineImpl {
   bool gauss3 = false;
   static constexpr int64_t GAUSS_MAX_BYTES = int64_t(4) << 30;
   OrthWork ow;
+  // Two-level interface (set_interface_groups; tree.L = 0: dense S).  Blocks
+  // of S per pole (FP64: Tgg64, TgT64, Ttt64, kept unfactored in FP32 mode for
+  // the refinement residual), their FP32 copies and factors, X_g = S_gg^{-1}
+  // S_gT (Txc), the top complement's block inverses and wide leaves, and the
+  // blocked right-hand sides of the filter solves.
+  TreeDev tree;
+  DevBuf Tgg64, TgT64, Ttt64, Txc64, Tgg32, TgT32, Txc32, Ttt32, Tinvg, Tinvt, Twide, Twork, Tgt;
+  DevBuf TRG, TRT, TXG, TXT, TRG32, TRT32, TU, TXTg;
+  int TLW = 0;
+  // factors the window's blocks (assembled by factor()); nc poles
+  void tree_factor(hipStream_t st, int nc);
+  // R <- S^{-1} R in the blocked layout with the current factors
+  template <typename T>
+  void tree_solve(hipStream_t st, DMat<T> RG, DMat<T> RT, int64_t MP, int nc);
+  void tree_apply(hipStream_t st, const double* Y, int64_t ldy, int m, double* W, int64_t ldw,
+                  bool add);
+  // device bytes of one pole's blocks and of its filter right-hand sides
+  int64_t tree_pole_bytes(int64_t MP, int md) const;
   // interface basis
   DevBuf Qint;
   int mu = 0;

@@ -218,13 +218,14 @@ def test_end_to_end_parity(name, mode):
 
 
 def test_config2_full_size_against_stored_oracle():
-    """n = 65025, 64 subdomains, 8 poles, m = 300, 2 block steps: the Ritz
-    values of both precision modes against the oracle's stored values."""
+    """n = 65025, 64 subdomains, 8 poles, m = 300, at the stored run's block
+    steps, nev_b and psi: the Ritz values of both precision modes against the
+    oracle's stored values, and the residuals against the oracle's."""
     path = os.path.join(GOLD, "oracle_c2.json")
     if not os.path.exists(path):
         pytest.skip("stored oracle result missing")
     gold = json.load(open(path))
-    prob = W.config(2)
+    prob = W.config(2, steps=gold["steps"], nev_b=gold["nev_b"], psi=gold["psi"])
     assert (prob.alpha, prob.beta, prob.m) == (gold["alpha"], gold["beta"], gold["m"])
     th_ref = np.array(gold["theta"])
     for mode in (0, 1):
@@ -306,18 +307,38 @@ def test_saturated_krylov_steps():
 
 def test_no_deflation_matches_the_oracle():
     """nev_b = 0 (no V_j, so the resolvent levels are not deflated and Z is
-    ill-conditioned): the Ritz values equal the oracle's (same count, relative
-    error <= 1e-10) in both modes.  The (2,2) mode of this 11 x 11 grid
-    vanishes on the cross-shaped separator, so one of the six eigenvalues is
-    missed by both sides."""
+    ill-conditioned).  The (2,2) mode of this 11 x 11 grid vanishes on the
+    cross-shaped separator, so the interface filter cannot see it; only the
+    undeflated levels approximate it, along directions at the rank cut of the
+    Rayleigh-Ritz basis (singular values near 1e-12 of the largest).
+      * FP64: the same Ritz values as the oracle (count, relative error
+        <= 1e-10).
+      * FP32 + refinement: the filtered block differs from FP64 at the 1e-13
+        level and one more direction survives the cut, adding a Ritz value
+        0.5442 above the (2,2) eigenvalue 0.5359.  Every oracle Ritz value
+        is matched to 1e-10, and every extra one is a valid Ritz value of a
+        compression of (A, M): above the exact eigenvalue of its rank
+        (Courant-Fischer) and within its residual bound of an eigenvalue."""
     prob = W.tiny(N=11, P=2, nev=6, n_c=8, m=21, steps=1, nev_b=0, psi=6)
     ro = O.run(prob)
-    for mode in (0, 1):
-        g = _run_gpu(prob, mode)
-        assert g["theta"].size == ro.theta.size, (mode, g["theta"], ro.theta)
-        rel = np.abs(g["theta"] - ro.theta) / np.abs(ro.theta)
-        assert np.max(rel) <= EIG_TOL, (mode, rel)
-        assert np.all(g["resid"] <= 10 * ro.resid + 1e-12)
+    lam = W.closed_form_eigs((11, 11))
+    g = _run_gpu(prob, 0)
+    assert g["theta"].size == ro.theta.size, (g["theta"], ro.theta)
+    assert np.max(np.abs(g["theta"] - ro.theta) / np.abs(ro.theta)) <= EIG_TOL
+    assert np.all(g["resid"] <= 10 * ro.resid + 1e-12)
+    g = _run_gpu(prob, 1)
+    th = g["theta"]
+    assert th.size >= ro.theta.size
+    used = np.zeros(th.size, bool)
+    for t in ro.theta:
+        i = int(np.argmin(np.where(used, np.inf, np.abs(th - t))))
+        assert abs(th[i] - t) <= EIG_TOL * abs(t)
+        used[i] = True
+    assert np.all(th >= lam[:th.size] * (1 - 1e-12))
+    # M = I: some eigenvalue lies within ||A x - theta x|| / ||x|| = 8 resid
+    # (the residual is relative to the row-sum norm 8) of every Ritz value
+    for i in np.flatnonzero(~used):
+        assert np.min(np.abs(lam - th[i])) <= 8.0 * g["resid"][i] * (1 + 1e-6) + 1e-12
 
 
 def test_max_out_too_small_reports_count():
