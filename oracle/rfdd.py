@@ -16,7 +16,8 @@ import scipy.sparse as sp
 __all__ = [
     "quadrature", "rho", "DD", "schur", "factor_poles", "filter_apply", "filter_apply_streamed",
     "orth",
-    "filter_interface", "interior_basis", "interior_levels", "build_z",
+    "filter_interface", "filter_lanczos", "block_tridiagonal", "interior_basis",
+    "interior_levels", "build_z",
     "rayleigh_ritz", "residuals", "norm_a", "inertia_count", "run", "OracleResult",
 ]
 
@@ -242,6 +243,85 @@ def filter_interface(dd: DD, zeta, omega, Y0: np.ndarray, steps: int, factors=No
     return np.asfortranarray(K), factors
 
 
+LANCZOS_TOL = 1e-6    # Sec. 6: tolerance of the stopping test of Alg. 3.1
+LANCZOS_EVERY = 10    # Sec. 6: the test is applied every ten iterations
+
+
+def filter_lanczos(dd: DD, zeta, omega, Y0: np.ndarray, tol: float = LANCZOS_TOL,
+                   max_steps: int = 64, factors=None, streamed: bool = False,
+                   every: int = LANCZOS_EVERY, keep: Optional[dict] = None):
+    """Alg. 3.1 (Sec. 3.2), Lanczos restricted to the interface, run on a
+    block of m = Y0.shape[1] vectors with full reorthogonalisation, on
+    F = 2 Re sum_l omega_l S(zeta_l)^{-1} (eq. (3.5)):
+
+      Q_1 = orth(Y0)                               (the start block, line 0)
+      for t = 1, 2, ...:
+        W = F Q_t                                  (line 2)
+        A_t = Q_t^T W                              (line 3, a_mu = w^T q)
+        the sum of the eigenvalues of T_t is its trace, sum_i tr(A_i); the
+        process stops when it changed by at most tol (relative) since the
+        last test (line 13), the test running every `every` vectors
+        Q_{t+1} = orth(W) against Q_1..Q_t, twice  (lines 4-12; a vanishing
+        direction is dropped, line 8)
+        B_{t+1} = Q_{t+1}^T W                      (b_{mu+1})
+      Q = [Q_1 .. Q_t]                             (line 15)
+
+    Returns (Q, info) with info: steps, traces (after every block), the
+    blocks A_t and B_t (block tridiagonal T), converged."""
+    if streamed:
+        F = lambda X: filter_apply_streamed(dd, zeta, omega, X)
+    else:
+        if factors is None:
+            factors = factor_poles(dd, zeta)
+        F = lambda X: filter_apply(factors, omega, X)
+    m = Y0.shape[1]
+    test_blocks = max(1, -(-every // m))          # blocks per test of the stopping rule
+    Qt = orth(Y0)
+    K = Qt
+    As, Bs, traces = [], [], []
+    tr = 0.0
+    tr_test = None
+    converged = False
+    t = 0
+    while Qt.shape[1] > 0:
+        t += 1
+        W = F(Qt)
+        A = Qt.T @ W
+        As.append(A)
+        tr += float(np.trace(A))
+        traces.append(tr)
+        if t % test_blocks == 0:
+            if tr_test is not None and abs(tr - tr_test) <= tol * abs(tr):
+                converged = True
+                break
+            tr_test = tr
+        if t >= max_steps or K.shape[1] >= dd.s:
+            break
+        Qn = orth(W, K)
+        if Qn.shape[1] == 0:
+            break
+        Bs.append(Qn.T @ W)
+        K = np.hstack([K, Qn])
+        Qt = Qn
+    if keep is not None:
+        keep["F"] = F
+    return np.asfortranarray(K), dict(steps=t, traces=traces, A=As, B=Bs, converged=converged)
+
+
+def block_tridiagonal(info) -> np.ndarray:
+    """T_t of Alg. 3.1 in block form: diagonal blocks A_1..A_t, sub-diagonal
+    blocks B_2..B_t (B_{i+1} sits below A_i) and their transposes above."""
+    sizes = [a.shape[0] for a in info["A"]]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    T = np.zeros((off[-1], off[-1]))
+    for i, a in enumerate(info["A"]):
+        T[off[i]:off[i + 1], off[i]:off[i + 1]] = a
+    for i, b in enumerate(info["B"][:len(sizes) - 1]):
+        T[off[i + 1]:off[i + 2], off[i]:off[i + 1]] = b
+        T[off[i]:off[i + 1], off[i + 1]:off[i + 2]] = b.T
+    return T
+
+
 # ---------------------------------------------------------------------------
 # Sec. 4 / 5: interior part
 # ---------------------------------------------------------------------------
@@ -436,10 +516,12 @@ class OracleResult:
 
 
 def run(prob, want_vectors: bool = True, deflate_levels: bool = True,
-        streamed: bool = False) -> OracleResult:
+        streamed: bool = False, lanczos: Optional[dict] = None) -> OracleResult:
     """Alg. 5.1 on a workloads.Problem.  streamed=True: sparse C, M_C and one
     pole's S(zeta) at a time (filter_apply_streamed), for the largest
-    pencils; the arithmetic is that of the default path."""
+    pencils; the arithmetic is that of the default path.  lanczos = dict(tol=,
+    max_steps=) computes Q by filter_lanczos (Alg. 3.1 with its stopping test)
+    instead of prob.steps fixed block-Krylov steps."""
     t = {}
     t0 = time.perf_counter()
     dd = DD(prob.A, prob.M, prob.part, dense_interface=not streamed)
@@ -450,7 +532,12 @@ def run(prob, want_vectors: bool = True, deflate_levels: bool = True,
     t["interior_basis"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     kept = {}
-    Q, _ = filter_interface(dd, zeta, omega, prob.Y0, prob.steps, streamed=streamed, keep=kept)
+    if lanczos is not None:
+        Q, info = filter_lanczos(dd, zeta, omega, prob.Y0, streamed=streamed, **lanczos)
+        t["lanczos_steps"] = info["steps"]
+    else:
+        Q, _ = filter_interface(dd, zeta, omega, prob.Y0, prob.steps, streamed=streamed,
+                                keep=kept)
     t["filter"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     Sig, Gam = interior_levels(dd, prob.sigma, prob.psi, Q, V if deflate_levels else None)

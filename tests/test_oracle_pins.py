@@ -467,3 +467,63 @@ def test_streamed_run_equals_the_default_run():
     assert a.theta.size == b.theta.size == 6
     assert np.max(np.abs(a.theta - b.theta) / a.theta) <= 1e-13
     assert np.max(np.abs(a.W1 - b.W1)) <= 1e-14 * np.max(np.abs(a.W1))
+
+
+# ---------------------------------------------------------------- Alg. 3.1 (Lanczos)
+def _lanczos_case(m=3, n_c=6, tol=0.0, max_steps=6, cfg=63):
+    prob = W.tiny(N=13, P=3, nev=6, n_c=n_c, m=m, steps=1, nev_b=6, psi=3,
+                  mass_kind="random", cfg_id=cfg)
+    dd = O.DD(prob.A, prob.M, prob.part)
+    z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
+    fac = O.factor_poles(dd, z)
+    Q, info = O.filter_lanczos(dd, z, w, prob.Y0, tol=tol, max_steps=max_steps, factors=fac)
+    return prob, dd, z, w, fac, Q, info
+
+
+def test_lanczos_recurrence_is_the_projection_of_the_filter():
+    """With full reorthogonalisation the block tridiagonal T_t built from the
+    recurrence's A_t, B_t equals Q^T F Q for the filter of eq. (3.5) applied
+    independently to the whole basis, including the zeros outside the band
+    (the three-term structure of Lanczos)."""
+    prob, dd, z, w, fac, Q, info = _lanczos_case()
+    assert info["steps"] == 6 and Q.shape[1] == 18
+    assert np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1]))) < 1e-13
+    P = Q.T @ O.filter_apply(fac, w, Q)
+    T = O.block_tridiagonal(info)
+    assert np.max(np.abs(T - P)) <= 1e-12 * np.max(np.abs(P))
+    # the sum of the eigenvalues of T_t is the traced quantity of the stopping test
+    assert abs(np.sum(np.linalg.eigvalsh(T)) - info["traces"][-1]) <= 1e-12 * abs(info["traces"][-1])
+    # a recurrence without the reorthogonalisation against older blocks would
+    # leave T != Q^T F Q: a planted mistake (A and B swapped) fails
+    bad = dict(info, A=[info["A"][0]] + info["B"][:5], B=info["A"][1:])
+    assert np.max(np.abs(O.block_tridiagonal(bad) - P)) > 1e-3 * np.max(np.abs(P))
+
+
+def test_lanczos_starts_from_the_start_block():
+    prob, dd, z, w, fac, Q, info = _lanczos_case(max_steps=2)
+    # Q_1 spans Y0 (line 0 of Alg. 3.1 normalises the start vector)
+    Y = prob.Y0
+    assert np.max(np.abs(Y - Q[:, :3] @ (Q[:, :3].T @ Y))) < 1e-13 * np.max(np.abs(Y))
+    assert np.allclose(info["A"][0], Q[:, :3].T @ O.filter_apply(fac, w, Q[:, :3]), atol=1e-14)
+
+
+def test_lanczos_terminates_early_and_captures_the_wanted_subspace():
+    """Prop. 3.1 / Sec. 3.2: the trace of T_t stops growing once the range of
+    F is captured, before the interface is exhausted; the resulting Q gives
+    the eigenvalues of the pencil after the interior part and Rayleigh-Ritz."""
+    prob = W.tiny(N=21, P=2, nev=8, n_c=8, m=4, steps=1, nev_b=30, psi=6, mass_kind="random",
+                  cfg_id=64)
+    dd = O.DD(prob.A, prob.M, prob.part)
+    z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
+    Q, info = O.filter_lanczos(dd, z, w, prob.Y0, tol=1e-6, max_steps=200)
+    assert info["converged"]
+    assert Q.shape[1] < dd.s
+    # successive traces settle: the last relative change is within the tolerance
+    tr = info["traces"]
+    assert abs(tr[-1] - tr[-4]) <= 1e-6 * abs(tr[-1])    # tested every 10 vectors = 3 blocks of 4
+    r = O.run(prob, lanczos=dict(tol=1e-6, max_steps=200))
+    lam = sl.eigh(prob.A.toarray(), prob.M.toarray(), eigvals_only=True)
+    ex = lam[(lam >= prob.alpha) & (lam <= prob.beta)]
+    assert r.theta.size == ex.size == 8
+    assert np.max(np.abs(r.theta - ex) / ex) < 1e-9
+    assert r.mu == Q.shape[1]
