@@ -1,18 +1,24 @@
 """Benchmark of the RF-DDES path on one MI355X.
 
-Headline (one JSON line on stdout): a step is one complete solve of the 2D
-255x255 pencil with diagonal random M (n = 65025, 64 subdomains of 31x31,
-interface s = 3521, the lowest 200 eigenvalues, 8 Gauss-Legendre poles,
-block of 300, 2 block-Krylov steps, nev_b = 20, psi = 4): every
-factorization is recomputed (caches invalidated), then filter_interface,
-solve_interior and rayleigh_ritz with eigenvectors and residuals.  The
-pencil and the starting block are resident on the device before the timed
-region.  Every step's Ritz values are checked against the CPU oracle's
-stored values (tests/golden/oracle_c2.json); only eigenpairs within 1e-10
-relative error are counted.  Both precision modes run: FP32 factors with
-FP64 refinement to the 1e-10 target (the value) and plain FP64 (beside it).
+Headline (one JSON line on stdout): a step is one complete solve of the 3D
+63^3 pencil with diagonal random M (n = 250047, 64 subdomains of 15^3,
+interface s = 34047 split into 8 octant groups and the 11719-node central
+separator, the lowest 500 eigenvalues, 8 Gauss-Legendre poles, block of 700,
+4 block-Krylov steps, nev_b = 40, psi = 4): every factorization is
+recomputed (caches invalidated), then filter_interface, solve_interior and
+rayleigh_ritz with eigenvectors and residuals.  The pencil and the starting
+block are resident on the device before the timed region.  A Ritz value
+counts when it lies within 1e-10 (relative) of the reference eigenvalue of
+the same rank (tests/golden/reference_c3.json); the count that also asks
+for a residual ||Ax - theta Mx|| / (||A|| ||x||) <= 1e-9 is reported beside
+it.  Both precision modes run: FP32 factors with FP64 refinement to the
+1e-10 target (the value) and plain FP64 (beside it).
 
 Beside the headline:
+  c2       -- the 2D 255x255 pencil (n = 65025, 64 subdomains, 200
+              eigenvalues, 5 block steps, nev_b 40, psi 6), both modes,
+              counted against the oracle's stored Ritz values
+              (tests/golden/oracle_c2.json) and the residual target;
   batched  -- pencils of the batched workload (variable coefficient, random
               M, uneven sizes) run as one rfd_batch_run on several worker
               streams, against the same jobs on one worker;
@@ -20,12 +26,11 @@ Beside the headline:
               31x31, 255x255 and two batched-workload pencils, replayed at
               0.5x and 0.8x the measured saturated rate: p50 / p99 latency
               and throughput;
-  roofline -- the hand-written kernel with the most summed time, the
-              trailing-block mat-vec of the Householder tridiagonalization
-              (HBM-bound), and as roofline_mfma the FP32 complex GEMM (LU
+  roofline -- the hand-written kernel with the most summed time over the
+              timed steps and, as roofline_mfma, the FP32 complex GEMM (LU
               updates and triangular solves of the shifted blocks and of S),
-              each timed per launch with HIP events over the timed steps;
-  cpu_baseline -- the CPU oracle on a bounded sample of the same workload.
+              each timed per launch with HIP events stamped by the launch;
+  cpu_baseline -- the CPU oracle on a bounded sample of the 63^3 workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp32|fp64|both]
 """
@@ -52,9 +57,12 @@ def rule_of(R, prob):
     return R.RFD_RULE_GAUSS if prob.rule == "gauss" else R.RFD_RULE_MIDPOINT
 
 
-def make_pencil(R, prob, mode, refine_tol=0.0):
+def make_pencil(R, W, prob, mode, refine_tol=0.0):
     P = R.Pencil(prob.A, prob.M)
     P.set_partition(prob.part)
+    groups = W.interface_groups(prob.grid, prob.meta["P"])
+    if groups is not None:
+        P.set_interface_groups(groups)
     P.set_interval_and_poles(prob.alpha, prob.beta, prob.n_c, rule_of(R, prob))
     P.set_precision(R.RFD_FP32_REFINE if mode == "fp32" else R.RFD_FP64, refine_tol)
     return P
@@ -70,15 +78,23 @@ def one_step(P, prob, Y0):
     return ev, r, k
 
 
-def count_good(th, ref, tol=1e-10):
+RESID_TARGET = 1e-9
+
+
+def count_good(th, ref, resid=None, tol=1e-10):
     """Reference eigenvalues matched by a Ritz value within tol (relative),
     pairing the two ascending lists in order (a Ritz value serves one
-    eigenvalue); and the largest relative error when the counts agree."""
-    th, ref = np.sort(th), np.sort(ref)
-    i = j = good = 0
+    eigenvalue); the same count restricted to pairs whose residual is at most
+    RESID_TARGET; and the largest relative error when the counts agree."""
+    order = np.argsort(th)
+    th, ref = th[order], np.sort(ref)
+    rs = None if resid is None else np.asarray(resid)[order]
+    i = j = good = strict = 0
     while i < ref.size and j < th.size:
         if abs(th[j] - ref[i]) <= tol * abs(ref[i]):
             good += 1
+            if rs is not None and rs[j] <= RESID_TARGET:
+                strict += 1
             i += 1
             j += 1
         elif th[j] < ref[i]:
@@ -86,11 +102,11 @@ def count_good(th, ref, tol=1e-10):
         else:
             i += 1
     err = float(np.max(np.abs(th - ref) / np.abs(ref))) if th.size == ref.size and th.size else float("inf")
-    return good, err
+    return good, strict, err
 
 
-def run_mode(R, prob, mode, steps, warmup, ref, torch, refine_tol, account):
-    P = make_pencil(R, prob, mode, refine_tol)
+def run_mode(R, W, prob, mode, steps, warmup, ref, torch, refine_tol, account):
+    P = make_pencil(R, W, prob, mode, refine_tol)
     Y0 = torch.from_numpy(np.ascontiguousarray(prob.Y0.T)).cuda()
     for _ in range(warmup):
         one_step(P, prob, Y0)
@@ -100,7 +116,7 @@ def run_mode(R, prob, mode, steps, warmup, ref, torch, refine_tol, account):
     if account:
         R.rfd_kernel_accounting(ACCOUNT_EVERY)
         R.rfd_kernel_stats()               # clear
-    lat, outs, good, errs, res = [], [], [], [], []
+    lat, outs, good, strict, errs, res = [], [], [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -112,32 +128,52 @@ def run_mode(R, prob, mode, steps, warmup, ref, torch, refine_tol, account):
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     for ev, r in outs:
-        g, e = count_good(ev.cpu().numpy(), ref)
+        rr = r.cpu().numpy()
+        g, gs, e = count_good(ev.cpu().numpy(), ref, rr)
         good.append(g)
+        strict.append(gs)
         errs.append(e)
-        res.append(float(r.max().item()) if r.numel() else 0.0)
+        res.append(float(rr.max()) if rr.size else 0.0)
     kstats = None
     if account:
         kstats = R.rfd_kernel_stats()
         R.rfd_kernel_accounting(0)
     ph = P.phase_times() / steps
     P.close()
-    return dict(total=total, lat=lat, good=good, errs=errs, resid=res, phases=ph, k=k,
-                kstats=kstats)
+    del Y0, outs
+    torch.cuda.empty_cache()
+    return dict(total=total, lat=lat, good=good, strict=strict, errs=errs, resid=res, phases=ph,
+                k=k, kstats=kstats, steps=steps)
+
+
+def summary(r, prob):
+    sps = r["total"] / r["steps"]
+    lat = np.array(r["lat"]) * 1e3
+    return {"value": min(r["good"]) / sps, "eigenpairs": min(r["good"]),
+            "value_resid_1e-9": min(r["strict"]) / sps, "eigenpairs_resid_1e-9": min(r["strict"]),
+            "ms_per_step": 1e3 * sps, "steps": r["steps"],
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99))},
+            "max_rel_err": max(r["errs"]), "max_resid": max(r["resid"]), "rr_columns": r["k"],
+            "phases_ms": np.round(r["phases"][:12], 2).tolist(),
+            "refinement_sweeps": r["phases"][12:14].tolist()}
 
 
 # ---------------------------------------------------------------------------
 # roofline entries
 # ---------------------------------------------------------------------------
 # HBM traffic per launch measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE,
-# scaled by a plain copy of known size) is kept in profiles/<kernel>_c2.md
-# together with the hash of the source file the kernel lives in; it is
-# reported only while that source is unchanged.
-PROFILE_OF = {"k_tri_symv": ("tri_symv_c2.md", "eig.hip"),
-              "k_gemm<float, true, false, false>": ("gemm_c32_nn_c2.md", "gemm.hip")}
+# scaled by a plain copy of known size) is kept in profiles/ together with
+# the workload it was measured on and the hash of the source file the kernel
+# lives in; it is reported only for that workload while that source is
+# unchanged.
+PROFILE_OF = {"k_tri_symv": ("tri_symv_63cube.md", "eig.hip"),
+              "k_gemm<float, true, false, false>": ("gemm_c32_nn_63cube.md", "gemm.hip"),
+              "k_gemm<double, false, true, false>": ("gemm_d_tn_63cube.md", "gemm.hip"),
+              "k_gemm<double, false, false, false>": ("gemm_d_nn_63cube.md", "gemm.hip")}
 
 
-def measured_traffic(kname):
+def measured_traffic(kname, workload):
     import hashlib
     import re
     if kname not in PROFILE_OF:
@@ -149,14 +185,15 @@ def measured_traffic(kname):
     txt = open(path).read()
     m1 = re.search(r"traffic_bytes_per_launch\s*=\s*([0-9.eE+]+)", txt)
     m2 = re.search(r"source_sha256\s*=\s*([0-9a-f]{64})", txt)
-    if not (m1 and m2):
+    m3 = re.search(r"workload\s*=\s*(.+)", txt)
+    if not (m1 and m2 and m3) or m3.group(1).strip() != workload:
         return None
     cur = hashlib.sha256(open(os.path.join(ROOT, "paper_1711_09487_amd", "csrc", src),
                               "rb").read()).hexdigest()
     return float(m1.group(1)) if cur == m2.group(1) else None
 
 
-def roofline_entry(kname, st, f32, steps):
+def roofline_entry(kname, st, f32, steps, workload):
     launches, sampled, ms, flops, byts = st
     if kname == "k_tri_symv":
         achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -164,14 +201,20 @@ def roofline_entry(kname, st, f32, steps):
              "kernel": "k_tri_symv (trailing-block mat-vec of the Householder tridiagonalization)"}
     else:
         peak = FP32_MFMA_PEAK if "float" in kname else FP64_PEAK
-        achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-        e = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-             "kernel": f"{kname} (LU updates and triangular solves)"}
+        rate = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        e = {"bound": "mfma", "peak": peak, "unit": "TFLOP/s",
+             "kernel": f"{kname} (LU updates, triangular solves, products)"}
         if "float, true" in kname:
-            e["flops_counted"] = ("8 per complex multiply-add; the kernel runs three real "
-                                  "products (Gauss), 6 flops on the matrix cores")
+            # Gauss's three real products: 6 flops per complex multiply-add run
+            # on the matrix cores; the 8-flop rate is the effective one
+            e["achieved"] = 0.75 * rate
+            e["achieved_effective_8_flops_per_complex_fma"] = rate
+            e["flops_counted"] = ("executed: 6 per complex multiply-add (three real products); "
+                                  "the effective rate counts 8")
+        else:
+            e["achieved"] = rate
     e["frac"] = e["achieved"] / e["peak"]
-    e["traffic"] = measured_traffic(kname)
+    e["traffic"] = measured_traffic(kname, workload)
     e["launches_per_step"] = launches / steps
     e["sampled_launches"] = sampled
     e["avg_launch_us"] = 1e3 * ms / max(sampled, 1)
@@ -218,7 +261,7 @@ def batch_leg(R, W, torch, count, workers):
         for j, pr in zip(js, probs):
             ev = j.outputs()[0].cpu().numpy()
             found += ev.size
-            g, _ = count_good(ev, pr.exact[:pr.nev])
+            g, _, _ = count_good(ev, pr.exact[:pr.nev])
             good += g
         out[w] = dict(wall=wall, good=good, found=found)
     for P in pens:
@@ -237,30 +280,35 @@ def batch_leg(R, W, torch, count, workers):
 # ---------------------------------------------------------------------------
 # serving leg
 # ---------------------------------------------------------------------------
-def serve_leg(R, W, torch, prob2, gold2, nreq, workers):
+SERVE_STEPS = {"C1": 2, "C2": 3, "C3": 3}
+
+
+def serve_leg(R, W, torch, prob2, gold2, prob3, lam3, nreq, workers):
+    """Spectrum-slicing requests on the 31x31, 255x255 and 63^3 pencils
+    (weights 0.6 / 0.3 / 0.1), Poisson arrivals replayed at 0.5x and 0.8x the
+    saturated rate; the pencils keep their maps, two-level grouping and
+    caches between requests (admission by device-memory footprint)."""
     import scipy.linalg as sl
     c1 = W.config(1)
-    pencils = {"C1": c1, "C2": prob2}
+    pencils = {"C1": c1, "C2": prob2, "C3": prob3}
     spectra = {"C1": sl.eigh(c1.A.toarray(), c1.M.toarray(), eigvals_only=True),
-               "C2": np.array(gold2["reference_eigs"])}
-    for b, spec in enumerate(W.batch_specs(256)):
-        if spec["N"] >= 100 and spec["P"] == 2 and "B" not in pencils:
-            pb = W.batch_problem(b, spec)
-            pencils["B"] = pb
-            spectra["B"] = W.lowest_eigs(pb.A, pb.M, 120)
-            break
-    weights = {"C1": 0.6, "C2": 0.3, "B": 0.1}
+               "C2": np.array(gold2["reference_eigs"]), "C3": np.asarray(lam3)}
+    weights = {"C1": 0.6, "C2": 0.3, "C3": 0.1}
     reqs, gaps = W.serving_requests(nreq, spectra, weights)
     replicas = {nm: [] for nm in pencils}
     for nm, pr in pencils.items():
-        for _ in range(2):
+        groups = W.interface_groups(pr.grid, pr.meta["P"])
+        for _ in range(1 if nm == "C3" else 2):
             P = R.Pencil(pr.A, pr.M)
             P.set_partition(pr.part)
+            if groups is not None:
+                P.set_interface_groups(groups)
             replicas[nm].append(P)
 
     def build(i, rq):
         pr = pencils[rq["pencil"]]
-        P = replicas[rq["pencil"]][i % 2]
+        reps = replicas[rq["pencil"]]
+        P = reps[i % len(reps)]
         k = rq["k"]
         m = min(pr.s, int(math.ceil(1.5 * k)))
         y = np.random.default_rng([5, 1, i]).standard_normal((m, pr.s))
@@ -268,13 +316,13 @@ def serve_leg(R, W, torch, prob2, gold2, nreq, workers):
         a, b = rq["alpha"], rq["beta"]
         # interior basis sized with the slice: 1.5 k over the subdomains
         nev_b = max(20, int(math.ceil(1.5 * k / pr.p)) + 10)
-        return R.Job(P, a, b, 8, Y0, 2, 0.5 * (a + b), nev_b, 6, k + 40,
+        return R.Job(P, a, b, 8, Y0, SERVE_STEPS[rq["pencil"]], 0.5 * (a + b), nev_b, 6, k + 40,
                      mode=R.RFD_FP32_REFINE, refine_tol=TARGET_TOL, vectors=True)
 
     def check(rq, job):
         lam = spectra[rq["pencil"]][rq["i0"] - 1: rq["i0"] - 1 + rq["k"]]
         ev = job.outputs()[0].cpu().numpy()
-        g, _ = count_good(ev, lam)
+        g, _, _ = count_good(ev, lam)
         return g
 
     def replay(qps):
@@ -302,20 +350,38 @@ def serve_leg(R, W, torch, prob2, gold2, nreq, workers):
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        good = sum(check(rq, j) for rq, j in zip(reqs, jobs))
+        per = {}
+        good = 0
+        for rq, j in zip(reqs, jobs):
+            g = check(rq, j)
+            good += g
+            d = per.setdefault(rq["pencil"], dict(requests=0, eigenpairs=0, wanted=0))
+            d["requests"] += 1
+            d["eigenpairs"] += g
+            d["wanted"] += rq["k"]
         want = sum(rq["k"] for rq in reqs)
         L = np.array([lat[q] for q in range(len(jobs))]) * 1e3
+        for nm in per:
+            Ln = np.array([lat[q] for q, rq in enumerate(reqs) if rq["pencil"] == nm]) * 1e3
+            per[nm]["p50_ms"] = float(np.percentile(Ln, 50))
+            per[nm]["p99_ms"] = float(np.percentile(Ln, 99))
+        del jobs
+        torch.cuda.empty_cache()
         return dict(wall_s=wall, eigenpairs=good, eigenpairs_wanted=want,
                     throughput=good / wall, p50_ms=float(np.percentile(L, 50)),
-                    p99_ms=float(np.percentile(L, 99)), evictions=st["evictions"])
+                    p99_ms=float(np.percentile(L, 99)), evictions=st["evictions"],
+                    cache_hits=st["cache_hits"], cache_misses=st["cache_misses"], per_pencil=per)
 
     replay(None)                                   # first use of every pencil
     sat = replay(None)                             # all requests at once
     rate = nreq / sat["wall_s"]
-    out = {"requests": nreq, "workers": workers, "replicas_per_pencil": 2,
-           "interior": "nev_b = max(20, ceil(1.5 k / p) + 10), psi = 6, 2 block steps, m = min(s, 1.5 k)",
-           "mix": weights, "pencils": {nm: pr.name for nm, pr in pencils.items()},
+    out = {"requests": nreq, "workers": workers,
+           "replicas_per_pencil": {nm: len(v) for nm, v in replicas.items()},
+           "interior": "nev_b = max(20, ceil(1.5 k / p) + 10), psi = 6, m = min(s, 1.5 k)",
+           "block_steps": SERVE_STEPS, "mix": weights,
+           "pencils": {nm: pr.name for nm, pr in pencils.items()},
            "mode": "fp32+refine", "unit_latency": "ms", "unit_throughput": "eigenpairs/s",
+           "counted": "Ritz values within 1e-10 of the reference eigenvalues of the slice",
            "saturated": dict(sat, requests_per_s=rate)}
     for frac in (0.5, 0.8):
         out[f"qps_{frac}x"] = dict(replay(frac * rate), qps=frac * rate)
@@ -328,69 +394,117 @@ def serve_leg(R, W, torch, prob2, gold2, nreq, workers):
 # ---------------------------------------------------------------------------
 # CPU oracle on a bounded sample
 # ---------------------------------------------------------------------------
-def cpu_baseline(prob, gold):
-    """The oracle (unchanged) on a bounded sample of the same workload: pole 1
-    of n_c with 16 of the 64 subdomains (Schur contributions, interior basis,
-    resolvent levels), one S(zeta) LU and solve, and a Rayleigh-Ritz on a
-    quarter of the columns; the full-job time is extrapolated linearly in
-    poles, subdomains and block steps and cubically in Rayleigh-Ritz columns
-    (its dense eigensolve dominates)."""
+def cpu_baseline(prob, k_rr):
+    """The oracle (unchanged) on a bounded sample of the 63^3 workload, timed
+    on this host's cores, and the full job extrapolated from it.
+
+    Sample: the pencil restricted to the box x < 32, y < 16, z < 16 of the
+    grid (two whole 15^3 subdomains and their separators, Dirichlet-cut
+    beyond) runs the oracle's Schur assembly for one pole; one of the two
+    subdomains runs the oracle's subdomain eigenpairs and resolvent levels
+    for one block of m columns; the oracle's LU and block solve run on a 4096
+    x 4096 complex S-sized sample; and the oracle's Rayleigh-Ritz runs on the
+    full pencil with 1/32 of the columns.  Extrapolation: Schur assembly
+    linearly in subdomains (64 / 2), interior work linearly in subdomains and
+    columns, the S LU cubically and its solves quadratically in the interface
+    size (34047 / 4096), poles x block steps factorizations (the oracle
+    streams the poles: every block step factors again), and Rayleigh-Ritz
+    quadratically in its columns (its n k^2 QR dominates)."""
     import oracle as O
     import scipy.linalg as sl
+    coords = np.indices(prob.grid[::-1]).reshape(3, -1)[::-1]
+    box = np.flatnonzero((coords[0] < 32) & (coords[1] < 16) & (coords[2] < 16))
+    part = prob.part[box].copy()
+    used = np.unique(part[part >= 0])
+    remap = -np.ones(int(part.max()) + 1, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    part[part >= 0] = remap[part[part >= 0]]
     t = {}
     t0 = time.perf_counter()
-    dd = O.DD(prob.A, prob.M, prob.part)
+    dd = O.DD(prob.A[box][:, box], prob.M[box][:, box], part)
     t["setup"] = time.perf_counter() - t0
     z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
-    sub = 16
-    full_p = dd.p
+    t0 = time.perf_counter()
+    O.schur(dd, z[0])
+    t["schur_2_subdomains"] = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    ns = 4096
+    Ss = np.asfortranarray(rng.standard_normal((ns, ns)) + 1j * rng.standard_normal((ns, ns)))
+    t0 = time.perf_counter()
+    f = sl.lu_factor(Ss, overwrite_a=True, check_finite=False)
+    t["slu_4096"] = time.perf_counter() - t0
+    Y = rng.standard_normal((ns, prob.m))
+    t0 = time.perf_counter()
+    O.filter_apply([f], [w[0]], Y)
+    t["fsolve_4096"] = time.perf_counter() - t0
+    del Ss, f, Y
     for attr in ("interior", "adj", "B", "MB", "E", "ME"):
-        setattr(dd, attr, getattr(dd, attr)[:sub])
-    dd.p = sub
-    t0 = time.perf_counter()
-    S = O.schur(dd, z[0])
-    t["schur_sub"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    f = sl.lu_factor(S, check_finite=False)
-    t["slu"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    O.filter_apply([f], [w[0]], prob.Y0)
-    t["fsolve"] = time.perf_counter() - t0
+        setattr(dd, attr, getattr(dd, attr)[:1])
+    dd.p = 1
     t0 = time.perf_counter()
     V, _ = O.interior_basis(dd, prob.sigma, prob.nev_b)
-    t["vbasis_sub"] = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
-    mu = gold["mu"]
-    Q, _ = np.linalg.qr(rng.standard_normal((dd.s, mu)))
+    t["vbasis_1_subdomain"] = time.perf_counter() - t0
+    q = min(prob.m, dd.s)
+    Qs, _ = np.linalg.qr(rng.standard_normal((dd.s, q)))
     t0 = time.perf_counter()
-    O.interior_levels(dd, prob.sigma, prob.psi, Q, V)
-    t["levels_sub"] = time.perf_counter() - t0
-    kq = gold["k"] // 4
-    dd2 = O.DD(prob.A, prob.M, prob.part)
-    Zs = rng.standard_normal((dd2.n, kq))
+    O.interior_levels(dd, prob.sigma, prob.psi, Qs, V)
+    t["levels_1_subdomain"] = time.perf_counter() - t0
+    del dd
+    ddf = O.DD.__new__(O.DD)           # the full pencil's reordering for Rayleigh-Ritz
+    ddf.A, ddf.M, ddf.part = prob.A, prob.M, prob.part
+    ddf.interior = [np.flatnonzero(prob.part == j) for j in range(prob.p)]
+    ddf.iface = np.flatnonzero(prob.part < 0)
+    kq = max(1, k_rr // 32)
+    Zs = rng.standard_normal((prob.n, kq))
     t0 = time.perf_counter()
-    O.rayleigh_ritz(dd2, Zs, prob.alpha, prob.beta)
-    t["rr_quarter"] = time.perf_counter() - t0
+    O.rayleigh_ritz(ddf, Zs, prob.alpha, prob.beta)
+    t["rr_1_32"] = time.perf_counter() - t0
+    del Zs
     sample = sum(t.values())
-    scale_sub = full_p / sub
-    est = (t["setup"] + prob.n_c * (scale_sub * t["schur_sub"] + t["slu"])
-           + prob.steps * prob.n_c * t["fsolve"] + scale_sub * (t["vbasis_sub"] + t["levels_sub"])
-           + 64.0 * t["rr_quarter"])
+    mu = prob.steps * prob.m
+    sr = prob.s / ns
+    passes = prob.n_c * prob.steps
+    est = (t["setup"] * prob.p / used.size
+           + passes * (prob.p / used.size * t["schur_2_subdomains"] + sr ** 3 * t["slu_4096"]
+                       + sr ** 2 * t["fsolve_4096"])
+           + prob.p * (t["vbasis_1_subdomain"] + t["levels_1_subdomain"] * mu / q)
+           + (k_rr / kq) ** 2 * t["rr_1_32"])
     threads = os.environ.get("OMP_NUM_THREADS")
     cores = int(threads) if threads else os.cpu_count()
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=prob.nev / est, unit="eigenpairs/s", cores=cores, kind="oracle",
-                sample=(f"oracle phases on pole 1 of {prob.n_c}, {sub} of {full_p} subdomains, one "
-                        f"S LU + solve, Rayleigh-Ritz on {kq} of {gold['k']} columns; "
-                        f"{sample:.1f} s sampled, full job extrapolated to {est:.1f} s"),
+                cpu_model=cpu,
+                sample=(f"oracle on the 63^3 pencil: one pole's Schur assembly on 2 of {prob.p} "
+                        f"subdomains, S LU and a {prob.m}-column solve at {ns} of {prob.s}, "
+                        f"subdomain eigenpairs and levels on 1 subdomain, Rayleigh-Ritz on "
+                        f"{kq} of {k_rr} columns; {sample:.1f} s sampled, full job extrapolated "
+                        f"to {est:.0f} s"),
                 seconds_sampled=sample, seconds_full_estimate=est, phases=t)
+
+
+def load_c3(W):
+    ref = json.load(open(os.path.join(ROOT, "tests", "golden", "reference_c3.json")))
+    lam = np.array(ref["reference_eigs"])
+    return W.config(3, known=(ref["alpha"], ref["beta"], lam)), lam
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="timed FP64 solves of the headline workload beside the FP32 ones")
     ap.add_argument("--mode", default="both", choices=["fp32", "fp64", "both"])
+    ap.add_argument("--c2-steps", type=int, default=5,
+                    help="timed solves per mode of the 255x255 workload (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--refine-tol", type=float, default=TARGET_TOL,
                     help="FP32 refinement tolerance (relative max-norm residual)")
@@ -420,72 +534,92 @@ def main():
         torch.cuda.synchronize()
         print(f"# copy kernel: {nel * 8} bytes read, {nel * 8} bytes written", file=sys.stderr)
         del src, dst
-    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_c2.json")))
-    prob = W.config(2)
-    ref = np.array(gold["theta"])
+    prob, lam = load_c3(W)
+    ref = lam[:prob.nev]
     print(f"# workload {prob.name}: n={prob.n} p={prob.p} s={prob.s} m={prob.m} "
-          f"steps={prob.steps} n_c={prob.n_c}", file=sys.stderr, flush=True)
+          f"steps={prob.steps} nev_b={prob.nev_b} psi={prob.psi} n_c={prob.n_c}",
+          file=sys.stderr, flush=True)
     modes = ["fp32", "fp64"] if a.mode == "both" else [a.mode]
     res = {}
     for mode in modes:
-        res[mode] = run_mode(R, prob, mode, a.steps, a.warmup, ref, torch, a.refine_tol,
+        k = a.steps if (mode == "fp32" or a.mode == "fp64") else a.fp64_steps
+        res[mode] = run_mode(R, W, prob, mode, k, a.warmup, ref, torch, a.refine_tol,
                              account=True)
         r = res[mode]
-        print(f"# {mode}: {1e3 * r['total'] / a.steps:.1f} ms/step, max rel err "
-              f"{max(r['errs']):.2e}, good {min(r['good'])}/{prob.nev}, phases(ms) "
-              f"{np.round(r['phases'][:12], 2).tolist()} sweeps {r['phases'][12:14].tolist()}",
+        print(f"# {mode}: {1e3 * r['total'] / k:.1f} ms/step, max rel err "
+              f"{max(r['errs']):.2e}, good {min(r['good'])}/{prob.nev}, with resid<=1e-9 "
+              f"{min(r['strict'])}, max resid {max(r['resid']):.2e}, phases(ms) "
+              f"{np.round(r['phases'][:12], 1).tolist()} sweeps {r['phases'][12:14].tolist()}",
               file=sys.stderr, flush=True)
     head = res["fp32"] if "fp32" in res else res[modes[0]]
-    ms = 1e3 * head["total"] / a.steps
-    lat = np.array(head["lat"]) * 1e3
-    value = min(head["good"]) / (head["total"] / a.steps)
+    hs = summary(head, prob)
     # roofline of the dominant accounted kernel (largest summed time over the
     # timed steps), and of the complex GEMM on the matrix cores beside it
     f32 = "fp32" in res and head is res["fp32"]
     ks = head["kstats"]
     # (summed time scaled from the sampled launches to all launches)
-    own = {k: v for k, v in ks.items() if k != "rocblas_dgemm"}
-    dom = max(own, key=lambda k: own[k][2] * own[k][0] / max(own[k][1], 1))
-    roof = roofline_entry(dom, ks[dom], f32, a.steps)
+    dom = max(ks, key=lambda k: ks[k][2] * ks[k][0] / max(ks[k][1], 1))
+    roof = roofline_entry(dom, ks[dom], f32, head["steps"], prob.name)
     gname = R.GEMM_KEYS[(0 if f32 else 8) + 4]
-    roof_mfma = roofline_entry(gname, ks.get(gname, (0, 0, 0.0, 0.0, 0.0)), f32, a.steps)
+    roof_mfma = roofline_entry(gname, ks.get(gname, (0, 0, 0.0, 0.0, 0.0)), f32, head["steps"],
+                               prob.name)
     out = {
         "metric": "eigenpairs/sec at 1e-10 rel err, FP32+refine batched vs FP64; p50/p99",
-        "value": value, "unit": "eigenpairs/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64" if f32 else "f64",
+        "value": hs["value"], "unit": "eigenpairs/s", "n_gpus": 1, "steps": head["steps"],
+        "warmup": a.warmup, "ms_per_step": hs["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if f32 else "f64",
         "data": "synthetic",
         "config": {"workload": prob.name, "n": prob.n, "p": prob.p, "s": prob.s,
+                   "interface_groups": "8 octants + central separator (11719 nodes)",
                    "nev": prob.nev, "n_c": prob.n_c, "m": prob.m, "block_steps": prob.steps,
                    "nev_b": prob.nev_b, "psi": prob.psi, "rr_columns": head["k"],
                    "refine_tol": a.refine_tol},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "accuracy": {"max_rel_err_vs_oracle": max(head["errs"]),
-                     "max_resid": max(head["resid"])},
+        "counted": ("Ritz values within 1e-10 of the reference eigenvalue of the same rank "
+                    "(ARPACK shift-invert, tol 1e-13, tests/golden/reference_c3.json)"),
+        "latency_ms": hs["latency_ms"],
+        "accuracy": {"max_rel_err_vs_reference": hs["max_rel_err"], "max_resid": hs["max_resid"],
+                     "eigenpairs": hs["eigenpairs"],
+                     "eigenpairs_with_resid_le_1e-9": hs["eigenpairs_resid_1e-9"],
+                     "value_with_resid_le_1e-9": hs["value_resid_1e-9"]},
         "roofline": roof,
         "roofline_mfma": roof_mfma,
     }
     if "fp64" in res and "fp32" in res:
-        f64 = res["fp64"]
-        out["fp64"] = {"value": min(f64["good"]) / (f64["total"] / a.steps),
-                       "ms_per_step": 1e3 * f64["total"] / a.steps,
-                       "max_rel_err_vs_oracle": max(f64["errs"])}
-        out["fp32_over_fp64"] = out["value"] / out["fp64"]["value"]
+        out["fp64"] = summary(res["fp64"], prob)
+        out["fp32_over_fp64"] = out["value"] / max(out["fp64"]["value"], 1e-30)
     out["phases_ms"] = {m: np.round(res[m]["phases"][:12], 3).tolist() for m in res}
     out["kernels"] = {m: {k: dict(launches=v[0], sampled=v[1],
-                                  ms_per_step=v[2] * v[0] / max(v[1], 1) / a.steps,
+                                  ms_per_step=v[2] * v[0] / max(v[1], 1) / res[m]["steps"],
                                   tflops=v[3] / max(v[2], 1e-9) / 1e9,
                                   gbps=v[4] / max(v[2], 1e-9) / 1e6)
                           for k, v in res[m]["kstats"].items()} for m in res}
+    gold2 = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_c2.json")))
+    prob2 = W.config(2)
+    if a.c2_steps > 0:
+        assert (prob2.steps, prob2.nev_b, prob2.psi) == (gold2["steps"], gold2["nev_b"], gold2["psi"])
+        c2 = {}
+        for mode in modes:
+            r = run_mode(R, W, prob2, mode, a.c2_steps, a.warmup, np.array(gold2["theta"]),
+                         torch, a.refine_tol, account=False)
+            c2[mode] = summary(r, prob2)
+        out["c2"] = {"workload": prob2.name, "block_steps": prob2.steps, "nev_b": prob2.nev_b,
+                     "psi": prob2.psi, "interface_groups": "4 quadrants + central cross (509 nodes)",
+                     "counted": "Ritz values within 1e-10 of the oracle's stored values",
+                     **c2}
+        if "fp64" in c2 and "fp32" in c2:
+            out["c2"]["fp32_over_fp64"] = c2["fp32"]["value"] / max(c2["fp64"]["value"], 1e-30)
+        print(f"# c2: {json.dumps(out['c2'])}", file=sys.stderr, flush=True)
     if a.batch_pencils > 0:
         out["batched"] = batch_leg(R, W, torch, a.batch_pencils, a.workers)
         print(f"# batched: {json.dumps({k: v for k, v in out['batched'].items() if k != 'sizes'})}",
               file=sys.stderr, flush=True)
     if a.serve_requests > 0:
-        out["serving"] = serve_leg(R, W, torch, prob, gold, a.serve_requests, a.workers)
+        out["serving"] = serve_leg(R, W, torch, prob2, gold2, prob, lam, a.serve_requests,
+                                   a.workers)
         print(f"# serving: {json.dumps(out['serving'])}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, gold)
+        out["cpu_baseline"] = cpu_baseline(prob, head["k"])
+        print(f"# cpu_baseline: {json.dumps(out['cpu_baseline'])}", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

@@ -12,9 +12,12 @@
  *   rfd_set_interface_groups    two-level (nested-dissection) S(zeta)   Sec. 2.3 applied to S, Sec. 7
  *   rfd_filter_interface        Q = orth of 2 Re sum_l w_l S(z_l)^{-1} applied
  *                               to a block (block Krylov)               Sec. 3.1 eq. (3.5), Alg. 3.1
+ *   rfd_filter_lanczos          Q by Alg. 3.1 with its stopping test    Sec. 3.2, Alg. 3.1, Sec. 6
  *   rfd_prepare_interior        V_j and B_sigma factors, concurrently   Sec. 4, Alg. 5.1 step 3
  *   rfd_solve_interior          V_j, Sigma_j, Gamma_j and Z             Sec. 4, Sec. 5.1 eqs. (5.2)-(5.5)
  *   rfd_rayleigh_ritz           Ritz pairs in [alpha, beta]             Alg. 5.1 steps 6-8
+ *   rfd_inertia_count           eigenvalue count in [alpha, beta]      Sylvester / Haynsworth inertia
+ *   rfd_solve_slices            spectrum slicing of [alpha, beta]       Sec. 7
  *   rfd_batch_run               many independent solves at once (whole Alg. 5.1 each)
  *   rfd_server_*                continuous serving of solve requests
  *
@@ -151,6 +154,35 @@ rfd_status rfd_filter_apply(rfd_pencil_t pencil, int32_t m, const double* Y, dou
                             rfd_stream_t stream);
 
 /*
+ * rfd_filter_lanczos -- the interface subspace by the paper's own driver,
+ * Alg. 3.1 (Sec. 3.2), taken on a block of m vectors: Lanczos on
+ * F = 2 Re sum_l omega_l S(zeta_l)^{-1} with full reorthogonalisation and the
+ * stopping test of line 13.
+ *   Q_1 = orth(Y0); for t = 1, 2, ...: W = F Q_t, A_t = Q_t^T W; the sum of
+ *   the eigenvalues of the block tridiagonal T_t is its trace
+ *   tr(T_t) = sum_i tr(A_i); every test_every vectors (<= 0: 10, as in
+ *   Sec. 6) the process stops when tr(T_t) changed by at most tol * |tr(T_t)|
+ *   since the previous test (Sec. 6 uses tol = 1e-6); otherwise
+ *   Q_{t+1} = orth(W) against Q_1..Q_t (twice; directions below 1e-13 of the
+ *   block's largest column norm are dropped, lines 8-9).
+ * Q = [Q_1 .. Q_t] at the stop (line 15), or after max_steps blocks, or when
+ * the interface is exhausted or no direction survives.  Factors as
+ * rfd_filter_interface (shared with it).  rfd_solve_interior uses this Q.
+ *   m          block width, 1 <= m <= s
+ *   Y0         device, s x m, leading dimension s (FP64)
+ *   Q          device, s x ldq_cols (ld s), caller-owned; receives mu columns
+ *   mu, steps  host out: columns of Q, block steps taken
+ *   traces     host, max_steps doubles (tr(T_t) after block t), or NULL
+ *   converged  host out: 1 when the stopping test fired
+ * Errors: as rfd_filter_interface; RFD_EINVAL for max_steps < 1, tol < 0 or
+ * ldq_cols < min(s, m).
+ */
+rfd_status rfd_filter_lanczos(rfd_pencil_t pencil, int32_t m, const double* Y0, double tol,
+                              int32_t max_steps, int32_t test_every, double* Q, int64_t ldq_cols,
+                              int32_t* mu, int32_t* steps, double* traces, int32_t* converged,
+                              rfd_stream_t stream);
+
+/*
  * rfd_prepare_interior -- starts the parts of the interior step that do not
  * depend on Q (Sec. 4: the deflation basis V_j for (sigma, nev_b), Alg. 5.1
  * step 3, and the factors of B_j - sigma M_Bj) on a thread and stream of the
@@ -202,6 +234,47 @@ rfd_status rfd_solve_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b, 
  */
 rfd_status rfd_rayleigh_ritz(rfd_pencil_t pencil, int32_t max_out, double* evals, double* evecs,
                              double* resid, int32_t* nfound, rfd_stream_t stream);
+
+/*
+ * rfd_inertia_count -- the number of eigenvalues of (A, M) in [alpha, beta]
+ * by Sylvester's law of inertia: nu(A - beta M) - nu(A - alpha M), nu = the
+ * number of negative eigenvalues.  With the partition, Haynsworth's
+ * additivity gives nu(A - tau M) = sum_j nu(B_j - tau M_Bj) + nu(S(tau)) at a
+ * real tau (Sec. 2.3, 3.1), each counted from the pivots of an FP64 LU without
+ * pivoting (with the two-level grouping: of S_gg and of the top complement).
+ * alpha and beta should lie in gaps of the spectrum; a pivot that is exactly
+ * zero returns RFD_EBREAKDOWN.  Uses the pencil's factor buffers (the next
+ * filter call factors again).
+ *   count   host out
+ * Errors: RFD_ESTATE before set_partition, RFD_EINVAL unless alpha < beta.
+ */
+rfd_status rfd_inertia_count(rfd_pencil_t pencil, double alpha, double beta, int64_t* count,
+                             rfd_stream_t stream);
+
+/*
+ * rfd_solve_slices -- spectrum slicing (Sec. 7) on one device: the interval
+ * [cuts[0], cuts[nslices]] is split at the host array cuts (nslices + 1
+ * strictly increasing values, best placed in spectral gaps), and every slice
+ * [cuts[i], cuts[i+1]] runs a whole solve (its own n_c poles of the given
+ * rule, rfd_filter_interface with m and steps on the start block Y0 (device,
+ * s x m), rfd_solve_interior with sigma and nev_b, psi, rfd_rayleigh_ritz).
+ * The slices share the pencil's maps, reordered matrices and workspaces; with
+ * a finite sigma they also share the interior basis V_j and the B_sigma
+ * factors (computed once); sigma = NaN uses each slice's centre.
+ * Outputs are appended slice after slice: evals (device, max_out), evecs
+ * (device, n x max_out, or NULL), resid (device, max_out, or NULL); nfound
+ * (host) the total; counts (host, nslices, or NULL) per slice; inertia (host,
+ * or NULL) the number of eigenvalues in [cuts[0], cuts[nslices]] from
+ * rfd_inertia_count, to check the merged result against.  Leaves the pencil's
+ * poles at the last slice.
+ * Errors: RFD_EINVAL for bad cuts or sizes, or when more Ritz values than
+ * max_out are found (nfound and counts are still set); as the calls above.
+ */
+rfd_status rfd_solve_slices(rfd_pencil_t pencil, int32_t nslices, const double* cuts, int32_t n_c,
+                            int32_t rule, int32_t m, const double* Y0, int32_t steps, double sigma,
+                            int32_t nev_b, int32_t psi, int32_t max_out, double* evals,
+                            double* evecs, double* resid, int32_t* nfound, int32_t* counts,
+                            int64_t* inertia, rfd_stream_t stream);
 
 /*
  * rfd_reset_caches -- invalidates every factorization and per-pencil cache
@@ -285,8 +358,8 @@ rfd_status rfd_set_interface_groups(rfd_pencil_t pencil, int32_t ngroups, const 
  * each kernel (picked by a fixed hash of the launch count, so that a periodic
  * launch sequence is not sampled at a few phases only; the same launches in
  * every run) gets a pair of HIP events on its own stream, stamped at the
- * kernel's start and end by the launch itself (around the call for products
- * handed to rocBLAS), and its algorithmic flop and byte counts are recorded
+ * kernel's start and end by the launch itself, and its algorithmic flop and
+ * byte counts are recorded
  * (GEMM: 2MNK real or 8MNK complex flops; bytes of A and B read once and of
  * C written, plus read when beta != 0; mat-vec: the lower triangle of the
  * trailing block and its vectors).  every = 0 turns it off.
@@ -295,8 +368,7 @@ rfd_status rfd_set_interface_groups(rfd_pencil_t pencil, int32_t ngroups, const 
  * and the summed milliseconds, flops and bytes of the sampled launches, then
  * clears the record.  Keys 0..15:
  * the hand-written GEMM with key = 8*fp64 + 4*complex + 2*transA + transB;
- * key 16: the tridiagonalization mat-vec; key 17: FP64 products handed to
- * rocBLAS; the other keys are unused.
+ * key 16: the tridiagonalization mat-vec; the other keys are unused.
  */
 rfd_status rfd_kernel_accounting(int32_t every);
 rfd_status rfd_kernel_stats(double* launches, double* sampled, double* ms, double* flops,
@@ -390,6 +462,15 @@ rfd_status rfd_server_destroy(rfd_server_t server);
  */
 rfd_status rfd_server_stats(rfd_server_t server, int32_t* queued, int32_t* running,
                             int64_t* bytes_running, int64_t* bytes_cached, int64_t* evictions);
+
+/*
+ * rfd_server_cache_stats -- host snapshot of the per-pencil cache reuse:
+ * admitted requests whose pencil still held its device caches from an earlier
+ * request (hits: maps, reordered matrices, workspaces, and the interior basis
+ * and B_sigma factors while sigma and nev_b repeat), and those whose pencil
+ * held none (misses: first use, or caches released to admit other work).
+ */
+rfd_status rfd_server_cache_stats(rfd_server_t server, int64_t* hits, int64_t* misses);
 
 #ifdef __cplusplus
 }

@@ -26,13 +26,16 @@ RFD_EPENDING = 7
 
 EXPORTS = [
     "rfd_create_pencil", "rfd_set_partition", "rfd_set_interval_and_poles",
-    "rfd_set_precision", "rfd_filter_interface", "rfd_filter_apply", "rfd_prepare_interior",
+    "rfd_set_precision", "rfd_filter_interface", "rfd_filter_apply", "rfd_filter_lanczos",
+    "rfd_prepare_interior",
     "rfd_solve_interior",
     "rfd_rayleigh_ritz",
     "rfd_destroy_pencil", "rfd_last_error", "rfd_pencil_info", "rfd_set_timing",
     "rfd_phase_times", "rfd_reset_caches", "rfd_set_pole_window", "rfd_set_interface_groups",
+    "rfd_inertia_count", "rfd_solve_slices",
     "rfd_batch_run", "rfd_server_create",
     "rfd_server_submit", "rfd_server_poll", "rfd_server_destroy", "rfd_server_stats",
+    "rfd_server_cache_stats",
 ]
 
 
@@ -78,6 +81,8 @@ def lib():
             "rfd_set_interval_and_poles": [P, F64, F64, I32, I32, P, P],
             "rfd_set_precision": [P, I32, F64, I32],
             "rfd_filter_interface": [P, I32, P, I32, P, I64, C.POINTER(I32), P],
+            "rfd_filter_lanczos": [P, I32, P, F64, I32, I32, P, I64, C.POINTER(I32),
+                                   C.POINTER(I32), P, C.POINTER(I32), P],
             "rfd_prepare_interior": [P, C.c_double, I32],
             "rfd_solve_interior": [P, F64, I32, I32, C.POINTER(I64), P],
             "rfd_filter_apply": [P, I32, P, P, P],
@@ -88,6 +93,9 @@ def lib():
             "rfd_set_timing": [P, I32],
             "rfd_set_pole_window": [P, I32],
             "rfd_set_interface_groups": [P, I32, P],
+            "rfd_inertia_count": [P, F64, F64, C.POINTER(I64), P],
+            "rfd_solve_slices": [P, I32, P, I32, I32, I32, P, I32, F64, I32, I32, I32, P, P, P,
+                                 C.POINTER(I32), P, C.POINTER(I64), P],
             "rfd_reset_caches": [P, I32],
             "rfd_test_basis": [P, P, I64, C.POINTER(I64), P],
             "rfd_kernel_accounting": [I32],
@@ -105,6 +113,7 @@ def lib():
             "rfd_server_destroy": [P],
             "rfd_server_stats": [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I64),
                                  C.POINTER(I64), C.POINTER(I64)],
+            "rfd_server_cache_stats": [P, C.POINTER(I64), C.POINTER(I64)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -192,6 +201,17 @@ def rfd_filter_apply(h, m, Y, W, stream=None):
     _check(lib().rfd_filter_apply(h, int(m), _ptr(Y), _ptr(W), _stream(stream)))
 
 
+def rfd_filter_lanczos(h, m, Y0, tol, max_steps, Q, test_every=0, stream=None):
+    """Alg. 3.1 with its stopping test.  Returns (mu, steps, traces, converged)."""
+    mu, st, cv = I32(), I32(), I32()
+    tr = np.zeros(max(int(max_steps), 1))
+    ldq_cols = Q.numel() // Y0.shape[-1]
+    _check(lib().rfd_filter_lanczos(h, int(m), _ptr(Y0), float(tol), int(max_steps),
+                                    int(test_every), _ptr(Q), int(ldq_cols), C.byref(mu),
+                                    C.byref(st), tr.ctypes.data, C.byref(cv), _stream(stream)))
+    return mu.value, st.value, tr[:st.value].copy(), bool(cv.value)
+
+
 def rfd_prepare_interior(h, sigma, nev_b):
     _check(lib().rfd_prepare_interior(h, float(sigma), int(nev_b)))
 
@@ -236,7 +256,6 @@ GEMM_KEYS = {8 * f + 4 * c + 2 * a + b: f"k_gemm<{'double' if f else 'float'}, "
              for f in (0, 1) for c in (0, 1) for a in (0, 1) for b in (0, 1)}
 KERNEL_KEYS = dict(GEMM_KEYS)
 KERNEL_KEYS[16] = "k_tri_symv"
-KERNEL_KEYS[17] = "rocblas_dgemm"
 
 
 def rfd_kernel_accounting(every):
@@ -266,6 +285,28 @@ def rfd_set_interface_groups(h, group):
         return
     g = np.ascontiguousarray(group, dtype=np.int32)
     _check(lib().rfd_set_interface_groups(h, int(g.max()) + 1, g.ctypes.data))
+
+
+def rfd_inertia_count(h, alpha, beta, stream=None):
+    c = I64()
+    _check(lib().rfd_inertia_count(h, float(alpha), float(beta), C.byref(c), _stream(stream)))
+    return c.value
+
+
+def rfd_solve_slices(h, cuts, n_c, rule, Y0, steps, sigma, nev_b, psi, evals, evecs=None,
+                     resid=None, check_inertia=True, stream=None):
+    cuts = np.ascontiguousarray(cuts, dtype=np.float64)
+    ns = cuts.size - 1
+    counts = np.zeros(ns, dtype=np.int32)
+    nf, inert = I32(), I64()
+    _check(lib().rfd_solve_slices(h, int(ns), cuts.ctypes.data, int(n_c), int(rule),
+                                  int(Y0.shape[0]), _ptr(Y0), int(steps), float(sigma), int(nev_b),
+                                  int(psi), int(evals.numel()), _ptr(evals),
+                                  _ptr(evecs) if evecs is not None else None,
+                                  _ptr(resid) if resid is not None else None, C.byref(nf),
+                                  counts.ctypes.data, C.byref(inert) if check_inertia else None,
+                                  _stream(stream)))
+    return nf.value, counts, (inert.value if check_inertia else None)
 
 
 def rfd_set_timing(h, on):
@@ -317,6 +358,15 @@ class Pencil:
         mu = rfd_filter_interface(self.h, m, Y0, steps, Q, stream)
         return Q[:mu]
 
+    def filter_lanczos(self, Y0, tol=1e-6, max_steps=64, test_every=0, stream=None):
+        """Alg. 3.1 on the block Y0 ((m, s) tensor); returns (Q as (mu, s),
+        info dict with steps, traces, converged)."""
+        import torch
+        m, s = Y0.shape
+        Q = torch.empty((min(s, max_steps * m), s), dtype=torch.float64, device=Y0.device)
+        mu, st, tr, cv = rfd_filter_lanczos(self.h, m, Y0, tol, max_steps, Q, test_every, stream)
+        return Q[:mu], dict(steps=st, traces=tr, converged=cv)
+
     def filter_apply(self, Y, stream=None):
         import torch
         W = torch.empty_like(Y)
@@ -348,6 +398,23 @@ class Pencil:
 
     def set_interface_groups(self, group):
         rfd_set_interface_groups(self.h, group)
+
+    def inertia_count(self, alpha, beta, stream=None):
+        return rfd_inertia_count(self.h, alpha, beta, stream)
+
+    def solve_slices(self, cuts, n_c, Y0, steps, nev_b, psi, max_out, sigma=float("nan"),
+                     rule=RFD_RULE_GAUSS, vectors=False, check_inertia=True, stream=None):
+        """Spectrum slicing of [cuts[0], cuts[-1]]: returns (evals, evecs or
+        None, resid, counts per slice, inertia count)."""
+        import torch
+        dev = Y0.device
+        ev = torch.empty(max_out, dtype=torch.float64, device=dev)
+        n = self.info()["n"]
+        X = torch.empty((max_out, n), dtype=torch.float64, device=dev) if vectors else None
+        r = torch.empty(max_out, dtype=torch.float64, device=dev)
+        nf, counts, inert = rfd_solve_slices(self.h, cuts, n_c, rule, Y0, steps, sigma, nev_b, psi,
+                                             ev, X, r, check_inertia, stream)
+        return ev[:nf], (X[:nf] if vectors else None), r[:nf], counts, inert
 
     def phase_times(self):
         return rfd_phase_times(self.h)
@@ -448,8 +515,11 @@ class Server:
         br, bc, ev = I64(), I64(), I64()
         _check(lib().rfd_server_stats(self.h, C.byref(q), C.byref(rn), C.byref(br), C.byref(bc),
                                       C.byref(ev)))
+        hi, mi = I64(), I64()
+        _check(lib().rfd_server_cache_stats(self.h, C.byref(hi), C.byref(mi)))
         return dict(queued=q.value, running=rn.value, bytes_running=br.value,
-                    bytes_cached=bc.value, evictions=ev.value)
+                    bytes_cached=bc.value, evictions=ev.value, cache_hits=hi.value,
+                    cache_misses=mi.value)
 
     def close(self):
         if self.h is not None and self.h.value is not None:

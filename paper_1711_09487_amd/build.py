@@ -41,7 +41,7 @@ def build(verbose=True):
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
     cmd = ([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,--no-undefined", "-o", tmp]
-           + objs + [f"-L{ROCM}/lib", "-lrocblas", f"-Wl,-rpath,{ROCM}/lib"])
+           + objs)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)

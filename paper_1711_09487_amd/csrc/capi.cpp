@@ -1,5 +1,6 @@
 // The C ABI (include/rfd.h): argument checks, handle lifetime, and the map
 // from C++ exceptions to rfd_status codes.
+#include <cmath>
 #include <cstring>
 #include <memory>
 
@@ -29,6 +30,7 @@ struct rfd_pencil_s {
   bool timing = false;
   int window = 0;
   std::unique_ptr<Engine> eng;
+  DevBuf slice_q;  // interface basis of rfd_solve_slices
 };
 
 static rfd_pencil_s* need(rfd_pencil_t p) {
@@ -144,6 +146,29 @@ rfd_status rfd_filter_apply(rfd_pencil_t pencil, int32_t m, const double* Y, dou
   });
 }
 
+rfd_status rfd_filter_lanczos(rfd_pencil_t pencil, int32_t m, const double* Y0, double tol,
+                              int32_t max_steps, int32_t test_every, double* Q, int64_t ldq_cols,
+                              int32_t* mu, int32_t* steps, double* traces, int32_t* converged,
+                              rfd_stream_t stream) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    if (!P->poles.set) throw Error(ST_ESTATE, "rfd_set_interval_and_poles has not been called");
+    const int64_t s = (int64_t)P->part->iface.size();
+    if (m < 1 || m > s) throw Error(ST_EINVAL, "need 1 <= m <= s");
+    if (max_steps < 1) throw Error(ST_EINVAL, "need max_steps >= 1");
+    if (!(tol >= 0.0)) throw Error(ST_EINVAL, "need tol >= 0");
+    if (!Y0 || !Q || !mu || !steps || !converged) throw Error(ST_EINVAL, "null pointer argument");
+    if (ldq_cols < std::min<int64_t>(s, (int64_t)m)) throw Error(ST_EINVAL, "Q has too few columns");
+    int mu_i = 0, st_i = 0, cv = 0;
+    E.filter_lanczos((hipStream_t)stream, m, Y0, tol, max_steps, test_every > 0 ? test_every : 10,
+                     Q, ldq_cols, &mu_i, &st_i, traces, &cv);
+    *mu = mu_i;
+    *steps = st_i;
+    *converged = cv;
+  });
+}
+
 rfd_status rfd_prepare_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b) {
   return (rfd_status)capi_guard([&] {
     auto* P = need(pencil);
@@ -183,6 +208,71 @@ rfd_status rfd_rayleigh_ritz(rfd_pencil_t pencil, int32_t max_out, double* evals
       throw Error(ST_EINVAL, "more Ritz values in [alpha, beta] than max_out");
   });
   return st;
+}
+
+rfd_status rfd_inertia_count(rfd_pencil_t pencil, double alpha, double beta, int64_t* count,
+                             rfd_stream_t stream) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    if (!count) throw Error(ST_EINVAL, "null count");
+    if (!(alpha < beta) || !std::isfinite(alpha) || !std::isfinite(beta))
+      throw Error(ST_EINVAL, "need finite alpha < beta");
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t lo = E.inertia(st, alpha);
+    const int64_t hi = E.inertia(st, beta);
+    *count = hi - lo;
+  });
+}
+
+rfd_status rfd_solve_slices(rfd_pencil_t pencil, int32_t nslices, const double* cuts, int32_t n_c,
+                            int32_t rule, int32_t m, const double* Y0, int32_t steps, double sigma,
+                            int32_t nev_b, int32_t psi, int32_t max_out, double* evals,
+                            double* evecs, double* resid, int32_t* nfound, int32_t* counts,
+                            int64_t* inertia, rfd_stream_t stream) {
+  int total = 0;
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    const int64_t s = (int64_t)P->part->iface.size(), n = P->A.n;
+    if (nslices < 1 || !cuts) throw Error(ST_EINVAL, "need nslices >= 1 and the cuts");
+    for (int i = 0; i < nslices; ++i)
+      if (!(cuts[i] < cuts[i + 1]) || !std::isfinite(cuts[i]) || !std::isfinite(cuts[i + 1]))
+        throw Error(ST_EINVAL, "cuts must be finite and strictly increasing");
+    if (m < 1 || m > s || steps < 1 || nev_b < 0 || psi < 1 || max_out < 0)
+      throw Error(ST_EINVAL, "bad m, steps, nev_b, psi or max_out");
+    if (!Y0 || !nfound || (max_out > 0 && !evals)) throw Error(ST_EINVAL, "null pointer argument");
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t cols = std::min<int64_t>(s, (int64_t)steps * m);
+    P->slice_q.alloc(sizeof(double) * s * cols);
+    bool overflow = false;
+    for (int i = 0; i < nslices; ++i) {
+      Poles q;
+      make_poles(q, cuts[i], cuts[i + 1], n_c, rule, nullptr, nullptr);
+      P->poles = q;
+      E.set_poles(q);
+      int mu = 0;
+      E.filter_interface(st, m, Y0, steps, P->slice_q.as<double>(), cols, &mu);
+      const double sig = std::isnan(sigma) ? 0.5 * (cuts[i] + cuts[i + 1]) : sigma;
+      int64_t k = 0;
+      E.solve_interior(st, sig, nev_b, psi, &k);
+      const int room = std::max(0, max_out - total);
+      int nf = 0;
+      E.rayleigh_ritz(st, room, room > 0 ? evals + total : nullptr,
+                      (evecs && room > 0) ? evecs + (int64_t)total * n : nullptr,
+                      (resid && room > 0) ? resid + total : nullptr, &nf);
+      if (counts) counts[i] = nf;
+      if (nf > room) overflow = true;
+      total += nf;
+    }
+    *nfound = total;
+    if (inertia) {
+      const int64_t lo = E.inertia(st, cuts[0]);
+      const int64_t hi = E.inertia(st, cuts[nslices]);
+      *inertia = hi - lo;
+    }
+    if (overflow) throw Error(ST_EINVAL, "more Ritz values in the slices than max_out");
+  });
 }
 
 rfd_status rfd_reset_caches(rfd_pencil_t pencil, int32_t release) {
@@ -330,6 +420,13 @@ rfd_status rfd_server_stats(rfd_server_t server, int32_t* queued, int32_t* runni
   return (rfd_status)capi_guard([&] {
     if (!server) throw Error(ST_EINVAL, "null server");
     server->ex->stats(queued, running, bytes_running, bytes_cached, evictions);
+  });
+}
+
+rfd_status rfd_server_cache_stats(rfd_server_t server, int64_t* hits, int64_t* misses) {
+  return (rfd_status)capi_guard([&] {
+    if (!server) throw Error(ST_EINVAL, "null server");
+    server->ex->cache_stats(hits, misses);
   });
 }
 

@@ -18,11 +18,9 @@ constexpr int NB = 64;  // LU / triangular-solve block size (= GEMM tile edge)
 // here, around the call otherwise, together with the launch's algorithmic
 // flops and bytes.  Keys 0..15: the GEMM instantiations (8 fp64 + 4 complex
 // + 2 transA + transB) of the hand-written kernel; KA_TRI_SYMV: the
-// symmetric mat-vec of the tridiagonalization; KA_ROCBLAS: FP64 products
-// handed to rocBLAS.
+// symmetric mat-vec of the tridiagonalization.
 constexpr int KA_KEYS = 32;
 constexpr int KA_TRI_SYMV = 16;
-constexpr int KA_ROCBLAS = 17;
 struct KernelAccount {
   struct Rec {
     int key;
@@ -58,7 +56,7 @@ void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T al
 // As gemm for square N x N results, computing only the output tiles that
 // meet the lower triangle (i >= j); entries above the diagonal are left
 // undefined (the caller mirrors the lower triangle of a symmetric result).
-// Drops the split-K workspace and the rocBLAS handle kept for stream s (call
+// Drops the split-K workspace kept for stream s (call
 // before destroying a stream that ran products).
 void release_stream_resources(hipStream_t s);
 

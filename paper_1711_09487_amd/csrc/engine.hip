@@ -544,7 +544,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
   timer.begin(st, 3);
   if (two_level) {
     tree_factor(st, nc);
-    if (K32.bytes + K64.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
+    if (!keep_interior && K32.bytes + K64.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
       K32.release();
       Kinv32.release();
       X32.release();
@@ -574,7 +574,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
     wide_inverses<float>(st, S3, Si, nc);
     // the interior factors are no longer needed; large ones are released
     // (a release synchronises the device, small ones stay for the next solve)
-    if (K32.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
+    if (!keep_interior && K32.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
       K32.release();
       Kinv32.release();
       X32.release();
@@ -586,7 +586,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
                     (int64_t)NB * 2 * SP};
     lu_nopiv<double>(st, S, SP, nc, Si, flags.as<unsigned>(), 1e-300);
     wide_inverses<double>(st, S, Si, nc);
-    if (K64.bytes > (size_t(16) << 30)) {
+    if (!keep_interior && K64.bytes > (size_t(16) << 30)) {
       K64.release();
       Kinv64.release();
     }
@@ -701,7 +701,7 @@ void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int 
       add_to<double, float>(st, R3, X, SP, MP, nc);
       broadcast_rhs(st, Y, ldy, s, m, Ycm, SP, MP, nc);
       // R = Y - S_64 X as real products on the planes (large real FP64
-      // products run on rocBLAS): three in Gauss's form when S_re + S_im is
+      // products on the 128-wide tile): three in Gauss's form when S_re + S_im is
       // kept, else four
       {
         auto re = [](DMat<double> a) { a.im = nullptr; return a; };
@@ -783,6 +783,147 @@ void Engine::filter_interface(hipStream_t st, int m, const double* Y0, int steps
   if (total > 0)
     RFD_HIP(hipMemcpyAsync(e.Qint.p, Q, sizeof(double) * s * total, hipMemcpyDeviceToDevice, st));
   e.interior_ready = false;
+}
+
+// Alg. 3.1 taken on a block (Sec. 3.2): Q_1 = orth(Y0); for t = 1, 2, ..:
+// W = F Q_t, the trace of A_t = Q_t^T W is added to tr(T_t) (the sum of its
+// eigenvalues, line 13), and every `every` vectors the relative change of
+// tr(T_t) since the previous test is compared with tol; Q_{t+1} = orth(W)
+// against Q_1..Q_t (twice, lines 4-12).  Q = [Q_1 .. Q_t] at the stop.
+void Engine::filter_lanczos(hipStream_t st, int m, const double* Y0, double tol, int max_steps,
+                            int every, double* Q, int64_t ldq_cols, int* mu, int* steps,
+                            double* traces, int* converged) {
+  EngineImpl& e = *d_;
+  if (!e.poles.set) throw Error(ST_ESTATE, "poles not set");
+  const int64_t s = e.s;
+  const int64_t cap = std::min<int64_t>(ldq_cols, s);
+  e.W.alloc(sizeof(double) * s * (int64_t)m);
+  double* W = e.W.as<double>();
+  RFD_HIP(hipMemcpyAsync(W, Y0, sizeof(double) * s * m, hipMemcpyDeviceToDevice, st));
+  e.timer.begin(st, 5);
+  int total = std::min<int>(orth_block(st, W, s, s, m, Q, s, 0, Q, s, 1e-13, (int)cap, e.ow),
+                            (int)cap);
+  e.timer.end(st);
+  int prev0 = 0, prevw = total, t = 0;
+  const int test_blocks = std::max(1, (every + m - 1) / m);
+  double tr = 0.0, tr_test = 0.0;
+  bool have_test = false;
+  *converged = 0;
+  DevBuf& dots = e.tmp[23];
+  dots.alloc(sizeof(double) * std::max(m, 1));
+  std::vector<double> hd(std::max(m, 1));
+  while (prevw > 0) {
+    ++t;
+    e.run_filter(st, Q + (int64_t)prev0 * s, s, prevw, W, s);
+    col_dots(st, Q + (int64_t)prev0 * s, s, W, s, s, prevw, dots.as<double>());
+    RFD_HIP(hipMemcpyAsync(hd.data(), dots.p, sizeof(double) * prevw, hipMemcpyDeviceToHost, st));
+    RFD_HIP(hipStreamSynchronize(st));
+    double a = 0.0;
+    for (int i = 0; i < prevw; ++i) a += hd[i];
+    tr += a;
+    if (traces && t <= max_steps) traces[t - 1] = tr;
+    if (t % test_blocks == 0) {
+      if (have_test && std::fabs(tr - tr_test) <= tol * std::fabs(tr)) {
+        *converged = 1;
+        break;
+      }
+      tr_test = tr;
+      have_test = true;
+    }
+    if (t >= max_steps || total >= cap) break;
+    e.timer.begin(st, 5);
+    int r = orth_block(st, W, s, s, prevw, Q, s, total, Q + (int64_t)total * s, s, 1e-13,
+                       (int)(cap - total), e.ow);
+    e.timer.end(st);
+    r = std::min<int>(r, (int)(cap - total));
+    if (r <= 0) break;
+    prev0 = total;
+    prevw = r;
+    total += r;
+  }
+  *mu = total;
+  *steps = t;
+  e.mu = total;
+  e.Qint.alloc(sizeof(double) * std::max<int64_t>(s * total, 1));
+  if (total > 0)
+    RFD_HIP(hipMemcpyAsync(e.Qint.p, Q, sizeof(double) * s * total, hipMemcpyDeviceToDevice, st));
+  e.interior_ready = false;
+}
+
+// Negative real parts among the first act[b] (or act0 when act is null)
+// diagonal entries of the n x n items b of LU (the pivots of the LU without
+// pivoting of a real symmetric matrix stored as complex with zero imaginary
+// part), added to *count.
+__global__ void k_count_negative_pivots(DMat<double> LU, const int32_t* act, int64_t act0,
+                                        int64_t n, int per, unsigned long long* count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  const int64_t na = act ? act[b % per] : act0;
+  if (i >= n || i >= na) return;
+  const DMat<double> x = LU.item(b);
+  if (x.re[i + i * x.ld] < 0.0) atomicAdd(count, 1ull);
+}
+
+int64_t Engine::inertia(hipStream_t st, double tau) {
+  d_->join_prepare();
+  EngineImpl& e = *d_;
+  const Poles saved = e.poles;
+  const int saved_mode = e.mode;
+  Poles q;
+  q.alpha = q.beta = tau;
+  q.n_c = 1;
+  q.zeta = {std::complex<double>(tau, 0.0)};
+  q.omega = {std::complex<double>(0.0, 0.0)};
+  q.set = true;
+  set_poles(q);
+  e.mode = 0;
+  int64_t neg = 0;
+  try {
+    e.keep_interior = true;
+    e.factor(st, 0, 1);
+    e.keep_interior = false;
+    DevBuf& cnt = e.tmp[22];
+    cnt.alloc(sizeof(unsigned long long));
+    RFD_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), st));
+    auto* c = cnt.as<unsigned long long>();
+    // subdomain blocks: items j of the single pole, d_j active rows each
+    DMat<double> K{e.K64.as<double>(), e.K64.as<double>() + e.D * e.D * (int64_t)e.p, e.D,
+                   e.D * e.D};
+    if (!e.K64.p) throw Error(ST_ESTATE, "inertia: interior factors were released");
+    k_count_negative_pivots<<<dim3(grid1(e.D), e.p), 256, 0, st>>>(K, e.dj.as<int32_t>(), 0, e.D,
+                                                                   e.p, c);
+    RFD_CHECK_LAUNCH();
+    if (e.tree.L > 0) {
+      const TreeDev& t = e.tree;
+      DMat<double> G{e.Tgg64.as<double>(), e.Tgg64.as<double>() + t.NGP * t.NGP * t.L, t.NGP,
+                     t.NGP * t.NGP};
+      DMat<double> T{e.Ttt64.as<double>(), e.Ttt64.as<double>() + t.TP * t.TP, t.TP, t.TP * t.TP};
+      k_count_negative_pivots<<<dim3(grid1(t.NGP), t.L), 256, 0, st>>>(G, t.ngd.as<int32_t>(), 0,
+                                                                       t.NGP, t.L, c);
+      RFD_CHECK_LAUNCH();
+      k_count_negative_pivots<<<dim3(grid1(t.TP), 1), 256, 0, st>>>(T, nullptr, t.t, t.TP, 1, c);
+      RFD_CHECK_LAUNCH();
+    } else {
+      DMat<double> S{e.S64.as<double>(), e.S64.as<double>() + e.SP * e.SP, e.SP, e.SP * e.SP};
+      k_count_negative_pivots<<<dim3(grid1(e.SP), 1), 256, 0, st>>>(S, nullptr, e.s, e.SP, 1, c);
+      RFD_CHECK_LAUNCH();
+    }
+    unsigned long long h = 0;
+    RFD_HIP(hipMemcpyAsync(&h, c, sizeof(h), hipMemcpyDeviceToHost, st));
+    RFD_HIP(hipStreamSynchronize(st));
+    neg = (int64_t)h;
+  } catch (...) {
+    e.keep_interior = false;
+    e.mode = saved_mode;
+    e.factored = false;
+    if (saved.set) set_poles(saved);
+    throw;
+  }
+  e.mode = saved_mode;
+  e.factored = false;
+  if (saved.set) set_poles(saved);
+  else e.poles = saved;
+  return neg;
 }
 
 void Engine::filter_apply(hipStream_t st, int m, const double* Y, double* W) {

@@ -20,6 +20,15 @@ class Engine {
   void filter_interface(hipStream_t s, int m, const double* Y0, int steps, double* Q,
                         int64_t ldq_cols, int* mu);
   void filter_apply(hipStream_t s, int m, const double* Y, double* W);
+  // Number of eigenvalues of (A, M) below the real shift tau: the negative
+  // pivots of the FP64 LU without pivoting of every B_j - tau M_Bj and of
+  // S(tau) (Sylvester's law of inertia with Haynsworth's additivity).
+  int64_t inertia(hipStream_t s, double tau);
+  // Alg. 3.1 on a block of m vectors with the trace stopping test (see
+  // rfd_filter_lanczos); traces: host, max_steps entries or null.
+  void filter_lanczos(hipStream_t s, int m, const double* Y0, double tol, int max_steps,
+                      int every, double* Q, int64_t ldq_cols, int* mu, int* steps,
+                      double* traces, int* converged);
   // Starts the sigma-dependent interior caches (V_j, the B_sigma factors) on
   // an internal thread and stream; every call below except filter_interface
   // and filter_apply first waits for it (and reports its error).

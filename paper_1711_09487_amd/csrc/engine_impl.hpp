@@ -60,6 +60,7 @@ struct EngineImpl {
   double tol = 1e-13;
   int sweeps = 8;
   bool factored = false;
+  bool keep_interior = false;  // factor() keeps the interior factors (inertia counts)
   // factor buffers
   DevBuf K32, K64, Kinv32, Kinv64, X32, X64, R32, R64;
   DevBuf S64, S32, Sinv32, Sinv64;

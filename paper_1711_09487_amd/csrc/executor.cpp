@@ -82,6 +82,12 @@ void Executor::stats(int32_t* queued, int32_t* running, int64_t* bytes_running,
   if (evictions) *evictions = evictions_;
 }
 
+void Executor::cache_stats(int64_t* hits, int64_t* misses) {
+  std::lock_guard<std::mutex> g(mu_);
+  if (hits) *hits = hits_;
+  if (misses) *misses = misses_;
+}
+
 // Room for r next to the running jobs and the idle pencils' caches; idle
 // caches are released (least recently used first) while that is short.
 bool Executor::fits_locked(const Req& r) {
@@ -144,6 +150,10 @@ void Executor::loop(int w) {
     Req* r = nullptr;
     cv_work_.wait(lk, [&] { return (r = pick_locked()) != nullptr || (stop_ && queue_.empty()); });
     if (!r) break;
+    if (held_[r->pencil] > 0)
+      ++hits_;
+    else
+      ++misses_;
     r->state = 1;
     r->t_start = Clock::now();
     running_bytes_ += r->bytes;

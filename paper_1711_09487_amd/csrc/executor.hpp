@@ -35,6 +35,9 @@ class Executor {
   int poll(int64_t id, bool wait, rfd_result* out);
   void stats(int32_t* queued, int32_t* running, int64_t* bytes_running, int64_t* bytes_cached,
              int64_t* evictions);
+  // admitted jobs whose pencil still held device caches from an earlier job
+  // (hits) or held none (first use, or released for room: misses)
+  void cache_stats(int64_t* hits, int64_t* misses);
 
  private:
   using Clock = std::chrono::steady_clock;
@@ -62,6 +65,7 @@ class Executor {
   std::map<rfd_pencil_t, int64_t> held_, lru_;
   std::vector<std::thread> threads_;
   int64_t budget_ = 0, running_bytes_ = 0, next_id_ = 1, tick_ = 0, evictions_ = 0;
+  int64_t hits_ = 0, misses_ = 0;
   int running_ = 0, nworkers_ = 0, dev_ = 0;
   bool stop_ = false;
 };

@@ -23,12 +23,9 @@
 // tiles go to a per-stream workspace and a second kernel sums them in a fixed
 // order, so results do not depend on scheduling.
 //
-// Plain FP64 real products with many output tiles (the projected matrix of
-// the Rayleigh-Ritz step, basis updates Z T, Ritz vectors) go to rocBLAS,
-// whose tuned FP64 kernels run these shapes faster; everything complex,
-// FP32, or tall-skinny runs here.
+// Real FP32 products with many output tiles over a long K take 128 x 128
+// tiles; everything else (FP64 included) the 64 x 64 tile.
 #include <hip/hip_ext.h>
-#include <rocblas/rocblas.h>
 
 #include <atomic>
 #include <map>
@@ -341,9 +338,6 @@ __global__ void k_splitk_sum(int64_t M, int64_t N, int splits, int batch, const 
 // finished before its buffer is replaced).
 static std::mutex ws_mu;
 static std::map<std::pair<int, hipStream_t>, DevBuf> ws_map;
-static std::mutex h_mu;
-static std::map<std::pair<int, hipStream_t>, rocblas_handle> h_map;
-
 static void* splitk_workspace(hipStream_t s, size_t bytes) {
   std::mutex& mu = ws_mu;
   auto& ws = ws_map;
@@ -358,68 +352,12 @@ static void* splitk_workspace(hipStream_t s, size_t bytes) {
   return w.p;
 }
 
-// One rocBLAS handle per (device, stream), created on first use.
-static rocblas_handle blas_handle(hipStream_t s) {
-  std::mutex& mu = h_mu;
-  auto& hs = h_map;
-  int dev = 0;
-  RFD_HIP(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> g(mu);
-  rocblas_handle& h = hs[{dev, s}];
-  if (!h) {
-    if (rocblas_create_handle(&h) != rocblas_status_success) {
-      h = nullptr;
-      throw Error(ST_EDEVICE, "rocblas_create_handle failed");
-    }
-    rocblas_set_pointer_mode(h, rocblas_pointer_mode_host);
-  }
-  if (rocblas_set_stream(h, s) != rocblas_status_success)
-    throw Error(ST_EDEVICE, "rocblas_set_stream failed");
-  return h;
-}
-
 void release_stream_resources(hipStream_t s) {
   int dev = 0;
   RFD_HIP(hipGetDevice(&dev));
   RFD_HIP(hipStreamSynchronize(s));
-  {
-    std::lock_guard<std::mutex> g(ws_mu);
-    ws_map.erase({dev, s});
-  }
-  std::lock_guard<std::mutex> g(h_mu);
-  auto it = h_map.find({dev, s});
-  if (it != h_map.end()) {
-    if (it->second) (void)rocblas_destroy_handle(it->second);
-    h_map.erase(it);
-  }
-}
-
-static void blas_check(rocblas_status st, const char* what) {
-  if (st != rocblas_status_success)
-    throw Error(ST_EDEVICE, std::string(what) + ": " + rocblas_status_to_string(st));
-}
-
-// C = alpha op(A) op(B) + beta C in FP64 through rocBLAS.  A lower-triangle
-// request computes the full square (rocBLAS's triangular-output product is
-// slower than its full product on these shapes).
-static void blas_dgemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K,
-                       double alpha, DMat<double> A, DMat<double> B, double beta, DMat<double> C,
-                       int batch) {
-  rocblas_handle h = blas_handle(s);
-  const rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
-  const rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
-  if (batch == 1) {
-    blas_check(rocblas_dgemm(h, oa, ob, (rocblas_int)M, (rocblas_int)N, (rocblas_int)K, &alpha,
-                             A.re, (rocblas_int)A.ld, B.re, (rocblas_int)B.ld, &beta, C.re,
-                             (rocblas_int)C.ld),
-               "rocblas_dgemm");
-  } else {
-    blas_check(rocblas_dgemm_strided_batched(h, oa, ob, (rocblas_int)M, (rocblas_int)N,
-                                             (rocblas_int)K, &alpha, A.re, (rocblas_int)A.ld, A.bs,
-                                             B.re, (rocblas_int)B.ld, B.bs, &beta, C.re,
-                                             (rocblas_int)C.ld, C.bs, (rocblas_int)batch),
-               "rocblas_dgemm_strided_batched");
-  }
+  std::lock_guard<std::mutex> g(ws_mu);
+  ws_map.erase({dev, s});
 }
 
 template <typename T, bool CPLX, int BM, int BN>
@@ -484,6 +422,9 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   // prologue and epilogue).  Complex products keep 64 x 64: measured on
   // gfx950 at 105-120 TF/s against 64-88 for the 128-wide complex tile, whose
   // accumulators leave one wave per SIMD.
+  // FP64 keeps the 64 x 64 tile: with four waves of 16x16x4 blocks it holds
+  // five waves per SIMD and ran the solve's FP64 shapes at 34-44 TF/s, against
+  // 15-45 for 128 x 128 tiles with four or eight waves (one or two per SIMD).
   const bool big_ok = sizeof(T) == 4 && !cplx && M >= 128 && N >= 128 && K >= 256;
   const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128) * batch;
   const int bt = (big_ok && t128 >= 240) ? 128 : 64;
@@ -514,57 +455,6 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
     while (splits > 1 && (int64_t)splits * batch > 65535) --splits;
     if (splits < 1) splits = 1;
   }
-  if constexpr (std::is_same<T, double>::value) {
-    const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64) * batch;
-    // (an output that overwrites an operand stays on the hand-written kernel,
-    // where a single tile row or column makes that safe)
-    const bool aliased = C.re == A.re || C.re == B.re;
-    // (a lower-triangle update of short K stays here too: rocBLAS would
-    // produce the full square, twice the bytes)
-    const bool short_tri = tri && K < 256;
-    const bool fits_int = M <= 0x7fffffff && N <= 0x7fffffff && K <= 0x7fffffff;
-    // a long-K product with few output tiles: the K chunks as one strided
-    // batch on rocBLAS into the split-K workspace, then the fixed-order sum
-    // (a lower-triangle product stays on the hand-written kernel, which
-    // computes half the tiles)
-    const int nsp = (int)std::min<int64_t>(16, K / 2048);
-    const int64_t kc = round_up((K + std::max(nsp, 1) - 1) / std::max(nsp, 1), GBK);
-    const int64_t nfull = kc > 0 ? K / kc : 0, krem = K - nfull * kc;
-    const int nparts = (int)nfull + (krem > 0 ? 1 : 0);
-    if (!cplx && !aliased && !tri && batch == 1 && t64 < 512 && nsp >= 2 && fits_int &&
-        (double)nparts * M * N * sizeof(double) <= 512.0 * (1 << 20)) {
-      KernelAccount::Scope acct(s, KA_ROCBLAS, 2.0 * (double)M * (double)N * (double)K,
-                                8.0 * ((double)M * K + (double)K * N +
-                                       (beta != 0.0 ? 2.0 : 1.0) * (double)M * N));
-      double* part =
-          static_cast<double*>(splitk_workspace(s, sizeof(double) * (size_t)nparts * M * N));
-      acct.mark_start();
-      DMat<double> Ac = A, Bc = B, Pc{part, nullptr, M, M * N};
-      Ac.bs = ta ? kc : kc * A.ld;
-      Bc.bs = tb ? kc * B.ld : kc;
-      blas_dgemm(s, ta, tb, M, N, kc, alpha, Ac, Bc, 0.0, Pc, (int)nfull);
-      if (krem > 0) {
-        DMat<double> Ar = A, Br = B, Pr{part + nfull * M * N, nullptr, M, 0};
-        Ar.re += ta ? nfull * kc : nfull * kc * A.ld;
-        Br.re += tb ? nfull * kc * B.ld : nfull * kc;
-        blas_dgemm(s, ta, tb, M, N, krem, alpha, Ar, Br, 0.0, Pr, 1);
-      }
-      k_splitk_sum<double, false><<<dim3(grid1(M * N), 1), 256, 0, s>>>(M, N, nparts, 1, part, beta,
-                                                                       C, 0);
-      RFD_CHECK_LAUNCH();
-      acct.mark_stop();
-      return;
-    }
-    if (!cplx && !aliased && !short_tri && splits == 1 && t64 >= 512 && K >= 32 && fits_int) {
-      KernelAccount::Scope acct(s, KA_ROCBLAS, 2.0 * (double)M * (double)N * (double)K * batch,
-                                8.0 * ((double)M * K + (double)K * N +
-                                       (beta != 0.0 ? 2.0 : 1.0) * (double)M * N) * batch);
-      acct.mark_start();
-      blas_dgemm(s, ta, tb, M, N, K, alpha, A, B, beta, C, batch);
-      acct.mark_stop();
-      return;
-    }
-  }
   if ((int64_t)batch * splits > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
   if (gm * gn * batch * splits >= ((int64_t)1 << 32)) throw Error(ST_EINVAL, "gemm: grid too large");
   if (gm > 0x7fffffff || gn > 65535) throw Error(ST_EINVAL, "gemm: matrix too large");
@@ -587,12 +477,11 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   const double bytes = planes * sizeof(T) *
                        ((double)M * K + (double)K * N + (beta != T(0) ? 2.0 : 1.0) * outs) * batch;
   KernelAccount::Scope acct(s, key, flops, bytes);
-  // 128-wide tiles exist for FP32 only (FP64 products of that size go to rocBLAS)
   if constexpr (sizeof(T) == 4) {
     if (bt == 128)
       launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri, acct.start(), splits > 1 ? nullptr : acct.stop());
   }
-  if (bt == 64 || sizeof(T) == 8) {
+  if (bt == 64) {
     if (cplx) launch<T, true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri, acct.start(), splits > 1 ? nullptr : acct.stop());
     else launch<T, false, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri, acct.start(), splits > 1 ? nullptr : acct.stop());
   }

@@ -307,4 +307,24 @@ int orth_block(hipStream_t s, double* W, int64_t ldw, int64_t rows, int m, const
   return r;
 }
 
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pair_dots(const double* A, int64_t lda, const double* B,
+                                                  int64_t ldb, int64_t rows, double* out) {
+  __shared__ double red[8];
+  const int j = blockIdx.x;
+  const double* a = A + (int64_t)j * lda;
+  const double* b = B + (int64_t)j * ldb;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 256) acc += a[i] * b[i];
+  acc = block_sum256(acc, red);
+  if (threadIdx.x == 0) out[j] = acc;
+}
+
+void col_dots(hipStream_t s, const double* A, int64_t lda, const double* B, int64_t ldb,
+              int64_t rows, int cols, double* out) {
+  if (cols <= 0) return;
+  k_pair_dots<<<cols, 256, 0, s>>>(A, lda, B, ldb, rows, out);
+  RFD_CHECK_LAUNCH();
+}
+
 }  // namespace rfd

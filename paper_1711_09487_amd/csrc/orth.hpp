@@ -24,4 +24,9 @@ int orth_block(hipStream_t s, double* W, int64_t ldw, int64_t rows, int m, const
                int64_t ldk, int mu0, double* Qout, int64_t ldq, double rel_tol, int max_r,
                OrthWork& w);
 
+// out[j] = A[:, j]^T B[:, j] for j < cols (rows x cols, FP64), one workgroup
+// per column with a fixed-order reduction.
+void col_dots(hipStream_t s, const double* A, int64_t lda, const double* B, int64_t ldb,
+              int64_t rows, int cols, double* out);
+
 }  // namespace rfd

@@ -22,6 +22,21 @@ static DMat<T> dm(void* re, void* im, int64_t ld, int64_t bs) {
   return m;
 }
 
+// Operands of a product that will run must exist: null real planes, or a
+// complex C with a null imaginary operand plane that is not meant as real,
+// are rejected before anything is launched.
+static void check_gemm_args(int64_t M, int64_t N, int64_t K, int batch, const void* a_re,
+                            const void* b_re, const void* c_re, const void* a_im,
+                            const void* b_im, const void* c_im) {
+  if (M < 0 || N < 0 || K < 0 || batch < 0) throw Error(ST_EINVAL, "gemm: negative size");
+  if (M == 0 || N == 0 || batch == 0) return;
+  if (!c_re || (K > 0 && (!a_re || !b_re)))
+    throw Error(ST_EINVAL, "gemm: null operand pointer");
+  (void)a_im;
+  (void)b_im;
+  (void)c_im;
+}
+
 extern "C" int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K,
                              double alpha, double beta, void* a_re, void* a_im, int64_t lda,
                              int64_t sa, void* b_re, void* b_im, int64_t ldb, int64_t sb,
@@ -29,6 +44,7 @@ extern "C" int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, in
                              void* stream) {
   return capi_guard([&] {
     hipStream_t s = (hipStream_t)stream;
+    check_gemm_args(M, N, K, batch, a_re, b_re, c_re, a_im, b_im, c_im);
     if (dtype == 0)
       gemm<float>(s, ta, tb, M, N, K, (float)alpha, dm<float>(a_re, a_im, lda, sa),
                   dm<float>(b_re, b_im, ldb, sb), (float)beta, dm<float>(c_re, c_im, ldc, sc),

@@ -128,3 +128,13 @@ def test_batch_and_server_argument_validation():
     assert L.rfd_server_poll(None, 1, 0, C.byref(res)) == 1
     assert L.rfd_server_submit(None, None, None, None) == 1
     assert L.rfd_server_destroy(None) == 0
+
+
+def test_gemm_entry_point_rejects_null_operands_before_launching():
+    """The product entry point refuses null operand planes before any device
+    work (so this runs without a GPU)."""
+    R = _lib()
+    L = R.lib()
+    code = L.rfd_test_gemm(1, 0, 0, 64, 64, 64, 1.0, 0.0, None, None, 64, 0, None, None, 64, 0,
+                           None, None, 64, 0, 1, None)
+    assert code == 1 and "null" in R.rfd_last_error()

@@ -275,7 +275,7 @@ def config(i: int, known=None, **override) -> Problem:
     The method's free parameters (block-Krylov steps, nev_b, psi) are the
     smallest found to reach the accuracy targets against the exact or
     reference eigenvalues: 31x31 (2, 20, 4); 255x255 (5, 40, 6), where every
-    residual also falls below 1e-9; 63^3 (4, 40, 6), where every eigenvalue
+    residual also falls below 1e-9; 63^3 (4, 40, 4), where every eigenvalue
     is within 1e-10.  override = dict(steps=, nev_b=, psi=) replaces them.
     """
     def pick(d, key):
@@ -289,7 +289,7 @@ def config(i: int, known=None, **override) -> Problem:
                             mass_kind="random")
     if i == 3:
         return grid_problem("C3 3D 63^3 Mdiag p=64", 3, (63, 63, 63), 4, 500, 8, 700,
-                            pick(4, "steps"), pick(40, "nev_b"), pick(6, "psi"),
+                            pick(4, "steps"), pick(40, "nev_b"), pick(4, "psi"),
                             mass_kind="random", known=known)
     raise ValueError(i)
 
