@@ -23,9 +23,9 @@ Beside the headline:
               M, uneven sizes) run as one rfd_batch_run on several worker
               streams, against the same jobs on one worker;
   serving  -- a seeded Poisson stream of spectrum-slicing requests on the
-              31x31, 255x255 and two batched-workload pencils, replayed at
-              0.5x and 0.8x the measured saturated rate: p50 / p99 latency
-              and throughput;
+              31x31, 255x255 and 63^3 pencils (weights 0.6 / 0.3 / 0.1),
+              replayed at 0.5x and 0.8x the measured saturated rate: p50 /
+              p99 latency, throughput, cache hits and evictions;
   roofline -- the hand-written kernel with the most summed time over the
               timed steps and, as roofline_mfma, the FP32 complex GEMM (LU
               updates and triangular solves of the shifted blocks and of S),
