@@ -26,6 +26,22 @@ int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K, do
                   void* b_im, int64_t ldb, int64_t sb, void* c_re, void* c_im, int64_t ldc,
                   int64_t sc, int batch, void* stream);
 
+/* rfd_test_gemm for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same product, allocating nothing.  The split-K partial tiles of
+ * products with few output tiles go to a fixed 64 MiB device array that the
+ * library holds on each device until the process ends (the per-call split
+ * count is lowered until they fit).  Products whose output (M * N * batch
+ * elements, times 2 when complex, of 4 or 8 bytes) takes more than 32 MiB are
+ * rejected with RFD_EINVAL.  Every call on a device shares that array: calls
+ * that overlap on one device (other streams or threads) race, so serialise
+ * them.  Nothing in the array needs clearing between calls. */
+int rfd_test_gemm_static(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K,
+                         double alpha, double beta, void* a_re, void* a_im, int64_t lda,
+                         int64_t sa, void* b_re, void* b_im, int64_t ldb, int64_t sb,
+                         void* c_re, void* c_im, int64_t ldc, int64_t sc, int batch,
+                         void* stream);
+
 /* Factors each n x n item of A in place (pivot = 0: LU without pivoting, as
  * for the shifted blocks B_j - zeta M_Bj and S(zeta) of Section 3; pivot = 1:
  * partial pivoting, real only, as for B_j - sigma M_Bj of Section 4) and

@@ -64,6 +64,15 @@ template <typename T>
 void gemm_lower(hipStream_t s, bool ta, bool tb, int64_t N, int64_t K, T alpha, DMat<T> A,
                 DMat<T> B, T beta, DMat<T> C, int batch);
 
+// As gemm, allocating nothing: split-K partial tiles go to a fixed device
+// array of GEMM_STATIC_SCRATCH_BYTES per device (shared by every call on the
+// device; overlapping calls race).  Products whose output (M N batch planes
+// elements) takes more than half of it are rejected (ST_EINVAL).
+constexpr size_t GEMM_STATIC_SCRATCH_BYTES = size_t(64) << 20;
+template <typename T>
+void gemm_static(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha,
+                 DMat<T> A, DMat<T> B, T beta, DMat<T> C, int batch);
+
 // In-place LU without pivoting of n x n items (n multiple of NB).  inv
 // receives, per item, the inverses of the unit-lower and upper diagonal
 // blocks: an NB x (2 n) matrix [Linv_0 Uinv_0 Linv_1 Uinv_1 ...].  A pivot

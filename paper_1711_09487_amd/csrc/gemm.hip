@@ -410,9 +410,13 @@ static bool aligned16(const DMat<T>& X, int vw) {
   return X.ld % vw == 0 && X.bs % vw == 0 && al(X.re) && (X.im == nullptr || al(X.im));
 }
 
+// fixed_part: caller-provided memory of fixed_bytes for the split-K partial
+// tiles (the split count is lowered until they fit; no allocation and no
+// kernel accounting), or null for the per-stream workspace.
 template <typename T>
 static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha,
-                      DMat<T> A, DMat<T> B, T beta, DMat<T> C, int batch, int tri) {
+                      DMat<T> A, DMat<T> B, T beta, DMat<T> C, int batch, int tri,
+                      T* fixed_part = nullptr, size_t fixed_bytes = 0) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   const bool cplx = C.cplx();
   const int NP = cplx ? 2 : 1;
@@ -463,9 +467,22 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
     kchunk = round_up((K + splits - 1) / splits, GBK);
     splits = (int)((K + kchunk - 1) / kchunk);
   }
+  if (fixed_part) {
+    while (splits > 1 && sizeof(T) * (size_t)splits * batch * M * N * NP > fixed_bytes) {
+      --splits;
+      kchunk = round_up((K + splits - 1) / splits, GBK);
+      splits = (int)((K + kchunk - 1) / kchunk);
+    }
+    if (splits <= 1) {
+      splits = 1;
+      kchunk = K;
+    }
+  }
   T* part = nullptr;
   if (splits > 1)
-    part = static_cast<T*>(splitk_workspace(s, sizeof(T) * (size_t)splits * batch * M * N * NP));
+    part = fixed_part ? fixed_part
+                      : static_cast<T*>(splitk_workspace(s, sizeof(T) * (size_t)splits * batch * M *
+                                                                N * NP));
   const int va = aligned16(A, VW), vb = aligned16(B, VW);
   dim3 g((unsigned)gm, (unsigned)gn, (unsigned)(batch * splits));
   const int key = (sizeof(T) == 8 ? 8 : 0) + (cplx ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
@@ -476,7 +493,7 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   const double planes = cplx ? 2.0 : 1.0;
   const double bytes = planes * sizeof(T) *
                        ((double)M * K + (double)K * N + (beta != T(0) ? 2.0 : 1.0) * outs) * batch;
-  KernelAccount::Scope acct(s, key, flops, bytes);
+  KernelAccount::Scope acct(s, fixed_part ? -1 : key, flops, bytes);
   if constexpr (sizeof(T) == 4) {
     if (bt == 128)
       launch<T, false, 128, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, splits, kchunk, part, va, vb, tri, acct.start(), splits > 1 ? nullptr : acct.stop());
@@ -510,11 +527,51 @@ void gemm_lower(hipStream_t s, bool ta, bool tb, int64_t N, int64_t K, T alpha, 
   gemm_impl<T>(s, ta, tb, N, N, K, alpha, A, B, beta, C, batch, 1);
 }
 
+// ---------------------------------------------------------------------------
+// Products for callers that cannot allocate: the split-K partial tiles go to
+// a file-scope device array instead of the per-stream workspace.  Each device
+// holds its own copy; its address is looked up once per device (with that
+// device current) and kept.  Every call on a device shares the array, so
+// calls that overlap on one device race; nothing in it needs to start at zero
+// (every partial tile is written before it is summed).
+static __device__ __align__(256) unsigned char scratch[GEMM_STATIC_SCRATCH_BYTES];
+
+static void* static_scratch() {
+  static std::mutex mu;
+  static void* ptr[64] = {};
+  int dev = 0;
+  RFD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(ST_EDEVICE, "gemm_static: device index out of range");
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(ST_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    ptr[dev] = p;
+  }
+  return ptr[dev];
+}
+
+template <typename T>
+void gemm_static(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha,
+                 DMat<T> A, DMat<T> B, T beta, DMat<T> C, int batch) {
+  const int64_t NP = C.cplx() ? 2 : 1;
+  if (M > 0 && N > 0 && batch > 0 &&
+      (double)M * N * batch * NP * sizeof(T) > 0.5 * (double)GEMM_STATIC_SCRATCH_BYTES)
+    throw Error(ST_EINVAL, "gemm_static: the output (M N batch planes elements) may take at most " +
+                               std::to_string(GEMM_STATIC_SCRATCH_BYTES / 2) + " bytes");
+  gemm_impl<T>(s, ta, tb, M, N, K, alpha, A, B, beta, C, batch, 0,
+               static_cast<T*>(static_scratch()), GEMM_STATIC_SCRATCH_BYTES);
+}
+
 #define RFD_GEMM_INST(T)                                                                        \
   template void gemm<T>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, T, DMat<T>, DMat<T>, \
                         T, DMat<T>, int);                                                        \
   template void gemm_lower<T>(hipStream_t, bool, bool, int64_t, int64_t, T, DMat<T>, DMat<T>, T, \
-                              DMat<T>, int);
+                              DMat<T>, int);                                                  \
+  template void gemm_static<T>(hipStream_t, bool, bool, int64_t, int64_t, int64_t, T, DMat<T>,  \
+                               DMat<T>, T, DMat<T>, int);
 RFD_GEMM_INST(float)
 RFD_GEMM_INST(double)
 

@@ -56,6 +56,27 @@ extern "C" int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, in
   });
 }
 
+// rfd_test_gemm for callers that cannot allocate: split-K partial tiles in
+// the library's fixed per-device scratch array (gemm_static).
+extern "C" int rfd_test_gemm_static(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K,
+                                    double alpha, double beta, void* a_re, void* a_im,
+                                    int64_t lda, int64_t sa, void* b_re, void* b_im, int64_t ldb,
+                                    int64_t sb, void* c_re, void* c_im, int64_t ldc, int64_t sc,
+                                    int batch, void* stream) {
+  return capi_guard([&] {
+    hipStream_t s = (hipStream_t)stream;
+    check_gemm_args(M, N, K, batch, a_re, b_re, c_re, a_im, b_im, c_im);
+    if (dtype == 0)
+      gemm_static<float>(s, ta, tb, M, N, K, (float)alpha, dm<float>(a_re, a_im, lda, sa),
+                         dm<float>(b_re, b_im, ldb, sb), (float)beta,
+                         dm<float>(c_re, c_im, ldc, sc), batch);
+    else
+      gemm_static<double>(s, ta, tb, M, N, K, alpha, dm<double>(a_re, a_im, lda, sa),
+                          dm<double>(b_re, b_im, ldb, sb), beta, dm<double>(c_re, c_im, ldc, sc),
+                          batch);
+  });
+}
+
 // Factors A (n x n items, in place) and solves A X = R in place (n x r items).
 // pivot = 1 selects partial pivoting (real only).  *flags_out receives the
 // breakdown flags.

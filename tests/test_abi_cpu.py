@@ -130,11 +130,17 @@ def test_batch_and_server_argument_validation():
     assert L.rfd_server_destroy(None) == 0
 
 
-def test_gemm_entry_point_rejects_null_operands_before_launching():
-    """The product entry point refuses null operand planes before any device
-    work (so this runs without a GPU)."""
+def test_gemm_entry_points_reject_bad_operands_before_launching():
+    """Both product entry points refuse null operand planes, and the
+    allocation-free one refuses outputs beyond half its 64 MiB scratch, before
+    any device work (so these run without a GPU)."""
     R = _lib()
     L = R.lib()
-    code = L.rfd_test_gemm(1, 0, 0, 64, 64, 64, 1.0, 0.0, None, None, 64, 0, None, None, 64, 0,
-                           None, None, 64, 0, 1, None)
-    assert code == 1 and "null" in R.rfd_last_error()
+    for fn in (L.rfd_test_gemm, L.rfd_test_gemm_static):
+        code = fn(1, 0, 0, 64, 64, 64, 1.0, 0.0, None, None, 64, 0, None, None, 64, 0, None, None,
+                  64, 0, 1, None)
+        assert code == 1 and "null" in R.rfd_last_error()
+    fake = 1 << 20          # never dereferenced: the size check comes first
+    code = L.rfd_test_gemm_static(1, 0, 0, 2048, 2048, 64, 1.0, 0.0, fake, fake, 2048, 0, fake, fake,
+                                  64, 0, fake, fake, 2048, 0, 1, None)
+    assert code == 1 and "at most" in R.rfd_last_error()
