@@ -19,9 +19,10 @@ Beside the headline:
               eigenvalues, 5 block steps, nev_b 40, psi 6), both modes,
               counted against the oracle's stored Ritz values
               (tests/golden/oracle_c2.json) and the residual target;
-  batched  -- pencils of the batched workload (variable coefficient, random
-              M, uneven sizes) run as one rfd_batch_run on several worker
-              streams, against the same jobs on one worker;
+  batched  -- the 256 pencils of the batched workload (variable coefficient,
+              random M, uneven sizes) run as one rfd_batch_run on several
+              worker streams in FP32+refine, against the same jobs on one
+              worker and in plain FP64;
   serving  -- a seeded Poisson stream of spectrum-slicing requests on the
               31x31, 255x255 and 63^3 pencils (weights 0.6 / 0.3 / 0.1),
               replayed at 0.5x and 0.8x the measured saturated rate: p50 /
@@ -232,6 +233,9 @@ BATCH_NEV_B, BATCH_PSI, BATCH_STEPS = 40, 6, 3
 
 
 def batch_leg(R, W, torch, count, workers):
+    """The batched workload as rfd_batch_run calls: FP32+refine on `workers`
+    streams (the value) and on one stream, and plain FP64 on `workers`
+    streams beside it."""
     specs = W.batch_specs(count)
     probs = [W.batch_problem(b, sp, nev_b=BATCH_NEV_B, psi=BATCH_PSI, steps=BATCH_STEPS)
              for b, sp in enumerate(specs)]
@@ -242,16 +246,17 @@ def batch_leg(R, W, torch, count, workers):
         pens.append(P)
     y0 = [torch.from_numpy(np.ascontiguousarray(pr.Y0.T)).cuda() for pr in probs]
 
-    def jobs():
+    def jobs(mode):
         return [R.Job(P, pr.alpha, pr.beta, pr.n_c, y, pr.steps, pr.sigma, pr.nev_b, pr.psi,
-                      pr.nev + 30, mode=R.RFD_FP32_REFINE, rule=rule_of(R, pr),
-                      refine_tol=TARGET_TOL)
+                      pr.nev + 30, mode=mode, rule=rule_of(R, pr),
+                      refine_tol=TARGET_TOL if mode == R.RFD_FP32_REFINE else 0.0)
                 for P, pr, y in zip(pens, probs, y0)]
 
-    R.batch_run(jobs(), workers=workers)          # first use: maps, reordered matrices
+    R.batch_run(jobs(R.RFD_FP32_REFINE), workers=workers)   # first use: maps, reordered matrices
     out = {}
-    for w in (workers, 1):
-        js = jobs()
+    for key, mode, w in (("fp32", R.RFD_FP32_REFINE, workers), ("fp32_1", R.RFD_FP32_REFINE, 1),
+                         ("fp64", R.RFD_FP64, workers)):
+        js = jobs(mode)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         R.batch_run(js, workers=w)
@@ -263,14 +268,18 @@ def batch_leg(R, W, torch, count, workers):
             found += ev.size
             g, _, _ = count_good(ev, pr.exact[:pr.nev])
             good += g
-        out[w] = dict(wall=wall, good=good, found=found)
+        out[key] = dict(wall=wall, good=good, found=found)
+        del js
     for P in pens:
         P.close()
-    b, s1 = out[workers], out[1]
+    b, s1, d = out["fp32"], out["fp32_1"], out["fp64"]
     return {"pencils": count, "workers": workers, "eigenpairs": b["good"],
+            "eigenpairs_wanted": int(sum(pr.nev for pr in probs)),
             "eigenpairs_found": b["found"], "value": b["good"] / b["wall"],
             "unit": "eigenpairs/s", "wall_s": b["wall"], "one_worker_value": s1["good"] / s1["wall"],
             "one_worker_wall_s": s1["wall"], "speedup_vs_one_worker": s1["wall"] / b["wall"],
+            "fp64": {"value": d["good"] / d["wall"], "eigenpairs": d["good"], "wall_s": d["wall"]},
+            "fp32_over_fp64": (b["good"] / b["wall"]) / max(d["good"] / d["wall"], 1e-30),
             "mode": "fp32+refine", "counted": "Ritz values within 1e-10 of a reference eigensolver",
             "nev_b": BATCH_NEV_B, "psi": BATCH_PSI, "block_steps": BATCH_STEPS,
             "sizes": {"N": [s["N"] for s in specs], "P": [s["P"] for s in specs],
@@ -508,7 +517,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--refine-tol", type=float, default=TARGET_TOL,
                     help="FP32 refinement tolerance (relative max-norm residual)")
-    ap.add_argument("--batch-pencils", type=int, default=32,
+    ap.add_argument("--batch-pencils", type=int, default=256,
                     help="pencils of the batched workload (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests per serving replay (0: skip)")

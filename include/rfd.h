@@ -61,6 +61,7 @@ typedef enum {
 
 enum { RFD_RULE_GAUSS = 0, RFD_RULE_MIDPOINT = 1, RFD_RULE_EXPLICIT = 2 };
 enum { RFD_FP64 = 0, RFD_FP32_REFINE = 1 };
+enum { RFD_INTERIOR_LU = 0, RFD_INTERIOR_SPECTRAL = 1 };
 
 /*
  * rfd_create_pencil -- the pencil (A, M) of Sec. 1: A symmetric, M symmetric
@@ -324,6 +325,28 @@ rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16);
  * the order of the final sum.  Errors: RFD_EINVAL for max_poles < 0.
  */
 rfd_status rfd_set_pole_window(rfd_pencil_t pencil, int32_t max_poles);
+
+/*
+ * rfd_set_interior_solver -- how the shifted interior blocks are inverted.
+ * RFD_INTERIOR_LU (default): every B_j - zeta_l M_Bj is factored for each
+ * pole (Sec. 3.1) and B_j - sigma M_Bj once per sigma (Sec. 4).
+ * RFD_INTERIOR_SPECTRAL: the eigendecomposition B_j V_j = M_Bj V_j Lambda_j,
+ * V_j^T M_Bj V_j = I, of every subdomain block is computed once per pencil
+ * (the expansion (B_j - z M_Bj)^{-1} = V_j (Lambda_j - z I)^{-1} V_j^T of
+ * Sec. 4.1, used in the proof of Thm. 4.2) and serves every pole, sigma and
+ * interval afterwards: the Schur contributions become X_j = V_j (Lambda_j -
+ * zeta I)^{-1} V_j^T Ehat_j (real products, FP64 in either precision mode,
+ * no refinement), the resolvent levels V_j (Lambda_j - sigma I)^{-1} V_j^T
+ * M_B X, and the deflation vectors V_j of Alg. 5.1 step 3 a column window of
+ * the stored eigenvectors.  The decomposition is kept until the pencil is
+ * destroyed, re-partitioned or rfd_reset_caches(pencil, 1) releases the
+ * buffers; it holds p D^2 + p D SJ doubles (D, SJ: interior and adjacency
+ * sizes padded to 64).  Results equal the LU path's up to rounding.  Errors:
+ * RFD_EINVAL for another kind or, for the spectral path, a non-diagonal M;
+ * RFD_ESTATE before rfd_set_partition.  The next solve rebuilds what depends
+ * on the choice.
+ */
+rfd_status rfd_set_interior_solver(rfd_pencil_t pencil, int32_t kind);
 
 /*
  * rfd_set_interface_groups -- factor S(zeta) in two levels (a nested

@@ -26,6 +26,12 @@ int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K, do
                   void* b_im, int64_t ldb, int64_t sb, void* c_re, void* c_im, int64_t ldc,
                   int64_t sc, int batch, void* stream);
 
+/* Largest |U_j^T U_j - I| over the subdomain eigenvector blocks of the last
+ * spectral decomposition (U_j = M_Bj^{1/2} V_j, after its orthonormalising
+ * steps), or 0 when the pencil has none: the departure from M_Bj-orthonormal
+ * eigenvectors on which the expansion of rfd_set_interior_solver rests. */
+int rfd_test_spectral_orthogonality(void* pencil, double* dev);
+
 /* rfd_test_gemm for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same product, allocating nothing.  The split-K partial tiles of

@@ -20,6 +20,7 @@ __all__ = [
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfd.so")
 RFD_FP64, RFD_FP32_REFINE = 0, 1
 RFD_RULE_GAUSS, RFD_RULE_MIDPOINT, RFD_RULE_EXPLICIT = 0, 1, 2
+RFD_INTERIOR_LU, RFD_INTERIOR_SPECTRAL = 0, 1
 STATUS = {0: "RFD_OK", 1: "RFD_EINVAL", 2: "RFD_ENOMEM", 3: "RFD_EBREAKDOWN",
           4: "RFD_ENOCONV", 5: "RFD_EDEVICE", 6: "RFD_ESTATE", 7: "RFD_EPENDING"}
 RFD_EPENDING = 7
@@ -32,6 +33,7 @@ EXPORTS = [
     "rfd_rayleigh_ritz",
     "rfd_destroy_pencil", "rfd_last_error", "rfd_pencil_info", "rfd_set_timing",
     "rfd_phase_times", "rfd_reset_caches", "rfd_set_pole_window", "rfd_set_interface_groups",
+    "rfd_set_interior_solver",
     "rfd_inertia_count", "rfd_solve_slices",
     "rfd_batch_run", "rfd_server_create",
     "rfd_server_submit", "rfd_server_poll", "rfd_server_destroy", "rfd_server_stats",
@@ -97,6 +99,8 @@ def lib():
             "rfd_solve_slices": [P, I32, P, I32, I32, I32, P, I32, F64, I32, I32, I32, P, P, P,
                                  C.POINTER(I32), P, C.POINTER(I64), P],
             "rfd_reset_caches": [P, I32],
+            "rfd_set_interior_solver": [P, I32],
+            "rfd_test_spectral_orthogonality": [P, C.POINTER(F64)],
             "rfd_test_basis": [P, P, I64, C.POINTER(I64), P],
             "rfd_kernel_accounting": [I32],
             "rfd_kernel_stats": [P, P, P, P, P],
@@ -279,6 +283,16 @@ def rfd_set_pole_window(h, max_poles):
     _check(lib().rfd_set_pole_window(h, int(max_poles)))
 
 
+def rfd_set_interior_solver(h, kind):
+    _check(lib().rfd_set_interior_solver(h, int(kind)))
+
+
+def rfd_test_spectral_orthogonality(h):
+    v = C.c_double(0.0)
+    _check(lib().rfd_test_spectral_orthogonality(h, C.byref(v)))
+    return v.value
+
+
 def rfd_set_interface_groups(h, group):
     """group: int32 per interface node (interface order), -1 for the top set,
     or None for the dense S."""
@@ -400,6 +414,12 @@ class Pencil:
 
     def set_interface_groups(self, group):
         rfd_set_interface_groups(self.h, group)
+
+    def set_interior_solver(self, kind):
+        rfd_set_interior_solver(self.h, kind)
+
+    def spectral_orthogonality(self):
+        return rfd_test_spectral_orthogonality(self.h)
 
     def inertia_count(self, alpha, beta, stream=None):
         return rfd_inertia_count(self.h, alpha, beta, stream)

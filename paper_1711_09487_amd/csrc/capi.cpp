@@ -29,6 +29,7 @@ struct rfd_pencil_s {
   int sweeps = 8;
   bool timing = false;
   int window = 0;
+  int interior_solver = RFD_INTERIOR_LU;
   std::unique_ptr<Engine> eng;
   DevBuf slice_q;  // interface basis of rfd_solve_slices
 };
@@ -89,6 +90,10 @@ rfd_status rfd_set_partition(rfd_pencil_t pencil, int32_t p, const int32_t* part
     P->eng->set_precision(P->mode, P->tol, P->sweeps);
     P->eng->set_timing(P->timing);
     P->eng->set_pole_window(P->window);
+    if (P->interior_solver != RFD_INTERIOR_LU && P->part->m_diag)
+      P->eng->set_interior_solver(P->interior_solver);
+    else
+      P->interior_solver = RFD_INTERIOR_LU;
     if (P->poles.set) P->eng->set_poles(P->poles);
   });
 }
@@ -314,6 +319,23 @@ rfd_status rfd_set_pole_window(rfd_pencil_t pencil, int32_t max_poles) {
     if (max_poles < 0) throw Error(ST_EINVAL, "need max_poles >= 0");
     P->window = max_poles;
     if (P->eng) P->eng->set_pole_window(max_poles);
+  });
+}
+
+rfd_status rfd_set_interior_solver(rfd_pencil_t pencil, int32_t kind) {
+  return (rfd_status)capi_guard([&] {
+    auto* P = need(pencil);
+    Engine& E = need_engine(P);
+    E.set_interior_solver(kind);
+    P->interior_solver = kind;
+  });
+}
+
+int rfd_test_spectral_orthogonality(void* pencil, double* dev) {
+  return capi_guard([&] {
+    auto* P = need(static_cast<rfd_pencil_t>(pencil));
+    if (!dev) throw Error(ST_EINVAL, "null output");
+    *dev = need_engine(P).spectral_orthogonality();
   });
 }
 

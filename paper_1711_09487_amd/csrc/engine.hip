@@ -197,6 +197,8 @@ int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, i
   b += p * (D * VB + 3 * D * D + D * (int64_t)psi * MUP) * 8;     // V_j, B_sigma, levels
   b += p * (2 * 256 * D + 256 * MUP) * 8;                          // B_sigma wide leaves, their work
   b += n * (k * 3 + 4 * mu) * 8 + k * k * 8 * 2;                  // Z, A Z, H, level work
+  if (e.interior_solver == 1)                                      // eigenvectors, work, F, F_zeta
+    b += p * (2 * D * D + D * SJ * (1 + 2 * chunk) + D * MUP) * 8;
   return b + b / 10 + (int64_t(64) << 20);
 }
 
@@ -216,6 +218,8 @@ void Engine::reset_caches(bool release) {
   if (e.h_stream) RFD_HIP(hipStreamSynchronize(e.h_stream));
   e.h_ready = false;
   if (!release) return;
+  e.spec_valid = e.spec_f_valid = false;
+  e.spec_orth = 0;
   for (DevBuf* b : e.solve_buffers()) b->release();
   e.tw_v.cap = e.tw_h.cap = 0;
   e.ow.v_elems = 0;
@@ -232,6 +236,28 @@ void Engine::set_pole_window(int w) {
   d_->join_prepare();
   if (d_->max_window != w) d_->factored = false;
   d_->max_window = w;
+}
+
+int Engine::set_interior_solver(int kind) {
+  d_->join_prepare();
+  EngineImpl& e = *d_;
+  if (kind != 0 && kind != 1) throw Error(ST_EINVAL, "interior solver kind must be 0 or 1");
+  if (kind == 1 && !e.P->m_diag)
+    throw Error(ST_EINVAL, "the spectral interior path needs a diagonal M");
+  const int prev = e.interior_solver;
+  if (kind != prev) {
+    e.factored = false;
+    e.vcache_valid = false;
+    e.bs_valid = false;
+    e.interior_ready = false;
+  }
+  e.interior_solver = kind;
+  return prev;
+}
+
+double Engine::spectral_orthogonality() const {
+  d_->join_prepare();
+  return d_->spec_orth;
 }
 void Engine::phase_times(double* ms16) {
   d_->join_prepare();
@@ -302,7 +328,7 @@ std::vector<DevBuf*> EngineImpl::solve_buffers() {
                          &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank, &ow.wg, &ow.wt,
                          &ow.w1, &ow.w2, &Tgg64, &TgT64, &Ttt64, &Txc64, &Tgg32, &TgT32,
                          &Txc32, &Ttt32, &Tinvg, &Tinvt, &Twide, &Twork, &Tgt, &TRG, &TRT, &TXG,
-                         &TXT, &TRG32, &TRT32, &TU, &TXTg};
+                         &TXT, &TRG32, &TRT32, &TU, &TXTg, &Vs, &lam_s, &Fs, &Fz, &Ts, &Gsp};
   for (TriWork* t : {&tw_v, &tw_h})
     for (DevBuf* b : {&t->d, &t->e, &t->tau, &t->pt, &t->acol, &t->vw, &t->red, &t->sq, &t->ptvp,
                       &t->wv, &t->wg, &t->wt, &t->w1, &t->w2})
@@ -347,6 +373,9 @@ void EngineImpl::join_prepare() {
 void Engine::prepare_interior(double sig, int nevb) {
   EngineImpl& e = *d_;
   e.join_prepare();
+  // the spectral path's interior caches are a column window of the pencil's
+  // eigendecomposition, which the filter's factorization makes first
+  if (e.interior_solver == 1) return;
   if (e.vcache_valid && e.vcache_sigma == sig && e.vcache_nevb == nevb && e.bs_valid &&
       e.bs_sigma == sig)
     return;
@@ -462,7 +491,10 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
   const int64_t kk = D * D * (int64_t)items_max, ki = (int64_t)NB * 2 * D * items_max,
                 xs = D * SJ * (int64_t)items_max;
   const bool fp32 = (mode == 1);
-  if (fp32) {
+  const bool spectral = interior_solver == 1;
+  if (spectral) {
+    spectral_decompose(st);
+  } else if (fp32) {
     K32.alloc(2 * kk * sizeof(float));
     Kinv32.alloc(2 * ki * sizeof(float));
     X32.alloc(2 * xs * sizeof(float));
@@ -471,14 +503,19 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
     Kinv64.alloc(2 * ki * sizeof(double));
   }
   X64.alloc(2 * xs * sizeof(double));
-  if (fp32) R64.alloc(2 * xs * sizeof(double));
+  if (fp32 && !spectral) R64.alloc(2 * xs * sizeof(double));
   int max_sweeps_used = 0;
   for (int l0 = w0; l0 < w0 + nc; l0 += chunk) {
     const int np = std::min(chunk, w0 + nc - l0);
     const int items = np * p;
     DMat<double> X{X64.as<double>(), X64.as<double>() + xs, D, D * SJ};
-    timer.begin(st, 0);
-    if (fp32) {
+    if (spectral) {
+      // no shifted block is factored: X = V (Lambda - zeta)^{-1} V^T Ehat
+      timer.begin(st, 1);
+      spectral_schur(st, l0, np, X);
+      timer.end(st);
+    } else if (fp32) {
+      timer.begin(st, 0);
       DMat<float> K{K32.as<float>(), K32.as<float>() + kk, D, D * D};
       DMat<float> Ki{Kinv32.as<float>(), Kinv32.as<float>() + ki, NB, (int64_t)NB * 2 * D};
       fill<float>(st, K, D, D, items, 0.f);
@@ -510,6 +547,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
       max_sweeps_used = std::max(max_sweeps_used, sw);
       timer.end(st);
     } else {
+      timer.begin(st, 0);
       DMat<double> K{K64.as<double>(), K64.as<double>() + kk, D, D * D};
       DMat<double> Ki{Kinv64.as<double>(), Kinv64.as<double>() + ki, NB, (int64_t)NB * 2 * D};
       fill<double>(st, K, D, D, items, 0.0);
@@ -886,13 +924,22 @@ int64_t Engine::inertia(hipStream_t st, double tau) {
     cnt.alloc(sizeof(unsigned long long));
     RFD_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), st));
     auto* c = cnt.as<unsigned long long>();
-    // subdomain blocks: items j of the single pole, d_j active rows each
-    DMat<double> K{e.K64.as<double>(), e.K64.as<double>() + e.D * e.D * (int64_t)e.p, e.D,
-                   e.D * e.D};
-    if (!e.K64.p) throw Error(ST_ESTATE, "inertia: interior factors were released");
-    k_count_negative_pivots<<<dim3(grid1(e.D), e.p), 256, 0, st>>>(K, e.dj.as<int32_t>(), 0, e.D,
-                                                                   e.p, c);
-    RFD_CHECK_LAUNCH();
+    int64_t below = 0;
+    if (e.interior_solver == 1) {
+      // subdomain blocks: eigenvalues of (B_j, M_Bj) below tau
+      for (int j = 0; j < e.p; ++j) {
+        const int d = (int)e.P->interior[j].size();
+        for (int i = 0; i < d; ++i) below += e.lam_h[(size_t)j * e.DE + i] < tau ? 1 : 0;
+      }
+    } else {
+      // subdomain blocks: items j of the single pole, d_j active rows each
+      DMat<double> K{e.K64.as<double>(), e.K64.as<double>() + e.D * e.D * (int64_t)e.p, e.D,
+                     e.D * e.D};
+      if (!e.K64.p) throw Error(ST_ESTATE, "inertia: interior factors were released");
+      k_count_negative_pivots<<<dim3(grid1(e.D), e.p), 256, 0, st>>>(K, e.dj.as<int32_t>(), 0,
+                                                                     e.D, e.p, c);
+      RFD_CHECK_LAUNCH();
+    }
     if (e.tree.L > 0) {
       const TreeDev& t = e.tree;
       DMat<double> G{e.Tgg64.as<double>(), e.Tgg64.as<double>() + t.NGP * t.NGP * t.L, t.NGP,
@@ -911,7 +958,7 @@ int64_t Engine::inertia(hipStream_t st, double tau) {
     unsigned long long h = 0;
     RFD_HIP(hipMemcpyAsync(&h, c, sizeof(h), hipMemcpyDeviceToHost, st));
     RFD_HIP(hipStreamSynchronize(st));
-    neg = (int64_t)h;
+    neg = (int64_t)h + below;
   } catch (...) {
     e.keep_interior = false;
     e.mode = saved_mode;

@@ -47,6 +47,12 @@ class Engine {
   // interface position, -1 = top set); L = 0 returns to the dense S.
   void set_interface_groups(int L, const int32_t* group);
   void phase_times(double* ms16);
+  // 0: every shifted interior block B_j - z M_Bj is factored (LU); 1: the
+  // spectral path, one eigendecomposition of every (B_j, M_Bj) per pencil
+  // serving all poles and every sigma (Sec. 4.1).  Returns the previous kind.
+  int set_interior_solver(int kind);
+  // Largest |U^T U - I| of the last spectral decomposition (0 before one).
+  double spectral_orthogonality() const;
 
  private:
   std::unique_ptr<EngineImpl> d_;

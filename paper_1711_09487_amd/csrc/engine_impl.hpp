@@ -111,6 +111,21 @@ struct EngineImpl {
   int BLW = 0;
   bool bs_valid = false;
   double bs_sigma = 0;
+  // spectral interior path: one eigendecomposition of every (B_j, M_Bj)
+  // serves all shifts (poles, sigma) of the pencil
+  int interior_solver = 0;                // 0: LU per shift, 1: spectral
+  bool spec_valid = false, spec_f_valid = false;
+  int64_t DE = 0;                         // rows the eigensolver runs on (max d_j)
+  DevBuf Vs;                              // per subdomain D x D, M_B-orthonormal eigenvectors
+  DevBuf lam_s;                           // per subdomain DE eigenvalues, ascending
+  std::vector<double> lam_h;              // host copy of lam_s
+  DevBuf Fs, Fz, Ts;                      // V^T Ehat (D x SJ), scaled copies, level work
+  DevBuf Gsp;                             // decomposition work (Gram blocks, Ehat)
+  double spec_orth = 0;                   // max |U^T U - I| after the orthonormalisation
+  void spectral_decompose(hipStream_t st);
+  void spectral_select(hipStream_t st, double sigma, int nev_b);
+  void spectral_schur(hipStream_t st, int pole0, int np, DMat<double> X);
+  void spectral_level(hipStream_t st, DMat<double> X, int64_t cols, double sigma);
   DevBuf Lev;                             // levels: per subdomain D x (psi * MUP)
   int64_t MUP = 0;
   DevBuf Zt;                              // M-orthonormal basis of range(Z), n x k (reordered)

@@ -502,6 +502,10 @@ static std::vector<int> clusters(const std::vector<double>& lam, double gap) {
 
 void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   if (vcache_valid && vcache_sigma == sig && vcache_nevb == nevb) return;
+  if (interior_solver == 1) {
+    spectral_select(st, sig, nevb);
+    return;
+  }
   if (!P->m_diag) throw Error(ST_EINVAL, "the interior basis on the GPU needs a diagonal M");
   kappa.assign(p, 0);
   kappa_tot = 0;
@@ -619,9 +623,278 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   vcache_nevb = nevb;
 }
 
+// ---------------------------------------------------------------------------
+// Spectral interior path (Sec. 4.1, the expansion in the proof of Thm. 4.2).
+// With B_j V_j = M_Bj V_j Lambda_j and V_j^T M_Bj V_j = I, every shifted
+// block has (B_j - z M_Bj)^{-1} = V_j (Lambda_j - z I)^{-1} V_j^T.  One
+// eigendecomposition per pencil then gives, for every pole zeta and every
+// sigma, X_j = V_j (Lambda_j - zeta)^{-1} V_j^T Ehat_j (two real products per
+// pole), the resolvent levels B_sigma^{-1} M_B X = V_j (Lambda_j - sigma)^{-1}
+// V_j^T M_B X, and the deflation vectors V_j near sigma as a column window:
+// no shifted block is factored.  M_Bj is diagonal (M_E = 0, so Ehat_zeta =
+// Ehat for every pole).
+// ---------------------------------------------------------------------------
+
+// Fz_j[r, c] = (1 / (lam_j[r] - zeta_l)) F_j[r, c] for the pole l = pole0,
+// planar complex; rows at or beyond DE (no eigenpair) are zero.  Subdomains
+// j over grid z.
+__global__ void k_spec_scale(DMat<double> Fz, DMat<double> F, int64_t D, int64_t DE, int64_t SJ,
+                             int p, int pole0, const double* lam, Shifts z) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  const int j = blockIdx.z, l = pole0;
+  const int64_t c0 = (int64_t)blockIdx.y * CG;
+  DMat<double> f = F.item(j), o = Fz.item(j);
+  double wr = 0.0, wi = 0.0;
+  if (r < DE) {
+    const double dr = lam[(int64_t)j * DE + r] - z.z[2 * l], zi = z.z[2 * l + 1];
+    const double den = dr * dr + zi * zi;
+    wr = dr / den;
+    wi = zi / den;
+  }
+#pragma unroll
+  for (int u = 0; u < CG; ++u) {
+    const int64_t c = c0 + u;
+    if (c < SJ) {
+      const double v = f.re[r + c * f.ld];
+      o.re[r + c * o.ld] = wr * v;
+      o.im[r + c * o.ld] = wi * v;
+    }
+  }
+}
+
+// T_j[r, c] /= (lam_j[r] - sigma) for r < DE, c < cols.
+__global__ void k_spec_rowdiv(DMat<double> T, int64_t DE, int64_t cols, const double* lam,
+                              double sig) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= DE) return;
+  const int64_t c0 = (int64_t)blockIdx.y * CG;
+  DMat<double> t = T.item(blockIdx.z);
+  const double w = 1.0 / (lam[(int64_t)blockIdx.z * DE + r] - sig);
+#pragma unroll
+  for (int u = 0; u < CG; ++u)
+    if (c0 + u < cols) t.re[r + (c0 + u) * t.ld] *= w;
+}
+
+// G_j[i, i] += v for i < n.
+__global__ void k_add_diag(DMat<double> G, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  DMat<double> g = G.item(blockIdx.y);
+  g.re[i + i * g.ld] += v;
+}
+
+// U_j += a T_j over the leading n x n block.
+__global__ void k_axpy_block(DMat<double> U, DMat<double> T, int64_t n, double a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t r = e % n, c = e / n;
+  DMat<double> u = U.item(blockIdx.y), t = T.item(blockIdx.y);
+  u.re[r + c * u.ld] += a * t.re[r + c * t.ld];
+}
+
+// Every eigenpair of every (B_j, M_Bj), once per pencil: the batched
+// eigensolver of the interior basis run over the whole spectrum (bisection
+// for all DE values, inverse iteration, back-transformation), then the
+// eigenvector blocks U_j of M^{-1/2} B_j M^{-1/2} are brought to orthonormal
+// columns by Newton-Schulz steps U <- U - U (U^T U - I) / 2 (quadratic: a
+// departure of 1e-8 leaves 1e-16), so that V_j = M^{-1/2} U_j is
+// M_Bj-orthonormal to rounding and the expansion above holds to rounding.
+void EngineImpl::spectral_decompose(hipStream_t st) {
+  if (spec_valid) return;
+  if (!P->m_diag) throw Error(ST_EINVAL, "the spectral interior path needs a diagonal M");
+  timer.begin(st, 6);
+  spec_f_valid = false;
+  work1.alloc(sizeof(double) * 2 * p * D);
+  double* md = work1.as<double>();
+  double* mis = md + p * D;
+  k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, dj.as<int32_t>(), Bg.view(), md, mis);
+  RFD_CHECK_LAUNCH();
+  double mmin = 1e300;
+  for (double v : M->val) mmin = std::min(mmin, v > 0 ? v : 1e300);
+  // padding rows carry a value above the whole spectrum (||B|| / min M <= normA / mmin)
+  const double big = 4.0 * normA / std::max(mmin, 1e-300) + 1.0;
+  work2.alloc(sizeof(double) * D * D * p);
+  DMat<double> C{work2.as<double>(), nullptr, D, D * D};
+  fill<double>(st, C, D, D, p, 0.0);
+  k_expand_scaled<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), mis, big);
+  RFD_CHECK_LAUNCH();
+  DE = std::max<int64_t>(P->d_max, 1);
+  sy_tridiag(st, C, DE, p, tw_v);
+  std::vector<int> lo(p, 0), num(p, (int)DE);
+  DevBuf &lo_d = tmp[0], &num_d = tmp[1], &cl_d = tmp[4];
+  upload_v(st, lo_d, lo);
+  upload_v(st, num_d, num);
+  lam_s.alloc(sizeof(double) * (size_t)p * DE);
+  bisect(st, tw_v, DE, p, lo_d.as<int>(), num_d.as<int>(), (int)DE, lam_s.as<double>(), DE);
+  lam_h = download<double>(st, lam_s.p, (size_t)p * DE);
+  std::vector<int> cl((size_t)p * DE);
+  for (int j = 0; j < p; ++j) {
+    std::vector<double> v(lam_h.begin() + (size_t)j * DE, lam_h.begin() + (size_t)(j + 1) * DE);
+    auto c = clusters(v, 1e-10 * big);
+    std::copy(c.begin(), c.end(), cl.begin() + (size_t)j * DE);
+  }
+  upload_v(st, cl_d, cl);
+  Vs.alloc(sizeof(double) * D * D * p);
+  DMat<double> U{Vs.as<double>(), nullptr, D, D * D};
+  fill<double>(st, U, D, D, p, 0.0);
+  inverse_iteration(st, tw_v, DE, p, lam_s.as<double>(), num_d.as<int>(), cl_d.as<int>(), DE, U,
+                    tmp[6]);
+  back_transform(st, C, tw_v, DE, p, U, num_d.as<int>(), (int)DE);
+  RFD_HIP(hipStreamSynchronize(st));
+  tmp[6].release();  // inverse-iteration scratch (7 DE^2 p doubles)
+  // Newton-Schulz orthonormalisation (C's storage is free again: G and U G)
+  DevBuf& gbuf = Gsp;
+  gbuf.alloc(sizeof(double) * D * D * p);
+  DMat<double> G{gbuf.as<double>(), nullptr, D, D * D};
+  double dev = 0;
+  for (int it = 0;; ++it) {
+    gemm<double>(st, true, false, DE, DE, DE, 1.0, U, U, 0.0, G, p);
+    k_add_diag<<<dim3(grid1(DE), p), 256, 0, st>>>(G, DE, -1.0);
+    RFD_CHECK_LAUNCH();
+    zero_scalar(st, 2);
+    absmax<double>(st, G, DE, DE, p, scal.as<double>() + 2);
+    dev = read_scalar(st, 2);
+    if (!(dev == dev)) throw Error(ST_EBREAKDOWN, "non-finite subdomain eigenvectors");
+    if (dev <= 1e-14) break;
+    if (dev > 0.25 || it >= 6)
+      throw Error(ST_EBREAKDOWN, "subdomain eigenvectors not orthonormal (max |U^T U - I| = " +
+                                     std::to_string(dev) + ")");
+    gemm<double>(st, false, false, DE, DE, DE, 1.0, U, G, 0.0, C, p);
+    k_axpy_block<<<dim3(grid1(DE * DE), p), 256, 0, st>>>(U, C, DE, -0.5);
+    RFD_CHECK_LAUNCH();
+  }
+  spec_orth = dev;
+  gbuf.release();
+  // V = M^{-1/2} U
+  k_scale_rows<<<dim3(grid1(D * D), p), 256, 0, st>>>(U, D, D, mis, D);
+  RFD_CHECK_LAUNCH();
+  timer.end(st);
+  RFD_HIP(hipStreamSynchronize(st));
+  spec_valid = true;
+  vcache_valid = false;
+}
+
+// The nev_b eigenpairs of each (B_j, M_Bj) closest to sigma, whole clusters
+// at the cut (the rule of interior_basis), as a column window of V_j.
+void EngineImpl::spectral_select(hipStream_t st, double sig, int nevb) {
+  spectral_decompose(st);
+  timer.begin(st, 6);
+  work1.alloc(sizeof(double) * 2 * p * D);
+  k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, dj.as<int32_t>(), Bg.view(), work1.as<double>(),
+                                            work1.as<double>() + p * D);
+  RFD_CHECK_LAUNCH();
+  kappa.assign(p, 0);
+  kappa_tot = 0;
+  std::vector<int> w0(p, 0);
+  int kmax = 0;
+  for (int j = 0; j < p && nevb > 0; ++j) {
+    const int d = (int)P->interior[j].size();
+    const double* lj = lam_h.data() + (size_t)j * DE;
+    std::vector<int> ord(d);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+      return std::fabs(lj[x] - sig) < std::fabs(lj[y] - sig);
+    });
+    int k = std::min(nevb, d);
+    if (k > 0) {
+      const double cut = std::fabs(lj[ord[k - 1]] - sig);
+      while (k < d && std::fabs(lj[ord[k]] - sig) <= cut * (1.0 + 1e-9) + 1e-300) ++k;
+    }
+    int a = d, b = 0;
+    for (int q = 0; q < k; ++q) {
+      a = std::min(a, ord[q]);
+      b = std::max(b, ord[q] + 1);
+    }
+    if (k == 0) a = b = 0;
+    w0[j] = a;
+    kappa[j] = b - a;
+    kmax = std::max(kmax, kappa[j]);
+    kappa_tot += kappa[j];
+  }
+  VB = std::max<int64_t>(kmax, 1);
+  Vb.alloc(sizeof(double) * D * VB * p);
+  DMat<double> Y{Vb.as<double>(), nullptr, D, D * VB};
+  fill<double>(st, Y, D, VB, p, 0.0);
+  for (int j = 0; j < p; ++j)
+    if (kappa[j] > 0)
+      RFD_HIP(hipMemcpyAsync(Vb.as<double>() + (int64_t)j * D * VB,
+                             Vs.as<double>() + (int64_t)j * D * D + (int64_t)w0[j] * D,
+                             sizeof(double) * D * kappa[j], hipMemcpyDeviceToDevice, st));
+  upload_v(st, kap_d, kappa);
+  timer.end(st);
+  RFD_HIP(hipStreamSynchronize(st));
+  vcache_valid = true;
+  vcache_sigma = sig;
+  vcache_nevb = nevb;
+}
+
+// Schur-contribution solves of poles pole0 .. pole0 + np - 1 by the
+// expansion: X_(l,j) = V_j (Lambda_j - zeta_l)^{-1} F_j with F_j = V_j^T Ehat_j
+// (formed once per decomposition).  X: planar complex, D x SJ per item.
+void EngineImpl::spectral_schur(hipStream_t st, int pole0, int np, DMat<double> X) {
+  spectral_decompose(st);
+  Shifts z{zeta.as<double>()};
+  DMat<double> V{Vs.as<double>(), nullptr, D, D * D};
+  const int64_t fs = D * SJ * (int64_t)p;
+  if (!spec_f_valid) {
+    DevBuf& eb = Gsp;
+    eb.alloc(2 * sizeof(double) * fs);
+    DMat<double> E{eb.as<double>(), eb.as<double>() + fs, D, D * SJ};
+    fill<double>(st, E, D, SJ, p, 0.0);
+    // Ehat_zeta = Ehat - zeta M_E = Ehat for a diagonal M: any pole gives it
+    expand_rhs<double>(st, E, p, 1, 0, dj.as<int32_t>(), Eg.view(), z);
+    Fs.alloc(sizeof(double) * fs);
+    DMat<double> F{Fs.as<double>(), nullptr, D, D * SJ};
+    E.im = nullptr;
+    gemm<double>(st, true, false, D, SJ, D, 1.0, V, E, 0.0, F, p);
+    RFD_HIP(hipStreamSynchronize(st));
+    eb.release();
+    spec_f_valid = true;
+  }
+  // one pole at a time: F scaled by that pole's 1 / (lambda - zeta), then
+  // X = V F_zeta for its p items (real and imaginary planes)
+  Fz.alloc(2 * sizeof(double) * fs);
+  DMat<double> Fzm{Fz.as<double>(), Fz.as<double>() + fs, D, D * SJ};
+  DMat<double> F{Fs.as<double>(), nullptr, D, D * SJ};
+  DMat<double> Br{Fzm.re, nullptr, D, D * SJ}, Bi{Fzm.im, nullptr, D, D * SJ};
+  for (int q = 0; q < np; ++q) {
+    k_spec_scale<<<dim3(grid1(D), col_groups(SJ), (unsigned)p), 256, 0, st>>>(
+        Fzm, F, D, DE, SJ, p, pole0 + q, lam_s.as<double>(), z);
+    RFD_CHECK_LAUNCH();
+    const int64_t off = (int64_t)q * p * X.bs;
+    DMat<double> Cr{X.re + off, nullptr, X.ld, X.bs}, Ci{X.im + off, nullptr, X.ld, X.bs};
+    gemm<double>(st, false, false, D, SJ, DE, 1.0, V, Br, 0.0, Cr, p);
+    gemm<double>(st, false, false, D, SJ, DE, 1.0, V, Bi, 0.0, Ci, p);
+  }
+}
+
+// X_j <- B_sigma^{-1} X_j = V_j (Lambda_j - sigma)^{-1} V_j^T X_j (D x cols per item).
+void EngineImpl::spectral_level(hipStream_t st, DMat<double> X, int64_t cols, double sig) {
+  for (int j = 0; j < p; ++j) {
+    const int d = (int)P->interior[j].size();
+    for (int i = 0; i < d; ++i)
+      if (!(std::fabs(lam_h[(size_t)j * DE + i] - sig) > 1e-300))
+        throw Error(ST_EBREAKDOWN, "sigma is an eigenvalue of a subdomain block");
+  }
+  DMat<double> V{Vs.as<double>(), nullptr, D, D * D};
+  Ts.alloc(std::max<size_t>(Ts.bytes, sizeof(double) * D * cols * p));
+  DMat<double> T{Ts.as<double>(), nullptr, D, D * cols};
+  gemm<double>(st, true, false, DE, cols, D, 1.0, V, X, 0.0, T, p);
+  k_spec_rowdiv<<<dim3(grid1(DE), col_groups(cols), p), 256, 0, st>>>(T, DE, cols,
+                                                                      lam_s.as<double>(), sig);
+  RFD_CHECK_LAUNCH();
+  gemm<double>(st, false, false, D, cols, DE, 1.0, V, T, 0.0, X, p);
+}
+
 void EngineImpl::factor_bsigma(hipStream_t st, double sig, DevBuf* fl, bool check) {
   DevBuf& fw = fl ? *fl : flags;
   if (bs_valid && bs_sigma == sig) return;
+  if (interior_solver == 1) {  // the levels use the spectral expansion
+    bs_valid = true;
+    bs_sigma = sig;
+    return;
+  }
   timer.begin(st, 7);
   Bs.alloc(sizeof(double) * D * D * p);
   Bsinv.alloc(sizeof(double) * NB * 2 * D * p);
@@ -884,7 +1157,9 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   for (int t = 0; t < psi; ++t) {
     DMat<double> X = Lv.sub(0, t * MUP);
     convert<double, double>(st, Rh, X, D, MUP, p);
-    if (e.BLW) {
+    if (e.interior_solver == 1) {
+      e.spectral_level(st, X, MUP, sig);
+    } else if (e.BLW) {
       const int64_t per = (int64_t)e.BLW * 2 * D;
       e.Bswork.alloc(std::max<int64_t>(e.Bswork.bytes, sizeof(double) * e.BLW * MUP * p));
       lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p, 3,

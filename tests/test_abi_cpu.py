@@ -144,3 +144,18 @@ def test_gemm_entry_points_reject_bad_operands_before_launching():
     code = L.rfd_test_gemm_static(1, 0, 0, 2048, 2048, 64, 1.0, 0.0, fake, fake, 2048, 0, fake, fake,
                                   64, 0, fake, fake, 2048, 0, 1, None)
     assert code == 1 and "at most" in R.rfd_last_error()
+
+
+def test_interior_solver_needs_a_partition():
+    """rfd_set_interior_solver before rfd_set_partition: RFD_ESTATE (no device
+    work happens on this path)."""
+    R = _lib()
+    A = W.laplacian((5, 5))
+    M = sp.identity(25, format="csr")
+    h = R.rfd_create_pencil(A, M)
+    try:
+        with pytest.raises(R.RfdError) as e:
+            R.rfd_set_interior_solver(h, R.RFD_INTERIOR_SPECTRAL)
+        assert e.value.code == 6
+    finally:
+        R.rfd_destroy_pencil(h)

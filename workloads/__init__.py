@@ -174,7 +174,7 @@ def lowest_eigs(A, M, k: int, closed_shape=None) -> np.ndarray:
     n = A.shape[0]
     if closed_shape is not None:
         return closed_form_eigs(closed_shape)[:k]
-    if n <= 4000:
+    if n <= 1500:
         import scipy.linalg as sl
         return sl.eigh(A.toarray(), M.toarray(), eigvals_only=True)[:k]
     import scipy.sparse.linalg as sla
