@@ -15,6 +15,10 @@ it.  Both precision modes run: FP32 factors with FP64 refinement to the
 1e-10 target (the value) and plain FP64 (beside it).
 
 Beside the headline:
+  spectral -- the same pencil with the spectral interior path (one
+              eigendecomposition of every subdomain block, Sec. 4.1): a first
+              solve that computes it and a solve on the stored decomposition,
+              both modes;
   c2       -- the 2D 255x255 pencil (n = 65025, 64 subdomains, 200
               eigenvalues, 5 block steps, nev_b 40, psi 6), both modes,
               counted against the oracle's stored Ritz values
@@ -58,12 +62,14 @@ def rule_of(R, prob):
     return R.RFD_RULE_GAUSS if prob.rule == "gauss" else R.RFD_RULE_MIDPOINT
 
 
-def make_pencil(R, W, prob, mode, refine_tol=0.0):
+def make_pencil(R, W, prob, mode, refine_tol=0.0, spectral=False):
     P = R.Pencil(prob.A, prob.M)
     P.set_partition(prob.part)
     groups = W.interface_groups(prob.grid, prob.meta["P"])
     if groups is not None:
         P.set_interface_groups(groups)
+    if spectral:
+        P.set_interior_solver(R.RFD_INTERIOR_SPECTRAL)
     P.set_interval_and_poles(prob.alpha, prob.beta, prob.n_c, rule_of(R, prob))
     P.set_precision(R.RFD_FP32_REFINE if mode == "fp32" else R.RFD_FP64, refine_tol)
     return P
@@ -225,11 +231,55 @@ def roofline_entry(kname, st, f32, steps, workload):
 
 
 # ---------------------------------------------------------------------------
+# spectral interior path
+# ---------------------------------------------------------------------------
+def spectral_leg(R, W, prob, ref, torch, refine_tol, modes):
+    """The headline pencil with rfd_set_interior_solver(SPECTRAL), per mode:
+    a first solve that computes the eigendecomposition of every subdomain
+    block, then a solve on the stored decomposition (the pencil-level cache a
+    served pencil keeps between requests; everything that depends on the
+    interval or sigma is recomputed)."""
+    out = {}
+    Y0 = torch.from_numpy(np.ascontiguousarray(prob.Y0.T)).cuda()
+    for mode in modes:
+        P = make_pencil(R, W, prob, mode, refine_tol, spectral=True)
+        P.set_timing(True)
+        rows = []
+        for first in (True, False):
+            P.reset_caches(first)
+            P.phase_times()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev, r, k = one_step(P, prob, Y0)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ph = P.phase_times()
+            rr = r.cpu().numpy()
+            g, gs, e = count_good(ev.cpu().numpy(), ref, rr)
+            rows.append(dict(seconds=dt, eigenpairs=g, eigenpairs_resid_1e_9=gs, max_rel_err=e,
+                             max_resid=float(rr.max()) if rr.size else 0.0,
+                             decomposition_ms=float(ph[6]), phases_ms=np.round(ph[:12], 1).tolist()))
+        P.close()
+        torch.cuda.empty_cache()
+        a, b = rows
+        out[mode] = {"first_solve": a, "stored_decomposition": b,
+                     "value_stored": b["eigenpairs"] / b["seconds"],
+                     "value_first": a["eigenpairs"] / a["seconds"]}
+        print(f"# spectral {mode}: first {a['seconds']:.2f} s (decomposition "
+              f"{a['decomposition_ms']:.0f} ms), stored {b['seconds']:.2f} s, good "
+              f"{b['eigenpairs']}/{prob.nev}, max rel err {b['max_rel_err']:.2e}",
+              file=sys.stderr, flush=True)
+    del Y0
+    return out
+
+
+# ---------------------------------------------------------------------------
 # batched leg
 # ---------------------------------------------------------------------------
-# interior sizing of the batched pencils (few poles: more block steps and a
-# richer interior basis reach the 1e-10 target against exact eigenvalues)
-BATCH_NEV_B, BATCH_PSI, BATCH_STEPS = 40, 6, 3
+# parameters of the batched pencils: with 4-8 poles and m = 1.5 nev the
+# interface block needs 5 block steps (3 or 4 leave up to 1e-9 on pencils cut
+# 3 x 3); nev_b 30, psi 4 then reach 1e-10 (checked on the oracle)
+BATCH_NEV_B, BATCH_PSI, BATCH_STEPS = 30, 4, 5
 
 
 def batch_leg(R, W, torch, count, workers):
@@ -296,7 +346,9 @@ def serve_leg(R, W, torch, prob2, gold2, prob3, lam3, nreq, workers):
     """Spectrum-slicing requests on the 31x31, 255x255 and 63^3 pencils
     (weights 0.6 / 0.3 / 0.1), Poisson arrivals replayed at 0.5x and 0.8x the
     saturated rate; the pencils keep their maps, two-level grouping and
-    caches between requests (admission by device-memory footprint)."""
+    caches between requests (admission by device-memory footprint), the
+    eigendecomposition of their subdomain blocks among them (spectral
+    interior path)."""
     import scipy.linalg as sl
     c1 = W.config(1)
     pencils = {"C1": c1, "C2": prob2, "C3": prob3}
@@ -312,6 +364,8 @@ def serve_leg(R, W, torch, prob2, gold2, prob3, lam3, nreq, workers):
             P.set_partition(pr.part)
             if groups is not None:
                 P.set_interface_groups(groups)
+            # one eigendecomposition per pencil serves every slice (Sec. 4.1)
+            P.set_interior_solver(R.RFD_INTERIOR_SPECTRAL)
             replicas[nm].append(P)
 
     def build(i, rq):
@@ -384,7 +438,7 @@ def serve_leg(R, W, torch, prob2, gold2, prob3, lam3, nreq, workers):
     replay(None)                                   # first use of every pencil
     sat = replay(None)                             # all requests at once
     rate = nreq / sat["wall_s"]
-    out = {"requests": nreq, "workers": workers,
+    out = {"requests": nreq, "workers": workers, "interior_solver": "spectral",
            "replicas_per_pencil": {nm: len(v) for nm, v in replicas.items()},
            "interior": "nev_b = max(20, ceil(1.5 k / p) + 10), psi = 6, m = min(s, 1.5 k)",
            "block_steps": SERVE_STEPS, "mix": weights,
@@ -411,12 +465,12 @@ def cpu_baseline(prob, k_rr):
     grid (two whole 15^3 subdomains and their separators, Dirichlet-cut
     beyond) runs the oracle's Schur assembly for one pole; one of the two
     subdomains runs the oracle's subdomain eigenpairs and resolvent levels
-    for one block of m columns; the oracle's LU and block solve run on a 4096
-    x 4096 complex S-sized sample; and the oracle's Rayleigh-Ritz runs on the
-    full pencil with 1/32 of the columns.  Extrapolation: Schur assembly
+    for one block of m columns; the oracle's LU and block solve run on a 6144
+    x 6144 complex S-sized sample; and the oracle's Rayleigh-Ritz runs on the
+    full pencil with 1/12 of the columns.  Extrapolation: Schur assembly
     linearly in subdomains (64 / 2), interior work linearly in subdomains and
     columns, the S LU cubically and its solves quadratically in the interface
-    size (34047 / 4096), poles x block steps factorizations (the oracle
+    size (34047 / 6144), poles x block steps factorizations (the oracle
     streams the poles: every block step factors again), and Rayleigh-Ritz
     quadratically in its columns (its n k^2 QR dominates)."""
     import oracle as O
@@ -437,15 +491,15 @@ def cpu_baseline(prob, k_rr):
     O.schur(dd, z[0])
     t["schur_2_subdomains"] = time.perf_counter() - t0
     rng = np.random.default_rng(0)
-    ns = 4096
+    ns = 6144
     Ss = np.asfortranarray(rng.standard_normal((ns, ns)) + 1j * rng.standard_normal((ns, ns)))
     t0 = time.perf_counter()
     f = sl.lu_factor(Ss, overwrite_a=True, check_finite=False)
-    t["slu_4096"] = time.perf_counter() - t0
+    t["slu_sample"] = time.perf_counter() - t0
     Y = rng.standard_normal((ns, prob.m))
     t0 = time.perf_counter()
     O.filter_apply([f], [w[0]], Y)
-    t["fsolve_4096"] = time.perf_counter() - t0
+    t["fsolve_sample"] = time.perf_counter() - t0
     del Ss, f, Y
     for attr in ("interior", "adj", "B", "MB", "E", "ME"):
         setattr(dd, attr, getattr(dd, attr)[:1])
@@ -463,21 +517,21 @@ def cpu_baseline(prob, k_rr):
     ddf.A, ddf.M, ddf.part = prob.A, prob.M, prob.part
     ddf.interior = [np.flatnonzero(prob.part == j) for j in range(prob.p)]
     ddf.iface = np.flatnonzero(prob.part < 0)
-    kq = max(1, k_rr // 32)
+    kq = max(1, k_rr // 12)
     Zs = rng.standard_normal((prob.n, kq))
     t0 = time.perf_counter()
     O.rayleigh_ritz(ddf, Zs, prob.alpha, prob.beta)
-    t["rr_1_32"] = time.perf_counter() - t0
+    t["rr_sample"] = time.perf_counter() - t0
     del Zs
     sample = sum(t.values())
     mu = prob.steps * prob.m
     sr = prob.s / ns
     passes = prob.n_c * prob.steps
     est = (t["setup"] * prob.p / used.size
-           + passes * (prob.p / used.size * t["schur_2_subdomains"] + sr ** 3 * t["slu_4096"]
-                       + sr ** 2 * t["fsolve_4096"])
+           + passes * (prob.p / used.size * t["schur_2_subdomains"] + sr ** 3 * t["slu_sample"]
+                       + sr ** 2 * t["fsolve_sample"])
            + prob.p * (t["vbasis_1_subdomain"] + t["levels_1_subdomain"] * mu / q)
-           + (k_rr / kq) ** 2 * t["rr_1_32"])
+           + (k_rr / kq) ** 2 * t["rr_sample"])
     threads = os.environ.get("OMP_NUM_THREADS")
     cores = int(threads) if threads else os.cpu_count()
     cpu = "unknown"
@@ -488,7 +542,16 @@ def cpu_baseline(prob, k_rr):
                 break
     except OSError:
         pass
+    full = {}
+    try:
+        g3 = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_c3.json")))
+        full = {"seconds": g3["oracle_seconds"], "threads": g3["threads"],
+                "params": f"steps={g3['steps']}, nev_b={g3['nev_b']}, psi={g3['psi']}",
+                "host": "the build container (8 cores), tests/golden/make_oracle_golden.py"}
+    except (OSError, KeyError, ValueError):
+        pass
     return dict(value=prob.nev / est, unit="eigenpairs/s", cores=cores, kind="oracle",
+                full_oracle_run_smaller_setting=full,
                 cpu_model=cpu,
                 sample=(f"oracle on the 63^3 pencil: one pole's Schur assembly on 2 of {prob.p} "
                         f"subdomains, S LU and a {prob.m}-column solve at {ns} of {prob.s}, "
@@ -512,9 +575,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="timed FP64 solves of the headline workload beside the FP32 ones")
     ap.add_argument("--mode", default="both", choices=["fp32", "fp64", "both"])
-    ap.add_argument("--c2-steps", type=int, default=5,
+    ap.add_argument("--c2-steps", type=int, default=3,
                     help="timed solves per mode of the 255x255 workload (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-spectral", action="store_true",
+                    help="skip the spectral-interior leg of the headline pencil")
     ap.add_argument("--refine-tol", type=float, default=TARGET_TOL,
                     help="FP32 refinement tolerance (relative max-norm residual)")
     ap.add_argument("--batch-pencils", type=int, default=256,
@@ -602,6 +667,12 @@ def main():
                                   tflops=v[3] / max(v[2], 1e-9) / 1e9,
                                   gbps=v[4] / max(v[2], 1e-9) / 1e6)
                           for k, v in res[m]["kstats"].items()} for m in res}
+    if not a.no_spectral:
+        out["spectral"] = spectral_leg(R, W, prob, ref, torch, a.refine_tol, modes)
+        if "fp64" in out["spectral"] and "fp32" in out["spectral"]:
+            out["spectral"]["fp32_over_fp64_stored"] = (
+                out["spectral"]["fp32"]["value_stored"] /
+                max(out["spectral"]["fp64"]["value_stored"], 1e-30))
     gold2 = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_c2.json")))
     prob2 = W.config(2)
     if a.c2_steps > 0:
