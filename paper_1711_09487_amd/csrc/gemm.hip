@@ -24,7 +24,10 @@
 // order, so results do not depend on scheduling.
 //
 // Real FP32 products with many output tiles over a long K take 128 x 128
-// tiles; everything else (FP64 included) the 64 x 64 tile.
+// tiles, large real FP64 products the 64 x 128 tile of k_dgemm (scalar
+// loads from clamped indices, no bounds branches in the K loop, alpha and
+// beta folded into the operands and accumulators); everything else the 64 x
+// 64 tile.
 #include <hip/hip_ext.h>
 
 #include <atomic>
@@ -307,6 +310,189 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
     }
 }
 
+// Large FP64 products: real on 64 x 128 tiles (each of the 4 waves, 2 x 2,
+// computes 32 x 64 of v_mfma_f64_16x16x4f64 blocks), complex on 64 x 64
+// tiles (four real products per block into a real and an imaginary
+// accumulator); either way twice the matrix-core work per K slab of the
+// real 64 x 64 tile, with two waves per SIMD.  Loads are scalar 8-byte loads
+// (no alignment condition: the long operands of the solve have odd leading
+// dimensions) at a block-uniform base per K slab plus a per-thread 32-bit
+// offset fixed for the whole loop, from row and column indices clamped into
+// the matrices, so the loop has no bounds branches: rows of op(A) beyond M
+// and columns of op(B) beyond N only feed outputs that are never stored,
+// and K indices beyond the range (last slab only) read as 0.  Consecutive
+// lanes read consecutive addresses of the contiguous dimension.  alpha
+// (real) scales op(A) as it is staged and the accumulators start from
+// beta C, so the epilogue stores them unchanged.
+template <bool CPLX, bool TA, bool TB, int BM, int BN>
+__global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
+                                                  double beta, DMat<double> A, DMat<double> B,
+                                                  DMat<double> C, int tri) {
+  constexpr int NP = CPLX ? 2 : 1;
+  constexpr int PA = BM + 2, PB = BN + 2;
+  constexpr int XM = BM / 32, XN = BN / 32;                // 16 x 16 blocks per wave
+  constexpr int LA = BM * GBK / 256, LB = BN * GBK / 256;  // loads per plane, thread and slab
+  __shared__ __attribute__((aligned(16))) double As[2][NP][GBK][PA];
+  __shared__ __attribute__((aligned(16))) double Bs[2][NP][GBK][PB];
+
+  const uint3 blk = xcd_block();
+  const int64_t m0 = (int64_t)blk.x * BM, n0 = (int64_t)blk.y * BN;
+  if (tri && n0 >= m0 + BM) return;
+  const int b = (int)blk.z;
+  A = A.item(b);
+  B = B.item(b);
+  C = C.item(b);
+  const int64_t ke = K;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
+
+  constexpr int ASTEP = TA ? 256 / GBK : 256 / BM;  // stride of the other index per load
+  constexpr int BSTEP = TB ? 256 / BN : 256 / GBK;
+  const int a_c = TA ? tid % GBK : tid % BM;  // contiguous index (k if TA, else m)
+  const int a_o = TA ? tid / GBK : tid / BM;  // first other index
+  const int b_c = TB ? tid % BN : tid % GBK;  // contiguous index (n if TB, else k)
+  const int b_o = TB ? tid / BN : tid / GBK;
+  const int lda = (int)A.ld, ldb = (int)B.ld;
+  uint32_t offa[LA], offb[LB];
+#pragma unroll
+  for (int q = 0; q < LA; ++q) {
+    const int64_t mi = TA ? m0 + a_o + ASTEP * q : m0 + a_c;
+    const int mr = (int)((mi < M ? mi : M - 1) - m0);
+    const int kr = TA ? a_c : a_o + ASTEP * q;
+    offa[q] = TA ? (uint32_t)(kr + mr * lda) : (uint32_t)(mr + kr * lda);
+  }
+#pragma unroll
+  for (int q = 0; q < LB; ++q) {
+    const int64_t ni = TB ? n0 + b_c : n0 + b_o + BSTEP * q;
+    const int nr = (int)((ni < N ? ni : N - 1) - n0);
+    const int kr = TB ? b_o + BSTEP * q : b_c;
+    offb[q] = TB ? (uint32_t)(nr + kr * ldb) : (uint32_t)(kr + nr * ldb);
+  }
+  const int64_t a_tile = TA ? m0 * A.ld : m0, b_tile = TB ? n0 : n0 * B.ld;
+  double ra[NP][LA], rb[NP][LB];
+  auto gload = [&](int64_t k0) {
+    const int64_t ka = TA ? k0 : k0 * A.ld, kb_ = TB ? k0 * B.ld : k0;
+    const double* pa[2] = {A.re + a_tile + ka, CPLX ? A.im + a_tile + ka : nullptr};
+    const double* pb[2] = {B.re + b_tile + kb_, CPLX ? B.im + b_tile + kb_ : nullptr};
+    if (k0 + GBK <= ke) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) ra[p][q] = pa[p][offa[q]];
+#pragma unroll
+        for (int q = 0; q < LB; ++q) rb[p][q] = pb[p][offb[q]];
+      }
+    } else {
+      // the last slab: K indices beyond ke load from index ke - 1 and read as 0
+      const int kl = (int)(ke - 1 - k0);
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int kr = TA ? a_c : a_o + ASTEP * q;
+        const int kc = kr < kl ? kr : kl;
+        const uint32_t o = TA ? offa[q] - (uint32_t)kr + (uint32_t)kc
+                              : offa[q] - (uint32_t)(kr * lda) + (uint32_t)(kc * lda);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const double v = pa[p][o];
+          ra[p][q] = kr <= kl ? v : 0.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int kr = TB ? b_o + BSTEP * q : b_c;
+        const int kc = kr < kl ? kr : kl;
+        const uint32_t o = TB ? offb[q] - (uint32_t)(kr * ldb) + (uint32_t)(kc * ldb)
+                              : offb[q] - (uint32_t)kr + (uint32_t)kc;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const double v = pb[p][o];
+          rb[p][q] = kr <= kl ? v : 0.0;
+        }
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        if (TA) As[buf][p][a_c][a_o + ASTEP * q] = alpha * ra[p][q];
+        else As[buf][p][a_o + ASTEP * q][a_c] = alpha * ra[p][q];
+      }
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        if (TB) Bs[buf][p][b_o + BSTEP * q][b_c] = rb[p][q];
+        else Bs[buf][p][b_c][b_o + BSTEP * q] = rb[p][q];
+      }
+    }
+  };
+
+  const int64_t il = m0 + wm + (lane & 15), jl = n0 + wn + (lane >> 4);
+  const bool use_c = beta != 0.0;
+  doublex4 acc[NP][XM][XN];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int x = 0; x < XM; ++x)
+#pragma unroll
+      for (int y = 0; y < XN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = il + 16 * x, j = jl + 16 * y + 4 * r;
+          const double* cp = p ? C.im : C.re;
+          acc[p][x][y][r] = (use_c && i < M && j < N) ? beta * cp[i + j * C.ld] : 0.0;
+        }
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = 0; k0 < ke; k0 += GBK) {
+    const bool more = k0 + GBK < ke;
+    if (more) gload(k0 + GBK);
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 4) {
+      const int kr = kk + (lane >> 4), r = lane & 15;
+      double ar[NP][XM], br[NP][XN];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int x = 0; x < XM; ++x) ar[p][x] = As[buf][p][kr][wm + 16 * x + r];
+#pragma unroll
+        for (int y = 0; y < XN; ++y) br[p][y] = Bs[buf][p][kr][wn + 16 * y + r];
+      }
+#pragma unroll
+      for (int x = 0; x < XM; ++x)
+#pragma unroll
+        for (int y = 0; y < XN; ++y) {
+          acc[0][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[0][y], ar[0][x], acc[0][x][y], 0, 0, 0);
+          if constexpr (CPLX) {
+            acc[0][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-br[1][y], ar[1][x], acc[0][x][y], 0, 0, 0);
+            acc[1][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[0][y], ar[1][x], acc[1][x][y], 0, 0, 0);
+            acc[1][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[1][y], ar[0][x], acc[1][x][y], 0, 0, 0);
+          }
+        }
+    }
+    // the other buffer was last read before the previous barrier
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int x = 0; x < XM; ++x)
+#pragma unroll
+      for (int y = 0; y < XN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = il + 16 * x, j = jl + 16 * y + 4 * r;
+          double* cp = p ? C.im : C.re;
+          if (i < M && j < N) cp[i + j * C.ld] = acc[p][x][y][r];
+        }
+}
+
 // C_b = sum over splits of the partial tiles (alpha applied) + beta C_b.
 template <typename T, bool CPLX>
 __global__ void k_splitk_sum(int64_t M, int64_t N, int splits, int batch, const T* part, T beta,
@@ -374,6 +560,20 @@ static void launch(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N
 #undef RFD_GEMM_GO
 }
 
+template <bool CPLX, int BM, int BN>
+static void launch_d(hipStream_t s, bool ta, bool tb, dim3 g, int64_t M, int64_t N, int64_t K,
+                     double alpha, double beta, DMat<double> A, DMat<double> B, DMat<double> C,
+                     int tri, hipEvent_t ea, hipEvent_t eb) {
+#define RFD_DGEMM_GO(TA_, TB_)                                                                  \
+  hipExtLaunchKernelGGL(k_dgemm<CPLX, TA_, TB_, BM, BN>, g, dim3(256), 0, s, ea, eb, 0, M, N, K, \
+                        alpha, beta, A, B, C, tri)
+  if (!ta && !tb) RFD_DGEMM_GO(false, false);
+  else if (ta && !tb) RFD_DGEMM_GO(true, false);
+  else if (!ta && tb) RFD_DGEMM_GO(false, true);
+  else RFD_DGEMM_GO(true, true);
+#undef RFD_DGEMM_GO
+}
+
 // Workgroups of one k_gemm variant that the device holds at once (per-CU
 // occupancy from registers and LDS, times the CU count), per device.
 template <typename T, bool CPLX, int BM, int BN>
@@ -426,9 +626,8 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   // prologue and epilogue).  Complex products keep 64 x 64: measured on
   // gfx950 at 105-120 TF/s against 64-88 for the 128-wide complex tile, whose
   // accumulators leave one wave per SIMD.
-  // FP64 keeps the 64 x 64 tile: with four waves of 16x16x4 blocks it holds
-  // five waves per SIMD and ran the solve's FP64 shapes at 34-44 TF/s, against
-  // 15-45 for 128 x 128 tiles with four or eight waves (one or two per SIMD).
+  // Large real FP64 products go to k_dgemm below; the rest keep the 64 x 64
+  // tile here.
   const bool big_ok = sizeof(T) == 4 && !cplx && M >= 128 && N >= 128 && K >= 256;
   const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128) * batch;
   const int bt = (big_ok && t128 >= 240) ? 128 : 64;
@@ -458,6 +657,48 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
       --splits;
     while (splits > 1 && (int64_t)splits * batch > 65535) --splits;
     if (splits < 1) splits = 1;
+  }
+  // large FP64 products go to k_dgemm (unless the output overwrites an
+  // operand: its tiles would read what other tiles have written, or a complex
+  // operand has no imaginary plane)
+  if constexpr (sizeof(T) == 8) {
+    const bool alias = C.re == A.re || C.re == B.re ||
+                       (cplx && (C.im == A.im || C.im == B.im || !A.im || !B.im));
+    if (!alias && batch <= 65535) {
+      // real: 64 x 128 tiles when they fill the device twice and a 128-wide
+      // tile column is not mostly padding (measured on the solve's shapes:
+      // 63 / 54 TFLOP/s against 50 / 40 for 64 x 64; 128 x 128 tiles ran no
+      // faster and need more registers than two waves per SIMD allow);
+      // complex: 64 x 64 tiles
+      const int bn = cplx ? 64 : 128;
+      const int64_t nt = (N + bn - 1) / bn, g64 = (M + 63) / 64;
+      const int64_t t64 = (tri ? g64 * (g64 + 1) / (bn / 32) : g64 * nt) * batch;
+      const bool wide_ok = cplx || nt * bn <= N + N / 4 || N >= 512;
+      // per-thread element offsets within a tile's K slab must fit 32 bits
+      const int64_t span_a = ta ? (int64_t)GBK + 64 * A.ld : (int64_t)64 + GBK * A.ld;
+      const int64_t span_b = tb ? (int64_t)bn + GBK * B.ld : (int64_t)GBK + bn * B.ld;
+      // (short K, as in the LU trailing updates, stays on the 64 x 64 tile:
+      // a few K slabs do not repay the larger tile's epilogue)
+      if (wide_ok && t64 >= 512 && K >= 256 && nt <= 65535 && g64 <= 0x7fffffff &&
+          span_a < (int64_t(1) << 31) && span_b < (int64_t(1) << 31)) {
+        const int key = 8 + (cplx ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
+        const double outs = tri ? 0.5 * (double)N * (double)(N + 1) : (double)M * (double)N;
+        const double flops = (cplx ? 8.0 : 2.0) * outs * (double)K * batch;
+        const double bytes = (cplx ? 2.0 : 1.0) * 8.0 *
+                             ((double)M * K + (double)K * N + (beta != T(0) ? 2.0 : 1.0) * outs) *
+                             batch;
+        KernelAccount::Scope acct(s, fixed_part ? -1 : key, flops, bytes);
+        dim3 g((unsigned)g64, (unsigned)nt, (unsigned)batch);
+        if (cplx)
+          launch_d<true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, tri, acct.start(),
+                                 acct.stop());
+        else
+          launch_d<false, 64, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, tri,
+                                   acct.start(), acct.stop());
+        RFD_CHECK_LAUNCH();
+        return;
+      }
+    }
   }
   if ((int64_t)batch * splits > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
   if (gm * gn * batch * splits >= ((int64_t)1 << 32)) throw Error(ST_EINVAL, "gemm: grid too large");

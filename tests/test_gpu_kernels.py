@@ -27,13 +27,15 @@ def _host(t):
 
 
 # (M, N, K, batch): ragged small tiles with unaligned leading dimensions;
-# 128-wide tiles with aligned operands and ragged edges (FP64 real from
-# K = 128); a long K split over workgroups (partial sums reduced by a second
-# kernel); a single long-K product; a 128-wide FP64 product with few tiles
-# over a long K (split K on the large tile) and ragged edges
+# 128-wide FP32 tiles with aligned operands and ragged edges; a long K split
+# over workgroups (partial sums reduced by a second kernel); a single long-K
+# product; few tiles over a long K; FP64 products on the large-product
+# kernel (64 x 128 real, 64 x 64 complex tiles) with ragged M, N and a K that
+# ends in a partial slab, the first one with odd leading dimensions
 GEMM_SHAPES = {"small_unaligned": (70, 130, 37, 3), "tile128_ragged": (1100, 1030, 72, 3),
                "tile128_k200": (300, 260, 200, 2), "split_k": (100, 70, 5000, 2),
-               "split_k_single": (100, 70, 9000, 1), "tile128_split_k": (390, 250, 20000, 1)}
+               "split_k_single": (100, 70, 9000, 1), "tile128_split_k": (390, 250, 20000, 1),
+               "dgemm_tall": (4099, 501, 293, 2), "dgemm_square": (4100, 4130, 261, 1)}
 
 
 @pytest.mark.parametrize("shape", list(GEMM_SHAPES))
