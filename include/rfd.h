@@ -202,10 +202,13 @@ rfd_status rfd_prepare_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b
  * last rfd_filter_interface call.
  * V_j: eigenvectors of (B_j, M_Bj) for the nev_b eigenvalues closest to
  * sigma (a cluster at the cut is kept whole), M_Bj-orthonormal (Alg. 5.1
- * step 3; cached per pencil and sigma).  Sigma_j^(psi), Gamma_j^(psi) as in
- * eqs. (5.2)-(5.4) with B_sigma = B_j - sigma M_Bj; every level is made
- * M_Bj-orthogonal to V_j before the next one is formed (this leaves range(Z)
- * unchanged because V_j is part of Z).  Z of eq. (5.5) stays on the device.
+ * step 3; cached per pencil and sigma); for a non-diagonal M they come from
+ * the standard form G^{-1} B_j G^{-T} with M_Bj = G G^T.  Sigma_j^(psi),
+ * Gamma_j^(psi) as in eqs. (5.2)-(5.4) with B_sigma = B_j - sigma M_Bj (the
+ * Gamma_j blocks exist when M couples interiors to the interface, M_E != 0,
+ * and give Z psi * mu more columns); every level is made M_Bj-orthogonal to
+ * V_j before the next one is formed (this leaves range(Z) unchanged because
+ * V_j is part of Z).  Z of eq. (5.5) stays on the device.
  * For a large basis (A Z of 2^24 entries or more) the projected matrix
  * Z^T A Z of rfd_rayleigh_ritz is assembled block by block on a library
  * stream while Z is built, and may still be in progress when this call
@@ -213,7 +216,8 @@ rfd_status rfd_prepare_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b
  * call that reuses the pencil's buffers waits for it first.
  *   k_out   host out: number of columns of Z
  * Errors: RFD_ESTATE without a Q, RFD_EINVAL for nev_b < 0 or psi < 1,
- * RFD_EBREAKDOWN if B_sigma is singular to working precision.
+ * RFD_EBREAKDOWN if B_sigma is singular to working precision or a block M_Bj
+ * is not positive definite.
  */
 rfd_status rfd_solve_interior(rfd_pencil_t pencil, double sigma, int32_t nev_b, int32_t psi,
                               int64_t* k_out, rfd_stream_t stream);
@@ -380,7 +384,8 @@ rfd_status rfd_set_interface_groups(rfd_pencil_t pencil, int32_t ngroups, const 
  * eigensolver's tridiagonalization.  With every = k >= 1, one launch in k of
  * each kernel (picked by a fixed hash of the launch count, so that a periodic
  * launch sequence is not sampled at a few phases only; the same launches in
- * every run) gets a pair of HIP events on its own stream, stamped at the
+ * every run), and every launch of 1e11 flops or more, gets a pair of HIP
+ * events on its own stream, stamped at the
  * kernel's start and end by the launch itself, and its algorithmic flop and
  * byte counts are recorded
  * (GEMM: 2MNK real or 8MNK complex flops; bytes of A and B read once and of
@@ -391,7 +396,9 @@ rfd_status rfd_set_interface_groups(rfd_pencil_t pencil, int32_t ngroups, const 
  * and the summed milliseconds, flops and bytes of the sampled launches, then
  * clears the record.  Keys 0..15:
  * the hand-written GEMM with key = 8*fp64 + 4*complex + 2*transA + transB;
- * key 16: the tridiagonalization mat-vec; the other keys are unused.
+ * key 16: the tridiagonalization mat-vec; keys 17..24: the large-tile FP64
+ * GEMM that takes the large FP64 products, key = 17 + 4*complex + 2*transA +
+ * transB; the other keys are unused.
  */
 rfd_status rfd_kernel_accounting(int32_t every);
 rfd_status rfd_kernel_stats(double* launches, double* sampled, double* ms, double* flops,

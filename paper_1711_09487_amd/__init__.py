@@ -262,6 +262,9 @@ GEMM_KEYS = {8 * f + 4 * c + 2 * a + b: f"k_gemm<{'double' if f else 'float'}, "
              for f in (0, 1) for c in (0, 1) for a in (0, 1) for b in (0, 1)}
 KERNEL_KEYS = dict(GEMM_KEYS)
 KERNEL_KEYS[16] = "k_tri_symv"
+KERNEL_KEYS.update({17 + 4 * c + 2 * a + b: f"k_dgemm<{'true' if c else 'false'}, "
+                    f"{'true' if a else 'false'}, {'true' if b else 'false'}>"
+                    for c in (0, 1) for a in (0, 1) for b in (0, 1)})
 
 
 def rfd_kernel_accounting(every):
@@ -291,6 +294,15 @@ def rfd_test_spectral_orthogonality(h):
     v = C.c_double(0.0)
     _check(lib().rfd_test_spectral_orthogonality(h, C.byref(v)))
     return v.value
+
+
+def rfd_test_basis(h, dst, cap, stream=None):
+    """Copies up to cap columns of the M-orthonormal basis of range(Z) (n
+    rows, interiors then interface) into the device array dst; returns the
+    number of columns the basis has."""
+    k = I64()
+    _check(lib().rfd_test_basis(h, _ptr(dst), int(cap), C.byref(k), _stream(stream)))
+    return k.value
 
 
 def rfd_set_interface_groups(h, group):
@@ -420,6 +432,14 @@ class Pencil:
 
     def spectral_orthogonality(self):
         return rfd_test_spectral_orthogonality(self.h)
+
+    def basis(self, cap, stream=None):
+        """The basis of range(Z) of the last solve_interior (device tensor
+        of shape (k, n): column-major n x k, reordered numbering)."""
+        import torch
+        Z = torch.empty((max(int(cap), 1), self.n), dtype=torch.float64, device="cuda")
+        k = rfd_test_basis(self.h, Z, cap, stream)
+        return Z[:min(k, int(cap))]
 
     def inertia_count(self, alpha, beta, stream=None):
         return rfd_inertia_count(self.h, alpha, beta, stream)

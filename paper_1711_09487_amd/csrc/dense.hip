@@ -26,12 +26,14 @@ KernelAccount::Scope::Scope(hipStream_t s, int key, double flops, double bytes) 
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> g(k.mu);
   // a pseudo-random one launch in `every` (a fixed hash of the launch count):
-  // a plain stride would sample a periodic launch sequence at a few phases
+  // a plain stride would sample a periodic launch sequence at a few phases.
+  // Launches of at least KA_ALWAYS_FLOPS are all timed: they are few, and a
+  // pair of events costs nothing beside them.
   uint64_t h = (uint64_t)k.count[key]++ * 0x9E3779B97F4A7C15ull + (uint64_t)key;
   h ^= h >> 31;
   h *= 0xBF58476D1CE4E5B9ull;
   h ^= h >> 29;
-  if (h % (uint64_t)k.every != 0) return;
+  if (h % (uint64_t)k.every != 0 && flops < KA_ALWAYS_FLOPS) return;
   Rec r;
   r.key = key;
   r.flops = flops;

@@ -18,9 +18,12 @@ constexpr int NB = 64;  // LU / triangular-solve block size (= GEMM tile edge)
 // here, around the call otherwise, together with the launch's algorithmic
 // flops and bytes.  Keys 0..15: the GEMM instantiations (8 fp64 + 4 complex
 // + 2 transA + transB) of the hand-written kernel; KA_TRI_SYMV: the
-// symmetric mat-vec of the tridiagonalization.
+// symmetric mat-vec of the tridiagonalization; KA_DGEMM + (4 complex + 2
+// transA + transB): the large-tile FP64 kernel.
 constexpr int KA_KEYS = 32;
 constexpr int KA_TRI_SYMV = 16;
+constexpr int KA_DGEMM = 17;
+constexpr double KA_ALWAYS_FLOPS = 1e11;  // launches this large are always sampled
 struct KernelAccount {
   struct Rec {
     int key;

@@ -328,7 +328,8 @@ std::vector<DevBuf*> EngineImpl::solve_buffers() {
                          &ow.cn, &ow.used, &ow.piv, &ow.tau, &ow.scal, &ow.rank, &ow.wg, &ow.wt,
                          &ow.w1, &ow.w2, &Tgg64, &TgT64, &Ttt64, &Txc64, &Tgg32, &TgT32,
                          &Txc32, &Ttt32, &Tinvg, &Tinvt, &Twide, &Twork, &Tgt, &TRG, &TRT, &TXG,
-                         &TXT, &TRG32, &TRT32, &TU, &TXTg, &Vs, &lam_s, &Fs, &Fz, &Ts, &Gsp};
+                         &TXT, &TRG32, &TRT32, &TU, &TXTg, &Vs, &lam_s, &Fs, &Fz, &Ts, &Gsp,
+                         &Mlu, &Mluinv, &mflag};
   for (TriWork* t : {&tw_v, &tw_h})
     for (DevBuf* b : {&t->d, &t->e, &t->tau, &t->pt, &t->acol, &t->vw, &t->red, &t->sq, &t->ptvp,
                       &t->wv, &t->wg, &t->wt, &t->w1, &t->w2})
@@ -340,7 +341,7 @@ std::vector<DevBuf*> EngineImpl::solve_buffers() {
 // Buffers an interior preparation writes (see prepare_interior).
 std::vector<DevBuf*> EngineImpl::prep_buffers() {
   std::vector<DevBuf*> v{&Vb, &work1, &work2, &work3, &kap_d, &Bs, &Bsinv, &Bspiv, &Bswide,
-                         &Bswork, &prep_flags};
+                         &Bswork, &prep_flags, &Mlu, &Mluinv, &mflag};
   for (DevBuf* b : {&tw_v.d, &tw_v.e, &tw_v.tau, &tw_v.pt, &tw_v.acol, &tw_v.vw, &tw_v.red,
                     &tw_v.sq, &tw_v.ptvp, &tw_v.wv, &tw_v.wg, &tw_v.wt, &tw_v.w1, &tw_v.w2})
     v.push_back(b);

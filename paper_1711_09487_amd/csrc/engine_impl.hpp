@@ -106,6 +106,7 @@ struct EngineImpl {
   DevBuf Vb;                              // per subdomain D x VB (M_B-orthonormal)
   int64_t VB = 0;                         // padded column capacity per subdomain
   DevBuf kap_d, delta_d;
+  DevBuf Mlu, Mluinv, mflag;              // non-diagonal M: M_Bj = L U (no pivoting), flags
   DevBuf Bs, Bsinv, Bspiv;                // B_sigma LU (FP64, pivoted)
   DevBuf Bswide, Bswork;                  // its BLW-wide diagonal inverses, leaf workspace
   int BLW = 0;
@@ -198,6 +199,7 @@ struct EngineImpl {
                int64_t cols);
   void col_mnorms(hipStream_t st, const double* X, int64_t cols, double* MX, double* out);
   void interior_basis(hipStream_t st, double sigma, int nev_b);
+  double mb_standard_form(hipStream_t st, DMat<double> C, double* sq, double* isq, double sigma);
   void factor_bsigma(hipStream_t st, double sigma, DevBuf* fl = nullptr, bool check = true);
   int gram_orth(hipStream_t st, const double* B, int ncol, double* MB, double* Out,
                 double droptol);

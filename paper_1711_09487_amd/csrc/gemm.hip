@@ -681,7 +681,7 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
       // a few K slabs do not repay the larger tile's epilogue)
       if (wide_ok && t64 >= 512 && K >= 256 && nt <= 65535 && g64 <= 0x7fffffff &&
           span_a < (int64_t(1) << 31) && span_b < (int64_t(1) << 31)) {
-        const int key = 8 + (cplx ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
+        const int key = KA_DGEMM + (cplx ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
         const double outs = tri ? 0.5 * (double)N * (double)(N + 1) : (double)M * (double)N;
         const double flops = (cplx ? 8.0 : 2.0) * outs * (double)K * batch;
         const double bytes = (cplx ? 2.0 : 1.0) * 8.0 *

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <numeric>
 
 #include "dense.hpp"
@@ -149,11 +150,157 @@ __global__ void k_level_drop(DMat<double> X, int64_t D, int64_t cols, const doub
   }
 }
 
-// rhs_j[r, c] = -((Ehat_j - sigma Mhat_E) Q[adj_j, :])[r, c]  (Phi of eq. (5.2), negated
-// so that the first level carries the sign of eq. (5.5)).
+// ---------------------------------------------------------------------------
+// A non-diagonal M_Bj.  The blocks are brought to standard form through the
+// factorization M_Bj = L_j U_j without pivoting (M_Bj is symmetric positive
+// definite, so U_j = diag(u) L_j^T and G_j = L_j diag(u)^{1/2} is its
+// Cholesky factor): C_j = G_j^{-1} B_j G_j^{-T} = diag(u)^{-1/2} L_j^{-1} B_j
+// L_j^{-T} diag(u)^{-1/2}, and eigenvectors Y of C_j give the M_Bj-orthonormal
+// eigenvectors V = G_j^{-T} Y = U_j^{-1} diag(u)^{1/2} Y of (B_j, M_Bj).
+// ---------------------------------------------------------------------------
+
+// Dense image of every subdomain block (A values when which == 0, M values
+// otherwise; C zero on entry), diagonal `pad` on the padding rows.
+__global__ void k_expand_block(DMat<double> C, int64_t D, const int32_t* dj, DevPairCsr B,
+                               int which, double pad) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= D) return;
+  DMat<double> c = C.item(j);
+  if (r >= dj[j]) {
+    c.re[r + r * c.ld] = pad;
+    return;
+  }
+  const int64_t* ptr = B.ptr + B.roff[j];
+  const double* v = which ? B.m : B.a;
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) c.re[r + (int64_t)B.idx[e] * c.ld] = v[e];
+}
+
+// sq = sqrt(u_rr), isq = 1 / sqrt(u_rr) from the diagonal of the factors of
+// M_Bj (p x D; 1 on the padding rows).  A pivot that is not positive (M_Bj not
+// positive definite) sets bit 1 of *flags.
+__global__ void k_lu_diag(DMat<double> LU, int64_t D, const int32_t* dj, double* sq, double* isq,
+                          unsigned* flags) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= D) return;
+  DMat<double> f = LU.item(j);
+  double u = r < dj[j] ? f.re[r + r * f.ld] : 1.0;
+  if (!(u > 0.0) || !isfinite(u)) {
+    atomicOr(flags, 1u);
+    u = 1.0;
+  }
+  sq[(int64_t)j * D + r] = sqrt(u);
+  isq[(int64_t)j * D + r] = 1.0 / sqrt(u);
+}
+
+// 32 x 32 LDS tiles over the leading D x D block of every item (grid D/32 x
+// D/32 x items, 256 threads).  sym == 0: Y = X^T.  sym == 1: Y = (X + X^T) / 2
+// scaled by g[r] g[q] over the active d_j x d_j part (g: p x D), zero
+// elsewhere.  Both reads and the write run along columns.
+constexpr int TT = 32;
+__global__ __launch_bounds__(256) void k_tile_transpose(DMat<double> X, DMat<double> Y, int64_t D,
+                                                        const int32_t* dj, const double* g,
+                                                        int sym) {
+  __shared__ double t[TT][TT + 1];
+  const int j = blockIdx.z;
+  DMat<double> x = X.item(j), y = Y.item(j);
+  const int64_t r0 = (int64_t)blockIdx.x * TT, q0 = (int64_t)blockIdx.y * TT;
+  const int tx = threadIdx.x & (TT - 1), ty = threadIdx.x / TT;
+  // t[c][a] = X[q0 + a, r0 + c]
+  for (int c = ty; c < TT; c += 256 / TT) {
+    const int64_t q = q0 + tx, r = r0 + c;
+    t[c][tx] = (q < D && r < D) ? x.re[q + r * x.ld] : 0.0;
+  }
+  __syncthreads();
+  const int64_t dact = dj ? dj[j] : D;
+  for (int c = ty; c < TT; c += 256 / TT) {
+    const int64_t r = r0 + tx, q = q0 + c;
+    if (r >= D || q >= D) continue;
+    const double tv = t[tx][c];  // X[q, r]
+    if (!sym) {
+      y.re[r + q * y.ld] = tv;
+    } else {
+      const bool act = r < dact && q < dact;
+      const double* gj = g + (int64_t)j * D;
+      y.re[r + q * y.ld] = act ? 0.5 * (x.re[r + q * x.ld] + tv) * gj[r] * gj[q] : 0.0;
+    }
+  }
+}
+
+// *out = max over the active rows of every item of sum_q |C_j[r, q]|
+// (||C_j||_inf, a bound on its spectral radius), bitwise atomic max.
+__global__ void k_row_absmax(DMat<double> C, int64_t D, const int32_t* dj,
+                             unsigned long long* out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int64_t d = dj[j];
+  if (r >= d) return;
+  DMat<double> c = C.item(j);
+  double acc = 0;
+  for (int64_t q = 0; q < d; ++q) acc += fabs(c.re[r + q * c.ld]);
+  atomicMax(out, (unsigned long long)__double_as_longlong(acc));
+}
+
+// C_j[r, r] = v on the padding rows d_j <= r < D.
+__global__ void k_pad_diag(DMat<double> C, int64_t D, const int32_t* dj, double v) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= D || r < dj[j]) return;
+  DMat<double> c = C.item(j);
+  c.re[r + r * c.ld] = v;
+}
+
+// Y_j = M_Bj X_j on the active rows, zero on the padding rows (CG columns
+// per thread, subdomains over grid z), from the M values of the subdomain
+// CSR blocks.
+__global__ void k_block_mb(DMat<double> X, DMat<double> Y, int64_t D, int64_t cols,
+                           const int32_t* dj, DevPairCsr B) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  const int j = blockIdx.z;
+  const int64_t c0 = (int64_t)blockIdx.y * CG;
+  DMat<double> x = X.item(j), y = Y.item(j);
+  double acc[CG] = {};
+  if (r < dj[j]) {
+    const int64_t* ptr = B.ptr + B.roff[j];
+    for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+      const double m = B.m[e];
+      const double* xc = x.re + (int64_t)B.idx[e] + c0 * x.ld;
+#pragma unroll
+      for (int u = 0; u < CG; ++u)
+        if (c0 + u < cols) acc[u] += m * xc[u * x.ld];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < CG; ++u)
+    if (c0 + u < cols) y.re[r + (c0 + u) * y.ld] = acc[u];
+}
+
+// out[c] = sqrt(sum_j x_j^T (M_Bj x_j)) for column c of a level, from the
+// level X and MX = M_B X (one workgroup per column).
+__global__ void k_level_coldot(DMat<double> X, DMat<double> MX, int p, const int32_t* dj,
+                               double* out) {
+  __shared__ double red[256];
+  const int64_t c = blockIdx.x;
+  double acc = 0;
+  for (int j = 0; j < p; ++j) {
+    DMat<double> x = X.item(j), mx = MX.item(j);
+    const int64_t dr = dj[j];
+    const double* xc = x.re + c * x.ld;
+    const double* mc = mx.re + c * mx.ld;
+    for (int64_t r = threadIdx.x; r < dr; r += 256) acc += xc[r] * mc[r];
+  }
+  acc = bsum(acc, red);
+  if (threadIdx.x == 0) out[c] = sqrt(fmax(acc, 0.0));
+}
+
+// rhs_j[r, c] = ((ca Ehat_j + cm Mhat_E^(j)) Q[adj_j, :])[r, c].  With ca = -1,
+// cm = sigma: Phi of eq. (5.2), negated so that the first level carries the
+// sign of eq. (5.5); with ca = 0, cm = 1: Psi = Mhat_E Q of eq. (5.3).
 __global__ void k_gather_phi(DMat<double> R, int64_t D, int64_t cols_pad, const int32_t* dj,
-                             DevPairCsr E, double sigma, const double* Q, int64_t ldq, int mu,
-                             const int32_t* adj, int64_t SJ) {
+                             DevPairCsr E, double ca, double cm, const double* Q, int64_t ldq,
+                             int mu, const int32_t* adj, int64_t SJ) {
   const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (e0 >= D * cols_pad) return;
@@ -163,7 +310,7 @@ __global__ void k_gather_phi(DMat<double> R, int64_t D, int64_t cols_pad, const 
   if (r < dj[j] && c < mu) {
     const int64_t* ptr = E.ptr + E.roff[j];
     for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e)
-      v -= (E.a[e] - sigma * E.m[e]) * Q[adj[(int64_t)j * SJ + E.idx[e]] + c * ldq];
+      v += (ca * E.a[e] + cm * E.m[e]) * Q[adj[(int64_t)j * SJ + E.idx[e]] + c * ldq];
   }
   x.re[r + c * x.ld] = v;
 }
@@ -500,13 +647,63 @@ static std::vector<int> clusters(const std::vector<double>& lam, double gap) {
   return c;
 }
 
+// Standard form of the pencils (B_j, M_Bj) for a non-diagonal M: C_j =
+// G_j^{-1} B_j G_j^{-T} (C zero on entry) with M_Bj = G_j G_j^T from the
+// factorization M_Bj = L_j U_j kept in Mlu / Mluinv; sq, isq (p x D) receive
+// sqrt(u) and 1 / sqrt(u).  Sets the padding diagonal of C and returns it: a
+// value above ||C_j||_inf of every block and |sigma|.
+double EngineImpl::mb_standard_form(hipStream_t st, DMat<double> C, double* sq, double* isq,
+                                    double sig) {
+  Mlu.alloc(sizeof(double) * D * D * p);
+  Mluinv.alloc(sizeof(double) * NB * 2 * D * p);
+  mflag.alloc(sizeof(unsigned long long) * 2);
+  RFD_HIP(hipMemsetAsync(mflag.p, 0, sizeof(unsigned long long) * 2, st));
+  unsigned* fl = mflag.as<unsigned>();
+  unsigned long long* nrm = mflag.as<unsigned long long>() + 1;
+  DMat<double> F{Mlu.as<double>(), nullptr, D, D * D};
+  DMat<double> Fi{Mluinv.as<double>(), nullptr, NB, NB * 2 * D};
+  fill<double>(st, F, D, D, p, 0.0);
+  k_expand_block<<<dim3(grid1(D), p), 256, 0, st>>>(F, D, dj.as<int32_t>(), Bg.view(), 1, 1.0);
+  RFD_CHECK_LAUNCH();
+  lu_nopiv<double>(st, F, D, p, Fi, fl, 1e-300);
+  k_lu_diag<<<dim3(grid1(D), p), 256, 0, st>>>(F, D, dj.as<int32_t>(), sq, isq, fl);
+  RFD_CHECK_LAUNCH();
+  // C = L^{-1} B, W = C^T = B L^{-T}, W = L^{-1} W, C = sym(W) scaled by
+  // diag(u)^{-1/2} on both sides
+  k_expand_block<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), 0, 0.0);
+  RFD_CHECK_LAUNCH();
+  lu_solve<double>(st, F, Fi, nullptr, D, C, D, p, 1);
+  DevBuf& wb = tmp[6];
+  wb.alloc(sizeof(double) * D * D * p);
+  DMat<double> Wm{wb.as<double>(), nullptr, D, D * D};
+  const dim3 tg((unsigned)((D + TT - 1) / TT), (unsigned)((D + TT - 1) / TT), (unsigned)p);
+  k_tile_transpose<<<tg, 256, 0, st>>>(C, Wm, D, nullptr, nullptr, 0);
+  RFD_CHECK_LAUNCH();
+  lu_solve<double>(st, F, Fi, nullptr, D, Wm, D, p, 1);
+  k_tile_transpose<<<tg, 256, 0, st>>>(Wm, C, D, dj.as<int32_t>(), isq, 1);
+  RFD_CHECK_LAUNCH();
+  k_row_absmax<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), nrm);
+  RFD_CHECK_LAUNCH();
+  unsigned long long h[2] = {0, 0};
+  RFD_HIP(hipMemcpyAsync(h, mflag.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  RFD_HIP(hipStreamSynchronize(st));
+  if ((unsigned)h[0])
+    throw Error(ST_EBREAKDOWN, "M_B factorization: a subdomain block of M is not positive definite");
+  double cn = 0.0;
+  std::memcpy(&cn, &h[1], sizeof(double));
+  if (!std::isfinite(cn)) throw Error(ST_EBREAKDOWN, "M_B factorization: non-finite value");
+  const double big = 2.0 * cn + 4.0 * std::fabs(sig) + 1.0;
+  k_pad_diag<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), big);
+  RFD_CHECK_LAUNCH();
+  return big;
+}
+
 void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   if (vcache_valid && vcache_sigma == sig && vcache_nevb == nevb) return;
   if (interior_solver == 1) {
     spectral_select(st, sig, nevb);
     return;
   }
-  if (!P->m_diag) throw Error(ST_EINVAL, "the interior basis on the GPU needs a diagonal M");
   kappa.assign(p, 0);
   kappa_tot = 0;
   VB = 0;
@@ -517,20 +714,28 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
     return;
   }
   timer.begin(st, 6);
-  // M-scaled dense blocks
+  // standard-form dense blocks: M^{-1/2} B M^{-1/2} (diagonal M) or
+  // G^{-1} B G^{-T} with M_Bj = G G^T (otherwise); the padding rows get a
+  // diagonal value above every eigenvalue of the blocks
   work1.alloc(sizeof(double) * 2 * p * D);
-  double* md = work1.as<double>();
-  double* mis = md + p * D;
-  k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, dj.as<int32_t>(), Bg.view(), md, mis);
-  RFD_CHECK_LAUNCH();
-  double mmin = 1e300;
-  for (double v : M->val) mmin = std::min(mmin, v > 0 ? v : 1e300);
-  const double big = 4.0 * normA / std::max(mmin, 1e-300) + 4.0 * std::fabs(sig) + 1.0;
+  double* md = work1.as<double>();   // diag(M_B), or sqrt(u) of M_B = L U
+  double* mis = md + p * D;          // its inverse square roots, or 1 / sqrt(u)
   work2.alloc(sizeof(double) * D * D * p);
   DMat<double> C{work2.as<double>(), nullptr, D, D * D};
   fill<double>(st, C, D, D, p, 0.0);
-  k_expand_scaled<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), mis, big);
-  RFD_CHECK_LAUNCH();
+  double big;
+  if (P->m_diag) {
+    k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, dj.as<int32_t>(), Bg.view(), md, mis);
+    RFD_CHECK_LAUNCH();
+    double mmin = 1e300;
+    for (double v : M->val) mmin = std::min(mmin, v > 0 ? v : 1e300);
+    big = 4.0 * normA / std::max(mmin, 1e-300) + 4.0 * std::fabs(sig) + 1.0;
+    k_expand_scaled<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), mis,
+                                                       big);
+    RFD_CHECK_LAUNCH();
+  } else {
+    big = mb_standard_form(st, C, md, mis, sig);
+  }
   TriWork& tw = tw_v;
   // the eigensolver runs on the leading DE = max d_j rows and columns: beyond
   // them every block is the decoupled identity padding
@@ -612,9 +817,18 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
   inverse_iteration(st, tw, DE, p, sel_d.as<double>(), kn_d.as<int>(), cl_d.as<int>(), VB, Y,
                     scratch);
   back_transform(st, C, tw, DE, p, Y, kn_d.as<int>(), (int)VB);
-  // V = M^{-1/2} Y
-  k_scale_rows<<<dim3(grid1(D * VB), p), 256, 0, st>>>(Y, D, VB, mis, D);
-  RFD_CHECK_LAUNCH();
+  if (P->m_diag) {
+    // V = M^{-1/2} Y
+    k_scale_rows<<<dim3(grid1(D * VB), p), 256, 0, st>>>(Y, D, VB, mis, D);
+    RFD_CHECK_LAUNCH();
+  } else {
+    // V = G^{-T} Y = U^{-1} diag(u)^{1/2} Y
+    k_scale_rows<<<dim3(grid1(D * VB), p), 256, 0, st>>>(Y, D, VB, md, D);
+    RFD_CHECK_LAUNCH();
+    DMat<double> F{Mlu.as<double>(), nullptr, D, D * D};
+    DMat<double> Fi{Mluinv.as<double>(), nullptr, NB, NB * 2 * D};
+    lu_solve<double>(st, F, Fi, nullptr, D, Y, VB, p, 2);
+  }
   upload_v(st, kap_d, kappa);
   timer.end(st);
   RFD_HIP(hipStreamSynchronize(st));
@@ -1114,7 +1328,6 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   EngineImpl& e = *d_;
   e.join_prepare();
   if (e.Qint.p == nullptr) throw Error(ST_ESTATE, "rfd_filter_interface has not been called");
-  if (!e.P->m_diag) throw Error(ST_EINVAL, "the interior part on the GPU needs a diagonal M");
   e.ensure_reordered(st);
   e.interior_basis(st, sig, nevb);
   e.factor_bsigma(st, sig);
@@ -1126,7 +1339,8 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   e.psi = psi;
   e.MUP = round_up(std::max(mu, 1), NB);
   const int64_t MUP = e.MUP;
-  const double* md = e.work1.as<double>();  // diag(M_B) per subdomain row (from interior_basis)
+  // diag(M_B) per subdomain row, from interior_basis (read for a diagonal M only)
+  const double* md = e.work1.as<double>();
   if (nevb == 0) {
     e.work1.alloc(sizeof(double) * 2 * p * D);
     k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, e.dj.as<int32_t>(), e.Bg.view(),
@@ -1134,69 +1348,84 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
     RFD_CHECK_LAUNCH();
     md = e.work1.as<double>();
   }
-  // resolvent levels
+  // resolvent levels: Sigma (from Phi) and, when M_E != 0, Gamma (from Psi)
+  const bool mdg = e.P->m_diag;
+  const int ng = e.P->m_e_zero ? 1 : 2;
+  const int nlev = psi * ng;
   e.timer.begin(st, 8);
-  e.Lev.alloc(sizeof(double) * D * psi * MUP * p);
+  e.Lev.alloc(sizeof(double) * D * nlev * MUP * p);
   e.work3.alloc(sizeof(double) * D * MUP * p);            // right-hand side / M_B X
   e.work4.alloc(sizeof(double) * std::max<int64_t>(e.VB, 1) * MUP * p);  // V^T M X
-  DMat<double> Lv{e.Lev.as<double>(), nullptr, D, D * psi * MUP};
+  DMat<double> Lv{e.Lev.as<double>(), nullptr, D, D * nlev * MUP};
   DMat<double> Rh{e.work3.as<double>(), nullptr, D, D * MUP};
   DMat<double> Ki{e.Bsinv.as<double>(), nullptr, NB, NB * 2 * D};
   DMat<double> Bm{e.Bs.as<double>(), nullptr, D, D * D};
   DMat<double> Vm{e.Vb.as<double>(), nullptr, D, D * e.VB};
   DMat<double> Tm{e.work4.as<double>(), nullptr, std::max<int64_t>(e.VB, 1),
                   std::max<int64_t>(e.VB, 1) * MUP};
-  k_gather_phi<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(
-      Rh, D, MUP, e.dj.as<int32_t>(), e.Eg.view(), sig, e.Qint.as<double>(), s, mu,
-      e.adj.as<int32_t>(), e.SJ);
-  RFD_CHECK_LAUNCH();
+  const dim3 lg(grid1(D), col_groups(MUP), p);
+  // Y = M_B X, per subdomain
+  auto apply_mb = [&](DMat<double> X, DMat<double> Y) {
+    if (mdg)
+      k_scaled_copy<<<lg, 256, 0, st>>>(X, Y, D, MUP, md, D);
+    else
+      k_block_mb<<<lg, 256, 0, st>>>(X, Y, D, MUP, e.dj.as<int32_t>(), e.Bg.view());
+    RFD_CHECK_LAUNCH();
+  };
+  // out[c] = M_B-norm of column c of a level (Rh is scratch for a general M)
+  auto level_norms = [&](DMat<double> X, double* out) {
+    if (mdg) {
+      k_level_colnorm<<<MUP, 256, 0, st>>>(X, p, e.dj.as<int32_t>(), md, D, out);
+    } else {
+      apply_mb(X, Rh);
+      k_level_coldot<<<MUP, 256, 0, st>>>(X, Rh, p, e.dj.as<int32_t>(), out);
+    }
+    RFD_CHECK_LAUNCH();
+  };
   DevBuf& nrm = e.tmp[7];
   nrm.alloc(sizeof(double) * 2 * MUP);
   double* pre = nrm.as<double>();
   double* post = pre + MUP;
-  for (int t = 0; t < psi; ++t) {
-    DMat<double> X = Lv.sub(0, t * MUP);
-    convert<double, double>(st, Rh, X, D, MUP, p);
-    if (e.interior_solver == 1) {
-      e.spectral_level(st, X, MUP, sig);
-    } else if (e.BLW) {
-      const int64_t per = (int64_t)e.BLW * 2 * D;
-      e.Bswork.alloc(std::max<int64_t>(e.Bswork.bytes, sizeof(double) * e.BLW * MUP * p));
-      lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p, 3,
-                       DMat<double>{e.Bswide.as<double>(), nullptr, e.BLW, per}, e.BLW,
-                       DMat<double>{e.Bswork.as<double>(), nullptr, e.BLW, e.BLW * MUP});
-    } else {
-      lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p);
-    }
-    // make the level M_B-orthogonal to V_j (twice)
-    if (e.kappa_tot > 0) {
-      if (t > 0) {
-        k_level_colnorm<<<MUP, 256, 0, st>>>(X, p, e.dj.as<int32_t>(), md, D, pre);
-        RFD_CHECK_LAUNCH();
+  for (int g = 0; g < ng; ++g) {
+    k_gather_phi<<<dim3(grid1(D * MUP), p), 256, 0, st>>>(
+        Rh, D, MUP, e.dj.as<int32_t>(), e.Eg.view(), g == 0 ? -1.0 : 0.0, g == 0 ? sig : 1.0,
+        e.Qint.as<double>(), s, mu, e.adj.as<int32_t>(), e.SJ);
+    RFD_CHECK_LAUNCH();
+    for (int t = 0; t < psi; ++t) {
+      DMat<double> X = Lv.sub(0, (g * psi + t) * MUP);
+      convert<double, double>(st, Rh, X, D, MUP, p);
+      if (e.interior_solver == 1) {
+        e.spectral_level(st, X, MUP, sig);
+      } else if (e.BLW) {
+        const int64_t per = (int64_t)e.BLW * 2 * D;
+        e.Bswork.alloc(std::max<int64_t>(e.Bswork.bytes, sizeof(double) * e.BLW * MUP * p));
+        lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p, 3,
+                         DMat<double>{e.Bswide.as<double>(), nullptr, e.BLW, per}, e.BLW,
+                         DMat<double>{e.Bswork.as<double>(), nullptr, e.BLW, e.BLW * MUP});
+      } else {
+        lu_solve<double>(st, Bm, Ki, e.Bspiv.as<int32_t>(), D, X, MUP, p);
       }
-      for (int pass = 0; pass < 2; ++pass) {
-        k_scaled_copy<<<dim3(grid1(D), col_groups(MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
-        RFD_CHECK_LAUNCH();
-        gemm<double>(st, true, false, e.VB, MUP, D, 1.0, Vm, Rh, 0.0, Tm, p);
-        gemm<double>(st, false, false, D, MUP, e.VB, -1.0, Vm, Tm, 1.0, X, p);
+      // make the level M_B-orthogonal to V_j (twice)
+      if (e.kappa_tot > 0) {
+        if (t > 0) level_norms(X, pre);
+        for (int pass = 0; pass < 2; ++pass) {
+          apply_mb(X, Rh);
+          gemm<double>(st, true, false, e.VB, MUP, D, 1.0, Vm, Rh, 0.0, Tm, p);
+          gemm<double>(st, false, false, D, MUP, e.VB, -1.0, Vm, Tm, 1.0, X, p);
+        }
+        if (t > 0) {
+          level_norms(X, post);
+          k_level_drop<<<lg, 256, 0, st>>>(X, D, MUP, pre, post, 1e-10);
+          RFD_CHECK_LAUNCH();
+        }
       }
-      if (t > 0) {
-        k_level_colnorm<<<MUP, 256, 0, st>>>(X, p, e.dj.as<int32_t>(), md, D, post);
-        RFD_CHECK_LAUNCH();
-        k_level_drop<<<dim3(grid1(D), col_groups(MUP), p), 256, 0, st>>>(X, D, MUP, pre, post,
-                                                                          1e-10);
-        RFD_CHECK_LAUNCH();
-      }
-    }
-    if (t + 1 < psi) {
-      k_scaled_copy<<<dim3(grid1(D), col_groups(MUP), p), 256, 0, st>>>(X, Rh, D, MUP, md, D);
-      RFD_CHECK_LAUNCH();
+      if (t + 1 < psi) apply_mb(X, Rh);
     }
   }
   e.timer.end(st);
   // M-orthonormal basis of range(Z): [V | levels orthonormalised level by level]
   e.timer.begin(st, 9);
-  const int64_t kmax = e.kappa_tot + (int64_t)psi * mu;
+  const int64_t kmax = e.kappa_tot + (int64_t)nlev * mu;
   e.h_begin(n * std::max<int64_t>(kmax, 1) >= (int64_t(1) << 24));
   e.Zt.alloc(sizeof(double) * n * std::max<int64_t>(kmax, 1));
   double* Z = e.Zt.as<double>();
@@ -1228,7 +1457,7 @@ void Engine::solve_interior(hipStream_t st, double sig, int nevb, int psi, int64
   double* n0 = e.work6.as<double>();             // column M-norms before / after projection
   double* n1 = n0 + mu;
   int64_t kz = e.kappa_tot;
-  for (int t = 0; t < psi && mu > 0; ++t) {
+  for (int t = 0; t < nlev && mu > 0; ++t) {
     k_build_level<<<dim3(grid1(n), col_groups(mu)), 256, 0, st>>>(
         Lb, n, Lv, t, MUP, e.ioff.as<int32_t>(), p, n_int, n, e.Qint.as<double>(), s, mu);
     RFD_CHECK_LAUNCH();

@@ -381,29 +381,151 @@ def test_mode_switch_refactors():
     assert np.max(np.abs(W0 - W1)) < 1e-11 * np.max(np.abs(W0))
 
 
+COUPLED = {
+    # nine uneven subdomains, a two-tile interface, one block step
+    "p9_uneven": (lambda: W.tiny(N=27, P=3, nev=6, n_c=4, m=16, steps=1, nev_b=6, psi=2,
+                                 mass_kind="coupled", cfg_id=49), False),
+    # 400-node interiors padded to 448 (seven tiles and a ragged tail)
+    "mid_7tiles": (lambda: W.tiny(N=41, P=2, nev=10, n_c=8, m=40, steps=2, nev_b=12, psi=4,
+                                  mass_kind="coupled", cfg_id=50), False),
+    "two_level": (lambda: W.tiny(N=41, P=4, nev=17, n_c=8, m=40, steps=2, nev_b=12, psi=5,
+                                 mass_kind="coupled", cfg_id=51), True),
+    "tiny3d_p8": (lambda: W.tiny(N=11, dim=3, P=2, nev=8, n_c=6, m=40, steps=2, nev_b=10,
+                                 psi=4, mass_kind="coupled", kfield=True, cfg_id=52), False),
+    # no deflation basis: the levels and Gamma blocks alone
+    "no_deflation": (lambda: W.tiny(N=27, P=3, nev=6, n_c=4, m=16, steps=2, nev_b=0, psi=3,
+                                    mass_kind="coupled", cfg_id=53), False),
+}
+_ccache = {}
+
+
+def _coupled(name):
+    """The problem, its groups flag, the oracle's run, its filtered block
+    W1 = F Y0 (eq. (3.5)), and the first Sigma and Gamma levels of W1 as
+    columns of eq. (5.5) ([-Sigma_1; W1] and [Gamma_1; 0], unit M-norm,
+    interior-first numbering).  span(Q) holds W1 on both sides, so these
+    columns lie in range(Z); the columns built from Q itself would not do as
+    a check, because the directions of Q beyond W1 are fixed by a
+    rank-revealing truncation only up to its drop tolerance."""
+    if name not in _ccache:
+        make, groups = COUPLED[name]
+        prob = make()
+        dd = O.DD(prob.A, prob.M, prob.part)
+        assert not dd.m_e_zero
+        z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
+        W1 = O.filter_apply(O.factor_poles(dd, z), w, prob.Y0)
+        ro = O.run(prob)
+        V, _ = O.interior_basis(dd, prob.sigma, prob.nev_b)
+        kap = sum(v.shape[1] for v in V)
+        S1, G1 = O.interior_levels(dd, prob.sigma, 1, W1, V)
+        Zw = O.build_z(dd, V, S1, G1, W1, 1)
+        m = W1.shape[1]
+        order = dd.order()
+        Mr = dd.M[order][:, order].tocsr()
+        first = Zw[:, kap:kap + 2 * m]
+        nrm = np.sqrt(np.einsum("ij,ij->j", first, Mr @ first))
+        assert np.all(nrm > 0)
+        _ccache[name] = (prob, groups, ro, W1, first / nrm, Mr, dd)
+    return _ccache[name]
+
+
+def test_coupled_mass_gamma_columns_add_directions():
+    """The check below that the Gamma columns lie in the GPU's basis can
+    fail: on the oracle's side, the first Gamma level of W1 has columns far
+    (relative M-distance > 1e-3) from the range of Z without its Gamma
+    blocks, in every coupled case."""
+    for name in COUPLED:
+        prob, _, ro, W1, first, Mr, dd = _coupled(name)
+        V, _ = O.interior_basis(dd, prob.sigma, prob.nev_b)
+        Sig, _ = O.interior_levels(dd, prob.sigma, prob.psi, ro.Q, V)
+        kap, mu = sum(v.shape[1] for v in V), ro.mu
+        Z = O.build_z(dd, V, Sig, [0 * S for S in Sig], ro.Q, prob.psi)[:, :kap + prob.psi * mu]
+        L = np.linalg.cholesky(Mr.toarray())
+        U, sv, _ = np.linalg.svd(L.T @ Z, full_matrices=False)
+        q = U[:, :int(np.count_nonzero(sv > 1e-13 * sv[0]))]
+        LG = L.T @ first[:, W1.shape[1]:]
+        rel = np.linalg.norm(LG - q @ (q.T @ LG), axis=0)
+        assert np.max(rel) > 1e-3, (name, np.max(rel))
+
+
 @pytest.mark.parametrize("mode", [0, 1])
-def test_filter_with_coupled_mass_matches_the_oracle(mode):
-    """A non-diagonal M couples the interface to the interiors (M_E != 0), so
-    the off-diagonal blocks of A - zeta M carry zeta and the Schur complement
-    takes their plain transpose (Sec. 3.1).  The filtered block (eq. (3.5))
-    matches the oracle element by element on nine uneven subdomains with a
-    two-tile interface.  The interior part needs a diagonal M on the GPU and
-    says so instead of computing."""
-    import paper_1711_09487_amd as R
+@pytest.mark.parametrize("name", list(COUPLED))
+def test_coupled_mass_matches_the_oracle(name, mode):
+    """A non-diagonal M couples the interface to the interiors (M_E != 0):
+    the off-diagonal blocks of A - zeta M carry zeta, V_j are eigenvectors of
+    (B_j, M_Bj) with a non-diagonal M_Bj, and Z of eq. (5.5) gains the
+    Gamma_j blocks of eqs. (5.3)-(5.4) next to Sigma_j.  Against the oracle
+    on the same seeded inputs:
+      * the filtered block F Y0 element by element;
+      * the GPU's basis is M-orthonormal and holds the oracle's first Sigma
+        and Gamma levels of W1 (relative M-distance <= 1e-8);
+      * the Ritz values (relative 1e-10), residuals (<= 10x the oracle's) and
+        Ritz vectors (principal angles per cluster);
+      * the inertia count of [alpha, beta] equals the number of eigenvalues
+        the interval was built to hold."""
     torch = _torch()
-    prob = W.tiny(N=27, P=3, nev=6, n_c=4, m=16, steps=1, nev_b=6, psi=2,
-                  mass_kind="coupled", cfg_id=49)
-    dd = O.DD(prob.A, prob.M, prob.part)
-    z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
-    ref = O.filter_apply(O.factor_poles(dd, z), w, prob.Y0)
+    prob, groups, ro, W1, first, Mr, _ = _coupled(name)
     P = _pencil(prob, mode)
+    if groups:
+        P.set_interface_groups(W.interface_groups(prob.grid, prob.meta["P"]))
     try:
         Wg = P.filter_apply(_dev_block(torch, prob.Y0)).cpu().numpy().T
-        err = np.max(np.abs(Wg - ref)) / np.max(np.abs(ref))
-        assert err < (1e-12 if mode == 0 else 1e-11), err
+        Q = P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
+        k = P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+        Z = P.basis(k).cpu().numpy().T
+        ev, X, res = P.rayleigh_ritz(max(prob.nev + 20, 64))
+        torch.cuda.synchronize()
+        th, X, res = ev.cpu().numpy(), X.cpu().numpy().T, res.cpu().numpy()
+        count = P.inertia_count(prob.alpha, prob.beta)
+    finally:
+        P.close()
+    assert count == prob.nev
+    err = np.max(np.abs(Wg - W1)) / np.max(np.abs(W1))
+    assert err < (1e-12 if mode == 0 else 1e-11), err
+    assert Q.shape[0] == ro.mu
+    assert Z.shape[1] == k
+    MZ = Mr @ Z
+    assert np.max(np.abs(Z.T @ MZ - np.eye(k))) < 1e-10
+    dist = first - Z @ (MZ.T @ first)
+    rel = np.sqrt(np.maximum(np.einsum("ij,ij->j", dist, Mr @ dist), 0.0))
+    assert np.max(rel) <= 1e-8, np.max(rel)
+    assert th.size == ro.theta.size == prob.nev
+    assert np.max(np.abs(th - ro.theta) / np.abs(ro.theta)) <= EIG_TOL
+    assert np.all(res <= 10 * ro.resid + 1e-12)
+    i = 0
+    while i < th.size:
+        j = i + 1
+        while j < th.size and ro.theta[j] - ro.theta[j - 1] < 1e-8 * abs(ro.theta[j]):
+            j += 1
+        ang = _sin_angles(X[:, i:j], ro.X[:, i:j])
+        assert np.max(ang) < 1e-4 + 100 * np.max(ro.resid[i:j]), (i, j, ang)
+        i = j
+
+
+def test_indefinite_interior_mass_block_is_reported():
+    """The interior basis takes M_Bj = G G^T; a subdomain block of M that is
+    not positive definite (two interior nodes of one subdomain coupled by 2
+    against unit diagonals, a 2 x 2 principal minor of -3; every diagonal
+    entry stays positive, which is all the pencil's creation checks) is
+    reported as RFD_EBREAKDOWN by rfd_solve_interior, computed from the
+    pivots of its factorization, not by a fault."""
+    import paper_1711_09487_amd as R
+    import scipy.sparse as sp
+    torch = _torch()
+    prob = W.tiny(N=13, P=2, nev=6, n_c=4, m=8, steps=1, nev_b=4, psi=2, mass_kind="coupled",
+                  cfg_id=54)
+    M = sp.lil_matrix(prob.M)
+    i, k = (int(x) for x in np.flatnonzero(prob.part == 0)[[3, 17]])
+    M[i, k] = M[k, i] = 2.0
+    P = R.Pencil(prob.A, sp.csr_matrix(M))
+    try:
+        P.set_partition(prob.part)
+        P.set_interval_and_poles(prob.alpha, prob.beta, prob.n_c, R.RFD_RULE_GAUSS)
         P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
-        with pytest.raises(R.RfdError, match="diagonal M"):
+        with pytest.raises(R.RfdError) as e:
             P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+        assert e.value.code == 3
+        assert "positive definite" in str(e.value)
     finally:
         P.close()
 
