@@ -71,7 +71,8 @@ def make_pencil(R, W, prob, mode, refine_tol=0.0, spectral=False):
     if spectral:
         P.set_interior_solver(R.RFD_INTERIOR_SPECTRAL)
     P.set_interval_and_poles(prob.alpha, prob.beta, prob.n_c, rule_of(R, prob))
-    P.set_precision(R.RFD_FP32_REFINE if mode == "fp32" else R.RFD_FP64, refine_tol)
+    P.set_precision({"fp32": R.RFD_FP32_AUTO, "fp32all": R.RFD_FP32_REFINE}.get(mode, R.RFD_FP64),
+                    refine_tol)
     return P
 
 
@@ -201,6 +202,7 @@ def measured_traffic(kname, workload):
 
 
 def roofline_entry(kname, st, f32, steps, workload):
+    # ms, flops and bytes: estimates over all launches of the timed steps
     launches, sampled, ms, flops, byts = st
     if kname == "k_tri_symv":
         achieved = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -223,10 +225,10 @@ def roofline_entry(kname, st, f32, steps, workload):
     e["frac"] = e["achieved"] / e["peak"]
     e["traffic"] = measured_traffic(kname, workload)
     e["launches_per_step"] = launches / steps
-    e["sampled_launches"] = sampled
-    e["avg_launch_us"] = 1e3 * ms / max(sampled, 1)
-    e["algorithmic_bytes_per_launch"] = byts / max(sampled, 1)
-    e["flops_per_launch"] = flops / max(sampled, 1)
+    e["timed_launches"] = sampled
+    e["avg_launch_us"] = 1e3 * ms / max(launches, 1)
+    e["algorithmic_bytes_per_launch"] = byts / max(launches, 1)
+    e["flops_per_launch"] = flops / max(launches, 1)
     return e
 
 
@@ -299,12 +301,12 @@ def batch_leg(R, W, torch, count, workers):
     def jobs(mode):
         return [R.Job(P, pr.alpha, pr.beta, pr.n_c, y, pr.steps, pr.sigma, pr.nev_b, pr.psi,
                       pr.nev + 30, mode=mode, rule=rule_of(R, pr),
-                      refine_tol=TARGET_TOL if mode == R.RFD_FP32_REFINE else 0.0)
+                      refine_tol=TARGET_TOL if mode != R.RFD_FP64 else 0.0)
                 for P, pr, y in zip(pens, probs, y0)]
 
-    R.batch_run(jobs(R.RFD_FP32_REFINE), workers=workers)   # first use: maps, reordered matrices
+    R.batch_run(jobs(R.RFD_FP32_AUTO), workers=workers)   # first use: maps, reordered matrices
     out = {}
-    for key, mode, w in (("fp32", R.RFD_FP32_REFINE, workers), ("fp32_1", R.RFD_FP32_REFINE, 1),
+    for key, mode, w in (("fp32", R.RFD_FP32_AUTO, workers), ("fp32_1", R.RFD_FP32_AUTO, 1),
                          ("fp64", R.RFD_FP64, workers)):
         js = jobs(mode)
         torch.cuda.synchronize()
@@ -380,7 +382,7 @@ def serve_leg(R, W, torch, prob2, gold2, prob3, lam3, nreq, workers):
         # interior basis sized with the slice: 1.5 k over the subdomains
         nev_b = max(20, int(math.ceil(1.5 * k / pr.p)) + 10)
         return R.Job(P, a, b, 8, Y0, SERVE_STEPS[rq["pencil"]], 0.5 * (a + b), nev_b, 6, k + 40,
-                     mode=R.RFD_FP32_REFINE, refine_tol=TARGET_TOL, vectors=True)
+                     mode=R.RFD_FP32_AUTO, refine_tol=TARGET_TOL, vectors=True)
 
     def check(rq, job):
         lam = spectra[rq["pencil"]][rq["i0"] - 1: rq["i0"] - 1 + rq["k"]]
@@ -574,7 +576,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="timed FP64 solves of the headline workload beside the FP32 ones")
-    ap.add_argument("--mode", default="both", choices=["fp32", "fp64", "both"])
+    ap.add_argument("--mode", default="both", choices=["fp32", "fp64", "fp32all", "both", "all"],
+                    help="fp32: FP32 factors + FP64 refinement where the cost model says they "
+                         "pay (RFD_FP32_AUTO); fp32all: every factor FP32 (RFD_FP32_REFINE); "
+                         "both: fp32 and fp64; all: the three")
     ap.add_argument("--c2-steps", type=int, default=3,
                     help="timed solves per mode of the 255x255 workload (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -613,10 +618,10 @@ def main():
     print(f"# workload {prob.name}: n={prob.n} p={prob.p} s={prob.s} m={prob.m} "
           f"steps={prob.steps} nev_b={prob.nev_b} psi={prob.psi} n_c={prob.n_c}",
           file=sys.stderr, flush=True)
-    modes = ["fp32", "fp64"] if a.mode == "both" else [a.mode]
+    modes = {"both": ["fp32", "fp64"], "all": ["fp32", "fp64", "fp32all"]}.get(a.mode, [a.mode])
     res = {}
     for mode in modes:
-        k = a.steps if (mode == "fp32" or a.mode == "fp64") else a.fp64_steps
+        k = a.steps if (mode == "fp32" or a.mode in ("fp64", "fp32all")) else a.fp64_steps
         res[mode] = run_mode(R, W, prob, mode, k, a.warmup, ref, torch, a.refine_tol,
                              account=True)
         r = res[mode]
@@ -631,8 +636,8 @@ def main():
     # timed steps), and of the complex GEMM on the matrix cores beside it
     f32 = "fp32" in res and head is res["fp32"]
     ks = head["kstats"]
-    # (summed time scaled from the sampled launches to all launches)
-    dom = max(ks, key=lambda k: ks[k][2] * ks[k][0] / max(ks[k][1], 1))
+    # (the accounting's estimate of the summed time of all launches)
+    dom = max(ks, key=lambda k: ks[k][2])
     roof = roofline_entry(dom, ks[dom], f32, head["steps"], prob.name)
     gname = R.GEMM_KEYS[(0 if f32 else 8) + 4]
     roof_mfma = roofline_entry(gname, ks.get(gname, (0, 0, 0.0, 0.0, 0.0)), f32, head["steps"],
@@ -642,6 +647,10 @@ def main():
         "value": hs["value"], "unit": "eigenpairs/s", "n_gpus": 1, "steps": head["steps"],
         "warmup": a.warmup, "ms_per_step": hs["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if f32 else "f64",
+        "precision": ("RFD_FP32_AUTO: FP32 factors refined in FP64 where the refinement costs "
+                      "less than the FP32 factorization saves (the shifted interior blocks), "
+                      "FP64 factors elsewhere (S at this size and column count)") if f32 else
+                     "RFD_FP64",
         "data": "synthetic",
         "config": {"workload": prob.name, "n": prob.n, "p": prob.p, "s": prob.s,
                    "interface_groups": "8 octants + central separator (11719 nodes)",
@@ -661,9 +670,12 @@ def main():
     if "fp64" in res and "fp32" in res:
         out["fp64"] = summary(res["fp64"], prob)
         out["fp32_over_fp64"] = out["value"] / max(out["fp64"]["value"], 1e-30)
+    if "fp32all" in res and head is not res["fp32all"]:
+        out["fp32all"] = summary(res["fp32all"], prob)
+        out["fp32all"]["precision"] = "RFD_FP32_REFINE: every factor FP32, refined in FP64"
     out["phases_ms"] = {m: np.round(res[m]["phases"][:12], 3).tolist() for m in res}
-    out["kernels"] = {m: {k: dict(launches=v[0], sampled=v[1],
-                                  ms_per_step=v[2] * v[0] / max(v[1], 1) / res[m]["steps"],
+    out["kernels"] = {m: {k: dict(launches=v[0], timed=v[1],
+                                  ms_per_step=v[2] / res[m]["steps"],
                                   tflops=v[3] / max(v[2], 1e-9) / 1e9,
                                   gbps=v[4] / max(v[2], 1e-9) / 1e6)
                           for k, v in res[m]["kstats"].items()} for m in res}

@@ -60,7 +60,7 @@ typedef enum {
 } rfd_status;
 
 enum { RFD_RULE_GAUSS = 0, RFD_RULE_MIDPOINT = 1, RFD_RULE_EXPLICIT = 2 };
-enum { RFD_FP64 = 0, RFD_FP32_REFINE = 1 };
+enum { RFD_FP64 = 0, RFD_FP32_REFINE = 1, RFD_FP32_AUTO = 2 };
 enum { RFD_INTERIOR_LU = 0, RFD_INTERIOR_SPECTRAL = 1 };
 
 /*
@@ -112,6 +112,15 @@ rfd_status rfd_set_interval_and_poles(rfd_pencil_t pencil, double alpha, double 
  * every shifted solve is refined in FP64 (FP64 residuals against the FP64
  * operators) until ||r||_F <= refine_tol ||b||_F, at most max_sweeps
  * corrections (refine_tol <= 0 or max_sweeps <= 0 select 1e-13 and 8).
+ * RFD_FP32_AUTO: FP32 factors with FP64 refinement where the refinement
+ * costs less than the FP32 factorization saves, FP64 factors elsewhere.  The
+ * interior blocks are always FP32 (their refinement residual is a sparse
+ * product).  S(zeta) is FP32 when sum N^3 > 12 c sum N^2 over its factored
+ * blocks (N: their sizes; c: the columns the filter will carry, m * steps
+ * for rfd_filter_interface, m * max_steps for rfd_filter_lanczos, m for
+ * rfd_filter_apply): each filtered column then costs about 16 N^2 FP64
+ * flops more (two residuals and two FP32 solves against one FP64 solve) and
+ * the FP32 LU saves about (4/3) N^3.
  * Orthonormalisation, the interior levels' residuals and Rayleigh-Ritz stay
  * FP64.  Errors: RFD_EINVAL for an unknown mode.  Invalidates the factors.
  */
@@ -392,9 +401,10 @@ rfd_status rfd_set_interface_groups(rfd_pencil_t pencil, int32_t ngroups, const 
  * C written, plus read when beta != 0; mat-vec: the lower triangle of the
  * trailing block and its vectors).  every = 0 turns it off.
  * rfd_kernel_stats synchronises the events and returns, for 32 keys (host
- * arrays of 32 doubles each), the number of launches, the number sampled,
- * and the summed milliseconds, flops and bytes of the sampled launches, then
- * clears the record.  Keys 0..15:
+ * arrays of 32 doubles each), the number of launches, the number timed, and
+ * the estimated milliseconds, flops and bytes of all launches (the launches
+ * timed for their size summed, the hashed sample of the others scaled by
+ * their count over the sample), then clears the record.  Keys 0..15:
  * the hand-written GEMM with key = 8*fp64 + 4*complex + 2*transA + transB;
  * key 16: the tridiagonalization mat-vec; keys 17..24: the large-tile FP64
  * GEMM that takes the large FP64 products, key = 17 + 4*complex + 2*transA +
@@ -427,7 +437,7 @@ typedef struct rfd_job {
   double alpha, beta;   /* interval, alpha < beta                                  */
   int32_t n_c;          /* poles in the upper half plane                           */
   int32_t rule;         /* RFD_RULE_GAUSS or RFD_RULE_MIDPOINT                     */
-  int32_t mode;         /* RFD_FP64 or RFD_FP32_REFINE                             */
+  int32_t mode;         /* RFD_FP64, RFD_FP32_REFINE or RFD_FP32_AUTO              */
   int32_t max_sweeps;   /* refinement sweeps (<= 0: default)                       */
   double refine_tol;    /* refinement tolerance (<= 0: default)                    */
   int32_t m, steps;     /* interface block width and block-Krylov steps            */

@@ -13,12 +13,12 @@ import os
 import numpy as np
 
 __all__ = [
-    "RfdError", "lib", "Pencil", "Job", "Server", "batch_run", "RFD_FP64", "RFD_FP32_REFINE",
+    "RfdError", "lib", "Pencil", "Job", "Server", "batch_run", "RFD_FP64", "RFD_FP32_REFINE", "RFD_FP32_AUTO",
     "RFD_RULE_GAUSS", "RFD_RULE_MIDPOINT", "RFD_RULE_EXPLICIT", "LIB_PATH",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfd.so")
-RFD_FP64, RFD_FP32_REFINE = 0, 1
+RFD_FP64, RFD_FP32_REFINE, RFD_FP32_AUTO = 0, 1, 2
 RFD_RULE_GAUSS, RFD_RULE_MIDPOINT, RFD_RULE_EXPLICIT = 0, 1, 2
 RFD_INTERIOR_LU, RFD_INTERIOR_SPECTRAL = 0, 1
 STATUS = {0: "RFD_OK", 1: "RFD_EINVAL", 2: "RFD_ENOMEM", 3: "RFD_EBREAKDOWN",
@@ -273,8 +273,9 @@ def rfd_kernel_accounting(every):
 
 
 def rfd_kernel_stats():
-    """{kernel name: (launches, sampled, ms, flops, bytes)} since the last
-    call; ms, flops and bytes are summed over the sampled launches."""
+    """{kernel name: (launches, timed, ms, flops, bytes)} since the last
+    call; ms, flops and bytes are estimates over all launches (the launches
+    timed for their size summed, a hashed sample of the rest scaled up)."""
     L, S, T, F, B = (np.zeros(32) for _ in range(5))
     _check(lib().rfd_kernel_stats(L.ctypes.data, S.ctypes.data, T.ctypes.data, F.ctypes.data,
                                   B.ctypes.data))

@@ -113,7 +113,8 @@ rfd_status rfd_set_precision(rfd_pencil_t pencil, int32_t mode, double refine_to
                              int32_t max_sweeps) {
   return (rfd_status)capi_guard([&] {
     auto* P = need(pencil);
-    if (mode != RFD_FP64 && mode != RFD_FP32_REFINE) throw Error(ST_EINVAL, "unknown precision mode");
+    if (mode != RFD_FP64 && mode != RFD_FP32_REFINE && mode != RFD_FP32_AUTO)
+      throw Error(ST_EINVAL, "unknown precision mode");
     P->mode = mode;
     P->tol = refine_tol > 0 ? refine_tol : 1e-13;
     P->sweeps = max_sweeps > 0 ? max_sweeps : 8;

@@ -33,9 +33,12 @@ KernelAccount::Scope::Scope(hipStream_t s, int key, double flops, double bytes) 
   h ^= h >> 31;
   h *= 0xBF58476D1CE4E5B9ull;
   h ^= h >> 29;
-  if (h % (uint64_t)k.every != 0 && flops < KA_ALWAYS_FLOPS) return;
+  const bool always = flops >= KA_ALWAYS_FLOPS;
+  if (!always) ++k.count_small[key];
+  if (h % (uint64_t)k.every != 0 && !always) return;
   Rec r;
   r.key = key;
+  r.always = always;
   r.flops = flops;
   r.bytes = bytes;
   if (hipEventCreate(&r.a) != hipSuccess) return;
@@ -59,24 +62,40 @@ void KernelAccount::Scope::mark_stop() {
 void KernelAccount::collect(double* launches, double* sampled, double* ms, double* flops,
                             double* bytes, int nkeys) {
   std::lock_guard<std::mutex> g(mu);
-  for (int k = 0; k < nkeys; ++k) {
-    launches[k] = (k < KA_KEYS) ? (double)count[k] : 0.0;
-    sampled[k] = ms[k] = flops[k] = bytes[k] = 0;
+  // [0]: always-timed launches, [1]: hashed sample of the others
+  std::vector<double> n[2], t[2], f[2], b[2];
+  for (int q = 0; q < 2; ++q) {
+    n[q].assign(KA_KEYS, 0.0);
+    t[q].assign(KA_KEYS, 0.0);
+    f[q].assign(KA_KEYS, 0.0);
+    b[q].assign(KA_KEYS, 0.0);
   }
   for (auto& r : recs) {
-    float t = 0;
-    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess &&
-        r.key < nkeys) {
-      sampled[r.key] += 1;
-      ms[r.key] += t;
-      flops[r.key] += r.flops;
-      bytes[r.key] += r.bytes;
+    float el = 0;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&el, r.a, r.b) == hipSuccess &&
+        r.key < KA_KEYS) {
+      const int q = r.always ? 0 : 1;
+      n[q][r.key] += 1;
+      t[q][r.key] += el;
+      f[q][r.key] += r.flops;
+      b[q][r.key] += r.bytes;
     }
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
+  for (int k = 0; k < nkeys; ++k) {
+    launches[k] = sampled[k] = ms[k] = flops[k] = bytes[k] = 0;
+    if (k >= KA_KEYS) continue;
+    const double sc = n[1][k] > 0 ? (double)count_small[k] / n[1][k] : 0.0;
+    launches[k] = (double)count[k];
+    sampled[k] = n[0][k] + n[1][k];
+    ms[k] = t[0][k] + sc * t[1][k];
+    flops[k] = f[0][k] + sc * f[1][k];
+    bytes[k] = b[0][k] + sc * b[1][k];
+  }
   recs.clear();
   for (auto& c : count) c = 0;
+  for (auto& c : count_small) c = 0;
 }
 
 // ---------------------------------------------------------------------------

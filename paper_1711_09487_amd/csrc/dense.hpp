@@ -27,14 +27,19 @@ constexpr double KA_ALWAYS_FLOPS = 1e11;  // launches this large are always samp
 struct KernelAccount {
   struct Rec {
     int key;
+    bool always;  // timed for its size (not picked by the hash)
     double flops, bytes;
     hipEvent_t a, b;
   };
   int every = 0;  // 0: off
   std::mutex mu;
   std::vector<Rec> recs;
-  int64_t count[KA_KEYS] = {};
+  int64_t count[KA_KEYS] = {};        // launches
+  int64_t count_small[KA_KEYS] = {};  // launches below KA_ALWAYS_FLOPS
   static KernelAccount& get();
+  // Per key: launches, launches timed, and the estimated milliseconds, flops
+  // and bytes of all launches (the always-timed ones summed, the hashed
+  // sample of the others scaled by their launch count over the sample).
   void collect(double* launches, double* sampled, double* ms, double* flops, double* bytes,
                int nkeys);
   // Decides whether this launch is sampled and holds its events.

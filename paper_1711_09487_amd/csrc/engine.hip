@@ -173,10 +173,12 @@ void Engine::set_precision(int mode, double tol, int sweeps) {
 
 int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, int psi) const {
   const EngineImpl& e = *d_;
-  const bool f32 = mode == 1;
+  const bool b32 = mode != 0;                                                   // interior
+  const bool f32 = e.s_precision(mode, std::min<int64_t>(e.s, (int64_t)steps * m)) == 1;  // S
   const int64_t es = f32 ? 4 : 8, D = e.D, SP = e.SP, SJ = e.SJ, p = e.p, n = e.n;
-  const int64_t per_pole = p * (D * D * 2 * es + (int64_t)NB * 2 * D * 2 * es +
-                                D * SJ * (f32 ? 16 + 16 + 8 + 8 : 16));
+  const int64_t bs = b32 ? 4 : 8;
+  const int64_t per_pole = p * (D * D * 2 * bs + (int64_t)NB * 2 * D * 2 * bs +
+                                D * SJ * (b32 ? 16 + 16 + 8 + 8 : 16));
   const int64_t chunk = std::min<int64_t>(n_c, std::max<int64_t>(1, (int64_t(96) << 30) / per_pole));
   const int64_t MP = round_up(std::max(m, 1), NB);
   const int64_t mu = std::min<int64_t>(e.s, (int64_t)steps * m);
@@ -185,7 +187,7 @@ int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, i
   const int64_t k = p * VB + (int64_t)psi * mu;
   int64_t b = chunk * per_pole;                                   // shifted blocks, Schur solves
   if (e.tree.L > 0) {
-    b += n_c * e.tree_pole_bytes(MP, mode);                        // two-level S, right-hand sides
+    b += n_c * e.tree_pole_bytes(MP, f32 ? 1 : 0);                 // two-level S, right-hand sides
   } else {
     b += SP * SP * n_c * 16 + (f32 ? SP * SP * n_c * 8 : 0);      // S (FP64, FP32 copy)
     if (f32 && SP * SP * n_c * 8 <= EngineImpl::GAUSS_MAX_BYTES)
@@ -429,11 +431,32 @@ void EngineImpl::check_flags(hipStream_t s, const char* what, DevBuf* fb) {
   }
 }
 
+// Precision of S's factors (see rfd_set_precision): FP32 pays when the LU
+// work it saves, (4/3) sum N^3 FP64-equivalent flops over the factored
+// blocks, exceeds what the refinement adds to c filtered columns, about
+// 16 sum N^2 per column (two FP64 residuals and two FP32 solves against one
+// FP64 solve).
+int EngineImpl::s_precision(int md, int64_t c) const {
+  if (md != 2) return md == 1 ? 1 : 0;
+  double n3 = 0.0, n2 = 0.0;
+  auto add = [&](double N, double count) {
+    n3 += count * N * N * N;
+    n2 += count * N * N;
+  };
+  if (tree.L > 0) {
+    add((double)tree.NGP, (double)tree.L);
+    add((double)tree.TP, 1.0);
+  } else {
+    add((double)SP, 1.0);
+  }
+  return n3 > 12.0 * (double)std::max<int64_t>(c, 1) * n2 ? 1 : 0;
+}
+
 // Poles processed together for the interior part: as many as fit the budget.
 int EngineImpl::pole_chunk() const {
   const int64_t items_bytes_per_pole =
-      (int64_t)p * (D * D * (mode == 1 ? 8 : 16) + NB * 2 * D * (mode == 1 ? 8 : 16) +
-                    D * SJ * (mode == 1 ? 16 + 16 + 8 + 8 : 16));
+      (int64_t)p * (D * D * (mode != 0 ? 8 : 16) + NB * 2 * D * (mode != 0 ? 8 : 16) +
+                    D * SJ * (mode != 0 ? 16 + 16 + 8 + 8 : 16));
   const int64_t budget = int64_t(48) << 30;
   int c = (int)std::max<int64_t>(1, budget / std::max<int64_t>(items_bytes_per_pole, 1));
   return std::min(c, poles.n_c);
@@ -491,7 +514,8 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
   }
   const int64_t kk = D * D * (int64_t)items_max, ki = (int64_t)NB * 2 * D * items_max,
                 xs = D * SJ * (int64_t)items_max;
-  const bool fp32 = (mode == 1);
+  const bool fp32 = (mode != 0);            // the interior blocks
+  s_mode = s_precision(mode, cols_hint);    // S
   const bool spectral = interior_solver == 1;
   if (spectral) {
     spectral_decompose(st);
@@ -583,15 +607,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
   timer.begin(st, 3);
   if (two_level) {
     tree_factor(st, nc);
-    if (!keep_interior && K32.bytes + K64.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
-      K32.release();
-      Kinv32.release();
-      X32.release();
-      R64.release();
-      K64.release();
-      Kinv64.release();
-    }
-  } else if (fp32) {
+  } else if (s_mode == 1) {
     S32.alloc(2 * SP * SP * (int64_t)nc * sizeof(float));
     Sinv32.alloc(2 * (int64_t)NB * 2 * SP * nc * sizeof(float));
     DMat<float> S3{S32.as<float>(), S32.as<float>() + SP * SP * nc, SP, SP * SP};
@@ -611,24 +627,22 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
     }
     lu_nopiv<float>(st, S3, SP, nc, Si, flags.as<unsigned>(), 1e-30);
     wide_inverses<float>(st, S3, Si, nc);
-    // the interior factors are no longer needed; large ones are released
-    // (a release synchronises the device, small ones stay for the next solve)
-    if (!keep_interior && K32.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
-      K32.release();
-      Kinv32.release();
-      X32.release();
-      R64.release();
-    }
   } else {
     Sinv64.alloc(2 * (int64_t)NB * 2 * SP * nc * sizeof(double));
     DMat<double> Si{Sinv64.as<double>(), Sinv64.as<double>() + (int64_t)NB * 2 * SP * nc, NB,
                     (int64_t)NB * 2 * SP};
     lu_nopiv<double>(st, S, SP, nc, Si, flags.as<unsigned>(), 1e-300);
     wide_inverses<double>(st, S, Si, nc);
-    if (!keep_interior && K64.bytes > (size_t(16) << 30)) {
-      K64.release();
-      Kinv64.release();
-    }
+  }
+  // the interior factors are no longer needed; large ones are released (a
+  // release synchronises the device, small ones stay for the next solve)
+  if (!keep_interior && K32.bytes + K64.bytes + X32.bytes + R64.bytes > (size_t(16) << 30)) {
+    K32.release();
+    Kinv32.release();
+    X32.release();
+    R64.release();
+    K64.release();
+    Kinv64.release();
   }
   if (X64.bytes > (size_t(8) << 30)) X64.release();
   timer.end(st);
@@ -645,15 +659,16 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
 // factors of the poles processed together.
 int EngineImpl::pole_window(int m) const {
   const int nc = poles.n_c;
-  const bool f32 = mode == 1;
+  const bool f32 = s_precision(mode, cols_hint) == 1;  // S
+  const bool b32 = mode != 0;                           // the interior blocks
   const int64_t MP = round_up(std::max(m, 1), NB);
-  const int64_t per_pole = tree.L > 0 ? tree_pole_bytes(MP, mode)
+  const int64_t per_pole = tree.L > 0 ? tree_pole_bytes(MP, f32 ? 1 : 0)
                                        : 2 * SP * SP * (f32 ? 8 + 4 : 8) +
                                              2 * (int64_t)NB * 2 * SP * (f32 ? 4 : 8) +
                                              2 * SP * MP * (f32 ? 8 + 8 + 4 : 8);
   const int64_t per_chunk_pole =
-      (int64_t)p * (D * D * (f32 ? 8 : 16) + (int64_t)NB * 2 * D * (f32 ? 8 : 16) +
-                    D * SJ * (f32 ? 48 : 16));
+      (int64_t)p * (D * D * (b32 ? 8 : 16) + (int64_t)NB * 2 * D * (b32 ? 8 : 16) +
+                    D * SJ * (b32 ? 48 : 16));
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
     (void)hipGetLastError();
@@ -702,7 +717,7 @@ void EngineImpl::run_filter(hipStream_t st, const double* Y, int64_t ldy, int m,
 }
 
 // W = 2 Re sum_l omega_l S(zeta_l)^{-1} Y  (eq. (3.5)); Y real s x m (ld ldy),
-// W real (ld ldw).  FP32 mode refines every pole's solve against S_64.
+// W real (ld ldw).  With FP32 factors every pole's solve is refined against S_64.
 void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int m, double* Wout,
                               int64_t ldw, bool add) {
   if (tree.L > 0) {
@@ -717,7 +732,7 @@ void EngineImpl::apply_filter(hipStream_t st, const double* Y, int64_t ldy, int 
   DMat<double> Ycm{Yc.as<double>(), Yc.as<double>() + ys, SP, SP * MP};
   DMat<double> S{S64.as<double>(), S64.as<double>() + SP * SP * nc, SP, SP * SP};
   timer.begin(st, 4);
-  if (mode == 1) {
+  if (s_mode == 1) {
     Xf.alloc(2 * ys * sizeof(double));
     Rf32.alloc(2 * ys * sizeof(float));
     DMat<double> X{Xf.as<double>(), Xf.as<double>() + ys, SP, SP * MP};
@@ -794,6 +809,7 @@ void Engine::filter_interface(hipStream_t st, int m, const double* Y0, int steps
   if (!e.poles.set) throw Error(ST_ESTATE, "poles not set");
   const int64_t s = e.s;
   const int64_t cap = std::min<int64_t>(ldq_cols, std::min<int64_t>(s, (int64_t)steps * m));
+  e.cols_hint = std::min<int64_t>(s, (int64_t)steps * m);
   e.W.alloc(sizeof(double) * s * (int64_t)m);
   double* W = e.W.as<double>();
   int total = 0, prev0 = 0, prevw = 0;
@@ -836,6 +852,7 @@ void Engine::filter_lanczos(hipStream_t st, int m, const double* Y0, double tol,
   if (!e.poles.set) throw Error(ST_ESTATE, "poles not set");
   const int64_t s = e.s;
   const int64_t cap = std::min<int64_t>(ldq_cols, s);
+  e.cols_hint = std::min<int64_t>(s, (int64_t)max_steps * m);
   e.W.alloc(sizeof(double) * s * (int64_t)m);
   double* W = e.W.as<double>();
   RFD_HIP(hipMemcpyAsync(W, Y0, sizeof(double) * s * m, hipMemcpyDeviceToDevice, st));
@@ -977,6 +994,7 @@ int64_t Engine::inertia(hipStream_t st, double tau) {
 void Engine::filter_apply(hipStream_t st, int m, const double* Y, double* W) {
   EngineImpl& e = *d_;
   if (!e.poles.set) throw Error(ST_ESTATE, "poles not set");
+  e.cols_hint = m;
   e.run_filter(st, Y, e.s, m, W, e.s);
 }
 

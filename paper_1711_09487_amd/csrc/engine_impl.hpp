@@ -56,7 +56,11 @@ struct EngineImpl {
   // poles and precision
   Poles poles;
   DevBuf zeta, omega;
-  int mode = 0;
+  int mode = 0;           // 0: FP64, 1: FP32 factors + FP64 refinement, 2: FP32 where it pays
+  int s_mode = 0;         // precision of S's factors in the current factorization (0 / 1)
+  int64_t cols_hint = 0;  // columns the coming filter applications carry in all
+  // 1 when the factors of S are FP32 for precision mode md and c columns
+  int s_precision(int md, int64_t c) const;
   double tol = 1e-13;
   int sweeps = 8;
   bool factored = false;

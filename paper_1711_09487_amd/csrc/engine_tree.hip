@@ -51,7 +51,7 @@ int64_t EngineImpl::tree_pole_bytes(int64_t MP, int md) const {
 
 // Block LU of the window's S(zeta_l): each S_gg, X_g = S_gg^{-1} S_gT, the
 // top complement S_TT - sum_g S_gT^T X_g, and its LU (with wide leaves for
-// the solves).  FP32 mode factors FP32 copies and keeps the FP64 blocks.
+// the solves).  FP32 factors (s_mode 1) are FP32 copies; the FP64 blocks stay.
 void EngineImpl::tree_factor(hipStream_t st, int nc) {
   const TreeDev& tr = tree;
   const int64_t G = tr.NGP, TG = tr.TGP, TP = tr.TP;
@@ -66,7 +66,7 @@ void EngineImpl::tree_factor(hipStream_t st, int nc) {
     DMat<T> wk{Twork.as<T>(), Twork.as<T>() + mw, TLW / 2, 0};
     merge_inverses<T>(st, C, Ci, TP, nc, w2, TLW, wk);
   };
-  if (mode == 1) {
+  if (s_mode == 1) {
     DMat<double> Sgg{Tgg64.as<double>(), Tgg64.as<double>() + G * G * ni, G, G * G};
     DMat<double> SgT{TgT64.as<double>(), TgT64.as<double>() + G * TG * ni, G, G * TG};
     DMat<double> Stt{Ttt64.as<double>(), Ttt64.as<double>() + TP * TP * nc, TP, TP * TP};
@@ -148,7 +148,7 @@ void EngineImpl::tree_solve(hipStream_t st, DMat<T> RG, DMat<T> RT, int64_t MP, 
 }
 
 // W (+)= 2 Re sum_l omega_l S(zeta_l)^{-1} Y over the window's poles.  FP32
-// mode: FP32 solves corrected by FP64 residuals R = Y - S X formed from the
+// factors: FP32 solves corrected by FP64 residuals R = Y - S X formed from the
 // FP64 blocks (R_g = Y_g - S_gg X_g - S_gT X_T[T_g],
 // R_T = Y_T - S_TT X_T - sum_g S_gT^T X_g).
 void EngineImpl::tree_apply(hipStream_t st, const double* Y, int64_t ldy, int m, double* Wout,
@@ -163,7 +163,7 @@ void EngineImpl::tree_apply(hipStream_t st, const double* Y, int64_t ldy, int m,
   TXTg.alloc(std::max<size_t>(TXTg.bytes, (size_t)(2 * TG * MP * ni) * sizeof(double)));
   DMat<double> RG = planes<double>(TRG, G, MP, ni), RT = planes<double>(TRT, TP, MP, nc);
   timer.begin(st, 4);
-  if (mode == 1) {
+  if (s_mode == 1) {
     DMat<double> XG = planes<double>(TXG, G, MP, ni), XT = planes<double>(TXT, TP, MP, nc);
     DMat<float> RG3 = planes<float>(TRG32, G, MP, ni), RT3 = planes<float>(TRT32, TP, MP, nc);
     DMat<double> Sgg{Tgg64.as<double>(), Tgg64.as<double>() + G * G * ni, G, G * G};

@@ -381,6 +381,53 @@ def test_mode_switch_refactors():
     assert np.max(np.abs(W0 - W1)) < 1e-11 * np.max(np.abs(W0))
 
 
+def test_per_factor_precision_mode():
+    """RFD_FP32_AUTO takes FP32 factors refined in FP64 for the interior
+    blocks always, and for S(zeta) only when sum N^3 > 12 c sum N^2 (c: the
+    columns the filter will carry).  On a dense S of 384 (s = 324 padded):
+      * filter_apply of 8 columns (384 > 96) factors S in FP32: the filter's
+        refinement runs, and the block equals the FP32 mode's bit for bit;
+      * two block steps of 40 columns (384 < 960) factor S in FP64: no filter
+        refinement, while the interior blocks keep theirs;
+    both against the oracle: F Y0 (relative 1e-11), Ritz values (1e-10),
+    residuals (<= 10x the oracle's)."""
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    prob, ro = _prob("p9_wide_leaves")
+    assert (prob.s, prob.m, prob.steps) == (324, 40, 2)
+    dd = O.DD(prob.A, prob.M, prob.part)
+    z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
+    ref8 = O.filter_apply(O.factor_poles(dd, z), w, prob.Y0[:, :8])
+    out = {}
+    for mode in (R.RFD_FP32_REFINE, R.RFD_FP32_AUTO):
+        P = _pencil(prob, mode)
+        try:
+            P.set_timing(True)
+            W8 = P.filter_apply(_dev_block(torch, prob.Y0[:, :8])).cpu().numpy().T
+            out[mode] = (W8, P.phase_times()[12:14])
+        finally:
+            P.close()
+    W8, sweeps = out[R.RFD_FP32_AUTO]
+    assert np.array_equal(W8, out[R.RFD_FP32_REFINE][0])
+    assert sweeps[1] >= 1
+    assert np.max(np.abs(W8 - ref8)) / np.max(np.abs(ref8)) < 1e-11
+    P = _pencil(prob, R.RFD_FP32_AUTO)
+    try:
+        P.set_timing(True)
+        P.filter_interface(_dev_block(torch, prob.Y0), prob.steps)
+        sweeps = P.phase_times()[12:14]
+        P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+        ev, _, res = P.rayleigh_ritz(max(prob.nev + 20, 64), vectors=False)
+        torch.cuda.synchronize()
+        th, res = ev.cpu().numpy(), res.cpu().numpy()
+    finally:
+        P.close()
+    assert sweeps[0] >= 1 and sweeps[1] == 0
+    assert th.size == ro.theta.size == prob.nev
+    assert np.max(np.abs(th - ro.theta) / np.abs(ro.theta)) <= EIG_TOL
+    assert np.all(res <= 10 * ro.resid + 1e-12)
+
+
 COUPLED = {
     # nine uneven subdomains, a two-tile interface, one block step
     "p9_uneven": (lambda: W.tiny(N=27, P=3, nev=6, n_c=4, m=16, steps=1, nev_b=6, psi=2,
