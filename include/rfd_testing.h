@@ -26,6 +26,16 @@ int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K, do
                   void* b_im, int64_t ldb, int64_t sb, void* c_re, void* c_im, int64_t ldc,
                   int64_t sc, int batch, void* stream);
 
+/* rfd_test_gemm for real FP64 operands, neither transposed, with every B_b
+ * upper triangular (B_b[k, j] = 0 for k > j; the entries below the diagonal
+ * are not read by the large-tile path, so they must be zero): the product
+ * Q = B U^{-1} D^{1/2} of the Cholesky QR that builds the M-orthonormal basis
+ * of range(Z) (Alg. 5.1 step 7), whose large instances skip the zero part of
+ * K. */
+int rfd_test_gemm_triu_b(int64_t M, int64_t N, int64_t K, double alpha, double beta, void* a,
+                         int64_t lda, int64_t sa, void* b, int64_t ldb, int64_t sb, void* c,
+                         int64_t ldc, int64_t sc, int batch, void* stream);
+
 /* Largest |U_j^T U_j - I| over the subdomain eigenvector blocks of the last
  * spectral decomposition (U_j = M_Bj^{1/2} V_j, after its orthonormalising
  * steps), or 0 when the pencil has none: the departure from M_Bj-orthonormal

@@ -109,6 +109,8 @@ def lib():
                               I64, P, P, I64, I64, I32, P],
             "rfd_test_gemm_static": [I32, I32, I32, I64, I64, I64, F64, F64, P, P, I64, I64, P, P,
                                      I64, I64, P, P, I64, I64, I32, P],
+            "rfd_test_gemm_triu_b": [I64, I64, I64, F64, F64, P, I64, I64, P, I64, I64, P, I64,
+                                     I64, I32, P],
             "rfd_test_lu": [I32, I32, I64, I32, P, P, I64, I64, P, P, I64, I64, I64,
                             C.POINTER(C.c_uint32), P],
             "rfd_test_syevx": [I64, I32, P, I32, I32, P, P, P],

@@ -64,6 +64,11 @@ void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T al
 // As gemm for square N x N results, computing only the output tiles that
 // meet the lower triangle (i >= j); entries above the diagonal are left
 // undefined (the caller mirrors the lower triangle of a symmetric result).
+// As gemm (real FP64, neither operand transposed) for an upper triangular B
+// (B[k, j] = 0 for k > j): the large products skip the zero part of K.
+void gemm_triu_b(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, DMat<double> A,
+                 DMat<double> B, double beta, DMat<double> C, int batch);
+
 // Drops the split-K workspace kept for stream s (call
 // before destroying a stream that ran products).
 void release_stream_resources(hipStream_t s);

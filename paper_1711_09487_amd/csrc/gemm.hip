@@ -7,11 +7,12 @@
 // FP64 v_mfma_f64_16x16x4f64.  The operands enter the MFMA swapped (the B
 // tile as the row operand) so that the accumulator rows run down the columns
 // of the column-major C and the epilogue stores are coalesced.  A complex
-// FP64 product is four real products into two accumulators.  A complex FP32
-// product takes three (Gauss): P1 = Ar Br, P2 = Ai Bi and
+// product takes three real products (Gauss): P1 = Ar Br, P2 = Ai Bi and
 // P3 = (Ar + Ai)(Br + Bi), then Re = P1 - P2 and Im = P3 - P1 - P2, a quarter
-// fewer matrix-core cycles; its FP32 rounding is the factorizations', which
-// the FP64 refinement corrects.
+// fewer matrix-core cycles (in FP32 its rounding is the factorizations',
+// which the FP64 refinement corrects; in FP64 the imaginary part's error
+// bound grows by at most a factor of about two).  Complex FP64 products of
+// the 64 x 64 k_gemm tile keep four real products into two accumulators.
 //
 // Operand lane layouts: 32x32x2 -- lane l holds X[l%32][l/32] of the row
 // operand and Y[l/32][l%32] of the column operand; D register r of lane l is
@@ -312,9 +313,10 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
 
 // Large FP64 products: real on 64 x 128 tiles (each of the 4 waves, 2 x 2,
 // computes 32 x 64 of v_mfma_f64_16x16x4f64 blocks), complex on 64 x 64
-// tiles (four real products per block into a real and an imaginary
-// accumulator); either way twice the matrix-core work per K slab of the
-// real 64 x 64 tile, with two waves per SIMD.  Loads are scalar 8-byte loads
+// tiles in Gauss's form (three real products per block: P1 = Ar Br, P2 =
+// Ai Bi, P3 = (Ar + Ai)(Br + Bi), the operand sums formed from the LDS
+// reads; Re = P1 - P2 and Im = P3 - P1 - P2 in the epilogue); two waves per
+// SIMD.  Loads are scalar 8-byte loads
 // (no alignment condition: the long operands of the solve have odd leading
 // dimensions) at a block-uniform base per K slab plus a per-thread 32-bit
 // offset fixed for the whole loop, from row and column indices clamped into
@@ -323,7 +325,8 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
 // and K indices beyond the range (last slab only) read as 0.  Consecutive
 // lanes read consecutive addresses of the contiguous dimension.  alpha
 // (real) scales op(A) as it is staged and the accumulators start from
-// beta C, so the epilogue stores them unchanged.
+// beta C (in Gauss's split for complex products), so the epilogue only
+// stores (and, complex, combines) them.
 template <bool CPLX, bool TA, bool TB, int BM, int BN>
 __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
                                                   double beta, DMat<double> A, DMat<double> B,
@@ -337,12 +340,13 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
 
   const uint3 blk = xcd_block();
   const int64_t m0 = (int64_t)blk.x * BM, n0 = (int64_t)blk.y * BN;
-  if (tri && n0 >= m0 + BM) return;
+  if (tri == 1 && n0 >= m0 + BM) return;
   const int b = (int)blk.z;
   A = A.item(b);
   B = B.item(b);
   C = C.item(b);
-  const int64_t ke = K;
+  // tri == 2: op(B) upper triangular, so the tile's columns need k < n0 + BN only
+  const int64_t ke = (tri == 2 && n0 + BN < K) ? n0 + BN : K;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
 
@@ -429,19 +433,26 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
 
   const int64_t il = m0 + wm + (lane & 15), jl = n0 + wn + (lane >> 4);
   const bool use_c = beta != 0.0;
-  doublex4 acc[NP][XM][XN];
+  // real: acc[0] = C.  complex: acc[0] = P1, acc[1] = P2, acc[2] = P3,
+  // started at beta Re C, 0 and beta (Re C + Im C)
+  constexpr int NA = CPLX ? 3 : 1;
+  doublex4 acc[NA][XM][XN];
 #pragma unroll
-  for (int p = 0; p < NP; ++p)
+  for (int x = 0; x < XM; ++x)
 #pragma unroll
-    for (int x = 0; x < XM; ++x)
+    for (int y = 0; y < XN; ++y)
 #pragma unroll
-      for (int y = 0; y < XN; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = il + 16 * x, j = jl + 16 * y + 4 * r;
-          const double* cp = p ? C.im : C.re;
-          acc[p][x][y][r] = (use_c && i < M && j < N) ? beta * cp[i + j * C.ld] : 0.0;
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = il + 16 * x, j = jl + 16 * y + 4 * r;
+        const bool in = use_c && i < M && j < N;
+        const double cr = in ? beta * C.re[i + j * C.ld] : 0.0;
+        acc[0][x][y][r] = cr;
+        if constexpr (CPLX) {
+          const double ci = in ? beta * C.im[i + j * C.ld] : 0.0;
+          acc[1][x][y][r] = 0.0;
+          acc[2][x][y][r] = cr + ci;
         }
+      }
 
   gload(0);
   lstore(0);
@@ -467,9 +478,9 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
         for (int y = 0; y < XN; ++y) {
           acc[0][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[0][y], ar[0][x], acc[0][x][y], 0, 0, 0);
           if constexpr (CPLX) {
-            acc[0][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-br[1][y], ar[1][x], acc[0][x][y], 0, 0, 0);
-            acc[1][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[0][y], ar[1][x], acc[1][x][y], 0, 0, 0);
-            acc[1][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[1][y], ar[0][x], acc[1][x][y], 0, 0, 0);
+            acc[1][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[1][y], ar[1][x], acc[1][x][y], 0, 0, 0);
+            acc[2][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(br[0][y] + br[1][y], ar[0][x] + ar[1][x],
+                                                                acc[2][x][y], 0, 0, 0);
           }
         }
     }
@@ -480,17 +491,22 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
   }
 
 #pragma unroll
-  for (int p = 0; p < NP; ++p)
+  for (int x = 0; x < XM; ++x)
 #pragma unroll
-    for (int x = 0; x < XM; ++x)
+    for (int y = 0; y < XN; ++y)
 #pragma unroll
-      for (int y = 0; y < XN; ++y)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = il + 16 * x, j = jl + 16 * y + 4 * r;
-          double* cp = p ? C.im : C.re;
-          if (i < M && j < N) cp[i + j * C.ld] = acc[p][x][y][r];
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = il + 16 * x, j = jl + 16 * y + 4 * r;
+        if (i < M && j < N) {
+          if constexpr (CPLX) {
+            const double p1 = acc[0][x][y][r], p2 = acc[1][x][y][r], p3 = acc[2][x][y][r];
+            C.re[i + j * C.ld] = p1 - p2;
+            C.im[i + j * C.ld] = p3 - p1 - p2;
+          } else {
+            C.re[i + j * C.ld] = acc[0][x][y][r];
+          }
         }
+      }
 }
 
 // C_b = sum over splits of the partial tiles (alpha applied) + beta C_b.
@@ -613,10 +629,13 @@ static bool aligned16(const DMat<T>& X, int vw) {
 // fixed_part: caller-provided memory of fixed_bytes for the split-K partial
 // tiles (the split count is lowered until they fit; no allocation and no
 // kernel accounting), or null for the per-stream workspace.
+// triub: op(B) is upper triangular (zero below its diagonal); the large-tile
+// FP64 kernel then skips the zero K range of each tile column (other paths
+// multiply the zeros).
 template <typename T>
 static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha,
                       DMat<T> A, DMat<T> B, T beta, DMat<T> C, int batch, int tri,
-                      T* fixed_part = nullptr, size_t fixed_bytes = 0) {
+                      T* fixed_part = nullptr, size_t fixed_bytes = 0, bool triub = false) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   const bool cplx = C.cplx();
   const int NP = cplx ? 2 : 1;
@@ -683,17 +702,22 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
           span_a < (int64_t(1) << 31) && span_b < (int64_t(1) << 31)) {
         const int key = KA_DGEMM + (cplx ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
         const double outs = tri ? 0.5 * (double)N * (double)(N + 1) : (double)M * (double)N;
-        const double flops = (cplx ? 8.0 : 2.0) * outs * (double)K * batch;
+        // (with a triangular op(B), column j takes min(j + 1, K) terms)
+        const double kavg = triub ? (double)(std::min(N, K) * (std::min(N, K) + 1) / 2 +
+                                             std::max<int64_t>(N - K, 0) * K) / (double)N
+                                  : (double)K;
+        const double flops = (cplx ? 8.0 : 2.0) * outs * kavg * batch;
         const double bytes = (cplx ? 2.0 : 1.0) * 8.0 *
                              ((double)M * K + (double)K * N + (beta != T(0) ? 2.0 : 1.0) * outs) *
                              batch;
         KernelAccount::Scope acct(s, fixed_part ? -1 : key, flops, bytes);
         dim3 g((unsigned)g64, (unsigned)nt, (unsigned)batch);
+        const int dtri = triub ? 2 : (tri ? 1 : 0);
         if (cplx)
-          launch_d<true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, tri, acct.start(),
+          launch_d<true, 64, 64>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, dtri, acct.start(),
                                  acct.stop());
         else
-          launch_d<false, 64, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, tri,
+          launch_d<false, 64, 128>(s, ta, tb, g, M, N, K, alpha, beta, A, B, C, dtri,
                                    acct.start(), acct.stop());
         RFD_CHECK_LAUNCH();
         return;
@@ -766,6 +790,12 @@ template <typename T>
 void gemm_lower(hipStream_t s, bool ta, bool tb, int64_t N, int64_t K, T alpha, DMat<T> A,
                 DMat<T> B, T beta, DMat<T> C, int batch) {
   gemm_impl<T>(s, ta, tb, N, N, K, alpha, A, B, beta, C, batch, 1);
+}
+
+void gemm_triu_b(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, DMat<double> A,
+                 DMat<double> B, double beta, DMat<double> C, int batch) {
+  if (C.cplx()) throw Error(ST_EINVAL, "gemm_triu_b: real operands only");
+  gemm_impl<double>(s, false, false, M, N, K, alpha, A, B, beta, C, batch, 0, nullptr, 0, true);
 }
 
 // ---------------------------------------------------------------------------

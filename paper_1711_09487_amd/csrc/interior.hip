@@ -1187,12 +1187,19 @@ int EngineImpl::gram_orth(hipStream_t st, const double* B, int ncol, double* MB,
     if (!dh[c]) kept.push_back(c);
   const int r = (int)kept.size();
   if (r == 0) return 0;
-  kept.push_back(r);  // device copy of the count follows the list
-  RFD_HIP(hipMemcpyAsync(keep, kept.data(), sizeof(int) * (r + 1), hipMemcpyHostToDevice, st));
-  k_gather_cols<<<dim3(grid1(np), r), 256, 0, st>>>(Ui, np, Tk, np, np, keep, keep + r);
-  RFD_CHECK_LAUNCH();
-  DMat<double> Tm{Tk, nullptr, np, 0}, Om{Out, nullptr, n, 0};
-  gemm<double>(st, false, false, n, r, ncol, 1.0, Bm, Tm, 0.0, Om, 1);
+  // Q = B U^{-1} D^{1/2} with U^{-1} D^{1/2} upper triangular (its dropped
+  // columns zero): the product skips the zero half of K, straight into Out
+  // when every column is kept, else into MB and the kept columns gathered
+  DMat<double> Om{Out, nullptr, n, 0};
+  if (r == ncol) {
+    gemm_triu_b(st, n, ncol, ncol, 1.0, Bm, Uim, 0.0, Om, 1);
+  } else {
+    kept.push_back(r);  // device copy of the count follows the list
+    RFD_HIP(hipMemcpyAsync(keep, kept.data(), sizeof(int) * (r + 1), hipMemcpyHostToDevice, st));
+    gemm_triu_b(st, n, ncol, ncol, 1.0, Bm, Uim, 0.0, MBm, 1);
+    k_gather_cols<<<dim3(grid1(n), r), 256, 0, st>>>(MB, n, Out, n, n, keep, keep + r);
+    RFD_CHECK_LAUNCH();
+  }
   RFD_HIP(hipStreamSynchronize(st));
   return r;
 }

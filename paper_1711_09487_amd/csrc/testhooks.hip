@@ -77,6 +77,19 @@ extern "C" int rfd_test_gemm_static(int dtype, int ta, int tb, int64_t M, int64_
   });
 }
 
+// C_b = alpha A_b B_b + beta C_b, real FP64, with every B_b upper triangular
+// (gemm_triu_b).
+extern "C" int rfd_test_gemm_triu_b(int64_t M, int64_t N, int64_t K, double alpha, double beta,
+                                    void* a, int64_t lda, int64_t sa, void* b, int64_t ldb,
+                                    int64_t sb, void* c, int64_t ldc, int64_t sc, int batch,
+                                    void* stream) {
+  return capi_guard([&] {
+    check_gemm_args(M, N, K, batch, a, b, c, nullptr, nullptr, nullptr);
+    gemm_triu_b((hipStream_t)stream, M, N, K, alpha, dm<double>(a, nullptr, lda, sa),
+                dm<double>(b, nullptr, ldb, sb), beta, dm<double>(c, nullptr, ldc, sc), batch);
+  });
+}
+
 // Factors A (n x n items, in place) and solves A X = R in place (n x r items).
 // pivot = 1 selects partial pivoting (real only).  *flags_out receives the
 // breakdown flags.

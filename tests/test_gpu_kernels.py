@@ -75,6 +75,32 @@ def test_gemm_batched(dtype, cplx, ta, tb, shape):
     assert np.max(np.abs(got - ref)) < tol * np.max(np.abs(ref)) * np.sqrt(K)
 
 
+@pytest.mark.parametrize("M,N,K,batch", [(8192, 512, 512, 1), (8191, 515, 515, 2),
+                                         (4099, 640, 700, 2), (70, 130, 130, 3)])
+def test_gemm_upper_triangular_b(M, N, K, batch):
+    """C = alpha A B + beta C with B upper triangular (B[k, j] = 0 for
+    k > j), the Cholesky-QR product of the basis construction: the large
+    shapes take the large-tile FP64 kernel, which skips each tile column's
+    zero K range (ragged tiles, K beyond N, batches); the small one the
+    64 x 64 kernel over the whole K."""
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    rs = np.random.default_rng(7)
+    A = rs.standard_normal((batch, M, K))
+    B = np.triu(rs.standard_normal((batch, K, N)))
+    Cm = rs.standard_normal((batch, M, N))
+    alpha, beta = 0.625, -1.5
+    ref = alpha * (A @ B) + beta * Cm
+    a, b, c = (_dev(torch, v, torch.float64) for v in (A, B, Cm))
+    code = R.lib().rfd_test_gemm_triu_b(M, N, K, alpha, beta, a.data_ptr(), M, M * K,
+                                        b.data_ptr(), K, K * N, c.data_ptr(), M, M * N, batch,
+                                        torch.cuda.current_stream().cuda_stream)
+    assert code == 0, R.rfd_last_error()
+    torch.cuda.synchronize()
+    got = _host(c)
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref)) * np.sqrt(K)
+
+
 def _shifted_blocks(rs, n, batch, cplx):
     """Shifted 1D/2D-Laplacian-like blocks B - z M, complex symmetric."""
     out = []
