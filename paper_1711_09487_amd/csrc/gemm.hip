@@ -373,8 +373,10 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
     offb[q] = TB ? (uint32_t)(nr + kr * ldb) : (uint32_t)(kr + nr * ldb);
   }
   const int64_t a_tile = TA ? m0 * A.ld : m0, b_tile = TB ? n0 : n0 * B.ld;
-  double ra[NP][LA], rb[NP][LB];
-  auto gload = [&](int64_t k0) {
+  // real products: two register sets, a slab's loads issued two slabs
+  // before it is used (complex ones use set 0 only)
+  double ra0[NP][LA], rb0[NP][LB], ra1[NP][LA], rb1[NP][LB];
+  auto gload = [&](int64_t k0, double (&ra)[NP][LA], double (&rb)[NP][LB]) {
     const int64_t ka = TA ? k0 : k0 * A.ld, kb_ = TB ? k0 * B.ld : k0;
     const double* pa[2] = {A.re + a_tile + ka, CPLX ? A.im + a_tile + ka : nullptr};
     const double* pb[2] = {B.re + b_tile + kb_, CPLX ? B.im + b_tile + kb_ : nullptr};
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
       }
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const double (&ra)[NP][LA], const double (&rb)[NP][LB]) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
@@ -454,13 +456,7 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
         }
       }
 
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k0 = 0; k0 < ke; k0 += GBK) {
-    const bool more = k0 + GBK < ke;
-    if (more) gload(k0 + GBK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < GBK; kk += 4) {
       const int kr = kk + (lane >> 4), r = lane & 15;
@@ -484,10 +480,42 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
           }
         }
     }
-    // the other buffer was last read before the previous barrier
-    if (more) lstore(buf ^ 1);
+  };
+  if constexpr (!CPLX) {
+    // slab s lives in LDS buffer s % 2; register set 0 carries the even
+    // slabs, set 1 the odd ones.  Each LDS buffer is rewritten only after the
+    // barrier that follows its last read.
+    gload(0, ra0, rb0);
+    lstore(0, ra0, rb0);
+    if (GBK < ke) gload(GBK, ra1, rb1);
     __syncthreads();
-    buf ^= 1;
+    for (int64_t k0 = 0; k0 < ke; k0 += 2 * GBK) {
+      if (k0 + 2 * GBK < ke) gload(k0 + 2 * GBK, ra0, rb0);
+      compute(0);
+      if (k0 + GBK < ke) lstore(1, ra1, rb1);
+      __syncthreads();
+      if (k0 + GBK >= ke) break;
+      if (k0 + 3 * GBK < ke) gload(k0 + 3 * GBK, ra1, rb1);
+      compute(1);
+      if (k0 + 2 * GBK < ke) lstore(0, ra0, rb0);
+      __syncthreads();
+    }
+  } else {
+    // complex: the three accumulator sets leave room for one register set,
+    // so each slab's loads are issued one slab ahead
+    gload(0, ra0, rb0);
+    lstore(0, ra0, rb0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = 0; k0 < ke; k0 += GBK) {
+      const bool more = k0 + GBK < ke;
+      if (more) gload(k0 + GBK, ra0, rb0);
+      compute(buf);
+      // the other buffer was last read before the previous barrier
+      if (more) lstore(buf ^ 1, ra0, rb0);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
 
 #pragma unroll
