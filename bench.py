@@ -177,8 +177,9 @@ def summary(r, prob):
 # unchanged.
 PROFILE_OF = {"k_tri_symv": ("tri_symv_63cube.md", "eig.hip"),
               "k_gemm<float, true, false, false>": ("gemm_c32_nn_63cube.md", "gemm.hip"),
-              "k_gemm<double, false, true, false>": ("gemm_d_tn_63cube.md", "gemm.hip"),
-              "k_gemm<double, false, false, false>": ("gemm_d_nn_63cube.md", "gemm.hip")}
+              "k_dgemm<false, true, false>": ("dgemm_tn_63cube.md", "gemm.hip"),
+              "k_dgemm<false, false, false>": ("dgemm_nn_63cube.md", "gemm.hip"),
+              "k_dgemm<true, false, false>": ("dgemm_c_nn_63cube.md", "gemm.hip")}
 
 
 def measured_traffic(kname, workload):
@@ -213,7 +214,7 @@ def roofline_entry(kname, st, f32, steps, workload):
         rate = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
         e = {"bound": "mfma", "peak": peak, "unit": "TFLOP/s",
              "kernel": f"{kname} (LU updates, triangular solves, products)"}
-        if "float, true" in kname:
+        if "float, true" in kname or kname.startswith("k_dgemm<true"):
             # Gauss's three real products: 6 flops per complex multiply-add run
             # on the matrix cores; the 8-flop rate is the effective one
             e["achieved"] = 0.75 * rate
