@@ -11,8 +11,11 @@ block are resident on the device before the timed region.  A Ritz value
 counts when it lies within 1e-10 (relative) of the reference eigenvalue of
 the same rank (tests/golden/reference_c3.json); the count that also asks
 for a residual ||Ax - theta Mx|| / (||A|| ||x||) <= 1e-9 is reported beside
-it.  Both precision modes run: FP32 factors with FP64 refinement to the
-1e-10 target (the value) and plain FP64 (beside it).
+it.  Three precision modes run: FP32 factors with FP64 refinement to the
+1e-10 target where the refinement costs less than the FP32 factorization
+saves (RFD_FP32_AUTO: the interior blocks; the value), every factor in
+FP32 with FP64 refinement (RFD_FP32_REFINE, beside it) and plain FP64
+(beside it).
 
 Beside the headline:
   spectral -- the same pencil with the spectral interior path (one
@@ -25,8 +28,9 @@ Beside the headline:
               (tests/golden/oracle_c2.json) and the residual target;
   batched  -- the 256 pencils of the batched workload (variable coefficient,
               random M, uneven sizes) run as one rfd_batch_run on several
-              worker streams in FP32+refine, against the same jobs on one
-              worker and in plain FP64;
+              worker streams in FP32+refine (RFD_FP32_AUTO), against the
+              same jobs on one worker, with every factor FP32, and in plain
+              FP64;
   serving  -- a seeded Poisson stream of spectrum-slicing requests on the
               31x31, 255x255 and 63^3 pencils (weights 0.6 / 0.3 / 0.1),
               replayed at 0.5x and 0.8x the measured saturated rate: p50 /
@@ -37,7 +41,7 @@ Beside the headline:
               each timed per launch with HIP events stamped by the launch;
   cpu_baseline -- the CPU oracle on a bounded sample of the 63^3 workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp32|fp64|both]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fp32|fp64|fp32all|both|all]
 """
 import argparse
 import json
@@ -308,7 +312,7 @@ def batch_leg(R, W, torch, count, workers):
     R.batch_run(jobs(R.RFD_FP32_AUTO), workers=workers)   # first use: maps, reordered matrices
     out = {}
     for key, mode, w in (("fp32", R.RFD_FP32_AUTO, workers), ("fp32_1", R.RFD_FP32_AUTO, 1),
-                         ("fp64", R.RFD_FP64, workers)):
+                         ("fp32all", R.RFD_FP32_REFINE, workers), ("fp64", R.RFD_FP64, workers)):
         js = jobs(mode)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -325,7 +329,7 @@ def batch_leg(R, W, torch, count, workers):
         del js
     for P in pens:
         P.close()
-    b, s1, d = out["fp32"], out["fp32_1"], out["fp64"]
+    b, s1, d, a32 = out["fp32"], out["fp32_1"], out["fp64"], out["fp32all"]
     return {"pencils": count, "workers": workers, "eigenpairs": b["good"],
             "eigenpairs_wanted": int(sum(pr.nev for pr in probs)),
             "eigenpairs_found": b["found"], "value": b["good"] / b["wall"],
@@ -333,7 +337,10 @@ def batch_leg(R, W, torch, count, workers):
             "one_worker_wall_s": s1["wall"], "speedup_vs_one_worker": s1["wall"] / b["wall"],
             "fp64": {"value": d["good"] / d["wall"], "eigenpairs": d["good"], "wall_s": d["wall"]},
             "fp32_over_fp64": (b["good"] / b["wall"]) / max(d["good"] / d["wall"], 1e-30),
-            "mode": "fp32+refine", "counted": "Ritz values within 1e-10 of a reference eigensolver",
+            "fp32all": {"value": a32["good"] / a32["wall"], "eigenpairs": a32["good"],
+                        "wall_s": a32["wall"], "precision": "RFD_FP32_REFINE: every factor FP32"},
+            "fp32all_over_fp64": (a32["good"] / a32["wall"]) / max(d["good"] / d["wall"], 1e-30),
+            "mode": "fp32+refine (RFD_FP32_AUTO)", "counted": "Ritz values within 1e-10 of a reference eigensolver",
             "nev_b": BATCH_NEV_B, "psi": BATCH_PSI, "block_steps": BATCH_STEPS,
             "sizes": {"N": [s["N"] for s in specs], "P": [s["P"] for s in specs],
                       "nev": [s["nev"] for s in specs], "n_c": [s["n_c"] for s in specs]}}
@@ -577,7 +584,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=2,
                     help="timed FP64 solves of the headline workload beside the FP32 ones")
-    ap.add_argument("--mode", default="both", choices=["fp32", "fp64", "fp32all", "both", "all"],
+    ap.add_argument("--mode", default="all", choices=["fp32", "fp64", "fp32all", "both", "all"],
                     help="fp32: FP32 factors + FP64 refinement where the cost model says they "
                          "pay (RFD_FP32_AUTO); fp32all: every factor FP32 (RFD_FP32_REFINE); "
                          "both: fp32 and fp64; all: the three")
@@ -681,7 +688,8 @@ def main():
                                   gbps=v[4] / max(v[2], 1e-9) / 1e6)
                           for k, v in res[m]["kstats"].items()} for m in res}
     if not a.no_spectral:
-        out["spectral"] = spectral_leg(R, W, prob, ref, torch, a.refine_tol, modes)
+        out["spectral"] = spectral_leg(R, W, prob, ref, torch, a.refine_tol,
+                                       [m for m in modes if m != "fp32all"])
         if "fp64" in out["spectral"] and "fp32" in out["spectral"]:
             out["spectral"]["fp32_over_fp64_stored"] = (
                 out["spectral"]["fp32"]["value_stored"] /
@@ -692,6 +700,8 @@ def main():
         assert (prob2.steps, prob2.nev_b, prob2.psi) == (gold2["steps"], gold2["nev_b"], gold2["psi"])
         c2 = {}
         for mode in modes:
+            if mode == "fp32all":
+                continue
             r = run_mode(R, W, prob2, mode, a.c2_steps, a.warmup, np.array(gold2["theta"]),
                          torch, a.refine_tol, account=False)
             c2[mode] = summary(r, prob2)
