@@ -386,6 +386,31 @@ rfd_status rfd_set_interior_solver(rfd_pencil_t pencil, int32_t kind);
 rfd_status rfd_set_interface_groups(rfd_pencil_t pencil, int32_t ngroups, const int32_t* group);
 
 /*
+ * rfd_set_gemm_tuning -- process-wide tile choices of the matrix-core GEMM
+ * behind every dense step (LU updates, triangular solves, refinement
+ * residuals, basis products; Secs. 3-5), as measured by an autotuner
+ * (python -m paper_1711_09487_amd.tune writes them per GPU architecture;
+ * the Python binding loads the file of the device's architecture).
+ *   entries  host, count x 9 int32: {fp64 (0 FP32, 1 FP64), complex, transA,
+ *            transB, floor(log2 M), floor(log2 N), floor(log2 K),
+ *            floor(log2 batch), variant} with variant 1: 64 x 64 tile, 2:
+ *            128 x 128 tile (real FP32 only), 3: the large-tile FP64 kernel
+ *            (FP64 only); log2 values in 0..62
+ *   count    number of entries; 0 clears the table (built-in rules only)
+ * Products whose class has no entry keep the built-in rules, and so do
+ * products an entry's variant cannot run.  Results differ only by rounding.
+ * Errors: RFD_EINVAL for a malformed entry (the table is then unchanged).
+ */
+rfd_status rfd_set_gemm_tuning(const int32_t* entries, int32_t count);
+
+/*
+ * rfd_device_arch -- the current HIP device's architecture name (for example
+ * "gfx950", without feature suffixes) into buf (host, len bytes, NUL-terminated).
+ * Errors: RFD_EINVAL for a null buf or len < 2; RFD_EDEVICE without a device.
+ */
+rfd_status rfd_device_arch(char* buf, int32_t len);
+
+/*
  * rfd_kernel_accounting / rfd_kernel_stats -- process-wide, sampled timing of
  * selected kernels: the batched GEMM (the matrix-core kernel behind the LU
  * updates, the triangular solves, the refinement residuals and the

@@ -26,6 +26,16 @@ int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K, do
                   void* b_im, int64_t ldb, int64_t sb, void* c_re, void* c_im, int64_t ldc,
                   int64_t sc, int batch, void* stream);
 
+/* rfd_test_gemm with the kernel variant forced (1: the 64 x 64 tile, 2: the
+ * 128 x 128 tile, real FP32 only, 3: the large-tile FP64 kernel, FP64 only):
+ * the candidates the autotuner behind rfd_set_gemm_tuning times for each
+ * product class.  RFD_EINVAL when the variant cannot run the product. */
+int rfd_test_gemm_variant(int variant, int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K,
+                          double alpha, double beta, void* a_re, void* a_im, int64_t lda,
+                          int64_t sa, void* b_re, void* b_im, int64_t ldb, int64_t sb,
+                          void* c_re, void* c_im, int64_t ldc, int64_t sc, int batch,
+                          void* stream);
+
 /* rfd_test_gemm for real FP64 operands, neither transposed, with every B_b
  * upper triangular (B_b[k, j] = 0 for k > j; the entries below the diagonal
  * are not read by the large-tile path, so they must be zero): the product

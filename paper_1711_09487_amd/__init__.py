@@ -111,6 +111,10 @@ def lib():
                                      I64, I64, P, P, I64, I64, I32, P],
             "rfd_test_gemm_triu_b": [I64, I64, I64, F64, F64, P, I64, I64, P, I64, I64, P, I64,
                                      I64, I32, P],
+            "rfd_test_gemm_variant": [I32, I32, I32, I32, I64, I64, I64, F64, F64, P, P, I64, I64,
+                                      P, P, I64, I64, P, P, I64, I64, I32, P],
+            "rfd_set_gemm_tuning": [P, I32],
+            "rfd_device_arch": [P, I32],
             "rfd_test_lu": [I32, I32, I64, I32, P, P, I64, I64, P, P, I64, I64, I64,
                             C.POINTER(C.c_uint32), P],
             "rfd_test_syevx": [I64, I32, P, I32, I32, P, P, P],
@@ -130,7 +134,54 @@ def lib():
         L.rfd_last_error.argtypes = []
         L.rfd_last_error.restype = C.c_char_p
         _lib = L
+        _load_tuning(L)
     return _lib
+
+
+TUNING_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning")
+tuning_loaded = None   # path of the GEMM tuning table in use, or None
+
+
+def device_arch(L=None):
+    """The current device's architecture name (e.g. 'gfx950'), or None
+    without a device."""
+    L = L or lib()
+    buf = C.create_string_buffer(64)
+    return buf.value.decode() if L.rfd_device_arch(buf, 64) == 0 else None
+
+
+def _load_tuning(L):
+    """Hands the autotuner's table for the device's architecture
+    (tuning/<arch>.json, written by python -m paper_1711_09487_amd.tune) to
+    rfd_set_gemm_tuning.  RFD_GEMM_TUNING=off keeps the built-in rules;
+    RFD_GEMM_TUNING=<path> names another table (for the same architecture)."""
+    global tuning_loaded
+    env = os.environ.get("RFD_GEMM_TUNING", "")
+    if env == "off":
+        return
+    arch = device_arch(L)
+    if arch is None:
+        return
+    path = env or os.path.join(TUNING_DIR, arch + ".json")
+    if not os.path.exists(path):
+        return
+    import json
+    t = json.load(open(path))
+    if t.get("arch") != arch:
+        raise RuntimeError(f"{path} was tuned for {t.get('arch')}, the device is {arch}")
+    ent = np.ascontiguousarray(np.array(t["entries"], dtype=np.int32).reshape(-1, 9))
+    code = L.rfd_set_gemm_tuning(ent.ctypes.data, int(ent.shape[0]))
+    if code != 0:
+        raise RfdError(code, L.rfd_last_error().decode())
+    tuning_loaded = path
+
+
+def rfd_set_gemm_tuning(entries):
+    """entries: (count, 9) int32 rows {fp64, complex, transA, transB, log2 M,
+    log2 N, log2 K, log2 batch, variant}; an empty table restores the
+    built-in rules."""
+    ent = np.ascontiguousarray(np.asarray(entries, dtype=np.int32).reshape(-1, 9))
+    _check(lib().rfd_set_gemm_tuning(ent.ctypes.data if ent.size else None, int(ent.shape[0])))
 
 
 def _check(code):

@@ -359,6 +359,26 @@ rfd_status rfd_phase_times(rfd_pencil_t pencil, double* ms16) {
   });
 }
 
+rfd_status rfd_set_gemm_tuning(const int32_t* entries, int32_t count) {
+  return (rfd_status)capi_guard([&] { set_gemm_tuning(entries, count); });
+}
+
+rfd_status rfd_device_arch(char* buf, int32_t len) {
+  return (rfd_status)capi_guard([&] {
+    if (!buf || len < 2) throw Error(ST_EINVAL, "need a buffer of at least 2 bytes");
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(ST_EDEVICE, "no HIP device");
+    }
+    std::string a(prop.gcnArchName);
+    a = a.substr(0, a.find(':'));
+    std::strncpy(buf, a.c_str(), (size_t)len - 1);
+    buf[len - 1] = 0;
+  });
+}
+
 rfd_status rfd_kernel_accounting(int32_t every) {
   return (rfd_status)capi_guard([&] {
     if (every < 0) throw Error(ST_EINVAL, "need every >= 0");

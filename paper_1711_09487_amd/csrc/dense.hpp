@@ -69,6 +69,14 @@ void gemm(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T al
 void gemm_triu_b(hipStream_t s, int64_t M, int64_t N, int64_t K, double alpha, DMat<double> A,
                  DMat<double> B, double beta, DMat<double> C, int batch);
 
+// Autotuned tile choices (rfd_set_gemm_tuning): count entries of 9 int32 each,
+// {fp64, complex, transA, transB, floor log2 M, N, K, batch, variant}; count
+// = 0 clears.  Process-wide.  gemm_tuning_size: entries held.
+void set_gemm_tuning(const int32_t* entries, int count);
+int gemm_tuning_size();
+// Forces a variant (0 = none) for the calling thread's next products.
+void gemm_force_variant(int v);
+
 // Drops the split-K workspace kept for stream s (call
 // before destroying a stream that ran products).
 void release_stream_resources(hipStream_t s);

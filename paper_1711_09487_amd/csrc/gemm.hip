@@ -33,9 +33,11 @@
 
 #include <atomic>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <type_traits>
+#include <unordered_map>
 
 #include "dense.hpp"
 
@@ -654,6 +656,74 @@ static bool aligned16(const DMat<T>& X, int vw) {
   return X.ld % vw == 0 && X.bs % vw == 0 && al(X.re) && (X.im == nullptr || al(X.im));
 }
 
+// ---------------------------------------------------------------------------
+// Tile choices measured by an autotuner (set_gemm_tuning): per class of
+// (precision, complex, transposes, floor log2 of M, N, K and the batch) the variant that
+// ran fastest -- 1: k_gemm 64 x 64, 2: k_gemm 128 x 128 (real FP32), 3:
+// k_dgemm (FP64).  Classes without an entry keep the built-in rules, and so
+// do lower-triangle and triangular-operand products.  A variant that cannot
+// run a product (an aliased output, sizes beyond its limits) falls back to
+// the built-in rules; the test hook that forces a variant reports it instead.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex tune_mu;
+std::shared_ptr<const std::unordered_map<uint64_t, int>> tune_table;
+thread_local int forced_variant = 0;
+
+int ilog2(int64_t x) {
+  int l = 0;
+  while (x > 1 && l < 62) {
+    x >>= 1;
+    ++l;
+  }
+  return l;
+}
+
+uint64_t tune_key(int dt, int cplx, int ta, int tb, int lm, int ln, int lk, int lb) {
+  return (uint64_t)dt | (uint64_t)cplx << 1 | (uint64_t)ta << 2 | (uint64_t)tb << 3 |
+         (uint64_t)lm << 4 | (uint64_t)ln << 12 | (uint64_t)lk << 20 | (uint64_t)lb << 28;
+}
+
+int tuned_variant(bool fp64, bool cplx, bool ta, bool tb, int64_t M, int64_t N, int64_t K,
+                  int batch) {
+  if (forced_variant) return forced_variant;
+  std::shared_ptr<const std::unordered_map<uint64_t, int>> t;
+  {
+    std::lock_guard<std::mutex> g(tune_mu);
+    t = tune_table;
+  }
+  if (!t || t->empty()) return 0;
+  const auto it =
+      t->find(tune_key(fp64, cplx, ta, tb, ilog2(M), ilog2(N), ilog2(K), ilog2(batch)));
+  return it == t->end() ? 0 : it->second;
+}
+}  // namespace
+
+void set_gemm_tuning(const int32_t* e, int count) {
+  if (count < 0 || (count > 0 && !e)) throw Error(ST_EINVAL, "gemm tuning: bad table");
+  auto t = std::make_shared<std::unordered_map<uint64_t, int>>();
+  for (int i = 0; i < count; ++i) {
+    const int32_t* r = e + 9 * (int64_t)i;
+    const int dt = r[0], cplx = r[1], ta = r[2], tb = r[3], v = r[8];
+    bool ok = (dt == 0 || dt == 1) && (cplx == 0 || cplx == 1) && (ta == 0 || ta == 1) &&
+              (tb == 0 || tb == 1) && v >= 1 && v <= 3;
+    for (int q = 4; q < 8; ++q) ok = ok && r[q] >= 0 && r[q] <= 62;
+    if (ok && v == 2) ok = dt == 0 && cplx == 0;
+    if (ok && v == 3) ok = dt == 1;
+    if (!ok) throw Error(ST_EINVAL, "gemm tuning: entry " + std::to_string(i) + " is malformed");
+    (*t)[tune_key(dt, cplx, ta, tb, r[4], r[5], r[6], r[7])] = v;
+  }
+  std::lock_guard<std::mutex> g(tune_mu);
+  tune_table = std::move(t);
+}
+
+int gemm_tuning_size() {
+  std::lock_guard<std::mutex> g(tune_mu);
+  return tune_table ? (int)tune_table->size() : 0;
+}
+
+void gemm_force_variant(int v) { forced_variant = v; }
+
 // fixed_part: caller-provided memory of fixed_bytes for the split-K partial
 // tiles (the split count is lowered until they fit; no allocation and no
 // kernel accounting), or null for the per-stream workspace.
@@ -675,9 +745,14 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
   // accumulators leave one wave per SIMD.
   // Large real FP64 products go to k_dgemm below; the rest keep the 64 x 64
   // tile here.
+  const int var = (tri || triub) ? 0 : tuned_variant(sizeof(T) == 8, cplx, ta, tb, M, N, K, batch);
+  if (forced_variant == 2 && (sizeof(T) != 4 || cplx))
+    throw Error(ST_EINVAL, "gemm variant 2 (128 x 128) takes real FP32 products only");
+  if (forced_variant == 3 && sizeof(T) != 8)
+    throw Error(ST_EINVAL, "gemm variant 3 (k_dgemm) takes FP64 products only");
   const bool big_ok = sizeof(T) == 4 && !cplx && M >= 128 && N >= 128 && K >= 256;
   const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128) * batch;
-  const int bt = (big_ok && t128 >= 240) ? 128 : 64;
+  const int bt = var == 2 ? 128 : var == 1 ? 64 : (big_ok && t128 >= 240) ? 128 : 64;
   const int64_t gm = (M + bt - 1) / bt, gn = (N + bt - 1) / bt;
   // tiles that do work (a lower-triangle product skips the strictly upper ones)
   const int64_t tiles = (tri ? gm * (gm + 1) / 2 : gm * gn) * batch;
@@ -726,8 +801,12 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
       const int64_t span_b = tb ? (int64_t)bn + GBK * B.ld : (int64_t)GBK + bn * B.ld;
       // (short K, as in the LU trailing updates, stays on the 64 x 64 tile:
       // a few K slabs do not repay the larger tile's epilogue)
-      if (wide_ok && t64 >= 512 && K >= 256 && nt <= 65535 && g64 <= 0x7fffffff &&
-          span_a < (int64_t(1) << 31) && span_b < (int64_t(1) << 31)) {
+      const bool fits = K >= GBK && nt <= 65535 && g64 <= 0x7fffffff &&
+                        span_a < (int64_t(1) << 31) && span_b < (int64_t(1) << 31);
+      if (forced_variant == 3 && !fits)
+        throw Error(ST_EINVAL, "gemm variant 3 (k_dgemm) cannot run this product");
+      const bool rule = wide_ok && t64 >= 512 && K >= 256;
+      if (fits && (var == 3 || (var == 0 && rule))) {
         const int key = KA_DGEMM + (cplx ? 4 : 0) + (ta ? 2 : 0) + (tb ? 1 : 0);
         const double outs = tri ? 0.5 * (double)N * (double)(N + 1) : (double)M * (double)N;
         // (with a triangular op(B), column j takes min(j + 1, K) terms)
@@ -752,6 +831,7 @@ static void gemm_impl(hipStream_t s, bool ta, bool tb, int64_t M, int64_t N, int
       }
     }
   }
+  if (forced_variant == 3) throw Error(ST_EINVAL, "gemm variant 3 (k_dgemm) cannot run this product");
   if ((int64_t)batch * splits > 65535) throw Error(ST_EINVAL, "gemm: batch too large");
   if (gm * gn * batch * splits >= ((int64_t)1 << 32)) throw Error(ST_EINVAL, "gemm: grid too large");
   if (gm > 0x7fffffff || gn > 65535) throw Error(ST_EINVAL, "gemm: matrix too large");

@@ -56,6 +56,32 @@ extern "C" int rfd_test_gemm(int dtype, int ta, int tb, int64_t M, int64_t N, in
   });
 }
 
+// rfd_test_gemm with the kernel variant forced (1: k_gemm 64 x 64, 2: k_gemm
+// 128 x 128, 3: k_dgemm): the candidates an autotuner times.
+extern "C" int rfd_test_gemm_variant(int variant, int dtype, int ta, int tb, int64_t M, int64_t N,
+                                     int64_t K, double alpha, double beta, void* a_re,
+                                     void* a_im, int64_t lda, int64_t sa, void* b_re, void* b_im,
+                                     int64_t ldb, int64_t sb, void* c_re, void* c_im, int64_t ldc,
+                                     int64_t sc, int batch, void* stream) {
+  return capi_guard([&] {
+    if (variant < 1 || variant > 3) throw Error(ST_EINVAL, "variant must be 1, 2 or 3");
+    hipStream_t s = (hipStream_t)stream;
+    check_gemm_args(M, N, K, batch, a_re, b_re, c_re, a_im, b_im, c_im);
+    struct Reset {
+      ~Reset() { gemm_force_variant(0); }
+    } reset;
+    gemm_force_variant(variant);
+    if (dtype == 0)
+      gemm<float>(s, ta, tb, M, N, K, (float)alpha, dm<float>(a_re, a_im, lda, sa),
+                  dm<float>(b_re, b_im, ldb, sb), (float)beta, dm<float>(c_re, c_im, ldc, sc),
+                  batch);
+    else
+      gemm<double>(s, ta, tb, M, N, K, alpha, dm<double>(a_re, a_im, lda, sa),
+                   dm<double>(b_re, b_im, ldb, sb), beta, dm<double>(c_re, c_im, ldc, sc),
+                   batch);
+  });
+}
+
 // rfd_test_gemm for callers that cannot allocate: split-K partial tiles in
 // the library's fixed per-device scratch array (gemm_static).
 extern "C" int rfd_test_gemm_static(int dtype, int ta, int tb, int64_t M, int64_t N, int64_t K,

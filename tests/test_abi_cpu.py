@@ -159,3 +159,29 @@ def test_interior_solver_needs_a_partition():
         assert e.value.code == 6
     finally:
         R.rfd_destroy_pencil(h)
+
+
+def test_gemm_tuning_table_validation():
+    """rfd_set_gemm_tuning takes rows of 9 int32 and rejects a malformed row
+    (unknown variant, the 128-wide tile for a complex or FP64 class, the
+    large-tile FP64 kernel for FP32, a log2 out of range) with RFD_EINVAL,
+    leaving the table as it was; an empty table restores the built-in rules.
+    The forced-variant hook refuses unknown variants before any device work."""
+    R = _lib()
+    good = [[1, 0, 1, 0, 13, 11, 17, 0, 3], [0, 0, 0, 0, 12, 12, 10, 0, 2],
+            [1, 1, 0, 0, 12, 12, 12, 3, 1]]
+    R.rfd_set_gemm_tuning(good)
+    for bad in ([1, 0, 0, 0, 10, 10, 10, 0, 4], [1, 1, 0, 0, 10, 10, 10, 0, 2],
+                [0, 1, 0, 0, 10, 10, 10, 0, 2], [0, 0, 0, 0, 10, 10, 10, 0, 3],
+                [1, 0, 2, 0, 10, 10, 10, 0, 1], [1, 0, 0, 0, 63, 10, 10, 0, 1],
+                [1, 0, 0, 0, 10, 10, -1, 0, 1]):
+        with pytest.raises(R.RfdError) as e:
+            R.rfd_set_gemm_tuning(good + [bad])
+        assert e.value.code == 1 and "malformed" in str(e.value)
+    R.rfd_set_gemm_tuning(np.zeros((0, 9), dtype=np.int32))
+    L = R.lib()
+    fake = 1 << 20
+    for v in (0, 4):
+        code = L.rfd_test_gemm_variant(v, 1, 0, 0, 64, 64, 64, 1.0, 0.0, fake, None, 64, 0, fake,
+                                       None, 64, 0, fake, None, 64, 0, 1, None)
+        assert code == 1 and "variant" in R.rfd_last_error()

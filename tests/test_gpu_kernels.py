@@ -244,3 +244,61 @@ def test_symmetric_eigensolver(n, batch, lo, num):
         res = A[b] @ X - X * lam[b]
         assert np.max(np.abs(res)) <= 1e-12 * nrm
         assert np.max(np.abs(X.T @ X - np.eye(num))) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype,cplx,ta,tb,M,N,K,batch", [
+    (1, 0, 0, 0, 700, 520, 300, 2), (1, 0, 1, 0, 300, 260, 1200, 1),
+    (1, 1, 0, 1, 513, 130, 290, 3), (0, 0, 0, 0, 640, 700, 300, 1), (0, 1, 1, 1, 130, 200, 77, 2)])
+def test_gemm_variants_and_tuning_table(dtype, cplx, ta, tb, M, N, K, batch):
+    """Every kernel variant the autotuner may pick (rfd_test_gemm_variant:
+    the 64 x 64 tile, the 128 x 128 tile for real FP32, the large-tile FP64
+    kernel) computes the product; a variant that cannot run the class says
+    so.  A tuning table entry for the class makes the default entry point
+    give the forced variant's result bit for bit."""
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    rs = np.random.default_rng(11)
+    dt = torch.float32 if dtype == 0 else torch.float64
+    Ash = (batch, K, M) if ta else (batch, M, K)
+    Bsh = (batch, N, K) if tb else (batch, K, N)
+    Ar, Ai, Br, Bi = (rs.standard_normal(s) for s in (Ash, Ash, Bsh, Bsh))
+    Cr, Ci = rs.standard_normal((batch, M, N)), rs.standard_normal((batch, M, N))
+    alpha, beta = 0.5, -1.25
+    A = Ar + 1j * Ai if cplx else Ar
+    B = Br + 1j * Bi if cplx else Br
+    opA = np.swapaxes(A, 1, 2) if ta else A
+    opB = np.swapaxes(B, 1, 2) if tb else B
+    ref = alpha * (opA @ opB) + beta * (Cr + 1j * Ci if cplx else Cr)
+    tol = (2e-5 if dtype == 0 else 1e-13) * np.max(np.abs(ref)) * np.sqrt(K)
+    L = R.lib()
+
+    def run(fn, *pre):
+        t = {k: _dev(torch, v, dt) for k, v in dict(ar=Ar, ai=Ai, br=Br, bi=Bi, cr=Cr, ci=Ci).items()}
+        code = fn(*pre, dtype, ta, tb, M, N, K, alpha, beta,
+                  t["ar"].data_ptr(), t["ai"].data_ptr() if cplx else None, Ash[1], Ash[1] * Ash[2],
+                  t["br"].data_ptr(), t["bi"].data_ptr() if cplx else None, Bsh[1], Bsh[1] * Bsh[2],
+                  t["cr"].data_ptr(), t["ci"].data_ptr() if cplx else None, M, M * N, batch,
+                  torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        return code, (_host(t["cr"]) + (1j * _host(t["ci"]) if cplx else 0)) if code == 0 else None
+
+    runs = {}
+    for v in (1, 2, 3):
+        code, got = run(L.rfd_test_gemm_variant, v)
+        runnable = v == 1 or (v == 2 and dtype == 0 and not cplx) or (v == 3 and dtype == 1)
+        if not runnable:
+            assert code == 1 and "variant" in R.rfd_last_error()
+            continue
+        assert code == 0, R.rfd_last_error()
+        assert np.max(np.abs(got - ref)) < tol, v
+        runs[v] = got
+    pick = max(runs)
+    key = [dtype, int(cplx), ta, tb] + [int(np.floor(np.log2(x))) for x in (M, N, K, batch)]
+    try:
+        R.rfd_set_gemm_tuning([key + [pick]])
+        code, got = run(L.rfd_test_gemm)
+        assert code == 0
+        assert np.array_equal(got, runs[pick])
+    finally:
+        R.rfd_set_gemm_tuning(np.zeros((0, 9), dtype=np.int32))
+        R._load_tuning(L)
