@@ -354,10 +354,13 @@ rfd_status rfd_set_pole_window(rfd_pencil_t pencil, int32_t max_poles);
  * the stored eigenvectors.  The decomposition is kept until the pencil is
  * destroyed, re-partitioned or rfd_reset_caches(pencil, 1) releases the
  * buffers; it holds p D^2 + p D SJ doubles (D, SJ: interior and adjacency
- * sizes padded to 64).  Results equal the LU path's up to rounding.  Errors:
- * RFD_EINVAL for another kind or, for the spectral path, a non-diagonal M;
- * RFD_ESTATE before rfd_set_partition.  The next solve rebuilds what depends
- * on the choice.
+ * sizes padded to 64), and for a non-diagonal M another p D^2 (the factors
+ * of M_Bj for the standard form) and, when M couples the interiors to the
+ * interface, p D SJ (V^T Mhat_E).  Results equal the LU path's up to
+ * rounding.  Errors: RFD_EINVAL for another kind; RFD_ESTATE before
+ * rfd_set_partition; RFD_EBREAKDOWN (at the next solve) when a block M_Bj is
+ * not positive definite.  The next solve rebuilds what depends on the
+ * choice.
  */
 rfd_status rfd_set_interior_solver(rfd_pencil_t pencil, int32_t kind);
 

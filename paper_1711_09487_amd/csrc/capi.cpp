@@ -90,10 +90,7 @@ rfd_status rfd_set_partition(rfd_pencil_t pencil, int32_t p, const int32_t* part
     P->eng->set_precision(P->mode, P->tol, P->sweeps);
     P->eng->set_timing(P->timing);
     P->eng->set_pole_window(P->window);
-    if (P->interior_solver != RFD_INTERIOR_LU && P->part->m_diag)
-      P->eng->set_interior_solver(P->interior_solver);
-    else
-      P->interior_solver = RFD_INTERIOR_LU;
+    if (P->interior_solver != RFD_INTERIOR_LU) P->eng->set_interior_solver(P->interior_solver);
     if (P->poles.set) P->eng->set_poles(P->poles);
   });
 }

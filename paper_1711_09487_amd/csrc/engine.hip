@@ -244,8 +244,6 @@ int Engine::set_interior_solver(int kind) {
   d_->join_prepare();
   EngineImpl& e = *d_;
   if (kind != 0 && kind != 1) throw Error(ST_EINVAL, "interior solver kind must be 0 or 1");
-  if (kind == 1 && !e.P->m_diag)
-    throw Error(ST_EINVAL, "the spectral interior path needs a diagonal M");
   const int prev = e.interior_solver;
   if (kind != prev) {
     e.factored = false;

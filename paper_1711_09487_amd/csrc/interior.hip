@@ -845,9 +845,54 @@ void EngineImpl::interior_basis(hipStream_t st, double sig, int nevb) {
 // sigma, X_j = V_j (Lambda_j - zeta)^{-1} V_j^T Ehat_j (two real products per
 // pole), the resolvent levels B_sigma^{-1} M_B X = V_j (Lambda_j - sigma)^{-1}
 // V_j^T M_B X, and the deflation vectors V_j near sigma as a column window:
-// no shifted block is factored.  M_Bj is diagonal (M_E = 0, so Ehat_zeta =
-// Ehat for every pole).
+// no shifted block is factored.  For a non-diagonal M the decomposition runs
+// on the standard form G^{-1} B_j G^{-T} (M_Bj = G G^T), and when M couples
+// the interiors to the interface, Ehat_zeta = Ehat - zeta Mhat_E, so that
+// V^T Ehat_zeta = V^T Ehat - zeta V^T Mhat_E from two products per pencil.
 // ---------------------------------------------------------------------------
+
+// C_j[r, c] = Ehat_j[r, c] (which == 0) or Mhat_E^(j)[r, c] (otherwise) on the
+// active rows r < d_j (C zero on entry; D x SJ items).
+__global__ void k_expand_e(DMat<double> C, const int32_t* dj, DevPairCsr E, int which) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= dj[j]) return;
+  DMat<double> c = C.item(j);
+  const int64_t* ptr = E.ptr + E.roff[j];
+  const double* v = which ? E.m : E.a;
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) c.re[r + (int64_t)E.idx[e] * c.ld] = v[e];
+}
+
+// Fz_j = (Lambda_j - zeta_l)^{-1} (FA_j - zeta_l FM_j) for the pole l = pole0
+// (FA = V^T Ehat, FM = V^T Mhat_E, real), planar complex; rows at or beyond DE
+// are zero.  Subdomains j over grid z.
+__global__ void k_spec_scale2(DMat<double> Fz, DMat<double> FA, DMat<double> FM, int64_t D,
+                              int64_t DE, int64_t SJ, int pole0, const double* lam, Shifts z) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  const int j = blockIdx.z, l = pole0;
+  const int64_t c0 = (int64_t)blockIdx.y * CG;
+  DMat<double> fa = FA.item(j), fm = FM.item(j), o = Fz.item(j);
+  const double zr = z.z[2 * l], zi = z.z[2 * l + 1];
+  double wr = 0.0, wi = 0.0;
+  if (r < DE) {
+    const double dr = lam[(int64_t)j * DE + r] - zr;
+    const double den = dr * dr + zi * zi;
+    wr = dr / den;
+    wi = zi / den;
+  }
+#pragma unroll
+  for (int u = 0; u < CG; ++u) {
+    const int64_t c = c0 + u;
+    if (c < SJ) {
+      // (wr + i wi) (a - i b) with a = FA - zr FM, b = zi FM
+      const double m = fm.re[r + c * fm.ld];
+      const double av = fa.re[r + c * fa.ld] - zr * m, bv = zi * m;
+      o.re[r + c * o.ld] = wr * av + wi * bv;
+      o.im[r + c * o.ld] = wi * av - wr * bv;
+    }
+  }
+}
 
 // Fz_j[r, c] = (1 / (lam_j[r] - zeta_l)) F_j[r, c] for the pole l = pole0,
 // planar complex; rows at or beyond DE (no eigenpair) are zero.  Subdomains
@@ -916,23 +961,29 @@ __global__ void k_axpy_block(DMat<double> U, DMat<double> T, int64_t n, double a
 // M_Bj-orthonormal to rounding and the expansion above holds to rounding.
 void EngineImpl::spectral_decompose(hipStream_t st) {
   if (spec_valid) return;
-  if (!P->m_diag) throw Error(ST_EINVAL, "the spectral interior path needs a diagonal M");
   timer.begin(st, 6);
   spec_f_valid = false;
   work1.alloc(sizeof(double) * 2 * p * D);
-  double* md = work1.as<double>();
-  double* mis = md + p * D;
-  k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, dj.as<int32_t>(), Bg.view(), md, mis);
-  RFD_CHECK_LAUNCH();
-  double mmin = 1e300;
-  for (double v : M->val) mmin = std::min(mmin, v > 0 ? v : 1e300);
-  // padding rows carry a value above the whole spectrum (||B|| / min M <= normA / mmin)
-  const double big = 4.0 * normA / std::max(mmin, 1e-300) + 1.0;
+  double* md = work1.as<double>();   // diag(M_B), or sqrt(u) of M_B = L U
+  double* mis = md + p * D;          // its inverse square roots, or 1 / sqrt(u)
   work2.alloc(sizeof(double) * D * D * p);
   DMat<double> C{work2.as<double>(), nullptr, D, D * D};
   fill<double>(st, C, D, D, p, 0.0);
-  k_expand_scaled<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), mis, big);
-  RFD_CHECK_LAUNCH();
+  double big;
+  if (P->m_diag) {
+    k_mdiag<<<dim3(grid1(D), p), 256, 0, st>>>(D, dj.as<int32_t>(), Bg.view(), md, mis);
+    RFD_CHECK_LAUNCH();
+    double mmin = 1e300;
+    for (double v : M->val) mmin = std::min(mmin, v > 0 ? v : 1e300);
+    // padding rows carry a value above the whole spectrum (||B|| / min M <= normA / mmin)
+    big = 4.0 * normA / std::max(mmin, 1e-300) + 1.0;
+    k_expand_scaled<<<dim3(grid1(D), p), 256, 0, st>>>(C, D, dj.as<int32_t>(), Bg.view(), mis,
+                                                       big);
+    RFD_CHECK_LAUNCH();
+  } else {
+    // standard form G^{-1} B G^{-T} with M_B = G G^T
+    big = mb_standard_form(st, C, md, mis, 0.0);
+  }
   DE = std::max<int64_t>(P->d_max, 1);
   sy_tridiag(st, C, DE, p, tw_v);
   std::vector<int> lo(p, 0), num(p, (int)DE);
@@ -980,9 +1031,18 @@ void EngineImpl::spectral_decompose(hipStream_t st) {
   }
   spec_orth = dev;
   gbuf.release();
-  // V = M^{-1/2} U
-  k_scale_rows<<<dim3(grid1(D * D), p), 256, 0, st>>>(U, D, D, mis, D);
-  RFD_CHECK_LAUNCH();
+  if (P->m_diag) {
+    // V = M^{-1/2} U
+    k_scale_rows<<<dim3(grid1(D * D), p), 256, 0, st>>>(U, D, D, mis, D);
+    RFD_CHECK_LAUNCH();
+  } else {
+    // V = G^{-T} U = U_M^{-1} diag(u)^{1/2} U (U_M: the upper factor of M_B)
+    k_scale_rows<<<dim3(grid1(D * D), p), 256, 0, st>>>(U, D, D, md, D);
+    RFD_CHECK_LAUNCH();
+    DMat<double> F{Mlu.as<double>(), nullptr, D, D * D};
+    DMat<double> Fi{Mluinv.as<double>(), nullptr, NB, NB * 2 * D};
+    lu_solve<double>(st, F, Fi, nullptr, D, U, D, p, 2);
+  }
   timer.end(st);
   RFD_HIP(hipStreamSynchronize(st));
   spec_valid = true;
@@ -1051,17 +1111,21 @@ void EngineImpl::spectral_schur(hipStream_t st, int pole0, int np, DMat<double> 
   Shifts z{zeta.as<double>()};
   DMat<double> V{Vs.as<double>(), nullptr, D, D * D};
   const int64_t fs = D * SJ * (int64_t)p;
+  // F = V^T Ehat, and FM = V^T Mhat_E when M couples interiors to the
+  // interface (then Ehat_zeta = Ehat - zeta Mhat_E, so V^T Ehat_zeta = F - zeta FM)
+  const bool me = !P->m_e_zero;
   if (!spec_f_valid) {
     DevBuf& eb = Gsp;
-    eb.alloc(2 * sizeof(double) * fs);
-    DMat<double> E{eb.as<double>(), eb.as<double>() + fs, D, D * SJ};
-    fill<double>(st, E, D, SJ, p, 0.0);
-    // Ehat_zeta = Ehat - zeta M_E = Ehat for a diagonal M: any pole gives it
-    expand_rhs<double>(st, E, p, 1, 0, dj.as<int32_t>(), Eg.view(), z);
-    Fs.alloc(sizeof(double) * fs);
-    DMat<double> F{Fs.as<double>(), nullptr, D, D * SJ};
-    E.im = nullptr;
-    gemm<double>(st, true, false, D, SJ, D, 1.0, V, E, 0.0, F, p);
+    eb.alloc(sizeof(double) * fs);
+    DMat<double> E{eb.as<double>(), nullptr, D, D * SJ};
+    Fs.alloc(sizeof(double) * fs * (me ? 2 : 1));
+    for (int w = 0; w < (me ? 2 : 1); ++w) {
+      fill<double>(st, E, D, SJ, p, 0.0);
+      k_expand_e<<<dim3(grid1(D), p), 256, 0, st>>>(E, dj.as<int32_t>(), Eg.view(), w);
+      RFD_CHECK_LAUNCH();
+      DMat<double> F{Fs.as<double>() + w * fs, nullptr, D, D * SJ};
+      gemm<double>(st, true, false, D, SJ, D, 1.0, V, E, 0.0, F, p);
+    }
     RFD_HIP(hipStreamSynchronize(st));
     eb.release();
     spec_f_valid = true;
@@ -1073,8 +1137,14 @@ void EngineImpl::spectral_schur(hipStream_t st, int pole0, int np, DMat<double> 
   DMat<double> F{Fs.as<double>(), nullptr, D, D * SJ};
   DMat<double> Br{Fzm.re, nullptr, D, D * SJ}, Bi{Fzm.im, nullptr, D, D * SJ};
   for (int q = 0; q < np; ++q) {
-    k_spec_scale<<<dim3(grid1(D), col_groups(SJ), (unsigned)p), 256, 0, st>>>(
-        Fzm, F, D, DE, SJ, p, pole0 + q, lam_s.as<double>(), z);
+    if (me) {
+      DMat<double> FM{Fs.as<double>() + fs, nullptr, D, D * SJ};
+      k_spec_scale2<<<dim3(grid1(D), col_groups(SJ), (unsigned)p), 256, 0, st>>>(
+          Fzm, F, FM, D, DE, SJ, pole0 + q, lam_s.as<double>(), z);
+    } else {
+      k_spec_scale<<<dim3(grid1(D), col_groups(SJ), (unsigned)p), 256, 0, st>>>(
+          Fzm, F, D, DE, SJ, p, pole0 + q, lam_s.as<double>(), z);
+    }
     RFD_CHECK_LAUNCH();
     const int64_t off = (int64_t)q * p * X.bs;
     DMat<double> Cr{X.re + off, nullptr, X.ld, X.bs}, Ci{X.im + off, nullptr, X.ld, X.bs};

@@ -15,6 +15,8 @@ Same seeded inputs on both sides; the checks:
     gives each solve the results of a fresh LU-path pencil (relative 1e-12);
   * inertia counts and spectrum slices in the spectral mode;
   * the documented errors.
+Cases include a non-diagonal M that couples the interiors to the interface
+(dense and two-level S).
 """
 import dataclasses
 
@@ -48,6 +50,12 @@ CASES = {
                                  psi=4, mass_kind="random", cfg_id=64), False),
     "kfield_identity": (lambda: W.tiny(N=14, P=2, nev=5, n_c=4, m=12, steps=2, nev_b=8, psi=4,
                                        kfield=True, cfg_id=65), False),
+    # non-diagonal M coupling the interiors to the interface (standard form of
+    # (B_j, M_Bj), V^T Ehat_zeta = V^T Ehat - zeta V^T Mhat_E, Gamma levels)
+    "coupled_p9": (lambda: W.tiny(N=27, P=3, nev=6, n_c=4, m=16, steps=1, nev_b=6, psi=2,
+                                  mass_kind="coupled", cfg_id=49), False),
+    "coupled_two_level": (lambda: W.tiny(N=41, P=4, nev=17, n_c=8, m=40, steps=2, nev_b=12,
+                                         psi=5, mass_kind="coupled", cfg_id=51), True),
 }
 _cache = {}
 
@@ -189,12 +197,22 @@ def test_interior_solver_errors():
         assert e.value.code == 1
     finally:
         P.close()
-    cm = W.tiny(N=11, P=2, nev=6, n_c=4, steps=2, nev_b=8, psi=3, mass_kind="coupled")
-    P = R.Pencil(cm.A, cm.M)
+    # a block of M that is not positive definite: RFD_EBREAKDOWN from the
+    # decomposition (two interior nodes coupled by 2 against unit diagonals)
+    import scipy.sparse as sp
+    cm = W.tiny(N=13, P=2, nev=6, n_c=4, m=8, steps=1, nev_b=4, psi=2, mass_kind="coupled",
+                cfg_id=54)
+    Mi = sp.lil_matrix(cm.M)
+    i, k = (int(x) for x in np.flatnonzero(cm.part == 0)[[3, 17]])
+    Mi[i, k] = Mi[k, i] = 2.0
+    torch = _torch()
+    P = R.Pencil(cm.A, sp.csr_matrix(Mi))
     try:
         P.set_partition(cm.part)
+        P.set_interior_solver(R.RFD_INTERIOR_SPECTRAL)
+        P.set_interval_and_poles(cm.alpha, cm.beta, cm.n_c, R.RFD_RULE_GAUSS)
         with pytest.raises(R.RfdError) as e:
-            P.set_interior_solver(R.RFD_INTERIOR_SPECTRAL)
-        assert e.value.code == 1
+            P.filter_interface(_dev(torch, cm.Y0), cm.steps)
+        assert e.value.code == 3 and "positive definite" in str(e.value)
     finally:
         P.close()
