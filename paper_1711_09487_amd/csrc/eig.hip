@@ -14,9 +14,32 @@ namespace rfd {
 constexpr double EPS = 2.220446049250313e-16;
 constexpr double SAFMIN = 2.2250738585072014e-308;
 
+// v + (v moved across lanes by the DPP control CTRL, in the rows of 16 lanes
+// that ROWS selects; other lanes add 0)
+template <int CTRL, int ROWS>
+__device__ inline double dpp_add(double v) {
+  const uint64_t w = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)w, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(w >> 32), CTRL, ROWS, 0xf, false);
+  return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active), the same value in
+// every lane: pairs and quads by quad permutations, 8 and 16 lanes by the
+// half-row and row mirrors, then row sums carried into rows 1 and 3 and row
+// 3 completed from lane 31; lane 63 holds the total.  Data-parallel moves
+// only, no round trip through the LDS crossbar.
 __device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+  v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+  const uint64_t w = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)w, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(w >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __device__ inline double block_sum256(double v, double* red) {
@@ -204,70 +227,83 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
 // block T = A[j1:n, j1:n] (j1 = j + 1) from its lower triangle.  Tiles of
 // 64 x 64 are anchored at jb (j1, or j1 rounded down to even when the
 // columns allow 16-byte loads; rows and columns below j1 are masked).
-// Workgroup g < ntile owns lower tile (I, J), I >= J, numbered row by row:
-// it writes T_IJ v_J (rows of block I) to slot J and T_IJ^T v_I (rows of
-// block J) to slot I + 1; a diagonal tile gives its strict lower part to
+// Workgroup g < ntile owns lower tile (I, J), I >= J, of the nbt x nbt tile
+// grid: it writes T_IJ v_J (rows of block I) to slot J and T_IJ^T v_I (rows
+// of block J) to slot I + 1; a diagonal tile gives its strict lower part to
 // slot I and its lower part with the diagonal to slot I + 1.  Every row of
 // block R thus gets one value in each slot 0 .. nbt, and p = their sum.  The
-// workgroup's share of p^T v goes to ptvp[g].  Within a tile, each wave owns
-// 16 columns and each half-wave one column per step, two rows per lane.
-// The reflector is v = e_j1 + scale u with u the entries of column j below
-// row j1, so the loads of u and of the tile do not wait for scale.
+// workgroup's share of p^T v goes to ptvp[g].  Tiles are numbered column by
+// column, backwards for every other column j: a mat-vec starts on the tiles
+// the previous one read last, which the caches still hold.  Within a tile,
+// each wave owns 16 columns and each half-wave one column per step, two rows
+// per lane.  The reflector is v = e_j1 + scale u with u the entries of column
+// j below row j1, so the loads of u and of the tile do not wait for scale;
+// every load of a workgroup is issued before its first wait.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int64_t j, int c,
                                                   double* vw, double* ev, double* tauv,
                                                   const double* acol, const double* sq, int nsq,
                                                   int64_t sqs, int64_t jb, int ntile, double* red,
                                                   double* pt, int64_t pts, double* ptvp,
-                                                  int64_t ptvs) {
+                                                  int64_t ptvs, int nbt, int rev) {
   __shared__ double hh[4];
   __shared__ double rsl[8][TRI_TB];
   __shared__ double cdl[TRI_TB];
+  __shared__ double urow[TRI_TB], ucol[TRI_TB];
   __shared__ double rs[8];
   const int b = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int g = (int)blockIdx.x;
   DMat<double> a = A.item(b);
   const double* ac = acol + (int64_t)b * n;
   const int64_t j1 = j + 1;
-  auto uval = [&](int64_t r) -> double { return (r > j1 && r < n) ? ac[r] : 0.0; };
-  // tile coordinates (row-major lower tiles: g = I (I + 1) / 2 + J)
+  // tile coordinates: lower tiles numbered column by column (column J starts
+  // at J nbt - J (J - 1) / 2), backwards when rev
   int I = 0, J = 0;
   const bool tile = g < ntile;
   if (tile) {
-    I = (int)((sqrt(8.0 * (double)g + 1.0) - 1.0) * 0.5);
-    while ((I + 1) * (I + 2) / 2 <= g) ++I;
-    while (I * (I + 1) / 2 > g) --I;
-    J = g - I * (I + 1) / 2;
+    const int gg = rev ? ntile - 1 - g : g;
+    auto off = [&](int cj) { return cj * nbt - cj * (cj - 1) / 2; };
+    const double q = 2.0 * nbt + 1.0;
+    J = (int)((q - sqrt(q * q - 8.0 * (double)gg)) * 0.5);
+    J = J < 0 ? 0 : (J > nbt - 1 ? nbt - 1 : J);
+    while (J + 1 <= nbt - 1 && off(J + 1) <= gg) ++J;
+    while (J > 0 && off(J) > gg) --J;
+    I = J + (gg - off(J));
   }
   const int64_t rb = jb + (int64_t)TRI_TB * I, cb = jb + (int64_t)TRI_TB * J;
   const int h = lane >> 5;
   const int64_t r0 = rb + 2 * (lane & 31);
-  // all global loads first
+  // all global loads first, with no wait between them: the tile, the
+  // entries of u at the tile's rows and columns, the partial sums of
+  // squares (four per lane of wave 0; longer columns loop over the rest)
   double2 x[8];
-  double uq[8];
-  double u0 = 0.0, u1 = 0.0, ur = 0.0, uc = 0.0;
   double dot = 0.0, y1 = 0.0;
+  // u at row r: an unconditional load from a clamped index, then a select
   if (tile) {
+    // a tile inside the trailing block and the matrix takes unmasked loads
+    // at a fixed column stride; the others mask columns before j1 or past n
+    // and rows past n
+    const bool full = VEC && cb >= j1 && cb + TRI_TB <= n && rb + TRI_TB <= n;
+    if (full) {
+      const double* p0 = a.re + (cb + 16 * wave + h) * a.ld + r0;
+      const int64_t cs = 2 * a.ld;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int64_t q = cb + 16 * wave + 2 * i + h;
-      const bool qok = q >= j1 && q < n;
-      const double* colp = a.re + (qok ? q : j1) * a.ld;
-      double2 v2 = make_double2(0.0, 0.0);
-      if (VEC && qok && r0 + 1 < n) {
-        v2 = *reinterpret_cast<const double2*>(colp + r0);
-      } else {
-        if (qok && r0 < n) v2.x = colp[r0];
-        if (qok && r0 + 1 < n) v2.y = colp[r0 + 1];
+      for (int i = 0; i < 8; ++i) x[i] = *reinterpret_cast<const double2*>(p0 + i * cs);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t q = cb + 16 * wave + 2 * i + h;
+        const bool qok = q >= j1 && q < n;
+        const double* colp = a.re + (qok ? q : j1) * a.ld;
+        double2 v2 = make_double2(0.0, 0.0);
+        if (VEC && qok && r0 + 1 < n) {
+          v2 = *reinterpret_cast<const double2*>(colp + r0);
+        } else {
+          if (qok && r0 < n) v2.x = colp[r0];
+          if (qok && r0 + 1 < n) v2.y = colp[r0 + 1];
+        }
+        x[i] = v2;
       }
-      x[i] = v2;
-      uq[i] = uval(q);
-    }
-    u0 = uval(r0);
-    u1 = uval(r0 + 1);
-    if (t < TRI_TB) {
-      ur = uval(rb + t);
-      uc = uval(cb + t);
     }
   } else {
     // W[:, e]^T u (e < c) or V[:, e - c]^T u, and the entries at row j1
@@ -287,9 +323,24 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     }
     if (t == 0) y1 = y[j1];
   }
+  // every lane loads (no branch, so no wait before the loads are all
+  // issued); the masks are applied once the values are used
+  const int64_t ru = rb + (t & (TRI_TB - 1)), cu = cb + (t & (TRI_TB - 1));
+  const double ua = ac[ru < n ? ru : n - 1], ub = ac[cu < n ? cu : n - 1];
+  const double* sqb = sq + (int64_t)b * sqs;
+  double sqv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sqv[k] = sqb[min(lane + 64 * k, nsq - 1)];
+  if (t < TRI_TB) {
+    urow[t] = (ru > j1 && ru < n) ? ua : 0.0;
+    ucol[t] = (cu > j1 && cu < n) ? ub : 0.0;
+  }
   double s2 = 0.0;
-  if (wave == 0)
-    for (int i = lane; i < nsq; i += 64) s2 += sq[(int64_t)b * sqs + i];
+  if (wave == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s2 += lane + 64 * k < nsq ? sqv[k] : 0.0;
+    for (int i = lane + 256; i < nsq; i += 64) s2 += sqb[i];
+  }
   const double alpha = ac[j1];
   if (wave == 0) {
     s2 = wave_sum(s2);
@@ -320,21 +371,52 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     return;
   }
   auto vof = [&](int64_t r, double u) -> double { return r == j1 ? 1.0 : scale * u; };
-  const double vi0 = vof(r0, u0), vi1 = vof(r0 + 1, u1);
+  // 32-bit tile-local indices against uniform thresholds: local row lr is
+  // row rb + lr, local column qc column cb + qc
+  auto clampi = [](int64_t v) { return (int)(v < -1 ? -1 : (v > 2 * TRI_TB ? 2 * TRI_TB : v)); };
+  const int lr = 2 * (lane & 31);
+  const int rfirst = clampi(j1 - rb);       // local rows >= rfirst are >= j1
+  const int cone = clampi(j1 - cb);         // local column of row / column j1
+  const int dq = (int)(rb - cb);            // r > q  <=>  lr - qc > -dq
+  const double vi0 = lr == rfirst ? 1.0 : scale * urow[lr];
+  const double vi1 = lr + 1 == rfirst ? 1.0 : scale * urow[lr + 1];
+  const double m0 = lr >= rfirst ? 1.0 : 0.0, m1 = lr + 1 >= rfirst ? 1.0 : 0.0;
   double rs0 = 0.0, rs1 = 0.0;
+  double cp[8];  // this lane's part of the column sums of its 8 columns
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int64_t q = cb + 16 * wave + 2 * i + h;
-    const double vq = vof(q, uq[i]);
+    const int qc = 16 * wave + 2 * i + h;
+    const double vq = qc == cone ? 1.0 : scale * ucol[qc];
     // the strict lower part feeds the row sums, the lower part with the
     // diagonal the column sums; rows below j1 are masked
-    const double x0 = (r0 >= j1) ? x[i].x : 0.0, x1 = (r0 + 1 >= j1) ? x[i].y : 0.0;
-    rs0 += (r0 > q ? x0 : 0.0) * vq;
-    rs1 += (r0 + 1 > q ? x1 : 0.0) * vq;
-    double cd = (r0 >= q ? x0 : 0.0) * vi0 + (r0 + 1 >= q ? x1 : 0.0) * vi1;
+    const double x0 = m0 * x[i].x, x1 = m1 * x[i].y;
+    const int d0 = lr - qc + dq;              // (rb + lr) - (cb + qc)
+    rs0 += (d0 > 0 ? x0 : 0.0) * vq;
+    rs1 += (d0 + 1 > 0 ? x1 : 0.0) * vq;
+    cp[i] = (d0 >= 0 ? x0 : 0.0) * vi0 + (d0 + 1 >= 0 ? x1 : 0.0) * vi1;
+  }
+  // column sums over the 32 lanes of each half-wave by halving exchanges:
+  // after the exchanges across lane bits 4, 3 and 2 a lane holds one column,
+  // i = 4 b4 + 2 b3 + b2, summed over 8 lanes; bits 1 and 0 finish the sum
+  {
+    const int l = lane & 31;
+    const bool b4 = l & 16, b3 = l & 8, b2 = l & 4;
+    double d4[4];
 #pragma unroll
-    for (int o = 16; o > 0; o >>= 1) cd += __shfl_xor(cd, o, 64);
-    if ((lane & 31) == 0) cdl[16 * wave + 2 * i + h] = cd;
+    for (int k = 0; k < 4; ++k) {
+      const double snd = b4 ? cp[k] : cp[k + 4];
+      d4[k] = (b4 ? cp[k + 4] : cp[k]) + __shfl_xor(snd, 16, 64);
+    }
+    double d2[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double snd = b3 ? d4[k] : d4[k + 2];
+      d2[k] = (b3 ? d4[k + 2] : d4[k]) + __shfl_xor(snd, 8, 64);
+    }
+    double f = (b2 ? d2[1] : d2[0]) + __shfl_xor(b2 ? d2[0] : d2[1], 4, 64);
+    f += __shfl_xor(f, 2, 64);
+    f += __shfl_xor(f, 1, 64);
+    if ((l & 3) == 0) cdl[16 * wave + 2 * (l >> 2) + h] = f;
   }
   rsl[2 * wave + h][2 * (lane & 31)] = rs0;
   rsl[2 * wave + h][2 * (lane & 31) + 1] = rs1;
@@ -342,7 +424,7 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     // the reflector: V[:, c] (both copies) and column j of A (rows >= j + 2)
     const int64_t r = rb + t;
     if (r >= j1 && r < n) {
-      const double v = vof(r, ur);
+      const double v = vof(r, urow[t]);
       double* V = vw + (int64_t)b * n * 3 * TRI_NB;
       V[r + (int64_t)c * n] = v;
       V[r + (int64_t)(2 * TRI_NB + c) * n] = v;
@@ -360,7 +442,7 @@ __global__ __launch_bounds__(256) void k_tri_symv(DMat<double> A, int64_t n, int
     const int64_t r = rb + t, q = cb + t;
     if (r < n) pb[(int64_t)J * n + r] = rsum;
     if (q < n) pb[(int64_t)(I + 1) * n + q] = cd;
-    share = vof(r, ur) * rsum + vof(q, uc) * cd;
+    share = vof(r, urow[t]) * rsum + vof(q, ucol[t]) * cd;
   }
   if (wave == 0) {
     share = wave_sum(share);
@@ -421,7 +503,7 @@ static void tridiag_launches(hipStream_t s, DMat<double> A, int64_t n, int batch
                             (const double*)w.sq.as<double>(),
                             (int)((n - j + COL_R - 1) / COL_R), sqs, anchor(j + 1), ntile,
                             w.red.as<double>(), w.pt.as<double>(), pts, w.ptvp.as<double>(),
-                            ptvs);
+                            ptvs, nb, (int)(j & 1));
       RFD_CHECK_LAUNCH();
     }
     // finish W's last column, then the lower triangle of the trailing block
