@@ -100,6 +100,7 @@ constexpr int COL_R = 64;  // rows per workgroup of k_tri_col (4 lanes per row)
 // slots of p congruent to k mod 4.  c = panel position of column j; upd = 0
 // only finishes W[:, c-1] (end of panel).  nslot / ntp: slots of p and
 // partial sums of p^T v left by the previous column's k_tri_symv.
+template <int LB>
 __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int64_t j, int c,
                                                  int upd, double* vw, const double* tauv,
                                                  const double* pt, int64_t pts, int nslot,
@@ -127,28 +128,37 @@ __global__ __launch_bounds__(256) void k_tri_col(DMat<double> A, int64_t n, int6
   }
   double pr = 0.0, ps = 0.0, pjp = 0.0, tp = 0.0;
   if (c >= 1) {
-    // (blocks of independent loads: up to 64 slots and 2048 partial sums
-    // in one round)
+    // (blocks of LB independent loads per lane, one wait each: up to 4 LB
+    // slots and 256 LB partial sums per round; every round is a memory round
+    // trip, so a single large matrix, whose few workgroups leave registers to
+    // spare, takes LB = 32)
     if (act) {
-      for (int s0 = k; s0 < nslot; s0 += 64) {
-        double pv[16];
+      for (int s0 = k; s0 < nslot; s0 += 4 * LB) {
+        double pv[LB];
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < LB; ++i)
           pv[i] = s0 + 4 * i < nslot ? p[r + (int64_t)(s0 + 4 * i) * n] : 0.0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) pr += pv[i];
+        for (int i = 0; i < LB; ++i) pr += pv[i];
       }
     }
     const double* pp = ptvp + (int64_t)b * ptvs;
-    for (int i0 = t; i0 < ntp; i0 += 2048) {
-      double pv[8];
+    for (int i0 = t; i0 < ntp; i0 += 256 * LB) {
+      double pv[LB];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) pv[i] = i0 + 256 * i < ntp ? pp[i0 + 256 * i] : 0.0;
+      for (int i = 0; i < LB; ++i) pv[i] = i0 + 256 * i < ntp ? pp[i0 + 256 * i] : 0.0;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) ps += pv[i];
+      for (int i = 0; i < LB; ++i) ps += pv[i];
     }
     if (wave == 1)
-      for (int s = lane; s < nslot; s += 64) pjp += p[j + (int64_t)s * n];
+      for (int s0 = lane; s0 < nslot; s0 += 256) {
+        double pv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          pv[i] = s0 + 64 * i < nslot ? p[j + (int64_t)(s0 + 64 * i) * n] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pjp += pv[i];
+      }
     tp = tauv[(int64_t)b * n + j - 1];
   }
   const double ajr = (act && upd && k == 0) ? a.re[r + j * a.ld] : 0.0;
@@ -477,10 +487,10 @@ static void tridiag_launches(hipStream_t s, DMat<double> A, int64_t n, int batch
     // the previous column's mat-vec covered rows from j
     const int nb = c >= 1 ? nblk(j) : 0;
     dim3 g1((unsigned)((n - j + COL_R - 1) / COL_R), batch);
-    k_tri_col<<<g1, 256, 0, s>>>(A, n, j, c, upd, vw, w.tau.as<double>(), w.pt.as<double>(), pts,
-                                 nb + 1, w.red.as<double>(), w.acol.as<double>(),
-                                 w.d.as<double>(), w.sq.as<double>(), sqs, w.ptvp.as<double>(),
-                                 ptvs, nb * (nb + 1) / 2);
+    (batch == 1 ? k_tri_col<32> : k_tri_col<16>)<<<g1, 256, 0, s>>>(
+        A, n, j, c, upd, vw, w.tau.as<double>(), w.pt.as<double>(), pts, nb + 1,
+        w.red.as<double>(), w.acol.as<double>(), w.d.as<double>(), w.sq.as<double>(), sqs,
+        w.ptvp.as<double>(), ptvs, nb * (nb + 1) / 2);
     RFD_CHECK_LAUNCH();
   };
   const int64_t nred = n - 2;  // columns that get a reflector
