@@ -272,7 +272,24 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
     pr = part + ((int64_t)(sk * batch + b) * NP) * M * N;
     pi = pr + (NP - 1) * M * N;
   }
-  auto put = [&](int64_t i, int64_t j, T vr, T vi) {
+  // this lane's outputs: RE per MFMA block
+  constexpr int RE = F32 ? 16 : 4;
+  auto ij = [&](int x, int y, int r, int64_t& i, int64_t& j) {
+    if constexpr (F32) {
+      i = m0 + wm + 32 * x + (lane & 31);
+      j = n0 + wn + 32 * y + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    } else {
+      i = m0 + wm + 16 * x + (lane & 15);
+      j = n0 + wn + 16 * y + (lane >> 4) + 4 * r;
+    }
+  };
+  // beta C in rounds of CH elements per lane (all of them in FP64; 8 in
+  // FP32, whose larger accumulator sets leave fewer registers): a round's
+  // loads are all issued before the first is used, from offsets clamped into
+  // C.  (Loads in per-element branches would each wait in turn, and the
+  // wait also covers every store issued before it.)
+  const bool use_c = splits == 1 && beta != T(0);
+  auto put = [&](int64_t i, int64_t j, T vr, T vi, T cr, T ci) {
     if (i >= M || j >= N) return;
     if (splits > 1) {
       pr[i + j * M] = alpha * vr;
@@ -281,36 +298,46 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, T
     }
     const int64_t off = i + j * C.ld;
     T outr = alpha * vr, outi = alpha * vi;
-    if (beta != T(0)) {
-      outr += beta * C.re[off];
-      if constexpr (CPLX) outi += beta * C.im[off];
+    if (use_c) {
+      outr += beta * cr;
+      if constexpr (CPLX) outi += beta * ci;
     }
     C.re[off] = outr;
     if constexpr (CPLX) C.im[off] = outi;
   };
+  constexpr int E = XM * XN * RE;
+  constexpr int CH = F32 ? 8 : E;
+  static_assert(E % CH == 0, "rounds of C loads do not divide the outputs");
 #pragma unroll
-  for (int x = 0; x < XM; ++x)
+  for (int e0 = 0; e0 < E; e0 += CH) {
+    T cr[CH], ci[CH];
+    if (use_c) {
 #pragma unroll
-    for (int y = 0; y < XN; ++y) {
-      if constexpr (F32) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int64_t i = m0 + wm + 32 * x + (lane & 31);
-          const int64_t j = n0 + wn + 32 * y + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          if constexpr (CPLX)
-            put(i, j, fr[x][y][r] - fi[x][y][r], (fs[x][y][r] - fr[x][y][r]) - fi[x][y][r]);
-          else
-            put(i, j, fr[x][y][r], 0.0f);
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = m0 + wm + 16 * x + (lane & 15);
-          const int64_t j = n0 + wn + 16 * y + (lane >> 4) + 4 * r;
-          put(i, j, dr[x][y][r], CPLX ? di[x][y][r] : 0.0);
-        }
+      for (int u = 0; u < CH; ++u) {
+        const int e = e0 + u, r = e % RE, y = (e / RE) % XN, x = e / (RE * XN);
+        int64_t i, j;
+        ij(x, y, r, i, j);
+        const int64_t off = (i < M && j < N) ? i + j * C.ld : 0;
+        cr[u] = C.re[off];
+        ci[u] = CPLX ? C.im[off] : T(0);
       }
     }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = e0 + u, r = e % RE, y = (e / RE) % XN, x = e / (RE * XN);
+      int64_t i, j;
+      ij(x, y, r, i, j);
+      if constexpr (F32) {
+        if constexpr (CPLX)
+          put(i, j, fr[x][y][r] - fi[x][y][r], (fs[x][y][r] - fr[x][y][r]) - fi[x][y][r], cr[u],
+              ci[u]);
+        else
+          put(i, j, fr[x][y][r], 0.0f, cr[u], ci[u]);
+      } else {
+        put(i, j, dr[x][y][r], CPLX ? di[x][y][r] : 0.0, cr[u], ci[u]);
+      }
+    }
+  }
 }
 
 // Large FP64 products: real on 64 x 128 tiles (each of the 4 waves, 2 x 2,
@@ -441,6 +468,21 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
   // started at beta Re C, 0 and beta (Re C + Im C)
   constexpr int NA = CPLX ? 3 : 1;
   doublex4 acc[NA][XM][XN];
+  // (the loads of C are all issued before the first is used, from offsets
+  // clamped into C: loads in per-element branches would each wait in turn)
+  if (use_c) {
+#pragma unroll
+    for (int x = 0; x < XM; ++x)
+#pragma unroll
+      for (int y = 0; y < XN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = il + 16 * x, j = jl + 16 * y + 4 * r;
+          const int64_t off = (i < M && j < N) ? i + j * C.ld : 0;
+          acc[0][x][y][r] = C.re[off];
+          if constexpr (CPLX) acc[1][x][y][r] = C.im[off];
+        }
+  }
 #pragma unroll
   for (int x = 0; x < XM; ++x)
 #pragma unroll
@@ -449,10 +491,10 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
       for (int r = 0; r < 4; ++r) {
         const int64_t i = il + 16 * x, j = jl + 16 * y + 4 * r;
         const bool in = use_c && i < M && j < N;
-        const double cr = in ? beta * C.re[i + j * C.ld] : 0.0;
+        const double cr = in ? beta * acc[0][x][y][r] : 0.0;
         acc[0][x][y][r] = cr;
         if constexpr (CPLX) {
-          const double ci = in ? beta * C.im[i + j * C.ld] : 0.0;
+          const double ci = in ? beta * acc[1][x][y][r] : 0.0;
           acc[1][x][y][r] = 0.0;
           acc[2][x][y][r] = cr + ci;
         }
