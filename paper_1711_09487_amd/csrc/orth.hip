@@ -105,10 +105,28 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
   // pivot: the unconsumed column of largest norm (lowest index on ties),
   // per thread, then across each wavefront by shuffles, then the four
   // wavefronts in order
+  // (loads in rounds of four per thread, all issued before the first is
+  // used, from clamped indices: a load per iteration would wait each time)
   double best = -1.0;
   int bi = m;
-  for (int q = t; q < m; q += blockDim.x)
-    if (!usc[q] && cnc[q] > best) { best = cnc[q]; bi = q; }
+  for (int q0 = t; q0 < m; q0 += 4 * 256) {
+    double cv[4];
+    int uv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + 256 * u, qc = q < m ? q : m - 1;
+      cv[u] = cnc[qc];
+      uv[u] = usc[qc];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + 256 * u;
+      if (q < m && !uv[u] && cv[u] > best) {
+        best = cv[u];
+        bi = q;
+      }
+    }
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     const double ob = __shfl_xor(best, o, 64);
@@ -148,11 +166,26 @@ __global__ __launch_bounds__(256) void k_hqr_step(double* A, int64_t lda, int64_
   const bool piv_col = c == P;
   const double x0 = ap[j];
   const double acj = piv_col ? 0.0 : ac[j];
+  // (rounds of U16 rows per thread, loads from clamped indices all issued
+  // before the first is used)
+  constexpr int U16 = 16;
   double s2 = 0, e = 0;
-  for (int64_t i = j + t; i < rows; i += blockDim.x) {
-    const double x = ap[i];
-    s2 += x * x;
-    if (!piv_col && i > j) e += x * ac[i];
+  for (int64_t i0 = j + t; i0 < rows; i0 += 256 * U16) {
+    double xv[U16], av[U16];
+#pragma unroll
+    for (int u = 0; u < U16; ++u) {
+      const int64_t i = i0 + 256 * u, ic = i < rows ? i : j;
+      xv[u] = ap[ic];
+      av[u] = piv_col ? 0.0 : ac[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < U16; ++u) {
+      const int64_t i = i0 + 256 * u;
+      if (i < rows) {
+        s2 += xv[u] * xv[u];
+        if (i > j) e += xv[u] * av[u];
+      }
+    }
   }
   block_sum256x2(s2, e, red);
   const double nrm = sqrt(s2);
