@@ -100,6 +100,68 @@ Engine::Engine(const Csr& A, const Csr& M, const Partition& P) : d_(new EngineIm
   upload_pair(e.Bg, bl);
   upload_pair(e.Eg, el);
   upload_pair(e.Etg, etl);
+  {
+    // renumbered blocks: new row = pad + position among [rows Ehat_j does not
+    // touch, rows it touches] (each in ascending order); pad rows carry a
+    // unit diagonal
+    std::vector<PairCsr> b2(e.p), e2(e.p), et2(e.p);
+    int64_t smax = 0;
+    for (int j = 0; j < e.p; ++j) {
+      const PairCsr &B = P.Bloc[j], &E = P.Eloc[j], &Et = P.EtLoc[j];
+      const int64_t d = B.rows, pad = e.D - d;
+      std::vector<int32_t> perm, pinv(d);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int64_t r = 0; r < d; ++r)
+          if ((E.ptr[r + 1] > E.ptr[r]) == (pass == 1)) perm.push_back((int32_t)r);
+      for (int64_t q = 0; q < d; ++q) pinv[perm[q]] = (int32_t)(pad + q);
+      int64_t touched = 0;
+      for (int64_t r = 0; r < d; ++r) touched += E.ptr[r + 1] > E.ptr[r] ? 1 : 0;
+      smax = std::max(smax, touched);
+      PairCsr& b = b2[j];
+      PairCsr& ee = e2[j];
+      b.rows = b.cols = e.D;
+      ee.rows = e.D;
+      ee.cols = E.cols;
+      b.ptr.assign(1, 0);
+      ee.ptr.assign(1, 0);
+      for (int64_t q = 0; q < pad; ++q) {
+        b.idx.push_back((int32_t)q);
+        b.a.push_back(1.0);
+        b.m.push_back(0.0);
+        b.ptr.push_back((int64_t)b.idx.size());
+        ee.ptr.push_back((int64_t)ee.idx.size());
+      }
+      for (int64_t q = 0; q < d; ++q) {
+        const int32_t r = perm[q];
+        for (int64_t k = B.ptr[r]; k < B.ptr[r + 1]; ++k) {
+          b.idx.push_back(pinv[B.idx[k]]);
+          b.a.push_back(B.a[k]);
+          b.m.push_back(B.m[k]);
+        }
+        b.ptr.push_back((int64_t)b.idx.size());
+        for (int64_t k = E.ptr[r]; k < E.ptr[r + 1]; ++k) {
+          ee.idx.push_back(E.idx[k]);
+          ee.a.push_back(E.a[k]);
+          ee.m.push_back(E.m[k]);
+        }
+        ee.ptr.push_back((int64_t)ee.idx.size());
+      }
+      et2[j] = Et;
+      for (auto& c : et2[j].idx) c = pinv[c];
+      et2[j].cols = e.D;
+    }
+    e.TS = std::min<int64_t>(round_up(std::max<int64_t>(smax, 1), NB), e.D);
+    std::vector<const PairCsr*> b2p, e2p, et2p;
+    for (int j = 0; j < e.p; ++j) {
+      b2p.push_back(&b2[j]);
+      e2p.push_back(&e2[j]);
+      et2p.push_back(&et2[j]);
+    }
+    upload_pair(e.Bg2, b2p);
+    upload_pair(e.Eg2, e2p);
+    upload_pair(e.Etg2, et2p);
+    upload(e.dj2, std::vector<int32_t>((size_t)e.p, (int32_t)e.D));
+  }
   upload_pair(e.Cg, {&P.Cloc});
   upload(e.dj, dj);
   upload(e.sj, sj);
@@ -173,7 +235,7 @@ void Engine::set_precision(int mode, double tol, int sweeps) {
 
 int64_t Engine::estimate_bytes(int mode, int n_c, int m, int steps, int nev_b, int psi) const {
   const EngineImpl& e = *d_;
-  const bool b32 = mode != 0;                                                   // interior
+  const bool b32 = e.b_fp32(mode);                                              // interior
   const bool f32 = e.s_precision(mode, std::min<int64_t>(e.s, (int64_t)steps * m)) == 1;  // S
   const int64_t es = f32 ? 4 : 8, D = e.D, SP = e.SP, SJ = e.SJ, p = e.p, n = e.n;
   const int64_t bs = b32 ? 4 : 8;
@@ -453,8 +515,8 @@ int EngineImpl::s_precision(int md, int64_t c) const {
 // Poles processed together for the interior part: as many as fit the budget.
 int EngineImpl::pole_chunk() const {
   const int64_t items_bytes_per_pole =
-      (int64_t)p * (D * D * (mode != 0 ? 8 : 16) + NB * 2 * D * (mode != 0 ? 8 : 16) +
-                    D * SJ * (mode != 0 ? 16 + 16 + 8 + 8 : 16));
+      (int64_t)p * (D * D * (b_fp32(mode) ? 8 : 16) + NB * 2 * D * (b_fp32(mode) ? 8 : 16) +
+                    D * SJ * (b_fp32(mode) ? 16 + 16 + 8 + 8 : 16));
   const int64_t budget = int64_t(48) << 30;
   int c = (int)std::max<int64_t>(1, budget / std::max<int64_t>(items_bytes_per_pole, 1));
   return std::min(c, poles.n_c);
@@ -512,7 +574,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
   }
   const int64_t kk = D * D * (int64_t)items_max, ki = (int64_t)NB * 2 * D * items_max,
                 xs = D * SJ * (int64_t)items_max;
-  const bool fp32 = (mode != 0);            // the interior blocks
+  const bool fp32 = b_fp32(mode);           // the interior blocks
   s_mode = s_precision(mode, cols_hint);    // S
   const bool spectral = interior_solver == 1;
   if (spectral) {
@@ -570,32 +632,39 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
       max_sweeps_used = std::max(max_sweeps_used, sw);
       timer.end(st);
     } else {
+      // renumbered blocks: Ehat_j touches only the last TS rows, so
+      // Ehat_j^T K^{-1} Ehat_j = Ehat_t^T (L_tt U_tt)^{-1} Ehat_t with the
+      // trailing TS x TS blocks of the factors (those of K^{-1} are the
+      // inverses of theirs), and only those rows of X are solved for
       timer.begin(st, 0);
       DMat<double> K{K64.as<double>(), K64.as<double>() + kk, D, D * D};
       DMat<double> Ki{Kinv64.as<double>(), Kinv64.as<double>() + ki, NB, (int64_t)NB * 2 * D};
       fill<double>(st, K, D, D, items, 0.0);
-      expand_shifted<double>(st, K, D, p, np, l0, dj.as<int32_t>(), Bg.view(), z, false, 0.0);
+      expand_shifted<double>(st, K, D, p, np, l0, dj2.as<int32_t>(), Bg2.view(), z, false, 0.0);
       lu_nopiv<double>(st, K, D, items, Ki, flags.as<unsigned>(), 1e-300);
       timer.end(st);
       timer.begin(st, 1);
-      fill<double>(st, X, D, SJ, items, 0.0);
-      expand_rhs<double>(st, X, p, np, l0, dj.as<int32_t>(), Eg.view(), z);
-      lu_solve<double>(st, K, Ki, nullptr, D, X, SJ, items);
+      const int64_t t0 = D - TS;
+      fill<double>(st, X.sub(t0, 0), TS, SJ, items, 0.0);
+      expand_rhs<double>(st, X, p, np, l0, dj2.as<int32_t>(), Eg2.view(), z);
+      lu_solve<double>(st, K.sub(t0, t0), Ki.sub(0, 2 * t0), nullptr, TS, X.sub(t0, 0), SJ,
+                       items);
       timer.end(st);
     }
     timer.begin(st, 2);
+    // (X in the renumbered rows on the FP64 path)
+    const DevPairCsr et = (!spectral && !fp32) ? Etg2.view() : Etg.view();
     if (!two_level) {
       DMat<double> Sc = S.item(l0 - w0);
       for (size_t c = 0; c < colors_d.size(); ++c)
         schur_scatter(st, Sc, X, SJ, p, np, l0, colors_d[c].as<int32_t>(),
-                      (int)P->colors[c].size(), sj.as<int32_t>(), adj.as<int32_t>(), Etg.view(),
-                      z);
+                      (int)P->colors[c].size(), sj.as<int32_t>(), adj.as<int32_t>(), et, z);
     } else {
       const int64_t i0 = (int64_t)(l0 - w0) * tL;
       for (size_t c = 0; c < colors_d.size(); ++c)
         tree_scatter(st, Tg.item(i0), TgT.item(i0), Tt.item(l0 - w0), X, SJ, p, np, l0,
-                     colors_d[c].as<int32_t>(), (int)P->colors[c].size(), sj.as<int32_t>(),
-                     Etg.view(), tree, z);
+                     colors_d[c].as<int32_t>(), (int)P->colors[c].size(), sj.as<int32_t>(), et,
+                     tree, z);
     }
     timer.end(st);
   }
@@ -658,7 +727,7 @@ void EngineImpl::factor(hipStream_t st, int w0, int wn) {
 int EngineImpl::pole_window(int m) const {
   const int nc = poles.n_c;
   const bool f32 = s_precision(mode, cols_hint) == 1;  // S
-  const bool b32 = mode != 0;                           // the interior blocks
+  const bool b32 = b_fp32(mode);                        // the interior blocks
   const int64_t MP = round_up(std::max(m, 1), NB);
   const int64_t per_pole = tree.L > 0 ? tree_pole_bytes(MP, f32 ? 1 : 0)
                                        : 2 * SP * SP * (f32 ? 8 + 4 : 8) +
@@ -952,7 +1021,8 @@ int64_t Engine::inertia(hipStream_t st, double tau) {
       DMat<double> K{e.K64.as<double>(), e.K64.as<double>() + e.D * e.D * (int64_t)e.p, e.D,
                      e.D * e.D};
       if (!e.K64.p) throw Error(ST_ESTATE, "inertia: interior factors were released");
-      k_count_negative_pivots<<<dim3(grid1(e.D), e.p), 256, 0, st>>>(K, e.dj.as<int32_t>(), 0,
+      // (renumbered items: the pad rows' unit pivots add nothing)
+      k_count_negative_pivots<<<dim3(grid1(e.D), e.p), 256, 0, st>>>(K, e.dj2.as<int32_t>(), 0,
                                                                      e.D, e.p, c);
       RFD_CHECK_LAUNCH();
     }

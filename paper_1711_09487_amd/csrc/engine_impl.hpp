@@ -49,6 +49,20 @@ struct EngineImpl {
   // pencil and maps
   DevPairGroup Bg, Eg, Etg, Cg;
   DevBuf dj, sj, adj, order, ioff;
+  // The subdomain blocks with rows renumbered for the FP64 Schur solves:
+  // padding first (unit diagonal), then the rows that Ehat_j does not touch,
+  // then the TS-row trailing part that holds every row it touches, so that
+  // Ehat_j^T K_j^{-1} Ehat_j needs only the trailing blocks of K_j's factors.
+  // Items are D x D with all D rows active (dj2 = D).
+  DevPairGroup Bg2, Eg2, Etg2;
+  DevBuf dj2;
+  int64_t TS = 0;
+  bool trailing_pays() const { return 2 * TS <= D; }
+  // FP32 factors of the shifted interior blocks for precision mode md: always
+  // with md = 1; with md = 2 only when the trailing part is not small enough
+  // for the FP64 Schur solves to beat FP32 solves with refinement (the
+  // refinement needs the full solution, so it forgoes the trailing blocks)
+  bool b_fp32(int md) const { return md == 1 || (md == 2 && !trailing_pays()); }
   std::vector<DevBuf> colors_d;
   DevBuf Aptr, Aidx, Aval, Mptr, Midx, Mval;      // original numbering
   DevBuf Arptr, Aridx, Arval, Mrptr, Mridx, Mrval;  // reordered numbering (lazy)
