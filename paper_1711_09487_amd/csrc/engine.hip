@@ -151,6 +151,7 @@ Engine::Engine(const Csr& A, const Csr& M, const Partition& P) : d_(new EngineIm
       et2[j].cols = e.D;
     }
     e.TS = std::min<int64_t>(round_up(std::max<int64_t>(smax, 1), NB), e.D);
+    e.SJA = P.sj_max;
     std::vector<const PairCsr*> b2p, e2p, et2p;
     for (int j = 0; j < e.p; ++j) {
       b2p.push_back(&b2[j]);

@@ -57,11 +57,18 @@ struct EngineImpl {
   DevPairGroup Bg2, Eg2, Etg2;
   DevBuf dj2;
   int64_t TS = 0;
-  bool trailing_pays() const { return 2 * TS <= D; }
+  int64_t SJA = 0;  // largest interface adjacency of a subdomain (columns of Ehat_j)
+  // FP64 factors with Schur solves on the trailing blocks cost, per item and
+  // in complex multiply-adds, D^3 / 3 + TS^2 SJ; FP32 factors (half the
+  // time on the matrix cores) with refinement, whose solves need the full
+  // solution, about (D^3 / 3 + 2 D^2 SJ) / 2 (one correcting solve).  FP64
+  // pays when D^3 / 6 < SJ (D^2 - TS^2).
+  bool trailing_pays() const {
+    const double d = (double)D, t = (double)TS, c = (double)SJA;
+    return d * d * d / 6.0 < c * (d * d - t * t);
+  }
   // FP32 factors of the shifted interior blocks for precision mode md: always
-  // with md = 1; with md = 2 only when the trailing part is not small enough
-  // for the FP64 Schur solves to beat FP32 solves with refinement (the
-  // refinement needs the full solution, so it forgoes the trailing blocks)
+  // with md = 1; with md = 2 unless FP64 with trailing solves costs less
   bool b_fp32(int md) const { return md == 1 || (md == 2 && !trailing_pays()); }
   std::vector<DevBuf> colors_d;
   DevBuf Aptr, Aidx, Aval, Mptr, Midx, Mval;      // original numbering

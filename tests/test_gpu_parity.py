@@ -382,28 +382,39 @@ def test_mode_switch_refactors():
 
 
 def _trailing_rows(prob, nb=64):
-    """(D, TS): the padded subdomain size and the trailing part that holds
+    """(D, TS, SJ): the padded subdomain size, the trailing part that holds
     every interior row coupled to the interface (rows of Ehat_j), both
-    rounded up to the 64-row tiles, as the library sizes them."""
+    rounded up to the 64-row tiles as the library sizes them, and the largest
+    number of interface nodes coupled to one subdomain (columns of Ehat_j)."""
     part = np.asarray(prob.part)
     X = (abs(prob.A) + abs(prob.M)).tocsr()
-    d, touched = [], []
+    iface = np.flatnonzero(part < 0)
+    Xi = X[:, iface].tocsr()
+    touched_row = np.diff(Xi.indptr) > 0
+    d, touched, sj = [], [], []
     for j in range(int(part.max()) + 1):
         rows = np.flatnonzero(part == j)
         d.append(rows.size)
-        sub = X[rows]
-        touched.append(int(np.count_nonzero(
-            np.diff((sub[:, np.flatnonzero(part < 0)] != 0).tocsr().indptr))))
+        touched.append(int(np.count_nonzero(touched_row[rows])))
+        sj.append(int(np.unique(Xi[rows].indices).size))
     up = lambda x: -(-max(x, 1) // nb) * nb
     D = up(max(d))
-    return D, min(up(max(touched)), D)
+    return D, min(up(max(touched)), D), max(sj)
+
+
+def _fp64_interior(prob):
+    """RFD_FP32_AUTO's choice for the interior blocks: FP64 with Schur solves
+    on the trailing blocks when D^3 / 6 < SJ (D^2 - TS^2)."""
+    D, TS, SJ = _trailing_rows(prob)
+    return D ** 3 / 6.0 < SJ * (D * D - TS * TS)
 
 
 def test_per_factor_precision_mode():
     """RFD_FP32_AUTO picks a precision per factor.  The interior blocks take
-    FP64 when the rows coupled to the interface fit a trailing part of at
-    most half the padded block (the Schur solves then use the trailing blocks
-    of the factors only), else FP32 refined in FP64; S(zeta) takes FP32 only
+    FP64 when the Schur solves on the trailing blocks of FP64 factors cost
+    less than FP32 factors with refinement (D^3 / 6 < SJ (D^2 - TS^2), TS the
+    trailing part holding the rows coupled to the interface), else FP32
+    refined in FP64; S(zeta) takes FP32 only
     when sum N^3 > 12 c sum N^2 (c: the columns the filter will carry).  On a
     dense S of 384 (s = 324 padded):
       * filter_apply of 8 columns (384 > 96) factors S in FP32: the filter's
@@ -417,8 +428,7 @@ def test_per_factor_precision_mode():
     import paper_1711_09487_amd as R
     prob, ro = _prob("p9_wide_leaves")
     assert (prob.s, prob.m, prob.steps) == (324, 40, 2)
-    D, TS = _trailing_rows(prob)
-    trailing = 2 * TS <= D
+    trailing = _fp64_interior(prob)
     dd = O.DD(prob.A, prob.M, prob.part)
     z, w = O.quadrature(prob.alpha, prob.beta, prob.n_c, prob.rule)
     ref8 = O.filter_apply(O.factor_poles(dd, z), w, prob.Y0[:, :8])
