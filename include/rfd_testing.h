@@ -92,6 +92,23 @@ int rfd_test_syevx(int64_t n, int batch, double* A, int lo, int num, double* lam
  * *k_out = k. */
 int rfd_test_basis(void* pencil, double* dst, int64_t cap, int64_t* k_out, void* stream);
 
+/* The renumbering behind the Schur solves on trailing blocks (Sec. 3.1:
+ * S(zeta) = C_zeta - sum_j Ehat_j^T (B_j - zeta M_Bj)^{-1} Ehat_j reads the
+ * solution only on the rows Ehat_j touches), computed on the host for the
+ * pencil and partition given as to rfd_create_pencil and rfd_set_partition
+ * (same validation and errors).  Blocks are padded to D = the largest
+ * interior rounded up to 64 rows; in subdomain j's block the padding comes
+ * first, then the rows Ehat_j does not touch, then those it touches.
+ * Outputs: *D_out; *TS_out, the trailing rows (a multiple of 64, at most D)
+ * that hold every touched row; *SJ_out, the largest number of interface
+ * nodes coupled to one subdomain; pos[i] (room for n) = the row of interior
+ * node i in its subdomain's renumbered block, -1 for interface nodes.  No
+ * device work. */
+int rfd_test_schur_renumber(int64_t n, const int64_t* A_ptr, const int32_t* A_idx,
+                            const double* A_val, const int64_t* M_ptr, const int32_t* M_idx,
+                            const double* M_val, int32_t p, const int32_t* part, int64_t* D_out,
+                            int64_t* TS_out, int64_t* SJ_out, int32_t* pos);
+
 #ifdef __cplusplus
 }
 #endif

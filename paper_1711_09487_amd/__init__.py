@@ -118,6 +118,8 @@ def lib():
             "rfd_test_lu": [I32, I32, I64, I32, P, P, I64, I64, P, P, I64, I64, I64,
                             C.POINTER(C.c_uint32), P],
             "rfd_test_syevx": [I64, I32, P, I32, I32, P, P, P],
+            "rfd_test_schur_renumber": [I64, P, P, P, P, P, P, I32, P, C.POINTER(I64),
+                                        C.POINTER(I64), C.POINTER(I64), P],
             "rfd_batch_run": [I32, P, C.POINTER(rfd_job), C.POINTER(rfd_result), I32, I64],
             "rfd_server_create": [I32, I64, C.POINTER(P)],
             "rfd_server_submit": [P, P, C.POINTER(rfd_job), C.POINTER(I64)],
@@ -348,6 +350,27 @@ def rfd_test_spectral_orthogonality(h):
     v = C.c_double(0.0)
     _check(lib().rfd_test_spectral_orthogonality(h, C.byref(v)))
     return v.value
+
+
+def rfd_test_schur_renumber(A, M, part):
+    """Host-side renumbering behind the Schur solves on trailing blocks for
+    scipy CSR matrices A, M (full symmetric storage) and a partition vector
+    (subdomain index, -1 on the interface): returns (D, TS, SJ, pos) with pos
+    the row of each interior node in its subdomain's renumbered block (-1 on
+    the interface).  No device work."""
+    A = A.tocsr()
+    M = M.tocsr()
+    n = A.shape[0]
+    arrs = [np.ascontiguousarray(x, dtype=t) for x, t in
+            ((A.indptr, np.int64), (A.indices, np.int32), (A.data, np.float64),
+             (M.indptr, np.int64), (M.indices, np.int32), (M.data, np.float64))]
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    pos = np.empty(n, dtype=np.int32)
+    D, TS, SJ = I64(), I64(), I64()
+    _check(lib().rfd_test_schur_renumber(n, *[a.ctypes.data for a in arrs], int(part.max()) + 1,
+                                         part.ctypes.data, C.byref(D), C.byref(TS), C.byref(SJ),
+                                         pos.ctypes.data))
+    return D.value, TS.value, SJ.value, pos
 
 
 def rfd_test_basis(h, dst, cap, stream=None):

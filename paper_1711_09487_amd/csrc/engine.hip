@@ -101,62 +101,15 @@ Engine::Engine(const Csr& A, const Csr& M, const Partition& P) : d_(new EngineIm
   upload_pair(e.Eg, el);
   upload_pair(e.Etg, etl);
   {
-    // renumbered blocks: new row = pad + position among [rows Ehat_j does not
-    // touch, rows it touches] (each in ascending order); pad rows carry a
-    // unit diagonal
-    std::vector<PairCsr> b2(e.p), e2(e.p), et2(e.p);
-    int64_t smax = 0;
-    for (int j = 0; j < e.p; ++j) {
-      const PairCsr &B = P.Bloc[j], &E = P.Eloc[j], &Et = P.EtLoc[j];
-      const int64_t d = B.rows, pad = e.D - d;
-      std::vector<int32_t> perm, pinv(d);
-      for (int pass = 0; pass < 2; ++pass)
-        for (int64_t r = 0; r < d; ++r)
-          if ((E.ptr[r + 1] > E.ptr[r]) == (pass == 1)) perm.push_back((int32_t)r);
-      for (int64_t q = 0; q < d; ++q) pinv[perm[q]] = (int32_t)(pad + q);
-      int64_t touched = 0;
-      for (int64_t r = 0; r < d; ++r) touched += E.ptr[r + 1] > E.ptr[r] ? 1 : 0;
-      smax = std::max(smax, touched);
-      PairCsr& b = b2[j];
-      PairCsr& ee = e2[j];
-      b.rows = b.cols = e.D;
-      ee.rows = e.D;
-      ee.cols = E.cols;
-      b.ptr.assign(1, 0);
-      ee.ptr.assign(1, 0);
-      for (int64_t q = 0; q < pad; ++q) {
-        b.idx.push_back((int32_t)q);
-        b.a.push_back(1.0);
-        b.m.push_back(0.0);
-        b.ptr.push_back((int64_t)b.idx.size());
-        ee.ptr.push_back((int64_t)ee.idx.size());
-      }
-      for (int64_t q = 0; q < d; ++q) {
-        const int32_t r = perm[q];
-        for (int64_t k = B.ptr[r]; k < B.ptr[r + 1]; ++k) {
-          b.idx.push_back(pinv[B.idx[k]]);
-          b.a.push_back(B.a[k]);
-          b.m.push_back(B.m[k]);
-        }
-        b.ptr.push_back((int64_t)b.idx.size());
-        for (int64_t k = E.ptr[r]; k < E.ptr[r + 1]; ++k) {
-          ee.idx.push_back(E.idx[k]);
-          ee.a.push_back(E.a[k]);
-          ee.m.push_back(E.m[k]);
-        }
-        ee.ptr.push_back((int64_t)ee.idx.size());
-      }
-      et2[j] = Et;
-      for (auto& c : et2[j].idx) c = pinv[c];
-      et2[j].cols = e.D;
-    }
-    e.TS = std::min<int64_t>(round_up(std::max<int64_t>(smax, 1), NB), e.D);
-    e.SJA = P.sj_max;
+    // the blocks renumbered for the Schur solves on trailing blocks
+    const SchurRenumber R = make_schur_renumber(P, e.D, NB);
+    e.TS = R.TS;
+    e.SJA = R.SJ;
     std::vector<const PairCsr*> b2p, e2p, et2p;
     for (int j = 0; j < e.p; ++j) {
-      b2p.push_back(&b2[j]);
-      e2p.push_back(&e2[j]);
-      et2p.push_back(&et2[j]);
+      b2p.push_back(&R.B[j]);
+      e2p.push_back(&R.E[j]);
+      et2p.push_back(&R.Et[j]);
     }
     upload_pair(e.Bg2, b2p);
     upload_pair(e.Eg2, e2p);

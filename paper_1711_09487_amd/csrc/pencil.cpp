@@ -61,6 +61,66 @@ void check_symmetric(const Csr& A, const char* name) {
         throw Error(ST_EINVAL, std::string(name) + " is not symmetric");
 }
 
+SchurRenumber make_schur_renumber(const Partition& P, int64_t D, int64_t nb) {
+  SchurRenumber R;
+  const int p = P.p;
+  R.B.resize(p);
+  R.E.resize(p);
+  R.Et.resize(p);
+  R.pos.resize(p);
+  int64_t smax = 0;
+  for (int j = 0; j < p; ++j) {
+    const PairCsr &B = P.Bloc[j], &E = P.Eloc[j], &Et = P.EtLoc[j];
+    const int64_t d = B.rows, pad = D - d;
+    if (pad < 0) throw Error(ST_EINVAL, "schur renumbering: block larger than D");
+    std::vector<int32_t> perm;
+    std::vector<int32_t>& pinv = R.pos[j];
+    pinv.assign(d, 0);
+    int64_t touched = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int64_t r = 0; r < d; ++r)
+        if ((E.ptr[r + 1] > E.ptr[r]) == (pass == 1)) perm.push_back((int32_t)r);
+    for (int64_t q = 0; q < d; ++q) pinv[perm[q]] = (int32_t)(pad + q);
+    for (int64_t r = 0; r < d; ++r) touched += E.ptr[r + 1] > E.ptr[r] ? 1 : 0;
+    smax = std::max(smax, touched);
+    R.SJ = std::max<int64_t>(R.SJ, E.cols);
+    PairCsr& b = R.B[j];
+    PairCsr& ee = R.E[j];
+    b.rows = b.cols = D;
+    ee.rows = D;
+    ee.cols = E.cols;
+    b.ptr.assign(1, 0);
+    ee.ptr.assign(1, 0);
+    for (int64_t q = 0; q < pad; ++q) {
+      b.idx.push_back((int32_t)q);
+      b.a.push_back(1.0);
+      b.m.push_back(0.0);
+      b.ptr.push_back((int64_t)b.idx.size());
+      ee.ptr.push_back((int64_t)ee.idx.size());
+    }
+    for (int64_t q = 0; q < d; ++q) {
+      const int32_t r = perm[q];
+      for (int64_t k = B.ptr[r]; k < B.ptr[r + 1]; ++k) {
+        b.idx.push_back(pinv[B.idx[k]]);
+        b.a.push_back(B.a[k]);
+        b.m.push_back(B.m[k]);
+      }
+      b.ptr.push_back((int64_t)b.idx.size());
+      for (int64_t k = E.ptr[r]; k < E.ptr[r + 1]; ++k) {
+        ee.idx.push_back(E.idx[k]);
+        ee.a.push_back(E.a[k]);
+        ee.m.push_back(E.m[k]);
+      }
+      ee.ptr.push_back((int64_t)ee.idx.size());
+    }
+    R.Et[j] = Et;
+    for (auto& c : R.Et[j].idx) c = pinv[c];
+    R.Et[j].cols = D;
+  }
+  R.TS = std::min<int64_t>((std::max<int64_t>(smax, 1) + nb - 1) / nb * nb, D);
+  return R;
+}
+
 double abs_row_sum_max(const Csr& A) {
   double mx = 0;
   for (int64_t i = 0; i < A.n; ++i) {

@@ -59,6 +59,19 @@ Csr make_csr(int64_t n, const int64_t* ptr, const int32_t* idx, const double* va
              const char* name);
 void check_symmetric(const Csr& A, const char* name);
 Partition make_partition(const Csr& A, const Csr& M, int p, const int32_t* part);
+
+// The subdomain blocks renumbered for Schur solves on trailing blocks: in
+// each D-row item the padding rows come first (a unit diagonal entry each),
+// then the rows of B_j that Ehat_j does not touch, then the rows it touches
+// (both in ascending order).  pos[j][r] = new row of local row r; TS = the
+// trailing rows (a multiple of nb, at most D) that hold every touched row of
+// every subdomain; SJ = the largest number of columns of an Ehat_j.
+struct SchurRenumber {
+  std::vector<PairCsr> B, E, Et;  // D x D, D x s_j, s_j x D
+  std::vector<std::vector<int32_t>> pos;
+  int64_t TS = 0, SJ = 0;
+};
+SchurRenumber make_schur_renumber(const Partition& P, int64_t D, int64_t nb);
 double abs_row_sum_max(const Csr& A);
 
 }  // namespace rfd

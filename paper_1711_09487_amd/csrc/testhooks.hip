@@ -8,6 +8,7 @@
 
 #include "dense.hpp"
 #include "eig.hpp"
+#include "pencil.hpp"
 #include "rfd_capi_util.hpp"
 
 using namespace rfd;
@@ -204,5 +205,28 @@ extern "C" int rfd_test_syevx(int64_t n, int batch, double* A, int lo, int num, 
     inverse_iteration(s, tw, n, batch, lam, num_d.as<int>(), cl_d.as<int>(), num, Ym, scr);
     back_transform(s, Am, tw, n, batch, Ym, num_d.as<int>(), num);
     RFD_HIP(hipStreamSynchronize(s));
+  });
+}
+
+extern "C" int rfd_test_schur_renumber(int64_t n, const int64_t* A_ptr, const int32_t* A_idx,
+                                       const double* A_val, const int64_t* M_ptr,
+                                       const int32_t* M_idx, const double* M_val, int32_t p,
+                                       const int32_t* part, int64_t* D_out, int64_t* TS_out,
+                                       int64_t* SJ_out, int32_t* pos) {
+  return capi_guard([&] {
+    if (!D_out || !TS_out || !SJ_out || !pos) throw Error(ST_EINVAL, "null output");
+    const Csr A = make_csr(n, A_ptr, A_idx, A_val, "A");
+    const Csr M = make_csr(n, M_ptr, M_idx, M_val, "M");
+    check_symmetric(A, "A");
+    check_symmetric(M, "M");
+    const Partition P = make_partition(A, M, p, part);
+    const int64_t D = (P.d_max + NB - 1) / NB * NB;
+    const SchurRenumber R = make_schur_renumber(P, D, NB);
+    *D_out = D;
+    *TS_out = R.TS;
+    *SJ_out = R.SJ;
+    for (int64_t i = 0; i < n; ++i) pos[i] = -1;
+    for (int j = 0; j < P.p; ++j)
+      for (size_t r = 0; r < P.interior[j].size(); ++r) pos[P.interior[j][r]] = R.pos[j][r];
   });
 }
