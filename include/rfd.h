@@ -114,8 +114,14 @@ rfd_status rfd_set_interval_and_poles(rfd_pencil_t pencil, double alpha, double 
  * corrections (refine_tol <= 0 or max_sweeps <= 0 select 1e-13 and 8).
  * RFD_FP32_AUTO: FP32 factors with FP64 refinement where the refinement
  * costs less than the FP32 factorization saves, FP64 factors elsewhere.  The
- * interior blocks are always FP32 (their refinement residual is a sparse
- * product).  S(zeta) is FP32 when sum N^3 > 12 c sum N^2 over its factored
+ * interior blocks (padded to D rows; TS = the trailing rows that hold every
+ * row coupled to the interface, those rows being numbered last; SJ = the
+ * largest number of interface nodes coupled to one subdomain) are FP64 when
+ * D^3 / 6 < SJ (D^2 - TS^2): FP64 factors then need Schur solves on the
+ * trailing TS x TS blocks only, while refining FP32 factors needs the full
+ * solves (Sec. 3.1 uses only the rows of the solution that E_i touches).
+ * Otherwise they are FP32 with a sparse-product refinement residual.
+ * S(zeta) is FP32 when sum N^3 > 12 c sum N^2 over its factored
  * blocks (N: their sizes; c: the columns the filter will carry, m * steps
  * for rfd_filter_interface, m * max_steps for rfd_filter_lanczos, m for
  * rfd_filter_apply): each filtered column then costs about 16 N^2 FP64
