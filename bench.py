@@ -11,11 +11,13 @@ block are resident on the device before the timed region.  A Ritz value
 counts when it lies within 1e-10 (relative) of the reference eigenvalue of
 the same rank (tests/golden/reference_c3.json); the count that also asks
 for a residual ||Ax - theta Mx|| / (||A|| ||x||) <= 1e-9 is reported beside
-it.  Three precision modes run: FP32 factors with FP64 refinement to the
-1e-10 target where the refinement costs less than the FP32 factorization
-saves (RFD_FP32_AUTO: the interior blocks; the value), every factor in
-FP32 with FP64 refinement (RFD_FP32_REFINE, beside it) and plain FP64
-(beside it).
+it.  Three precision modes run: a precision per factor, FP32 with FP64
+refinement to the 1e-10 target where that costs less than FP64
+(RFD_FP32_AUTO; the value: at 63^3 every factor comes out FP64, the
+interior blocks because their Schur solves then run on trailing blocks;
+the batched 2D pencils take FP32 interior blocks), every factor in FP32
+with FP64 refinement (RFD_FP32_REFINE, beside it) and plain FP64 (beside
+it).
 
 Beside the headline:
   spectral -- the same pencil with the spectral interior path (one
