@@ -464,6 +464,40 @@ def test_per_factor_precision_mode():
     assert np.all(res <= 10 * ro.resid + 1e-12)
 
 
+def test_auto_takes_fp64_interior_when_trailing_solves_pay():
+    """A 3D pencil whose interior blocks (125 rows, padded to 128) couple to
+    the interface through 61 of them (TS = 64) and to 75 interface nodes:
+    D^3 / 6 < SJ (D^2 - TS^2), so RFD_FP32_AUTO takes FP64 interior factors
+    with Schur solves on the trailing blocks, and with 80 filtered columns S
+    stays FP64 too.  Every factor then matches RFD_FP64: the interface basis
+    and the Ritz values come out bit for bit the same, with no refinement
+    sweep, and the Ritz values match the oracle."""
+    torch = _torch()
+    import paper_1711_09487_amd as R
+    prob = W.tiny(N=11, dim=3, P=2, nev=8, n_c=6, m=40, steps=2, nev_b=10, psi=4,
+                  mass_kind="random", kfield=True, cfg_id=54)
+    assert _fp64_interior(prob)
+    ro = O.run(prob)
+    out = {}
+    for mode in (R.RFD_FP64, R.RFD_FP32_AUTO):
+        P = _pencil(prob, mode)
+        try:
+            P.set_timing(True)
+            Q = P.filter_interface(_dev_block(torch, prob.Y0), prob.steps).cpu().numpy()
+            sweeps = P.phase_times()[12:14]
+            P.solve_interior(prob.sigma, prob.nev_b, prob.psi)
+            ev, _, _ = P.rayleigh_ritz(max(prob.nev + 20, 64), vectors=False)
+            torch.cuda.synchronize()
+            out[mode] = (Q, ev.cpu().numpy(), sweeps)
+        finally:
+            P.close()
+    (q0, e0, _), (q2, e2, sw) = out[R.RFD_FP64], out[R.RFD_FP32_AUTO]
+    assert sw[0] == 0 and sw[1] == 0
+    assert np.array_equal(q0, q2) and np.array_equal(e0, e2)
+    assert e2.size == ro.theta.size == prob.nev
+    assert np.max(np.abs(e2 - ro.theta) / np.abs(ro.theta)) <= EIG_TOL
+
+
 COUPLED = {
     # nine uneven subdomains, a two-tile interface, one block step
     "p9_uneven": (lambda: W.tiny(N=27, P=3, nev=6, n_c=4, m=16, steps=1, nev_b=6, psi=2,
